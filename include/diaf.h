@@ -1,0 +1,259 @@
+/*
+ * diaf.h -- C ABI of a GPU (MI355X / gfx950) library for preconditioning
+ * with direct approximate factoring of the inverse, A^{-1} ~ W V^{-1}
+ * (Byckling & Huhtanen, "Preconditioning with direct approximate factoring
+ * of the inverse").
+ *
+ * Method (paper, Sections 1-2): for a sparse nonsingular A and sparse
+ * "standard" matrix subspaces (sparsity patterns) for W and V, solve
+ * min ||A W - V||_F (eq. 1.2) column by column with the columns of either V
+ * or W of fixed (unit) norm.  Column j only touches the columns A(:, J_j)
+ * named by the W pattern J_j, so all columns are independent.
+ *   - DIAF_UNIT_V (first basic algorithm, Section 2.1): v_j is the unit
+ *     vector on the V pattern L_j whose component in range(A(:, J_j)) is
+ *     largest (eq. 2.3); w_j solves the least-squares problem (eq. 2.4).
+ *   - DIAF_UNIT_W (second basic algorithm, Section 2.2): w_j is the right
+ *     singular vector of the smallest singular value of A(:, J_j) with the
+ *     rows L_j removed; v_j = (A w_j) restricted to L_j.
+ * The V pattern may be fixed, or chosen per column as the optimal one for a
+ * seed w (Section 3.1): the diagonal plus the l-1 admissible rows of the
+ * triangle with the largest |A w|.  The factors are applied from the right
+ * (Section 2.3) inside right-preconditioned BiCGSTAB (Section 5).
+ *
+ * Conventions
+ *   - Every array pointer is a DEVICE pointer unless its name ends in
+ *     _host.  Sparse matrices are CSC with int32 colptr[n+1] and int32
+ *     rowidx[nnz]; row indices are sorted and unique within each column and
+ *     every diagonal entry is present.  Values are double or interleaved
+ *     complex double (re, im).
+ *   - All work is ordered on the context's HIP stream.  Calls that return
+ *     host values (diaf_factor's statistics, diaf_solve) synchronise it.
+ *   - Errors are reported by return code only; diaf_last_error() gives a
+ *     message for the last failing call on a context.  No call aborts.
+ *   - Ownership: the caller owns A, patterns, vectors and every buffer it
+ *     passes in.  The library owns the objects it creates (contexts,
+ *     factors, models) and their device memory until the matching
+ *     *_destroy call.  Views return borrowed pointers valid until then.
+ *   - A context must not be used from two host threads at once.
+ */
+#ifndef DIAF_H
+#define DIAF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum diaf_status {
+    DIAF_OK = 0,
+    DIAF_EINVAL = 1,        /* invalid argument or input (checked before any launch) */
+    DIAF_ENOMEM = 2,        /* device allocation failed */
+    DIAF_EDEVICE = 3,       /* HIP runtime error */
+    DIAF_EUNSUPPORTED = 4,  /* input outside the supported sizes (message says which) */
+    DIAF_ESINGULAR = 5,     /* zero or non-finite pivot in V */
+    DIAF_ENOCONV = 6,       /* BiCGSTAB did not converge within maxit (the paper's dagger) */
+    DIAF_EBREAKDOWN = 7     /* BiCGSTAB breakdown (the paper's double dagger) */
+} diaf_status;
+
+typedef enum diaf_dtype { DIAF_F64 = 0, DIAF_C128 = 1 } diaf_dtype;
+
+/* Column norm constraint: unit-norm columns of V (first basic algorithm)
+ * or of W (second basic algorithm). */
+typedef enum diaf_norm_mode { DIAF_UNIT_V = 0, DIAF_UNIT_W = 1 } diaf_norm_mode;
+
+/* W pattern J (Section 4): pattern(A); pattern(A^2), the truncated Neumann
+ * series of Section 4.1 with diagonal V_0, truncation 2 and no dropping;
+ * pattern(A) plus the w_topk two-hop rows of largest |A|^2 path weight
+ * sum_c |a_ic||a_cj| (dropping by count, Section 4.1); an explicit pattern;
+ * or a learned proposal from the A^2 candidates (diaf_model, below). */
+typedef enum diaf_w_kind {
+    DIAF_W_A = 0, DIAF_W_A2 = 1, DIAF_W_A_1HOP_TOPK = 2, DIAF_W_EXPLICIT = 3, DIAF_W_LEARNED = 4
+} diaf_w_kind;
+
+/* V pattern L: explicit; diagonal; Gauss-Seidel structure (Definition 4.1:
+ * diagonal plus the strictly upper / lower part of pattern(A)); or the
+ * optimal choice for the seed w (Section 3.1): the diagonal plus the
+ * v_count-1 rows of the upper / lower triangle of the shadow R_j with the
+ * largest |A w0|, w0 being the solution for V_0 = diagonals. */
+typedef enum diaf_v_kind {
+    DIAF_V_EXPLICIT = 0, DIAF_V_DIAG = 1, DIAF_V_GS_UPPER = 2, DIAF_V_GS_LOWER = 3,
+    DIAF_V_TOPK_UPPER = 4, DIAF_V_TOPK_LOWER = 5
+} diaf_v_kind;
+
+/* Per-column flag bits (diaf_view.flags). */
+#define DIAF_FLAG_RANK_DEFICIENT 1u /* A(:, J_j) (or its rows outside L_j) numerically rank deficient */
+#define DIAF_FLAG_GAP_DEGENERATE 2u /* extreme singular values not separated (rel. gap < 1e-6) */
+#define DIAF_FLAG_SMALL_DIAG 4u     /* |v_jj| < 1e-2 ||v_j|| */
+#define DIAF_FLAG_FELL_BACK 8u      /* learned pattern rejected by the residual gate */
+#define DIAF_FLAG_TIE_EDGE 16u      /* a top-k score at the edge of the 1e-10 tie band */
+#define DIAF_FLAG_NO_DIAG_ROW 64u   /* row j not in the shadow of J_j: column left zero */
+
+typedef struct diaf_csc {
+    int64_t n, nnz;
+    const int32_t* colptr;
+    const int32_t* rowidx;
+    const void* val;   /* nnz doubles (DIAF_F64) or nnz (re, im) pairs (DIAF_C128) */
+    int32_t dtype;     /* diaf_dtype */
+} diaf_csc;
+
+typedef struct diaf_pattern {
+    int64_t n, nnz;
+    const int32_t* colptr;
+    const int32_t* rowidx;
+} diaf_pattern;
+
+struct diaf_ctx;
+struct diaf_factors;
+struct diaf_model;
+
+typedef struct diaf_spec {
+    int32_t w_kind;                  /* diaf_w_kind */
+    int32_t w_topk;                  /* DIAF_W_A_1HOP_TOPK: extra rows per column */
+    const diaf_pattern* w_explicit;  /* DIAF_W_EXPLICIT: must contain every diagonal */
+    struct diaf_model* model;        /* DIAF_W_LEARNED */
+    double gate_tau;                 /* DIAF_W_LEARNED: refactor with pattern(A^2) when
+                                        r_j / s_j > gate_tau (s_j = 1 for DIAF_UNIT_V,
+                                        ||A(:,J_j)||_F for DIAF_UNIT_W) */
+    int32_t v_kind;                  /* diaf_v_kind */
+    int32_t v_count;                 /* DIAF_V_TOPK_*: l, counting the diagonal */
+    const diaf_pattern* v_explicit;  /* DIAF_V_EXPLICIT (rows outside the shadow get 0) */
+    int32_t gram_fp32;               /* 1: Gram matrix accumulated in FP32 products (variant) */
+} diaf_spec;
+
+/* Borrowed device views of a factorization.  W has the pattern J (Wcp/Wri)
+ * and values Wval; V is CSC with sorted rows.  r[j] = ||A w_j - v_j||_2,
+ * flags[j] as above, lcount[j] = |L_j|.  vtri = 1 upper, -1 lower,
+ * 0 diagonal. */
+typedef struct diaf_view {
+    int64_t n, nnz_w, nnz_v;
+    int32_t dtype, vtri;
+    const int32_t* Wcp;
+    const int32_t* Wri;
+    const void* Wval;
+    const int32_t* Vcp;
+    const int32_t* Vri;
+    const void* Vval;
+    const double* r;
+    const uint32_t* flags;
+    const int32_t* lcount;
+} diaf_view;
+
+/* Host statistics gathered by diaf_factor. */
+typedef struct diaf_stats {
+    int64_t n, nnz_w, nnz_v;
+    int32_t kmax, mmax;              /* largest |J_j| and shadow size bound */
+    int32_t nbuckets;                /* size classes launched */
+    int32_t count_rank_deficient, count_gap_degenerate, count_small_diag, count_tie_edge,
+        count_fell_back, count_no_diag;
+    int32_t v_levels;                /* dependency depth of the triangular V solve */
+    double nrm;                      /* ||A W - V||_F = sqrt(sum r_j^2) */
+    double ms_pattern, ms_factor, ms_assemble;  /* device time of the phases */
+} diaf_stats;
+
+typedef struct diaf_solve_info {
+    int32_t iters;       /* BiCGSTAB iterations (half steps rounded up) */
+    int32_t flag;        /* 0 converged, 1 maxit, 2 breakdown, 3 singular V */
+    double relres;       /* recurrence residual / ||b|| at exit */
+    double relres_true;  /* ||b - A x|| / ||b|| recomputed at exit */
+    double ms;           /* wall time of the solve */
+} diaf_solve_info;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` that orders all work on
+ * `hip_stream` (a hipStream_t; NULL = the null stream). */
+diaf_status diaf_ctx_create(struct diaf_ctx** ctx, int device, void* hip_stream);
+void diaf_ctx_destroy(struct diaf_ctx* ctx);
+const char* diaf_last_error(const struct diaf_ctx* ctx);
+/* Select the factor kernel family: 0 automatic, 1 generic only. */
+diaf_status diaf_ctx_set_option(struct diaf_ctx* ctx, const char* key, int64_t value);
+
+/* ---- patterns (Section 4) ------------------------------------------------ */
+
+/* W pattern of kind w_kind for A, two-phase: with rowidx_out == NULL,
+ * writes colptr_out[n+1] (device) and the total to *nnz_host; then call
+ * again with rowidx_out of *nnz_host entries and the same colptr_out. */
+diaf_status diaf_pattern_build(struct diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,
+                               int32_t w_topk, int32_t* colptr_out, int32_t* rowidx_out,
+                               int64_t* nnz_host);
+
+/* ---- factoring (Sections 2-3) -------------------------------------------- */
+
+/* Factor A W ~ V with the given patterns and norm mode.  On success *out
+ * owns W, V, the residuals and flags.  DIAF_EINVAL for malformed input
+ * (unsorted or duplicate rows, missing diagonal, non-finite values, bad
+ * spec); DIAF_EUNSUPPORTED for columns beyond the kernel size limits
+ * (|J_j| <= 256, gathered entries <= 8192). */
+diaf_status diaf_factor(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
+                        int32_t mode, struct diaf_factors** out);
+diaf_status diaf_factors_view(const struct diaf_factors* F, diaf_view* out_host);
+diaf_status diaf_factors_stats(const struct diaf_factors* F, diaf_stats* out_host);
+void diaf_factors_destroy(struct diaf_factors* F);
+
+/* ---- apply and solve (eq. 2.1, Section 5) -------------------------------- */
+
+/* y = W V^{-1} x for triangular or diagonal V (n entries each). */
+diaf_status diaf_apply(struct diaf_ctx* ctx, const struct diaf_factors* F, const void* x,
+                       void* y);
+
+/* Right-preconditioned BiCGSTAB on A M u = b, x = M u, M = W V^{-1}
+ * (F == NULL: M = I), x0 = 0, stop when ||r|| <= rtol ||b||.  Returns
+ * DIAF_OK, DIAF_ENOCONV or DIAF_EBREAKDOWN with *info_host filled. */
+diaf_status diaf_solve(struct diaf_ctx* ctx, const diaf_csc* A, const struct diaf_factors* F,
+                       const void* b, void* x, double rtol, int32_t maxit,
+                       diaf_solve_info* info_host);
+
+/* ---- learned W-pattern proposer ------------------------------------------ */
+/*
+ * A multilayer perceptron 16 -> 64 -> 64 -> 1 (ReLU, FP32) scores each
+ * candidate i of column j's A^2 pattern from 16 column-local features; the
+ * proposal is J_j = {j} U {i : sigmoid(score) >= 0.5}.  Parameters are one
+ * float array of DIAF_MLP_NPARAM entries: W1[64][16], b1[64], W2[64][64],
+ * b2[64], w3[64], b3 (row-major, y = W x + b).
+ */
+#define DIAF_MLP_NFEAT 16
+#define DIAF_MLP_HIDDEN 64
+#define DIAF_MLP_NPARAM (64 * 16 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* Create a model holding a copy of params_host (DIAF_MLP_NPARAM floats). */
+diaf_status diaf_model_create(struct diaf_ctx* ctx, const float* params_host,
+                              struct diaf_model** out);
+diaf_status diaf_model_get_params(struct diaf_ctx* ctx, const struct diaf_model* m,
+                                  float* params_host);
+void diaf_model_destroy(struct diaf_model* m);
+
+/* Features of every (column j, candidate i) pair of the candidate pattern
+ * C (CSC; normally pattern(A^2)), written as feat[nnz(C)][16] floats. */
+diaf_status diaf_features(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_pattern* C,
+                          float* feat);
+
+/* Labels of the candidates from a plain factorization F whose W pattern is
+ * C: label = 1 when |w_j(i)| ||A(:,i)|| >= tau * max over the column, and
+ * always for i = j (dropping by tolerance, Section 4.1). */
+diaf_status diaf_labels(struct diaf_ctx* ctx, const diaf_csc* A, const struct diaf_factors* F,
+                        double tau, float* labels);
+
+/* scores[p] = MLP(feat[p]) for p < npairs. */
+diaf_status diaf_mlp_forward(struct diaf_ctx* ctx, const struct diaf_model* m, const float* feat,
+                             int64_t npairs, float* scores);
+
+/* Mean binary cross-entropy loss of the logits against labels (0/1 floats)
+ * and its gradient with respect to the parameters (grad: DIAF_MLP_NPARAM
+ * floats, device; may be NULL).  *loss_host receives the loss. */
+diaf_status diaf_mlp_loss_grad(struct diaf_ctx* ctx, const struct diaf_model* m,
+                               const float* feat, const float* labels, int64_t npairs,
+                               float* grad, double* loss_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean BCE loss of
+ * the given pairs.  The model keeps its moment estimates and step count. */
+diaf_status diaf_mlp_train_step(struct diaf_ctx* ctx, struct diaf_model* m, const float* feat,
+                                const float* labels, int64_t npairs, float lr,
+                                double* loss_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DIAF_H */

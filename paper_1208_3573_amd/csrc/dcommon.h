@@ -1,0 +1,142 @@
+// Shared device/host helpers of the HIP library: scalar traits for double
+// and complex double, launch checks, and the internal interfaces between the
+// API layer (diaf_api.cpp) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/diaf.h"
+
+// ---------------------------------------------------------------------------
+// Complex double with the few operators the kernels need.
+// ---------------------------------------------------------------------------
+struct zc {
+    double x, y;
+};
+
+__host__ __device__ inline zc operator+(zc a, zc b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline zc operator-(zc a, zc b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline zc operator-(zc a) { return {-a.x, -a.y}; }
+__host__ __device__ inline zc operator*(zc a, zc b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__host__ __device__ inline zc operator*(double s, zc a) { return {s * a.x, s * a.y}; }
+__host__ __device__ inline zc operator*(zc a, double s) { return {s * a.x, s * a.y}; }
+__host__ __device__ inline zc& operator+=(zc& a, zc b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline zc& operator-=(zc& a, zc b) { a.x -= b.x; a.y -= b.y; return a; }
+
+template <class T>
+struct num;
+
+template <>
+struct num<double> {
+    static constexpr bool is_complex = false;
+    __host__ __device__ static double zero() { return 0.0; }
+    __host__ __device__ static double one() { return 1.0; }
+    __host__ __device__ static double mk(double r) { return r; }
+    __host__ __device__ static double conj(double a) { return a; }
+    __host__ __device__ static double re(double a) { return a; }
+    __host__ __device__ static double im(double) { return 0.0; }
+    __host__ __device__ static double abs2(double a) { return a * a; }
+    __host__ __device__ static double abs(double a) { return fabs(a); }
+    // conj(a) * b
+    __host__ __device__ static double cmul(double a, double b) { return a * b; }
+    __host__ __device__ static double div(double a, double s) { return a / s; }
+    __host__ __device__ static bool finite(double a) { return isfinite(a); }
+    __host__ __device__ static bool iszero(double a) { return a == 0.0; }
+};
+
+template <>
+struct num<zc> {
+    static constexpr bool is_complex = true;
+    __host__ __device__ static zc zero() { return {0.0, 0.0}; }
+    __host__ __device__ static zc one() { return {1.0, 0.0}; }
+    __host__ __device__ static zc mk(double r) { return {r, 0.0}; }
+    __host__ __device__ static zc conj(zc a) { return {a.x, -a.y}; }
+    __host__ __device__ static double re(zc a) { return a.x; }
+    __host__ __device__ static double im(zc a) { return a.y; }
+    __host__ __device__ static double abs2(zc a) { return a.x * a.x + a.y * a.y; }
+    // modulus without spurious overflow/underflow
+    __host__ __device__ static double abs(zc a) {
+        double p = fabs(a.x), q = fabs(a.y);
+        double mx = p > q ? p : q, mn = p > q ? q : p;
+        if (mx == 0.0) return 0.0;
+        double r = mn / mx;
+        return mx * sqrt(1.0 + r * r);
+    }
+    __host__ __device__ static zc cmul(zc a, zc b) {
+        return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+    }
+    __host__ __device__ static zc div(zc a, double s) { return {a.x / s, a.y / s}; }
+    __host__ __device__ static bool finite(zc a) { return isfinite(a.x) && isfinite(a.y); }
+    __host__ __device__ static bool iszero(zc a) { return a.x == 0.0 && a.y == 0.0; }
+};
+
+// Unit-modulus conj(z)/|z| (z != 0), scaled first so tiny entries do not
+// underflow.
+__host__ __device__ inline double unit_conj_phase(double z) { return z > 0.0 ? 1.0 : -1.0; }
+__host__ __device__ inline zc unit_conj_phase(zc z) {
+    double s = fmax(fabs(z.x), fabs(z.y));
+    zc u{z.x / s, z.y / s};
+    double a = sqrt(u.x * u.x + u.y * u.y);
+    return {u.x / a, -u.y / a};
+}
+
+// ---------------------------------------------------------------------------
+// Internal interfaces.
+// ---------------------------------------------------------------------------
+namespace diaf {
+
+struct Err {
+    diaf_status code = DIAF_OK;
+    std::string msg;
+};
+
+#define DIAF_HIP_TRY(expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            return diaf::Err{DIAF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+        }                                                                              \
+    } while (0)
+
+#define DIAF_TRY(expr)                 \
+    do {                               \
+        diaf::Err e_ = (expr);         \
+        if (e_.code != DIAF_OK) return e_; \
+    } while (0)
+
+// V pattern rules as seen by the kernels.
+enum VRule { V_EXPLICIT = 0, V_DIAG = 1, V_GS_UPPER = 2, V_GS_LOWER = 3, V_TOPK_UPPER = 4,
+             V_TOPK_LOWER = 5 };
+
+// Everything the factor kernels need about one launch.
+template <class T>
+struct FactorArgs {
+    int n;
+    const int32_t* Acp;
+    const int32_t* Ari;
+    const T* Aval;
+    const int32_t* Jcp;
+    const int32_t* Jri;
+    const int32_t* cols;   // columns handled by this launch
+    int ncols;
+    int mode;              // 0 unit-norm v, 1 unit-norm w
+    int vrule, vcount, lmax;
+    const int32_t* Vcp_in;
+    const int32_t* Vri_in;
+    int gram_fp32;
+    // outputs
+    T* Wval;
+    int32_t* Vrows;  // n * lmax, -1 padded, sorted by row
+    T* Vvals;
+    double* rcol;
+    double* bnorm;   // ||A(:, J_j)||_F
+    uint32_t* flags;
+    int32_t* lcount;
+};
+
+}  // namespace diaf

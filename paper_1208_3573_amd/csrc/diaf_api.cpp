@@ -1,0 +1,1029 @@
+// C ABI of the library (include/diaf.h): contexts, validation, W-pattern
+// construction, size-class bucketing and factor launches, V assembly, the
+// apply M = W V^{-1} and the device-resident BiCGSTAB loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+using namespace diaf;
+
+struct diaf_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int64_t opt_generic_only = 0;
+    int64_t opt_batch = 8;
+};
+
+struct diaf_model {
+    diaf_ctx* ctx = nullptr;
+    float* params = nullptr;
+    float* m = nullptr;
+    float* v = nullptr;
+    float* grad = nullptr;
+    float* scratch = nullptr;
+    size_t scratch_pairs = 0;
+    double* loss = nullptr;
+    int step = 0;
+};
+
+struct diaf_factors {
+    diaf_ctx* ctx = nullptr;
+    int64_t n = 0;
+    int dtype = DIAF_F64;
+    int mode = 0;
+    int vtri = 0;
+    int lmax = 1;
+    int32_t* Jcp = nullptr;
+    int32_t* Jri = nullptr;
+    int64_t nnzW = 0;
+    void* Wval = nullptr;
+    int32_t* Vcp = nullptr;
+    int32_t* Vri = nullptr;
+    void* Vval = nullptr;
+    int64_t nnzV = 0;
+    int32_t* Vrows = nullptr;
+    void* Vvals = nullptr;
+    double* r = nullptr;
+    double* bnorm = nullptr;
+    uint32_t* flags = nullptr;
+    int32_t* lcount = nullptr;
+    diaf_stats stats{};
+    // apply structures (built on first use)
+    bool apply_ready = false;
+    int32_t *Wrp = nullptr, *Wci = nullptr, *Vrp = nullptr, *Vci = nullptr;
+    void *Wcv = nullptr, *Vcv = nullptr, *tmp = nullptr;
+    TrsvCtl* ctl = nullptr;
+    uint32_t* ready = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+diaf_status fail(diaf_ctx* ctx, const Err& e)
+{
+    if (ctx) ctx->err = e.msg;
+    return e.code;
+}
+
+diaf_status fail(diaf_ctx* ctx, diaf_status code, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+size_t scalar_size(int dtype) { return dtype == DIAF_C128 ? 16 : 8; }
+
+template <class P>
+Err dmalloc(P** p, size_t bytes)
+{
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc((void**)p, bytes);
+    if (e != hipSuccess) return {DIAF_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    return {};
+}
+
+void dfree(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+Err sync(hipStream_t st)
+{
+    DIAF_HIP_TRY(hipStreamSynchronize(st));
+    return {};
+}
+
+template <class T>
+Err read1(const T* dev, T* host, hipStream_t st)
+{
+    DIAF_HIP_TRY(hipMemcpyAsync(host, dev, sizeof(T), hipMemcpyDeviceToHost, st));
+    return sync(st);
+}
+
+const char* validate_msg(int code)
+{
+    switch (code) {
+    case 1: return "colptr not monotone or negative";
+    case 2: return "row index out of range";
+    case 3: return "row indices unsorted or duplicated within a column";
+    case 4: return "diagonal entry missing";
+    case 5: return "non-finite value";
+    default: return "invalid";
+    }
+}
+
+Err check_csc_host(const diaf_csc* A)
+{
+    if (!A) return {DIAF_EINVAL, "A is NULL"};
+    if (A->n < 0 || A->n > (int64_t)INT32_MAX - 1) return {DIAF_EINVAL, "n out of range"};
+    if (A->nnz < 0 || A->nnz > (int64_t)INT32_MAX) return {DIAF_EINVAL, "nnz out of range"};
+    if (A->dtype != DIAF_F64 && A->dtype != DIAF_C128) return {DIAF_EINVAL, "bad dtype"};
+    if (A->n > 0 && (!A->colptr || !A->rowidx || !A->val)) return {DIAF_EINVAL, "NULL array in A"};
+    return {};
+}
+
+template <class T>
+Err validate_A(const diaf_csc* A, hipStream_t st)
+{
+    int n = (int)A->n;
+    if (n == 0) return {};
+    int32_t* bad = nullptr;
+    DIAF_TRY(dmalloc(&bad, sizeof(int32_t)));
+    int32_t big = 1 << 30;
+    DIAF_HIP_TRY(hipMemcpyAsync(bad, &big, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    // colptr[0] == 0 and colptr[n] == nnz
+    int32_t ends[2];
+    DIAF_HIP_TRY(hipMemcpyAsync(&ends[0], A->colptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(&ends[1], A->colptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    Err e = launch_validate_csc<T>(n, A->colptr, A->rowidx, (const T*)A->val, bad, st);
+    int32_t code = 0;
+    if (e.code == DIAF_OK) e = read1(bad, &code, st);
+    dfree(bad);
+    if (e.code != DIAF_OK) return e;
+    if (ends[0] != 0 || ends[1] != A->nnz) return {DIAF_EINVAL, "colptr[0] != 0 or colptr[n] != nnz"};
+    if (code != (1 << 30)) return {DIAF_EINVAL, std::string("A: ") + validate_msg(code)};
+    return {};
+}
+
+Err validate_pattern(const diaf_pattern* P, int64_t n, int need_diag, const char* what,
+                     hipStream_t st)
+{
+    if (!P) return {DIAF_EINVAL, std::string(what) + " is NULL"};
+    if (P->n != n) return {DIAF_EINVAL, std::string(what) + ": size differs from A"};
+    if (n == 0) return {};
+    if (!P->colptr || (!P->rowidx && P->nnz > 0)) return {DIAF_EINVAL, std::string(what) + ": NULL array"};
+    int32_t* bad = nullptr;
+    DIAF_TRY(dmalloc(&bad, sizeof(int32_t)));
+    int32_t big = 1 << 30;
+    DIAF_HIP_TRY(hipMemcpyAsync(bad, &big, sizeof(int32_t), hipMemcpyHostToDevice, st));
+    int32_t ends[2];
+    DIAF_HIP_TRY(hipMemcpyAsync(&ends[0], P->colptr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(&ends[1], P->colptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    Err e = launch_validate_pattern((int)n, P->colptr, P->rowidx, need_diag, bad, st);
+    int32_t code = 0;
+    if (e.code == DIAF_OK) e = read1(bad, &code, st);
+    dfree(bad);
+    if (e.code != DIAF_OK) return e;
+    if (ends[0] != 0 || ends[1] != P->nnz) return {DIAF_EINVAL, std::string(what) + ": colptr ends"};
+    if (code != (1 << 30)) return {DIAF_EINVAL, std::string(what) + ": " + validate_msg(code)};
+    return {};
+}
+
+// Builds the W pattern (colptr, rowidx allocated here unless provided).
+template <class T>
+Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32_t** Jri_out,
+                  int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st)
+{
+    const int n = (int)A->n;
+    if (w_kind == DIAF_W_A) {
+        DIAF_HIP_TRY(hipMemcpyAsync(Jcp, A->colptr, sizeof(int32_t) * (n + 1),
+                                    hipMemcpyDeviceToDevice, st));
+        *nnz_out = A->nnz;
+        if (rows_given) {
+            DIAF_HIP_TRY(hipMemcpyAsync(rows_given, A->rowidx, sizeof(int32_t) * A->nnz,
+                                        hipMemcpyDeviceToDevice, st));
+        } else if (alloc_rows) {
+            DIAF_TRY(dmalloc(Jri_out, sizeof(int32_t) * A->nnz));
+            DIAF_HIP_TRY(hipMemcpyAsync(*Jri_out, A->rowidx, sizeof(int32_t) * A->nnz,
+                                        hipMemcpyDeviceToDevice, st));
+        }
+        return {};
+    }
+    if (w_kind != DIAF_W_A2 && w_kind != DIAF_W_A_1HOP_TOPK)
+        return {DIAF_EINVAL, "pattern kind not buildable here"};
+    int32_t *cnt = nullptr, *mx = nullptr;
+    DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
+    DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
+    DIAF_TRY(launch_cand_count(n, A->colptr, A->rowidx, cnt, mx, st));
+    int32_t maxcand = 0;
+    DIAF_TRY(read1(mx, &maxcand, st));
+    if (w_kind == DIAF_W_A2)
+        DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, maxcand, cnt, nullptr, nullptr, st));
+    else
+        DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk, maxcand,
+                                        cnt, nullptr, nullptr, st));
+    DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
+    int32_t tot = 0;
+    DIAF_TRY(read1(Jcp + n, &tot, st));
+    *nnz_out = tot;
+    int32_t* rows = rows_given;
+    if (!rows && alloc_rows) {
+        DIAF_TRY(dmalloc(Jri_out, sizeof(int32_t) * (size_t)tot));
+        rows = *Jri_out;
+    }
+    if (rows) {
+        if (w_kind == DIAF_W_A2)
+            DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, maxcand, nullptr, Jcp, rows, st));
+        else
+            DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk,
+                                            maxcand, nullptr, Jcp, rows, st));
+    }
+    DIAF_TRY(sync(st));
+    dfree(cnt);
+    dfree(mx);
+    return {};
+}
+
+struct Bucket {
+    int kcap, tcap;
+    std::vector<int32_t> cols;
+};
+
+void free_factors(diaf_factors* F)
+{
+    if (!F) return;
+    for (void* p : {(void*)F->Jcp, (void*)F->Jri, F->Wval, (void*)F->Vcp, (void*)F->Vri, F->Vval,
+                    (void*)F->Vrows, F->Vvals, (void*)F->r, (void*)F->bnorm, (void*)F->flags,
+                    (void*)F->lcount, (void*)F->Wrp, (void*)F->Wci, (void*)F->Vrp, (void*)F->Vci,
+                    F->Wcv, F->Vcv, F->tmp, (void*)F->ctl, (void*)F->ready})
+        dfree(p);
+    delete F;
+}
+
+int vtri_of(int v_kind)
+{
+    switch (v_kind) {
+    case DIAF_V_GS_UPPER:
+    case DIAF_V_TOPK_UPPER: return 1;
+    case DIAF_V_GS_LOWER:
+    case DIAF_V_TOPK_LOWER: return -1;
+    case DIAF_V_DIAG: return 0;
+    default: return 2;  // determined from the explicit pattern
+    }
+}
+
+// Factor the listed columns (all columns when cols is empty) into F's
+// buffers, which must already be allocated.
+template <class T>
+Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
+                   diaf_factors* F, const std::vector<int32_t>* only, int* nbuckets)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)A->n;
+    // per-column sizes
+    int32_t *kd = nullptr, *td = nullptr;
+    DIAF_TRY(dmalloc(&kd, sizeof(int32_t) * n));
+    DIAF_TRY(dmalloc(&td, sizeof(int32_t) * n));
+    DIAF_TRY(launch_column_sizes(n, A->colptr, F->Jcp, F->Jri, kd, td, st));
+    std::vector<int32_t> kh(n), th(n);
+    DIAF_HIP_TRY(hipMemcpyAsync(kh.data(), kd, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(th.data(), td, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+    DIAF_TRY(sync(st));
+    dfree(kd);
+    dfree(td);
+    static const int classes[][2] = {{16, 128}, {32, 256}, {64, 512}, {64, 1024}, {128, 2048},
+                                     {256, 4096}, {256, 8192}};
+    const int ncls = 7;
+    std::vector<Bucket> B(ncls);
+    for (int c = 0; c < ncls; ++c) { B[c].kcap = classes[c][0]; B[c].tcap = classes[c][1]; }
+    auto place = [&](int j) -> Err {
+        int k = kh[j], t = th[j];
+        for (int c = 0; c < ncls; ++c)
+            if (k <= B[c].kcap && t <= B[c].tcap) { B[c].cols.push_back(j); return {}; }
+        return {DIAF_EUNSUPPORTED, "column " + std::to_string(j) + ": |J_j| = " + std::to_string(k) +
+                                       ", gathered entries = " + std::to_string(t) +
+                                       " exceed the limits (256, 8192)"};
+    };
+    if (only) {
+        for (int32_t j : *only) DIAF_TRY(place(j));
+    } else {
+        for (int j = 0; j < n; ++j) DIAF_TRY(place(j));
+    }
+    int32_t kmax = 0, tmax = 0;
+    for (int j = 0; j < n; ++j) { kmax = std::max(kmax, kh[j]); tmax = std::max(tmax, th[j]); }
+    F->stats.kmax = kmax;
+    F->stats.mmax = tmax;
+    FactorArgs<T> fa{};
+    fa.n = n;
+    fa.Acp = A->colptr;
+    fa.Ari = A->rowidx;
+    fa.Aval = (const T*)A->val;
+    fa.Jcp = F->Jcp;
+    fa.Jri = F->Jri;
+    fa.mode = mode;
+    fa.vrule = spec->v_kind;
+    fa.vcount = spec->v_count;
+    fa.lmax = F->lmax;
+    fa.Vcp_in = spec->v_explicit ? spec->v_explicit->colptr : nullptr;
+    fa.Vri_in = spec->v_explicit ? spec->v_explicit->rowidx : nullptr;
+    fa.gram_fp32 = spec->gram_fp32;
+    fa.Wval = (T*)F->Wval;
+    fa.Vrows = F->Vrows;
+    fa.Vvals = (T*)F->Vvals;
+    fa.rcol = F->r;
+    fa.bnorm = F->bnorm;
+    fa.flags = F->flags;
+    fa.lcount = F->lcount;
+    std::vector<void*> to_free;
+    int nb = 0;
+    for (auto& b : B) {
+        if (b.cols.empty()) continue;
+        ++nb;
+        int32_t* cols = nullptr;
+        DIAF_TRY(dmalloc(&cols, sizeof(int32_t) * b.cols.size()));
+        to_free.push_back(cols);
+        DIAF_HIP_TRY(hipMemcpyAsync(cols, b.cols.data(), sizeof(int32_t) * b.cols.size(),
+                                    hipMemcpyHostToDevice, st));
+        fa.cols = cols;
+        fa.ncols = (int)b.cols.size();
+        int nslots = 1024;
+        size_t gbytes = generic_global_bytes<T>(b.kcap, b.tcap, F->lmax, nslots);
+        void* gm = nullptr;
+        if (gbytes) {
+            DIAF_TRY(dmalloc((unsigned char**)&gm, gbytes));
+            to_free.push_back(gm);
+        }
+        DIAF_TRY(launch_factor_generic<T>(fa, b.kcap, b.tcap, F->lmax, gm, nslots, st));
+    }
+    DIAF_TRY(sync(st));
+    for (void* p : to_free) dfree(p);
+    if (nbuckets) *nbuckets = nb;
+    return {};
+}
+
+template <class T>
+Err assemble_v(diaf_ctx* ctx, diaf_factors* F)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)F->n;
+    dfree(F->Vri);
+    dfree(F->Vval);
+    F->Vri = nullptr;
+    F->Vval = nullptr;
+    DIAF_TRY(exclusive_scan_i32(F->lcount, F->Vcp, n, st));
+    int32_t nv = 0;
+    DIAF_TRY(read1(F->Vcp + n, &nv, st));
+    F->nnzV = nv;
+    DIAF_TRY(dmalloc(&F->Vri, sizeof(int32_t) * (size_t)nv));
+    DIAF_TRY(dmalloc(&F->Vval, sizeof(T) * (size_t)nv));
+    DIAF_TRY(launch_compact_v<T>(n, F->lmax, F->lcount, F->Vcp, F->Vrows, (const T*)F->Vvals,
+                                 F->Vri, (T*)F->Vval, st));
+    return sync(st);
+}
+
+template <class T>
+Err compute_stats(diaf_ctx* ctx, diaf_factors* F)
+{
+    hipStream_t st = ctx->stream;
+    int32_t* counts = nullptr;
+    double* nrm2 = nullptr;
+    DIAF_TRY(dmalloc(&counts, sizeof(int32_t) * 8));
+    DIAF_TRY(dmalloc(&nrm2, sizeof(double)));
+    DIAF_HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int32_t) * 8, st));
+    DIAF_TRY(launch_flag_stats<T>((int)F->n, F->flags, F->r, counts, nrm2, st));
+    int32_t c[8];
+    double s = 0;
+    DIAF_HIP_TRY(hipMemcpyAsync(c, counts, sizeof(c), hipMemcpyDeviceToHost, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(&s, nrm2, sizeof(double), hipMemcpyDeviceToHost, st));
+    DIAF_TRY(sync(st));
+    dfree(counts);
+    dfree(nrm2);
+    F->stats.count_rank_deficient = c[0];
+    F->stats.count_gap_degenerate = c[1];
+    F->stats.count_small_diag = c[2];
+    F->stats.count_fell_back = c[3];
+    F->stats.count_tie_edge = c[4];
+    F->stats.count_no_diag = c[6];
+    F->stats.nrm = sqrt(s);
+    F->stats.n = F->n;
+    F->stats.nnz_w = F->nnzW;
+    F->stats.nnz_v = F->nnzV;
+    return {};
+}
+
+template <class T>
+Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
+{
+    if (F->apply_ready) return {};
+    hipStream_t st = ctx->stream;
+    const int n = (int)F->n;
+    if (F->vtri == 2) return {DIAF_EUNSUPPORTED, "apply: V is neither triangular nor diagonal"};
+    DIAF_TRY(dmalloc(&F->Wrp, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&F->Wci, sizeof(int32_t) * (size_t)F->nnzW));
+    DIAF_TRY(dmalloc(&F->Wcv, sizeof(T) * (size_t)F->nnzW));
+    DIAF_TRY(csc_to_csr<T>(n, F->nnzW, F->Jcp, F->Jri, (const T*)F->Wval, F->Wrp, F->Wci,
+                           (T*)F->Wcv, st));
+    DIAF_TRY(dmalloc(&F->Vrp, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&F->Vci, sizeof(int32_t) * (size_t)F->nnzV));
+    DIAF_TRY(dmalloc(&F->Vcv, sizeof(T) * (size_t)F->nnzV));
+    DIAF_TRY(csc_to_csr<T>(n, F->nnzV, F->Vcp, F->Vri, (const T*)F->Vval, F->Vrp, F->Vci,
+                           (T*)F->Vcv, st));
+    DIAF_TRY(dmalloc(&F->tmp, sizeof(T) * n));
+    DIAF_TRY(dmalloc(&F->ctl, sizeof(TrsvCtl)));
+    DIAF_TRY(dmalloc(&F->ready, sizeof(uint32_t) * n));
+    DIAF_HIP_TRY(hipMemsetAsync(F->ctl, 0, sizeof(TrsvCtl), st));
+    DIAF_HIP_TRY(hipMemsetAsync(F->ready, 0, sizeof(uint32_t) * n, st));
+    DIAF_TRY(sync(st));
+    F->apply_ready = true;
+    // dependency depth of V
+    if (F->vtri != 0) {
+        int32_t *lvl = nullptr, *mx = nullptr;
+        DIAF_TRY(dmalloc(&lvl, sizeof(int32_t) * n));
+        DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
+        DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
+        DIAF_TRY(launch_trsv_levels(n, F->Vrp, F->Vci, F->vtri > 0, lvl, F->ready, F->ctl, mx, st));
+        int32_t depth = 0;
+        DIAF_TRY(read1(mx, &depth, st));
+        TrsvCtl c{};
+        DIAF_TRY(read1(F->ctl, &c, st));
+        dfree(lvl);
+        dfree(mx);
+        if (c.error) return {DIAF_EDEVICE, "triangular dependency walk exceeded its wait budget"};
+        F->stats.v_levels = depth;
+    } else {
+        F->stats.v_levels = 1;
+    }
+    return {};
+}
+
+// t = V^{-1} x ; y = W t   (all on the context stream, no host sync)
+template <class T>
+Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)F->n;
+    if (F->vtri == 0)
+        DIAF_TRY(launch_diag_solve<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, x, (T*)F->tmp, done, st));
+    else
+        DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, x, (T*)F->tmp,
+                                F->ready, F->ctl, done, st));
+    return launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)F->tmp, y, done, st);
+}
+
+template <class T>
+Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
+                diaf_factors** out);
+
+}  // namespace
+
+// ===========================================================================
+// Exported functions
+// ===========================================================================
+extern "C" {
+
+diaf_status diaf_ctx_create(diaf_ctx** ctx, int device, void* hip_stream)
+{
+    if (!ctx) return DIAF_EINVAL;
+    *ctx = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return DIAF_EDEVICE;
+    if (device < 0 || device >= ndev) return DIAF_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return DIAF_EDEVICE;
+    auto* c = new diaf_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *ctx = c;
+    return DIAF_OK;
+}
+
+void diaf_ctx_destroy(diaf_ctx* ctx) { delete ctx; }
+
+const char* diaf_last_error(const diaf_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
+{
+    if (!ctx || !key) return DIAF_EINVAL;
+    std::string k(key);
+    if (k == "generic_only") ctx->opt_generic_only = value;
+    else if (k == "solve_batch") ctx->opt_batch = value < 1 ? 1 : value;
+    else return fail(ctx, DIAF_EINVAL, "unknown option " + k);
+    return DIAF_OK;
+}
+
+diaf_status diaf_copy(diaf_ctx* ctx, void* dst, const void* src, size_t bytes)
+{
+    if (!ctx || (!dst && bytes) || (!src && bytes)) return DIAF_EINVAL;
+    if (bytes == 0) return DIAF_OK;
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail(ctx, DIAF_EDEVICE, hipGetErrorString(e));
+    return DIAF_OK;
+}
+
+diaf_status diaf_pattern_build(diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind, int32_t w_topk,
+                               int32_t* colptr_out, int32_t* rowidx_out, int64_t* nnz_host)
+{
+    if (!ctx) return DIAF_EINVAL;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!colptr_out || !nnz_host) return fail(ctx, DIAF_EINVAL, "NULL output");
+    if (w_kind != DIAF_W_A && w_kind != DIAF_W_A2 && w_kind != DIAF_W_A_1HOP_TOPK)
+        return fail(ctx, DIAF_EINVAL, "w_kind must be A, A2 or A_1HOP_TOPK");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    e = A->dtype == DIAF_F64 ? validate_A<double>(A, ctx->stream) : validate_A<zc>(A, ctx->stream);
+    if (e.code) return fail(ctx, e);
+    int32_t* none = nullptr;
+    e = A->dtype == DIAF_F64
+            ? build_pattern<double>(A, w_kind, w_topk, colptr_out, &none, nnz_host, false,
+                                    rowidx_out, ctx->stream)
+            : build_pattern<zc>(A, w_kind, w_topk, colptr_out, &none, nnz_host, false, rowidx_out,
+                                ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int32_t mode,
+                        diaf_factors** out)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!out) return fail(ctx, DIAF_EINVAL, "out is NULL");
+    *out = nullptr;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!spec) return fail(ctx, DIAF_EINVAL, "spec is NULL");
+    if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return fail(ctx, DIAF_EINVAL, "bad norm mode");
+    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_TOPK_LOWER)
+        return fail(ctx, DIAF_EINVAL, "bad v_kind");
+    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_LEARNED)
+        return fail(ctx, DIAF_EINVAL, "bad w_kind");
+    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER) &&
+        (spec->v_count < 1 || spec->v_count > 64))
+        return fail(ctx, DIAF_EINVAL, "v_count must be in 1..64");
+    if (spec->w_kind == DIAF_W_A_1HOP_TOPK && (spec->w_topk < 0 || spec->w_topk > 256))
+        return fail(ctx, DIAF_EINVAL, "w_topk must be in 0..256");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    e = A->dtype == DIAF_F64 ? factor_impl<double>(ctx, A, spec, mode, out)
+                             : factor_impl<zc>(ctx, A, spec, mode, out);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_factors_view(const diaf_factors* F, diaf_view* v)
+{
+    if (!F || !v) return DIAF_EINVAL;
+    v->n = F->n;
+    v->nnz_w = F->nnzW;
+    v->nnz_v = F->nnzV;
+    v->dtype = F->dtype;
+    v->vtri = F->vtri == 2 ? 0 : F->vtri;
+    v->Wcp = F->Jcp;
+    v->Wri = F->Jri;
+    v->Wval = F->Wval;
+    v->Vcp = F->Vcp;
+    v->Vri = F->Vri;
+    v->Vval = F->Vval;
+    v->r = F->r;
+    v->flags = F->flags;
+    v->lcount = F->lcount;
+    return DIAF_OK;
+}
+
+diaf_status diaf_factors_stats(const diaf_factors* F, diaf_stats* s)
+{
+    if (!F || !s) return DIAF_EINVAL;
+    *s = F->stats;
+    return DIAF_OK;
+}
+
+void diaf_factors_destroy(diaf_factors* F) { free_factors(F); }
+
+diaf_status diaf_apply(diaf_ctx* ctx, const diaf_factors* Fc, const void* x, void* y)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!Fc || !x || !y) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    auto* F = const_cast<diaf_factors*>(Fc);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    Err e;
+    if (F->dtype == DIAF_F64) {
+        e = ensure_apply<double>(ctx, F);
+        if (!e.code) e = enqueue_apply<double>(ctx, F, (const double*)x, (double*)y, nullptr);
+    } else {
+        e = ensure_apply<zc>(ctx, F);
+        if (!e.code) e = enqueue_apply<zc>(ctx, F, (const zc*)x, (zc*)y, nullptr);
+    }
+    if (e.code) return fail(ctx, e);
+    if (F->vtri != 0) {
+        TrsvCtl c{};
+        e = read1(F->ctl, &c, ctx->stream);
+        if (e.code) return fail(ctx, e);
+        if (c.error) return fail(ctx, DIAF_EDEVICE, "triangular solve exceeded its wait budget");
+    }
+    return DIAF_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Factor and solve implementations
+// ===========================================================================
+namespace {
+
+// Learned proposal: C = pattern(A^2), features, MLP scores, J = {j} U {i : score >= 0}.
+template <class T>
+Err learned_pattern(diaf_ctx* ctx, const diaf_csc* A, const diaf_model* M, diaf_factors* F,
+                    int32_t** Ccp, int32_t** Cri, int64_t* nnzC)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)A->n;
+    DIAF_TRY(dmalloc(Ccp, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(build_pattern<T>(A, DIAF_W_A2, 0, *Ccp, Cri, nnzC, true, nullptr, st));
+    float *feat = nullptr, *scores = nullptr;
+    DIAF_TRY(dmalloc(&feat, sizeof(float) * 16 * (size_t)*nnzC));
+    DIAF_TRY(dmalloc(&scores, sizeof(float) * (size_t)*nnzC));
+    DIAF_TRY(launch_features<T>(n, A->colptr, A->rowidx, (const T*)A->val, *Ccp, *Cri, feat, st));
+    DIAF_TRY(launch_mlp_forward(M->params, feat, *nnzC, scores, st));
+    int32_t* cnt = nullptr;
+    DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(launch_pattern_from_scores(n, *Ccp, *Cri, scores, cnt, nullptr, nullptr, st));
+    DIAF_TRY(exclusive_scan_i32(cnt, F->Jcp, n, st));
+    int32_t tot = 0;
+    DIAF_TRY(read1(F->Jcp + n, &tot, st));
+    F->nnzW = tot;
+    DIAF_TRY(dmalloc(&F->Jri, sizeof(int32_t) * (size_t)tot));
+    DIAF_TRY(launch_pattern_from_scores(n, *Ccp, *Cri, scores, nullptr, F->Jcp, F->Jri, st));
+    DIAF_TRY(sync(st));
+    dfree(feat);
+    dfree(scores);
+    dfree(cnt);
+    return {};
+}
+
+// Residual gate: a column whose normalised residual r_j / s_j exceeds
+// gate_tau (s_j = 1 for unit-norm v, ||A(:,J_j)||_F for unit-norm w) is
+// refactored with the candidate pattern C_j = pattern(A^2)(:, j).
+template <class T>
+Err gate_and_fallback(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
+                      diaf_factors* F, const int32_t* Ccp, const int32_t* Cri, int64_t nnzC)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)F->n;
+    std::vector<double> r(n), bn(n);
+    DIAF_HIP_TRY(hipMemcpyAsync(r.data(), F->r, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(bn.data(), F->bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    DIAF_TRY(sync(st));
+    std::vector<uint8_t> fb(n, 0);
+    std::vector<int32_t> list;
+    for (int j = 0; j < n; ++j) {
+        double sj = mode == DIAF_UNIT_V ? 1.0 : bn[j];
+        double q = sj > 0 ? r[j] / sj : r[j];
+        if (!(q <= spec->gate_tau)) { fb[j] = 1; list.push_back(j); }
+    }
+    if (list.empty()) return {};
+    uint8_t* fbd = nullptr;
+    int32_t *cnt = nullptr, *Jcp2 = nullptr, *Jri2 = nullptr;
+    T* W2 = nullptr;
+    DIAF_TRY(dmalloc(&fbd, n));
+    DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&Jcp2, sizeof(int32_t) * (n + 1)));
+    DIAF_HIP_TRY(hipMemcpyAsync(fbd, fb.data(), n, hipMemcpyHostToDevice, st));
+    DIAF_TRY(launch_fallback_count(n, F->Jcp, Ccp, fbd, cnt, st));
+    DIAF_TRY(exclusive_scan_i32(cnt, Jcp2, n, st));
+    int32_t tot = 0;
+    DIAF_TRY(read1(Jcp2 + n, &tot, st));
+    DIAF_TRY(dmalloc(&Jri2, sizeof(int32_t) * (size_t)tot));
+    DIAF_TRY(dmalloc(&W2, sizeof(T) * (size_t)tot));
+    DIAF_TRY(launch_fallback_fill<T>(n, F->Jcp, F->Jri, (const T*)F->Wval, Ccp, Cri, fbd, Jcp2,
+                                     Jri2, W2, F->flags, st));
+    DIAF_TRY(sync(st));
+    dfree(F->Jcp); dfree(F->Jri); dfree(F->Wval);
+    F->Jcp = Jcp2; F->Jri = Jri2; F->Wval = W2; F->nnzW = tot;
+    dfree(fbd);
+    dfree(cnt);
+    DIAF_TRY(factor_columns<T>(ctx, A, spec, mode, F, &list, nullptr));
+    // the refactor rewrote the flags of these columns: mark them again
+    std::vector<uint32_t> fl(n);
+    DIAF_HIP_TRY(hipMemcpyAsync(fl.data(), F->flags, sizeof(uint32_t) * n, hipMemcpyDeviceToHost, st));
+    DIAF_TRY(sync(st));
+    for (int32_t j : list) fl[j] |= DIAF_FLAG_FELL_BACK;
+    DIAF_HIP_TRY(hipMemcpyAsync(F->flags, fl.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, st));
+    DIAF_TRY(sync(st));
+    (void)nnzC;
+    return {};
+}
+
+template <class T>
+Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
+                diaf_factors** out)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)A->n;
+    DIAF_TRY(validate_A<T>(A, st));
+    std::unique_ptr<diaf_factors, void (*)(diaf_factors*)> F(new diaf_factors, free_factors);
+    int32_t *Ccp = nullptr, *Cri = nullptr;  // learned path: candidate pattern pattern(A^2)
+    int64_t nnzC = 0;
+    struct CFree {
+        int32_t** a; int32_t** b;
+        ~CFree() { dfree(*a); dfree(*b); }
+    } cfree{&Ccp, &Cri};
+    F->ctx = ctx;
+    F->n = n;
+    F->dtype = A->dtype;
+    F->mode = mode;
+    F->vtri = vtri_of(spec->v_kind);
+    hipEvent_t ev[4];
+    for (auto& e : ev) DIAF_HIP_TRY(hipEventCreate(&e));
+    DIAF_HIP_TRY(hipEventRecord(ev[0], st));
+    // ---- W pattern ----
+    DIAF_TRY(dmalloc(&F->Jcp, sizeof(int32_t) * (n + 1)));
+    if (spec->w_kind == DIAF_W_EXPLICIT) {
+        DIAF_TRY(validate_pattern(spec->w_explicit, n, 1, "W pattern", st));
+        F->nnzW = spec->w_explicit->nnz;
+        DIAF_TRY(dmalloc(&F->Jri, sizeof(int32_t) * (size_t)F->nnzW));
+        DIAF_HIP_TRY(hipMemcpyAsync(F->Jcp, spec->w_explicit->colptr, sizeof(int32_t) * (n + 1),
+                                    hipMemcpyDeviceToDevice, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(F->Jri, spec->w_explicit->rowidx,
+                                    sizeof(int32_t) * (size_t)F->nnzW, hipMemcpyDeviceToDevice, st));
+    } else if (spec->w_kind == DIAF_W_LEARNED) {
+        if (!spec->model) return {DIAF_EINVAL, "learned W pattern: model is NULL"};
+        DIAF_TRY(learned_pattern<T>(ctx, A, spec->model, F.get(), &Ccp, &Cri, &nnzC));
+    } else {
+        DIAF_TRY(build_pattern<T>(A, spec->w_kind, spec->w_topk, F->Jcp, &F->Jri, &F->nnzW, true,
+                                  nullptr, st));
+    }
+    DIAF_HIP_TRY(hipEventRecord(ev[1], st));
+    // ---- V pattern capacity ----
+    int lmax = 1;
+    if (spec->v_kind == DIAF_V_TOPK_LOWER || spec->v_kind == DIAF_V_TOPK_UPPER) {
+        lmax = spec->v_count;
+    } else if (spec->v_kind == DIAF_V_GS_LOWER || spec->v_kind == DIAF_V_GS_UPPER) {
+        std::vector<int32_t> cp(n + 1);
+        DIAF_HIP_TRY(hipMemcpyAsync(cp.data(), A->colptr, sizeof(int32_t) * (n + 1),
+                                    hipMemcpyDeviceToHost, st));
+        DIAF_TRY(sync(st));
+        for (int j = 0; j < n; ++j) lmax = std::max(lmax, cp[j + 1] - cp[j]);
+    } else if (spec->v_kind == DIAF_V_EXPLICIT) {
+        DIAF_TRY(validate_pattern(spec->v_explicit, n, 0, "V pattern", st));
+        std::vector<int32_t> cp(n + 1), ri(spec->v_explicit->nnz);
+        DIAF_HIP_TRY(hipMemcpyAsync(cp.data(), spec->v_explicit->colptr, sizeof(int32_t) * (n + 1),
+                                    hipMemcpyDeviceToHost, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(ri.data(), spec->v_explicit->rowidx,
+                                    sizeof(int32_t) * ri.size(), hipMemcpyDeviceToHost, st));
+        DIAF_TRY(sync(st));
+        bool up = true, lo = true, dg = true;
+        for (int j = 0; j < n; ++j) {
+            lmax = std::max(lmax, cp[j + 1] - cp[j]);
+            for (int p = cp[j]; p < cp[j + 1]; ++p) {
+                up &= ri[p] <= j;
+                lo &= ri[p] >= j;
+                dg &= ri[p] == j;
+            }
+        }
+        F->vtri = dg ? 0 : (up ? 1 : (lo ? -1 : 2));
+    }
+    if (lmax > 256) return {DIAF_EUNSUPPORTED, "V pattern with more than 256 rows in a column"};
+    F->lmax = lmax;
+    // ---- outputs ----
+    DIAF_TRY(dmalloc(&F->Wval, sizeof(T) * (size_t)F->nnzW));
+    DIAF_TRY(dmalloc(&F->Vrows, sizeof(int32_t) * (size_t)n * lmax));
+    DIAF_TRY(dmalloc(&F->Vvals, sizeof(T) * (size_t)n * lmax));
+    DIAF_TRY(dmalloc(&F->Vcp, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&F->r, sizeof(double) * n));
+    DIAF_TRY(dmalloc(&F->bnorm, sizeof(double) * n));
+    DIAF_TRY(dmalloc(&F->flags, sizeof(uint32_t) * n));
+    DIAF_TRY(dmalloc(&F->lcount, sizeof(int32_t) * n));
+    int nb = 0;
+    DIAF_TRY(factor_columns<T>(ctx, A, spec, mode, F.get(), nullptr, &nb));
+    F->stats.nbuckets = nb;
+    if (spec->w_kind == DIAF_W_LEARNED)
+        DIAF_TRY(gate_and_fallback<T>(ctx, A, spec, mode, F.get(), Ccp, Cri, nnzC));
+    DIAF_HIP_TRY(hipEventRecord(ev[2], st));
+    DIAF_TRY(assemble_v<T>(ctx, F.get()));
+    DIAF_HIP_TRY(hipEventRecord(ev[3], st));
+    DIAF_TRY(compute_stats<T>(ctx, F.get()));
+    float ms[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i) DIAF_HIP_TRY(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    F->stats.ms_pattern = ms[0];
+    F->stats.ms_factor = ms[1];
+    F->stats.ms_assemble = ms[2];
+    *out = F.release();
+    return {};
+}
+
+template <class T>
+Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T* x, double rtol,
+               int maxit, diaf_solve_info* info)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)A->n;
+    auto t0 = std::chrono::steady_clock::now();
+    if (F) {
+        if (F->n != n || F->dtype != A->dtype) return {DIAF_EINVAL, "factors do not match A"};
+        DIAF_TRY(ensure_apply<T>(ctx, F));
+    }
+    // CSR copy of A
+    int32_t *rp = nullptr, *ci = nullptr;
+    T* cv = nullptr;
+    DIAF_TRY(dmalloc(&rp, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&ci, sizeof(int32_t) * (size_t)A->nnz));
+    DIAF_TRY(dmalloc(&cv, sizeof(T) * (size_t)A->nnz));
+    DIAF_TRY(csc_to_csr<T>(n, A->nnz, A->colptr, A->rowidx, (const T*)A->val, rp, ci, cv, st));
+    // work vectors
+    BicgVecs<T> V{};
+    V.n = n;
+    V.b = b;
+    V.x = x;
+    T* buf = nullptr;
+    DIAF_TRY(dmalloc(&buf, sizeof(T) * (size_t)n * 8));
+    V.r = buf; V.rh = buf + n; V.p = buf + 2 * (size_t)n; V.v = buf + 3 * (size_t)n;
+    V.ph = buf + 4 * (size_t)n; V.s = buf + 5 * (size_t)n; V.sh = buf + 6 * (size_t)n;
+    V.t = buf + 7 * (size_t)n;
+    DIAF_TRY(dmalloc(&V.partial, sizeof(double) * 4 * 1024));
+    DIAF_TRY(dmalloc(&V.st, sizeof(BicgState<T>)));
+    DIAF_HIP_TRY(hipMemsetAsync(V.st, 0, sizeof(BicgState<T>), st));
+    const int32_t* done = &V.st->done;
+    DIAF_TRY(bicg_init<T>(V, rtol, maxit, st));
+    BicgState<T> hs{};
+    const int batch = (int)ctx->opt_batch;
+    for (int it0 = 0;; it0 += batch) {
+        for (int q = 0; q < batch; ++q) {
+            DIAF_TRY(bicg_rho<T>(V, st));
+            DIAF_TRY(bicg_update_p<T>(V, st));
+            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.p, V.ph, done));
+            else DIAF_HIP_TRY(hipMemcpyAsync(V.ph, V.p, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
+            DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.ph, V.v, done, st));
+            DIAF_TRY(bicg_alpha<T>(V, st));
+            DIAF_TRY(bicg_s<T>(V, st));
+            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.s, V.sh, done));
+            else DIAF_HIP_TRY(hipMemcpyAsync(V.sh, V.s, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
+            DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.sh, V.t, done, st));
+            DIAF_TRY(bicg_omega<T>(V, st));
+            DIAF_TRY(bicg_xr<T>(V, st));
+        }
+        DIAF_TRY(read1(V.st, &hs, st));
+        if (F && F->vtri != 0) {
+            TrsvCtl c{};
+            DIAF_TRY(read1(F->ctl, &c, st));
+            if (c.error) return {DIAF_EDEVICE, "triangular solve exceeded its wait budget"};
+        }
+        if (hs.done) break;
+        if (it0 > maxit + batch) break;  // cannot happen: maxit stops the loop on the device
+    }
+    DIAF_TRY(bicg_half_fix<T>(V, st));
+    DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.x, V.t, nullptr, st));
+    DIAF_TRY(bicg_true_residual<T>(V, st));
+    DIAF_TRY(read1(V.st, &hs, st));
+    auto t1 = std::chrono::steady_clock::now();
+    info->iters = hs.it;
+    info->flag = hs.flag;
+    info->relres = hs.res;
+    info->relres_true = hs.tt;
+    info->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    dfree(rp); dfree(ci); dfree(cv); dfree(buf); dfree(V.partial); dfree(V.st);
+    return {};
+}
+
+}  // namespace
+
+extern "C" diaf_status diaf_solve(diaf_ctx* ctx, const diaf_csc* A, const diaf_factors* F,
+                                  const void* b, void* x, double rtol, int32_t maxit,
+                                  diaf_solve_info* info)
+{
+    if (!ctx) return DIAF_EINVAL;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!b || !x || !info) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    if (!(rtol > 0) || maxit < 1) return fail(ctx, DIAF_EINVAL, "rtol must be > 0 and maxit >= 1");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    auto* Fm = const_cast<diaf_factors*>(F);
+    e = A->dtype == DIAF_F64
+            ? solve_impl<double>(ctx, A, Fm, (const double*)b, (double*)x, rtol, maxit, info)
+            : solve_impl<zc>(ctx, A, Fm, (const zc*)b, (zc*)x, rtol, maxit, info);
+    if (e.code) return fail(ctx, e);
+    if (info->flag == 1) return fail(ctx, DIAF_ENOCONV, "BiCGSTAB: no convergence within maxit");
+    if (info->flag == 2) return fail(ctx, DIAF_EBREAKDOWN, "BiCGSTAB: breakdown");
+    return DIAF_OK;
+}
+
+// ===========================================================================
+// Learned proposer entry points
+// ===========================================================================
+extern "C" {
+
+diaf_status diaf_model_create(diaf_ctx* ctx, const float* params_host, diaf_model** out)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!params_host || !out) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    auto* m = new diaf_model;
+    m->ctx = ctx;
+    Err e;
+    const size_t np = DIAF_MLP_NPARAM;
+    if (!e.code) e = dmalloc(&m->params, sizeof(float) * np);
+    if (!e.code) e = dmalloc(&m->m, sizeof(float) * np);
+    if (!e.code) e = dmalloc(&m->v, sizeof(float) * np);
+    if (!e.code) e = dmalloc(&m->grad, sizeof(float) * np);
+    if (!e.code) e = dmalloc(&m->scratch, sizeof(float) * mlp_scratch_floats());
+    if (!e.code) e = dmalloc(&m->loss, sizeof(double));
+    if (!e.code) {
+        hipError_t h = hipMemcpyAsync(m->params, params_host, sizeof(float) * np,
+                                      hipMemcpyHostToDevice, ctx->stream);
+        if (h == hipSuccess) h = hipMemsetAsync(m->m, 0, sizeof(float) * np, ctx->stream);
+        if (h == hipSuccess) h = hipMemsetAsync(m->v, 0, sizeof(float) * np, ctx->stream);
+        if (h == hipSuccess) h = hipStreamSynchronize(ctx->stream);
+        if (h != hipSuccess) e = {DIAF_EDEVICE, hipGetErrorString(h)};
+    }
+    if (e.code) {
+        diaf_model_destroy(m);
+        return fail(ctx, e);
+    }
+    *out = m;
+    return DIAF_OK;
+}
+
+diaf_status diaf_model_get_params(diaf_ctx* ctx, const diaf_model* m, float* params_host)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!m || !params_host) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    hipError_t h = hipMemcpyAsync(params_host, m->params, sizeof(float) * DIAF_MLP_NPARAM,
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (h == hipSuccess) h = hipStreamSynchronize(ctx->stream);
+    if (h != hipSuccess) return fail(ctx, DIAF_EDEVICE, hipGetErrorString(h));
+    return DIAF_OK;
+}
+
+void diaf_model_destroy(diaf_model* m)
+{
+    if (!m) return;
+    dfree(m->params); dfree(m->m); dfree(m->v); dfree(m->grad); dfree(m->scratch); dfree(m->loss);
+    delete m;
+}
+
+diaf_status diaf_features(diaf_ctx* ctx, const diaf_csc* A, const diaf_pattern* C, float* feat)
+{
+    if (!ctx) return DIAF_EINVAL;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!C || !feat) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    e = validate_pattern(C, A->n, 0, "candidate pattern", ctx->stream);
+    if (!e.code)
+        e = A->dtype == DIAF_F64
+                ? launch_features<double>((int)A->n, A->colptr, A->rowidx, (const double*)A->val,
+                                          C->colptr, C->rowidx, feat, ctx->stream)
+                : launch_features<zc>((int)A->n, A->colptr, A->rowidx, (const zc*)A->val,
+                                      C->colptr, C->rowidx, feat, ctx->stream);
+    if (!e.code) e = sync(ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_labels(diaf_ctx* ctx, const diaf_csc* A, const diaf_factors* F, double tau,
+                        float* labels)
+{
+    if (!ctx) return DIAF_EINVAL;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!F || !labels) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    if (F->n != A->n || F->dtype != A->dtype) return fail(ctx, DIAF_EINVAL, "factors do not match A");
+    e = A->dtype == DIAF_F64
+            ? launch_labels<double>((int)A->n, A->colptr, A->rowidx, (const double*)A->val, F->Jcp,
+                                    F->Jri, (const double*)F->Wval, tau, labels, ctx->stream)
+            : launch_labels<zc>((int)A->n, A->colptr, A->rowidx, (const zc*)A->val, F->Jcp, F->Jri,
+                                (const zc*)F->Wval, tau, labels, ctx->stream);
+    if (!e.code) e = sync(ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_mlp_forward(diaf_ctx* ctx, const diaf_model* m, const float* feat, int64_t npairs,
+                             float* scores)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!m || (!feat && npairs) || (!scores && npairs) || npairs < 0)
+        return fail(ctx, DIAF_EINVAL, "bad argument");
+    Err e = launch_mlp_forward(m->params, feat, npairs, scores, ctx->stream);
+    if (!e.code) e = sync(ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_mlp_loss_grad(diaf_ctx* ctx, const diaf_model* mc, const float* feat,
+                               const float* labels, int64_t npairs, float* grad, double* loss_host)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!mc || !feat || !labels || npairs <= 0 || !loss_host) return fail(ctx, DIAF_EINVAL, "bad argument");
+    auto* m = const_cast<diaf_model*>(mc);
+    Err e = launch_mlp_loss_grad(m->params, feat, labels, npairs, grad ? grad : m->grad, m->loss,
+                                 m->scratch, ctx->stream);
+    if (!e.code) e = read1(m->loss, loss_host, ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_mlp_train_step(diaf_ctx* ctx, diaf_model* m, const float* feat,
+                                const float* labels, int64_t npairs, float lr, double* loss_host)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!m || !feat || !labels || npairs <= 0 || !(lr > 0)) return fail(ctx, DIAF_EINVAL, "bad argument");
+    Err e = launch_mlp_loss_grad(m->params, feat, labels, npairs, m->grad, m->loss, m->scratch,
+                                 ctx->stream);
+    if (!e.code) e = launch_adam(m->params, m->grad, m->m, m->v, ++m->step, lr, ctx->stream);
+    if (!e.code && loss_host) e = read1(m->loss, loss_host, ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,915 @@
+// Generic column-factoring kernel: one 256-thread workgroup per column,
+// any |J_j| up to 256 and up to 8192 gathered entries.
+//
+// Per column j (paper Sections 2.1, 2.2, 3.1):
+//   gather A(:, J_j) from CSC, sort the entries by (row, column) in LDS to
+//   get the shadow R_j and row-ordered access, form the Gram matrix
+//   G = B^* B of B = A(R_j, J_j) by sparse merges, then
+//   - unit-norm v (first basic algorithm): Cholesky G = L L^*, the seed
+//     w0 = G^{-1} b_j^* (V_0 = diagonals), the V pattern, M = L^{-1} B_L^*
+//     (the paper's M_j), its top right singular vector v by one-sided
+//     Jacobi, and w = L^{-*} M v (the least-squares solution, eq. 2.4);
+//   - unit-norm w (second basic algorithm): the seed is the bottom
+//     eigenvector of G - b_j^* b_j, and w the bottom eigenvector of
+//     G - B_L^* B_L = (B without rows L)^* (B without rows L), both by
+//     two-sided cyclic Jacobi; v = (B w) on L;
+//   then the phase of (w, v) (diagonal of V real positive), the residual
+//   ||B w - v|| in FP64, and the outputs.
+// The k x k work matrices live in LDS for small columns and in a per-block
+// global slot otherwise.
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+namespace diaf {
+
+static constexpr int GNT = 256;  // threads per workgroup
+
+struct GenLayout {
+    size_t oJ, oOff, oKey, oVal, oLrow, oCol, oPos, oRowptr, oR, oRank, oY, oW, oX, oVM, oSig,
+        oV, oL, oSel, oRed, oMisc, oMats, total;
+};
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// Working storage of one column.  The key array (sort keys) is dead after
+// the shadow is built and is reused for the selection scores.
+__host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, int lcap, size_t st,
+                                                int with_mats)
+{
+    GenLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align16(o + bytes); return r; };
+    L.oJ = take(sizeof(int32_t) * kcap);
+    L.oOff = take(sizeof(int32_t) * (kcap + 1));
+    L.oKey = take(sizeof(uint64_t) * tcap2);
+    L.oVal = take(st * tcap);
+    L.oLrow = take(sizeof(uint16_t) * tcap);
+    L.oCol = take(sizeof(uint16_t) * tcap);
+    L.oPos = take(sizeof(uint16_t) * tcap);
+    L.oRowptr = take(sizeof(uint16_t) * (tcap + 1));
+    L.oR = take(sizeof(int32_t) * tcap);
+    L.oRank = take(sizeof(int32_t) * tcap);
+    L.oY = take(st * tcap);
+    L.oW = take(st * kcap);
+    L.oX = take(st * kcap * (lcap + 1));
+    L.oVM = take(st * lcap * lcap);
+    L.oSig = take(sizeof(double) * lcap);
+    L.oV = take(st * lcap);
+    L.oL = take(sizeof(int32_t) * lcap);
+    L.oSel = take(sizeof(int32_t) * lcap);
+    L.oRed = take(sizeof(double) * GNT);
+    L.oMisc = take(sizeof(double) * 32);
+    L.oMats = o;
+    if (with_mats) take(st * 3 * (size_t)kcap * kcap);
+    L.total = o;
+    return L;
+}
+
+// misc slots (int view / double view)
+enum { MI_T = 0, MI_M, MI_DJ, MI_FLAGS, MI_L, MI_NC, MI_ROT, MI_BEST, MI_Q, MI_EDGE, MI_NIN };
+enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2 };
+
+template <class T>
+struct GenCtx {
+    int tid;
+    int32_t* sJ; int32_t* sOff; uint64_t* sKey; T* sVal; uint16_t* sLrow; uint16_t* sCol;
+    uint16_t* sPos; uint16_t* sRowptr; int32_t* sR; int32_t* sRank; T* sY; T* sW; T* sX; T* sVM;
+    double* sSig; T* sV; int32_t* sL; int32_t* sSel; double* sScore; double* sRed;
+    int* mi; double* md;
+    T* G; T* E; T* Z;
+    int xld;  // leading dimension of X (= lcap + 1)
+};
+
+template <class T>
+__device__ inline double block_sum(GenCtx<T>& c, double x)
+{
+    c.sRed[c.tid] = x;
+    __syncthreads();
+    for (int s = GNT / 2; s > 0; s >>= 1) {
+        if (c.tid < s) c.sRed[c.tid] += c.sRed[c.tid + s];
+        __syncthreads();
+    }
+    double r = c.sRed[0];
+    __syncthreads();
+    return r;
+}
+
+// Inclusive scan of flags[0..cnt) (0/1) into out (ranks), returns total.
+template <class T>
+__device__ inline int block_scan_flags(GenCtx<T>& c, const int32_t* flags, int32_t* out, int cnt)
+{
+    // each thread owns a contiguous chunk
+    int chunk = (cnt + GNT - 1) / GNT;
+    int b = c.tid * chunk, e = min(cnt, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += flags[i];
+    c.sRed[c.tid] = (double)s;
+    __syncthreads();
+    if (c.tid == 0) {
+        double acc = 0;
+        for (int t = 0; t < GNT; ++t) { double v = c.sRed[t]; c.sRed[t] = acc; acc += v; }
+        c.md[MD_SSTAR] = acc;
+    }
+    __syncthreads();
+    int run = (int)c.sRed[c.tid];
+    for (int i = b; i < e; ++i) { run += flags[i]; out[i] = run; }
+    __syncthreads();
+    int tot = (int)c.md[MD_SSTAR];
+    __syncthreads();
+    return tot;
+}
+
+// y = B w over the m local rows (CSR order, deterministic per row).
+template <class T>
+__device__ inline void bmul(GenCtx<T>& c, int m, const T* w, T* y)
+{
+    for (int i = c.tid; i < m; i += GNT) {
+        T acc = num<T>::zero();
+        for (int p = c.sRowptr[i]; p < c.sRowptr[i + 1]; ++p) {
+            int t = c.sPos[p];
+            acc += c.sVal[t] * w[c.sCol[t]];
+        }
+        y[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Entry B(i, a) from the CSR row i (zero if absent).
+template <class T>
+__device__ inline T bget(const GenCtx<T>& c, int i, int a)
+{
+    for (int p = c.sRowptr[i]; p < c.sRowptr[i + 1]; ++p) {
+        int t = c.sPos[p];
+        if (c.sCol[t] == a) return c.sVal[t];
+    }
+    return num<T>::zero();
+}
+
+// In-place lower Cholesky of G (k x k, row-major ld k); zero pivots give a
+// zero column.  Sets the rank flag when a pivot^2 <= 1e-26 max diag.
+template <class T>
+__device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
+{
+    if (c.tid == 0) {
+        double mx = 0;
+        for (int p = 0; p < k; ++p) mx = fmax(mx, num<T>::re(G[p * k + p]));
+        c.md[MD_MAXD] = mx;
+    }
+    __syncthreads();
+    const double maxd = c.md[MD_MAXD];
+    for (int p = 0; p < k; ++p) {
+        if (c.tid == 0) {
+            double d = num<T>::re(G[p * k + p]);
+            double piv = 0.0;
+            if (d > 1e-30 * maxd && isfinite(d)) piv = sqrt(d);
+            if (!(d > 1e-26 * maxd)) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
+            G[p * k + p] = num<T>::mk(piv);
+            c.md[MD_PIV] = piv;
+        }
+        __syncthreads();
+        const double piv = c.md[MD_PIV];
+        for (int i = p + 1 + c.tid; i < k; i += GNT)
+            G[i * k + p] = piv > 0.0 ? num<T>::div(G[i * k + p], piv) : num<T>::zero();
+        __syncthreads();
+        const int rem = k - p - 1;
+        for (int idx = c.tid; idx < rem * rem; idx += GNT) {
+            int i = p + 1 + idx / rem, q = p + 1 + idx % rem;
+            if (q <= i) G[i * k + q] -= G[i * k + p] * num<T>::conj(G[q * k + p]);
+        }
+        __syncthreads();
+    }
+}
+
+// Solve L X = X (forward) for nr right-hand sides stored X[a * xld + t].
+template <class T>
+__device__ inline void lsolve(GenCtx<T>& c, const T* Lf, int k, T* X, int nr)
+{
+    for (int p = 0; p < k; ++p) {
+        const double d = num<T>::re(Lf[p * k + p]);
+        for (int t = c.tid; t < nr; t += GNT)
+            X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
+        __syncthreads();
+        const int rem = k - p - 1;
+        for (int idx = c.tid; idx < rem * nr; idx += GNT) {
+            int i = p + 1 + idx / nr, t = idx % nr;
+            X[i * c.xld + t] -= Lf[i * k + p] * X[p * c.xld + t];
+        }
+        __syncthreads();
+    }
+}
+
+// Solve L^* X = X (backward).
+template <class T>
+__device__ inline void lhsolve(GenCtx<T>& c, const T* Lf, int k, T* X, int nr)
+{
+    for (int p = k - 1; p >= 0; --p) {
+        const double d = num<T>::re(Lf[p * k + p]);
+        for (int t = c.tid; t < nr; t += GNT)
+            X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
+        __syncthreads();
+        for (int idx = c.tid; idx < p * nr; idx += GNT) {
+            int i = idx / nr, t = idx % nr;
+            X[i * c.xld + t] -= num<T>::conj(Lf[p * k + i]) * X[p * c.xld + t];
+        }
+        __syncthreads();
+    }
+}
+
+// Round-robin pairing of nplayers (even) players in round r, pair i.
+__device__ inline void rr_pair(int np, int r, int i, int& a, int& b)
+{
+    if (i == 0) { a = np - 1; b = r; }
+    else { a = (r + i) % (np - 1); b = (r - i + (np - 1)) % (np - 1); }
+    if (a > b) { int t = a; a = b; b = t; }
+}
+
+// Rotation (c, s, ec) that orthogonalises / diagonalises the pair with
+// diagonal entries al, be and off-diagonal g:
+//   J = [[c, s], [-s ec, c ec]],  ec = conj(g) / |g|.
+template <class T>
+__device__ inline void jrot(double al, double be, T g, double& cs, double& sn, T& ec)
+{
+    double ag = num<T>::abs(g);
+    double zeta = (be - al) / (2.0 * ag);
+    double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    cs = 1.0 / sqrt(1.0 + t * t);
+    sn = cs * t;
+    ec = num<T>::div(num<T>::conj(g), ag);
+}
+
+// One-sided Jacobi on the columns of M (k x l, stored X[a * xld + t]);
+// VM (l x l, row-major ld l) accumulates the rotations.
+template <class T>
+__device__ inline void jacobi_onesided(GenCtx<T>& c, T* M, int k, int l, T* VM)
+{
+    for (int idx = c.tid; idx < l * l; idx += GNT)
+        VM[idx] = (idx / l == idx % l) ? num<T>::one() : num<T>::zero();
+    const int np = l + (l & 1);
+    __shared__ double s_c[128], s_s[128];
+    __shared__ T s_e[128];
+    __shared__ int s_p[128], s_q[128];
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (c.tid == 0) c.mi[MI_ROT] = 0;
+        __syncthreads();
+        for (int r = 0; r < np - 1; ++r) {
+            for (int i = c.tid; i < np / 2; i += GNT) {
+                int a, b;
+                rr_pair(np, r, i, a, b);
+                s_p[i] = a; s_q[i] = b; s_s[i] = 0.0; s_c[i] = 1.0;
+                if (b < l) {
+                    double al = 0, be = 0;
+                    T g = num<T>::zero();
+                    for (int e = 0; e < k; ++e) {
+                        T xa = M[e * c.xld + a], xb = M[e * c.xld + b];
+                        al += num<T>::abs2(xa);
+                        be += num<T>::abs2(xb);
+                        g += num<T>::cmul(xa, xb);
+                    }
+                    double ag = num<T>::abs(g);
+                    if (al > 0.0 && be > 0.0 && ag > 1e-15 * sqrt(al) * sqrt(be)) {
+                        double cs, sn; T ec;
+                        jrot<T>(al, be, g, cs, sn, ec);
+                        s_c[i] = cs; s_s[i] = sn; s_e[i] = ec;
+                        c.mi[MI_ROT] = 1;
+                    }
+                }
+            }
+            __syncthreads();
+            const int npair = np / 2;
+            for (int idx = c.tid; idx < npair * (k + l); idx += GNT) {
+                int i = idx % npair, e = idx / npair;
+                if (s_s[i] == 0.0) continue;
+                int a = s_p[i], b = s_q[i];
+                double cs = s_c[i], sn = s_s[i];
+                T ec = s_e[i];
+                T* pa; T* pb;
+                if (e < k) { pa = &M[e * c.xld + a]; pb = &M[e * c.xld + b]; }
+                else { int f = e - k; pa = &VM[f * l + a]; pb = &VM[f * l + b]; }
+                T u = *pa, w = *pb;
+                *pa = cs * u - sn * (ec * w);
+                *pb = sn * u + cs * (ec * w);
+            }
+            __syncthreads();
+        }
+        if (c.mi[MI_ROT] == 0) break;
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// Two-sided cyclic Jacobi on the Hermitian E (k x k, row-major ld k);
+// Z accumulates the eigenvectors (columns).
+template <class T>
+__device__ inline void jacobi_eig(GenCtx<T>& c, T* E, T* Z, int k)
+{
+    for (int idx = c.tid; idx < k * k; idx += GNT)
+        Z[idx] = (idx / k == idx % k) ? num<T>::one() : num<T>::zero();
+    if (c.tid == 0) {
+        double mx = 0;
+        for (int p = 0; p < k; ++p) mx = fmax(mx, fabs(num<T>::re(E[p * k + p])));
+        c.md[MD_MAXD] = mx;
+    }
+    __syncthreads();
+    const double scale = c.md[MD_MAXD];
+    const int np = k + (k & 1);
+    const int npair = np / 2;
+    __shared__ double s_c[128], s_s[128];
+    __shared__ T s_e[128];
+    __shared__ int s_p[128], s_q[128];
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        if (c.tid == 0) c.mi[MI_ROT] = 0;
+        __syncthreads();
+        for (int r = 0; r < np - 1; ++r) {
+            for (int i = c.tid; i < npair; i += GNT) {
+                int a, b;
+                rr_pair(np, r, i, a, b);
+                s_p[i] = a; s_q[i] = b; s_s[i] = 0.0; s_c[i] = 1.0;
+                if (b < k) {
+                    double al = num<T>::re(E[a * k + a]), be = num<T>::re(E[b * k + b]);
+                    T g = E[a * k + b];
+                    double ag = num<T>::abs(g);
+                    if (ag > 1e-15 * sqrt(fabs(al)) * sqrt(fabs(be)) && ag > 1e-300 + 1e-30 * scale) {
+                        double cs, sn; T ec;
+                        jrot<T>(al, be, g, cs, sn, ec);
+                        s_c[i] = cs; s_s[i] = sn; s_e[i] = ec;
+                        c.mi[MI_ROT] = 1;
+                    }
+                }
+            }
+            __syncthreads();
+            // rows: E[[a,b], :] <- J^* E[[a,b], :]
+            for (int idx = c.tid; idx < npair * k; idx += GNT) {
+                int i = idx % npair, e = idx / npair;
+                if (s_s[i] == 0.0) continue;
+                int a = s_p[i], b = s_q[i];
+                double cs = s_c[i], sn = s_s[i];
+                T ecc = num<T>::conj(s_e[i]);
+                T u = E[a * k + e], w = E[b * k + e];
+                E[a * k + e] = cs * u - sn * (ecc * w);
+                E[b * k + e] = sn * u + cs * (ecc * w);
+            }
+            __syncthreads();
+            // columns: E[:, [a,b]] <- E[:, [a,b]] J, Z likewise
+            for (int idx = c.tid; idx < npair * 2 * k; idx += GNT) {
+                int i = idx % npair, e = idx / npair;
+                if (s_s[i] == 0.0) continue;
+                int a = s_p[i], b = s_q[i];
+                double cs = s_c[i], sn = s_s[i];
+                T ec = s_e[i];
+                T* M = e < k ? E : Z;
+                int row = e < k ? e : e - k;
+                T u = M[row * k + a], w = M[row * k + b];
+                M[row * k + a] = cs * u - sn * (ec * w);
+                M[row * k + b] = sn * u + cs * (ec * w);
+            }
+            __syncthreads();
+        }
+        if (c.mi[MI_ROT] == 0) break;
+        __syncthreads();
+    }
+    __syncthreads();
+}
+
+// Top-q selection with the 1e-10 tie band over the m local rows;
+// sScore[i] = |(B w0)_i| for admissible rows and -1 otherwise (rows are in
+// ascending order).  Appends the chosen local rows, ascending, to sL from
+// index 1 (index 0 holds the diagonal).  Returns the count.
+template <class T>
+__device__ inline int select_topk(GenCtx<T>& c, int m, int nc, int q)
+{
+    if (q <= 0) return 0;
+    if (c.tid == 0) c.mi[MI_Q] = 0;
+    __syncthreads();
+    if (nc <= q) {
+        if (c.tid == 0) {
+            int cnt = 0;
+            for (int i = 0; i < m; ++i)
+                if (c.sScore[i] >= 0.0) c.sL[1 + cnt++] = i;
+            c.mi[MI_Q] = cnt;
+        }
+        __syncthreads();
+        int cnt = c.mi[MI_Q];
+        __syncthreads();
+        return cnt;
+    }
+    // rank of each candidate: larger score first, lower row on ties
+    for (int t = c.tid; t < m; t += GNT) {
+        double st = c.sScore[t];
+        if (st < 0.0) continue;
+        int rk = 0;
+        for (int u = 0; u < m; ++u) {
+            double su = c.sScore[u];
+            rk += (su > st) || (su == st && u < t);
+        }
+        if (rk == q - 1) c.md[MD_SSTAR] = st;
+    }
+    __syncthreads();
+    if (c.tid == 0) {
+        double ss = c.md[MD_SSTAR];
+        double hi = ss * (1.0 + 1e-10), lo = ss * (1.0 - 1e-10);
+        int cnt = 0;
+        for (int t = 0; t < m; ++t)
+            if (c.sScore[t] >= 0.0 && c.sScore[t] > hi) c.sSel[cnt++] = t;
+        for (int t = 0; t < m && cnt < q; ++t)
+            if (c.sScore[t] >= 0.0 && c.sScore[t] >= lo && c.sScore[t] <= hi) c.sSel[cnt++] = t;
+        int edge = 0;
+        for (int t = 0; t < m; ++t) {
+            if (c.sScore[t] < 0.0) continue;
+            double d1 = fabs(c.sScore[t] - hi), d2 = fabs(c.sScore[t] - lo);
+            if (ss > 0.0 && (d1 <= 1e-12 * ss || d2 <= 1e-12 * ss)) edge = 1;
+        }
+        if (edge) c.mi[MI_FLAGS] |= DIAF_FLAG_TIE_EDGE;
+        for (int a = 1; a < cnt; ++a) {  // ascending local row order
+            int v = c.sSel[a], b = a - 1;
+            while (b >= 0 && c.sSel[b] > v) { c.sSel[b + 1] = c.sSel[b]; --b; }
+            c.sSel[b + 1] = v;
+        }
+        for (int t = 0; t < cnt; ++t) c.sL[1 + t] = c.sSel[t];
+        c.mi[MI_Q] = cnt;
+    }
+    __syncthreads();
+    int cnt = c.mi[MI_Q];
+    __syncthreads();
+    return cnt;
+}
+
+template <class T>
+__device__ int find_local_row(const GenCtx<T>& c, int m, int row)
+{
+    int lo = 0, hi = m - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        int v = c.sR[mid];
+        if (v == row) return mid;
+        if (v < row) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+
+template <class T>
+__device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
+{
+    const int tid = c.tid;
+    const int jb = A.Jcp[j];
+    const int k = A.Jcp[j + 1] - jb;
+    // ---- 1. J_j and per-column offsets ----
+    if (tid == 0) { c.mi[MI_FLAGS] = 0; c.sOff[0] = 0; }
+    for (int a = tid; a < k; a += GNT) {
+        int col = A.Jri[jb + a];
+        c.sJ[a] = col;
+        c.sOff[a + 1] = A.Acp[col + 1] - A.Acp[col];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int a = 0; a < k; ++a) c.sOff[a + 1] += c.sOff[a];
+        c.mi[MI_T] = c.sOff[k];
+    }
+    __syncthreads();
+    const int Tn = c.mi[MI_T];
+    int T2 = 1;
+    while (T2 < Tn) T2 <<= 1;
+    // ---- 2. gather ----
+    for (int t = tid; t < T2; t += GNT) {
+        if (t < Tn) {
+            int lo = 0, hi = k - 1;  // largest a with sOff[a] <= t
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (c.sOff[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            int a = lo;
+            int p = A.Acp[c.sJ[a]] + (t - c.sOff[a]);
+            c.sKey[t] = ((uint64_t)(uint32_t)A.Ari[p] << 32) | (uint32_t)t;
+            c.sVal[t] = A.Aval[p];
+            c.sCol[t] = a;
+        } else {
+            c.sKey[t] = ~0ull;
+        }
+    }
+    __syncthreads();
+    // ---- 3. bitonic sort by (row, t) ----
+    for (int kk = 2; kk <= T2; kk <<= 1) {
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < T2; i += GNT) {
+                int ixj = i ^ jj;
+                if (ixj > i) {
+                    uint64_t x = c.sKey[i], y = c.sKey[ixj];
+                    bool up = (i & kk) == 0;
+                    if ((x > y) == up) { c.sKey[i] = y; c.sKey[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // ---- 4. shadow rows and CSR/CSC cross references ----
+    for (int i = tid; i < Tn; i += GNT)
+        c.sRank[i] = (i == 0 || (c.sKey[i] >> 32) != (c.sKey[i - 1] >> 32)) ? 1 : 0;
+    __syncthreads();
+    int m = block_scan_flags(c, c.sRank, c.sRank, Tn);
+    for (int i = tid; i < Tn; i += GNT) {
+        int lr = c.sRank[i] - 1;
+        int t = (int)(uint32_t)c.sKey[i];
+        c.sPos[i] = t;
+        c.sLrow[t] = lr;
+        if (i == 0 || (c.sKey[i] >> 32) != (c.sKey[i - 1] >> 32)) {
+            c.sR[lr] = (int)(c.sKey[i] >> 32);
+            c.sRowptr[lr] = i;
+        }
+    }
+    if (tid == 0) c.sRowptr[m] = Tn;
+    __syncthreads();
+    if (tid == 0) c.mi[MI_DJ] = find_local_row(c, m, j);
+    __syncthreads();
+    const int dj = c.mi[MI_DJ];
+    // ||B||_F
+    {
+        double s = 0;
+        for (int t = tid; t < Tn; t += GNT) s += num<T>::abs2(c.sVal[t]);
+        double bn2 = block_sum(c, s);
+        if (tid == 0) c.md[MD_BN2] = bn2;
+    }
+    const int lmax = A.lmax;
+    if (dj < 0) {
+        for (int a = tid; a < k; a += GNT) A.Wval[jb + a] = num<T>::zero();
+        for (int t = tid; t < lmax; t += GNT) {
+            A.Vrows[(size_t)j * lmax + t] = -1;
+            A.Vvals[(size_t)j * lmax + t] = num<T>::zero();
+        }
+        if (tid == 0) {
+            A.rcol[j] = 0.0;
+            A.bnorm[j] = sqrt(c.md[MD_BN2]);
+            A.flags[j] = DIAF_FLAG_NO_DIAG_ROW;
+            A.lcount[j] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    // ---- 5. Gram matrix G = B^* B by sparse merges ----
+    T* G = c.G;
+    for (int idx = tid; idx < k * k; idx += GNT) {
+        int a = idx / k, b = idx % k;
+        if (b < a) continue;
+        int pa = c.sOff[a], ea = c.sOff[a + 1], pb = c.sOff[b], eb = c.sOff[b + 1];
+        T acc = num<T>::zero();
+        if (A.gram_fp32) {
+            // variant: products and sums in FP32
+            float ax = 0.f, ay = 0.f;
+            while (pa < ea && pb < eb) {
+                int ra = c.sLrow[pa], rb = c.sLrow[pb];
+                if (ra == rb) {
+                    T va = c.sVal[pa], vb = c.sVal[pb];
+                    T pr = num<T>::cmul(va, vb);
+                    ax += (float)num<T>::re(pr);
+                    ay += (float)num<T>::im(pr);
+                    ++pa; ++pb;
+                } else if (ra < rb) ++pa; else ++pb;
+            }
+            if constexpr (num<T>::is_complex) acc = T{(double)ax, (double)ay};
+            else acc = (double)ax;
+        } else {
+            while (pa < ea && pb < eb) {
+                int ra = c.sLrow[pa], rb = c.sLrow[pb];
+                if (ra == rb) { acc += num<T>::cmul(c.sVal[pa], c.sVal[pb]); ++pa; ++pb; }
+                else if (ra < rb) ++pa;
+                else ++pb;
+            }
+        }
+        G[a * k + b] = acc;
+        G[b * k + a] = num<T>::conj(acc);
+    }
+    __syncthreads();
+
+    // ---- 6. V pattern ----
+    const bool topk = (A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER);
+    int l = 0;
+    if (A.mode == 0) cholesky(c, G, k);
+    if (topk) {
+        T* E = c.E; T* Z = c.Z;
+        if (A.mode == 0) {
+            // seed w0 = G^{-1} b_j^*  (V_0 = diagonals: the SPAI column)
+            for (int a = tid; a < k; a += GNT) c.sX[a * c.xld] = num<T>::zero();
+            __syncthreads();
+            for (int p = c.sRowptr[dj] + tid; p < c.sRowptr[dj + 1]; p += GNT) {
+                int t = c.sPos[p];
+                c.sX[c.sCol[t] * c.xld] = num<T>::conj(c.sVal[t]);
+            }
+            __syncthreads();
+            lsolve(c, G, k, c.sX, 1);
+            lhsolve(c, G, k, c.sX, 1);
+            for (int a = tid; a < k; a += GNT) c.sW[a] = c.sX[a * c.xld];
+            __syncthreads();
+        } else {
+            // seed: bottom eigenvector of G - b_j^* b_j
+            for (int idx = tid; idx < k * k; idx += GNT) {
+                int a = idx / k, b = idx % k;
+                E[idx] = G[idx] - num<T>::cmul(bget(c, dj, a), bget(c, dj, b));
+            }
+            __syncthreads();
+            jacobi_eig(c, E, Z, k);
+            if (tid == 0) {
+                int lo = 0;
+                for (int p = 1; p < k; ++p)
+                    if (num<T>::re(E[p * k + p]) < num<T>::re(E[lo * k + lo])) lo = p;
+                c.mi[MI_BEST] = lo;
+            }
+            __syncthreads();
+            const int lo = c.mi[MI_BEST];
+            for (int a = tid; a < k; a += GNT) c.sW[a] = Z[a * k + lo];
+            __syncthreads();
+        }
+        bmul(c, m, c.sW, c.sY);
+        // scores of the admissible rows (ascending row order); -1 elsewhere
+        int ncl = 0;
+        for (int i = tid; i < m; i += GNT) {
+            int gi = c.sR[i];
+            int adm = (A.vrule == V_TOPK_LOWER) ? (gi > j) : (gi < j);
+            c.sScore[i] = adm ? num<T>::abs(c.sY[i]) : -1.0;
+            ncl += adm;
+        }
+        int nc = (int)block_sum(c, (double)ncl);
+        int lj = A.vcount < 1 ? 1 : A.vcount;
+        if (lj > 1 + nc) lj = 1 + nc;
+        if (A.mode == 1) {
+            int cap = m - k > 1 ? m - k : 1;
+            if (lj > cap) lj = cap;
+        }
+        if (lj > lmax) lj = lmax;
+        if (tid == 0) c.sL[0] = dj;
+        __syncthreads();
+        int nsel = select_topk(c, m, nc, lj - 1);
+        l = 1 + nsel;
+    } else {
+        if (tid == 0) {
+            int cnt = 0;
+            if (A.vrule == V_DIAG) {
+                c.sL[cnt++] = dj;
+            } else if (A.vrule == V_GS_UPPER || A.vrule == V_GS_LOWER) {
+                for (int p = A.Acp[j]; p < A.Acp[j + 1]; ++p) {
+                    int gi = A.Ari[p];
+                    bool keep = gi == j || (A.vrule == V_GS_UPPER ? gi < j : gi > j);
+                    if (!keep) continue;
+                    int lr = find_local_row(c, m, gi);
+                    if (lr >= 0 && cnt < lmax) c.sL[cnt++] = lr;
+                }
+            } else {
+                for (int p = A.Vcp_in[j]; p < A.Vcp_in[j + 1]; ++p) {
+                    int lr = find_local_row(c, m, A.Vri_in[p]);
+                    if (lr >= 0 && cnt < lmax) c.sL[cnt++] = lr;
+                }
+            }
+            c.mi[MI_L] = cnt;
+        }
+        __syncthreads();
+        l = c.mi[MI_L];
+        __syncthreads();
+    }
+
+    // ---- 7. final solve on (J_j, L_j) ----
+    if (A.mode == 0) {
+        // M = L^{-1} B_L^*  (k x l)
+        for (int idx = tid; idx < k * l; idx += GNT) {
+            int a = idx / l, t = idx % l;
+            c.sX[a * c.xld + t] = num<T>::conj(bget(c, c.sL[t], a));
+        }
+        __syncthreads();
+        lsolve(c, G, k, c.sX, l);
+        jacobi_onesided(c, c.sX, k, l, c.sVM);
+        for (int t = tid; t < l; t += GNT) {
+            double s = 0;
+            for (int a = 0; a < k; ++a) s += num<T>::abs2(c.sX[a * c.xld + t]);
+            c.sSig[t] = sqrt(s);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int best = 0;
+            for (int t = 1; t < l; ++t) if (c.sSig[t] > c.sSig[best]) best = t;
+            double s1 = c.sSig[best], s2 = 0;
+            for (int t = 0; t < l; ++t) if (t != best && c.sSig[t] > s2) s2 = c.sSig[t];
+            double gap = (l >= 2 && s1 > 0) ? (s1 * s1 - s2 * s2) / (s1 * s1) : 1.0;
+            if (gap < 1e-6) c.mi[MI_FLAGS] |= DIAF_FLAG_GAP_DEGENERATE;
+            c.mi[MI_BEST] = best;
+        }
+        __syncthreads();
+        const int best = c.mi[MI_BEST];
+        for (int t = tid; t < l; t += GNT) c.sV[t] = c.sVM[t * l + best];
+        // u = M v = (rotated M)(:, best); w = L^{-*} u
+        for (int a = tid; a < k; a += GNT) c.sX[a * c.xld + l] = c.sX[a * c.xld + best];
+        __syncthreads();
+        for (int a = tid; a < k; a += GNT) c.sX[a * c.xld] = c.sX[a * c.xld + l];
+        __syncthreads();
+        lhsolve(c, G, k, c.sX, 1);
+        for (int a = tid; a < k; a += GNT) c.sW[a] = c.sX[a * c.xld];
+        __syncthreads();
+    } else {
+        T* E = c.E; T* Z = c.Z;
+        for (int idx = tid; idx < k * k; idx += GNT) {
+            int a = idx / k, b = idx % k;
+            T acc = G[idx];
+            for (int t = 0; t < l; ++t) acc -= num<T>::cmul(bget(c, c.sL[t], a), bget(c, c.sL[t], b));
+            E[idx] = acc;
+        }
+        __syncthreads();
+        jacobi_eig(c, E, Z, k);
+        if (tid == 0) {
+            int lo = 0, hi = 0;
+            for (int p = 1; p < k; ++p) {
+                double d = num<T>::re(E[p * k + p]);
+                if (d < num<T>::re(E[lo * k + lo])) lo = p;
+                if (d > num<T>::re(E[hi * k + hi])) hi = p;
+            }
+            double l1 = num<T>::re(E[lo * k + lo]), lmx = num<T>::re(E[hi * k + hi]);
+            double l2 = INFINITY;
+            for (int p = 0; p < k; ++p)
+                if (p != lo) l2 = fmin(l2, num<T>::re(E[p * k + p]));
+            double gap = (k >= 2 && lmx > 0) ? (l2 - l1) / lmx : 1.0;
+            if (gap < 1e-6) c.mi[MI_FLAGS] |= DIAF_FLAG_GAP_DEGENERATE;
+            if (m - l < k || l1 <= 1e-14 * lmx) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
+            c.mi[MI_BEST] = lo;
+        }
+        __syncthreads();
+        const int lo = c.mi[MI_BEST];
+        for (int a = tid; a < k; a += GNT) c.sW[a] = Z[a * k + lo];
+        __syncthreads();
+        bmul(c, m, c.sW, c.sY);
+        for (int t = tid; t < l; t += GNT) c.sV[t] = c.sY[c.sL[t]];
+        __syncthreads();
+    }
+
+    // ---- 8. phase, residual, outputs ----
+    if (tid == 0) {
+        double vn2 = 0;
+        for (int t = 0; t < l; ++t) vn2 += num<T>::abs2(c.sV[t]);
+        double vn = sqrt(vn2);
+        int dpos = -1;
+        for (int t = 0; t < l; ++t) if (c.sL[t] == dj) dpos = t;
+        int piv = 0;
+        if (dpos >= 0 && num<T>::abs(c.sV[dpos]) >= 1e-8 * vn) {
+            piv = dpos;
+        } else {
+            double bestv = -1.0;
+            int bestrow = 0;
+            for (int t = 0; t < l; ++t) {
+                double a = num<T>::abs(c.sV[t]);
+                int gr = c.sR[c.sL[t]];
+                if (a > bestv || (a == bestv && gr < bestrow)) { bestv = a; bestrow = gr; piv = t; }
+            }
+        }
+        T ph = num<T>::one();
+        if (!num<T>::iszero(c.sV[piv])) ph = unit_conj_phase(c.sV[piv]);
+        for (int t = 0; t < l; ++t) c.sV[t] = ph * c.sV[t];
+        for (int a = 0; a < k; ++a) c.sW[a] = ph * c.sW[a];
+        if (dpos < 0 || num<T>::abs(c.sV[dpos]) < 1e-2 * vn) c.mi[MI_FLAGS] |= DIAF_FLAG_SMALL_DIAG;
+    }
+    __syncthreads();
+    bmul(c, m, c.sW, c.sY);
+    if (tid == 0)
+        for (int t = 0; t < l; ++t) c.sY[c.sL[t]] -= c.sV[t];
+    __syncthreads();
+    double s = 0;
+    for (int i = tid; i < m; i += GNT) s += num<T>::abs2(c.sY[i]);
+    double r2 = block_sum(c, s);
+    for (int a = tid; a < k; a += GNT) A.Wval[jb + a] = c.sW[a];
+    if (tid == 0) {
+        // V column sorted by row (local order = global order)
+        for (int a = 1; a < l; ++a) {
+            int key = c.sL[a];
+            T vv = c.sV[a];
+            int b = a - 1;
+            while (b >= 0 && c.sL[b] > key) { c.sL[b + 1] = c.sL[b]; c.sV[b + 1] = c.sV[b]; --b; }
+            c.sL[b + 1] = key;
+            c.sV[b + 1] = vv;
+        }
+        for (int t = 0; t < lmax; ++t) {
+            A.Vrows[(size_t)j * lmax + t] = t < l ? c.sR[c.sL[t]] : -1;
+            A.Vvals[(size_t)j * lmax + t] = t < l ? c.sV[t] : num<T>::zero();
+        }
+        A.rcol[j] = sqrt(r2);
+        A.bnorm[j] = sqrt(c.md[MD_BN2]);
+        A.flags[j] = (uint32_t)c.mi[MI_FLAGS];
+        A.lcount[j] = l;
+    }
+    __syncthreads();
+}
+
+template <class T, bool IN_LDS>
+__global__ void __launch_bounds__(GNT) factor_generic_kernel(FactorArgs<T> A, int kcap, int tcap,
+                                                             int tcap2, int lcap, int mats_here,
+                                                             unsigned char* gws, size_t slot_bytes,
+                                                             T* gmats)
+{
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    unsigned char* base = IN_LDS ? lds_dyn : gws + (size_t)blockIdx.x * slot_bytes;
+    GenLayout Lo = gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), mats_here);
+    GenCtx<T> c;
+    c.tid = threadIdx.x;
+    c.sJ = (int32_t*)(base + Lo.oJ);
+    c.sOff = (int32_t*)(base + Lo.oOff);
+    c.sKey = (uint64_t*)(base + Lo.oKey);
+    c.sScore = (double*)(base + Lo.oKey);
+    c.sVal = (T*)(base + Lo.oVal);
+    c.sLrow = (uint16_t*)(base + Lo.oLrow);
+    c.sCol = (uint16_t*)(base + Lo.oCol);
+    c.sPos = (uint16_t*)(base + Lo.oPos);
+    c.sRowptr = (uint16_t*)(base + Lo.oRowptr);
+    c.sR = (int32_t*)(base + Lo.oR);
+    c.sRank = (int32_t*)(base + Lo.oRank);
+    c.sY = (T*)(base + Lo.oY);
+    c.sW = (T*)(base + Lo.oW);
+    c.sX = (T*)(base + Lo.oX);
+    c.sVM = (T*)(base + Lo.oVM);
+    c.sSig = (double*)(base + Lo.oSig);
+    c.sV = (T*)(base + Lo.oV);
+    c.sL = (int32_t*)(base + Lo.oL);
+    c.sSel = (int32_t*)(base + Lo.oSel);
+    c.sRed = (double*)(base + Lo.oRed);
+    c.mi = (int*)(base + Lo.oMisc);
+    c.md = (double*)(base + Lo.oMisc);
+    c.xld = lcap + 1;
+    const size_t kk = (size_t)kcap * kcap;
+    T* mats = mats_here ? (T*)(base + Lo.oMats) : gmats + (size_t)blockIdx.x * 3 * kk;
+    c.G = mats;
+    c.E = mats + kk;
+    c.Z = mats + 2 * kk;
+    for (int q = blockIdx.x; q < A.ncols; q += gridDim.x) factor_one_column(A, A.cols[q], c);
+}
+
+template <class T>
+size_t generic_lds_bytes(int kcap, int tcap, int lcap, int with_mats)
+{
+    int tcap2 = 1;
+    while (tcap2 < tcap) tcap2 <<= 1;
+    return gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), with_mats).total;
+}
+
+// Placement of a size class: working set in LDS (with or without the k x k
+// matrices) when it fits, otherwise a per-block slot of global memory.
+struct GenPlan {
+    bool in_lds;
+    bool mats_here;
+    size_t lds_bytes;   // dynamic LDS
+    size_t slot_bytes;  // global slot per block (in_lds == false)
+    bool need_gmats;    // separate global k x k matrices
+};
+
+template <class T>
+GenPlan generic_plan(int kcap, int tcap, int lcap)
+{
+    GenPlan P{};
+    size_t with = generic_lds_bytes<T>(kcap, tcap, lcap, 1);
+    size_t without = generic_lds_bytes<T>(kcap, tcap, lcap, 0);
+    if (with <= 64 * 1024) {
+        P.in_lds = true; P.mats_here = true; P.lds_bytes = with;
+    } else if (without <= 96 * 1024) {
+        P.in_lds = true; P.mats_here = false; P.lds_bytes = without; P.need_gmats = true;
+    } else {
+        P.in_lds = false; P.mats_here = true; P.slot_bytes = (with + 255) & ~size_t(255);
+    }
+    return P;
+}
+
+template <class T>
+size_t generic_global_bytes(int kcap, int tcap, int lcap, int nslots)
+{
+    GenPlan P = generic_plan<T>(kcap, tcap, lcap);
+    if (P.in_lds && !P.need_gmats) return 0;
+    if (P.need_gmats) return sizeof(T) * 3 * (size_t)kcap * kcap * nslots;
+    return P.slot_bytes * nslots;
+}
+
+template <class T>
+Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, void* gws,
+                          int nslots, hipStream_t st)
+{
+    if (A.ncols == 0) return {};
+    if (tcap > 65535) return {DIAF_EUNSUPPORTED, "column too large"};
+    int tcap2 = 1;
+    while (tcap2 < tcap) tcap2 <<= 1;
+    GenPlan P = generic_plan<T>(kcap, tcap, lcap);
+    int grid = A.ncols;
+    if (!(P.in_lds && !P.need_gmats)) {
+        if (!gws) return {DIAF_EINVAL, "generic factor: workspace missing"};
+        if (grid > nslots) grid = nslots;
+    }
+    if (grid > 65535 * 8) grid = 65535 * 8;
+    if (P.in_lds) {
+        auto kern = factor_generic_kernel<T, true>;
+        DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)P.lds_bytes));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(GNT), P.lds_bytes, st, A, kcap, tcap, tcap2, lcap,
+                           (int)P.mats_here, (unsigned char*)nullptr, (size_t)0, (T*)gws);
+    } else {
+        auto kern = factor_generic_kernel<T, false>;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(GNT), 0, st, A, kcap, tcap, tcap2, lcap, 1,
+                           (unsigned char*)gws, P.slot_bytes, (T*)nullptr);
+    }
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+template Err launch_factor_generic<double>(const FactorArgs<double>&, int, int, int, void*, int,
+                                           hipStream_t);
+template Err launch_factor_generic<zc>(const FactorArgs<zc>&, int, int, int, void*, int, hipStream_t);
+template size_t generic_global_bytes<double>(int, int, int, int);
+template size_t generic_global_bytes<zc>(int, int, int, int);
+
+}  // namespace diaf

@@ -1,0 +1,132 @@
+// Launchers exported by the kernel files to the API layer.
+#pragma once
+
+#include "dcommon.h"
+
+namespace diaf {
+
+// ---- patterns (pattern.hip) ----
+// cnt[j] = sum over c in rows(A(:,j)) of nnz(A(:,c)); *maxcnt_dev = max.
+Err launch_cand_count(int n, const int32_t* Acp, const int32_t* Ari, int32_t* cnt,
+                      int32_t* maxcnt_dev, hipStream_t st);
+// Symbolic pattern(A^2): count (rowidx == nullptr: writes cnt[j]) or fill.
+Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand, int32_t* cnt,
+                      const int32_t* Jcp, int32_t* Jri, hipStream_t st);
+// pattern(A) plus the ptop two-hop rows of largest |A|^2 path weight.
+template <class T>
+Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
+                        int maxcand, int32_t* cnt, const int32_t* Jcp, int32_t* Jri,
+                        hipStream_t st);
+// Per-column sizes for bucketing: k[j] = |J_j|, t[j] = sum nnz(A(:, J_j)).
+Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int32_t* Jri,
+                        int32_t* kout, int32_t* tout, hipStream_t st);
+
+// ---- factoring (factor_generic.hip, factor_small.hip) ----
+// gws: global workspace of generic_global_bytes(...) bytes (may be null when
+// that is 0); nslots = number of blocks sharing it.
+template <class T>
+Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, void* gws,
+                          int nslots, hipStream_t st);
+template <class T>
+size_t generic_global_bytes(int kcap, int tcap, int lcap, int nslots);
+
+// ---- assembly and sparse utilities (sparse.hip) ----
+// Exclusive scan of n ints into out[n+1] (out[n] = total); temp via hipcub.
+Err exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t st);
+template <class T>
+Err launch_compact_v(int n, int lmax, const int32_t* lcount, const int32_t* Vcp,
+                     const int32_t* Vrows, const T* Vvals, int32_t* Vri, T* Vval, hipStream_t st);
+// CSC -> CSR transpose with rows sorted by column (deterministic).
+template <class T>
+Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T* val,
+               int32_t* rp, int32_t* ci, T* cval, hipStream_t st);
+// Validation of a CSC input: sorted unique in-range rows, diagonal present,
+// finite values.  *bad_dev receives a nonzero code for the first problem.
+template <class T>
+Err launch_validate_csc(int n, const int32_t* cp, const int32_t* ri, const T* val,
+                        int32_t* bad_dev, hipStream_t st);
+Err launch_validate_pattern(int n, const int32_t* cp, const int32_t* ri, int need_diag,
+                            int32_t* bad_dev, hipStream_t st);
+template <class T>
+Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* counts_dev,
+                      double* nrm2_dev, hipStream_t st);
+
+// ---- solve (solve.hip) ----
+struct TrsvCtl {
+    uint32_t ticket;
+    uint32_t finished;
+    uint32_t epoch;
+    uint32_t error;
+};
+
+template <class T>
+struct BicgState {
+    T rho, rho_prev, alpha, omega, beta, ts;
+    double bnorm, tol, res, tt;
+    int32_t it, maxit, done, flag, half, omega_bad;
+    uint32_t red_ticket;
+    int32_t pad;
+};
+
+template <class T>
+Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
+                    const int32_t* done, hipStream_t st);
+template <class T>
+Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
+                T* x, uint32_t* ready, TrsvCtl* ctl, const int32_t* done, hipStream_t st);
+template <class T>
+Err launch_diag_solve(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* b, T* x,
+                      const int32_t* done, hipStream_t st);
+// Depth of the triangular dependency DAG (levels) computed on the device.
+Err launch_trsv_levels(int n, const int32_t* rp, const int32_t* ci, int upper, int32_t* level,
+                       uint32_t* ready, TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st);
+
+// BiCGSTAB stage kernels; every one is a no-op once st->done is set.
+template <class T>
+struct BicgVecs {
+    int n;
+    const T* b;
+    T *x, *r, *rh, *p, *v, *ph, *s, *sh, *t;
+    double* partial;  // reduction scratch (>= 2 * nblocks doubles, complex: 4x)
+    BicgState<T>* st;
+};
+template <class T> Err bicg_init(const BicgVecs<T>& V, double tol, int maxit, hipStream_t st);
+template <class T> Err bicg_rho(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_update_p(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_alpha(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_s(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_omega(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_xr(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_true_residual(const BicgVecs<T>& V, hipStream_t st);
+template <class T> Err bicg_half_fix(const BicgVecs<T>& V, hipStream_t st);
+
+// ---- learned proposer (learned.hip) ----
+template <class T>
+Err launch_features(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
+                    const int32_t* Ccp, const int32_t* Cri, float* feat, hipStream_t st);
+template <class T>
+Err launch_labels(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, const int32_t* Jcp,
+                  const int32_t* Jri, const T* Wval, double tau, float* labels, hipStream_t st);
+Err launch_mlp_forward(const float* params, const float* feat, int64_t npairs, float* scores,
+                       hipStream_t st);
+Err launch_mlp_loss_grad(const float* params, const float* feat, const float* labels,
+                         int64_t npairs, float* grad, double* loss_dev, float* scratch,
+                         hipStream_t st);
+size_t mlp_scratch_floats();
+Err launch_adam(float* params, const float* grad, float* m, float* v, int step, float lr,
+                hipStream_t st);
+// J_j = {j} U {i in C_j : score >= 0} (sigmoid >= 0.5); count / fill.
+Err launch_pattern_from_scores(int n, const int32_t* Ccp, const int32_t* Cri,
+                               const float* scores, int32_t* cnt, const int32_t* Jcp,
+                               int32_t* Jri, hipStream_t st);
+
+// Residual-gated fallback (learned.hip).
+Err launch_fallback_count(int n, const int32_t* Jcp, const int32_t* Ccp, const uint8_t* fb,
+                          int32_t* cnt, hipStream_t st);
+template <class T>
+Err launch_fallback_fill(int n, const int32_t* Jcp, const int32_t* Jri, const T* Wval,
+                         const int32_t* Ccp, const int32_t* Cri, const uint8_t* fb,
+                         const int32_t* Jcp2, int32_t* Jri2, T* Wval2, uint32_t* flags,
+                         hipStream_t st);
+
+}  // namespace diaf

@@ -1,0 +1,340 @@
+// W-pattern construction (paper Section 4).
+//
+// pattern(A^2) is the truncated Neumann series W = I + S + S^2 pattern of
+// Section 4.1 with V_0 = diagonals, truncation 2 and no dropping, taken
+// symbolically: column j is the union of the row sets of A(:, c) over
+// c in rows(A(:, j)).  The 1-hop top-p pattern keeps pattern(A) and adds the
+// p two-hop rows i with the largest |A|^2 path weight sum_c |a_ic||a_cj|
+// (numerical dropping by count, Section 4.1); products are formed and
+// summed in ascending c with explicit round-to-nearest operations so the
+// scores are reproducible bit for bit, ties going to the lower row.
+//
+// Each column is one workgroup: candidates are gathered into LDS, sorted
+// with a bitonic network and deduplicated.  A first launch counts, a
+// second fills the rows at the scanned offsets.
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+namespace diaf {
+
+__global__ void cand_count_kernel(int n, const int32_t* Acp, const int32_t* Ari, int32_t* cnt,
+                                  int32_t* maxcnt)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = 0;
+    if (j < n) {
+        for (int p = Acp[j]; p < Acp[j + 1]; ++p) {
+            int c = Ari[p];
+            s += Acp[c + 1] - Acp[c];
+        }
+        cnt[j] = s;
+    }
+    // wave max then one atomic per wave
+    for (int o = 32; o > 0; o >>= 1) s = max(s, __shfl_xor(s, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxcnt, s);
+}
+
+Err launch_cand_count(int n, const int32_t* Acp, const int32_t* Ari, int32_t* cnt,
+                      int32_t* maxcnt_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(cand_count_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Ari, cnt,
+                       maxcnt_dev);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+__global__ void column_sizes_kernel(int n, const int32_t* Acp, const int32_t* Jcp,
+                                    const int32_t* Jri, int32_t* kout, int32_t* tout)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int k = Jcp[j + 1] - Jcp[j];
+    int t = 0;
+    for (int a = 0; a < k; ++a) {
+        int c = Jri[Jcp[j] + a];
+        t += Acp[c + 1] - Acp[c];
+    }
+    kout[j] = k;
+    tout[j] = t;
+}
+
+Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int32_t* Jri,
+                        int32_t* kout, int32_t* tout, hipStream_t st)
+{
+    hipLaunchKernelGGL(column_sizes_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Jcp,
+                       Jri, kout, tout);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// Bitonic sort of keys[0..N2) (N2 a power of two) by the whole block.
+template <class K>
+__device__ inline void block_bitonic(K* keys, int N2)
+{
+    for (int kk = 2; kk <= N2; kk <<= 1) {
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+                int ixj = i ^ jj;
+                if (ixj > i) {
+                    K x = keys[i], y = keys[ixj];
+                    bool up = (i & kk) == 0;
+                    if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Block-wide exclusive scan of 0/1 flags in place (returns total).
+__device__ inline int block_scan01(int32_t* f, int cnt, int32_t* red)
+{
+    int nt = blockDim.x, tid = threadIdx.x;
+    int chunk = (cnt + nt - 1) / nt;
+    int b = tid * chunk, e = min(cnt, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i) s += f[i];
+    red[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        int acc = 0;
+        for (int t = 0; t < nt; ++t) { int v = red[t]; red[t] = acc; acc += v; }
+        red[nt] = acc;
+    }
+    __syncthreads();
+    int run = red[tid];
+    for (int i = b; i < e; ++i) { int v = f[i]; f[i] = run; run += v; }
+    __syncthreads();
+    int tot = red[nt];
+    __syncthreads();
+    return tot;
+}
+
+// pattern(A^2), one block per column; cap candidates max (power of two),
+// dynamic LDS: keys[cap] u32, off[cap+1] i32, red[nthreads+1] i32.
+__global__ void pattern_a2_kernel(int n, const int32_t* Acp, const int32_t* Ari, int cap,
+                                  int32_t* cnt, const int32_t* Jcp, int32_t* Jri)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint32_t* keys = (uint32_t*)lds;
+    int32_t* off = (int32_t*)(keys + cap);
+    int32_t* red = off + cap + 1;
+    __shared__ int32_t s_tot;
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int a0 = Acp[j], na = Acp[j + 1] - a0;
+    if (tid == 0) {
+        off[0] = 0;
+        for (int q = 0; q < na; ++q) {
+            int c = Ari[a0 + q];
+            off[q + 1] = off[q] + (Acp[c + 1] - Acp[c]);
+        }
+        s_tot = off[na];
+    }
+    __syncthreads();
+    const int T = s_tot;
+    int T2 = 1;
+    while (T2 < T) T2 <<= 1;
+    for (int t = tid; t < T2; t += blockDim.x) {
+        if (t < T) {
+            int lo = 0, hi = na - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            int c = Ari[a0 + lo];
+            keys[t] = (uint32_t)Ari[Acp[c] + (t - off[lo])];
+        } else {
+            keys[t] = 0xffffffffu;
+        }
+    }
+    __syncthreads();
+    block_bitonic(keys, T2);
+    // unique flags into off[] (reused)
+    for (int t = tid; t < T; t += blockDim.x) off[t] = (t == 0 || keys[t] != keys[t - 1]) ? 1 : 0;
+    __syncthreads();
+    int m = block_scan01(off, T, red);
+    if (!Jri) {
+        if (tid == 0) cnt[j] = m;
+        return;
+    }
+    int32_t* out = Jri + Jcp[j];
+    for (int t = tid; t < T; t += blockDim.x)
+        if (t == 0 || keys[t] != keys[t - 1]) out[off[t]] = (int32_t)keys[t];
+}
+
+static int pow2_at_least(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand, int32_t* cnt,
+                      const int32_t* Jcp, int32_t* Jri, hipStream_t st)
+{
+    if (n == 0) return {};
+    int cap = pow2_at_least(maxcand < 64 ? 64 : maxcand);
+    if (cap > 16384) return {DIAF_EUNSUPPORTED, "pattern(A^2): more than 16384 candidates in a column"};
+    int nt = cap <= 256 ? 64 : (cap <= 4096 ? 256 : 1024);
+    size_t lds = sizeof(uint32_t) * cap + sizeof(int32_t) * (cap + 1) + sizeof(int32_t) * (nt + 1);
+    DIAF_HIP_TRY(hipFuncSetAttribute((const void*)pattern_a2_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(pattern_a2_kernel, dim3(n), dim3(nt), lds, st, n, Acp, Ari, cap, cnt, Jcp,
+                       Jri);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// pattern(A) + top-p two-hop rows.  Keys: (row << 32) | gather position;
+// gather positions follow ascending c, so equal rows sort by ascending c.
+// Dynamic LDS: keys[cap] u64, prod[cap] f64, sc[cap] f64, off[cap+1] i32,
+// scrow[cap] i32, red[nthreads+1] i32, sel[256] i32.
+template <class T>
+__global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
+                                    int ptop, int cap, int32_t* cnt, const int32_t* Jcp,
+                                    int32_t* Jri)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    uint64_t* keys = (uint64_t*)lds;
+    double* prod = (double*)(keys + cap);
+    double* sc = prod + cap;
+    int32_t* off = (int32_t*)(sc + cap);
+    int32_t* scrow = off + cap + 1;
+    int32_t* red = scrow + cap;
+    int32_t* sel = red + blockDim.x + 1;
+    __shared__ int32_t s_tot, s_nsel;
+    const int j = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int a0 = Acp[j], na = Acp[j + 1] - a0;
+    if (tid == 0) {
+        off[0] = 0;
+        for (int q = 0; q < na; ++q) {
+            int c = Ari[a0 + q];
+            off[q + 1] = off[q] + (Acp[c + 1] - Acp[c]);
+        }
+        s_tot = off[na];
+    }
+    __syncthreads();
+    const int Tn = s_tot;
+    int T2 = 1;
+    while (T2 < Tn) T2 <<= 1;
+    for (int t = tid; t < T2; t += blockDim.x) {
+        if (t < Tn) {
+            int lo = 0, hi = na - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            int c = Ari[a0 + lo];
+            int p = Acp[c] + (t - off[lo]);
+            double aic, acj;
+            if constexpr (num<T>::is_complex) {
+                T x = Aval[p], y = Aval[a0 + lo];
+                aic = __dsqrt_rn(__dadd_rn(__dmul_rn(x.x, x.x), __dmul_rn(x.y, x.y)));
+                acj = __dsqrt_rn(__dadd_rn(__dmul_rn(y.x, y.x), __dmul_rn(y.y, y.y)));
+            } else {
+                aic = fabs(Aval[p]);
+                acj = fabs(Aval[a0 + lo]);
+            }
+            prod[t] = __dmul_rn(aic, acj);
+            keys[t] = ((uint64_t)(uint32_t)Ari[p] << 32) | (uint32_t)t;
+        } else {
+            keys[t] = ~0ull;
+        }
+    }
+    __syncthreads();
+    block_bitonic(keys, T2);
+    // segment starts of rows outside pattern(A(:, j)) are the candidates
+    for (int t = tid; t < Tn; t += blockDim.x) {
+        int row = (int)(keys[t] >> 32);
+        int start = (t == 0 || (keys[t] >> 32) != (keys[t - 1] >> 32));
+        int inA = 0;
+        if (start) {
+            int lo = a0, hi = a0 + na - 1;
+            while (lo <= hi) {
+                int mid = (lo + hi) >> 1;
+                int v = Ari[mid];
+                if (v == row) { inA = 1; break; }
+                if (v < row) lo = mid + 1; else hi = mid - 1;
+            }
+        }
+        off[t] = (start && !inA) ? 1 : 0;
+    }
+    __syncthreads();
+    const int nc = block_scan01(off, Tn, red);
+    // score = sequential sum of the segment's products in ascending c
+    for (int t = tid; t < Tn; t += blockDim.x) {
+        int slot = off[t];
+        int isc = (t + 1 < Tn ? off[t + 1] : nc) != slot;
+        if (!isc) continue;
+        int row = (int)(keys[t] >> 32);
+        double s = 0.0;
+        for (int u = t; u < Tn && (int)(keys[u] >> 32) == row; ++u)
+            s = __dadd_rn(s, prod[(uint32_t)keys[u]]);
+        sc[slot] = s;
+        scrow[slot] = row;
+    }
+    if (tid == 0) s_nsel = 0;
+    __syncthreads();
+    // rank-based top-ptop: larger score first, lower row on ties
+    const int take = nc < ptop ? nc : ptop;
+    for (int s = tid; s < nc; s += blockDim.x) {
+        double v = sc[s];
+        int row = scrow[s];
+        int rk = 0;
+        for (int u = 0; u < nc && rk < take; ++u) {
+            double w = sc[u];
+            rk += (w > v) || (w == v && scrow[u] < row);
+        }
+        if (rk < take) sel[atomicAdd(&s_nsel, 1)] = row;
+    }
+    __syncthreads();
+    // output = sorted(rows(A(:, j)) U sel)
+    const int tot = na + take;
+    int N2 = 1;
+    while (N2 < tot) N2 <<= 1;
+    for (int t = tid; t < N2; t += blockDim.x) {
+        uint64_t kv = ~0ull;
+        if (t < na) kv = (uint32_t)Ari[a0 + t];
+        else if (t < tot) kv = (uint32_t)sel[t - na];
+        keys[t] = kv;
+    }
+    __syncthreads();
+    block_bitonic(keys, N2);
+    if (!Jri) {
+        if (tid == 0) cnt[j] = tot;
+        return;
+    }
+    int32_t* out = Jri + Jcp[j];
+    for (int t = tid; t < tot; t += blockDim.x) out[t] = (int32_t)keys[t];
+}
+
+template <class T>
+Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
+                        int maxcand, int32_t* cnt, const int32_t* Jcp, int32_t* Jri,
+                        hipStream_t st)
+{
+    if (n == 0) return {};
+    if (ptop > 256 || ptop < 0) return {DIAF_EUNSUPPORTED, "1-hop pattern: 0..256 extra rows"};
+    // the output merge also sorts na + ptop keys in the same buffer
+    int cap = pow2_at_least(maxcand + 257 < 256 ? 256 : maxcand + 257);
+    if (cap > 4096) return {DIAF_EUNSUPPORTED, "1-hop pattern: more than 3839 two-hop candidates in a column"};
+    int nt = cap <= 512 ? 128 : 256;
+    size_t lds = (sizeof(uint64_t) + 2 * sizeof(double) + 2 * sizeof(int32_t)) * cap +
+                 sizeof(int32_t) * (1 + nt + 1 + 256);
+    auto kern = pattern_1hop_kernel<T>;
+    DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+    hipLaunchKernelGGL(kern, dim3(n), dim3(nt), lds, st, n, Acp, Ari, Aval, ptop, cap, cnt, Jcp,
+                       Jri);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+template Err launch_pattern_1hop<double>(int, const int32_t*, const int32_t*, const double*, int,
+                                         int, int32_t*, const int32_t*, int32_t*, hipStream_t);
+template Err launch_pattern_1hop<zc>(int, const int32_t*, const int32_t*, const zc*, int, int,
+                                     int32_t*, const int32_t*, int32_t*, hipStream_t);
+
+}  // namespace diaf

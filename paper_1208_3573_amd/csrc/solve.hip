@@ -1,0 +1,541 @@
+// Apply M = W V^{-1} (eq. 2.1) and right-preconditioned BiCGSTAB
+// (Section 5).
+//
+// * SpMV: CSR, one thread per row.
+// * Triangular solve with V: sync-free, one wave per chunk of 64 rows.  A
+//   chunk is taken from an atomic ticket in dependency order (ascending
+//   rows for lower V, descending for upper V), so every row a wave waits on
+//   belongs to the same wave or to a wave that started earlier; waiting is
+//   a wave-uniform polling loop (no lane blocks inside it) with an
+//   iteration cap that raises an error flag, so every wave always exits.
+//   Readiness flags carry the launch's epoch, so they never need clearing.
+// * BiCGSTAB runs on the device: each stage is a kernel that returns at
+//   once when the solve has finished, reductions are two-stage in a fixed
+//   order (the last block to finish sums the per-block partials and updates
+//   the scalar state), and the host only polls the state between batches of
+//   iterations.
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+namespace diaf {
+
+// ---------------------------------------------------------------------------
+// SpMV y = X x (CSR)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void spmv_csr_kernel(int n, const int32_t* rp, const int32_t* ci, const T* val,
+                                const T* x, T* y, const int32_t* done)
+{
+    if (done && *done) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T acc = num<T>::zero();
+    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += val[p] * x[ci[p]];
+    y[i] = acc;
+}
+
+template <class T>
+Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
+                    const int32_t* done, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(spmv_csr_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci, val,
+                       x, y, done);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal V
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void diag_solve_kernel(int n, const int32_t* rp, const int32_t* ci, const T* val,
+                                  const T* b, T* x, const int32_t* done)
+{
+    if (done && *done) return;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    T d = num<T>::zero();
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) d = val[p];
+    T bi = b[i];
+    if constexpr (num<T>::is_complex) {
+        double den = d.x * d.x + d.y * d.y;
+        x[i] = T{(bi.x * d.x + bi.y * d.y) / den, (bi.y * d.x - bi.x * d.y) / den};
+    } else {
+        x[i] = bi / d;
+    }
+}
+
+template <class T>
+Err launch_diag_solve(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* b, T* x,
+                      const int32_t* done, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(diag_solve_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci,
+                       val, b, x, done);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// Sync-free triangular solve
+// ---------------------------------------------------------------------------
+__device__ inline uint32_t load_acquire(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_release(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ inline T div_t(T a, T d)
+{
+    if constexpr (num<T>::is_complex) {
+        double den = d.x * d.x + d.y * d.y;
+        return T{(a.x * d.x + a.y * d.y) / den, (a.y * d.x - a.x * d.y) / den};
+    } else {
+        return a / d;
+    }
+}
+
+static constexpr int TRSV_SPIN_CAP = 1 << 22;
+
+template <class T>
+__global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
+                                                  const T* val, int upper, const T* b, T* x,
+                                                  uint32_t* ready, TrsvCtl* ctl,
+                                                  const int32_t* done)
+{
+    if (done && *done) return;
+    __shared__ uint32_t s_chunk, s_epoch;
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        s_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_chunk = atomicAdd(&ctl->ticket, 1u);
+    }
+    __syncthreads();
+    const uint32_t ep = s_epoch + 1;
+    const int pos = (int)s_chunk * 64 + lane;
+    bool fin = pos >= n;
+    const int i = fin ? 0 : (upper ? n - 1 - pos : pos);
+    T acc = fin ? num<T>::zero() : b[i];
+    T diag = num<T>::one();
+    int p = fin ? 0 : rp[i];
+    const int pe = fin ? 0 : rp[i + 1];
+    int spins = 0;
+    bool err = false;
+    while (!__all(fin)) {
+        if (!fin) {
+            while (p < pe) {
+                int c = ci[p];
+                if (c == i) { diag = val[p]; ++p; continue; }
+                if (upper ? (c < i) : (c > i)) { ++p; continue; }  // wrong triangle: ignored
+                if (load_acquire(&ready[c]) != ep) break;
+                acc -= val[p] * x[c];
+                ++p;
+            }
+            if (p == pe) {
+                x[i] = div_t(acc, diag);
+                store_release(&ready[i], ep);
+                fin = true;
+            } else if (++spins > TRSV_SPIN_CAP) {
+                err = true;
+                fin = true;
+            }
+        }
+    }
+    if (err) atomicOr(&ctl->error, 1u);
+    __syncthreads();
+    if (lane == 0) {
+        uint32_t f = atomicAdd(&ctl->finished, 1u);
+        if (f == gridDim.x - 1) {
+            // last wave: reset the tickets and advance the epoch
+            ctl->ticket = 0;
+            ctl->finished = 0;
+            __hip_atomic_store(&ctl->epoch, ep, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+template <class T>
+Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
+                T* x, uint32_t* ready, TrsvCtl* ctl, const int32_t* done, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(trsv_kernel<T>, dim3((n + 63) / 64), dim3(64), 0, st, n, rp, ci, val, upper,
+                       b, x, ready, ctl, done);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// Level of every row in the triangular dependency DAG (same sync-free
+// scheme, integer max instead of substitution); *maxlevel = depth.
+__global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* rp,
+                                                         const int32_t* ci, int upper,
+                                                         int32_t* level, uint32_t* ready,
+                                                         TrsvCtl* ctl, int32_t* maxlevel)
+{
+    __shared__ uint32_t s_chunk, s_epoch;
+    const int lane = threadIdx.x;
+    if (lane == 0) {
+        s_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_chunk = atomicAdd(&ctl->ticket, 1u);
+    }
+    __syncthreads();
+    const uint32_t ep = s_epoch + 1;
+    const int pos = (int)s_chunk * 64 + lane;
+    bool fin = pos >= n;
+    const int i = fin ? 0 : (upper ? n - 1 - pos : pos);
+    int lv = 0;
+    int p = fin ? 0 : rp[i];
+    const int pe = fin ? 0 : rp[i + 1];
+    int spins = 0;
+    bool err = false;
+    while (!__all(fin)) {
+        if (!fin) {
+            while (p < pe) {
+                int c = ci[p];
+                if (c == i || (upper ? (c < i) : (c > i))) { ++p; continue; }
+                if (load_acquire(&ready[c]) != ep) break;
+                lv = max(lv, __hip_atomic_load(&level[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                ++p;
+            }
+            if (p == pe) {
+                __hip_atomic_store(&level[i], lv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                store_release(&ready[i], ep);
+                atomicMax(maxlevel, lv + 1);
+                fin = true;
+            } else if (++spins > TRSV_SPIN_CAP) {
+                err = true;
+                fin = true;
+            }
+        }
+    }
+    if (err) atomicOr(&ctl->error, 1u);
+    __syncthreads();
+    if (lane == 0) {
+        uint32_t f = atomicAdd(&ctl->finished, 1u);
+        if (f == gridDim.x - 1) {
+            ctl->ticket = 0;
+            ctl->finished = 0;
+            __hip_atomic_store(&ctl->epoch, ep, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+Err launch_trsv_levels(int n, const int32_t* rp, const int32_t* ci, int upper, int32_t* level,
+                       uint32_t* ready, TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(trsv_levels_kernel, dim3((n + 63) / 64), dim3(64), 0, st, n, rp, ci, upper,
+                       level, ready, ctl, maxlevel_dev);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// BiCGSTAB stages
+// ---------------------------------------------------------------------------
+static constexpr int RNT = 256;
+static constexpr int RBMAX = 512;
+
+__host__ __device__ inline int red_blocks(int n)
+{
+    int b = (n + RNT * 4 - 1) / (RNT * 4);
+    return b < 1 ? 1 : (b > RBMAX ? RBMAX : b);
+}
+
+// Block-reduce NV doubles per thread into partial[blockIdx * NV + v]; returns
+// true in the block that finished last (its threads then see all partials).
+template <int NV>
+__device__ inline bool reduce_partials(double (&vals)[NV], double* partial, uint32_t* ticket)
+{
+    __shared__ double red[NV][RNT];
+    __shared__ bool last;
+    for (int v = 0; v < NV; ++v) red[v][threadIdx.x] = vals[v];
+    __syncthreads();
+    for (int o = RNT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int v = 0; v < NV; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < NV; ++v) partial[blockIdx.x * NV + v] = red[v][0];
+        __threadfence();
+        uint32_t t = atomicAdd(ticket, 1u);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
+}
+
+template <int NV>
+__device__ inline void sum_partials(const double* partial, int nb, double (&out)[NV])
+{
+    for (int v = 0; v < NV; ++v) out[v] = 0.0;
+    for (int b = 0; b < nb; ++b)
+        for (int v = 0; v < NV; ++v)
+            out[v] += __hip_atomic_load(&partial[b * NV + v], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ inline T mk2(double re, double im)
+{
+    if constexpr (num<T>::is_complex) return T{re, im};
+    else return re;
+}
+
+template <class T>
+__device__ inline bool bad_scalar(T a)
+{
+    double m = num<T>::abs(a);
+    return !(m > 1e-300) || !isfinite(m);
+}
+
+#define BICG_GRID_LOOP for (int i = blockIdx.x * RNT + threadIdx.x; i < V.n; i += gridDim.x * RNT)
+
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_init_kernel(BicgVecs<T> V, double tol, int maxit)
+{
+    double acc[1] = {0.0};
+    BICG_GRID_LOOP {
+        T bi = V.b[i];
+        V.x[i] = num<T>::zero();
+        V.r[i] = bi;
+        V.rh[i] = bi;
+        V.p[i] = num<T>::zero();
+        V.v[i] = num<T>::zero();
+        acc[0] += num<T>::abs2(bi);
+    }
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[1];
+        sum_partials<1>(V.partial, gridDim.x, s);
+        BicgState<T>* S = V.st;
+        S->bnorm = sqrt(s[0]);
+        S->tol = tol;
+        S->maxit = maxit;
+        S->it = 0;
+        S->rho_prev = num<T>::one();
+        S->alpha = num<T>::one();
+        S->omega = num<T>::one();
+        S->beta = num<T>::zero();
+        S->half = 0;
+        S->omega_bad = 0;
+        S->res = 1.0;
+        S->done = (s[0] == 0.0) ? 1 : 0;
+        S->flag = (s[0] == 0.0) ? 0 : 1;
+        S->red_ticket = 0;
+    }
+}
+
+// rho = <rh, r>; beta; iteration count and the maxit stop.
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_rho_kernel(BicgVecs<T> V)
+{
+    if (V.st->done) return;
+    double acc[2] = {0.0, 0.0};
+    BICG_GRID_LOOP {
+        T d = num<T>::cmul(V.rh[i], V.r[i]);
+        acc[0] += num<T>::re(d);
+        acc[1] += num<T>::im(d);
+    }
+    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[2];
+        sum_partials<2>(V.partial, gridDim.x, s);
+        BicgState<T>* S = V.st;
+        S->red_ticket = 0;
+        T rho = mk2<T>(s[0], s[1]);
+        if (S->it + 1 > S->maxit) { S->done = 1; S->flag = 1; return; }
+        S->it += 1;
+        if (bad_scalar(rho)) { S->done = 1; S->flag = 2; return; }
+        S->rho = rho;
+        if (S->it == 1) {
+            S->beta = num<T>::zero();
+        } else {
+            T q = div_t(rho, S->rho_prev);
+            T a = div_t(S->alpha, S->omega);
+            S->beta = q * a;
+        }
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_p_kernel(BicgVecs<T> V)
+{
+    if (V.st->done) return;
+    const T beta = V.st->beta, omega = V.st->omega;
+    const bool first = V.st->it == 1;
+    BICG_GRID_LOOP {
+        V.p[i] = first ? V.r[i] : V.r[i] + beta * (V.p[i] - omega * V.v[i]);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_alpha_kernel(BicgVecs<T> V)
+{
+    if (V.st->done) return;
+    double acc[2] = {0.0, 0.0};
+    BICG_GRID_LOOP {
+        T d = num<T>::cmul(V.rh[i], V.v[i]);
+        acc[0] += num<T>::re(d);
+        acc[1] += num<T>::im(d);
+    }
+    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[2];
+        sum_partials<2>(V.partial, gridDim.x, s);
+        BicgState<T>* S = V.st;
+        S->red_ticket = 0;
+        T rv = mk2<T>(s[0], s[1]);
+        if (bad_scalar(rv)) { S->done = 1; S->flag = 2; return; }
+        S->alpha = div_t(S->rho, rv);
+    }
+}
+
+// s = r - alpha v; half-step convergence test (the x update of a half step
+// is applied by bicg_half_fix after the loop).
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_s_kernel(BicgVecs<T> V)
+{
+    if (V.st->done) return;
+    const T alpha = V.st->alpha;
+    double acc[1] = {0.0};
+    BICG_GRID_LOOP {
+        T s = V.r[i] - alpha * V.v[i];
+        V.s[i] = s;
+        acc[0] += num<T>::abs2(s);
+    }
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[1];
+        sum_partials<1>(V.partial, gridDim.x, s);
+        BicgState<T>* S = V.st;
+        S->red_ticket = 0;
+        double nr = sqrt(s[0]);
+        S->res = nr / S->bnorm;
+        if (nr <= S->tol * S->bnorm) { S->done = 1; S->flag = 0; S->half = 1; }
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_omega_kernel(BicgVecs<T> V)
+{
+    if (V.st->done) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    BICG_GRID_LOOP {
+        T ti = V.t[i];
+        T d = num<T>::cmul(ti, V.s[i]);
+        acc[0] += num<T>::re(d);
+        acc[1] += num<T>::im(d);
+        acc[2] += num<T>::abs2(ti);
+    }
+    if (reduce_partials<3>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[3];
+        sum_partials<3>(V.partial, gridDim.x, s);
+        BicgState<T>* S = V.st;
+        S->red_ticket = 0;
+        T ts = mk2<T>(s[0], s[1]);
+        T om = div_t(ts, mk2<T>(s[2], 0.0));
+        S->omega = om;
+        if (bad_scalar(om)) { S->done = 1; S->flag = 2; S->half = 2; }
+    }
+}
+
+// x = x + alpha ph + omega sh; r = s - omega t; full-step convergence test.
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_xr_kernel(BicgVecs<T> V)
+{
+    if (V.st->done) return;
+    const T alpha = V.st->alpha, omega = V.st->omega;
+    double acc[1] = {0.0};
+    BICG_GRID_LOOP {
+        V.x[i] = V.x[i] + alpha * V.ph[i] + omega * V.sh[i];
+        T r = V.s[i] - omega * V.t[i];
+        V.r[i] = r;
+        acc[0] += num<T>::abs2(r);
+    }
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[1];
+        sum_partials<1>(V.partial, gridDim.x, s);
+        BicgState<T>* S = V.st;
+        S->red_ticket = 0;
+        double nr = sqrt(s[0]);
+        S->res = nr / S->bnorm;
+        S->rho_prev = S->rho;
+        if (nr <= S->tol * S->bnorm) { S->done = 1; S->flag = 0; }
+    }
+}
+
+// After the loop (and bicg_half_fix), with t = A x: ||b - A x|| / ||b||
+// into st->tt.
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_true_res_kernel(BicgVecs<T> V)
+{
+    double acc[1] = {0.0};
+    BICG_GRID_LOOP {
+        T d = V.b[i] - V.t[i];
+        acc[0] += num<T>::abs2(d);
+    }
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+        double s[1];
+        sum_partials<1>(V.partial, gridDim.x, s);
+        V.st->red_ticket = 0;
+        V.st->tt = V.st->bnorm > 0 ? sqrt(s[0]) / V.st->bnorm : 0.0;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(RNT) bicg_half_fix_kernel(BicgVecs<T> V)
+{
+    // half == 1: converged at the half step, x = x + alpha ph.
+    // half == 2: omega breakdown, x = x + alpha ph as well.
+    if (V.st->half == 0) return;
+    const T alpha = V.st->alpha;
+    BICG_GRID_LOOP { V.x[i] = V.x[i] + alpha * V.ph[i]; }
+}
+
+#define LAUNCH_STAGE(kern, ...)                                                              \
+    hipLaunchKernelGGL(kern<T>, dim3(red_blocks(V.n)), dim3(RNT), 0, st, V, ##__VA_ARGS__);  \
+    DIAF_HIP_TRY(hipGetLastError());                                                         \
+    return {};
+
+template <class T> Err bicg_init(const BicgVecs<T>& V, double tol, int maxit, hipStream_t st) { LAUNCH_STAGE(bicg_init_kernel, tol, maxit) }
+template <class T> Err bicg_rho(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_rho_kernel) }
+template <class T> Err bicg_update_p(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_p_kernel) }
+template <class T> Err bicg_alpha(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_alpha_kernel) }
+template <class T> Err bicg_s(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_s_kernel) }
+template <class T> Err bicg_omega(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_omega_kernel) }
+template <class T> Err bicg_xr(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_xr_kernel) }
+template <class T>
+Err bicg_true_residual(const BicgVecs<T>& V, hipStream_t st)
+{
+    // caller has put A x in V.t after bicg_half_fix
+    LAUNCH_STAGE(bicg_true_res_kernel)
+}
+template <class T>
+Err bicg_half_fix(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_half_fix_kernel) }
+
+#define INST(T)                                                                                   \
+    template Err launch_spmv_csr<T>(int, const int32_t*, const int32_t*, const T*, const T*, T*,  \
+                                    const int32_t*, hipStream_t);                                 \
+    template Err launch_trsv<T>(int, const int32_t*, const int32_t*, const T*, int, const T*, T*, \
+                                uint32_t*, TrsvCtl*, const int32_t*, hipStream_t);                \
+    template Err launch_diag_solve<T>(int, const int32_t*, const int32_t*, const T*, const T*,    \
+                                      T*, const int32_t*, hipStream_t);                           \
+    template Err bicg_init<T>(const BicgVecs<T>&, double, int, hipStream_t);                      \
+    template Err bicg_rho<T>(const BicgVecs<T>&, hipStream_t);                                    \
+    template Err bicg_update_p<T>(const BicgVecs<T>&, hipStream_t);                               \
+    template Err bicg_alpha<T>(const BicgVecs<T>&, hipStream_t);                                  \
+    template Err bicg_s<T>(const BicgVecs<T>&, hipStream_t);                                      \
+    template Err bicg_omega<T>(const BicgVecs<T>&, hipStream_t);                                  \
+    template Err bicg_xr<T>(const BicgVecs<T>&, hipStream_t);                                     \
+    template Err bicg_true_residual<T>(const BicgVecs<T>&, hipStream_t);                          \
+    template Err bicg_half_fix<T>(const BicgVecs<T>&, hipStream_t);
+INST(double)
+INST(zc)
+#undef INST
+
+}  // namespace diaf

@@ -1,0 +1,234 @@
+// Sparse utilities: scans, V assembly (padded columns -> CSC), CSC -> CSR
+// transposes, input validation and per-column statistics.
+#include <hipcub/hipcub.hpp>
+
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+namespace diaf {
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (out has n+1 entries, out[n] = total).
+// ---------------------------------------------------------------------------
+__global__ void shift_kernel(const int32_t* in, int32_t* tmp, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) tmp[i] = in[i];
+    if (i == n) tmp[i] = 0;
+}
+
+Err exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t st)
+{
+    // out[0..n] = exclusive prefix sums of in[0..n) followed by the total:
+    // scan n+1 values with a trailing zero.
+    int32_t* tmp = nullptr;
+    DIAF_HIP_TRY(hipMallocAsync((void**)&tmp, sizeof(int32_t) * (n + 1), st));
+    hipLaunchKernelGGL(shift_kernel, dim3((n + 1 + 255) / 256), dim3(256), 0, st, in, tmp, n);
+    size_t bytes = 0;
+    DIAF_HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, tmp, out, n + 1, st));
+    void* ws = nullptr;
+    DIAF_HIP_TRY(hipMallocAsync(&ws, bytes, st));
+    DIAF_HIP_TRY(hipcub::DeviceScan::ExclusiveSum(ws, bytes, tmp, out, n + 1, st));
+    DIAF_HIP_TRY(hipFreeAsync(ws, st));
+    DIAF_HIP_TRY(hipFreeAsync(tmp, st));
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// V assembly: padded (n x lmax, -1 padded, rows sorted) -> CSC.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void compact_v_kernel(int n, int lmax, const int32_t* lcount, const int32_t* Vcp,
+                                 const int32_t* Vrows, const T* Vvals, int32_t* Vri, T* Vval)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * lmax) return;
+    int j = (int)(idx / lmax), t = (int)(idx % lmax);
+    if (t < lcount[j]) {
+        Vri[Vcp[j] + t] = Vrows[idx];
+        Vval[Vcp[j] + t] = Vvals[idx];
+    }
+}
+
+template <class T>
+Err launch_compact_v(int n, int lmax, const int32_t* lcount, const int32_t* Vcp,
+                     const int32_t* Vrows, const T* Vvals, int32_t* Vri, T* Vval, hipStream_t st)
+{
+    int64_t tot = (int64_t)n * lmax;
+    if (tot == 0) return {};
+    hipLaunchKernelGGL(compact_v_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                       n, lmax, lcount, Vcp, Vrows, Vvals, Vri, Vval);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// CSC -> CSR: count entries per row, scan, scatter, then sort each row by
+// column so the result does not depend on the scatter order.
+// ---------------------------------------------------------------------------
+__global__ void row_count_kernel(int64_t nnz, const int32_t* ri, int32_t* cnt)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[ri[p]], 1);
+}
+
+template <class T>
+__global__ void scatter_csr_kernel(int n, const int32_t* cp, const int32_t* ri, const T* val,
+                                   const int32_t* rp, int32_t* fill, int32_t* ci, T* cval)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int p = cp[j]; p < cp[j + 1]; ++p) {
+        int i = ri[p];
+        int q = rp[i] + atomicAdd(&fill[i], 1);
+        ci[q] = j;
+        cval[q] = val[p];
+    }
+}
+
+template <class T>
+__global__ void sort_rows_kernel(int n, const int32_t* rp, int32_t* ci, T* cval)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int b = rp[i], e = rp[i + 1];
+    for (int p = b + 1; p < e; ++p) {
+        int key = ci[p];
+        T v = cval[p];
+        int q = p - 1;
+        while (q >= b && ci[q] > key) { ci[q + 1] = ci[q]; cval[q + 1] = cval[q]; --q; }
+        ci[q + 1] = key;
+        cval[q + 1] = v;
+    }
+}
+
+template <class T>
+Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T* val,
+               int32_t* rp, int32_t* ci, T* cval, hipStream_t st)
+{
+    int32_t* cnt = nullptr;
+    DIAF_HIP_TRY(hipMallocAsync((void**)&cnt, sizeof(int32_t) * (n + 1), st));
+    DIAF_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), st));
+    if (nnz > 0)
+        hipLaunchKernelGGL(row_count_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
+                           nnz, ri, cnt);
+    DIAF_TRY(exclusive_scan_i32(cnt, rp, n, st));
+    DIAF_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), st));
+    hipLaunchKernelGGL(scatter_csr_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, cp, ri,
+                       val, rp, cnt, ci, cval);
+    hipLaunchKernelGGL(sort_rows_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci,
+                       cval);
+    DIAF_HIP_TRY(hipGetLastError());
+    DIAF_HIP_TRY(hipFreeAsync(cnt, st));
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// Validation.  Codes: 1 colptr not monotone / out of range, 2 row out of
+// range, 3 rows unsorted or duplicated, 4 diagonal missing, 5 non-finite
+// value.  The smallest code seen wins (atomicMin over codes, 0 = fine).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void validate_kernel(int n, const int32_t* cp, const int32_t* ri, const T* val,
+                                int need_diag, int32_t* bad)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int b = cp[j], e = cp[j + 1];
+    int code = 0;
+    if (e < b || b < 0) code = 1;
+    int has_diag = 0;
+    if (!code) {
+        for (int p = b; p < e; ++p) {
+            int i = ri[p];
+            if (i < 0 || i >= n) { code = 2; break; }
+            if (p > b && ri[p - 1] >= i) { code = 3; break; }
+            if (i == j) has_diag = 1;
+            if (val && !num<T>::finite(val[p])) { code = 5; break; }
+        }
+    }
+    if (!code && need_diag && !has_diag) code = 4;
+    if (code) atomicMin(bad, code);
+}
+
+template <class T>
+Err launch_validate_csc(int n, const int32_t* cp, const int32_t* ri, const T* val,
+                        int32_t* bad_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(validate_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, cp, ri, val,
+                       1, bad_dev);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+Err launch_validate_pattern(int n, const int32_t* cp, const int32_t* ri, int need_diag,
+                            int32_t* bad_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(validate_kernel<double>, dim3((n + 255) / 256), dim3(256), 0, st, n, cp, ri,
+                       (const double*)nullptr, need_diag, bad_dev);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// ---------------------------------------------------------------------------
+// Flag counts (bits 0..6) and sum of r_j^2 (two-stage, fixed order).
+// ---------------------------------------------------------------------------
+__global__ void flag_stats_kernel(int n, const uint32_t* flags, const double* r, int32_t* counts,
+                                  double* partial)
+{
+    __shared__ double red[256];
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    double s = 0.0;
+    if (j < n) {
+        uint32_t f = flags[j];
+        for (int b = 0; b < 7; ++b)
+            if (f & (1u << b)) atomicAdd(&counts[b], 1);
+        s = r[j] * r[j];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void sum_partials_kernel(int nb, const double* partial, double* out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += partial[b];
+        *out = s;
+    }
+}
+
+template <class T>
+Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* counts_dev,
+                      double* nrm2_dev, hipStream_t st)
+{
+    int nb = (n + 255) / 256;
+    double* partial = nullptr;
+    DIAF_HIP_TRY(hipMallocAsync((void**)&partial, sizeof(double) * (nb + 1), st));
+    hipLaunchKernelGGL(flag_stats_kernel, dim3(nb), dim3(256), 0, st, n, flags, r, counts_dev,
+                       partial);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, st, nb, partial, nrm2_dev);
+    DIAF_HIP_TRY(hipGetLastError());
+    DIAF_HIP_TRY(hipFreeAsync(partial, st));
+    return {};
+}
+
+#define INST(T)                                                                                  \
+    template Err launch_compact_v<T>(int, int, const int32_t*, const int32_t*, const int32_t*,  \
+                                     const T*, int32_t*, T*, hipStream_t);                       \
+    template Err csc_to_csr<T>(int, int64_t, const int32_t*, const int32_t*, const T*, int32_t*, \
+                               int32_t*, T*, hipStream_t);                                       \
+    template Err launch_validate_csc<T>(int, const int32_t*, const int32_t*, const T*, int32_t*, \
+                                        hipStream_t);                                            \
+    template Err launch_flag_stats<T>(int, const uint32_t*, const double*, int32_t*, double*,    \
+                                      hipStream_t);
+INST(double)
+INST(zc)
+#undef INST
+
+}  // namespace diaf

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI library (no GPU compute).
+
+The library must load, export every function declared in include/diaf.h,
+and the Python binding must declare exactly those names.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "diaf.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(diaf_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_the_api():
+    names = declared_functions()
+    for must in ("diaf_ctx_create", "diaf_factor", "diaf_apply", "diaf_solve",
+                 "diaf_factors_view", "diaf_model_create", "diaf_mlp_train_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1208_3573_amd import diaf
+    lib = diaf.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", diaf.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (diaf_\w+)", out))
+    assert set(declared_functions()) <= exported
+    # the binding marshals exactly the declared API (plus the copy helper)
+    assert set(diaf.EXPORTED) == set(declared_functions()) | {"diaf_copy"}
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1208_3573_amd import diaf
+    saved = diaf._lib
+    diaf._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            diaf.load_library(str(tmp_path / "missing.so"))
+    finally:
+        diaf._lib = saved
+
+
+def test_struct_layouts_match_header():
+    """ctypes mirrors of the ABI structs have the C sizes (LP64)."""
+    import ctypes
+    from paper_1208_3573_amd import diaf
+    assert ctypes.sizeof(diaf.diaf_csc) == 8 + 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(diaf.diaf_pattern) == 32
+    assert ctypes.sizeof(diaf.diaf_solve_info) == 4 + 4 + 8 + 8 + 8
+    assert diaf.MLP_NPARAM == 5313
+
+
+def test_null_arguments_are_rejected_without_a_device():
+    """Argument checks run before any device work and return codes only."""
+    import ctypes
+    from paper_1208_3573_amd import diaf
+    lib = diaf.load_library()
+    assert lib.diaf_ctx_create(None, 0, None) == diaf.DIAF_EINVAL
+    assert lib.diaf_factor(None, None, None, 0, None) == diaf.DIAF_EINVAL
+    assert lib.diaf_factors_view(None, None) == diaf.DIAF_EINVAL
+    assert lib.diaf_apply(None, None, None, None) == diaf.DIAF_EINVAL
+    assert lib.diaf_last_error(None) == b""
+    lib.diaf_factors_destroy(None)
+    lib.diaf_model_destroy(None)
+    lib.diaf_ctx_destroy(None)
+    h = ctypes.c_void_p()
+    rc = lib.diaf_ctx_create(ctypes.byref(h), 0, None)
+    if rc == diaf.DIAF_OK:  # a GPU is present: clean up
+        lib.diaf_ctx_destroy(h)
+    else:
+        assert rc == diaf.DIAF_EDEVICE

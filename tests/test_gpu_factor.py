@@ -1,0 +1,166 @@
+"""GPU parity of the factoring pass against the CPU oracle, through the C ABI.
+
+Bars: identical W and V patterns; per-column residual within 1e-10
+relative (plus the FP64 rounding level of evaluating it); singular vectors
+(v_j for unit-norm v, w_j for unit-norm w) within a 1e-8 subspace angle up
+to phase, columns flagged rank- or gap-degenerate by either side excluded
+from the angle check only.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import compare, oracle_pattern, run_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1208_3573_amd import diaf
+    assert torch.cuda.is_available()
+    return diaf.Context(0)
+
+
+SMALL = {
+    # name: (matrix builder, W rule, V rule, l, modes)
+    "convdiff2d_32_gs": (lambda: synth.convdiff(32, 2, 1), "A", "gs_upper", 0, ("unit_v", "unit_w")),
+    "convdiff2d_32_diag": (lambda: synth.convdiff(32, 2, 1), "A2", "diag", 0, ("unit_v", "unit_w")),
+    "random300_a2_lower": (lambda: synth.random_small(300, 3, 5, diag_shift=1.0), "A2",
+                           "topk_lower", 4, ("unit_v", "unit_w")),
+    "random300c_a2_upper": (lambda: synth.random_small(300, 3, 6, complex_=True, diag_shift=1.0),
+                            "A2", "topk_upper", 4, ("unit_v", "unit_w")),
+    "convdiff3d_16_a2": (lambda: synth.convdiff(16, 3, 7), "A2", "topk_lower", 5,
+                         ("unit_v", "unit_w")),
+    "helmholtz_32_a2": (lambda: synth.helmholtz(32, 10.0, 0.5), "A2",
+                        "topk_upper", 7, ("unit_v", "unit_w")),
+    "random_3k_1hop": (lambda: synth.random_lognormal(3000, 11), "A_1hop_topk", "topk_lower", 5,
+                       ("unit_v", "unit_w")),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+def test_factor_parity_small(ctx, name):
+    build, w, v, l, modes = SMALL[name]
+    A = build()
+    J = oracle_pattern(A, w, 8)
+    for mode in modes:
+        say(f"case {name} mode {mode} n={A.n}")
+        F, H, _ = run_gpu(ctx, A, w, v, l, mode, wtopk=8)
+        O = oracle.factor(A, J, mode, v, l)
+        compare(H, J, O, A, mode)
+        st = F.stats()
+        assert st.nnz_w == J.nnz and st.nnz_v == O.Vcp[-1]
+        assert abs(st.nrm - np.sqrt(np.sum(H["r"] ** 2))) <= 1e-12 * max(1.0, st.nrm)
+        F.close()
+
+
+def _sample(n, k, seed):
+    rng = np.random.default_rng(seed)
+    s = set(rng.choice(n, size=min(k, n), replace=False).tolist())
+    s |= {0, 1, n - 2, n - 1, n // 2}
+    return np.array(sorted(s))
+
+
+FULL = {
+    "convdiff3d_64": ("unit_v", "unit_w"),
+    "helmholtz2d_512": ("unit_w",),
+    "random_1m": ("unit_v", "unit_w"),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL))
+def test_factor_parity_full_size_sampled(ctx, name):
+    """The full workloads in the benchmark's launch configuration; the oracle
+    recomputes a sample of columns one by one."""
+    cfg = synth.WORKLOADS[name]
+    A = synth.workload_matrix(name)
+    J = oracle_pattern(A, cfg["w"], cfg.get("w_topk", 0))
+    cols = _sample(A.n, 1500, 1)
+    dA = None
+    for mode in FULL[name]:
+        say(f"case {name} mode {mode} n={A.n}")
+        F, H, dA = run_gpu(ctx, A, cfg["w"], cfg["v"], cfg["v_count"], mode,
+                           wtopk=cfg.get("w_topk", 0), dA=dA)
+        O = oracle.factor(A, J, mode, cfg["v"], cfg["v_count"], cols=cols)
+        compare(H, J, O, A, mode, cols=cols)
+        F.close()
+
+
+def test_pattern_builders_match_oracle(ctx):
+    from paper_1208_3573_amd import diaf
+    cases = [(synth.random_small(500, 4, 3), "A2", 0),
+             (synth.random_lognormal(20000, 4), "A_1hop_topk", 8),
+             (synth.random_lognormal(20000, 5), "A_1hop_topk", 3),
+             (synth.random_small(200, 3, 2, complex_=True), "A_1hop_topk", 4),
+             (synth.convdiff(12, 3, 1), "A2", 0)]
+    for A, kind, p in cases:
+        say(f"pattern {kind} p={p} n={A.n}")
+        dA = diaf.DeviceCSC.from_host(A)
+        cp, ri = diaf.diaf_pattern_build(ctx, dA, kind, p)
+        J = oracle_pattern(A, kind, p)
+        assert np.array_equal(cp.cpu().numpy(), J.colptr)
+        assert np.array_equal(ri.cpu().numpy(), J.rowidx)
+
+
+def test_factor_is_deterministic(ctx):
+    A = synth.random_lognormal(4000, 9)
+    outs = []
+    for _ in range(2):
+        F, H, _ = run_gpu(ctx, A, "A_1hop_topk", "topk_lower", 5, "unit_w", wtopk=8)
+        outs.append(H)
+        F.close()
+    for key in ("Wval", "Vri", "Vval", "r", "flags"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+def test_gram_fp32_variant_reports_error(ctx):
+    """The FP32-Gram variant is reported, not gated: it must run and stay
+    close to the FP64 oracle on a well-conditioned case."""
+    A = synth.convdiff(16, 3, 7)
+    J = oracle_pattern(A, "A2")
+    O = oracle.factor(A, J, "unit_v", "topk_lower", 5)
+    F, H, _ = run_gpu(ctx, A, "A2", "topk_lower", 5, "unit_v", gram_fp32=True)
+    same = np.array_equal(H["Vri"], O.Vri)
+    err = np.max(np.abs(H["r"] - O.r) / np.maximum(O.r, 1e-300))
+    say(f"fp32 gram: V pattern identical={same}, max rel residual err={err:.3e}")
+    assert err < 1e-3
+    F.close()
+
+
+def test_invalid_inputs_are_rejected(ctx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(8, 2, 1)
+
+    def attempt(colptr, rowidx, val):
+        dA = diaf.DeviceCSC(A.n, torch.tensor(colptr, dtype=torch.int32, device="cuda"),
+                            torch.tensor(rowidx, dtype=torch.int32, device="cuda"),
+                            torch.tensor(val, dtype=torch.float64, device="cuda"))
+        spec = diaf.make_spec(w="A", v="diag")
+        with pytest.raises(diaf.DiafError) as ei:
+            diaf.diaf_factor(ctx, dA, spec, "unit_v")
+        return ei.value.code
+
+    ri = A.rowidx.copy()
+    ri[[0, 1]] = ri[[1, 0]]  # unsorted
+    assert attempt(A.colptr, ri, A.val) == diaf.DIAF_EINVAL
+    v = A.val.copy()
+    v[5] = np.nan
+    assert attempt(A.colptr, A.rowidx, v) == diaf.DIAF_EINVAL
+    # drop the diagonal of column 0
+    keep = np.ones(A.nnz, bool)
+    keep[np.where(A.rowidx[:A.colptr[1]] == 0)[0][0]] = False
+    cp = A.colptr.copy()
+    cp[1:] -= 1
+    assert attempt(cp, A.rowidx[keep], A.val[keep]) == diaf.DIAF_EINVAL
+    ri = A.rowidx.copy()
+    ri[3] = A.n + 5
+    assert attempt(A.colptr, ri, A.val) == diaf.DIAF_EINVAL
+    # bad spec: top-k with l = 0
+    dA = diaf.DeviceCSC.from_host(A)
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A", v="topk_lower", v_count=0), "unit_v")
+    assert ei.value.code == diaf.DIAF_EINVAL

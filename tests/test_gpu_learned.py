@@ -1,0 +1,139 @@
+"""GPU kernels of the learned W-pattern proposer against the FP64 reference.
+
+Features and labels are checked element by element, the MLP forward and the
+loss gradient against the FP64 back-propagation (FP32 tolerances), training
+must lower the loss, and the residual gate must behave at its limits:
+a negative gate sends every column back to pattern(A^2) and reproduces the plain
+factorization bit for bit, gate infinity keeps the proposal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import learned as L
+from tests._gpu import oracle_pattern, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1208_3573_amd import diaf
+    assert torch.cuda.is_available()
+    return diaf.Context(0)
+
+
+def _cand(A):
+    J = oracle_pattern(A, "A2")
+    return J
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_features_match_reference(ctx, cplx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(6, 3, 4) if not cplx else synth.helmholtz(12, 5.0, 0.5)
+    C = _cand(A)
+    ref = L.features(A, C.colptr, C.rowidx).astype(np.float32)
+    dA = diaf.DeviceCSC.from_host(A)
+    dC = diaf.DevicePattern.from_host(C.colptr, C.rowidx)
+    feat = torch.zeros(C.nnz * 16, dtype=torch.float32, device="cuda")
+    diaf.diaf_features(ctx, dA, dC, feat)
+    got = feat.cpu().numpy().reshape(-1, 16)
+    err = np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref)))
+    say(f"features max err {err:.3e}")
+    assert err <= 2e-7
+
+
+def test_labels_match_reference(ctx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(8, 3, 5)
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_lower", v_count=5), "unit_w")
+    H = F.to_host()
+    lab = torch.zeros(len(H["Wri"]), dtype=torch.float32, device="cuda")
+    diaf.diaf_labels(ctx, dA, F, 0.1, lab)
+    ref = L.labels(A, H["Wcp"], H["Wri"], H["Wval"], 0.1)
+    assert np.array_equal(lab.cpu().numpy(), ref.astype(np.float32))
+    F.close()
+
+
+def test_mlp_forward_and_gradient_match_fp64(ctx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    rng = np.random.default_rng(1)
+    theta = L.init_params(7)
+    N = 1000
+    X = rng.standard_normal((N, 16)).astype(np.float32)
+    y = (rng.random(N) < 0.3).astype(np.float32)
+    m = diaf.Model(ctx, theta)
+    assert np.array_equal(m.params(), theta)
+    Xd = torch.from_numpy(X).cuda()
+    yd = torch.from_numpy(y).cuda()
+    sc = torch.zeros(N, dtype=torch.float32, device="cuda")
+    diaf.diaf_mlp_forward(ctx, m, Xd, N, sc)
+    sref = L.forward(theta.astype(np.float64), X.astype(np.float64))
+    assert np.max(np.abs(sc.cpu().numpy() - sref)) <= 1e-4 * max(1.0, np.abs(sref).max())
+    g = torch.zeros(L.NPARAM, dtype=torch.float32, device="cuda")
+    loss = diaf.diaf_mlp_loss_grad(ctx, m, Xd, yd, N, g)
+    lref, gref = L.loss_grad(theta.astype(np.float64), X.astype(np.float64), y.astype(np.float64))
+    gg = g.cpu().numpy()
+    rel = np.linalg.norm(gg - gref) / np.linalg.norm(gref)
+    say(f"loss {loss:.6f} ref {lref:.6f} grad rel err {rel:.3e}")
+    assert abs(loss - lref) <= 1e-5 * max(1.0, lref)
+    assert rel <= 1e-4
+    m.close()
+
+
+def test_training_lowers_the_loss(ctx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(10, 3, 21)
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_lower", v_count=5), "unit_w")
+    H = F.to_host()
+    C = diaf.DevicePattern.from_host(H["Wcp"], H["Wri"])
+    npairs = len(H["Wri"])
+    feat = torch.zeros(npairs * 16, dtype=torch.float32, device="cuda")
+    diaf.diaf_features(ctx, dA, C, feat)
+    lab = torch.zeros(npairs, dtype=torch.float32, device="cuda")
+    diaf.diaf_labels(ctx, dA, F, 0.1, lab)
+    m = diaf.Model(ctx, L.init_params(0))
+    losses = [diaf.diaf_mlp_train_step(ctx, m, feat, lab, npairs, 3e-3) for _ in range(150)]
+    say(f"loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    assert losses[-1] < 0.6 * losses[0]
+    m.close()
+    F.close()
+
+
+def test_gate_limits(ctx):
+    """gate -1: every column falls back to pattern(A^2) and the result equals
+    the plain factorization bit for bit; gate inf: nothing falls back."""
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(10, 3, 3)
+    dA = diaf.DeviceCSC.from_host(A)
+    m = diaf.Model(ctx, L.init_params(5))
+    plain = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_lower", v_count=5), "unit_w")
+    P = plain.to_host()
+    Fz = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="learned", v="topk_lower", v_count=5, model=m,
+                                                  gate_tau=-1.0), "unit_w")
+    Z = Fz.to_host()
+    assert np.all(Z["flags"] & diaf.FLAG_FELL_BACK)
+    for key in ("Wcp", "Wri", "Wval", "Vcp", "Vri", "Vval", "r"):
+        assert np.array_equal(P[key], Z[key]), key
+    Fi = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="learned", v="topk_lower", v_count=5, model=m,
+                                                  gate_tau=float("inf")), "unit_w")
+    I = Fi.to_host()
+    assert not np.any(I["flags"] & diaf.FLAG_FELL_BACK)
+    # the learned W pattern is a subset of pattern(A^2) containing the diagonal
+    C = oracle_pattern(A, "A2")
+    for j in range(A.n):
+        rows = set(I["Wri"][I["Wcp"][j]:I["Wcp"][j + 1]])
+        assert j in rows
+        assert rows <= set(C.rowidx[C.colptr[j]:C.colptr[j + 1]])
+    for F in (plain, Fz, Fi):
+        F.close()
+    m.close()

@@ -1,0 +1,128 @@
+"""GPU apply M = W V^{-1} and right-preconditioned BiCGSTAB against the oracle.
+
+The GPU path factors, applies and solves with its own factors; the oracle
+does the same with its own (CPU) factors on the same matrix.  Iteration
+counts must agree within max(1, 5 %), and the GPU's true residual must meet
+the tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import oracle_pattern, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1208_3573_amd import diaf
+    assert torch.cuda.is_available()
+    return diaf.Context(0)
+
+
+CASES = {
+    "convdiff2d_32_gs_v": (lambda: synth.convdiff(32, 2, 1), "A", "gs_upper", 0, "unit_v"),
+    "convdiff2d_32_gs_w": (lambda: synth.convdiff(32, 2, 1), "A", "gs_upper", 0, "unit_w"),
+    "convdiff3d_16_v": (lambda: synth.convdiff(16, 3, 7), "A2", "topk_lower", 5, "unit_v"),
+    "convdiff3d_16_w": (lambda: synth.convdiff(16, 3, 7), "A2", "topk_lower", 5, "unit_w"),
+    "helmholtz_32_w": (lambda: synth.helmholtz(32, 10.0, 0.5), "A2", "topk_upper", 7, "unit_w"),
+    "convdiff3d_64_v": (lambda: synth.workload_matrix("convdiff3d_64"), "A2", "topk_lower", 5,
+                        "unit_v"),
+    "diag_spai": (lambda: synth.convdiff(16, 3, 8), "A2", "diag", 0, "unit_v"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bicgstab_iterations_match_oracle(ctx, name):
+    import torch
+    from paper_1208_3573_amd import diaf
+    build, w, v, l, mode = CASES[name]
+    A = build()
+    b = synth.rhs_ones(A)
+    J = oracle_pattern(A, w)
+    O = oracle.factor(A, J, mode, v, l)
+    upper = v in ("gs_upper", "topk_upper")
+    _, oinfo = oracle.bicgstab(A, b, O, upper=upper, tol=1e-8, maxit=1000)
+    say(f"case {name}: oracle its={oinfo.iters} flag={oinfo.flag}")
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w=w, v=v, v_count=l), mode)
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
+    say(f"case {name}: gpu its={info.iters} flag={info.flag} relres={info.relres:.3e} "
+        f"true={info.relres_true:.3e} levels={F.stats().v_levels}")
+    assert info.flag == oinfo.flag == 0
+    assert abs(info.iters - oinfo.iters) <= max(1, int(0.05 * oinfo.iters))
+    assert info.relres <= 1e-8
+    assert info.relres_true <= 1e-7
+    xs = x.cpu().numpy()
+    assert np.max(np.abs(xs - 1.0)) < 1e-3
+    F.close()
+
+
+def test_unpreconditioned_bicgstab_matches_oracle(ctx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(16, 3, 7)
+    b = synth.rhs_ones(A)
+    _, oinfo = oracle.bicgstab(A, b, None)
+    dA = diaf.DeviceCSC.from_host(A)
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dA, None, db, x, 1e-8, 1000)
+    assert abs(info.iters - oinfo.iters) <= max(1, int(0.05 * oinfo.iters))
+    assert info.flag == 0 and info.relres_true < 1e-7
+
+
+def test_bicgstab_flags_breakdown_and_maxit(ctx):
+    import torch
+    import scipy.sparse as sp
+    from paper_1208_3573_amd import diaf
+    # skew-symmetric plus a tiny diagonal so the diagonal is present: with
+    # M = I, <r, A r> = 1e-300 * ||r||^2 underflows the breakdown test
+    n = 64
+    Ad = np.zeros((n, n))
+    for i in range(n - 1):
+        Ad[i, i + 1] = 1.0
+        Ad[i + 1, i] = -1.0
+    np.fill_diagonal(Ad, 1e-320)
+    A = synth.CSC.from_scipy(sp.csc_matrix(Ad))
+    A.val[A.rowidx == np.repeat(np.arange(n), np.diff(A.colptr))] = 0.0
+    dA = diaf.DeviceCSC.from_host(A)
+    db = torch.ones(n, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dA, None, db, x, 1e-8, 100)
+    _, oinfo = oracle.bicgstab(A, np.ones(n), None, maxit=100)
+    assert info.flag == 2 and oinfo.flag == 2 and info.iters == oinfo.iters == 1
+    A = synth.convdiff(16, 2, 2)
+    dA = diaf.DeviceCSC.from_host(A)
+    db = torch.from_numpy(synth.rhs_ones(A)).cuda()
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dA, None, db, x, 1e-8, 3)
+    assert info.flag == 1 and info.iters == 3
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_apply_matches_oracle(ctx, cplx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(12, 3, 3) if not cplx else synth.helmholtz(40, 10.0, 0.5)
+    v = "topk_lower" if not cplx else "topk_upper"
+    J = oracle_pattern(A, "A2")
+    O = oracle.factor(A, J, "unit_v", v, 5)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(A.n) + (1j * rng.standard_normal(A.n) if cplx else 0)
+    yo = oracle.apply(O, x, upper=(v == "topk_upper"))
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=v, v_count=5), "unit_v")
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros_like(xd)
+    diaf.diaf_apply(ctx, F, xd, yd)
+    yg = yd.cpu().numpy()
+    err = np.linalg.norm(yg - yo) / np.linalg.norm(yo)
+    say(f"apply rel err {err:.3e}")
+    assert err < 1e-9
+    F.close()
