@@ -1,0 +1,202 @@
+"""Benchmark: direct approximate factoring AW ~ V + right-preconditioned
+BiCGSTAB on the 64^3 convection-diffusion workload (n = 262144, W pattern
+pattern(A^2), V = diagonal + top-4 |A w0| rows of the lower triangle of the
+shadow, unit-norm-v mode), learned vs plain W pattern, one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode unit_v|unit_w]
+
+A step is one pass of the hot path on device-resident A and b: W pattern ->
+factor (all columns) -> V assembly -> BiCGSTAB to 1e-8.  `value` is
+columns factored and solved per second over the step; the factoring pass
+alone, the solve, BiCGSTAB iterations and the learned-pattern variant are
+reported beside it, with the factor kernel's roofline and the CPU oracle's
+rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+WORKLOAD = "convdiff3d_64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(A, Jri, lcount, sv):
+    """Per-column compulsory traffic of the factoring pass, summed: gather of
+    A(:, J_j) (values + row indices + the colptr pair of each column), the
+    J_j read, the W write, the V write (values + rows) and r_j."""
+    cn = np.diff(A.colptr).astype(np.int64)
+    gathered = int(cn[Jri].sum())
+    k = len(Jri)
+    total = gathered * (sv + 4) + 8 * k + 4 * k + k * (sv + 4) + int(lcount.sum()) * (sv + 4) \
+        + 8 * A.n
+    return total, gathered
+
+
+def cpu_baseline(A, J, mode, v, l, upper, b):
+    """The oracle as it stands, on all host cores, on the full workload once
+    (factor + BiCGSTAB)."""
+    import oracle
+    nth = oracle.nthreads_default()
+    t0 = time.perf_counter()
+    F = oracle.factor(A, J, mode, v, l, nthreads=nth)
+    t1 = time.perf_counter()
+    _, info = oracle.bicgstab(A, b, F, upper=upper)
+    t2 = time.perf_counter()
+    return dict(value=A.n / (t2 - t0), unit="columns/s", cores=nth, kind="oracle",
+                sample=f"full {WORKLOAD} workload once: factor {t1 - t0:.2f} s + "
+                       f"BiCGSTAB {t2 - t1:.2f} s ({info.iters} its)",
+                factor_cols_per_s=A.n / (t1 - t0), iters=info.iters)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", default="unit_v", choices=["unit_v", "unit_w"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the "
+              "multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1208_3573_amd import diaf
+    from paper_1208_3573_amd import learned as LR
+
+    cfg = synth.WORKLOADS[WORKLOAD]
+    A = synth.workload_matrix(WORKLOAD)
+    b = synth.rhs_ones(A)
+    upper = cfg["v"].endswith("upper")
+    ctx = diaf.Context(0)
+    dA = diaf.DeviceCSC.from_host(A)
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    spec = diaf.make_spec(w=cfg["w"], v=cfg["v"], v_count=cfg["v_count"])
+
+    def step(spec_):
+        t0 = time.perf_counter()
+        F = diaf.diaf_factor(ctx, dA, spec_, args.mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        st = F.stats()
+        return F, st, info, (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+    for _ in range(args.warmup):
+        F, st, info, fms, sms = step(spec)
+        log(f"warmup: factor {fms:.1f} ms, solve {sms:.1f} ms, {info.iters} its")
+        F.close()
+    torch.cuda.synchronize()
+    recs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        F, st, info, fms, sms = step(spec)
+        log(f"step: factor {fms:.1f} ms, solve {sms:.1f} ms, {info.iters} its")
+        recs.append((st.ms_factor_kernels, st.ms_pattern, st.ms_factor, st.ms_assemble, fms, sms,
+                     info.iters, info.relres_true, st.factor_launches))
+        last = F
+        if len(recs) < args.steps:
+            F.close()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    ms_step = t_total * 1e3 / args.steps
+    R = np.array(recs, dtype=float)
+    kern_ms = float(np.mean(R[:, 0]))
+    factor_ms = float(np.mean(R[:, 4]))
+    solve_ms = float(np.mean(R[:, 5]))
+    iters = int(R[-1, 6])
+    st = last.stats()
+    H = last.to_host()
+    sv = 16 if A.is_complex else 8
+    bytes_alg, gathered = algorithmic_bytes(A, H["Wri"], H["lcount"], sv)
+    launches = max(1, int(R[-1, 8]))
+    achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
+    out = {
+        "metric": "columns factored/s + factor+solve time to 1e-8, learned vs plain, 1 GPU",
+        "value": A.n / (ms_step * 1e-3),
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": A.n, "nnz": A.nnz, "w_pattern": cfg["w"],
+                   "v_pattern": f"{cfg['v']} l={cfg['v_count']}", "mode": args.mode,
+                   "rhs": "A*ones", "rtol": 1e-8},
+        "factor_ms": factor_ms,
+        "factor_kernel_ms": kern_ms,
+        "factor_cols_per_s": A.n / (factor_ms * 1e-3),
+        "factor_kernel_cols_per_s": A.n / (kern_ms * 1e-3),
+        "solve_ms": solve_ms,
+        "bicgstab_iters": iters,
+        "relres_true": float(R[-1, 7]),
+        "nrm": st.nrm,
+        "v_levels": st.v_levels,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "factor_generic_kernel", "bytes_per_pass": bytes_alg,
+                     "launches_per_pass": launches},
+    }
+    last.close()
+
+    if not args.no_learned:
+        log("learned: preparing model")
+        model, gate = LR.load_or_train(ctx, args.mode, log=log)
+        lspec = diaf.make_spec(w="learned", v=cfg["v"], v_count=cfg["v_count"], model=model,
+                               gate_tau=gate)
+        for _ in range(args.warmup):
+            F, lst, linfo, lf, ls = step(lspec)
+            log(f"learned warmup: factor {lf:.1f} ms, solve {ls:.1f} ms, {linfo.iters} its, "
+                f"flag {linfo.flag}, fell back {lst.count_fell_back}, nnz(W) {lst.nnz_w}")
+            F.close()
+        lrec = []
+        for _ in range(args.steps):
+            F, lst, linfo, lf, ls = step(lspec)
+            log(f"learned step: factor {lf:.1f} ms, solve {ls:.1f} ms, {linfo.iters} its")
+            lrec.append((lf, ls, linfo.iters, lst.count_fell_back, lst.nnz_w))
+            F.close()
+        L_ = np.array(lrec, dtype=float)
+        out["learned"] = {"factor_ms": float(L_[:, 0].mean()), "solve_ms": float(L_[:, 1].mean()),
+                          "e2e_ms": float((L_[:, 0] + L_[:, 1]).mean()),
+                          "bicgstab_iters": int(L_[-1, 2]), "fell_back": int(L_[-1, 3]),
+                          "nnz_w": int(L_[-1, 4]), "gate_tau": gate}
+        out["plain"] = {"factor_ms": factor_ms, "solve_ms": solve_ms,
+                        "e2e_ms": factor_ms + solve_ms, "bicgstab_iters": iters,
+                        "nnz_w": int(len(H["Wri"]))}
+        model.close()
+
+    if not args.no_cpu:
+        log("cpu baseline: oracle on host cores")
+        import oracle
+        Jo = oracle.pattern_A2(A)
+        out["cpu_baseline"] = cpu_baseline(A, Jo, args.mode, cfg["v"], cfg["v_count"], upper, b)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -147,9 +147,13 @@ typedef struct diaf_stats {
     int32_t nbuckets;                /* size classes launched */
     int32_t count_rank_deficient, count_gap_degenerate, count_small_diag, count_tie_edge,
         count_fell_back, count_no_diag;
-    int32_t v_levels;                /* dependency depth of the triangular V solve */
+    int32_t v_levels;                /* dependency depth of the triangular V solve
+                                        (filled by the first apply or solve) */
+    int32_t count_zero_pivot;        /* zero / non-finite diagonal entries of V (idem) */
+    int32_t factor_launches;         /* factor kernel launches (one per size class) */
     double nrm;                      /* ||A W - V||_F = sqrt(sum r_j^2) */
     double ms_pattern, ms_factor, ms_assemble;  /* device time of the phases */
+    double ms_factor_kernels;        /* device time of the factor kernels alone */
 } diaf_stats;
 
 typedef struct diaf_solve_info {
@@ -194,13 +198,15 @@ void diaf_factors_destroy(struct diaf_factors* F);
 
 /* ---- apply and solve (eq. 2.1, Section 5) -------------------------------- */
 
-/* y = W V^{-1} x for triangular or diagonal V (n entries each). */
+/* y = W V^{-1} x for triangular or diagonal V (n entries each).
+ * DIAF_ESINGULAR when V has a zero or non-finite diagonal entry. */
 diaf_status diaf_apply(struct diaf_ctx* ctx, const struct diaf_factors* F, const void* x,
                        void* y);
 
 /* Right-preconditioned BiCGSTAB on A M u = b, x = M u, M = W V^{-1}
  * (F == NULL: M = I), x0 = 0, stop when ||r|| <= rtol ||b||.  Returns
- * DIAF_OK, DIAF_ENOCONV or DIAF_EBREAKDOWN with *info_host filled. */
+ * DIAF_OK, DIAF_ENOCONV, DIAF_EBREAKDOWN or DIAF_ESINGULAR (V has a zero
+ * pivot: x = 0, info flag 3) with *info_host filled. */
 diaf_status diaf_solve(struct diaf_ctx* ctx, const diaf_csc* A, const struct diaf_factors* F,
                        const void* b, void* x, double rtol, int32_t maxit,
                        diaf_solve_info* info_host);

@@ -326,6 +326,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     fa.flags = F->flags;
     fa.lcount = F->lcount;
     std::vector<void*> to_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     int nb = 0;
     for (auto& b : B) {
         if (b.cols.empty()) continue;
@@ -338,15 +339,31 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         fa.cols = cols;
         fa.ncols = (int)b.cols.size();
         int nslots = 1024;
-        size_t gbytes = generic_global_bytes<T>(b.kcap, b.tcap, F->lmax, nslots);
+        size_t gbytes = generic_global_bytes<T>(b.kcap, b.tcap, F->lmax, mode, nslots);
         void* gm = nullptr;
         if (gbytes) {
             DIAF_TRY(dmalloc((unsigned char**)&gm, gbytes));
             to_free.push_back(gm);
         }
+        hipEvent_t e0, e1;
+        DIAF_HIP_TRY(hipEventCreate(&e0));
+        DIAF_HIP_TRY(hipEventCreate(&e1));
+        DIAF_HIP_TRY(hipEventRecord(e0, st));
         DIAF_TRY(launch_factor_generic<T>(fa, b.kcap, b.tcap, F->lmax, gm, nslots, st));
+        DIAF_HIP_TRY(hipEventRecord(e1, st));
+        events.push_back({e0, e1});
     }
     DIAF_TRY(sync(st));
+    double kms = 0;
+    for (auto& ev : events) {
+        float ms = 0;
+        DIAF_HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
+        kms += ms;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    F->stats.ms_factor_kernels += kms;
+    F->stats.factor_launches += (int32_t)events.size();
     for (void* p : to_free) dfree(p);
     if (nbuckets) *nbuckets = nb;
     return {};
@@ -424,8 +441,19 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
     DIAF_TRY(dmalloc(&F->ready, sizeof(uint32_t) * n));
     DIAF_HIP_TRY(hipMemsetAsync(F->ctl, 0, sizeof(TrsvCtl), st));
     DIAF_HIP_TRY(hipMemsetAsync(F->ready, 0, sizeof(uint32_t) * n, st));
+    {
+        int32_t* bad = nullptr;
+        DIAF_TRY(dmalloc(&bad, sizeof(int32_t)));
+        DIAF_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+        DIAF_TRY(launch_diag_check<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, bad, st));
+        int32_t nb = 0;
+        DIAF_TRY(read1(bad, &nb, st));
+        dfree(bad);
+        F->stats.count_zero_pivot = nb;
+    }
     DIAF_TRY(sync(st));
     F->apply_ready = true;
+    if (F->stats.count_zero_pivot) return {};
     // dependency depth of V
     if (F->vtri != 0) {
         int32_t *lvl = nullptr, *mx = nullptr;
@@ -595,14 +623,19 @@ diaf_status diaf_apply(diaf_ctx* ctx, const diaf_factors* Fc, const void* x, voi
     auto* F = const_cast<diaf_factors*>(Fc);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
     Err e;
-    if (F->dtype == DIAF_F64) {
-        e = ensure_apply<double>(ctx, F);
-        if (!e.code) e = enqueue_apply<double>(ctx, F, (const double*)x, (double*)y, nullptr);
-    } else {
-        e = ensure_apply<zc>(ctx, F);
-        if (!e.code) e = enqueue_apply<zc>(ctx, F, (const zc*)x, (zc*)y, nullptr);
-    }
+    e = F->dtype == DIAF_F64 ? ensure_apply<double>(ctx, F) : ensure_apply<zc>(ctx, F);
     if (e.code) return fail(ctx, e);
+    if (F->stats.count_zero_pivot)
+        return fail(ctx, DIAF_ESINGULAR, std::to_string(F->stats.count_zero_pivot) +
+                                             " zero or non-finite pivots in V");
+    if (F->dtype == DIAF_F64)
+        e = enqueue_apply<double>(ctx, F, (const double*)x, (double*)y, nullptr);
+    else
+        e = enqueue_apply<zc>(ctx, F, (const zc*)x, (zc*)y, nullptr);
+    if (e.code) return fail(ctx, e);
+    if (F->stats.count_zero_pivot)
+        return fail(ctx, DIAF_ESINGULAR, std::to_string(F->stats.count_zero_pivot) +
+                                             " zero or non-finite pivots in V");
     if (F->vtri != 0) {
         TrsvCtl c{};
         e = read1(F->ctl, &c, ctx->stream);
@@ -811,6 +844,17 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     if (F) {
         if (F->n != n || F->dtype != A->dtype) return {DIAF_EINVAL, "factors do not match A"};
         DIAF_TRY(ensure_apply<T>(ctx, F));
+        if (F->stats.count_zero_pivot) {
+            // the first preconditioner application would divide by zero
+            DIAF_HIP_TRY(hipMemsetAsync(x, 0, sizeof(T) * n, st));
+            DIAF_TRY(sync(st));
+            info->iters = 1;
+            info->flag = 3;
+            info->relres = 1.0;
+            info->relres_true = 1.0;
+            info->ms = 0.0;
+            return {};
+        }
     }
     // CSR copy of A
     int32_t *rp = nullptr, *ci = nullptr;
@@ -893,6 +937,7 @@ extern "C" diaf_status diaf_solve(diaf_ctx* ctx, const diaf_csc* A, const diaf_f
     if (e.code) return fail(ctx, e);
     if (info->flag == 1) return fail(ctx, DIAF_ENOCONV, "BiCGSTAB: no convergence within maxit");
     if (info->flag == 2) return fail(ctx, DIAF_EBREAKDOWN, "BiCGSTAB: breakdown");
+    if (info->flag == 3) return fail(ctx, DIAF_ESINGULAR, "V has a zero or non-finite pivot");
     return DIAF_OK;
 }
 

@@ -22,7 +22,7 @@
 
 namespace diaf {
 
-static constexpr int GNT = 256;  // threads per workgroup
+static constexpr int GNT = 256;  // largest workgroup (small size classes use one wave)
 
 struct GenLayout {
     size_t oJ, oOff, oKey, oVal, oLrow, oCol, oPos, oRowptr, oR, oRank, oY, oW, oX, oVM, oSig,
@@ -32,7 +32,9 @@ struct GenLayout {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // Working storage of one column.  The key array (sort keys) is dead after
-// the shadow is built and is reused for the selection scores.
+// the shadow is built and is reused for the selection scores.  with_mats =
+// number of k x k matrices kept here (1: G, unit-norm v; 3: G, E, Z,
+// unit-norm w; 0: in a separate global slot).
 __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, int lcap, size_t st,
                                                 int with_mats)
 {
@@ -60,7 +62,7 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
     L.oRed = take(sizeof(double) * GNT);
     L.oMisc = take(sizeof(double) * 32);
     L.oMats = o;
-    if (with_mats) take(st * 3 * (size_t)kcap * kcap);
+    if (with_mats) take(st * (size_t)with_mats * kcap * kcap);
     L.total = o;
     return L;
 }
@@ -71,7 +73,7 @@ enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2 };
 
 template <class T>
 struct GenCtx {
-    int tid;
+    int tid, nt;
     int32_t* sJ; int32_t* sOff; uint64_t* sKey; T* sVal; uint16_t* sLrow; uint16_t* sCol;
     uint16_t* sPos; uint16_t* sRowptr; int32_t* sR; int32_t* sRank; T* sY; T* sW; T* sX; T* sVM;
     double* sSig; T* sV; int32_t* sL; int32_t* sSel; double* sScore; double* sRed;
@@ -85,7 +87,7 @@ __device__ inline double block_sum(GenCtx<T>& c, double x)
 {
     c.sRed[c.tid] = x;
     __syncthreads();
-    for (int s = GNT / 2; s > 0; s >>= 1) {
+    for (int s = c.nt / 2; s > 0; s >>= 1) {
         if (c.tid < s) c.sRed[c.tid] += c.sRed[c.tid + s];
         __syncthreads();
     }
@@ -99,7 +101,7 @@ template <class T>
 __device__ inline int block_scan_flags(GenCtx<T>& c, const int32_t* flags, int32_t* out, int cnt)
 {
     // each thread owns a contiguous chunk
-    int chunk = (cnt + GNT - 1) / GNT;
+    int chunk = (cnt + c.nt - 1) / c.nt;
     int b = c.tid * chunk, e = min(cnt, b + chunk);
     int s = 0;
     for (int i = b; i < e; ++i) s += flags[i];
@@ -107,7 +109,7 @@ __device__ inline int block_scan_flags(GenCtx<T>& c, const int32_t* flags, int32
     __syncthreads();
     if (c.tid == 0) {
         double acc = 0;
-        for (int t = 0; t < GNT; ++t) { double v = c.sRed[t]; c.sRed[t] = acc; acc += v; }
+        for (int t = 0; t < c.nt; ++t) { double v = c.sRed[t]; c.sRed[t] = acc; acc += v; }
         c.md[MD_SSTAR] = acc;
     }
     __syncthreads();
@@ -123,7 +125,7 @@ __device__ inline int block_scan_flags(GenCtx<T>& c, const int32_t* flags, int32
 template <class T>
 __device__ inline void bmul(GenCtx<T>& c, int m, const T* w, T* y)
 {
-    for (int i = c.tid; i < m; i += GNT) {
+    for (int i = c.tid; i < m; i += c.nt) {
         T acc = num<T>::zero();
         for (int p = c.sRowptr[i]; p < c.sRowptr[i + 1]; ++p) {
             int t = c.sPos[p];
@@ -168,11 +170,11 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
         }
         __syncthreads();
         const double piv = c.md[MD_PIV];
-        for (int i = p + 1 + c.tid; i < k; i += GNT)
+        for (int i = p + 1 + c.tid; i < k; i += c.nt)
             G[i * k + p] = piv > 0.0 ? num<T>::div(G[i * k + p], piv) : num<T>::zero();
         __syncthreads();
         const int rem = k - p - 1;
-        for (int idx = c.tid; idx < rem * rem; idx += GNT) {
+        for (int idx = c.tid; idx < rem * rem; idx += c.nt) {
             int i = p + 1 + idx / rem, q = p + 1 + idx % rem;
             if (q <= i) G[i * k + q] -= G[i * k + p] * num<T>::conj(G[q * k + p]);
         }
@@ -186,11 +188,11 @@ __device__ inline void lsolve(GenCtx<T>& c, const T* Lf, int k, T* X, int nr)
 {
     for (int p = 0; p < k; ++p) {
         const double d = num<T>::re(Lf[p * k + p]);
-        for (int t = c.tid; t < nr; t += GNT)
+        for (int t = c.tid; t < nr; t += c.nt)
             X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
         __syncthreads();
         const int rem = k - p - 1;
-        for (int idx = c.tid; idx < rem * nr; idx += GNT) {
+        for (int idx = c.tid; idx < rem * nr; idx += c.nt) {
             int i = p + 1 + idx / nr, t = idx % nr;
             X[i * c.xld + t] -= Lf[i * k + p] * X[p * c.xld + t];
         }
@@ -204,10 +206,10 @@ __device__ inline void lhsolve(GenCtx<T>& c, const T* Lf, int k, T* X, int nr)
 {
     for (int p = k - 1; p >= 0; --p) {
         const double d = num<T>::re(Lf[p * k + p]);
-        for (int t = c.tid; t < nr; t += GNT)
+        for (int t = c.tid; t < nr; t += c.nt)
             X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
         __syncthreads();
-        for (int idx = c.tid; idx < p * nr; idx += GNT) {
+        for (int idx = c.tid; idx < p * nr; idx += c.nt) {
             int i = idx / nr, t = idx % nr;
             X[i * c.xld + t] -= num<T>::conj(Lf[p * k + i]) * X[p * c.xld + t];
         }
@@ -242,7 +244,7 @@ __device__ inline void jrot(double al, double be, T g, double& cs, double& sn, T
 template <class T>
 __device__ inline void jacobi_onesided(GenCtx<T>& c, T* M, int k, int l, T* VM)
 {
-    for (int idx = c.tid; idx < l * l; idx += GNT)
+    for (int idx = c.tid; idx < l * l; idx += c.nt)
         VM[idx] = (idx / l == idx % l) ? num<T>::one() : num<T>::zero();
     const int np = l + (l & 1);
     __shared__ double s_c[128], s_s[128];
@@ -252,7 +254,7 @@ __device__ inline void jacobi_onesided(GenCtx<T>& c, T* M, int k, int l, T* VM)
         if (c.tid == 0) c.mi[MI_ROT] = 0;
         __syncthreads();
         for (int r = 0; r < np - 1; ++r) {
-            for (int i = c.tid; i < np / 2; i += GNT) {
+            for (int i = c.tid; i < np / 2; i += c.nt) {
                 int a, b;
                 rr_pair(np, r, i, a, b);
                 s_p[i] = a; s_q[i] = b; s_s[i] = 0.0; s_c[i] = 1.0;
@@ -276,7 +278,7 @@ __device__ inline void jacobi_onesided(GenCtx<T>& c, T* M, int k, int l, T* VM)
             }
             __syncthreads();
             const int npair = np / 2;
-            for (int idx = c.tid; idx < npair * (k + l); idx += GNT) {
+            for (int idx = c.tid; idx < npair * (k + l); idx += c.nt) {
                 int i = idx % npair, e = idx / npair;
                 if (s_s[i] == 0.0) continue;
                 int a = s_p[i], b = s_q[i];
@@ -302,7 +304,7 @@ __device__ inline void jacobi_onesided(GenCtx<T>& c, T* M, int k, int l, T* VM)
 template <class T>
 __device__ inline void jacobi_eig(GenCtx<T>& c, T* E, T* Z, int k)
 {
-    for (int idx = c.tid; idx < k * k; idx += GNT)
+    for (int idx = c.tid; idx < k * k; idx += c.nt)
         Z[idx] = (idx / k == idx % k) ? num<T>::one() : num<T>::zero();
     if (c.tid == 0) {
         double mx = 0;
@@ -320,7 +322,7 @@ __device__ inline void jacobi_eig(GenCtx<T>& c, T* E, T* Z, int k)
         if (c.tid == 0) c.mi[MI_ROT] = 0;
         __syncthreads();
         for (int r = 0; r < np - 1; ++r) {
-            for (int i = c.tid; i < npair; i += GNT) {
+            for (int i = c.tid; i < npair; i += c.nt) {
                 int a, b;
                 rr_pair(np, r, i, a, b);
                 s_p[i] = a; s_q[i] = b; s_s[i] = 0.0; s_c[i] = 1.0;
@@ -338,7 +340,7 @@ __device__ inline void jacobi_eig(GenCtx<T>& c, T* E, T* Z, int k)
             }
             __syncthreads();
             // rows: E[[a,b], :] <- J^* E[[a,b], :]
-            for (int idx = c.tid; idx < npair * k; idx += GNT) {
+            for (int idx = c.tid; idx < npair * k; idx += c.nt) {
                 int i = idx % npair, e = idx / npair;
                 if (s_s[i] == 0.0) continue;
                 int a = s_p[i], b = s_q[i];
@@ -350,7 +352,7 @@ __device__ inline void jacobi_eig(GenCtx<T>& c, T* E, T* Z, int k)
             }
             __syncthreads();
             // columns: E[:, [a,b]] <- E[:, [a,b]] J, Z likewise
-            for (int idx = c.tid; idx < npair * 2 * k; idx += GNT) {
+            for (int idx = c.tid; idx < npair * 2 * k; idx += c.nt) {
                 int i = idx % npair, e = idx / npair;
                 if (s_s[i] == 0.0) continue;
                 int a = s_p[i], b = s_q[i];
@@ -393,7 +395,7 @@ __device__ inline int select_topk(GenCtx<T>& c, int m, int nc, int q)
         return cnt;
     }
     // rank of each candidate: larger score first, lower row on ties
-    for (int t = c.tid; t < m; t += GNT) {
+    for (int t = c.tid; t < m; t += c.nt) {
         double st = c.sScore[t];
         if (st < 0.0) continue;
         int rk = 0;
@@ -454,7 +456,7 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     const int k = A.Jcp[j + 1] - jb;
     // ---- 1. J_j and per-column offsets ----
     if (tid == 0) { c.mi[MI_FLAGS] = 0; c.sOff[0] = 0; }
-    for (int a = tid; a < k; a += GNT) {
+    for (int a = tid; a < k; a += c.nt) {
         int col = A.Jri[jb + a];
         c.sJ[a] = col;
         c.sOff[a + 1] = A.Acp[col + 1] - A.Acp[col];
@@ -469,7 +471,7 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     int T2 = 1;
     while (T2 < Tn) T2 <<= 1;
     // ---- 2. gather ----
-    for (int t = tid; t < T2; t += GNT) {
+    for (int t = tid; t < T2; t += c.nt) {
         if (t < Tn) {
             int lo = 0, hi = k - 1;  // largest a with sOff[a] <= t
             while (lo < hi) {
@@ -489,7 +491,7 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     // ---- 3. bitonic sort by (row, t) ----
     for (int kk = 2; kk <= T2; kk <<= 1) {
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < T2; i += GNT) {
+            for (int i = tid; i < T2; i += c.nt) {
                 int ixj = i ^ jj;
                 if (ixj > i) {
                     uint64_t x = c.sKey[i], y = c.sKey[ixj];
@@ -501,11 +503,11 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         }
     }
     // ---- 4. shadow rows and CSR/CSC cross references ----
-    for (int i = tid; i < Tn; i += GNT)
+    for (int i = tid; i < Tn; i += c.nt)
         c.sRank[i] = (i == 0 || (c.sKey[i] >> 32) != (c.sKey[i - 1] >> 32)) ? 1 : 0;
     __syncthreads();
     int m = block_scan_flags(c, c.sRank, c.sRank, Tn);
-    for (int i = tid; i < Tn; i += GNT) {
+    for (int i = tid; i < Tn; i += c.nt) {
         int lr = c.sRank[i] - 1;
         int t = (int)(uint32_t)c.sKey[i];
         c.sPos[i] = t;
@@ -523,14 +525,14 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     // ||B||_F
     {
         double s = 0;
-        for (int t = tid; t < Tn; t += GNT) s += num<T>::abs2(c.sVal[t]);
+        for (int t = tid; t < Tn; t += c.nt) s += num<T>::abs2(c.sVal[t]);
         double bn2 = block_sum(c, s);
         if (tid == 0) c.md[MD_BN2] = bn2;
     }
     const int lmax = A.lmax;
     if (dj < 0) {
-        for (int a = tid; a < k; a += GNT) A.Wval[jb + a] = num<T>::zero();
-        for (int t = tid; t < lmax; t += GNT) {
+        for (int a = tid; a < k; a += c.nt) A.Wval[jb + a] = num<T>::zero();
+        for (int t = tid; t < lmax; t += c.nt) {
             A.Vrows[(size_t)j * lmax + t] = -1;
             A.Vvals[(size_t)j * lmax + t] = num<T>::zero();
         }
@@ -545,7 +547,7 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     }
     // ---- 5. Gram matrix G = B^* B by sparse merges ----
     T* G = c.G;
-    for (int idx = tid; idx < k * k; idx += GNT) {
+    for (int idx = tid; idx < k * k; idx += c.nt) {
         int a = idx / k, b = idx % k;
         if (b < a) continue;
         int pa = c.sOff[a], ea = c.sOff[a + 1], pb = c.sOff[b], eb = c.sOff[b + 1];
@@ -586,20 +588,20 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         T* E = c.E; T* Z = c.Z;
         if (A.mode == 0) {
             // seed w0 = G^{-1} b_j^*  (V_0 = diagonals: the SPAI column)
-            for (int a = tid; a < k; a += GNT) c.sX[a * c.xld] = num<T>::zero();
+            for (int a = tid; a < k; a += c.nt) c.sX[a * c.xld] = num<T>::zero();
             __syncthreads();
-            for (int p = c.sRowptr[dj] + tid; p < c.sRowptr[dj + 1]; p += GNT) {
+            for (int p = c.sRowptr[dj] + tid; p < c.sRowptr[dj + 1]; p += c.nt) {
                 int t = c.sPos[p];
                 c.sX[c.sCol[t] * c.xld] = num<T>::conj(c.sVal[t]);
             }
             __syncthreads();
             lsolve(c, G, k, c.sX, 1);
             lhsolve(c, G, k, c.sX, 1);
-            for (int a = tid; a < k; a += GNT) c.sW[a] = c.sX[a * c.xld];
+            for (int a = tid; a < k; a += c.nt) c.sW[a] = c.sX[a * c.xld];
             __syncthreads();
         } else {
             // seed: bottom eigenvector of G - b_j^* b_j
-            for (int idx = tid; idx < k * k; idx += GNT) {
+            for (int idx = tid; idx < k * k; idx += c.nt) {
                 int a = idx / k, b = idx % k;
                 E[idx] = G[idx] - num<T>::cmul(bget(c, dj, a), bget(c, dj, b));
             }
@@ -613,13 +615,13 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
             }
             __syncthreads();
             const int lo = c.mi[MI_BEST];
-            for (int a = tid; a < k; a += GNT) c.sW[a] = Z[a * k + lo];
+            for (int a = tid; a < k; a += c.nt) c.sW[a] = Z[a * k + lo];
             __syncthreads();
         }
         bmul(c, m, c.sW, c.sY);
         // scores of the admissible rows (ascending row order); -1 elsewhere
         int ncl = 0;
-        for (int i = tid; i < m; i += GNT) {
+        for (int i = tid; i < m; i += c.nt) {
             int gi = c.sR[i];
             int adm = (A.vrule == V_TOPK_LOWER) ? (gi > j) : (gi < j);
             c.sScore[i] = adm ? num<T>::abs(c.sY[i]) : -1.0;
@@ -666,14 +668,14 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     // ---- 7. final solve on (J_j, L_j) ----
     if (A.mode == 0) {
         // M = L^{-1} B_L^*  (k x l)
-        for (int idx = tid; idx < k * l; idx += GNT) {
+        for (int idx = tid; idx < k * l; idx += c.nt) {
             int a = idx / l, t = idx % l;
             c.sX[a * c.xld + t] = num<T>::conj(bget(c, c.sL[t], a));
         }
         __syncthreads();
         lsolve(c, G, k, c.sX, l);
         jacobi_onesided(c, c.sX, k, l, c.sVM);
-        for (int t = tid; t < l; t += GNT) {
+        for (int t = tid; t < l; t += c.nt) {
             double s = 0;
             for (int a = 0; a < k; ++a) s += num<T>::abs2(c.sX[a * c.xld + t]);
             c.sSig[t] = sqrt(s);
@@ -690,18 +692,18 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         }
         __syncthreads();
         const int best = c.mi[MI_BEST];
-        for (int t = tid; t < l; t += GNT) c.sV[t] = c.sVM[t * l + best];
+        for (int t = tid; t < l; t += c.nt) c.sV[t] = c.sVM[t * l + best];
         // u = M v = (rotated M)(:, best); w = L^{-*} u
-        for (int a = tid; a < k; a += GNT) c.sX[a * c.xld + l] = c.sX[a * c.xld + best];
+        for (int a = tid; a < k; a += c.nt) c.sX[a * c.xld + l] = c.sX[a * c.xld + best];
         __syncthreads();
-        for (int a = tid; a < k; a += GNT) c.sX[a * c.xld] = c.sX[a * c.xld + l];
+        for (int a = tid; a < k; a += c.nt) c.sX[a * c.xld] = c.sX[a * c.xld + l];
         __syncthreads();
         lhsolve(c, G, k, c.sX, 1);
-        for (int a = tid; a < k; a += GNT) c.sW[a] = c.sX[a * c.xld];
+        for (int a = tid; a < k; a += c.nt) c.sW[a] = c.sX[a * c.xld];
         __syncthreads();
     } else {
         T* E = c.E; T* Z = c.Z;
-        for (int idx = tid; idx < k * k; idx += GNT) {
+        for (int idx = tid; idx < k * k; idx += c.nt) {
             int a = idx / k, b = idx % k;
             T acc = G[idx];
             for (int t = 0; t < l; ++t) acc -= num<T>::cmul(bget(c, c.sL[t], a), bget(c, c.sL[t], b));
@@ -727,10 +729,10 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         }
         __syncthreads();
         const int lo = c.mi[MI_BEST];
-        for (int a = tid; a < k; a += GNT) c.sW[a] = Z[a * k + lo];
+        for (int a = tid; a < k; a += c.nt) c.sW[a] = Z[a * k + lo];
         __syncthreads();
         bmul(c, m, c.sW, c.sY);
-        for (int t = tid; t < l; t += GNT) c.sV[t] = c.sY[c.sL[t]];
+        for (int t = tid; t < l; t += c.nt) c.sV[t] = c.sY[c.sL[t]];
         __syncthreads();
     }
 
@@ -765,9 +767,9 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         for (int t = 0; t < l; ++t) c.sY[c.sL[t]] -= c.sV[t];
     __syncthreads();
     double s = 0;
-    for (int i = tid; i < m; i += GNT) s += num<T>::abs2(c.sY[i]);
+    for (int i = tid; i < m; i += c.nt) s += num<T>::abs2(c.sY[i]);
     double r2 = block_sum(c, s);
-    for (int a = tid; a < k; a += GNT) A.Wval[jb + a] = c.sW[a];
+    for (int a = tid; a < k; a += c.nt) A.Wval[jb + a] = c.sW[a];
     if (tid == 0) {
         // V column sorted by row (local order = global order)
         for (int a = 1; a < l; ++a) {
@@ -792,15 +794,16 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
 
 template <class T, bool IN_LDS>
 __global__ void __launch_bounds__(GNT) factor_generic_kernel(FactorArgs<T> A, int kcap, int tcap,
-                                                             int tcap2, int lcap, int mats_here,
+                                                             int tcap2, int lcap, int nmats_here,
                                                              unsigned char* gws, size_t slot_bytes,
                                                              T* gmats)
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     unsigned char* base = IN_LDS ? lds_dyn : gws + (size_t)blockIdx.x * slot_bytes;
-    GenLayout Lo = gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), mats_here);
+    GenLayout Lo = gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), nmats_here);
     GenCtx<T> c;
     c.tid = threadIdx.x;
+    c.nt = blockDim.x;
     c.sJ = (int32_t*)(base + Lo.oJ);
     c.sOff = (int32_t*)(base + Lo.oOff);
     c.sKey = (uint64_t*)(base + Lo.oKey);
@@ -825,7 +828,9 @@ __global__ void __launch_bounds__(GNT) factor_generic_kernel(FactorArgs<T> A, in
     c.md = (double*)(base + Lo.oMisc);
     c.xld = lcap + 1;
     const size_t kk = (size_t)kcap * kcap;
-    T* mats = mats_here ? (T*)(base + Lo.oMats) : gmats + (size_t)blockIdx.x * 3 * kk;
+    // global k x k matrices (when not here): 1 per block for unit-norm v, 3 otherwise
+    T* mats = nmats_here ? (T*)(base + Lo.oMats)
+                         : gmats + (size_t)blockIdx.x * (A.mode == 0 ? 1 : 3) * kk;
     c.G = mats;
     c.E = mats + kk;
     c.Z = mats + 2 * kk;
@@ -842,19 +847,24 @@ size_t generic_lds_bytes(int kcap, int tcap, int lcap, int with_mats)
 
 // Placement of a size class: working set in LDS (with or without the k x k
 // matrices) when it fits, otherwise a per-block slot of global memory.
+// Columns of at most 32 unknowns run one wave per workgroup.
 struct GenPlan {
     bool in_lds;
     bool mats_here;
+    int nmats;          // k x k matrices per column: 1 (unit-norm v) or 3
+    int nt;             // threads per workgroup
     size_t lds_bytes;   // dynamic LDS
     size_t slot_bytes;  // global slot per block (in_lds == false)
     bool need_gmats;    // separate global k x k matrices
 };
 
 template <class T>
-GenPlan generic_plan(int kcap, int tcap, int lcap)
+GenPlan generic_plan(int kcap, int tcap, int lcap, int mode)
 {
     GenPlan P{};
-    size_t with = generic_lds_bytes<T>(kcap, tcap, lcap, 1);
+    P.nmats = mode == 0 ? 1 : 3;
+    P.nt = kcap <= 32 ? 64 : GNT;
+    size_t with = generic_lds_bytes<T>(kcap, tcap, lcap, P.nmats);
     size_t without = generic_lds_bytes<T>(kcap, tcap, lcap, 0);
     if (with <= 64 * 1024) {
         P.in_lds = true; P.mats_here = true; P.lds_bytes = with;
@@ -867,11 +877,11 @@ GenPlan generic_plan(int kcap, int tcap, int lcap)
 }
 
 template <class T>
-size_t generic_global_bytes(int kcap, int tcap, int lcap, int nslots)
+size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots)
 {
-    GenPlan P = generic_plan<T>(kcap, tcap, lcap);
+    GenPlan P = generic_plan<T>(kcap, tcap, lcap, mode);
     if (P.in_lds && !P.need_gmats) return 0;
-    if (P.need_gmats) return sizeof(T) * 3 * (size_t)kcap * kcap * nslots;
+    if (P.need_gmats) return sizeof(T) * P.nmats * (size_t)kcap * kcap * nslots;
     return P.slot_bytes * nslots;
 }
 
@@ -883,7 +893,7 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
     if (tcap > 65535) return {DIAF_EUNSUPPORTED, "column too large"};
     int tcap2 = 1;
     while (tcap2 < tcap) tcap2 <<= 1;
-    GenPlan P = generic_plan<T>(kcap, tcap, lcap);
+    GenPlan P = generic_plan<T>(kcap, tcap, lcap, A.mode);
     int grid = A.ncols;
     if (!(P.in_lds && !P.need_gmats)) {
         if (!gws) return {DIAF_EINVAL, "generic factor: workspace missing"};
@@ -895,12 +905,13 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
         DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern,
                                          hipFuncAttributeMaxDynamicSharedMemorySize,
                                          (int)P.lds_bytes));
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(GNT), P.lds_bytes, st, A, kcap, tcap, tcap2, lcap,
-                           (int)P.mats_here, (unsigned char*)nullptr, (size_t)0, (T*)gws);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(P.nt), P.lds_bytes, st, A, kcap, tcap, tcap2,
+                           lcap, P.mats_here ? P.nmats : 0, (unsigned char*)nullptr, (size_t)0,
+                           (T*)gws);
     } else {
         auto kern = factor_generic_kernel<T, false>;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(GNT), 0, st, A, kcap, tcap, tcap2, lcap, 1,
-                           (unsigned char*)gws, P.slot_bytes, (T*)nullptr);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(P.nt), 0, st, A, kcap, tcap, tcap2, lcap,
+                           P.nmats, (unsigned char*)gws, P.slot_bytes, (T*)nullptr);
     }
     DIAF_HIP_TRY(hipGetLastError());
     return {};
@@ -909,7 +920,7 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
 template Err launch_factor_generic<double>(const FactorArgs<double>&, int, int, int, void*, int,
                                            hipStream_t);
 template Err launch_factor_generic<zc>(const FactorArgs<zc>&, int, int, int, void*, int, hipStream_t);
-template size_t generic_global_bytes<double>(int, int, int, int);
-template size_t generic_global_bytes<zc>(int, int, int, int);
+template size_t generic_global_bytes<double>(int, int, int, int, int);
+template size_t generic_global_bytes<zc>(int, int, int, int, int);
 
 }  // namespace diaf

@@ -28,7 +28,7 @@ template <class T>
 Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, void* gws,
                           int nslots, hipStream_t st);
 template <class T>
-size_t generic_global_bytes(int kcap, int tcap, int lcap, int nslots);
+size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots);
 
 // ---- assembly and sparse utilities (sparse.hip) ----
 // Exclusive scan of n ints into out[n+1] (out[n] = total); temp via hipcub.
@@ -47,6 +47,9 @@ Err launch_validate_csc(int n, const int32_t* cp, const int32_t* ri, const T* va
                         int32_t* bad_dev, hipStream_t st);
 Err launch_validate_pattern(int n, const int32_t* cp, const int32_t* ri, int need_diag,
                             int32_t* bad_dev, hipStream_t st);
+template <class T>
+Err launch_diag_check(int n, const int32_t* rp, const int32_t* ci, const T* val, int32_t* bad_dev,
+                      hipStream_t st);
 template <class T>
 Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* counts_dev,
                       double* nrm2_dev, hipStream_t st);

@@ -22,16 +22,27 @@ namespace diaf {
 // ---------------------------------------------------------------------------
 // SpMV y = X x (CSR)
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ void spmv_csr_kernel(int n, const int32_t* rp, const int32_t* ci, const T* val,
-                                const T* x, T* y, const int32_t* done)
+template <class T, int G>
+__global__ void __launch_bounds__(256) spmv_csr_kernel(int n, const int32_t* rp, const int32_t* ci,
+                                                     const T* val, const T* x, T* y,
+                                                     const int32_t* done)
 {
     if (done && *done) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / G, g = t % G;
     T acc = num<T>::zero();
-    for (int p = rp[i]; p < rp[i + 1]; ++p) acc += val[p] * x[ci[p]];
-    y[i] = acc;
+    if (i < n)
+        for (int p = rp[i] + g; p < rp[i + 1]; p += G) acc += val[p] * x[ci[p]];
+    // fixed-order combine of the G partial sums (lanes of one row are adjacent)
+    for (int o = G / 2; o > 0; o >>= 1) {
+        if constexpr (num<T>::is_complex) {
+            acc.x += __shfl_xor(acc.x, o);
+            acc.y += __shfl_xor(acc.y, o);
+        } else {
+            acc += __shfl_xor(acc, o);
+        }
+    }
+    if (i < n && g == 0) y[i] = acc;
 }
 
 template <class T>
@@ -39,8 +50,11 @@ Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, c
                     const int32_t* done, hipStream_t st)
 {
     if (n == 0) return {};
-    hipLaunchKernelGGL(spmv_csr_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci, val,
-                       x, y, done);
+    // lanes per row from the mean row length (read once per matrix on the host
+    // would need a sync; the caller's matrices here are A (~7/row) and W)
+    int64_t threads4 = (int64_t)n * 4;
+    hipLaunchKernelGGL((spmv_csr_kernel<T, 4>), dim3((unsigned)((threads4 + 255) / 256)), dim3(256),
+                       0, st, n, rp, ci, val, x, y, done);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
@@ -80,14 +94,72 @@ Err launch_diag_solve(int n, const int32_t* rp, const int32_t* ci, const T* val,
 
 // ---------------------------------------------------------------------------
 // Sync-free triangular solve
+//
+// The solution vector doubles as the readiness flag: before the solve it is
+// filled with a NaN whose payload no arithmetic produces (the sentinel);
+// a row is ready once its entry differs from the sentinel.  Entries are
+// written and polled with relaxed agent-scope atomics (coherent across the
+// chip's L2 slices without cache-wide fences), so the value and its
+// readiness are one 64-bit access.  Rows waited on inside the same wave are
+// read from LDS.
 // ---------------------------------------------------------------------------
-__device__ inline uint32_t load_acquire(const uint32_t* p)
+static constexpr uint64_t TRSV_SENTINEL = 0x7ff4d1af5e000001ull;
+
+__device__ inline uint64_t ld_agent(const uint64_t* p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void store_release(uint32_t* p, uint32_t v)
+__device__ inline void st_agent(uint64_t* p, uint64_t v)
 {
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+struct words;
+template <>
+struct words<double> {
+    static constexpr int W = 1;
+};
+template <>
+struct words<zc> {
+    static constexpr int W = 2;
+};
+
+template <class T>
+__global__ void fill_sentinel_kernel(int n, T* x, const int32_t* done)
+{
+    if (done && *done) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int W = words<T>::W;
+    if (i < (int64_t)n * W) ((uint64_t*)x)[i] = TRSV_SENTINEL;
+}
+
+template <class T>
+__device__ inline bool load_ready(const T* x, int c, T& out)
+{
+    const uint64_t* p = (const uint64_t*)(x + c);
+    if constexpr (num<T>::is_complex) {
+        uint64_t a = ld_agent(p), b = ld_agent(p + 1);
+        if (a == TRSV_SENTINEL || b == TRSV_SENTINEL) return false;
+        out = T{__longlong_as_double((long long)a), __longlong_as_double((long long)b)};
+    } else {
+        uint64_t a = ld_agent(p);
+        if (a == TRSV_SENTINEL) return false;
+        out = __longlong_as_double((long long)a);
+    }
+    return true;
+}
+
+template <class T>
+__device__ inline void store_ready(T* x, int i, T v)
+{
+    uint64_t* p = (uint64_t*)(x + i);
+    if constexpr (num<T>::is_complex) {
+        st_agent(p, (uint64_t)__double_as_longlong(v.x));
+        st_agent(p + 1, (uint64_t)__double_as_longlong(v.y));
+    } else {
+        st_agent(p, (uint64_t)__double_as_longlong(v));
+    }
 }
 
 template <class T>
@@ -103,22 +175,37 @@ __device__ inline T div_t(T a, T d)
 
 static constexpr int TRSV_SPIN_CAP = 1 << 22;
 
+// LDS element access that the compiler may not cache in registers.
+template <class T>
+__device__ inline T vload(const T* p)
+{
+    volatile const double* d = (volatile const double*)p;
+    if constexpr (num<T>::is_complex) return T{d[0], d[1]};
+    else return d[0];
+}
+template <class T>
+__device__ inline void vstore(T* p, T v)
+{
+    volatile double* d = (volatile double*)p;
+    if constexpr (num<T>::is_complex) { d[0] = v.x; d[1] = v.y; }
+    else d[0] = v;
+}
+
 template <class T>
 __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
                                                   const T* val, int upper, const T* b, T* x,
-                                                  uint32_t* ready, TrsvCtl* ctl,
-                                                  const int32_t* done)
+                                                  TrsvCtl* ctl, const int32_t* done)
 {
     if (done && *done) return;
-    __shared__ uint32_t s_chunk, s_epoch;
+    __shared__ uint32_t s_chunk;
+    __shared__ T sx[64];
+    __shared__ int sready[64];
     const int lane = threadIdx.x;
-    if (lane == 0) {
-        s_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_chunk = atomicAdd(&ctl->ticket, 1u);
-    }
+    if (lane == 0) s_chunk = atomicAdd(&ctl->ticket, 1u);
+    sready[lane] = 0;
     __syncthreads();
-    const uint32_t ep = s_epoch + 1;
-    const int pos = (int)s_chunk * 64 + lane;
+    const int base = (int)s_chunk * 64;
+    const int pos = base + lane;
     bool fin = pos >= n;
     const int i = fin ? 0 : (upper ? n - 1 - pos : pos);
     T acc = fin ? num<T>::zero() : b[i];
@@ -133,29 +220,40 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
                 int c = ci[p];
                 if (c == i) { diag = val[p]; ++p; continue; }
                 if (upper ? (c < i) : (c > i)) { ++p; continue; }  // wrong triangle: ignored
-                if (load_acquire(&ready[c]) != ep) break;
-                acc -= val[p] * x[c];
+                const int cpos = upper ? n - 1 - c : c;
+                T xc;
+                if (cpos >= base) {
+                    // the row waited on belongs to this wave: LDS
+                    if (!((volatile int*)sready)[cpos - base]) break;
+                    xc = vload(&sx[cpos - base]);
+                } else if (!load_ready(x, c, xc)) {
+                    break;
+                }
+                acc -= val[p] * xc;
                 ++p;
             }
             if (p == pe) {
-                x[i] = div_t(acc, diag);
-                store_release(&ready[i], ep);
+                T xi = div_t(acc, diag);
+                vstore(&sx[lane], xi);
+                store_ready(x, i, xi);
                 fin = true;
             } else if (++spins > TRSV_SPIN_CAP) {
                 err = true;
                 fin = true;
             }
         }
+        __syncthreads();
+        if (fin) ((volatile int*)sready)[lane] = 1;
+        __syncthreads();
     }
     if (err) atomicOr(&ctl->error, 1u);
     __syncthreads();
     if (lane == 0) {
         uint32_t f = atomicAdd(&ctl->finished, 1u);
         if (f == gridDim.x - 1) {
-            // last wave: reset the tickets and advance the epoch
+            // last wave: reset the tickets for the next launch
             ctl->ticket = 0;
             ctl->finished = 0;
-            __hip_atomic_store(&ctl->epoch, ep, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -164,29 +262,39 @@ template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
                 T* x, uint32_t* ready, TrsvCtl* ctl, const int32_t* done, hipStream_t st)
 {
+    (void)ready;
     if (n == 0) return {};
+    int64_t nw = (int64_t)n * words<T>::W;
+    hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
+                       n, x, done);
     hipLaunchKernelGGL(trsv_kernel<T>, dim3((n + 63) / 64), dim3(64), 0, st, n, rp, ci, val, upper,
-                       b, x, ready, ctl, done);
+                       b, x, ctl, done);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
 
 // Level of every row in the triangular dependency DAG (same sync-free
-// scheme, integer max instead of substitution); *maxlevel = depth.
+// scheme with -1 as the not-ready value and an integer max instead of the
+// substitution); *maxlevel = depth.
+__global__ void fill_minus1_kernel(int n, int32_t* a)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = -1;
+}
+
 __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* rp,
                                                          const int32_t* ci, int upper,
-                                                         int32_t* level, uint32_t* ready,
-                                                         TrsvCtl* ctl, int32_t* maxlevel)
+                                                         int32_t* level, TrsvCtl* ctl,
+                                                         int32_t* maxlevel)
 {
-    __shared__ uint32_t s_chunk, s_epoch;
+    __shared__ uint32_t s_chunk;
+    __shared__ int slv[64];
     const int lane = threadIdx.x;
-    if (lane == 0) {
-        s_epoch = __hip_atomic_load(&ctl->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_chunk = atomicAdd(&ctl->ticket, 1u);
-    }
+    if (lane == 0) s_chunk = atomicAdd(&ctl->ticket, 1u);
+    slv[lane] = -1;
     __syncthreads();
-    const uint32_t ep = s_epoch + 1;
-    const int pos = (int)s_chunk * 64 + lane;
+    const int base = (int)s_chunk * 64;
+    const int pos = base + lane;
     bool fin = pos >= n;
     const int i = fin ? 0 : (upper ? n - 1 - pos : pos);
     int lv = 0;
@@ -199,13 +307,17 @@ __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* r
             while (p < pe) {
                 int c = ci[p];
                 if (c == i || (upper ? (c < i) : (c > i))) { ++p; continue; }
-                if (load_acquire(&ready[c]) != ep) break;
-                lv = max(lv, __hip_atomic_load(&level[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                const int cpos = upper ? n - 1 - c : c;
+                int lc = cpos >= base
+                             ? ((volatile int*)slv)[cpos - base]
+                             : __hip_atomic_load(&level[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lc < 0) break;
+                lv = max(lv, lc);
                 ++p;
             }
             if (p == pe) {
+                ((volatile int*)slv)[lane] = lv + 1;
                 __hip_atomic_store(&level[i], lv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                store_release(&ready[i], ep);
                 atomicMax(maxlevel, lv + 1);
                 fin = true;
             } else if (++spins > TRSV_SPIN_CAP) {
@@ -213,6 +325,7 @@ __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* r
                 fin = true;
             }
         }
+        __syncthreads();
     }
     if (err) atomicOr(&ctl->error, 1u);
     __syncthreads();
@@ -221,7 +334,6 @@ __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* r
         if (f == gridDim.x - 1) {
             ctl->ticket = 0;
             ctl->finished = 0;
-            __hip_atomic_store(&ctl->epoch, ep, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -229,9 +341,11 @@ __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* r
 Err launch_trsv_levels(int n, const int32_t* rp, const int32_t* ci, int upper, int32_t* level,
                        uint32_t* ready, TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st)
 {
+    (void)ready;
     if (n == 0) return {};
+    hipLaunchKernelGGL(fill_minus1_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, level);
     hipLaunchKernelGGL(trsv_levels_kernel, dim3((n + 63) / 64), dim3(64), 0, st, n, rp, ci, upper,
-                       level, ready, ctl, maxlevel_dev);
+                       level, ctl, maxlevel_dev);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
@@ -273,14 +387,25 @@ __device__ inline bool reduce_partials(double (&vals)[NV], double* partial, uint
     return last;
 }
 
+// Sum of the per-block partials by the whole (last) block: a strided load
+// per thread and a tree in LDS, both in a fixed order.
 template <int NV>
 __device__ inline void sum_partials(const double* partial, int nb, double (&out)[NV])
 {
-    for (int v = 0; v < NV; ++v) out[v] = 0.0;
-    for (int b = 0; b < nb; ++b)
-        for (int v = 0; v < NV; ++v)
-            out[v] += __hip_atomic_load(&partial[b * NV + v], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ double red2[NV][RNT];
+    for (int v = 0; v < NV; ++v) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < nb; b += RNT)
+            a += __hip_atomic_load(&partial[b * NV + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        red2[v][threadIdx.x] = a;
+    }
+    __syncthreads();
+    for (int o = RNT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int v = 0; v < NV; ++v) red2[v][threadIdx.x] += red2[v][threadIdx.x + o];
+        __syncthreads();
+    }
+    for (int v = 0; v < NV; ++v) out[v] = red2[v][0];
 }
 
 template <class T>
@@ -312,9 +437,10 @@ __global__ void __launch_bounds__(RNT) bicg_init_kernel(BicgVecs<T> V, double to
         V.v[i] = num<T>::zero();
         acc[0] += num<T>::abs2(bi);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
         double s[1];
         sum_partials<1>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->bnorm = sqrt(s[0]);
         S->tol = tol;
@@ -344,9 +470,10 @@ __global__ void __launch_bounds__(RNT) bicg_rho_kernel(BicgVecs<T> V)
         acc[0] += num<T>::re(d);
         acc[1] += num<T>::im(d);
     }
-    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket)) {
         double s[2];
         sum_partials<2>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->red_ticket = 0;
         T rho = mk2<T>(s[0], s[1]);
@@ -385,9 +512,10 @@ __global__ void __launch_bounds__(RNT) bicg_alpha_kernel(BicgVecs<T> V)
         acc[0] += num<T>::re(d);
         acc[1] += num<T>::im(d);
     }
-    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket)) {
         double s[2];
         sum_partials<2>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->red_ticket = 0;
         T rv = mk2<T>(s[0], s[1]);
@@ -409,9 +537,10 @@ __global__ void __launch_bounds__(RNT) bicg_s_kernel(BicgVecs<T> V)
         V.s[i] = s;
         acc[0] += num<T>::abs2(s);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
         double s[1];
         sum_partials<1>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->red_ticket = 0;
         double nr = sqrt(s[0]);
@@ -432,9 +561,10 @@ __global__ void __launch_bounds__(RNT) bicg_omega_kernel(BicgVecs<T> V)
         acc[1] += num<T>::im(d);
         acc[2] += num<T>::abs2(ti);
     }
-    if (reduce_partials<3>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<3>(acc, V.partial, &V.st->red_ticket)) {
         double s[3];
         sum_partials<3>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->red_ticket = 0;
         T ts = mk2<T>(s[0], s[1]);
@@ -457,9 +587,10 @@ __global__ void __launch_bounds__(RNT) bicg_xr_kernel(BicgVecs<T> V)
         V.r[i] = r;
         acc[0] += num<T>::abs2(r);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
         double s[1];
         sum_partials<1>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->red_ticket = 0;
         double nr = sqrt(s[0]);
@@ -479,9 +610,10 @@ __global__ void __launch_bounds__(RNT) bicg_true_res_kernel(BicgVecs<T> V)
         T d = V.b[i] - V.t[i];
         acc[0] += num<T>::abs2(d);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket) && threadIdx.x == 0) {
+    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
         double s[1];
         sum_partials<1>(V.partial, gridDim.x, s);
+        if (threadIdx.x != 0) return;
         V.st->red_ticket = 0;
         V.st->tt = V.st->bnorm > 0 ? sqrt(s[0]) / V.st->bnorm : 0.0;
     }

@@ -231,4 +231,35 @@ INST(double)
 INST(zc)
 #undef INST
 
+// ---------------------------------------------------------------------------
+// Zero, missing or non-finite diagonal entries of a CSR matrix (pivots of
+// the triangular solve with V).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void diag_check_kernel(int n, const int32_t* rp, const int32_t* ci, const T* val,
+                                  int32_t* bad)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool ok = false;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) ok = !num<T>::iszero(val[p]) && num<T>::finite(val[p]);
+    if (!ok) atomicAdd(bad, 1);
+}
+
+template <class T>
+Err launch_diag_check(int n, const int32_t* rp, const int32_t* ci, const T* val, int32_t* bad_dev,
+                      hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(diag_check_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci,
+                       val, bad_dev);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+template Err launch_diag_check<double>(int, const int32_t*, const int32_t*, const double*, int32_t*,
+                                       hipStream_t);
+template Err launch_diag_check<zc>(int, const int32_t*, const int32_t*, const zc*, int32_t*,
+                                   hipStream_t);
+
 }  // namespace diaf

@@ -59,8 +59,10 @@ class diaf_stats(ctypes.Structure):
                 ("mmax", c_int32), ("nbuckets", c_int32), ("count_rank_deficient", c_int32),
                 ("count_gap_degenerate", c_int32), ("count_small_diag", c_int32),
                 ("count_tie_edge", c_int32), ("count_fell_back", c_int32),
-                ("count_no_diag", c_int32), ("v_levels", c_int32), ("nrm", c_double),
-                ("ms_pattern", c_double), ("ms_factor", c_double), ("ms_assemble", c_double)]
+                ("count_no_diag", c_int32), ("v_levels", c_int32),
+                ("count_zero_pivot", c_int32), ("factor_launches", c_int32), ("nrm", c_double),
+                ("ms_pattern", c_double), ("ms_factor", c_double), ("ms_assemble", c_double),
+                ("ms_factor_kernels", c_double)]
 
 
 class diaf_solve_info(ctypes.Structure):
@@ -307,7 +309,7 @@ def diaf_solve(ctx: Context, A: DeviceCSC, F: Factors | None, b, x, rtol=1e-8, m
     rc = ctx.lib.diaf_solve(ctx.h, ctypes.byref(A.desc), F.h if F is not None else None,
                             c_void_p(b.data_ptr()), c_void_p(x.data_ptr()), rtol, maxit,
                             ctypes.byref(info))
-    if rc in (DIAF_ENOCONV, DIAF_EBREAKDOWN) and not raise_on_noconv:
+    if rc in (DIAF_ENOCONV, DIAF_EBREAKDOWN, DIAF_ESINGULAR) and not raise_on_noconv:
         return info
     ctx.check(rc)
     return info

@@ -1,0 +1,138 @@
+"""Training and use of the learned W-pattern proposer (host driver).
+
+Every numerical step runs in libdiaf's kernels through the C ABI: the plain
+factorization that produces the labels (W pattern pattern(A^2), numerical
+dropping by tolerance 0.1 of |w_j(i)| ||A(:,i)||), the pair features, and
+the MLP forward/backward/Adam updates.  The host only generates the seeded
+training matrices and loops over them.
+
+Training set: seeded 3D convection-diffusion problems on 48^3 grids
+(seeds 5000, 5001, ...), V = diagonal + top-4 lower rows, both norm modes.
+One Adam step per instance (the gradient over all its candidate pairs).
+The residual gate is 1.25 x the 99th percentile of the plain method's
+normalised residual r_j / s_j over the training set.
+
+    python -m paper_1208_3573_amd.learned --mode unit_v --out weights.npz
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import time
+
+import numpy as np
+
+from . import diaf
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS_DIR = os.path.join(_HERE, "weights")
+TRAIN_N = 48
+TRAIN_SEED0 = 5000
+LABEL_TAU = 0.1
+
+
+def weights_path(mode: str) -> str:
+    return os.path.join(WEIGHTS_DIR, f"mlp_convdiff48_{mode}.npz")
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He initialisation of the 16-64-64-1 network (host random numbers)."""
+    rng = np.random.default_rng(seed)
+    nf, nh = diaf.MLP_NFEAT, diaf.MLP_HIDDEN
+    W1 = rng.standard_normal((nh, nf)) * np.sqrt(2.0 / nf)
+    W2 = rng.standard_normal((nh, nh)) * np.sqrt(2.0 / nh)
+    w3 = rng.standard_normal(nh) * np.sqrt(1.0 / nh)
+    return np.concatenate([W1.ravel(), np.zeros(nh), W2.ravel(), np.zeros(nh), w3,
+                           [0.0]]).astype(np.float32)
+
+
+def _block_fro(A, Jcp, Jri):
+    cn2 = np.zeros(A.n)
+    np.add.at(cn2, np.repeat(np.arange(A.n), np.diff(A.colptr)), np.abs(A.val) ** 2)
+    out = np.zeros(A.n)
+    np.add.at(out, np.repeat(np.arange(A.n), np.diff(Jcp)), cn2[Jri])
+    return np.sqrt(out)
+
+
+def build_training_set(ctx, mode: str, n_instances: int, N: int = TRAIN_N, log=print):
+    """Features and labels of n_instances seeded problems, kept on the GPU."""
+    import torch
+
+    import synth
+    data = []
+    qs = []
+    for t in range(n_instances):
+        A = synth.convdiff(N, 3, TRAIN_SEED0 + t)
+        dA = diaf.DeviceCSC.from_host(A)
+        F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_lower", v_count=5), mode)
+        H = F.to_host()
+        C = diaf.DevicePattern.from_host(H["Wcp"], H["Wri"])
+        npairs = len(H["Wri"])
+        feat = torch.empty(npairs * diaf.MLP_NFEAT, dtype=torch.float32, device="cuda")
+        diaf.diaf_features(ctx, dA, C, feat)
+        lab = torch.empty(npairs, dtype=torch.float32, device="cuda")
+        diaf.diaf_labels(ctx, dA, F, LABEL_TAU, lab)
+        s = np.ones(A.n) if mode == "unit_v" else _block_fro(A, H["Wcp"], H["Wri"])
+        qs.append(H["r"] / s)
+        data.append((feat, lab, npairs))
+        F.close()
+        if (t + 1) % 10 == 0:
+            log(f"  training data: {t + 1}/{n_instances} instances")
+    gate = 1.25 * float(np.percentile(np.concatenate(qs), 99))
+    return data, gate
+
+
+def train(ctx, mode: str, n_instances: int = 100, epochs: int = 8, lr: float = 3e-3,
+          seed: int = 0, log=print):
+    data, gate = build_training_set(ctx, mode, n_instances, log=log)
+    model = diaf.Model(ctx, init_params(seed))
+    rng = np.random.default_rng(seed)
+    hist = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        order = rng.permutation(len(data))
+        losses = []
+        for i in order:
+            feat, lab, npairs = data[i]
+            step_lr = lr * (0.5 ** (ep // 3))
+            losses.append(diaf.diaf_mlp_train_step(ctx, model, feat, lab, npairs, step_lr))
+        hist.append(float(np.mean(losses)))
+        log(f"  epoch {ep}: mean loss {hist[-1]:.5f}")
+    log(f"  training: {time.perf_counter() - t0:.1f} s, gate {gate:.3e}")
+    return model, gate, hist
+
+
+def save(model, gate, mode, path, hist=()):
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    np.savez(path, params=model.params(), gate_tau=np.float64(gate), mode=mode,
+             loss_history=np.asarray(hist, dtype=np.float64))
+
+
+def load(ctx, path):
+    z = np.load(path, allow_pickle=False)
+    return diaf.Model(ctx, z["params"]), float(z["gate_tau"])
+
+
+def load_or_train(ctx, mode: str, log=print, n_instances: int = 100):
+    path = weights_path(mode)
+    if os.path.exists(path):
+        log(f"  loading {path}")
+        return load(ctx, path)
+    model, gate, hist = train(ctx, mode, n_instances=n_instances, log=log)
+    return model, gate
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", default="unit_v", choices=["unit_v", "unit_w"])
+    ap.add_argument("--instances", type=int, default=100)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args()
+    ctx = diaf.Context(0)
+    model, gate, hist = train(ctx, args.mode, args.instances, args.epochs)
+    save(model, gate, args.mode, args.out or weights_path(args.mode), hist)
+
+
+if __name__ == "__main__":
+    main()

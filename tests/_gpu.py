@@ -10,11 +10,15 @@ import oracle
 
 EPS = np.finfo(np.float64).eps
 
-# Residual bar: |r_gpu - r_oracle| <= 1e-10 r_oracle + 64 eps s_j, where the
-# second term is the rounding level of evaluating ||B_j w_j - v_j|| in FP64
-# (s_j = 1 + ||B_j||_F ||w_j|| for unit-norm v, ||B_j||_F for unit-norm w).
+# Residual bar: |r_gpu - r_oracle| <= 1e-10 r_oracle + 1e-12 s_j with the
+# column scale s_j = 1 + ||B_j||_F ||w_j|| (unit-norm v) or ||B_j||_F
+# (unit-norm w).  The relative term binds wherever the residual is resolved;
+# the floor covers numerically exact columns (r ~ 1e-13 s_j), where the
+# residual is first order in the rounding of the singular vector and the
+# QR route and the Gram route land on different rounding-level values.  The
+# number of columns that pass only through the floor is reported.
 RES_REL = 1e-10
-RES_FLOOR_EPS = 64.0
+RES_FLOOR = 1e-12
 ANGLE_TOL = 1e-8
 EXCLUDE = oracle.RANK_DEFICIENT | oracle.GAP_DEGENERATE
 
@@ -75,6 +79,7 @@ def compare(H, J, O, A, mode, cols=None, check_pattern=True):
     worst_res = 0.0
     worst_ang = 0.0
     excluded = 0
+    floor_only = 0
     vpat_bad = []
     res_bad = []
     ang_bad = []
@@ -91,9 +96,11 @@ def compare(H, J, O, A, mode, cols=None, check_pattern=True):
         g_w = H["Wval"][wsl]
         o_w = O.Wval[wsl]
         s = bn[j] if mode == "unit_w" else 1.0 + bn[j] * np.linalg.norm(o_w)
-        tol = RES_REL * O.r[j] + RES_FLOOR_EPS * EPS * s
+        tol = RES_REL * O.r[j] + RES_FLOOR * s
         d = abs(H["r"][j] - O.r[j])
         worst_res = max(worst_res, d / max(tol, 1e-300))
+        if d > RES_REL * O.r[j]:
+            floor_only += 1
         if not d <= tol:
             res_bad.append((int(j), float(H["r"][j]), float(O.r[j]), float(tol)))
         if (int(H["flags"][j]) | int(O.flags[j])) & EXCLUDE:
@@ -103,7 +110,8 @@ def compare(H, J, O, A, mode, cols=None, check_pattern=True):
         worst_ang = max(worst_ang, a)
         if not a <= ANGLE_TOL:
             ang_bad.append((int(j), a))
-    summ = dict(cols=len(cols), excluded=excluded, worst_res_over_tol=worst_res,
+    summ = dict(cols=len(cols), excluded=excluded, floor_only=floor_only,
+                worst_res_over_tol=worst_res,
                 worst_angle=worst_ang, vpattern_mismatch=len(vpat_bad),
                 gpu_tie_edge=int(np.sum((H["flags"][cols] & oracle.TIE_EDGE) != 0)))
     say("parity:", summ)

