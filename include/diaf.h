@@ -151,6 +151,8 @@ typedef struct diaf_stats {
                                         (filled by the first apply or solve) */
     int32_t count_zero_pivot;        /* zero / non-finite diagonal entries of V (idem) */
     int32_t factor_launches;         /* factor kernel launches (one per size class) */
+    int32_t count_deferred;          /* columns the small-column kernel handed to the
+                                        generic one */
     double nrm;                      /* ||A W - V||_F = sqrt(sum r_j^2) */
     double ms_pattern, ms_factor, ms_assemble;  /* device time of the phases */
     double ms_factor_kernels;        /* device time of the factor kernels alone */

@@ -328,6 +328,50 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     std::vector<void*> to_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     int nb = 0;
+    // Unit-norm v with small columns: the one-wave kernel; columns it cannot
+    // hold (shadow above 64 rows) come back on a deferred list for the
+    // generic kernel.
+    if (mode == 0 && !ctx->opt_generic_only && F->lmax <= 8) {
+        std::vector<int32_t> small;
+        for (int c = 0; c < ncls; ++c) {
+            if (B[c].kcap > 32 || B[c].tcap > 256) continue;
+            small.insert(small.end(), B[c].cols.begin(), B[c].cols.end());
+            B[c].cols.clear();
+        }
+        if (!small.empty()) {
+            int32_t *cols = nullptr, *defl = nullptr, *ndef = nullptr;
+            DIAF_TRY(dmalloc(&cols, sizeof(int32_t) * small.size()));
+            DIAF_TRY(dmalloc(&defl, sizeof(int32_t) * small.size()));
+            DIAF_TRY(dmalloc(&ndef, sizeof(int32_t)));
+            to_free.push_back(cols);
+            to_free.push_back(defl);
+            to_free.push_back(ndef);
+            DIAF_HIP_TRY(hipMemcpyAsync(cols, small.data(), sizeof(int32_t) * small.size(),
+                                        hipMemcpyHostToDevice, st));
+            DIAF_HIP_TRY(hipMemsetAsync(ndef, 0, sizeof(int32_t), st));
+            fa.cols = cols;
+            fa.ncols = (int)small.size();
+            hipEvent_t e0, e1;
+            DIAF_HIP_TRY(hipEventCreate(&e0));
+            DIAF_HIP_TRY(hipEventCreate(&e1));
+            DIAF_HIP_TRY(hipEventRecord(e0, st));
+            DIAF_TRY(launch_factor_small<T>(fa, defl, ndef, st));
+            DIAF_HIP_TRY(hipEventRecord(e1, st));
+            events.push_back({e0, e1});
+            ++nb;
+            int32_t nd = 0;
+            DIAF_TRY(read1(ndef, &nd, st));
+            if (nd > 0) {
+                std::vector<int32_t> dl(nd);
+                DIAF_HIP_TRY(hipMemcpyAsync(dl.data(), defl, sizeof(int32_t) * nd,
+                                            hipMemcpyDeviceToHost, st));
+                DIAF_TRY(sync(st));
+                std::sort(dl.begin(), dl.end());
+                for (int32_t j : dl) DIAF_TRY(place(j));
+            }
+            F->stats.count_deferred += nd;
+        }
+    }
     for (auto& b : B) {
         if (b.cols.empty()) continue;
         ++nb;

@@ -29,6 +29,10 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
                           int nslots, hipStream_t st);
 template <class T>
 size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots);
+// One-wave kernel for unit-norm v and |J_j| <= 32, shadow <= 64, gathered
+// entries <= 256, |L_j| <= 8; other columns are appended to deferred.
+template <class T>
+Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, hipStream_t st);
 
 // ---- assembly and sparse utilities (sparse.hip) ----
 // Exclusive scan of n ints into out[n+1] (out[n] = total); temp via hipcub.

@@ -1,0 +1,578 @@
+// Small-column kernel for the first basic algorithm (unit-norm columns of
+// V, paper Section 2.1): one wave per column, |J_j| <= 32, shadow |R_j| <= 64,
+// at most 256 gathered entries and |L_j| <= 8.  Columns outside these limits
+// are appended to a deferred list for the generic kernel.
+//
+// Per column, with B = A(R_j, J_j) and G = B^* B:
+//   * shadow R_j: the gathered row indices are deduplicated in an LDS hash
+//     table and the <= 64 distinct rows sorted across the wave with a
+//     register bitonic network; row-ordered access (CSR) is built with
+//     per-row counts, a wave scan and a per-row sort;
+//   * G by sparse merges of the gathered columns;
+//   * G^{-1} by the symmetric sweep (Gauss-Jordan) operator held in
+//     registers, lane c owning column c, one LDS broadcast of the pivot row
+//     per step; all later solves are matrix-vector products:
+//   * seed w0 = G^{-1} b_j^* (V_0 = diagonals, Example 2.1), scores
+//     |(B w0)_i| on the admissible rows and the top-(l-1) selection with the
+//     1e-10 tie band (Section 3.1);
+//   * Y = G^{-1} B_L^*, H = B_L Y (l x l) = M^* M for the paper's M_j
+//     (eq. 2.3); v = top eigenvector of H by a parallel cyclic Jacobi with
+//     one lane per entry of the padded 8 x 8 matrix; w = Y v (eq. 2.4);
+//   * phase (diagonal of V real positive), residual ||B w - v|| in FP64.
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+namespace diaf {
+
+static constexpr int SKM = 32;   // max |J_j|
+static constexpr int SMM = 64;   // max shadow size
+static constexpr int STM = 256;  // max gathered entries
+static constexpr int SLM = 8;    // max |L_j|
+static constexpr int SHS = 256;  // hash slots
+
+template <class T>
+struct SmallLds {
+    T eval[STM];
+    T G[SKM * SKM];
+    T bc[2][SKM];
+    T w[SKM];
+    T Y[SKM * SLM];
+    T y[SMM];
+    T v[SLM];
+    double score[SMM];
+    int J[SKM];
+    int off[SKM + 1];
+    int erow[STM];
+    int hkey[SHS];
+    int R[SMM];
+    int tmp[SMM];
+    int rcnt[SMM];
+    int rptr[SMM + 1];
+    int L[SLM];
+    int misc[8];
+    uint8_t eloc[STM];
+    uint8_t ecol[STM];
+    uint8_t eslot[STM];
+    uint8_t hval[SHS];
+    uint8_t csr[STM];
+};
+
+template <class T>
+__device__ inline T shfl(T v, int src)
+{
+    if constexpr (num<T>::is_complex) return T{__shfl(v.x, src), __shfl(v.y, src)};
+    else return __shfl(v, src);
+}
+
+__device__ inline int wave_incl_scan(int x, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ inline double wave_sum(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ inline double wave_max(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Partner of player x in round r of the round-robin pairing of np players.
+__device__ inline int rr_partner(int x, int r, int np)
+{
+    if (x >= np) return -1;
+    if (x == np - 1) return r;
+    if (x == r) return np - 1;
+    int p = (2 * r - x) % (np - 1);
+    if (p < 0) p += np - 1;
+    return p;
+}
+
+template <class T>
+__device__ inline void rot_params(double al, double be, T g, double scale, double& cs, double& sn,
+                                  T& ec, bool& rot)
+{
+    double ag = num<T>::abs(g);
+    rot = ag > 1e-15 * sqrt(fabs(al)) * sqrt(fabs(be)) && ag > 1e-300 + 1e-30 * scale;
+    cs = 1.0;
+    sn = 0.0;
+    ec = num<T>::one();
+    if (rot) {
+        double zeta = (be - al) / (2.0 * ag);
+        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        cs = 1.0 / sqrt(1.0 + t * t);
+        sn = cs * t;
+        ec = num<T>::div(num<T>::conj(g), ag);
+    }
+}
+
+template <class T>
+__device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int* deferred,
+                             int* ndeferred)
+{
+    const int lane = threadIdx.x;
+    const int jb = A.Jcp[j];
+    const int k = A.Jcp[j + 1] - jb;
+    const int lmax = A.lmax;
+    // ---- 1. J_j and gather offsets ----
+    int len = 0;
+    if (lane < k && k <= SKM) {
+        int c = A.Jri[jb + lane];
+        S.J[lane] = c;
+        len = A.Acp[c + 1] - A.Acp[c];
+    }
+    int inc = wave_incl_scan(len, lane);
+    if (lane < k && k <= SKM) S.off[lane + 1] = inc;
+    if (lane == 0) S.off[0] = 0;
+    const int Tn = __shfl(inc, 63);
+    for (int s = lane; s < SHS; s += 64) S.hkey[s] = -1;
+    __syncthreads();
+    if (k > SKM || Tn > STM) {
+        if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+        return;
+    }
+    // ---- 2. gather ----
+    for (int t = lane; t < Tn; t += 64) {
+        int lo = 0, hi = k - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        int p = A.Acp[S.J[lo]] + (t - S.off[lo]);
+        S.erow[t] = A.Ari[p];
+        S.eval[t] = A.Aval[p];
+        S.ecol[t] = (uint8_t)lo;
+    }
+    __syncthreads();
+    // ---- 3. shadow: hash dedup, sort, local row ids ----
+    for (int t = lane; t < Tn; t += 64) {
+        int row = S.erow[t];
+        unsigned h = ((unsigned)row * 2654435761u) >> 24;
+        for (;;) {
+            int prev = atomicCAS(&S.hkey[h], -1, row);
+            if (prev == -1 || prev == row) break;
+            h = (h + 1) & (SHS - 1);
+        }
+        S.eslot[t] = (uint8_t)h;
+    }
+    __syncthreads();
+    int m = 0;
+    for (int q = 0; q < SHS / 64; ++q) {
+        int s = q * 64 + lane;
+        int key = S.hkey[s];
+        bool occ = key != -1;
+        uint64_t mask = __ballot(occ);
+        int pos = m + __popcll(mask & ((1ull << lane) - 1ull));
+        if (occ && pos < SMM) { S.R[pos] = key; S.tmp[pos] = s; }
+        m += __popcll(mask);
+    }
+    __syncthreads();
+    if (m > SMM) {
+        if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+        return;
+    }
+    int myrow = lane < m ? S.R[lane] : 0x7fffffff;
+    int myslot = lane < m ? S.tmp[lane] : 0;
+    for (int kk = 2; kk <= 64; kk <<= 1) {
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            int orow = __shfl_xor(myrow, jj);
+            int oslot = __shfl_xor(myslot, jj);
+            bool up = (lane & kk) == 0;
+            bool lower = (lane & jj) == 0;
+            bool take = (lower == up) ? (orow < myrow) : (orow > myrow);
+            if (take) { myrow = orow; myslot = oslot; }
+        }
+    }
+    __syncthreads();
+    if (lane < m) {
+        S.R[lane] = myrow;
+        S.hval[myslot] = (uint8_t)lane;
+    }
+    if (lane < SMM) S.rcnt[lane] = 0;
+    const uint64_t dmask = __ballot(lane < m && myrow == j);
+    const int dj = dmask ? __ffsll((unsigned long long)dmask) - 1 : -1;
+    __syncthreads();
+    double bn2 = 0.0;
+    for (int t = lane; t < Tn; t += 64) {
+        int lr = S.hval[S.eslot[t]];
+        S.eloc[t] = (uint8_t)lr;
+        atomicAdd(&S.rcnt[lr], 1);
+        bn2 += num<T>::abs2(S.eval[t]);
+    }
+    bn2 = wave_sum(bn2);
+    __syncthreads();
+    {
+        int rc = lane < m ? S.rcnt[lane] : 0;
+        int ri = wave_incl_scan(rc, lane);
+        S.rptr[lane + 1] = ri;
+        if (lane == 0) S.rptr[0] = 0;
+        S.rcnt[lane] = 0;
+    }
+    __syncthreads();
+    for (int t = lane; t < Tn; t += 64) {
+        int lr = S.eloc[t];
+        int pos = S.rptr[lr] + atomicAdd(&S.rcnt[lr], 1);
+        S.csr[pos] = (uint8_t)t;
+    }
+    __syncthreads();
+    if (lane < m) {  // ascending entry index = ascending column within each row
+        int b = S.rptr[lane], e = S.rptr[lane + 1];
+        for (int p = b + 1; p < e; ++p) {
+            uint8_t key = S.csr[p];
+            int q = p - 1;
+            while (q >= b && S.csr[q] > key) { S.csr[q + 1] = S.csr[q]; --q; }
+            S.csr[q + 1] = key;
+        }
+    }
+    __syncthreads();
+    if (dj < 0) {
+        for (int a = lane; a < k; a += 64) A.Wval[jb + a] = num<T>::zero();
+        for (int t = lane; t < lmax; t += 64) {
+            A.Vrows[(size_t)j * lmax + t] = -1;
+            A.Vvals[(size_t)j * lmax + t] = num<T>::zero();
+        }
+        if (lane == 0) {
+            A.rcol[j] = 0.0;
+            A.bnorm[j] = sqrt(bn2);
+            A.flags[j] = DIAF_FLAG_NO_DIAG_ROW;
+            A.lcount[j] = 0;
+        }
+        return;
+    }
+    uint32_t flags = 0;
+    // ---- 4. Gram matrix (identity padding beyond k) ----
+    const int npair = k * (k + 1) / 2;
+    for (int q = lane; q < npair; q += 64) {
+        int a = 0, rem = q;
+        while (rem >= k - a) { rem -= k - a; ++a; }
+        int b = a + rem;
+        int pa = S.off[a], ea = S.off[a + 1], pb = S.off[b], eb = S.off[b + 1];
+        T acc = num<T>::zero();
+        while (pa < ea && pb < eb) {
+            int ra = S.eloc[pa], rb = S.eloc[pb];
+            if (ra == rb) { acc += num<T>::cmul(S.eval[pa], S.eval[pb]); ++pa; ++pb; }
+            else if (ra < rb) ++pa;
+            else ++pb;
+        }
+        S.G[a * SKM + b] = acc;
+        S.G[b * SKM + a] = num<T>::conj(acc);
+    }
+    for (int q = lane; q < SKM * SKM; q += 64) {
+        int a = q / SKM, b = q % SKM;
+        if (a >= k || b >= k) S.G[q] = (a == b) ? num<T>::one() : num<T>::zero();
+    }
+    __syncthreads();
+    // ---- 5. G^{-1} by the symmetric sweep, lane c holds column c ----
+    // g[q] holds entry (q + p) mod 32 of the column at step p, so the pivot
+    // entry is always g[0] and every register index is static; the array
+    // rotates by one per step and is back in place after 32 steps.
+    const int c = lane & (SKM - 1);
+    T g[SKM];
+#pragma unroll
+    for (int i = 0; i < SKM; ++i) g[i] = S.G[i * SKM + c];
+    double maxd = lane < k ? num<T>::re(S.G[c * SKM + c]) : 0.0;
+    maxd = wave_max(maxd);
+    for (int p = 0; p < SKM; ++p) {
+        T* bc = S.bc[p & 1];
+        if (lane < SKM) bc[lane] = g[0];  // pivot row p (a_pc for column c)
+        __syncthreads();
+        const double d = num<T>::re(bc[p]);
+        const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
+        if (p < k && !(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
+        const double inv = zero ? 0.0 : 1.0 / d;
+        // sweep on column c: a_ic -= a_ip a_pc / d (c != p), a_ip / d for the
+        // pivot column, a_pc / d and -1/d on the pivot row; one update with a
+        // per-lane coefficient (a_ip = conj(a_pi) keeps G Hermitian)
+        const bool piv = (c == p);
+        const T coef = piv ? num<T>::mk(1.0 - inv) : g[0] * inv;
+        const T gp = piv ? num<T>::mk(zero ? 0.0 : -inv) : g[0] * inv;
+#pragma unroll
+        for (int q = 1; q < SKM; ++q) g[q] -= num<T>::conj(bc[(q + p) & (SKM - 1)]) * coef;
+        // rotate: entry p goes to the back
+#pragma unroll
+        for (int q = 0; q < SKM - 1; ++q) g[q] = g[q + 1];
+        g[SKM - 1] = gp;
+    }
+    __syncthreads();
+    if (lane < SKM) {
+#pragma unroll
+        for (int i = 0; i < SKM; ++i) S.G[i * SKM + c] = -g[i];  // G^{-1}
+    }
+    __syncthreads();
+    // ---- 6. V pattern ----
+    const bool topk = A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER;
+    int l = 0;
+    if (topk) {
+        if (lane < k) {
+            T acc = num<T>::zero();
+            for (int pp = S.rptr[dj]; pp < S.rptr[dj + 1]; ++pp) {
+                int t = S.csr[pp];
+                acc += S.G[lane * SKM + S.ecol[t]] * num<T>::conj(S.eval[t]);
+            }
+            S.w[lane] = acc;
+        }
+        __syncthreads();
+        T yr = num<T>::zero();
+        if (lane < m)
+            for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {
+                int t = S.csr[pp];
+                yr += S.eval[t] * S.w[S.ecol[t]];
+            }
+        const bool adm = lane < m && (A.vrule == V_TOPK_LOWER ? myrow > j : myrow < j);
+        const double sc = adm ? num<T>::abs(yr) : -1.0;
+        S.score[lane] = sc;
+        const uint64_t amask = __ballot(adm);
+        const int nc = __popcll(amask);
+        int lj = A.vcount < 1 ? 1 : A.vcount;
+        if (lj > 1 + nc) lj = 1 + nc;
+        if (lj > lmax) lj = lmax;
+        const int q = lj - 1;
+        __syncthreads();
+        bool chosen = false;
+        if (q > 0 && nc <= q) {
+            chosen = adm;
+        } else if (q > 0) {
+            int rk = 0;
+            for (int u = 0; u < 64; ++u) {
+                double su = S.score[u];
+                rk += (su > sc) || (su == sc && u < lane);
+            }
+            const uint64_t smask = __ballot(adm && rk == q - 1);
+            const int slane = __ffsll((unsigned long long)smask) - 1;
+            const double ss = __shfl(sc, slane);
+            const double hi = ss * (1.0 + 1e-10), lo = ss * (1.0 - 1e-10);
+            const bool in = adm && sc > hi;
+            const bool tie = adm && sc >= lo && sc <= hi;
+            const uint64_t inmask = __ballot(in), tmask = __ballot(tie);
+            const int need = q - __popcll(inmask);
+            const int trank = __popcll(tmask & ((1ull << lane) - 1ull));
+            chosen = in || (tie && trank < need);
+            const bool edge = adm && ss > 0.0 &&
+                              (fabs(sc - hi) <= 1e-12 * ss || fabs(sc - lo) <= 1e-12 * ss);
+            if (__ballot(edge)) flags |= DIAF_FLAG_TIE_EDGE;
+        }
+        const uint64_t cmask = __ballot(chosen);
+        if (chosen) S.L[1 + __popcll(cmask & ((1ull << lane) - 1ull))] = lane;
+        if (lane == 0) S.L[0] = dj;
+        l = 1 + __popcll(cmask);
+    } else {
+        int b = 0, e = 0;
+        const int32_t* rows = nullptr;
+        if (A.vrule == V_DIAG) {
+            if (lane == 0) S.L[0] = dj;
+            l = 1;
+        } else {
+            if (A.vrule == V_EXPLICIT) { b = A.Vcp_in[j]; e = A.Vcp_in[j + 1]; rows = A.Vri_in; }
+            else { b = A.Acp[j]; e = A.Acp[j + 1]; rows = A.Ari; }
+            for (int p0 = b; p0 < e; p0 += 64) {
+                int lr = -1;
+                int p = p0 + lane;
+                if (p < e) {
+                    int gi = rows[p];
+                    bool keep = A.vrule == V_EXPLICIT || gi == j ||
+                                (A.vrule == V_GS_UPPER ? gi < j : gi > j);
+                    if (keep) {
+                        unsigned h = ((unsigned)gi * 2654435761u) >> 24;
+                        for (int probe = 0; probe < SHS; ++probe) {
+                            int key = S.hkey[h];
+                            if (key == gi) { lr = S.hval[h]; break; }
+                            if (key == -1) break;
+                            h = (h + 1) & (SHS - 1);
+                        }
+                    }
+                }
+                uint64_t km = __ballot(lr >= 0);
+                int pos = l + __popcll(km & ((1ull << lane) - 1ull));
+                if (lr >= 0 && pos < SLM) S.L[pos] = lr;
+                l += __popcll(km);
+            }
+            if (l > SLM || l > lmax) {
+                __syncthreads();
+                if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+                return;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- 7. Y = G^{-1} B_L^*, H = B_L Y ----
+    if (lane < k) {
+        for (int t = 0; t < l; ++t) {
+            T acc = num<T>::zero();
+            const int r = S.L[t];
+            for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                int e = S.csr[pp];
+                acc += S.G[lane * SKM + S.ecol[e]] * num<T>::conj(S.eval[e]);
+            }
+            S.Y[lane * SLM + t] = acc;
+        }
+    }
+    __syncthreads();
+    const int hs = lane >> 3, ht = lane & 7;
+    T h = num<T>::zero();
+    if (hs < l && ht < l) {
+        const int r = S.L[hs];
+        for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+            int e = S.csr[pp];
+            h += S.eval[e] * S.Y[S.ecol[e] * SLM + ht];
+        }
+    } else if (hs == ht) {
+        h = num<T>::mk(-1.0);  // padding below every eigenvalue of the PSD H
+    }
+    T z = (hs == ht) ? num<T>::one() : num<T>::zero();
+    // ---- 8. top eigenvector of H: parallel cyclic Jacobi, lane = (row, col) ----
+    {
+        const int np = (l + 1) & ~1;
+        double scale = (hs == ht && hs < l) ? fabs(num<T>::re(h)) : 0.0;
+        scale = wave_max(scale);
+        for (int sweep = 0; sweep < 40 && np >= 2; ++sweep) {
+            bool any = false;
+            for (int r = 0; r < np - 1; ++r) {
+                // row pair
+                const int pr = rr_partner(hs, r, np);
+                const int ar = pr < 0 ? hs : min(hs, pr), br = pr < 0 ? hs : max(hs, pr);
+                const double haa = num<T>::re(shfl(h, ar * 9)), hbb = num<T>::re(shfl(h, br * 9));
+                const T hab = shfl(h, ar * 8 + br);
+                double cs, sn;
+                T ec;
+                bool rot;
+                rot_params(haa, hbb, hab, scale, cs, sn, ec, rot);
+                if (pr < 0 || br >= l) rot = false;
+                // column pair (same pairing)
+                const int pc = rr_partner(ht, r, np);
+                const int ac = pc < 0 ? ht : min(ht, pc), bcl = pc < 0 ? ht : max(ht, pc);
+                const double caa = num<T>::re(shfl(h, ac * 9)), cbb = num<T>::re(shfl(h, bcl * 9));
+                const T cab = shfl(h, ac * 8 + bcl);
+                double cs2, sn2;
+                T ec2;
+                bool rot2;
+                rot_params(caa, cbb, cab, scale, cs2, sn2, ec2, rot2);
+                if (pc < 0 || bcl >= l) rot2 = false;
+                any |= rot;
+                // rows: [a; b] <- J^* [a; b]
+                const T hpart = shfl(h, (pr < 0 ? hs : pr) * 8 + ht);
+                if (rot) {
+                    const T ecc = num<T>::conj(ec);
+                    if (hs == ar) h = cs * h - sn * (ecc * hpart);
+                    else h = sn * hpart + cs * (ecc * h);
+                }
+                // columns: [a b] <- [a b] J, eigenvectors likewise
+                const T hq = shfl(h, hs * 8 + (pc < 0 ? ht : pc));
+                const T zq = shfl(z, hs * 8 + (pc < 0 ? ht : pc));
+                if (rot2) {
+                    if (ht == ac) {
+                        h = cs2 * h - sn2 * (ec2 * hq);
+                        z = cs2 * z - sn2 * (ec2 * zq);
+                    } else {
+                        h = sn2 * hq + cs2 * (ec2 * h);
+                        z = sn2 * zq + cs2 * (ec2 * z);
+                    }
+                }
+            }
+            if (!__ballot(any)) break;
+        }
+    }
+    // eigenvalues on the diagonal lanes; the largest (lowest index on ties)
+    const double lam = (hs == ht && hs < l) ? num<T>::re(h) : -INFINITY;
+    const double l1 = wave_max(lam);
+    const uint64_t bm = __ballot(hs == ht && hs < l && lam == l1);
+    const int best = (__ffsll((unsigned long long)bm) - 1) >> 3;
+    const uint64_t bm2 = __ballot(hs == ht && hs < l && hs != best);
+    double l2 = (hs == ht && hs < l && hs != best) ? lam : -INFINITY;
+    l2 = wave_max(l2);
+    if (bm2 && l1 > 0.0 && (l1 - l2) / l1 < 1e-6) flags |= DIAF_FLAG_GAP_DEGENERATE;
+    if (ht == best && hs < l) S.v[hs] = z;
+    __syncthreads();
+    // ---- 9. w = Y v ; phase ; residual ----
+    if (lane < k) {
+        T acc = num<T>::zero();
+        for (int t = 0; t < l; ++t) acc += S.Y[lane * SLM + t] * S.v[t];
+        S.w[lane] = acc;
+    }
+    __syncthreads();
+    T vt = lane < l ? S.v[lane] : num<T>::zero();
+    const double vn = sqrt(wave_sum(lane < l ? num<T>::abs2(vt) : 0.0));
+    const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
+    const int dpos = dposm ? __ffsll((unsigned long long)dposm) - 1 : -1;
+    int piv;
+    if (dpos >= 0 && num<T>::abs(shfl(vt, dpos)) >= 1e-8 * vn) {
+        piv = dpos;
+    } else {
+        const double av = lane < l ? num<T>::abs(vt) : -1.0;
+        const double mx = wave_max(av);
+        // lowest global row among the maxima = lowest local row
+        const int lr = lane < l ? S.L[lane] : 0x7fffffff;
+        int cand = (lane < l && av == mx) ? lr : 0x7fffffff;
+        for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
+        const uint64_t pm = __ballot(lane < l && av == mx && lr == cand);
+        piv = __ffsll((unsigned long long)pm) - 1;
+    }
+    const T pvv = shfl(vt, piv);
+    const T ph = num<T>::iszero(pvv) ? num<T>::one() : unit_conj_phase(pvv);
+    vt = ph * vt;
+    if (dpos < 0 || num<T>::abs(shfl(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
+        flags |= DIAF_FLAG_SMALL_DIAG;
+    if (lane < l) S.v[lane] = vt;
+    if (lane < k) S.w[lane] = ph * S.w[lane];
+    __syncthreads();
+    T res = num<T>::zero();
+    if (lane < m)
+        for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {
+            int e = S.csr[pp];
+            res += S.eval[e] * S.w[S.ecol[e]];
+        }
+    for (int t = 0; t < l; ++t)
+        if (S.L[t] == lane) res -= S.v[t];
+    const double r2 = wave_sum(lane < m ? num<T>::abs2(res) : 0.0);
+    // ---- 10. outputs (V sorted by row) ----
+    if (lane < k) A.Wval[jb + lane] = S.w[lane];
+    int myL = lane < l ? S.L[lane] : 0x7fffffff;
+    int rank = 0;
+    for (int t = 0; t < l; ++t) rank += S.L[t] < myL;
+    if (lane < l) {
+        A.Vrows[(size_t)j * lmax + rank] = S.R[myL];
+        A.Vvals[(size_t)j * lmax + rank] = S.v[lane];
+    } else if (lane < lmax) {
+        A.Vrows[(size_t)j * lmax + lane] = -1;
+        A.Vvals[(size_t)j * lmax + lane] = num<T>::zero();
+    }
+    if (lane == 0) {
+        A.rcol[j] = sqrt(r2);
+        A.bnorm[j] = sqrt(bn2);
+        A.flags[j] = flags;
+        A.lcount[j] = l;
+    }
+    __syncthreads();
+}
+
+template <class T>
+__global__ void __launch_bounds__(64) factor_small_kernel(FactorArgs<T> A, int* deferred,
+                                                          int* ndeferred)
+{
+    __shared__ SmallLds<T> S;
+    for (int q = blockIdx.x; q < A.ncols; q += gridDim.x) small_column(A, A.cols[q], S, deferred,
+                                                                        ndeferred);
+}
+
+template <class T>
+Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, hipStream_t st)
+{
+    if (A.ncols == 0) return {};
+    if (A.mode != 0) return {DIAF_EINVAL, "small factor kernel: unit-norm v only"};
+    int grid = A.ncols < 256 * 16 ? A.ncols : 256 * 16;
+    hipLaunchKernelGGL(factor_small_kernel<T>, dim3(grid), dim3(64), 0, st, A, deferred, ndeferred);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+template Err launch_factor_small<double>(const FactorArgs<double>&, int*, int*, hipStream_t);
+template Err launch_factor_small<zc>(const FactorArgs<zc>&, int*, int*, hipStream_t);
+
+}  // namespace diaf

@@ -60,7 +60,8 @@ class diaf_stats(ctypes.Structure):
                 ("count_gap_degenerate", c_int32), ("count_small_diag", c_int32),
                 ("count_tie_edge", c_int32), ("count_fell_back", c_int32),
                 ("count_no_diag", c_int32), ("v_levels", c_int32),
-                ("count_zero_pivot", c_int32), ("factor_launches", c_int32), ("nrm", c_double),
+                ("count_zero_pivot", c_int32), ("factor_launches", c_int32),
+                ("count_deferred", c_int32), ("nrm", c_double),
                 ("ms_pattern", c_double), ("ms_factor", c_double), ("ms_assemble", c_double),
                 ("ms_factor_kernels", c_double)]
 
