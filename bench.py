@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--mode", default="unit_v", choices=["unit_v", "unit_w"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
+                    help="library context option, e.g. trsv_rows_per_lane=2")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the "
@@ -87,6 +89,9 @@ def main():
     b = synth.rhs_ones(A)
     upper = cfg["v"].endswith("upper")
     ctx = diaf.Context(0)
+    for kv in args.opt:
+        k, v = kv.split("=", 1)
+        ctx.set_option(k, int(v))
     dA = diaf.DeviceCSC.from_host(A)
     db = torch.from_numpy(b).cuda()
     x = torch.zeros_like(db)

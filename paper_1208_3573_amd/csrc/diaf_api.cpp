@@ -21,6 +21,7 @@ struct diaf_ctx {
     std::string err;
     int64_t opt_generic_only = 0;
     int64_t opt_batch = 8;
+    diaf::TrsvTune trsv;
 };
 
 struct diaf_model {
@@ -529,7 +530,7 @@ Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_
         DIAF_TRY(launch_diag_solve<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, x, (T*)F->tmp, done, st));
     else
         DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, x, (T*)F->tmp,
-                                F->ready, F->ctl, done, st));
+                                F->ctl, done, ctx->trsv, st));
     return launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)F->tmp, y, done, st);
 }
 
@@ -569,6 +570,12 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     std::string k(key);
     if (k == "generic_only") ctx->opt_generic_only = value;
     else if (k == "solve_batch") ctx->opt_batch = value < 1 ? 1 : value;
+    else if (k == "trsv_backoff") ctx->trsv.backoff = value ? 1 : 0;
+    else if (k == "trsv_rows_per_lane") {
+        if (value != 1 && value != 2 && value != 4)
+            return fail(ctx, DIAF_EINVAL, "trsv_rows_per_lane must be 1, 2 or 4");
+        ctx->trsv.rows_per_lane = (int)value;
+    }
     else return fail(ctx, DIAF_EINVAL, "unknown option " + k);
     return DIAF_OK;
 }

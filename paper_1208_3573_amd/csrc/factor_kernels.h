@@ -59,6 +59,7 @@ Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* co
                       double* nrm2_dev, hipStream_t st);
 
 // ---- solve (solve.hip) ----
+
 struct TrsvCtl {
     uint32_t ticket;
     uint32_t finished;
@@ -78,9 +79,16 @@ struct BicgState {
 template <class T>
 Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
                     const int32_t* done, hipStream_t st);
+// Launch shape of the sync-free triangular solve: rows per lane (1, 2 or 4;
+// one wave owns 64 x rows_per_lane consecutive rows) and whether a wave that
+// found nothing ready sleeps briefly before polling again.
+struct TrsvTune {
+    int rows_per_lane = 1;
+    int backoff = 1;
+};
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
-                T* x, uint32_t* ready, TrsvCtl* ctl, const int32_t* done, hipStream_t st);
+                T* x, TrsvCtl* ctl, const int32_t* done, TrsvTune tune, hipStream_t st);
 template <class T>
 Err launch_diag_solve(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* b, T* x,
                       const int32_t* done, hipStream_t st);

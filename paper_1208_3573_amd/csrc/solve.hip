@@ -2,13 +2,15 @@
 // (Section 5).
 //
 // * SpMV: CSR, one thread per row.
-// * Triangular solve with V: sync-free, one wave per chunk of 64 rows.  A
+// * Triangular solve with V: sync-free, one wave per chunk of 256 rows.  A
 //   chunk is taken from an atomic ticket in dependency order (ascending
 //   rows for lower V, descending for upper V), so every row a wave waits on
-//   belongs to the same wave or to a wave that started earlier; waiting is
-//   a wave-uniform polling loop (no lane blocks inside it) with an
-//   iteration cap that raises an error flag, so every wave always exits.
-//   Readiness flags carry the launch's epoch, so they never need clearing.
+//   belongs to the same wave or to a wave that started earlier.  Values
+//   inside the chunk pass through LDS; values from earlier waves are read
+//   from x itself, which is filled with a signalling-NaN sentinel before the
+//   launch (a value is ready once it differs from the sentinel).  Waiting is
+//   a wave-uniform polling loop with an iteration cap that raises an error
+//   flag, so every wave always exits.
 // * BiCGSTAB runs on the device: each stage is a kernel that returns at
 //   once when the solve has finished, reductions are two-stage in a fixed
 //   order (the last block to finish sums the per-block partials and updates
@@ -175,76 +177,183 @@ __device__ inline T div_t(T a, T d)
 
 static constexpr int TRSV_SPIN_CAP = 1 << 22;
 
-// LDS element access that the compiler may not cache in registers.
-template <class T>
-__device__ inline T vload(const T* p)
+// Orders the LDS accesses of the lanes of one wave (LDS executes one wave's
+// instructions in order, so this only has to stop the compiler from moving
+// or caching accesses across it); unlike a workgroup barrier it does not
+// wait for outstanding global stores.  LDS is accessed with plain loads and
+// stores: a volatile access through a generic pointer becomes a flat access
+// that waits on all outstanding memory operations.
+__device__ inline void wave_sync()
 {
-    volatile const double* d = (volatile const double*)p;
-    if constexpr (num<T>::is_complex) return T{d[0], d[1]};
-    else return d[0];
-}
-template <class T>
-__device__ inline void vstore(T* p, T v)
-{
-    volatile double* d = (volatile double*)p;
-    if constexpr (num<T>::is_complex) { d[0] = v.x; d[1] = v.y; }
-    else d[0] = v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __asm__ __volatile__("" ::: "memory");
 }
 
+// One wave owns RPL x 64 consecutive rows (in dependency order), lane l
+// the rows l, l + 64, ... which it finishes one after the other.  At start
+// the wave copies the right-hand side, the diagonal and the first
+// trsv_dmax<T> off-diagonal entries of each of its rows into LDS (a longer
+// row reads the rest from global memory when it gets there).  It then
+// alternates (a) rounds that advance every row whose next dependency lies
+// in the wave, through LDS, until none advances, and (b) one polling round
+// on global memory for the rows blocked on another wave, so global latency
+// is paid per hop between waves rather than per dependency step.  Entries
+// are consumed in CSR order, so the result does not depend on timing.
 template <class T>
+struct trsv_dmax { static constexpr int v = num<T>::is_complex ? 6 : 8; };
+
+template <class T, int RPL>
 __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
                                                   const T* val, int upper, const T* b, T* x,
-                                                  TrsvCtl* ctl, const int32_t* done)
+                                                  TrsvCtl* ctl, const int32_t* done,
+                                                  int sleep_cycles)
 {
     if (done && *done) return;
+    constexpr int ROWS = 64 * RPL;
+    constexpr int DM = trsv_dmax<T>::v;
     __shared__ uint32_t s_chunk;
-    __shared__ T sx[64];
-    __shared__ int sready[64];
+    __shared__ T sx[ROWS];         // right-hand side, then the solution
+    __shared__ int sready[ROWS];
+    __shared__ T sdg[ROWS];        // diagonal entry of each row
+    __shared__ int snd[ROWS];      // off-diagonal entries held in LDS
+    __shared__ int sov[ROWS];      // first entry not held in LDS (= row end if none)
+    __shared__ int spe[ROWS];      // row end
+    __shared__ int sdc[RPL * DM * 64];
+    __shared__ T sdv[RPL * DM * 64];
     const int lane = threadIdx.x;
     if (lane == 0) s_chunk = atomicAdd(&ctl->ticket, 1u);
-    sready[lane] = 0;
+    for (int k = lane; k < ROWS; k += 64) sready[k] = 0;
     __syncthreads();
-    const int base = (int)s_chunk * 64;
-    const int pos = base + lane;
+    const int base = (int)s_chunk * ROWS;
+    const auto wrong_tri = [&](int c, int r) { return upper ? (c < r) : (c > r); };
+
+    for (int qq = 0; qq < RPL; ++qq) {
+        const int ps = base + qq * 64 + lane;
+        if (ps >= n) break;
+        const int ii = upper ? n - 1 - ps : ps;
+        const int pe = rp[ii + 1];
+        T dg = num<T>::one();
+        int nd = 0, ov = pe;
+        for (int pp = rp[ii]; pp < pe; ++pp) {
+            const int c = ci[pp];
+            if (c == ii) { dg = val[pp]; continue; }
+            if (wrong_tri(c, ii)) continue;  // entries outside the triangle are ignored
+            if (nd < DM) {
+                sdc[(qq * DM + nd) * 64 + lane] = c;
+                sdv[(qq * DM + nd) * 64 + lane] = val[pp];
+                ++nd;
+            } else if (ov == pe) {
+                ov = pp;
+            }
+        }
+        sx[qq * 64 + lane] = b[ii];
+        sdg[qq * 64 + lane] = dg;
+        snd[qq * 64 + lane] = nd;
+        sov[qq * 64 + lane] = ov;
+        spe[qq * 64 + lane] = pe;
+    }
+    __syncthreads();
+
+    int q = 0;
+    int pos = base + lane;
     bool fin = pos >= n;
-    const int i = fin ? 0 : (upper ? n - 1 - pos : pos);
-    T acc = fin ? num<T>::zero() : b[i];
-    T diag = num<T>::one();
-    int p = fin ? 0 : rp[i];
-    const int pe = fin ? 0 : rp[i + 1];
+    int i = 0, d = 0, nd = 0, ov = 0, pe = 0;
+    T acc = num<T>::zero();
+    const auto start_row = [&]() {
+        const int k = q * 64 + lane;
+        i = upper ? n - 1 - pos : pos;
+        acc = sx[k];
+        d = 0;
+        nd = snd[k];
+        ov = sov[k];
+        pe = spe[k];
+    };
+    // next unconsumed dependency of the current row; false once none is left.
+    // Consumption reads LDS only: when a long row has used up its LDS list,
+    // the next entries are first copied there from global memory (so no
+    // wait for global loads sits on the common path).
+    const auto next_dep = [&](int& c, T& v) -> bool {
+        if (d == nd) {
+            if (ov >= pe) return false;
+            int cnt = 0;
+            for (; ov < pe && cnt < DM; ++ov) {
+                const int cc = ci[ov];
+                if (cc == i || wrong_tri(cc, i)) continue;
+                sdc[(q * DM + cnt) * 64 + lane] = cc;
+                sdv[(q * DM + cnt) * 64 + lane] = val[ov];
+                ++cnt;
+            }
+            d = 0;
+            nd = cnt;
+            if (cnt == 0) return false;
+        }
+        c = sdc[(q * DM + d) * 64 + lane];
+        v = sdv[(q * DM + d) * 64 + lane];
+        return true;
+    };
+    const auto consume = [&]() { ++d; };
+    if (!fin) start_row();
+
     int spins = 0;
     bool err = false;
     while (!__all(fin)) {
-        if (!fin) {
-            while (p < pe) {
-                int c = ci[p];
-                if (c == i) { diag = val[p]; ++p; continue; }
-                if (upper ? (c < i) : (c > i)) { ++p; continue; }  // wrong triangle: ignored
-                const int cpos = upper ? n - 1 - c : c;
-                T xc;
-                if (cpos >= base) {
-                    // the row waited on belongs to this wave: LDS
-                    if (!((volatile int*)sready)[cpos - base]) break;
-                    xc = vload(&sx[cpos - base]);
-                } else if (!load_ready(x, c, xc)) {
-                    break;
+        // (a) LDS rounds
+        for (;;) {
+            bool prog = false;
+            int done_slot = -1;
+            if (!fin) {
+                int c;
+                T v;
+                bool more;
+                while ((more = next_dep(c, v))) {
+                    const int cpos = upper ? n - 1 - c : c;
+                    if (cpos < base) break;  // another wave: polled in (b)
+                    if (!sready[cpos - base]) break;
+                    acc -= v * sx[cpos - base];
+                    consume();
                 }
-                acc -= val[p] * xc;
-                ++p;
+                if (!more) {
+                    const int k = q * 64 + lane;
+                    const T xi = div_t(acc, sdg[k]);
+                    sx[k] = xi;
+                    store_ready(x, i, xi);
+                    done_slot = k;
+                    prog = true;
+                    spins = 0;
+                    ++q;
+                    pos += 64;
+                    if (q == RPL || pos >= n) fin = true;
+                    else start_row();
+                }
             }
-            if (p == pe) {
-                T xi = div_t(acc, diag);
-                vstore(&sx[lane], xi);
-                store_ready(x, i, xi);
-                fin = true;
-            } else if (++spins > TRSV_SPIN_CAP) {
+            wave_sync();
+            if (done_slot >= 0) sready[done_slot] = 1;
+            wave_sync();
+            if (!__any(prog)) break;
+        }
+        if (__all(fin)) break;
+        // (b) one polling round for rows waiting on another wave
+        bool polled = false;
+        if (!fin) {
+            int c;
+            T v;
+            while (next_dep(c, v)) {
+                const int cpos = upper ? n - 1 - c : c;
+                if (cpos >= base) break;  // inside the wave: back to (a)
+                T xc;
+                if (!load_ready(x, c, xc)) break;
+                acc -= v * xc;
+                consume();
+                polled = true;
+            }
+            if (!polled && ++spins > TRSV_SPIN_CAP) {
                 err = true;
                 fin = true;
             }
         }
-        __syncthreads();
-        if (fin) ((volatile int*)sready)[lane] = 1;
-        __syncthreads();
+        if (!__any(polled) && sleep_cycles) __builtin_amdgcn_s_sleep(1);
     }
     if (err) atomicOr(&ctl->error, 1u);
     __syncthreads();
@@ -260,15 +369,30 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
 
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
-                T* x, uint32_t* ready, TrsvCtl* ctl, const int32_t* done, hipStream_t st)
+                T* x, TrsvCtl* ctl, const int32_t* done, TrsvTune tune, hipStream_t st)
 {
-    (void)ready;
     if (n == 0) return {};
     int64_t nw = (int64_t)n * words<T>::W;
     hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
                        n, x, done);
-    hipLaunchKernelGGL(trsv_kernel<T>, dim3((n + 63) / 64), dim3(64), 0, st, n, rp, ci, val, upper,
-                       b, x, ctl, done);
+    const int rows = 64 * tune.rows_per_lane;
+    const dim3 grid((n + rows - 1) / rows);
+    switch (tune.rows_per_lane) {
+    case 1:
+        hipLaunchKernelGGL((trsv_kernel<T, 1>), grid, dim3(64), 0, st, n, rp, ci, val, upper, b, x,
+                           ctl, done, tune.backoff);
+        break;
+    case 2:
+        hipLaunchKernelGGL((trsv_kernel<T, 2>), grid, dim3(64), 0, st, n, rp, ci, val, upper, b, x,
+                           ctl, done, tune.backoff);
+        break;
+    case 4:
+        hipLaunchKernelGGL((trsv_kernel<T, 4>), grid, dim3(64), 0, st, n, rp, ci, val, upper, b, x,
+                           ctl, done, tune.backoff);
+        break;
+    default:
+        return {DIAF_EINVAL, "triangular solve: rows per lane must be 1, 2 or 4"};
+    }
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
@@ -309,14 +433,14 @@ __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* r
                 if (c == i || (upper ? (c < i) : (c > i))) { ++p; continue; }
                 const int cpos = upper ? n - 1 - c : c;
                 int lc = cpos >= base
-                             ? ((volatile int*)slv)[cpos - base]
+                             ? slv[cpos - base]
                              : __hip_atomic_load(&level[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (lc < 0) break;
                 lv = max(lv, lc);
                 ++p;
             }
             if (p == pe) {
-                ((volatile int*)slv)[lane] = lv + 1;
+                slv[lane] = lv + 1;
                 __hip_atomic_store(&level[i], lv + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 atomicMax(maxlevel, lv + 1);
                 fin = true;
@@ -654,7 +778,7 @@ Err bicg_half_fix(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_half
     template Err launch_spmv_csr<T>(int, const int32_t*, const int32_t*, const T*, const T*, T*,  \
                                     const int32_t*, hipStream_t);                                 \
     template Err launch_trsv<T>(int, const int32_t*, const int32_t*, const T*, int, const T*, T*, \
-                                uint32_t*, TrsvCtl*, const int32_t*, hipStream_t);                \
+                                TrsvCtl*, const int32_t*, TrsvTune, hipStream_t);                 \
     template Err launch_diag_solve<T>(int, const int32_t*, const int32_t*, const T*, const T*,    \
                                       T*, const int32_t*, hipStream_t);                           \
     template Err bicg_init<T>(const BicgVecs<T>&, double, int, hipStream_t);                      \
