@@ -8,16 +8,22 @@
 //     table and the <= 64 distinct rows sorted across the wave with a
 //     register bitonic network; row-ordered access (CSR) is built with
 //     per-row counts, a wave scan and a per-row sort;
-//   * G by sparse merges of the gathered columns;
-//   * G^{-1} by the symmetric sweep (Gauss-Jordan) operator held in
-//     registers, lane c owning column c, one LDS broadcast of the pivot row
-//     per step; all later solves are matrix-vector products:
+//   * G: the rows of every column of B form a 64-bit mask over the shadow, so
+//     each entry G(a, b) visits only the rows common to columns a and b (in
+//     ascending row order); the packed upper triangle goes to LDS;
+//   * G^{-1} by the symmetric sweep (Gauss-Jordan), lane c holding column c
+//     in registers and the pivot row broadcast through LDS; all later solves
+//     are products of G^{-1} with dense k-vectors:
 //   * seed w0 = G^{-1} b_j^* (V_0 = diagonals, Example 2.1), scores
 //     |(B w0)_i| on the admissible rows and the top-(l-1) selection with the
 //     1e-10 tie band (Section 3.1);
 //   * Y = G^{-1} B_L^*, H = B_L Y (l x l) = M^* M for the paper's M_j
-//     (eq. 2.3); v = top eigenvector of H by a parallel cyclic Jacobi with
-//     one lane per entry of the padded 8 x 8 matrix; w = Y v (eq. 2.4);
+//     (eq. 2.3).  H is positive semidefinite with eigenvalues in [0, 1], so
+//     its top eigenvector is the limit of the trace-normalised powers
+//     H^(2^s): repeated squaring, one lane per entry of the padded 8 x 8
+//     matrix, until the normalised power is rank one to 1e-12 (the angle
+//     error then falls below 1e-24 after one more squaring); w = Y v
+//     (eq. 2.4);
 //   * phase (diagonal of V real positive), residual ||B w - v|| in FP64.
 #include "dcommon.h"
 #include "factor_kernels.h"
@@ -30,23 +36,36 @@ static constexpr int STM = 256;  // max gathered entries
 static constexpr int SLM = 8;    // max |L_j|
 static constexpr int SHS = 256;  // hash slots
 
+static constexpr int STRI = SKM * (SKM + 1) / 2;  // packed upper triangle of G
+
+// Packed upper-triangle index of G(a, b), a <= b (column b holds rows 0..b).
+__device__ inline int tri(int a, int b) { return b * (b + 1) / 2 + a; }
+
 template <class T>
 struct SmallLds {
-    T eval[STM];
-    T G[SKM * SKM];
-    T bc[2][SKM];
-    T w[SKM];
-    T Y[SKM * SLM];
-    T y[SMM];
-    T v[SLM];
-    double score[SMM];
+    T eval[STM];  // gathered values, column by column in J order
+    union {
+        int erow[STM];  // gathered global rows (until the shadow is built)
+        T Gt[STRI];     // packed upper triangle of G (until the sweep)
+        T bc[2][SKM];   // pivot row of the sweep (double-buffered)
+        struct {
+            T U[SLM * SKM];   // U[t][i] = conj(B(L_t, i)), dense k-vectors
+            T Y[SKM * SLM];   // Y[i][t] = (G^{-1} U)(i, t)
+            T w[SKM];
+            T v[SLM];
+            T P[SLM * SLM];   // power of H being squared
+            double score[SMM];
+        } post;
+    };
+    uint64_t cmask[SKM];  // rows (local ids) of each column of B
     int J[SKM];
     int off[SKM + 1];
-    int erow[STM];
     int hkey[SHS];
     int R[SMM];
-    int tmp[SMM];
-    int rcnt[SMM];
+    union {
+        int tmp[SMM];
+        int rcnt[SMM];
+    };
     int rptr[SMM + 1];
     int L[SLM];
     int misc[8];
@@ -85,40 +104,14 @@ __device__ inline double wave_max(double x)
     return x;
 }
 
-// Partner of player x in round r of the round-robin pairing of np players.
-__device__ inline int rr_partner(int x, int r, int np)
-{
-    if (x >= np) return -1;
-    if (x == np - 1) return r;
-    if (x == r) return np - 1;
-    int p = (2 * r - x) % (np - 1);
-    if (p < 0) p += np - 1;
-    return p;
-}
-
-template <class T>
-__device__ inline void rot_params(double al, double be, T g, double scale, double& cs, double& sn,
-                                  T& ec, bool& rot)
-{
-    double ag = num<T>::abs(g);
-    rot = ag > 1e-15 * sqrt(fabs(al)) * sqrt(fabs(be)) && ag > 1e-300 + 1e-30 * scale;
-    cs = 1.0;
-    sn = 0.0;
-    ec = num<T>::one();
-    if (rot) {
-        double zeta = (be - al) / (2.0 * ag);
-        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        cs = 1.0 / sqrt(1.0 + t * t);
-        sn = cs * t;
-        ec = num<T>::div(num<T>::conj(g), ag);
-    }
-}
-
 template <class T>
 __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int* deferred,
                              int* ndeferred)
 {
-    const int lane = threadIdx.x;
+    // opaque per call: keeps lane-derived addresses from being hoisted out of
+    // the column loop (they would stay live in registers for the whole kernel)
+    int lane = threadIdx.x;
+    __asm__ volatile("" : "+v"(lane));
     const int jb = A.Jcp[j];
     const int k = A.Jcp[j + 1] - jb;
     const int lmax = A.lmax;
@@ -248,87 +241,100 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         return;
     }
     uint32_t flags = 0;
-    // ---- 4. Gram matrix (identity padding beyond k) ----
+    // ---- 4. Gram matrix: G(a, b) over the rows common to columns a and b ----
+    if (lane < k) {
+        uint64_t msk = 0;
+        for (int t = S.off[lane]; t < S.off[lane + 1]; ++t) msk |= 1ull << S.eloc[t];
+        S.cmask[lane] = msk;
+    }
+    __syncthreads();
     const int npair = k * (k + 1) / 2;
     for (int q = lane; q < npair; q += 64) {
-        int a = 0, rem = q;
-        while (rem >= k - a) { rem -= k - a; ++a; }
-        int b = a + rem;
-        int pa = S.off[a], ea = S.off[a + 1], pb = S.off[b], eb = S.off[b + 1];
+        int bb = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+        while (bb * (bb + 1) / 2 > q) --bb;
+        while ((bb + 1) * (bb + 2) / 2 <= q) ++bb;
+        const int aa = q - bb * (bb + 1) / 2;
+        const uint64_t ma = S.cmask[aa], mb = S.cmask[bb];
+        uint64_t common = ma & mb;
+        const int oa = S.off[aa], ob = S.off[bb];
         T acc = num<T>::zero();
-        while (pa < ea && pb < eb) {
-            int ra = S.eloc[pa], rb = S.eloc[pb];
-            if (ra == rb) { acc += num<T>::cmul(S.eval[pa], S.eval[pb]); ++pa; ++pb; }
-            else if (ra < rb) ++pa;
-            else ++pb;
+        while (common) {
+            const int r = __ffsll((unsigned long long)common) - 1;
+            const uint64_t below = (1ull << r) - 1ull;
+            acc += num<T>::cmul(S.eval[oa + __popcll(ma & below)], S.eval[ob + __popcll(mb & below)]);
+            common &= common - 1ull;
         }
-        S.G[a * SKM + b] = acc;
-        S.G[b * SKM + a] = num<T>::conj(acc);
-    }
-    for (int q = lane; q < SKM * SKM; q += 64) {
-        int a = q / SKM, b = q % SKM;
-        if (a >= k || b >= k) S.G[q] = (a == b) ? num<T>::one() : num<T>::zero();
+        S.Gt[q] = acc;
     }
     __syncthreads();
     // ---- 5. G^{-1} by the symmetric sweep, lane c holds column c ----
-    // g[q] holds entry (q + p) mod 32 of the column at step p, so the pivot
-    // entry is always g[0] and every register index is static; the array
-    // rotates by one per step and is back in place after 32 steps.
+    // Step p: a_qc -= a_qp a_pc / d (c != p), the pivot column becomes
+    // a_qp / d and entry p of every column a_pc / d (-1/d on the pivot); the
+    // result is -G^{-1}.  The iterate stays Hermitian, so a_qp = conj(a_pq):
+    // every lane publishes its a_pc and reads the pivot row back from LDS.
+    // All register indices are static.
     const int c = lane & (SKM - 1);
     T g[SKM];
 #pragma unroll
-    for (int i = 0; i < SKM; ++i) g[i] = S.G[i * SKM + c];
-    double maxd = lane < k ? num<T>::re(S.G[c * SKM + c]) : 0.0;
-    maxd = wave_max(maxd);
-    for (int p = 0; p < SKM; ++p) {
-        T* bc = S.bc[p & 1];
-        if (lane < SKM) bc[lane] = g[0];  // pivot row p (a_pc for column c)
-        __syncthreads();
-        const double d = num<T>::re(bc[p]);
-        const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
-        if (p < k && !(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
-        const double inv = zero ? 0.0 : 1.0 / d;
-        // sweep on column c: a_ic -= a_ip a_pc / d (c != p), a_ip / d for the
-        // pivot column, a_pc / d and -1/d on the pivot row; one update with a
-        // per-lane coefficient (a_ip = conj(a_pi) keeps G Hermitian)
-        const bool piv = (c == p);
-        const T coef = piv ? num<T>::mk(1.0 - inv) : g[0] * inv;
-        const T gp = piv ? num<T>::mk(zero ? 0.0 : -inv) : g[0] * inv;
-#pragma unroll
-        for (int q = 1; q < SKM; ++q) g[q] -= num<T>::conj(bc[(q + p) & (SKM - 1)]) * coef;
-        // rotate: entry p goes to the back
-#pragma unroll
-        for (int q = 0; q < SKM - 1; ++q) g[q] = g[q + 1];
-        g[SKM - 1] = gp;
+    for (int i = 0; i < SKM; ++i) {
+        if (i < k && c < k) g[i] = i <= c ? S.Gt[tri(i, c)] : num<T>::conj(S.Gt[tri(c, i)]);
+        else g[i] = (i == c) ? num<T>::one() : num<T>::zero();
     }
-    __syncthreads();
-    if (lane < SKM) {
+    double maxd = lane < k ? num<T>::re(S.Gt[tri(c, c)]) : 0.0;
+    maxd = wave_max(maxd);
+    __syncthreads();  // Gt is dead from here on; bc and post alias it
 #pragma unroll
-        for (int i = 0; i < SKM; ++i) S.G[i * SKM + c] = -g[i];  // G^{-1}
+    for (int p = 0; p < SKM; ++p) {
+        if (p < k) {
+            T* bc = S.bc[p & 1];
+            if (lane < SKM) bc[lane] = g[p];
+            __syncthreads();
+            const double d = num<T>::re(bc[p]);
+            const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
+            if (!(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
+            const double inv = zero ? 0.0 : 1.0 / d;
+            const bool piv = (c == p);
+            const T apc = g[p];
+            const T coef = piv ? num<T>::mk(1.0 - inv) : apc * inv;
+#pragma unroll
+            for (int q = 0; q < SKM; ++q)
+                if (q != p) g[q] -= num<T>::conj(bc[q]) * coef;
+            g[p] = piv ? num<T>::mk(zero ? 0.0 : -inv) : apc * inv;
+        }
     }
     __syncthreads();
     // ---- 6. V pattern ----
     const bool topk = A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER;
     int l = 0;
     if (topk) {
-        if (lane < k) {
-            T acc = num<T>::zero();
-            for (int pp = S.rptr[dj]; pp < S.rptr[dj + 1]; ++pp) {
-                int t = S.csr[pp];
-                acc += S.G[lane * SKM + S.ecol[t]] * num<T>::conj(S.eval[t]);
+        // w0 = G^{-1} u with u = conj(B(j, :)): lane c takes the product of
+        // its column of -G^{-1} (Hermitian) with u
+        if (lane < SKM) S.post.U[lane] = num<T>::zero();
+        __syncthreads();
+        {
+            const int pb = S.rptr[dj], pe = S.rptr[dj + 1];
+            if (lane < pe - pb) {
+                const int t = S.csr[pb + lane];
+                S.post.U[S.ecol[t]] = num<T>::conj(S.eval[t]);
             }
-            S.w[lane] = acc;
+        }
+        __syncthreads();
+        {
+            T acc = num<T>::zero();
+#pragma unroll
+            for (int i = 0; i < SKM; ++i) acc -= num<T>::conj(g[i]) * S.post.U[i];
+            if (lane < k) S.post.w[lane] = acc;
         }
         __syncthreads();
         T yr = num<T>::zero();
         if (lane < m)
             for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {
                 int t = S.csr[pp];
-                yr += S.eval[t] * S.w[S.ecol[t]];
+                yr += S.eval[t] * S.post.w[S.ecol[t]];
             }
         const bool adm = lane < m && (A.vrule == V_TOPK_LOWER ? myrow > j : myrow < j);
         const double sc = adm ? num<T>::abs(yr) : -1.0;
-        S.score[lane] = sc;
+        S.post.score[lane] = sc;
         const uint64_t amask = __ballot(adm);
         const int nc = __popcll(amask);
         int lj = A.vcount < 1 ? 1 : A.vcount;
@@ -342,7 +348,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         } else if (q > 0) {
             int rk = 0;
             for (int u = 0; u < 64; ++u) {
-                double su = S.score[u];
+                double su = S.post.score[u];
                 rk += (su > sc) || (su == sc && u < lane);
             }
             const uint64_t smask = __ballot(adm && rk == q - 1);
@@ -403,16 +409,22 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
     }
     __syncthreads();
     // ---- 7. Y = G^{-1} B_L^*, H = B_L Y ----
-    if (lane < k) {
-        for (int t = 0; t < l; ++t) {
-            T acc = num<T>::zero();
-            const int r = S.L[t];
-            for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
-                int e = S.csr[pp];
-                acc += S.G[lane * SKM + S.ecol[e]] * num<T>::conj(S.eval[e]);
-            }
-            S.Y[lane * SLM + t] = acc;
+    for (int q = lane; q < SLM * SKM; q += 64) S.post.U[q] = num<T>::zero();
+    __syncthreads();
+    for (int t = 0; t < l; ++t) {
+        const int r = S.L[t];
+        const int pb = S.rptr[r], pe = S.rptr[r + 1];
+        if (lane < pe - pb) {
+            const int e = S.csr[pb + lane];
+            S.post.U[t * SKM + S.ecol[e]] = num<T>::conj(S.eval[e]);
         }
+    }
+    __syncthreads();
+    for (int t = 0; t < l; ++t) {
+        T acc = num<T>::zero();
+#pragma unroll
+        for (int i = 0; i < SKM; ++i) acc -= num<T>::conj(g[i]) * S.post.U[t * SKM + i];
+        if (lane < k) S.post.Y[lane * SLM + t] = acc;
     }
     __syncthreads();
     const int hs = lane >> 3, ht = lane & 7;
@@ -421,83 +433,61 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         const int r = S.L[hs];
         for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
             int e = S.csr[pp];
-            h += S.eval[e] * S.Y[S.ecol[e] * SLM + ht];
+            h += S.eval[e] * S.post.Y[S.ecol[e] * SLM + ht];
         }
-    } else if (hs == ht) {
-        h = num<T>::mk(-1.0);  // padding below every eigenvalue of the PSD H
     }
-    T z = (hs == ht) ? num<T>::one() : num<T>::zero();
-    // ---- 8. top eigenvector of H: parallel cyclic Jacobi, lane = (row, col) ----
+    // ---- 8. top eigenvector of H by repeated squaring ----
+    // P = H / tr(H); each step P <- P^2 / tr(P^2), with tr(P^2) = ||P||_F^2.
+    // For P = sum mu_i v_i v_i^* (sum mu_i = 1), 1 - tr(P^2) ~ 2 mu_2, so the
+    // loop stops one squaring after 1 - tr(P^2) < 1e-12.  Not converging in
+    // 25 squarings means lambda_2 / lambda_1 > 1 - 1e-6: gap-degenerate.
     {
-        const int np = (l + 1) & ~1;
-        double scale = (hs == ht && hs < l) ? fabs(num<T>::re(h)) : 0.0;
-        scale = wave_max(scale);
-        for (int sweep = 0; sweep < 40 && np >= 2; ++sweep) {
-            bool any = false;
-            for (int r = 0; r < np - 1; ++r) {
-                // row pair
-                const int pr = rr_partner(hs, r, np);
-                const int ar = pr < 0 ? hs : min(hs, pr), br = pr < 0 ? hs : max(hs, pr);
-                const double haa = num<T>::re(shfl(h, ar * 9)), hbb = num<T>::re(shfl(h, br * 9));
-                const T hab = shfl(h, ar * 8 + br);
-                double cs, sn;
-                T ec;
-                bool rot;
-                rot_params(haa, hbb, hab, scale, cs, sn, ec, rot);
-                if (pr < 0 || br >= l) rot = false;
-                // column pair (same pairing)
-                const int pc = rr_partner(ht, r, np);
-                const int ac = pc < 0 ? ht : min(ht, pc), bcl = pc < 0 ? ht : max(ht, pc);
-                const double caa = num<T>::re(shfl(h, ac * 9)), cbb = num<T>::re(shfl(h, bcl * 9));
-                const T cab = shfl(h, ac * 8 + bcl);
-                double cs2, sn2;
-                T ec2;
-                bool rot2;
-                rot_params(caa, cbb, cab, scale, cs2, sn2, ec2, rot2);
-                if (pc < 0 || bcl >= l) rot2 = false;
-                any |= rot;
-                // rows: [a; b] <- J^* [a; b]
-                const T hpart = shfl(h, (pr < 0 ? hs : pr) * 8 + ht);
-                if (rot) {
-                    const T ecc = num<T>::conj(ec);
-                    if (hs == ar) h = cs * h - sn * (ecc * hpart);
-                    else h = sn * hpart + cs * (ecc * h);
-                }
-                // columns: [a b] <- [a b] J, eigenvectors likewise
-                const T hq = shfl(h, hs * 8 + (pc < 0 ? ht : pc));
-                const T zq = shfl(z, hs * 8 + (pc < 0 ? ht : pc));
-                if (rot2) {
-                    if (ht == ac) {
-                        h = cs2 * h - sn2 * (ec2 * hq);
-                        z = cs2 * z - sn2 * (ec2 * zq);
-                    } else {
-                        h = sn2 * hq + cs2 * (ec2 * h);
-                        z = sn2 * zq + cs2 * (ec2 * z);
-                    }
-                }
-            }
-            if (!__ballot(any)) break;
+        double tr = wave_sum((hs == ht) ? num<T>::re(h) : 0.0);
+        bool conv = false;
+        if (!(tr > 0.0) || !isfinite(tr)) {
+            h = (hs == 0 && ht == 0) ? num<T>::one() : num<T>::zero();
+            flags |= DIAF_FLAG_GAP_DEGENERATE;
+            conv = true;
+        } else {
+            h = num<T>::div(h, tr);
         }
+        for (int s = 0; s < 25 && !conv; ++s) {
+            const double f = wave_sum(num<T>::abs2(h));
+            conv = (1.0 - f) < 1e-12;
+            S.post.P[lane] = h;
+            __syncthreads();
+            T acc = num<T>::zero();
+#pragma unroll
+            for (int q = 0; q < SLM; ++q) acc += S.post.P[hs * SLM + q] * S.post.P[q * SLM + ht];
+            __syncthreads();
+            h = num<T>::div(acc, f);
+        }
+        if (!conv) flags |= DIAF_FLAG_GAP_DEGENERATE;
     }
-    // eigenvalues on the diagonal lanes; the largest (lowest index on ties)
-    const double lam = (hs == ht && hs < l) ? num<T>::re(h) : -INFINITY;
-    const double l1 = wave_max(lam);
-    const uint64_t bm = __ballot(hs == ht && hs < l && lam == l1);
-    const int best = (__ffsll((unsigned long long)bm) - 1) >> 3;
-    const uint64_t bm2 = __ballot(hs == ht && hs < l && hs != best);
-    double l2 = (hs == ht && hs < l && hs != best) ? lam : -INFINITY;
-    l2 = wave_max(l2);
-    if (bm2 && l1 > 0.0 && (l1 - l2) / l1 < 1e-6) flags |= DIAF_FLAG_GAP_DEGENERATE;
-    if (ht == best && hs < l) S.v[hs] = z;
+    // eigenvector: the column of P with the largest diagonal entry (lowest
+    // index on ties), normalised
+    {
+        const double dg = (hs == ht && hs < l) ? num<T>::re(h) : -1.0;
+        const double dmx = wave_max(dg);
+        const uint64_t cm = __ballot(hs == ht && hs < l && dg == dmx);
+        const int cstar = (__ffsll((unsigned long long)cm) - 1) >> 3;
+        if (ht == cstar && hs < SLM) S.post.v[hs] = h;
+        __syncthreads();
+        double nv = 0.0;
+        for (int t = 0; t < l; ++t) nv += num<T>::abs2(S.post.v[t]);
+        nv = sqrt(nv);
+        __syncthreads();
+        if (lane < l) S.post.v[lane] = num<T>::div(S.post.v[lane], nv);
+    }
     __syncthreads();
     // ---- 9. w = Y v ; phase ; residual ----
     if (lane < k) {
         T acc = num<T>::zero();
-        for (int t = 0; t < l; ++t) acc += S.Y[lane * SLM + t] * S.v[t];
-        S.w[lane] = acc;
+        for (int t = 0; t < l; ++t) acc += S.post.Y[lane * SLM + t] * S.post.v[t];
+        S.post.w[lane] = acc;
     }
     __syncthreads();
-    T vt = lane < l ? S.v[lane] : num<T>::zero();
+    T vt = lane < l ? S.post.v[lane] : num<T>::zero();
     const double vn = sqrt(wave_sum(lane < l ? num<T>::abs2(vt) : 0.0));
     const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
     const int dpos = dposm ? __ffsll((unsigned long long)dposm) - 1 : -1;
@@ -519,26 +509,26 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
     vt = ph * vt;
     if (dpos < 0 || num<T>::abs(shfl(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
         flags |= DIAF_FLAG_SMALL_DIAG;
-    if (lane < l) S.v[lane] = vt;
-    if (lane < k) S.w[lane] = ph * S.w[lane];
+    if (lane < l) S.post.v[lane] = vt;
+    if (lane < k) S.post.w[lane] = ph * S.post.w[lane];
     __syncthreads();
     T res = num<T>::zero();
     if (lane < m)
         for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {
             int e = S.csr[pp];
-            res += S.eval[e] * S.w[S.ecol[e]];
+            res += S.eval[e] * S.post.w[S.ecol[e]];
         }
     for (int t = 0; t < l; ++t)
-        if (S.L[t] == lane) res -= S.v[t];
+        if (S.L[t] == lane) res -= S.post.v[t];
     const double r2 = wave_sum(lane < m ? num<T>::abs2(res) : 0.0);
     // ---- 10. outputs (V sorted by row) ----
-    if (lane < k) A.Wval[jb + lane] = S.w[lane];
+    if (lane < k) A.Wval[jb + lane] = S.post.w[lane];
     int myL = lane < l ? S.L[lane] : 0x7fffffff;
     int rank = 0;
     for (int t = 0; t < l; ++t) rank += S.L[t] < myL;
     if (lane < l) {
         A.Vrows[(size_t)j * lmax + rank] = S.R[myL];
-        A.Vvals[(size_t)j * lmax + rank] = S.v[lane];
+        A.Vvals[(size_t)j * lmax + rank] = S.post.v[lane];
     } else if (lane < lmax) {
         A.Vrows[(size_t)j * lmax + lane] = -1;
         A.Vvals[(size_t)j * lmax + lane] = num<T>::zero();
