@@ -49,12 +49,15 @@ struct SmallLds {
         T Gt[STRI];     // packed upper triangle of G (until the sweep)
         T bc[2][SKM];   // pivot row of the sweep (double-buffered)
         struct {
-            T U[SLM * SKM];   // U[t][i] = conj(B(L_t, i)), dense k-vectors
-            T Y[SKM * SLM];   // Y[i][t] = (G^{-1} U)(i, t)
+            union {
+                T U[SLM * SKM];  // U[t][i] = conj(B(L_t, i)), dense k-vectors
+                struct {
+                    T P[SLM * SLM];  // power of H being squared (after Y)
+                    T v[SLM];
+                };
+            };
+            T Y[SKM * SLM];  // Y[i][t] = (G^{-1} U)(i, t)
             T w[SKM];
-            T v[SLM];
-            T P[SLM * SLM];   // power of H being squared
-            double score[SMM];
         } post;
     };
     uint64_t cmask[SKM];  // rows (local ids) of each column of B
@@ -68,7 +71,6 @@ struct SmallLds {
     };
     int rptr[SMM + 1];
     int L[SLM];
-    int misc[8];
     uint8_t eloc[STM];
     uint8_t ecol[STM];
     uint8_t eslot[STM];
@@ -81,6 +83,14 @@ __device__ inline T shfl(T v, int src)
 {
     if constexpr (num<T>::is_complex) return T{__shfl(v.x, src), __shfl(v.y, src)};
     else return __shfl(v, src);
+}
+
+// Value of lane ^ 32 (the other half of the wave).
+template <class T>
+__device__ inline T shfl_xor32(T v)
+{
+    if constexpr (num<T>::is_complex) return T{__shfl_xor(v.x, 32), __shfl_xor(v.y, 32)};
+    else return __shfl_xor(v, 32);
 }
 
 __device__ inline int wave_incl_scan(int x, int lane)
@@ -267,18 +277,22 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         S.Gt[q] = acc;
     }
     __syncthreads();
-    // ---- 5. G^{-1} by the symmetric sweep, lane c holds column c ----
-    // Step p: a_qc -= a_qp a_pc / d (c != p), the pivot column becomes
-    // a_qp / d and entry p of every column a_pc / d (-1/d on the pivot); the
-    // result is -G^{-1}.  The iterate stays Hermitian, so a_qp = conj(a_pq):
-    // every lane publishes its a_pc and reads the pivot row back from LDS.
-    // All register indices are static.
-    const int c = lane & (SKM - 1);
-    T g[SKM];
+    // ---- 5. G^{-1} by the symmetric sweep ----
+    // Lanes c and c + 32 hold rows 0..15 and 16..31 of column c (hf = lane /
+    // 32 picks the half).  Step p: a_qc -= a_qp a_pc / d (c != p), the pivot
+    // column becomes a_qp / d and entry p of every column a_pc / d (-1/d on
+    // the pivot); the result is -G^{-1}.  The iterate stays Hermitian, so
+    // a_qp = conj(a_pq): the half holding row p publishes a_pc for every
+    // column and all lanes read the pivot row back from LDS.  Register
+    // indices are static.
+    const int c = lane & (SKM - 1), hf = lane >> 5;
+    constexpr int SKH = SKM / 2;
+    T g[SKH];
 #pragma unroll
-    for (int i = 0; i < SKM; ++i) {
-        if (i < k && c < k) g[i] = i <= c ? S.Gt[tri(i, c)] : num<T>::conj(S.Gt[tri(c, i)]);
-        else g[i] = (i == c) ? num<T>::one() : num<T>::zero();
+    for (int i = 0; i < SKH; ++i) {
+        const int r = hf * SKH + i;
+        if (r < k && c < k) g[i] = r <= c ? S.Gt[tri(r, c)] : num<T>::conj(S.Gt[tri(c, r)]);
+        else g[i] = (r == c) ? num<T>::one() : num<T>::zero();
     }
     double maxd = lane < k ? num<T>::re(S.Gt[tri(c, c)]) : 0.0;
     maxd = wave_max(maxd);
@@ -287,19 +301,19 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
     for (int p = 0; p < SKM; ++p) {
         if (p < k) {
             T* bc = S.bc[p & 1];
-            if (lane < SKM) bc[lane] = g[p];
+            if ((p / SKH) == hf) bc[c] = g[p % SKH];
             __syncthreads();
             const double d = num<T>::re(bc[p]);
             const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
             if (!(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
             const double inv = zero ? 0.0 : 1.0 / d;
             const bool piv = (c == p);
-            const T apc = g[p];
+            const T apc = bc[c];
             const T coef = piv ? num<T>::mk(1.0 - inv) : apc * inv;
+            const T* brow = bc + hf * SKH;
 #pragma unroll
-            for (int q = 0; q < SKM; ++q)
-                if (q != p) g[q] -= num<T>::conj(bc[q]) * coef;
-            g[p] = piv ? num<T>::mk(zero ? 0.0 : -inv) : apc * inv;
+            for (int i = 0; i < SKH; ++i) g[i] -= num<T>::conj(brow[i]) * coef;
+            if ((p / SKH) == hf) g[p % SKH] = piv ? num<T>::mk(zero ? 0.0 : -inv) : apc * inv;
         }
     }
     __syncthreads();
@@ -322,7 +336,8 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         {
             T acc = num<T>::zero();
 #pragma unroll
-            for (int i = 0; i < SKM; ++i) acc -= num<T>::conj(g[i]) * S.post.U[i];
+            for (int i = 0; i < SKH; ++i) acc -= num<T>::conj(g[i]) * S.post.U[hf * SKH + i];
+            acc += shfl_xor32(acc);
             if (lane < k) S.post.w[lane] = acc;
         }
         __syncthreads();
@@ -334,7 +349,6 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
             }
         const bool adm = lane < m && (A.vrule == V_TOPK_LOWER ? myrow > j : myrow < j);
         const double sc = adm ? num<T>::abs(yr) : -1.0;
-        S.post.score[lane] = sc;
         const uint64_t amask = __ballot(adm);
         const int nc = __popcll(amask);
         int lj = A.vcount < 1 ? 1 : A.vcount;
@@ -346,14 +360,17 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         if (q > 0 && nc <= q) {
             chosen = adm;
         } else if (q > 0) {
-            int rk = 0;
-            for (int u = 0; u < 64; ++u) {
-                double su = S.post.score[u];
-                rk += (su > sc) || (su == sc && u < lane);
+            // the q-th largest score (ties: lower lane first), by q rounds of
+            // extracting the maximum
+            bool taken = false;
+            double ss = 0.0;
+            for (int r = 0; r < q; ++r) {
+                const double cand = (adm && !taken) ? sc : -2.0;
+                const double mx = wave_max(cand);
+                const uint64_t bm = __ballot(adm && !taken && sc == mx);
+                if (lane == __ffsll((unsigned long long)bm) - 1) taken = true;
+                ss = mx;
             }
-            const uint64_t smask = __ballot(adm && rk == q - 1);
-            const int slane = __ffsll((unsigned long long)smask) - 1;
-            const double ss = __shfl(sc, slane);
             const double hi = ss * (1.0 + 1e-10), lo = ss * (1.0 - 1e-10);
             const bool in = adm && sc > hi;
             const bool tie = adm && sc >= lo && sc <= hi;
@@ -423,7 +440,8 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
     for (int t = 0; t < l; ++t) {
         T acc = num<T>::zero();
 #pragma unroll
-        for (int i = 0; i < SKM; ++i) acc -= num<T>::conj(g[i]) * S.post.U[t * SKM + i];
+        for (int i = 0; i < SKH; ++i) acc -= num<T>::conj(g[i]) * S.post.U[t * SKM + hf * SKH + i];
+        acc += shfl_xor32(acc);
         if (lane < k) S.post.Y[lane * SLM + t] = acc;
     }
     __syncthreads();
