@@ -329,10 +329,11 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     std::vector<void*> to_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     int nb = 0;
-    // Unit-norm v with small columns: the one-wave kernel; columns it cannot
-    // hold (shadow above 64 rows) come back on a deferred list for the
-    // generic kernel.
-    if (mode == 0 && !ctx->opt_generic_only && F->lmax <= 8) {
+    // Small columns go to the one-wave kernel (both norm modes); columns it
+    // cannot hold (shadow above 64 rows) come back on a deferred list for the
+    // generic kernel.  The FP32-Gram variant is implemented by the generic
+    // kernel only.
+    if (!ctx->opt_generic_only && !spec->gram_fp32 && F->lmax <= 8) {
         std::vector<int32_t> small;
         for (int c = 0; c < ncls; ++c) {
             if (B[c].kcap > 32 || B[c].tcap > 256) continue;

@@ -1,5 +1,5 @@
-// Small-column kernel for the first basic algorithm (unit-norm columns of
-// V, paper Section 2.1): one wave per column, |J_j| <= 32, shadow |R_j| <= 64,
+// Small-column kernel for both basic algorithms (unit-norm columns of V,
+// paper Section 2.1, or of W, Section 2.2): one wave per column, |J_j| <= 32, shadow |R_j| <= 64,
 // at most 256 gathered entries and |L_j| <= 8.  Columns outside these limits
 // are appended to a deferred list for the generic kernel.
 //
@@ -41,13 +41,15 @@ static constexpr int STRI = SKM * (SKM + 1) / 2;  // packed upper triangle of G
 // Packed upper-triangle index of G(a, b), a <= b (column b holds rows 0..b).
 __device__ inline int tri(int a, int b) { return b * (b + 1) / 2 + a; }
 
-template <class T>
+template <class T, int MODE>
 struct SmallLds {
     T eval[STM];  // gathered values, column by column in J order
+    T Gk[MODE == 1 ? STRI : 1];  // unit-norm w: packed G, kept for two solves
     union {
         int erow[STM];  // gathered global rows (until the shadow is built)
         T Gt[STRI];     // packed upper triangle of G (until the sweep)
         T bc[2][SKM];   // pivot row of the sweep (double-buffered)
+        T Pm[MODE == 1 ? SKM * SKM : 1];  // unit-norm w: power being squared
         struct {
             union {
                 T U[SLM * SKM];  // U[t][i] = conj(B(L_t, i)), dense k-vectors
@@ -114,8 +116,147 @@ __device__ inline double wave_max(double x)
     return x;
 }
 
+// Symmetric sweep (Gauss-Jordan) of a Hermitian k x k matrix padded with
+// the identity to 32 x 32.  Lanes c and c + 32 hold rows 0..15 and 16..31 of
+// column c in g (hf = lane / 32).  Step p: a_qc -= a_qp a_pc / d (c != p),
+// the pivot column becomes a_qp / d and entry p of every column a_pc / d
+// (-1/d on the pivot); the result is minus the inverse.  The iterate stays
+// Hermitian, so a_qp = conj(a_pq): the half holding row p publishes a_pc for
+// every column and all lanes read the pivot row back from LDS.  Register
+// indices are static.
 template <class T>
-__device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int* deferred,
+__device__ __forceinline__ void sweep_inverse(T (&g)[SKM / 2], int k, int c, int hf, double maxd,
+                                              T (*bc)[SKM], uint32_t& flags)
+{
+    constexpr int SKH = SKM / 2;
+#pragma unroll
+    for (int p = 0; p < SKM; ++p) {
+        if (p < k) {
+            T* b = bc[p & 1];
+            if ((p / SKH) == hf) b[c] = g[p % SKH];
+            __syncthreads();
+            const double d = num<T>::re(b[p]);
+            const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
+            if (!(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
+            const double inv = zero ? 0.0 : 1.0 / d;
+            const bool piv = (c == p);
+            const T apc = b[c];
+            const T coef = piv ? num<T>::mk(1.0 - inv) : apc * inv;
+            const T* brow = b + hf * SKH;
+#pragma unroll
+            for (int i = 0; i < SKH; ++i) g[i] -= num<T>::conj(brow[i]) * coef;
+            if ((p / SKH) == hf) g[p % SKH] = piv ? num<T>::mk(zero ? 0.0 : -inv) : apc * inv;
+        }
+    }
+    __syncthreads();
+}
+
+// Top eigenvector of a Hermitian positive semidefinite k x k matrix P held
+// as half-columns (as in sweep_inverse) and zero outside k x k: the
+// trace-normalised powers P^(2^s) by repeated squaring until the power is
+// rank one to 1e-12 (one more squaring after that), then the column with
+// the largest diagonal entry (lowest index on ties), normalised, into out.
+// Returns false if 25 squarings did not reach rank one (the top eigenvalue
+// is then separated from the next by less than a relative 1e-6).
+template <class T>
+__device__ __forceinline__ bool top_eig_k(T (&pv)[SKM / 2], int k, int c, int hf, int lane, T* Pm,
+                                          T* out)
+{
+    constexpr int SKH = SKM / 2;
+    double dsum = 0.0;
+#pragma unroll
+    for (int i = 0; i < SKH; ++i)
+        if (hf * SKH + i == c && c < k) dsum += num<T>::re(pv[i]);
+    const double tr = wave_sum(dsum);
+    bool conv = false;
+    if (!(tr > 0.0) || !isfinite(tr)) {
+#pragma unroll
+        for (int i = 0; i < SKH; ++i)
+            pv[i] = (hf * SKH + i == c && c == 0) ? num<T>::one() : num<T>::zero();
+        conv = true;
+    } else {
+#pragma unroll
+        for (int i = 0; i < SKH; ++i) pv[i] = num<T>::div(pv[i], tr);
+    }
+    const bool ok = conv ? false : true;
+    for (int s = 0; s < 25 && !conv; ++s) {
+        double fs = 0.0;
+#pragma unroll
+        for (int i = 0; i < SKH; ++i) fs += num<T>::abs2(pv[i]);
+        const double f = wave_sum(fs);
+        conv = (1.0 - f) < 1e-12;
+#pragma unroll
+        for (int i = 0; i < SKH; ++i) Pm[c * SKM + hf * SKH + i] = pv[i];
+        __syncthreads();
+        T colc[SKM];
+#pragma unroll
+        for (int q = 0; q < SKM; ++q) colc[q] = Pm[c * SKM + q];
+#pragma unroll
+        for (int i = 0; i < SKH; ++i) {
+            const T* colr = Pm + (hf * SKH + i) * SKM;
+            T acc = num<T>::zero();
+#pragma unroll
+            for (int q = 0; q < SKM; ++q) acc += num<T>::conj(colr[q]) * colc[q];
+            pv[i] = num<T>::div(acc, f);
+        }
+        __syncthreads();
+    }
+    double dg = -1.0;
+#pragma unroll
+    for (int i = 0; i < SKH; ++i)
+        if (hf * SKH + i == c && c < k) dg = num<T>::re(pv[i]);
+    const double dmx = wave_max(dg);
+    const uint64_t cm = __ballot(dg == dmx && dg >= 0.0);
+    const int cstar = (__ffsll((unsigned long long)cm) - 1) & (SKM - 1);
+    if (c == cstar) {
+#pragma unroll
+        for (int i = 0; i < SKH; ++i)
+            if (hf * SKH + i < k) out[hf * SKH + i] = pv[i];
+    }
+    __syncthreads();
+    const double nv = sqrt(wave_sum(lane < k ? num<T>::abs2(out[lane]) : 0.0));
+    __syncthreads();
+    if (lane < k) out[lane] = num<T>::div(out[lane], nv);
+    __syncthreads();
+    return ok && conv;
+}
+
+// Unit-norm w: loads G - sum_{t<nt} U_t U_t^* + shift * I (the Gram matrix
+// of B without the rows held in U) as half-columns, inverts it by the
+// sweep and takes the top eigenvector of the inverse, i.e. the bottom
+// eigenvector of the downdated Gram matrix, into out (unit norm).
+template <class T, int MODE>
+__device__ __forceinline__ bool bottom_eig_w(SmallLds<T, MODE>& S, int k, int nt, int c, int hf,
+                                             int lane, double maxd, double shift, T* out)
+{
+    constexpr int SKH = SKM / 2;
+    T g[SKH];
+#pragma unroll
+    for (int i = 0; i < SKH; ++i) {
+        const int r = hf * SKH + i;
+        if (r < k && c < k) {
+            T a = r <= c ? S.Gk[tri(r, c)] : num<T>::conj(S.Gk[tri(c, r)]);
+            for (int t = 0; t < nt; ++t)
+                a -= S.post.U[t * SKM + r] * num<T>::conj(S.post.U[t * SKM + c]);
+            if (r == c) a += num<T>::mk(shift);
+            g[i] = a;
+        } else {
+            g[i] = (r == c) ? num<T>::one() : num<T>::zero();
+        }
+    }
+    __syncthreads();  // U has been read; bc and Pm alias it
+    uint32_t unused = 0;
+    sweep_inverse(g, k, c, hf, maxd, S.bc, unused);
+#pragma unroll
+    for (int i = 0; i < SKH; ++i) {
+        const int r = hf * SKH + i;
+        g[i] = (r < k && c < k) ? -g[i] : num<T>::zero();
+    }
+    return top_eig_k(g, k, c, hf, lane, S.Pm, out);
+}
+
+template <class T, int MODE>
+__device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S, int* deferred,
                              int* ndeferred)
 {
     // opaque per call: keeps lane-derived addresses from being hoisted out of
@@ -274,49 +415,33 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
             acc += num<T>::cmul(S.eval[oa + __popcll(ma & below)], S.eval[ob + __popcll(mb & below)]);
             common &= common - 1ull;
         }
-        S.Gt[q] = acc;
+        if constexpr (MODE == 1) S.Gk[q] = acc;
+        else S.Gt[q] = acc;
     }
     __syncthreads();
-    // ---- 5. G^{-1} by the symmetric sweep ----
+    // ---- 5. unit-norm v: G^{-1} by the symmetric sweep ----
     // Lanes c and c + 32 hold rows 0..15 and 16..31 of column c (hf = lane /
-    // 32 picks the half).  Step p: a_qc -= a_qp a_pc / d (c != p), the pivot
-    // column becomes a_qp / d and entry p of every column a_pc / d (-1/d on
-    // the pivot); the result is -G^{-1}.  The iterate stays Hermitian, so
-    // a_qp = conj(a_pq): the half holding row p publishes a_pc for every
-    // column and all lanes read the pivot row back from LDS.  Register
-    // indices are static.
+    // 32 picks the half); the sweep leaves -G^{-1} there.  Unit-norm w keeps
+    // G packed in LDS and solves twice (seed and final) further down.
     const int c = lane & (SKM - 1), hf = lane >> 5;
     constexpr int SKH = SKM / 2;
     T g[SKH];
-#pragma unroll
-    for (int i = 0; i < SKH; ++i) {
-        const int r = hf * SKH + i;
-        if (r < k && c < k) g[i] = r <= c ? S.Gt[tri(r, c)] : num<T>::conj(S.Gt[tri(c, r)]);
-        else g[i] = (r == c) ? num<T>::one() : num<T>::zero();
-    }
-    double maxd = lane < k ? num<T>::re(S.Gt[tri(c, c)]) : 0.0;
+    const T* Gp = (MODE == 1) ? S.Gk : S.Gt;
+    double maxd = lane < k ? num<T>::re(Gp[tri(c, c)]) : 0.0;
     maxd = wave_max(maxd);
-    __syncthreads();  // Gt is dead from here on; bc and post alias it
+    // shift for unit-norm w: the downdated Gram matrix plus shift * I is
+    // positive definite, and the shift leaves its eigenvectors unchanged
+    const double shift = 1e-12 * maxd;
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int p = 0; p < SKM; ++p) {
-        if (p < k) {
-            T* bc = S.bc[p & 1];
-            if ((p / SKH) == hf) bc[c] = g[p % SKH];
-            __syncthreads();
-            const double d = num<T>::re(bc[p]);
-            const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
-            if (!(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
-            const double inv = zero ? 0.0 : 1.0 / d;
-            const bool piv = (c == p);
-            const T apc = bc[c];
-            const T coef = piv ? num<T>::mk(1.0 - inv) : apc * inv;
-            const T* brow = bc + hf * SKH;
-#pragma unroll
-            for (int i = 0; i < SKH; ++i) g[i] -= num<T>::conj(brow[i]) * coef;
-            if ((p / SKH) == hf) g[p % SKH] = piv ? num<T>::mk(zero ? 0.0 : -inv) : apc * inv;
+        for (int i = 0; i < SKH; ++i) {
+            const int r = hf * SKH + i;
+            if (r < k && c < k) g[i] = r <= c ? S.Gt[tri(r, c)] : num<T>::conj(S.Gt[tri(c, r)]);
+            else g[i] = (r == c) ? num<T>::one() : num<T>::zero();
         }
+        __syncthreads();  // Gt is dead from here on; bc and post alias it
+        sweep_inverse(g, k, c, hf, maxd, S.bc, flags);
     }
-    __syncthreads();
     // ---- 6. V pattern ----
     const bool topk = A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER;
     int l = 0;
@@ -333,12 +458,16 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
             }
         }
         __syncthreads();
-        {
+        if constexpr (MODE == 0) {
             T acc = num<T>::zero();
 #pragma unroll
             for (int i = 0; i < SKH; ++i) acc -= num<T>::conj(g[i]) * S.post.U[hf * SKH + i];
             acc += shfl_xor32(acc);
             if (lane < k) S.post.w[lane] = acc;
+        } else {
+            // seed of the second basic algorithm: bottom eigenvector of
+            // G - b_j^* b_j (B without row j)
+            bottom_eig_w(S, k, 1, c, hf, lane, maxd, shift, S.post.w);
         }
         __syncthreads();
         T yr = num<T>::zero();
@@ -353,6 +482,10 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         const int nc = __popcll(amask);
         int lj = A.vcount < 1 ? 1 : A.vcount;
         if (lj > 1 + nc) lj = 1 + nc;
+        if (MODE == 1) {  // keep B without the rows of L at least k rows tall
+            const int cap = m - k > 1 ? m - k : 1;
+            if (lj > cap) lj = cap;
+        }
         if (lj > lmax) lj = lmax;
         const int q = lj - 1;
         __syncthreads();
@@ -437,74 +570,92 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
         }
     }
     __syncthreads();
-    for (int t = 0; t < l; ++t) {
-        T acc = num<T>::zero();
-#pragma unroll
-        for (int i = 0; i < SKH; ++i) acc -= num<T>::conj(g[i]) * S.post.U[t * SKM + hf * SKH + i];
-        acc += shfl_xor32(acc);
-        if (lane < k) S.post.Y[lane * SLM + t] = acc;
-    }
-    __syncthreads();
-    const int hs = lane >> 3, ht = lane & 7;
-    T h = num<T>::zero();
-    if (hs < l && ht < l) {
-        const int r = S.L[hs];
-        for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
-            int e = S.csr[pp];
-            h += S.eval[e] * S.post.Y[S.ecol[e] * SLM + ht];
-        }
-    }
-    // ---- 8. top eigenvector of H by repeated squaring ----
-    // P = H / tr(H); each step P <- P^2 / tr(P^2), with tr(P^2) = ||P||_F^2.
-    // For P = sum mu_i v_i v_i^* (sum mu_i = 1), 1 - tr(P^2) ~ 2 mu_2, so the
-    // loop stops one squaring after 1 - tr(P^2) < 1e-12.  Not converging in
-    // 25 squarings means lambda_2 / lambda_1 > 1 - 1e-6: gap-degenerate.
-    {
-        double tr = wave_sum((hs == ht) ? num<T>::re(h) : 0.0);
-        bool conv = false;
-        if (!(tr > 0.0) || !isfinite(tr)) {
-            h = (hs == 0 && ht == 0) ? num<T>::one() : num<T>::zero();
-            flags |= DIAF_FLAG_GAP_DEGENERATE;
-            conv = true;
-        } else {
-            h = num<T>::div(h, tr);
-        }
-        for (int s = 0; s < 25 && !conv; ++s) {
-            const double f = wave_sum(num<T>::abs2(h));
-            conv = (1.0 - f) < 1e-12;
-            S.post.P[lane] = h;
-            __syncthreads();
+    if constexpr (MODE == 0) {
+        for (int t = 0; t < l; ++t) {
             T acc = num<T>::zero();
 #pragma unroll
-            for (int q = 0; q < SLM; ++q) acc += S.post.P[hs * SLM + q] * S.post.P[q * SLM + ht];
-            __syncthreads();
-            h = num<T>::div(acc, f);
+            for (int i = 0; i < SKH; ++i) acc -= num<T>::conj(g[i]) * S.post.U[t * SKM + hf * SKH + i];
+            acc += shfl_xor32(acc);
+            if (lane < k) S.post.Y[lane * SLM + t] = acc;
         }
-        if (!conv) flags |= DIAF_FLAG_GAP_DEGENERATE;
-    }
-    // eigenvector: the column of P with the largest diagonal entry (lowest
-    // index on ties), normalised
-    {
-        const double dg = (hs == ht && hs < l) ? num<T>::re(h) : -1.0;
-        const double dmx = wave_max(dg);
-        const uint64_t cm = __ballot(hs == ht && hs < l && dg == dmx);
-        const int cstar = (__ffsll((unsigned long long)cm) - 1) >> 3;
-        if (ht == cstar && hs < SLM) S.post.v[hs] = h;
         __syncthreads();
-        double nv = 0.0;
-        for (int t = 0; t < l; ++t) nv += num<T>::abs2(S.post.v[t]);
-        nv = sqrt(nv);
+        const int hs = lane >> 3, ht = lane & 7;
+        T h = num<T>::zero();
+        if (hs < l && ht < l) {
+            const int r = S.L[hs];
+            for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                int e = S.csr[pp];
+                h += S.eval[e] * S.post.Y[S.ecol[e] * SLM + ht];
+            }
+        }
+        // ---- 8. top eigenvector of H by repeated squaring ----
+        // P = H / tr(H); each step P <- P^2 / tr(P^2), with tr(P^2) = ||P||_F^2.
+        // For P = sum mu_i v_i v_i^* (sum mu_i = 1), 1 - tr(P^2) ~ 2 mu_2, so the
+        // loop stops one squaring after 1 - tr(P^2) < 1e-12.  Not converging in
+        // 25 squarings means lambda_2 / lambda_1 > 1 - 1e-6: gap-degenerate.
+        {
+            double tr = wave_sum((hs == ht) ? num<T>::re(h) : 0.0);
+            bool conv = false;
+            if (!(tr > 0.0) || !isfinite(tr)) {
+                h = (hs == 0 && ht == 0) ? num<T>::one() : num<T>::zero();
+                flags |= DIAF_FLAG_GAP_DEGENERATE;
+                conv = true;
+            } else {
+                h = num<T>::div(h, tr);
+            }
+            for (int s = 0; s < 25 && !conv; ++s) {
+                const double f = wave_sum(num<T>::abs2(h));
+                conv = (1.0 - f) < 1e-12;
+                S.post.P[lane] = h;
+                __syncthreads();
+                T acc = num<T>::zero();
+#pragma unroll
+                for (int q = 0; q < SLM; ++q) acc += S.post.P[hs * SLM + q] * S.post.P[q * SLM + ht];
+                __syncthreads();
+                h = num<T>::div(acc, f);
+            }
+            if (!conv) flags |= DIAF_FLAG_GAP_DEGENERATE;
+        }
+        // eigenvector: the column of P with the largest diagonal entry (lowest
+        // index on ties), normalised
+        {
+            const double dg = (hs == ht && hs < l) ? num<T>::re(h) : -1.0;
+            const double dmx = wave_max(dg);
+            const uint64_t cm = __ballot(hs == ht && hs < l && dg == dmx);
+            const int cstar = (__ffsll((unsigned long long)cm) - 1) >> 3;
+            if (ht == cstar && hs < SLM) S.post.v[hs] = h;
+            __syncthreads();
+            double nv = 0.0;
+            for (int t = 0; t < l; ++t) nv += num<T>::abs2(S.post.v[t]);
+            nv = sqrt(nv);
+            __syncthreads();
+            if (lane < l) S.post.v[lane] = num<T>::div(S.post.v[lane], nv);
+        }
         __syncthreads();
-        if (lane < l) S.post.v[lane] = num<T>::div(S.post.v[lane], nv);
+        // w = Y v
+        if (lane < k) {
+            T acc = num<T>::zero();
+            for (int t = 0; t < l; ++t) acc += S.post.Y[lane * SLM + t] * S.post.v[t];
+            S.post.w[lane] = acc;
+        }
+        __syncthreads();
+    } else {
+        // final solve of the second basic algorithm (Section 2.2): w = bottom
+        // eigenvector of G - B_L^* B_L (B without the rows of L), v = (B w)|_L
+        if (!bottom_eig_w(S, k, l, c, hf, lane, maxd, shift, S.post.w))
+            flags |= DIAF_FLAG_GAP_DEGENERATE;
+        if (lane < l) {
+            const int r = S.L[lane];
+            T acc = num<T>::zero();
+            for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                const int e = S.csr[pp];
+                acc += S.eval[e] * S.post.w[S.ecol[e]];
+            }
+            S.post.v[lane] = acc;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // ---- 9. w = Y v ; phase ; residual ----
-    if (lane < k) {
-        T acc = num<T>::zero();
-        for (int t = 0; t < l; ++t) acc += S.post.Y[lane * SLM + t] * S.post.v[t];
-        S.post.w[lane] = acc;
-    }
-    __syncthreads();
+    // ---- 9. phase ; residual ----
     T vt = lane < l ? S.post.v[lane] : num<T>::zero();
     const double vn = sqrt(wave_sum(lane < l ? num<T>::abs2(vt) : 0.0));
     const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
@@ -539,6 +690,11 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
     for (int t = 0; t < l; ++t)
         if (S.L[t] == lane) res -= S.post.v[t];
     const double r2 = wave_sum(lane < m ? num<T>::abs2(res) : 0.0);
+    if constexpr (MODE == 1) {
+        // B without the rows of L has fewer rows than columns, or its
+        // smallest singular value is negligible against the largest
+        if (m - l < k || r2 <= 1e-14 * maxd) flags |= DIAF_FLAG_RANK_DEFICIENT;
+    }
     // ---- 10. outputs (V sorted by row) ----
     if (lane < k) A.Wval[jb + lane] = S.post.w[lane];
     int myL = lane < l ? S.L[lane] : 0x7fffffff;
@@ -560,11 +716,11 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T>& S, int*
     __syncthreads();
 }
 
-template <class T>
+template <class T, int MODE>
 __global__ void __launch_bounds__(64) factor_small_kernel(FactorArgs<T> A, int* deferred,
                                                           int* ndeferred)
 {
-    __shared__ SmallLds<T> S;
+    __shared__ SmallLds<T, MODE> S;
     for (int q = blockIdx.x; q < A.ncols; q += gridDim.x) small_column(A, A.cols[q], S, deferred,
                                                                         ndeferred);
 }
@@ -573,9 +729,13 @@ template <class T>
 Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, hipStream_t st)
 {
     if (A.ncols == 0) return {};
-    if (A.mode != 0) return {DIAF_EINVAL, "small factor kernel: unit-norm v only"};
-    int grid = A.ncols < 256 * 16 ? A.ncols : 256 * 16;
-    hipLaunchKernelGGL(factor_small_kernel<T>, dim3(grid), dim3(64), 0, st, A, deferred, ndeferred);
+    const int grid = A.ncols < 256 * 16 ? A.ncols : 256 * 16;
+    if (A.mode == 0)
+        hipLaunchKernelGGL((factor_small_kernel<T, 0>), dim3(grid), dim3(64), 0, st, A, deferred,
+                           ndeferred);
+    else
+        hipLaunchKernelGGL((factor_small_kernel<T, 1>), dim3(grid), dim3(64), 0, st, A, deferred,
+                           ndeferred);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
