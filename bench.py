@@ -229,9 +229,9 @@ def main():
 
     if not args.no_learned:
         log("learned: preparing model")
-        model, gate = LR.load_or_train(ctx, args.mode, log=log)
+        model, gate, gate_dom = LR.load_or_train(ctx, args.mode, log=log)
         lspec = diaf.make_spec(w="learned", v=cfg["v"], v_count=cfg["v_count"], model=model,
-                               gate_tau=gate)
+                               gate_tau=gate, gate_dom=gate_dom)
         for _ in range(args.warmup):
             F, lst, linfo, lf, ls = step(lspec)
             log(f"learned warmup: factor {lf:.1f} ms, solve {ls:.1f} ms, {linfo.iters} its, "
@@ -241,16 +241,17 @@ def main():
         for _ in range(args.steps):
             F, lst, linfo, lf, ls = step(lspec)
             log(f"learned step: factor {lf:.1f} ms, solve {ls:.1f} ms, {linfo.iters} its")
-            lrec.append((lf, ls, linfo.iters, lst.count_fell_back, lst.nnz_w))
+            lrec.append((lf, ls, linfo.iters, lst.count_fell_back, lst.nnz_w, lst.v_levels))
             F.close()
         L_ = np.array(lrec, dtype=float)
         out["learned"] = {"factor_ms": float(L_[:, 0].mean()), "solve_ms": float(L_[:, 1].mean()),
                           "e2e_ms": float((L_[:, 0] + L_[:, 1]).mean()),
                           "bicgstab_iters": int(L_[-1, 2]), "fell_back": int(L_[-1, 3]),
-                          "nnz_w": int(L_[-1, 4]), "gate_tau": gate}
+                          "nnz_w": int(L_[-1, 4]), "gate_tau": gate, "gate_dom": gate_dom,
+                          "v_levels": int(L_[-1, 5])}
         out["plain"] = {"factor_ms": factor_ms, "solve_ms": solve_ms,
                         "e2e_ms": factor_ms + solve_ms, "bicgstab_iters": iters,
-                        "nnz_w": int(len(H["Wri"]))}
+                        "nnz_w": int(len(H["Wri"])), "v_levels": int(st.v_levels)}
         model.close()
 
     if not args.no_cpu:

@@ -120,6 +120,10 @@ typedef struct diaf_spec {
     int32_t v_count;                 /* DIAF_V_TOPK_*: l, counting the diagonal */
     const diaf_pattern* v_explicit;  /* DIAF_V_EXPLICIT (rows outside the shadow get 0) */
     int32_t gram_fp32;               /* 1: Gram matrix accumulated in FP32 products (variant) */
+    double gate_dom;                 /* DIAF_W_LEARNED: also refactor with pattern(A^2) when
+                                        |v_jj| < gate_dom * sum_{i != j} |v_ij| for the
+                                        proposal's V column: chains of such columns make the
+                                        triangular solve with V grow exponentially (0 = off) */
 } diaf_spec;
 
 /* Borrowed device views of a factorization.  W has the pattern J (Wcp/Wri)

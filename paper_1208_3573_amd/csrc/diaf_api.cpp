@@ -21,6 +21,7 @@ struct diaf_ctx {
     std::string err;
     int64_t opt_generic_only = 0;
     int64_t opt_batch = 8;
+    int64_t opt_gate_small_diag = 1;
     diaf::TrsvTune trsv;
 };
 
@@ -572,6 +573,7 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     if (k == "generic_only") ctx->opt_generic_only = value;
     else if (k == "solve_batch") ctx->opt_batch = value < 1 ? 1 : value;
     else if (k == "trsv_backoff") ctx->trsv.backoff = value ? 1 : 0;
+    else if (k == "gate_small_diag") ctx->opt_gate_small_diag = value ? 1 : 0;
     else if (k == "trsv_rows_per_lane") {
         if (value != 1 && value != 2 && value != 4)
             return fail(ctx, DIAF_EINVAL, "trsv_rows_per_lane must be 1, 2 or 4");
@@ -743,16 +745,37 @@ Err gate_and_fallback(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, i
 {
     hipStream_t st = ctx->stream;
     const int n = (int)F->n;
-    std::vector<double> r(n), bn(n);
+    std::vector<double> r(n), bn(n), dom(n, INFINITY);
+    std::vector<uint32_t> fl0(n);
     DIAF_HIP_TRY(hipMemcpyAsync(r.data(), F->r, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     DIAF_HIP_TRY(hipMemcpyAsync(bn.data(), F->bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(fl0.data(), F->flags, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
+                                st));
+    if (spec->gate_dom > 0.0) {
+        double* domd = nullptr;
+        DIAF_TRY(dmalloc(&domd, sizeof(double) * n));
+        DIAF_TRY(launch_col_dominance<T>(n, F->lmax, F->Vrows, (const T*)F->Vvals, F->lcount,
+                                         domd, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(dom.data(), domd, sizeof(double) * n, hipMemcpyDeviceToHost,
+                                    st));
+        DIAF_TRY(sync(st));
+        dfree(domd);
+    }
     DIAF_TRY(sync(st));
     std::vector<uint8_t> fb(n, 0);
     std::vector<int32_t> list;
+    // a proposal is rejected when its normalised residual exceeds the gate,
+    // when its V column is not diagonally dominant enough (chains of such
+    // columns make the triangular solve with V grow exponentially) or, unless
+    // switched off, when V's diagonal entry is negligible (Section 3.2)
+    const uint32_t reject = ctx->opt_gate_small_diag ? DIAF_FLAG_SMALL_DIAG : 0u;
     for (int j = 0; j < n; ++j) {
         double sj = mode == DIAF_UNIT_V ? 1.0 : bn[j];
         double q = sj > 0 ? r[j] / sj : r[j];
-        if (!(q <= spec->gate_tau)) { fb[j] = 1; list.push_back(j); }
+        if (!(q <= spec->gate_tau) || (fl0[j] & reject) || !(dom[j] >= spec->gate_dom)) {
+            fb[j] = 1;
+            list.push_back(j);
+        }
     }
     if (list.empty()) return {};
     uint8_t* fbd = nullptr;

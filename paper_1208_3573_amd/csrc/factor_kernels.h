@@ -57,6 +57,10 @@ Err launch_diag_check(int n, const int32_t* rp, const int32_t* ci, const T* val,
 template <class T>
 Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* counts_dev,
                       double* nrm2_dev, hipStream_t st);
+// |v_jj| / sum_{i != j} |v_ij| per column of the padded V layout.
+template <class T>
+Err launch_col_dominance(int n, int lmax, const int32_t* Vrows, const T* Vvals,
+                         const int32_t* lcount, double* dom, hipStream_t st);
 
 // ---- solve (solve.hip) ----
 

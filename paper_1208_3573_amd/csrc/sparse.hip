@@ -218,7 +218,40 @@ Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* co
     return {};
 }
 
+// Diagonal dominance of each V column in the padded per-column layout:
+// dom[j] = |v_jj| / sum_{i != j} |v_ij| (infinite without off-diagonal
+// entries, 0 without a diagonal entry).
+template <class T>
+__global__ void col_dominance_kernel(int n, int lmax, const int32_t* Vrows, const T* Vvals,
+                                     const int32_t* lcount, double* dom)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double d = 0.0, off = 0.0;
+    const int l = lcount[j];
+    for (int t = 0; t < l; ++t) {
+        const int r = Vrows[(size_t)j * lmax + t];
+        const double a = num<T>::abs(Vvals[(size_t)j * lmax + t]);
+        if (r == j) d = a;
+        else off += a;
+    }
+    dom[j] = off > 0.0 ? d / off : (d > 0.0 ? INFINITY : 0.0);
+}
+
+template <class T>
+Err launch_col_dominance(int n, int lmax, const int32_t* Vrows, const T* Vvals,
+                         const int32_t* lcount, double* dom, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(col_dominance_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, lmax,
+                       Vrows, Vvals, lcount, dom);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
 #define INST(T)                                                                                  \
+    template Err launch_col_dominance<T>(int, int, const int32_t*, const T*, const int32_t*,     \
+                                         double*, hipStream_t);                                  \
     template Err launch_compact_v<T>(int, int, const int32_t*, const int32_t*, const int32_t*,  \
                                      const T*, int32_t*, T*, hipStream_t);                       \
     template Err csc_to_csr<T>(int, int64_t, const int32_t*, const int32_t*, const T*, int32_t*, \

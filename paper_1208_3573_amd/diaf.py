@@ -44,7 +44,7 @@ class diaf_spec(ctypes.Structure):
     _fields_ = [("w_kind", c_int32), ("w_topk", c_int32), ("w_explicit", POINTER(diaf_pattern)),
                 ("model", c_void_p), ("gate_tau", c_double), ("v_kind", c_int32),
                 ("v_count", c_int32), ("v_explicit", POINTER(diaf_pattern)),
-                ("gram_fp32", c_int32)]
+                ("gram_fp32", c_int32), ("gate_dom", c_double)]
 
 
 class diaf_view(ctypes.Structure):
@@ -225,7 +225,7 @@ MODES = {"unit_v": DIAF_UNIT_V, "unit_w": DIAF_UNIT_W}
 
 def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | None = None,
               v_explicit: DevicePattern | None = None, model=None, gate_tau=float("inf"),
-              gram_fp32=False):
+              gram_fp32=False, gate_dom=0.0):
     spec = diaf_spec()
     spec.w_kind = W_KINDS[w]
     spec.w_topk = w_topk
@@ -236,6 +236,7 @@ def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | 
     spec.v_count = v_count
     spec.v_explicit = ctypes.pointer(v_explicit.desc) if v_explicit is not None else None
     spec.gram_fp32 = int(bool(gram_fp32))
+    spec.gate_dom = gate_dom
     spec._keep = (w_explicit, v_explicit, model)
     return spec
 

@@ -2,7 +2,7 @@
 
 Every numerical step runs in libdiaf's kernels through the C ABI: the plain
 factorization that produces the labels (W pattern pattern(A^2), numerical
-dropping by tolerance 0.1 of |w_j(i)| ||A(:,i)||), the pair features, and
+dropping by a per-mode tolerance of |w_j(i)| ||A(:,i)||), the pair features, and
 the MLP forward/backward/Adam updates.  The host only generates the seeded
 training matrices and loops over them.
 
@@ -10,7 +10,10 @@ Training set: seeded 3D convection-diffusion problems on 48^3 grids
 (seeds 5000, 5001, ...), V = diagonal + top-4 lower rows, both norm modes.
 One Adam step per instance (the gradient over all its candidate pairs).
 The residual gate is 1.25 x the 99th percentile of the plain method's
-normalised residual r_j / s_j over the training set.
+normalised residual r_j / s_j over the training set; the stability gate
+rejects a proposal whose V column has |v_jj| below gate_dom times the sum of
+its off-diagonal magnitudes, with gate_dom half the 0.1 % quantile of that
+ratio for the plain method over the training set.
 
     python -m paper_1208_3573_amd.learned --mode unit_v --out weights.npz
 """
@@ -28,7 +31,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 WEIGHTS_DIR = os.path.join(_HERE, "weights")
 TRAIN_N = 48
 TRAIN_SEED0 = 5000
-LABEL_TAU = 0.1
+# dropping tolerance of the labels, per norm mode (unit-norm w concentrates w
+# on fewer entries, so it keeps entries down to a smaller fraction)
+LABEL_TAU = {"unit_v": 0.03, "unit_w": 0.01}
 
 
 def weights_path(mode: str) -> str:
@@ -54,37 +59,64 @@ def _block_fro(A, Jcp, Jri):
     return np.sqrt(out)
 
 
-def build_training_set(ctx, mode: str, n_instances: int, N: int = TRAIN_N, log=print):
-    """Features and labels of n_instances seeded problems, kept on the GPU."""
+def _dominance(H):
+    """|v_jj| / sum_{i != j} |v_ij| per column of V (host arrays)."""
+    n = len(H["Vcp"]) - 1
+    cp, ri, vv = H["Vcp"], H["Vri"], H["Vval"]
+    col = np.repeat(np.arange(n), np.diff(cp))
+    isd = ri == col
+    d = np.zeros(n)
+    d[col[isd]] = np.abs(vv[isd])
+    off = np.zeros(n)
+    np.add.at(off, col[~isd], np.abs(vv[~isd]))
+    return np.where(off > 0, d / np.maximum(off, 1e-300), np.inf)
+
+
+def gates_from(qs, doms):
+    """Residual and stability gates from the plain method's statistics."""
+    gate = 1.25 * float(np.percentile(np.concatenate(qs), 99))
+    gate_dom = 0.5 * float(np.quantile(np.concatenate(doms), 0.001))
+    return gate, gate_dom
+
+
+def build_training_set(ctx, mode: str, n_instances: int, N: int = TRAIN_N, log=print,
+                       with_data: bool = True, label_tau: float | None = None):
+    """Features and labels of n_instances seeded problems, kept on the GPU,
+    and the gates calibrated on the plain factorizations."""
     import torch
 
     import synth
     data = []
     qs = []
+    doms = []
     for t in range(n_instances):
         A = synth.convdiff(N, 3, TRAIN_SEED0 + t)
         dA = diaf.DeviceCSC.from_host(A)
         F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_lower", v_count=5), mode)
         H = F.to_host()
-        C = diaf.DevicePattern.from_host(H["Wcp"], H["Wri"])
-        npairs = len(H["Wri"])
-        feat = torch.empty(npairs * diaf.MLP_NFEAT, dtype=torch.float32, device="cuda")
-        diaf.diaf_features(ctx, dA, C, feat)
-        lab = torch.empty(npairs, dtype=torch.float32, device="cuda")
-        diaf.diaf_labels(ctx, dA, F, LABEL_TAU, lab)
         s = np.ones(A.n) if mode == "unit_v" else _block_fro(A, H["Wcp"], H["Wri"])
         qs.append(H["r"] / s)
-        data.append((feat, lab, npairs))
+        doms.append(_dominance(H))
+        if with_data:
+            C = diaf.DevicePattern.from_host(H["Wcp"], H["Wri"])
+            npairs = len(H["Wri"])
+            feat = torch.empty(npairs * diaf.MLP_NFEAT, dtype=torch.float32, device="cuda")
+            diaf.diaf_features(ctx, dA, C, feat)
+            lab = torch.empty(npairs, dtype=torch.float32, device="cuda")
+            diaf.diaf_labels(ctx, dA, F, LABEL_TAU[mode] if label_tau is None else label_tau,
+                             lab)
+            data.append((feat, lab, npairs))
         F.close()
         if (t + 1) % 10 == 0:
             log(f"  training data: {t + 1}/{n_instances} instances")
-    gate = 1.25 * float(np.percentile(np.concatenate(qs), 99))
-    return data, gate
+    gate, gate_dom = gates_from(qs, doms)
+    return data, gate, gate_dom
 
 
 def train(ctx, mode: str, n_instances: int = 100, epochs: int = 8, lr: float = 3e-3,
-          seed: int = 0, log=print):
-    data, gate = build_training_set(ctx, mode, n_instances, log=log)
+          seed: int = 0, log=print, label_tau: float | None = None):
+    data, gate, gate_dom = build_training_set(ctx, mode, n_instances, log=log,
+                                              label_tau=label_tau)
     model = diaf.Model(ctx, init_params(seed))
     rng = np.random.default_rng(seed)
     hist = []
@@ -98,19 +130,21 @@ def train(ctx, mode: str, n_instances: int = 100, epochs: int = 8, lr: float = 3
             losses.append(diaf.diaf_mlp_train_step(ctx, model, feat, lab, npairs, step_lr))
         hist.append(float(np.mean(losses)))
         log(f"  epoch {ep}: mean loss {hist[-1]:.5f}")
-    log(f"  training: {time.perf_counter() - t0:.1f} s, gate {gate:.3e}")
-    return model, gate, hist
+    log(f"  training: {time.perf_counter() - t0:.1f} s, gate {gate:.3e}, gate_dom {gate_dom:.3f}")
+    return model, gate, gate_dom, hist
 
 
-def save(model, gate, mode, path, hist=()):
+def save(model, gate, gate_dom, mode, path, hist=()):
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
-    np.savez(path, params=model.params(), gate_tau=np.float64(gate), mode=mode,
+    np.savez(path, params=model.params(), gate_tau=np.float64(gate),
+             gate_dom=np.float64(gate_dom), mode=mode,
              loss_history=np.asarray(hist, dtype=np.float64))
 
 
 def load(ctx, path):
+    """(model, gate_tau, gate_dom) from a weights file."""
     z = np.load(path, allow_pickle=False)
-    return diaf.Model(ctx, z["params"]), float(z["gate_tau"])
+    return diaf.Model(ctx, z["params"]), float(z["gate_tau"]), float(z["gate_dom"])
 
 
 def load_or_train(ctx, mode: str, log=print, n_instances: int = 100):
@@ -118,8 +152,20 @@ def load_or_train(ctx, mode: str, log=print, n_instances: int = 100):
     if os.path.exists(path):
         log(f"  loading {path}")
         return load(ctx, path)
-    model, gate, hist = train(ctx, mode, n_instances=n_instances, log=log)
-    return model, gate
+    model, gate, gate_dom, hist = train(ctx, mode, n_instances=n_instances, log=log)
+    save(model, gate, gate_dom, mode, path, hist)
+    return model, gate, gate_dom
+
+
+def recalibrate(ctx, mode: str, path: str, n_instances: int = 100, log=print):
+    """Recompute both gates of a weights file from the plain method on the
+    training instances (the network is left as it is)."""
+    z = dict(np.load(path, allow_pickle=False))
+    _, gate, gate_dom = build_training_set(ctx, mode, n_instances, log=log, with_data=False)
+    z["gate_tau"] = np.float64(gate)
+    z["gate_dom"] = np.float64(gate_dom)
+    np.savez(path, **z)
+    log(f"  {path}: gate {gate:.4e}, gate_dom {gate_dom:.4f}")
 
 
 def main():
@@ -128,10 +174,19 @@ def main():
     ap.add_argument("--instances", type=int, default=100)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--label-tau", type=float, default=None,
+                    help="dropping tolerance of the labels (default: per mode)")
+    ap.add_argument("--recalibrate", action="store_true",
+                    help="only recompute the gates of an existing weights file")
     args = ap.parse_args()
     ctx = diaf.Context(0)
-    model, gate, hist = train(ctx, args.mode, args.instances, args.epochs)
-    save(model, gate, args.mode, args.out or weights_path(args.mode), hist)
+    path = args.out or weights_path(args.mode)
+    if args.recalibrate:
+        recalibrate(ctx, args.mode, path, args.instances)
+        return
+    model, gate, gate_dom, hist = train(ctx, args.mode, args.instances, args.epochs,
+                                        label_tau=args.label_tau)
+    save(model, gate, gate_dom, args.mode, path, hist)
 
 
 if __name__ == "__main__":

@@ -137,3 +137,53 @@ def test_gate_limits(ctx):
     for F in (plain, Fz, Fi):
         F.close()
     m.close()
+
+
+@pytest.mark.parametrize("mode", ["unit_v", "unit_w"])
+def test_trained_proposer_with_partial_fallback(ctx, mode):
+    """The committed network on a held-out 3D problem (24^3, seed 77): the
+    columns whose proposal fails a gate are refactored with pattern(A^2) and
+    merged with the accepted ones.  The merged W and V must reproduce every
+    stored residual ||A w_j - v_j|| on the host, every column whose proposal
+    was accepted must pass both gates, and the preconditioned BiCGSTAB must
+    converge.  With an unreachable dominance gate every column with an
+    off-diagonal V entry falls back."""
+    import scipy.sparse as sp
+    import torch
+    from paper_1208_3573_amd import diaf
+    from paper_1208_3573_amd import learned as LR
+    A = synth.convdiff(24, 3, 77)
+    dA = diaf.DeviceCSC.from_host(A)
+    model, gate, gate_dom = LR.load(ctx, LR.weights_path(mode))
+    spec = diaf.make_spec(w="learned", v="topk_lower", v_count=5, model=model, gate_tau=gate,
+                          gate_dom=gate_dom)
+    F = diaf.diaf_factor(ctx, dA, spec, mode)
+    H = F.to_host()
+    n = A.n
+    W = sp.csc_matrix((H["Wval"], H["Wri"], H["Wcp"]), shape=(n, n))
+    V = sp.csc_matrix((H["Vval"], H["Vri"], H["Vcp"]), shape=(n, n))
+    R = (A.to_scipy().tocsc() @ W - V).tocsc()
+    rh = np.sqrt(np.asarray(R.multiply(R).sum(axis=0)).ravel())
+    assert np.max(np.abs(rh - H["r"])) <= 1e-12 * (1.0 + np.max(H["r"]))
+    fb = (H["flags"] & diaf.FLAG_FELL_BACK) != 0
+    s = np.ones(n) if mode == "unit_v" else LR._block_fro(A, H["Wcp"], H["Wri"])
+    acc = ~fb
+    assert np.all(H["r"][acc] / s[acc] <= gate)
+    assert np.all(LR._dominance(H)[acc] >= gate_dom)
+    say(f"{mode}: fell back {int(fb.sum())} of {n}, nnz(W) {len(H['Wri'])}")
+    b = torch.from_numpy(synth.rhs_ones(A)).cuda()
+    x = torch.zeros_like(b)
+    info = diaf.diaf_solve(ctx, dA, F, b, x, 1e-8, 1000)
+    assert info.flag == 0 and info.relres_true <= 1e-7
+    F.close()
+    spec_all = diaf.make_spec(w="learned", v="topk_lower", v_count=5, model=model, gate_tau=gate,
+                              gate_dom=1e300)
+    Fa = diaf.diaf_factor(ctx, dA, spec_all, mode)
+    Ha = Fa.to_host()
+    kept = (Ha["flags"] & diaf.FLAG_FELL_BACK) == 0
+    # only columns whose V column has no off-diagonal entry (infinitely
+    # dominant) can pass an unreachable dominance gate
+    assert np.all(np.isinf(LR._dominance(Ha)[kept]))
+    assert kept.sum() < n // 100
+    Fa.close()
+    model.close()
