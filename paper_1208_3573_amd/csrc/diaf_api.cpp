@@ -22,7 +22,10 @@ struct diaf_ctx {
     int64_t opt_generic_only = 0;
     int64_t opt_batch = 8;
     int64_t opt_gate_small_diag = 1;
+    int64_t opt_graph = 0;
     diaf::TrsvTune trsv;
+    diaf::FactorTune ftune;
+    hipStream_t gstream = nullptr;  // library stream for captured solve batches
 };
 
 struct diaf_model {
@@ -358,7 +361,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             DIAF_HIP_TRY(hipEventCreate(&e0));
             DIAF_HIP_TRY(hipEventCreate(&e1));
             DIAF_HIP_TRY(hipEventRecord(e0, st));
-            DIAF_TRY(launch_factor_small<T>(fa, defl, ndef, st));
+            DIAF_TRY(launch_factor_small<T>(fa, defl, ndef, ctx->ftune, st));
             DIAF_HIP_TRY(hipEventRecord(e1, st));
             events.push_back({e0, e1});
             ++nb;
@@ -396,7 +399,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         DIAF_HIP_TRY(hipEventCreate(&e0));
         DIAF_HIP_TRY(hipEventCreate(&e1));
         DIAF_HIP_TRY(hipEventRecord(e0, st));
-        DIAF_TRY(launch_factor_generic<T>(fa, b.kcap, b.tcap, F->lmax, gm, nslots, st));
+        DIAF_TRY(launch_factor_generic<T>(fa, b.kcap, b.tcap, F->lmax, gm, nslots, ctx->ftune, st));
         DIAF_HIP_TRY(hipEventRecord(e1, st));
         events.push_back({e0, e1});
     }
@@ -522,11 +525,11 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
     return {};
 }
 
-// t = V^{-1} x ; y = W t   (all on the context stream, no host sync)
+// t = V^{-1} x ; y = W t   (all on stream st, no host sync)
 template <class T>
-Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done)
+Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done,
+                  hipStream_t st)
 {
-    hipStream_t st = ctx->stream;
     const int n = (int)F->n;
     if (F->vtri == 0)
         DIAF_TRY(launch_diag_solve<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, x, (T*)F->tmp, done, st));
@@ -562,7 +565,12 @@ diaf_status diaf_ctx_create(diaf_ctx** ctx, int device, void* hip_stream)
     return DIAF_OK;
 }
 
-void diaf_ctx_destroy(diaf_ctx* ctx) { delete ctx; }
+void diaf_ctx_destroy(diaf_ctx* ctx)
+{
+    if (!ctx) return;
+    if (ctx->gstream) (void)hipStreamDestroy(ctx->gstream);
+    delete ctx;
+}
 
 const char* diaf_last_error(const diaf_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
@@ -574,6 +582,7 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     else if (k == "solve_batch") ctx->opt_batch = value < 1 ? 1 : value;
     else if (k == "trsv_backoff") ctx->trsv.backoff = value ? 1 : 0;
     else if (k == "gate_small_diag") ctx->opt_gate_small_diag = value ? 1 : 0;
+    else if (k == "graph") ctx->opt_graph = value ? 1 : 0;
     else if (k == "trsv_rows_per_lane") {
         if (value != 1 && value != 2 && value != 4)
             return fail(ctx, DIAF_EINVAL, "trsv_rows_per_lane must be 1, 2 or 4");
@@ -683,9 +692,9 @@ diaf_status diaf_apply(diaf_ctx* ctx, const diaf_factors* Fc, const void* x, voi
         return fail(ctx, DIAF_ESINGULAR, std::to_string(F->stats.count_zero_pivot) +
                                              " zero or non-finite pivots in V");
     if (F->dtype == DIAF_F64)
-        e = enqueue_apply<double>(ctx, F, (const double*)x, (double*)y, nullptr);
+        e = enqueue_apply<double>(ctx, F, (const double*)x, (double*)y, nullptr, ctx->stream);
     else
-        e = enqueue_apply<zc>(ctx, F, (const zc*)x, (zc*)y, nullptr);
+        e = enqueue_apply<zc>(ctx, F, (const zc*)x, (zc*)y, nullptr, ctx->stream);
     if (e.code) return fail(ctx, e);
     if (F->stats.count_zero_pivot)
         return fail(ctx, DIAF_ESINGULAR, std::to_string(F->stats.count_zero_pivot) +
@@ -913,7 +922,17 @@ template <class T>
 Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T* x, double rtol,
                int maxit, diaf_solve_info* info)
 {
+    // With graphs on, the iterations run on a library stream (the caller's
+    // may be the null stream, which cannot be captured): first wait for the
+    // caller's work, then everything below is ordered on that stream and the
+    // call returns after it has drained.
+    const bool use_graph = ctx->opt_graph && F != nullptr;
     hipStream_t st = ctx->stream;
+    if (use_graph) {
+        if (!ctx->gstream) DIAF_HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+        DIAF_TRY(sync(ctx->stream));
+        st = ctx->gstream;
+    }
     const int n = (int)A->n;
     auto t0 = std::chrono::steady_clock::now();
     if (F) {
@@ -955,21 +974,47 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     DIAF_TRY(bicg_init<T>(V, rtol, maxit, st));
     BicgState<T> hs{};
     const int batch = (int)ctx->opt_batch;
-    for (int it0 = 0;; it0 += batch) {
+    // one batch of iterations; every stage returns at once after convergence
+    const auto enqueue_batch = [&]() -> Err {
         for (int q = 0; q < batch; ++q) {
             DIAF_TRY(bicg_rho<T>(V, st));
             DIAF_TRY(bicg_update_p<T>(V, st));
-            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.p, V.ph, done));
+            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.p, V.ph, done, st));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.ph, V.p, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
             DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.ph, V.v, done, st));
             DIAF_TRY(bicg_alpha<T>(V, st));
             DIAF_TRY(bicg_s<T>(V, st));
-            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.s, V.sh, done));
+            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.s, V.sh, done, st));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.sh, V.s, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
             DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.sh, V.t, done, st));
             DIAF_TRY(bicg_omega<T>(V, st));
             DIAF_TRY(bicg_xr<T>(V, st));
         }
+        return {};
+    };
+    // captured once, replayed per batch (kernels only: no memset or copy nodes)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct GraphFree {
+        hipGraph_t* g; hipGraphExec_t* e;
+        ~GraphFree() {
+            if (*e) (void)hipGraphExecDestroy(*e);
+            if (*g) (void)hipGraphDestroy(*g);
+        }
+    } gfree{&graph, &gexec};
+    if (use_graph) {
+        DIAF_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        Err e = enqueue_batch();
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        graph = g;
+        DIAF_TRY(e);
+        DIAF_HIP_TRY(ec);
+        DIAF_HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+    for (int it0 = 0;; it0 += batch) {
+        if (use_graph) DIAF_HIP_TRY(hipGraphLaunch(gexec, st));
+        else DIAF_TRY(enqueue_batch());
         DIAF_TRY(read1(V.st, &hs, st));
         if (F && F->vtri != 0) {
             TrsvCtl c{};

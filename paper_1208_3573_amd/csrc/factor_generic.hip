@@ -859,11 +859,12 @@ struct GenPlan {
 };
 
 template <class T>
-GenPlan generic_plan(int kcap, int tcap, int lcap, int mode)
+GenPlan generic_plan(int kcap, int tcap, int lcap, int mode, int nt_override = 0)
 {
     GenPlan P{};
     P.nmats = mode == 0 ? 1 : 3;
     P.nt = kcap <= 32 ? 64 : GNT;
+    if (nt_override == 64 || nt_override == 128 || nt_override == GNT) P.nt = nt_override;
     size_t with = generic_lds_bytes<T>(kcap, tcap, lcap, P.nmats);
     size_t without = generic_lds_bytes<T>(kcap, tcap, lcap, 0);
     if (with <= 64 * 1024) {
@@ -887,13 +888,13 @@ size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots)
 
 template <class T>
 Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, void* gws,
-                          int nslots, hipStream_t st)
+                          int nslots, FactorTune tune, hipStream_t st)
 {
     if (A.ncols == 0) return {};
     if (tcap > 65535) return {DIAF_EUNSUPPORTED, "column too large"};
     int tcap2 = 1;
     while (tcap2 < tcap) tcap2 <<= 1;
-    GenPlan P = generic_plan<T>(kcap, tcap, lcap, A.mode);
+    GenPlan P = generic_plan<T>(kcap, tcap, lcap, A.mode, tune.generic_nt);
     int grid = A.ncols;
     if (!(P.in_lds && !P.need_gmats)) {
         if (!gws) return {DIAF_EINVAL, "generic factor: workspace missing"};
@@ -918,8 +919,9 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
 }
 
 template Err launch_factor_generic<double>(const FactorArgs<double>&, int, int, int, void*, int,
-                                           hipStream_t);
-template Err launch_factor_generic<zc>(const FactorArgs<zc>&, int, int, int, void*, int, hipStream_t);
+                                           FactorTune, hipStream_t);
+template Err launch_factor_generic<zc>(const FactorArgs<zc>&, int, int, int, void*, int, FactorTune,
+                                       hipStream_t);
 template size_t generic_global_bytes<double>(int, int, int, int, int);
 template size_t generic_global_bytes<zc>(int, int, int, int, int);
 

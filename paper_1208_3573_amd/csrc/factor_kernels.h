@@ -24,15 +24,21 @@ Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int
 // ---- factoring (factor_generic.hip, factor_small.hip) ----
 // gws: global workspace of generic_global_bytes(...) bytes (may be null when
 // that is 0); nslots = number of blocks sharing it.
+// Launch shapes chosen by the autotuner (0 = built-in choice).
+struct FactorTune {
+    int small_grid = 0;  // workgroups of the one-wave kernel (persistent over columns)
+    int generic_nt = 0;  // threads per column of the generic kernel (64, 128 or 256)
+};
 template <class T>
 Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, void* gws,
-                          int nslots, hipStream_t st);
+                          int nslots, FactorTune tune, hipStream_t st);
 template <class T>
 size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots);
 // One-wave kernel for unit-norm v and |J_j| <= 32, shadow <= 64, gathered
 // entries <= 256, |L_j| <= 8; other columns are appended to deferred.
 template <class T>
-Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, hipStream_t st);
+Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, FactorTune tune,
+                        hipStream_t st);
 
 // ---- assembly and sparse utilities (sparse.hip) ----
 // Exclusive scan of n ints into out[n+1] (out[n] = total); temp via hipcub.

@@ -726,10 +726,12 @@ __global__ void __launch_bounds__(64) factor_small_kernel(FactorArgs<T> A, int* 
 }
 
 template <class T>
-Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, hipStream_t st)
+Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, FactorTune tune,
+                        hipStream_t st)
 {
     if (A.ncols == 0) return {};
-    const int grid = A.ncols < 256 * 16 ? A.ncols : 256 * 16;
+    const int want = tune.small_grid > 0 ? tune.small_grid : 256 * 16;
+    const int grid = A.ncols < want ? A.ncols : want;
     if (A.mode == 0)
         hipLaunchKernelGGL((factor_small_kernel<T, 0>), dim3(grid), dim3(64), 0, st, A, deferred,
                            ndeferred);
@@ -740,7 +742,8 @@ Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, h
     return {};
 }
 
-template Err launch_factor_small<double>(const FactorArgs<double>&, int*, int*, hipStream_t);
-template Err launch_factor_small<zc>(const FactorArgs<zc>&, int*, int*, hipStream_t);
+template Err launch_factor_small<double>(const FactorArgs<double>&, int*, int*, FactorTune,
+                                         hipStream_t);
+template Err launch_factor_small<zc>(const FactorArgs<zc>&, int*, int*, FactorTune, hipStream_t);
 
 }  // namespace diaf

@@ -1,5 +1,5 @@
 // Sparse utilities: scans, V assembly (padded columns -> CSC), CSC -> CSR
-// transposes, input validation and per-column statistics.
+// transposes (stable radix sort by row), input validation and per-column statistics.
 #include <hipcub/hipcub.hpp>
 
 #include "dcommon.h"
@@ -72,36 +72,34 @@ __global__ void row_count_kernel(int64_t nnz, const int32_t* ri, int32_t* cnt)
     if (p < nnz) atomicAdd(&cnt[ri[p]], 1);
 }
 
-template <class T>
-__global__ void scatter_csr_kernel(int n, const int32_t* cp, const int32_t* ri, const T* val,
-                                   const int32_t* rp, int32_t* fill, int32_t* ci, T* cval)
+__global__ void iota_kernel(int64_t nnz, int32_t* v)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
-    for (int p = cp[j]; p < cp[j + 1]; ++p) {
-        int i = ri[p];
-        int q = rp[i] + atomicAdd(&fill[i], 1);
-        ci[q] = j;
-        cval[q] = val[p];
-    }
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) v[p] = (int32_t)p;
 }
 
+// Entry q of the CSR result comes from CSC position perm[q]; its column is
+// found by a binary search in the column pointers.
 template <class T>
-__global__ void sort_rows_kernel(int n, const int32_t* rp, int32_t* ci, T* cval)
+__global__ void gather_csr_kernel(int n, int64_t nnz, const int32_t* cp, const T* val,
+                                  const int32_t* perm, int32_t* ci, T* cval)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int b = rp[i], e = rp[i + 1];
-    for (int p = b + 1; p < e; ++p) {
-        int key = ci[p];
-        T v = cval[p];
-        int q = p - 1;
-        while (q >= b && ci[q] > key) { ci[q + 1] = ci[q]; cval[q + 1] = cval[q]; --q; }
-        ci[q + 1] = key;
-        cval[q + 1] = v;
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnz) return;
+    const int32_t p = perm[q];
+    int lo = 0, hi = n - 1;  // last column j with cp[j] <= p
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cp[mid] <= p) lo = mid;
+        else hi = mid - 1;
     }
+    ci[q] = lo;
+    cval[q] = val[p];
 }
 
+// CSC -> CSR: row counts and their scan give the row pointers; a stable
+// radix sort of the entries by row (CSC order already has the columns
+// ascending within every row, and stability keeps them so) gives the order.
 template <class T>
 Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T* val,
                int32_t* rp, int32_t* ci, T* cval, hipStream_t st)
@@ -113,13 +111,30 @@ Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T
         hipLaunchKernelGGL(row_count_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
                            nnz, ri, cnt);
     DIAF_TRY(exclusive_scan_i32(cnt, rp, n, st));
-    DIAF_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), st));
-    hipLaunchKernelGGL(scatter_csr_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, cp, ri,
-                       val, rp, cnt, ci, cval);
-    hipLaunchKernelGGL(sort_rows_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, rp, ci,
-                       cval);
-    DIAF_HIP_TRY(hipGetLastError());
     DIAF_HIP_TRY(hipFreeAsync(cnt, st));
+    if (nnz == 0) return {};
+    int32_t *kout = nullptr, *vin = nullptr, *vout = nullptr;
+    DIAF_HIP_TRY(hipMallocAsync((void**)&kout, sizeof(int32_t) * nnz, st));
+    DIAF_HIP_TRY(hipMallocAsync((void**)&vin, sizeof(int32_t) * nnz, st));
+    DIAF_HIP_TRY(hipMallocAsync((void**)&vout, sizeof(int32_t) * nnz, st));
+    const unsigned blocks = (unsigned)((nnz + 255) / 256);
+    hipLaunchKernelGGL(iota_kernel, dim3(blocks), dim3(256), 0, st, nnz, vin);
+    int bits = 1;
+    while ((1ll << bits) < (int64_t)n) ++bits;
+    size_t tmp_bytes = 0;
+    DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, ri, kout, vin, vout,
+                                                    (int)nnz, 0, bits, st));
+    void* tmp = nullptr;
+    DIAF_HIP_TRY(hipMallocAsync(&tmp, tmp_bytes, st));
+    DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, ri, kout, vin, vout, (int)nnz,
+                                                    0, bits, st));
+    hipLaunchKernelGGL(gather_csr_kernel<T>, dim3(blocks), dim3(256), 0, st, n, nnz, cp, val, vout,
+                       ci, cval);
+    DIAF_HIP_TRY(hipGetLastError());
+    DIAF_HIP_TRY(hipFreeAsync(tmp, st));
+    DIAF_HIP_TRY(hipFreeAsync(kout, st));
+    DIAF_HIP_TRY(hipFreeAsync(vin, st));
+    DIAF_HIP_TRY(hipFreeAsync(vout, st));
     return {};
 }
 
