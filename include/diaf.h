@@ -177,8 +177,31 @@ typedef struct diaf_solve_info {
 diaf_status diaf_ctx_create(struct diaf_ctx** ctx, int device, void* hip_stream);
 void diaf_ctx_destroy(struct diaf_ctx* ctx);
 const char* diaf_last_error(const struct diaf_ctx* ctx);
-/* Select the factor kernel family: 0 automatic, 1 generic only. */
+/* Tunables of the context (not of the method: results are identical for
+ * every setting).  Keys:
+ *   "generic_only"       1: every column goes to the generic factor kernel
+ *   "small_grid"         workgroups of the one-wave factor kernel (0 = 4096)
+ *   "generic_nt"         threads per column of the generic kernel (0 auto, 64,
+ *                        128, 256)
+ *   "solve_batch"        BiCGSTAB iterations between host polls (>= 1)
+ *   "graph"              1: replay each batch from one captured hipGraph
+ *   "trsv_backoff"       1: a waiting triangular-solve wave sleeps between polls
+ *   "trsv_rows_per_lane" 1, 2 or 4 rows per lane in the triangular solve
+ *   "gate_small_diag"    1: the learned path also rejects proposals whose V
+ *                        diagonal entry is flagged negligible
+ * DIAF_EINVAL for an unknown key or value.  get_option reads a value. */
 diaf_status diaf_ctx_set_option(struct diaf_ctx* ctx, const char* key, int64_t value);
+diaf_status diaf_ctx_get_option(const struct diaf_ctx* ctx, const char* key, int64_t* value);
+
+/* Autotuner for the batched factoring and the solve: times the candidate
+ * launch shapes on this problem (A, spec, mode, as for diaf_factor) and keeps
+ * the fastest in ctx: "small_grid" (1024 ... 16384), "generic_nt" (when
+ * generic buckets occur), then "graph", "solve_batch" and "trsv_backoff" by
+ * the wall time per iteration of 32-iteration solves with b = ones.  Runs
+ * about a dozen factorizations and solves; blocks until done.  Leaves the
+ * method's results unchanged. */
+diaf_status diaf_autotune(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
+                          int32_t mode);
 
 /* ---- patterns (Section 4) ------------------------------------------------ */
 

@@ -574,6 +574,22 @@ void diaf_ctx_destroy(diaf_ctx* ctx)
 
 const char* diaf_last_error(const diaf_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
 
+diaf_status diaf_ctx_get_option(const diaf_ctx* ctx, const char* key, int64_t* value)
+{
+    if (!ctx || !key || !value) return DIAF_EINVAL;
+    std::string k(key);
+    if (k == "generic_only") *value = ctx->opt_generic_only;
+    else if (k == "solve_batch") *value = ctx->opt_batch;
+    else if (k == "trsv_backoff") *value = ctx->trsv.backoff;
+    else if (k == "trsv_rows_per_lane") *value = ctx->trsv.rows_per_lane;
+    else if (k == "gate_small_diag") *value = ctx->opt_gate_small_diag;
+    else if (k == "graph") *value = ctx->opt_graph;
+    else if (k == "small_grid") *value = ctx->ftune.small_grid;
+    else if (k == "generic_nt") *value = ctx->ftune.generic_nt;
+    else return DIAF_EINVAL;
+    return DIAF_OK;
+}
+
 diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
 {
     if (!ctx || !key) return DIAF_EINVAL;
@@ -583,6 +599,12 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     else if (k == "trsv_backoff") ctx->trsv.backoff = value ? 1 : 0;
     else if (k == "gate_small_diag") ctx->opt_gate_small_diag = value ? 1 : 0;
     else if (k == "graph") ctx->opt_graph = value ? 1 : 0;
+    else if (k == "small_grid") ctx->ftune.small_grid = value < 0 ? 0 : (int)value;
+    else if (k == "generic_nt") {
+        if (value != 0 && value != 64 && value != 128 && value != 256)
+            return fail(ctx, DIAF_EINVAL, "generic_nt must be 0, 64, 128 or 256");
+        ctx->ftune.generic_nt = (int)value;
+    }
     else if (k == "trsv_rows_per_lane") {
         if (value != 1 && value != 2 && value != 4)
             return fail(ctx, DIAF_EINVAL, "trsv_rows_per_lane must be 1, 2 or 4");
@@ -1038,6 +1060,99 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     return {};
 }
 
+// Autotuner: times the candidate launch shapes on the caller's own problem
+// and keeps the fastest in the context.  Factor: persistent grid of the
+// one-wave kernel, then (when generic buckets occur) threads per column of
+// the generic kernel, each by the factor kernels' event time (best of 2).
+// Solve: graph replay, iterations per host poll and polling back-off, by the
+// wall time per iteration of 32-iteration solves after a warm-up solve.
+template <class T>
+Err autotune_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode)
+{
+    const int n = (int)A->n;
+    int launches = 0;
+    const auto time_factor = [&](double& best) -> Err {
+        best = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
+            diaf_factors* F = nullptr;
+            DIAF_TRY(factor_impl<T>(ctx, A, spec, mode, &F));
+            best = std::min(best, (double)F->stats.ms_factor_kernels);
+            launches = F->stats.factor_launches;
+            free_factors(F);
+        }
+        return {};
+    };
+    {
+        const int grids[] = {1024, 2048, 4096, 8192, 16384};
+        double best = INFINITY;
+        int pick = 0;
+        for (int g : grids) {
+            ctx->ftune.small_grid = g;
+            double ms;
+            DIAF_TRY(time_factor(ms));
+            if (ms < best) { best = ms; pick = g; }
+        }
+        ctx->ftune.small_grid = pick;
+    }
+    if (launches >= 2 || ctx->opt_generic_only || spec->gram_fp32) {
+        const int nts[] = {0, 64, 128, 256};
+        double best = INFINITY;
+        int pick = 0;
+        for (int t : nts) {
+            ctx->ftune.generic_nt = t;
+            double ms;
+            DIAF_TRY(time_factor(ms));
+            if (ms < best) { best = ms; pick = t; }
+        }
+        ctx->ftune.generic_nt = pick;
+    }
+    // solve
+    diaf_factors* F = nullptr;
+    DIAF_TRY(factor_impl<T>(ctx, A, spec, mode, &F));
+    std::unique_ptr<diaf_factors, void (*)(diaf_factors*)> Fh(F, free_factors);
+    T *b = nullptr, *x = nullptr;
+    DIAF_TRY(dmalloc(&b, sizeof(T) * (size_t)n));
+    DIAF_TRY(dmalloc(&x, sizeof(T) * (size_t)n));
+    struct VFree {
+        T** a; T** c;
+        ~VFree() { dfree(*a); dfree(*c); }
+    } vfree{&b, &x};
+    {
+        std::vector<T> ones((size_t)n, num<T>::one());
+        DIAF_HIP_TRY(hipMemcpy(b, ones.data(), sizeof(T) * (size_t)n, hipMemcpyHostToDevice));
+    }
+    const auto time_solve = [&](int maxit, double& ms_per_it) -> Err {
+        DIAF_HIP_TRY(hipMemsetAsync(x, 0, sizeof(T) * (size_t)n, ctx->stream));
+        DIAF_TRY(sync(ctx->stream));
+        diaf_solve_info info{};
+        DIAF_TRY(solve_impl<T>(ctx, A, F, b, x, 1e-300, maxit, &info));
+        ms_per_it = info.iters > 0 ? info.ms / info.iters : INFINITY;
+        return {};
+    };
+    double warm;
+    DIAF_TRY(time_solve(8, warm));  // first apply builds the CSR copies and levels
+    double best = INFINITY;
+    int pg = (int)ctx->opt_graph, pb = (int)ctx->opt_batch, po = ctx->trsv.backoff;
+    for (int g = 0; g < 2; ++g)
+        for (int bt : {8, 32})
+            for (int bo = 0; bo < 2; ++bo) {
+                ctx->opt_graph = g;
+                ctx->opt_batch = bt;
+                ctx->trsv.backoff = bo;
+                double ms = INFINITY;
+                for (int rep = 0; rep < 2; ++rep) {
+                    double t;
+                    DIAF_TRY(time_solve(32, t));
+                    ms = std::min(ms, t);
+                }
+                if (ms < best) { best = ms; pg = g; pb = bt; po = bo; }
+            }
+    ctx->opt_graph = pg;
+    ctx->opt_batch = pb;
+    ctx->trsv.backoff = po;
+    return {};
+}
+
 }  // namespace
 
 extern "C" diaf_status diaf_solve(diaf_ctx* ctx, const diaf_csc* A, const diaf_factors* F,
@@ -1058,6 +1173,21 @@ extern "C" diaf_status diaf_solve(diaf_ctx* ctx, const diaf_csc* A, const diaf_f
     if (info->flag == 1) return fail(ctx, DIAF_ENOCONV, "BiCGSTAB: no convergence within maxit");
     if (info->flag == 2) return fail(ctx, DIAF_EBREAKDOWN, "BiCGSTAB: breakdown");
     if (info->flag == 3) return fail(ctx, DIAF_ESINGULAR, "V has a zero or non-finite pivot");
+    return DIAF_OK;
+}
+
+extern "C" diaf_status diaf_autotune(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
+                                     int32_t mode)
+{
+    if (!ctx) return DIAF_EINVAL;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!spec) return fail(ctx, DIAF_EINVAL, "spec is NULL");
+    if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return fail(ctx, DIAF_EINVAL, "bad norm mode");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    e = A->dtype == DIAF_F64 ? autotune_impl<double>(ctx, A, spec, mode)
+                             : autotune_impl<zc>(ctx, A, spec, mode);
+    if (e.code) return fail(ctx, e);
     return DIAF_OK;
 }
 

@@ -76,6 +76,8 @@ _SIGS = {
     "diaf_ctx_destroy": (None, [c_void_p]),
     "diaf_last_error": (ctypes.c_char_p, [c_void_p]),
     "diaf_ctx_set_option": (c_int, [c_void_p, ctypes.c_char_p, c_int64]),
+    "diaf_ctx_get_option": (c_int, [c_void_p, ctypes.c_char_p, POINTER(c_int64)]),
+    "diaf_autotune": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_spec), c_int32]),
     "diaf_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t]),
     "diaf_pattern_build": (c_int, [c_void_p, POINTER(diaf_csc), c_int32, c_int32, c_void_p,
                                    c_void_p, POINTER(c_int64)]),
@@ -157,6 +159,11 @@ class Context:
 
     def set_option(self, key: str, value: int):
         self.check(self.lib.diaf_ctx_set_option(self.h, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = c_int64()
+        self.check(self.lib.diaf_ctx_get_option(self.h, key.encode(), ctypes.byref(v)))
+        return int(v.value)
 
     def copy(self, dst_ptr: int, src_ptr: int, nbytes: int):
         self.check(self.lib.diaf_copy(self.h, c_void_p(dst_ptr), c_void_p(src_ptr), nbytes))
@@ -299,6 +306,14 @@ def diaf_factor(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode) -> Factors:
     ctx.check(ctx.lib.diaf_factor(ctx.h, ctypes.byref(A.desc), ctypes.byref(spec), m,
                                   ctypes.byref(h)))
     return Factors(ctx, h, A)
+
+
+def diaf_autotune(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode) -> dict:
+    """Tune the context's launch shapes on this problem; returns the choices."""
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    ctx.check(ctx.lib.diaf_autotune(ctx.h, ctypes.byref(A.desc), ctypes.byref(spec), m))
+    return {k: ctx.get_option(k) for k in ("small_grid", "generic_nt", "graph", "solve_batch",
+                                           "trsv_backoff")}
 
 
 def diaf_apply(ctx: Context, F: Factors, x, y):

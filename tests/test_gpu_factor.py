@@ -164,3 +164,30 @@ def test_invalid_inputs_are_rejected(ctx):
     with pytest.raises(diaf.DiafError) as ei:
         diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A", v="topk_lower", v_count=0), "unit_v")
     assert ei.value.code == diaf.DIAF_EINVAL
+
+
+@pytest.mark.parametrize("mode", ["unit_v", "unit_w"])
+def test_autotune_keeps_results(ctx, mode):
+    """The autotuner only changes launch shapes: after tuning, the factors are
+    bit-identical to those with the built-in shapes, and every choice is one
+    of the candidates."""
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(16, 3, 21)
+    dA = diaf.DeviceCSC.from_host(A)
+    spec = diaf.make_spec(w="A2", v="topk_lower", v_count=5)
+    ref = diaf.diaf_factor(ctx, dA, spec, mode)
+    R = ref.to_host()
+    ref.close()
+    tuned = diaf.diaf_autotune(ctx, dA, spec, mode)
+    say(f"{mode}: {tuned}")
+    assert tuned["small_grid"] in (1024, 2048, 4096, 8192, 16384)
+    assert tuned["generic_nt"] in (0, 64, 128, 256)
+    assert tuned["graph"] in (0, 1) and tuned["solve_batch"] in (8, 32)
+    F = diaf.diaf_factor(ctx, dA, spec, mode)
+    H = F.to_host()
+    F.close()
+    for key in ("Wcp", "Wri", "Wval", "Vcp", "Vri", "Vval", "r", "flags"):
+        assert np.array_equal(R[key], H[key]), key
+    for k, v in (("small_grid", 0), ("generic_nt", 0), ("graph", 0), ("solve_batch", 8),
+                 ("trsv_backoff", 1)):
+        ctx.set_option(k, v)
