@@ -213,11 +213,46 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
     DIAF_TRY(launch_cand_count(n, A->colptr, A->rowidx, cnt, mx, st));
     int32_t maxcand = 0;
     DIAF_TRY(read1(mx, &maxcand, st));
+    // 1-hop rule: columns grouped by their number of two-hop candidates, so
+    // each launch sizes its LDS for its own class, not for the largest column
+    struct HopClass { int cand_max; std::vector<int32_t> cols; int32_t* dev = nullptr; };
+    std::vector<HopClass> hop;
+    struct HopFree {
+        std::vector<HopClass>* h;
+        ~HopFree() { for (auto& c : *h) dfree(c.dev); }
+    } hopfree{&hop};
+    if (w_kind == DIAF_W_A_1HOP_TOPK) {
+        std::vector<int32_t> tn(n);
+        DIAF_HIP_TRY(hipMemcpyAsync(tn.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        DIAF_TRY(sync(st));
+        for (int bound : {256 - w_topk - 1, 512 - w_topk - 1, 1024 - w_topk - 1, 2048 - w_topk - 1,
+                          4096 - w_topk - 1})
+            hop.push_back({bound, {}});
+        for (int j = 0; j < n; ++j) {
+            size_t c = 0;
+            while (c + 1 < hop.size() && tn[j] > hop[c].cand_max) ++c;
+            if (tn[j] > hop[c].cand_max)
+                return {DIAF_EUNSUPPORTED, "1-hop pattern: too many two-hop candidates in a column"};
+            hop[c].cols.push_back(j);
+        }
+        for (auto& c : hop) {
+            if (c.cols.empty()) continue;
+            DIAF_TRY(dmalloc(&c.dev, sizeof(int32_t) * c.cols.size()));
+            DIAF_HIP_TRY(hipMemcpyAsync(c.dev, c.cols.data(), sizeof(int32_t) * c.cols.size(),
+                                        hipMemcpyHostToDevice, st));
+        }
+    }
+    const auto run_1hop = [&](int32_t* cnt_out, const int32_t* Jcp_in, int32_t* rows_out) -> Err {
+        for (auto& c : hop)
+            DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk,
+                                            c.cand_max, c.dev, (int)c.cols.size(), cnt_out, Jcp_in,
+                                            rows_out, st));
+        return {};
+    };
     if (w_kind == DIAF_W_A2)
         DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, maxcand, cnt, nullptr, nullptr, st));
     else
-        DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk, maxcand,
-                                        cnt, nullptr, nullptr, st));
+        DIAF_TRY(run_1hop(cnt, nullptr, nullptr));
     DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
     int32_t tot = 0;
     DIAF_TRY(read1(Jcp + n, &tot, st));
@@ -231,8 +266,7 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
         if (w_kind == DIAF_W_A2)
             DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, maxcand, nullptr, Jcp, rows, st));
         else
-            DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk,
-                                            maxcand, nullptr, Jcp, rows, st));
+            DIAF_TRY(run_1hop(nullptr, Jcp, rows));
     }
     DIAF_TRY(sync(st));
     dfree(cnt);

@@ -15,8 +15,8 @@ Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand
 // pattern(A) plus the ptop two-hop rows of largest |A|^2 path weight.
 template <class T>
 Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
-                        int maxcand, int32_t* cnt, const int32_t* Jcp, int32_t* Jri,
-                        hipStream_t st);
+                        int cand_max, const int32_t* cols, int ncols, int32_t* cnt,
+                        const int32_t* Jcp, int32_t* Jri, hipStream_t st);
 // Per-column sizes for bucketing: k[j] = |J_j|, t[j] = sum nnz(A(:, J_j)).
 Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int32_t* Jri,
                         int32_t* kout, int32_t* tout, hipStream_t st);

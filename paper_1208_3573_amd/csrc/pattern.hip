@@ -192,8 +192,8 @@ Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand
 // scrow[cap] i32, red[nthreads+1] i32, sel[256] i32.
 template <class T>
 __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
-                                    int ptop, int cap, int32_t* cnt, const int32_t* Jcp,
-                                    int32_t* Jri)
+                                    int ptop, int cap, const int32_t* cols, int32_t* cnt,
+                                    const int32_t* Jcp, int32_t* Jri)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* keys = (uint64_t*)lds;
@@ -204,7 +204,7 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     int32_t* red = scrow + cap;
     int32_t* sel = red + blockDim.x + 1;
     __shared__ int32_t s_tot, s_nsel;
-    const int j = blockIdx.x;
+    const int j = cols[blockIdx.x];
     const int tid = threadIdx.x;
     const int a0 = Acp[j], na = Acp[j + 1] - a0;
     if (tid == 0) {
@@ -310,15 +310,17 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     for (int t = tid; t < tot; t += blockDim.x) out[t] = (int32_t)keys[t];
 }
 
+// cols: the columns of one size class, all with at most cand_max two-hop
+// candidates; the LDS buffers hold pow2(cand_max + ptop + 1) keys, enough for
+// the candidates and for the final merge of pattern(A(:, j)) with the picks.
 template <class T>
 Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
-                        int maxcand, int32_t* cnt, const int32_t* Jcp, int32_t* Jri,
-                        hipStream_t st)
+                        int cand_max, const int32_t* cols, int ncols, int32_t* cnt,
+                        const int32_t* Jcp, int32_t* Jri, hipStream_t st)
 {
-    if (n == 0) return {};
+    if (ncols == 0) return {};
     if (ptop > 256 || ptop < 0) return {DIAF_EUNSUPPORTED, "1-hop pattern: 0..256 extra rows"};
-    // the output merge also sorts na + ptop keys in the same buffer
-    int cap = pow2_at_least(maxcand + 257 < 256 ? 256 : maxcand + 257);
+    int cap = pow2_at_least(cand_max + ptop + 1 < 256 ? 256 : cand_max + ptop + 1);
     if (cap > 4096) return {DIAF_EUNSUPPORTED, "1-hop pattern: more than 3839 two-hop candidates in a column"};
     int nt = cap <= 512 ? 128 : 256;
     size_t lds = (sizeof(uint64_t) + 2 * sizeof(double) + 2 * sizeof(int32_t)) * cap +
@@ -326,15 +328,17 @@ Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* 
     auto kern = pattern_1hop_kernel<T>;
     DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
-    hipLaunchKernelGGL(kern, dim3(n), dim3(nt), lds, st, n, Acp, Ari, Aval, ptop, cap, cnt, Jcp,
-                       Jri);
+    hipLaunchKernelGGL(kern, dim3(ncols), dim3(nt), lds, st, n, Acp, Ari, Aval, ptop, cap, cols, cnt,
+                       Jcp, Jri);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
 
 template Err launch_pattern_1hop<double>(int, const int32_t*, const int32_t*, const double*, int,
-                                         int, int32_t*, const int32_t*, int32_t*, hipStream_t);
+                                         int, const int32_t*, int, int32_t*, const int32_t*,
+                                         int32_t*, hipStream_t);
 template Err launch_pattern_1hop<zc>(int, const int32_t*, const int32_t*, const zc*, int, int,
-                                     int32_t*, const int32_t*, int32_t*, hipStream_t);
+                                     const int32_t*, int, int32_t*, const int32_t*, int32_t*,
+                                     hipStream_t);
 
 }  // namespace diaf
