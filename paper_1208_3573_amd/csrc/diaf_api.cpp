@@ -616,6 +616,7 @@ diaf_status diaf_ctx_get_option(const diaf_ctx* ctx, const char* key, int64_t* v
     else if (k == "solve_batch") *value = ctx->opt_batch;
     else if (k == "trsv_backoff") *value = ctx->trsv.backoff;
     else if (k == "trsv_rows_per_lane") *value = ctx->trsv.rows_per_lane;
+    else if (k == "trsv_waves") *value = ctx->trsv.waves;
     else if (k == "gate_small_diag") *value = ctx->opt_gate_small_diag;
     else if (k == "graph") *value = ctx->opt_graph;
     else if (k == "small_grid") *value = ctx->ftune.small_grid;
@@ -638,6 +639,11 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
         if (value != 0 && value != 64 && value != 128 && value != 256)
             return fail(ctx, DIAF_EINVAL, "generic_nt must be 0, 64, 128 or 256");
         ctx->ftune.generic_nt = (int)value;
+    }
+    else if (k == "trsv_waves") {
+        if (value != 1 && value != 4 && value != 8 && value != 16)
+            return fail(ctx, DIAF_EINVAL, "trsv_waves must be 1, 4, 8 or 16");
+        ctx->trsv.waves = (int)value;
     }
     else if (k == "trsv_rows_per_lane") {
         if (value != 1 && value != 2 && value != 4)
@@ -1165,6 +1171,24 @@ Err autotune_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int m
     };
     double warm;
     DIAF_TRY(time_solve(8, warm));  // first apply builds the CSR copies and levels
+    {
+        // waves per workgroup of the triangular solve (rows per lane 1)
+        double bw = INFINITY;
+        int pw = ctx->trsv.waves;
+        for (int w : {1, 4, 8, 16}) {
+            if (num<T>::is_complex && w > 8) continue;
+            ctx->trsv.waves = w;
+            ctx->trsv.rows_per_lane = 1;
+            double ms = INFINITY;
+            for (int rep = 0; rep < 2; ++rep) {
+                double t;
+                DIAF_TRY(time_solve(32, t));
+                ms = std::min(ms, t);
+            }
+            if (ms < bw) { bw = ms; pw = w; }
+        }
+        ctx->trsv.waves = pw;
+    }
     double best = INFINITY;
     int pg = (int)ctx->opt_graph, pb = (int)ctx->opt_batch, po = ctx->trsv.backoff;
     for (int g = 0; g < 2; ++g)

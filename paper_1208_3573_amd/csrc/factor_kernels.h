@@ -95,6 +95,8 @@ Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, c
 struct TrsvTune {
     int rows_per_lane = 1;
     int backoff = 1;
+    int waves = 16;  // waves per workgroup sharing one chunk through LDS (1, 4, 8, 16;
+                     // complex values use at most 8)
 };
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,

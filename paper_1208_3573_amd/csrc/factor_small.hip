@@ -721,8 +721,22 @@ __global__ void __launch_bounds__(64) factor_small_kernel(FactorArgs<T> A, int* 
                                                           int* ndeferred)
 {
     __shared__ SmallLds<T, MODE> S;
-    for (int q = blockIdx.x; q < A.ncols; q += gridDim.x) small_column(A, A.cols[q], S, deferred,
-                                                                        ndeferred);
+    // Workgroups are dealt to the 8 XCDs round robin by index; each XCD takes
+    // a contiguous eighth of the column list, so neighbouring columns, which
+    // gather overlapping columns of A, share an L2.  (Any dispatch order is
+    // correct; this one only helps locality.)
+    constexpr int NX = 8;
+    const int nper = gridDim.x / NX;
+    if (nper == 0) {
+        for (int q = blockIdx.x; q < A.ncols; q += gridDim.x)
+            small_column(A, A.cols[q], S, deferred, ndeferred);
+        return;
+    }
+    if ((int)blockIdx.x >= nper * NX) return;
+    const int x = blockIdx.x % NX, w = blockIdx.x / NX;
+    const int chunk = (A.ncols + NX - 1) / NX;
+    const int qe = min(A.ncols, (x + 1) * chunk);
+    for (int q = x * chunk + w; q < qe; q += nper) small_column(A, A.cols[q], S, deferred, ndeferred);
 }
 
 template <class T>

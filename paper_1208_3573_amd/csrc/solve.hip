@@ -191,8 +191,10 @@ __device__ inline void wave_sync()
     __asm__ __volatile__("" ::: "memory");
 }
 
-// One wave owns RPL x 64 consecutive rows (in dependency order), lane l
-// the rows l, l + 64, ... which it finishes one after the other.  At start
+// A workgroup of NW waves owns NW x RPL x 64 consecutive rows (in dependency
+// order); wave w the w-th block of RPL x 64 rows, lane l of it the rows l,
+// l + 64, ... which it finishes one after the other.  Rows of the same chunk
+// hand their values over through LDS whichever wave owns them.  At start
 // the wave copies the right-hand side, the diagonal and the first
 // trsv_dmax<T> off-diagonal entries of each of its rows into LDS (a longer
 // row reads the rest from global memory when it gets there).  It then
@@ -204,14 +206,15 @@ __device__ inline void wave_sync()
 template <class T>
 struct trsv_dmax { static constexpr int v = num<T>::is_complex ? 6 : 8; };
 
-template <class T, int RPL>
-__global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
+template <class T, int NW, int RPL>
+__global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
                                                   const T* val, int upper, const T* b, T* x,
                                                   TrsvCtl* ctl, const int32_t* done,
                                                   int sleep_cycles)
 {
     if (done && *done) return;
-    constexpr int ROWS = 64 * RPL;
+    constexpr int WROWS = 64 * RPL;     // rows of one wave
+    constexpr int ROWS = NW * WROWS;    // rows of the workgroup's chunk
     constexpr int DM = trsv_dmax<T>::v;
     __shared__ uint32_t s_chunk;
     __shared__ T sx[ROWS];         // right-hand side, then the solution
@@ -220,17 +223,20 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
     __shared__ int snd[ROWS];      // off-diagonal entries held in LDS
     __shared__ int sov[ROWS];      // first entry not held in LDS (= row end if none)
     __shared__ int spe[ROWS];      // row end
-    __shared__ int sdc[RPL * DM * 64];
-    __shared__ T sdv[RPL * DM * 64];
-    const int lane = threadIdx.x;
-    if (lane == 0) s_chunk = atomicAdd(&ctl->ticket, 1u);
-    for (int k = lane; k < ROWS; k += 64) sready[k] = 0;
+    __shared__ int sdc[NW * RPL * DM * 64];
+    __shared__ T sdv[NW * RPL * DM * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) s_chunk = atomicAdd(&ctl->ticket, 1u);
+    for (int k = tid; k < ROWS; k += 64 * NW) sready[k] = 0;
     __syncthreads();
     const int base = (int)s_chunk * ROWS;
+    const int wbase = base + wv * WROWS;  // first row of this wave
+    const int lbase = wv * WROWS;         // its slot in the chunk arrays
+    const int dbase = wv * RPL;           // its rows in the entry lists
     const auto wrong_tri = [&](int c, int r) { return upper ? (c < r) : (c > r); };
 
     for (int qq = 0; qq < RPL; ++qq) {
-        const int ps = base + qq * 64 + lane;
+        const int ps = wbase + qq * 64 + lane;
         if (ps >= n) break;
         const int ii = upper ? n - 1 - ps : ps;
         const int pe = rp[ii + 1];
@@ -241,28 +247,28 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
             if (c == ii) { dg = val[pp]; continue; }
             if (wrong_tri(c, ii)) continue;  // entries outside the triangle are ignored
             if (nd < DM) {
-                sdc[(qq * DM + nd) * 64 + lane] = c;
-                sdv[(qq * DM + nd) * 64 + lane] = val[pp];
+                sdc[((dbase + qq) * DM + nd) * 64 + lane] = c;
+                sdv[((dbase + qq) * DM + nd) * 64 + lane] = val[pp];
                 ++nd;
             } else if (ov == pe) {
                 ov = pp;
             }
         }
-        sx[qq * 64 + lane] = b[ii];
-        sdg[qq * 64 + lane] = dg;
-        snd[qq * 64 + lane] = nd;
-        sov[qq * 64 + lane] = ov;
-        spe[qq * 64 + lane] = pe;
+        sx[lbase + qq * 64 + lane] = b[ii];
+        sdg[lbase + qq * 64 + lane] = dg;
+        snd[lbase + qq * 64 + lane] = nd;
+        sov[lbase + qq * 64 + lane] = ov;
+        spe[lbase + qq * 64 + lane] = pe;
     }
     __syncthreads();
 
     int q = 0;
-    int pos = base + lane;
+    int pos = wbase + lane;
     bool fin = pos >= n;
     int i = 0, d = 0, nd = 0, ov = 0, pe = 0;
     T acc = num<T>::zero();
     const auto start_row = [&]() {
-        const int k = q * 64 + lane;
+        const int k = lbase + q * 64 + lane;
         i = upper ? n - 1 - pos : pos;
         acc = sx[k];
         d = 0;
@@ -281,16 +287,16 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
             for (; ov < pe && cnt < DM; ++ov) {
                 const int cc = ci[ov];
                 if (cc == i || wrong_tri(cc, i)) continue;
-                sdc[(q * DM + cnt) * 64 + lane] = cc;
-                sdv[(q * DM + cnt) * 64 + lane] = val[ov];
+                sdc[((dbase + q) * DM + cnt) * 64 + lane] = cc;
+                sdv[((dbase + q) * DM + cnt) * 64 + lane] = val[ov];
                 ++cnt;
             }
             d = 0;
             nd = cnt;
             if (cnt == 0) return false;
         }
-        c = sdc[(q * DM + d) * 64 + lane];
-        v = sdv[(q * DM + d) * 64 + lane];
+        c = sdc[((dbase + q) * DM + d) * 64 + lane];
+        v = sdv[((dbase + q) * DM + d) * 64 + lane];
         return true;
     };
     const auto consume = [&]() { ++d; };
@@ -309,13 +315,18 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
                 bool more;
                 while ((more = next_dep(c, v))) {
                     const int cpos = upper ? n - 1 - c : c;
-                    if (cpos < base) break;  // another wave: polled in (b)
-                    if (!sready[cpos - base]) break;
+                    if (cpos < base) break;  // another chunk: polled in (b)
+                    if (!__hip_atomic_load(&sready[cpos - base], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP))
+                        break;
+                    // the row may belong to another wave of the workgroup: its
+                    // value is read only after its flag
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
                     acc -= v * sx[cpos - base];
                     consume();
                 }
                 if (!more) {
-                    const int k = q * 64 + lane;
+                    const int k = lbase + q * 64 + lane;
                     const T xi = div_t(acc, sdg[k]);
                     sx[k] = xi;
                     store_ready(x, i, xi);
@@ -329,7 +340,11 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
                 }
             }
             wave_sync();
-            if (done_slot >= 0) sready[done_slot] = 1;
+            if (done_slot >= 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+                __hip_atomic_store(&sready[done_slot], 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
             wave_sync();
             if (!__any(prog)) break;
         }
@@ -341,7 +356,7 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
             T v;
             while (next_dep(c, v)) {
                 const int cpos = upper ? n - 1 - c : c;
-                if (cpos >= base) break;  // inside the wave: back to (a)
+                if (cpos >= base) break;  // inside the chunk: back to (a)
                 T xc;
                 if (!load_ready(x, c, xc)) break;
                 acc -= v * xc;
@@ -357,10 +372,10 @@ __global__ void __launch_bounds__(64) trsv_kernel(int n, const int32_t* rp, cons
     }
     if (err) atomicOr(&ctl->error, 1u);
     __syncthreads();
-    if (lane == 0) {
+    if (tid == 0) {
         uint32_t f = atomicAdd(&ctl->finished, 1u);
         if (f == gridDim.x - 1) {
-            // last wave: reset the tickets for the next launch
+            // last workgroup: reset the tickets for the next launch
             ctl->ticket = 0;
             ctl->finished = 0;
         }
@@ -375,26 +390,27 @@ Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int u
     int64_t nw = (int64_t)n * words<T>::W;
     hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
                        n, x, done);
-    const int rows = 64 * tune.rows_per_lane;
+    if (num<T>::is_complex && tune.waves > 8) tune.waves = 8;  // LDS holds 8 x 64 complex rows
+    if (tune.waves > 1) tune.rows_per_lane = 1;
+    const int rows = 64 * tune.rows_per_lane * tune.waves;
     const dim3 grid((n + rows - 1) / rows);
-    switch (tune.rows_per_lane) {
-    case 1:
-        hipLaunchKernelGGL((trsv_kernel<T, 1>), grid, dim3(64), 0, st, n, rp, ci, val, upper, b, x,
-                           ctl, done, tune.backoff);
-        break;
-    case 2:
-        hipLaunchKernelGGL((trsv_kernel<T, 2>), grid, dim3(64), 0, st, n, rp, ci, val, upper, b, x,
-                           ctl, done, tune.backoff);
-        break;
-    case 4:
-        hipLaunchKernelGGL((trsv_kernel<T, 4>), grid, dim3(64), 0, st, n, rp, ci, val, upper, b, x,
-                           ctl, done, tune.backoff);
-        break;
-    default:
-        return {DIAF_EINVAL, "triangular solve: rows per lane must be 1, 2 or 4"};
+#define TRSV_CASE(NW, RPL)                                                                       \
+    if (tune.waves == NW && tune.rows_per_lane == RPL) {                                          \
+        hipLaunchKernelGGL((trsv_kernel<T, NW, RPL>), grid, dim3(64 * NW), 0, st, n, rp, ci, val, \
+                           upper, b, x, ctl, done, tune.backoff);                                 \
+        DIAF_HIP_TRY(hipGetLastError());                                                          \
+        return {};                                                                                \
     }
-    DIAF_HIP_TRY(hipGetLastError());
-    return {};
+    TRSV_CASE(1, 1)
+    TRSV_CASE(1, 2)
+    TRSV_CASE(1, 4)
+    TRSV_CASE(4, 1)
+    TRSV_CASE(8, 1)
+    if constexpr (!num<T>::is_complex) {
+        TRSV_CASE(16, 1)
+    }
+#undef TRSV_CASE
+    return {DIAF_EINVAL, "triangular solve: unsupported waves x rows-per-lane combination"};
 }
 
 // Level of every row in the triangular dependency DAG (same sync-free

@@ -312,8 +312,8 @@ def diaf_autotune(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode) -> dict:
     """Tune the context's launch shapes on this problem; returns the choices."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
     ctx.check(ctx.lib.diaf_autotune(ctx.h, ctypes.byref(A.desc), ctypes.byref(spec), m))
-    return {k: ctx.get_option(k) for k in ("small_grid", "generic_nt", "graph", "solve_batch",
-                                           "trsv_backoff")}
+    return {k: ctx.get_option(k) for k in ("small_grid", "generic_nt", "trsv_waves", "graph",
+                                           "solve_batch", "trsv_backoff")}
 
 
 def diaf_apply(ctx: Context, F: Factors, x, y):

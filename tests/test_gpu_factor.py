@@ -189,5 +189,5 @@ def test_autotune_keeps_results(ctx, mode):
     for key in ("Wcp", "Wri", "Wval", "Vcp", "Vri", "Vval", "r", "flags"):
         assert np.array_equal(R[key], H[key]), key
     for k, v in (("small_grid", 0), ("generic_nt", 0), ("graph", 0), ("solve_batch", 8),
-                 ("trsv_backoff", 1)):
+                 ("trsv_backoff", 1), ("trsv_waves", 16)):
         ctx.set_option(k, v)

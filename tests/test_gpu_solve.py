@@ -191,3 +191,34 @@ def test_graph_replay_matches_eager(ctx):
         assert v[0] == ref[0] and v[1] == ref[1] == 0, k
         assert np.array_equal(v[2], ref[2]), k
     F.close()
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_trsv_launch_shapes_agree(ctx, cplx):
+    """Every launch shape of the triangular solve (waves per workgroup x rows
+    per lane) consumes the entries of each row in the same order, so
+    W V^{-1} x comes out bit-identical, for lower (real) and upper (complex)
+    V, on a chunk count that leaves a ragged last chunk."""
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(21, 3, 5) if not cplx else synth.helmholtz(70, 10.0, 0.5)
+    v = "topk_lower" if not cplx else "gs_upper"
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=v, v_count=5), "unit_v")
+    rng = np.random.default_rng(1)
+    xh = rng.standard_normal(A.n) + (1j * rng.standard_normal(A.n) if cplx else 0)
+    xd = torch.from_numpy(xh).cuda()
+    shapes = [(1, 1), (1, 2), (1, 4), (4, 1), (8, 1)] + ([] if cplx else [(16, 1)])
+    ref = None
+    for waves, rpl in shapes:
+        ctx.set_option("trsv_waves", waves)
+        ctx.set_option("trsv_rows_per_lane", rpl)
+        yd = torch.zeros_like(xd)
+        diaf.diaf_apply(ctx, F, xd, yd)
+        y = yd.cpu().numpy()
+        if ref is None:
+            ref = y
+        assert np.array_equal(y, ref), (waves, rpl)
+    ctx.set_option("trsv_waves", 16)
+    ctx.set_option("trsv_rows_per_lane", 1)
+    F.close()
