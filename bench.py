@@ -121,7 +121,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
-                    help="library context option, e.g. trsv_rows_per_lane=2")
+                    help="library context option, e.g. trsv_waves=8")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes instead of tuning them first")
     ap.add_argument("--copy-calibration", action="store_true",

@@ -186,10 +186,10 @@ const char* diaf_last_error(const struct diaf_ctx* ctx);
  *   "solve_batch"        BiCGSTAB iterations between host polls (>= 1)
  *   "graph"              1: replay each batch from one captured hipGraph
  *   "trsv_backoff"       1: a waiting triangular-solve wave sleeps between polls
- *   "trsv_waves"         waves per workgroup of the triangular solve, sharing
- *                        one chunk of rows through LDS (1, 4, 8, 16; complex
- *                        values use at most 8; default 16)
- *   "trsv_rows_per_lane" 1, 2 or 4 rows per lane (single-wave workgroups only)
+ *   "trsv_waves"         waves per workgroup of the triangular solve (1, 2, 4,
+ *                        8, 16; default 16): the workgroup owns 64 x waves
+ *                        consecutive rows, one per lane, sharing their values
+ *                        through LDS
  *   "gate_small_diag"    1: the learned path also rejects proposals whose V
  *                        diagonal entry is flagged negligible
  * DIAF_EINVAL for an unknown key or value.  get_option reads a value. */

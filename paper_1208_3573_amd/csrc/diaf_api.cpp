@@ -615,7 +615,6 @@ diaf_status diaf_ctx_get_option(const diaf_ctx* ctx, const char* key, int64_t* v
     if (k == "generic_only") *value = ctx->opt_generic_only;
     else if (k == "solve_batch") *value = ctx->opt_batch;
     else if (k == "trsv_backoff") *value = ctx->trsv.backoff;
-    else if (k == "trsv_rows_per_lane") *value = ctx->trsv.rows_per_lane;
     else if (k == "trsv_waves") *value = ctx->trsv.waves;
     else if (k == "gate_small_diag") *value = ctx->opt_gate_small_diag;
     else if (k == "graph") *value = ctx->opt_graph;
@@ -641,14 +640,9 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
         ctx->ftune.generic_nt = (int)value;
     }
     else if (k == "trsv_waves") {
-        if (value != 1 && value != 4 && value != 8 && value != 16)
-            return fail(ctx, DIAF_EINVAL, "trsv_waves must be 1, 4, 8 or 16");
+        if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
+            return fail(ctx, DIAF_EINVAL, "trsv_waves must be 1, 2, 4, 8 or 16");
         ctx->trsv.waves = (int)value;
-    }
-    else if (k == "trsv_rows_per_lane") {
-        if (value != 1 && value != 2 && value != 4)
-            return fail(ctx, DIAF_EINVAL, "trsv_rows_per_lane must be 1, 2 or 4");
-        ctx->trsv.rows_per_lane = (int)value;
     }
     else return fail(ctx, DIAF_EINVAL, "unknown option " + k);
     return DIAF_OK;
@@ -1172,13 +1166,11 @@ Err autotune_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int m
     double warm;
     DIAF_TRY(time_solve(8, warm));  // first apply builds the CSR copies and levels
     {
-        // waves per workgroup of the triangular solve (rows per lane 1)
+        // waves per workgroup of the triangular solve
         double bw = INFINITY;
         int pw = ctx->trsv.waves;
-        for (int w : {1, 4, 8, 16}) {
-            if (num<T>::is_complex && w > 8) continue;
+        for (int w : {4, 8, 16}) {
             ctx->trsv.waves = w;
-            ctx->trsv.rows_per_lane = 1;
             double ms = INFINITY;
             for (int rep = 0; rep < 2; ++rep) {
                 double t;

@@ -89,14 +89,13 @@ struct BicgState {
 template <class T>
 Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
                     const int32_t* done, hipStream_t st);
-// Launch shape of the sync-free triangular solve: rows per lane (1, 2 or 4;
-// one wave owns 64 x rows_per_lane consecutive rows) and whether a wave that
-// found nothing ready sleeps briefly before polling again.
+// Launch shape of the sync-free triangular solve: waves per workgroup (1, 2,
+// 4, 8 or 16; the workgroup owns 64 x waves consecutive rows, one per lane)
+// and whether a wave that found nothing ready sleeps briefly before polling
+// again.
 struct TrsvTune {
-    int rows_per_lane = 1;
     int backoff = 1;
-    int waves = 16;  // waves per workgroup sharing one chunk through LDS (1, 4, 8, 16;
-                     // complex values use at most 8)
+    int waves = 16;
 };
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,

@@ -2,15 +2,15 @@
 // (Section 5).
 //
 // * SpMV: CSR, one thread per row.
-// * Triangular solve with V: sync-free, one wave per chunk of 256 rows.  A
-//   chunk is taken from an atomic ticket in dependency order (ascending
-//   rows for lower V, descending for upper V), so every row a wave waits on
-//   belongs to the same wave or to a wave that started earlier.  Values
-//   inside the chunk pass through LDS; values from earlier waves are read
-//   from x itself, which is filled with a signalling-NaN sentinel before the
-//   launch (a value is ready once it differs from the sentinel).  Waiting is
-//   a wave-uniform polling loop with an iteration cap that raises an error
-//   flag, so every wave always exits.
+// * Triangular solve with V: sync-free, one workgroup per chunk of 64 x NW
+//   rows, one row per lane.  A chunk is taken from an atomic ticket in
+//   dependency order (ascending rows for lower V, descending for upper V),
+//   so every row a workgroup waits on belongs to its own chunk or to a chunk
+//   taken earlier.  Values inside the chunk pass through LDS; values from
+//   earlier chunks are read from x itself.  Both are filled with a
+//   signalling-NaN sentinel first (a value is ready once it differs from the
+//   sentinel).  Waiting is a wave-uniform polling loop with an iteration cap
+//   that raises an error flag, so every wave always exits.
 // * BiCGSTAB runs on the device: each stage is a kernel that returns at
 //   once when the solve has finished, reductions are two-stage in a fixed
 //   order (the last block to finish sums the per-block partials and updates
@@ -136,18 +136,25 @@ __global__ void fill_sentinel_kernel(int n, T* x, const int32_t* done)
     if (i < (int64_t)n * W) ((uint64_t*)x)[i] = TRSV_SENTINEL;
 }
 
+// Polling of entry c of x in two steps: issue the load of its raw words now
+// and examine them later, so that other work can run while it is in flight.
 template <class T>
-__device__ inline bool load_ready(const T* x, int c, T& out)
+__device__ inline void poll_issue(const T* x, int c, uint64_t (&w)[words<T>::W])
 {
     const uint64_t* p = (const uint64_t*)(x + c);
+#pragma unroll
+    for (int k = 0; k < words<T>::W; ++k) w[k] = ld_agent(p + k);
+}
+
+template <class T>
+__device__ inline bool poll_value(const uint64_t (&w)[words<T>::W], T& out)
+{
     if constexpr (num<T>::is_complex) {
-        uint64_t a = ld_agent(p), b = ld_agent(p + 1);
-        if (a == TRSV_SENTINEL || b == TRSV_SENTINEL) return false;
-        out = T{__longlong_as_double((long long)a), __longlong_as_double((long long)b)};
+        if (w[0] == TRSV_SENTINEL || w[1] == TRSV_SENTINEL) return false;
+        out = T{__longlong_as_double((long long)w[0]), __longlong_as_double((long long)w[1])};
     } else {
-        uint64_t a = ld_agent(p);
-        if (a == TRSV_SENTINEL) return false;
-        out = __longlong_as_double((long long)a);
+        if (w[0] == TRSV_SENTINEL) return false;
+        out = __longlong_as_double((long long)w[0]);
     }
     return true;
 }
@@ -175,198 +182,244 @@ __device__ inline T div_t(T a, T d)
     }
 }
 
-static constexpr int TRSV_SPIN_CAP = 1 << 22;
-
-// Orders the LDS accesses of the lanes of one wave (LDS executes one wave's
-// instructions in order, so this only has to stop the compiler from moving
-// or caching accesses across it); unlike a workgroup barrier it does not
-// wait for outstanding global stores.  LDS is accessed with plain loads and
-// stores: a volatile access through a generic pointer becomes a flat access
-// that waits on all outstanding memory operations.
-__device__ inline void wave_sync()
+// acc - a * b with the rounding spelled out (explicit fused multiply-adds),
+// so that every call site rounds alike whatever the compiler contracts.
+template <class T>
+__device__ __forceinline__ T msub(T acc, T a, T b)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    __asm__ __volatile__("" ::: "memory");
+    if constexpr (num<T>::is_complex) {
+        double re = __builtin_fma(-a.x, b.x, acc.x);
+        re = __builtin_fma(a.y, b.y, re);
+        double im = __builtin_fma(-a.x, b.y, acc.y);
+        im = __builtin_fma(-a.y, b.x, im);
+        return T{re, im};
+    } else {
+        return __builtin_fma(-a, b, acc);
+    }
 }
 
-// A workgroup of NW waves owns NW x RPL x 64 consecutive rows (in dependency
-// order); wave w the w-th block of RPL x 64 rows, lane l of it the rows l,
-// l + 64, ... which it finishes one after the other.  Rows of the same chunk
-// hand their values over through LDS whichever wave owns them.  At start
-// the wave copies the right-hand side, the diagonal and the first
-// trsv_dmax<T> off-diagonal entries of each of its rows into LDS (a longer
-// row reads the rest from global memory when it gets there).  It then
-// alternates (a) rounds that advance every row whose next dependency lies
-// in the wave, through LDS, until none advances, and (b) one polling round
-// on global memory for the rows blocked on another wave, so global latency
-// is paid per hop between waves rather than per dependency step.  Entries
-// are consumed in CSR order, so the result does not depend on timing.
+// 1 / d, and a * b with the rounding spelled out.
+template <class T>
+__device__ inline T recip_t(T d)
+{
+    if constexpr (num<T>::is_complex) {
+        const double den = d.x * d.x + d.y * d.y;
+        return T{d.x / den, -d.y / den};
+    } else {
+        return 1.0 / d;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ T mul_t(T a, T b)
+{
+    if constexpr (num<T>::is_complex) {
+        return T{__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x)};
+    } else {
+        return a * b;
+    }
+}
+
+static constexpr int TRSV_SPIN_CAP = 1 << 22;
+
+// LDS copy of one solution entry, read and written as relaxed workgroup-scope
+// atomics of 64-bit words: the sentinel doubles as the not-ready mark, so a
+// value and its readiness are one access (a torn complex read shows a
+// sentinel half and is taken as not ready).
+template <class T>
+__device__ inline bool lds_take(const T* sx, int k, T& out)
+{
+    const uint64_t* p = (const uint64_t*)(sx + k);
+    uint64_t w[words<T>::W];
+#pragma unroll
+    for (int q = 0; q < words<T>::W; ++q)
+        w[q] = __hip_atomic_load(p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return poll_value(w, out);
+}
+
+template <class T>
+__device__ inline void lds_put(T* sx, int k, T v)
+{
+    uint64_t* p = (uint64_t*)(sx + k);
+    if constexpr (num<T>::is_complex) {
+        __hip_atomic_store(p, (uint64_t)__double_as_longlong(v.x), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(p + 1, (uint64_t)__double_as_longlong(v.y), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        __hip_atomic_store(p, (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Off-diagonal entries of a row held in LDS (more are copied in from
+// global memory when these are used up).
 template <class T>
 struct trsv_dmax { static constexpr int v = num<T>::is_complex ? 6 : 8; };
 
-template <class T, int NW, int RPL>
+// A workgroup of NW waves owns a chunk of NW x 64 consecutive rows in
+// dependency order (ascending rows for lower V, descending for upper V);
+// lane l of wave w owns row w * 64 + l of it.  The chunk is taken from an
+// atomic ticket, so every row it waits on lies in the chunk or in a chunk
+// taken earlier by a running workgroup.  The rows' dependencies are consumed
+// in ascending dependency order, the same for every launch shape, so the
+// result does not depend on the shape or on timing.
+//
+// Set-up: the chunk's solution slots in LDS are filled with the sentinel;
+// each lane keeps its row's right-hand side, diagonal and running sum in
+// registers and copies the first trsv_dmax<T> off-diagonal entries into LDS,
+// each coded as a chunk-local index or, for a dependency in an earlier
+// chunk, as ~column.  Then it repeats:
+//  (b1) issue loads of the next one or two dependencies that lie in earlier
+//       chunks (global x, also sentinel-filled);
+//  (a)  rounds in which every lane consumes the chunk-local dependencies
+//       whose values have appeared in LDS (one LDS read per waiting lane)
+//       and finishes its row when none is left (x = sum times the
+//       reciprocal of the diagonal), until a round makes no progress;
+//  (b2) consume the polled values that were ready.
+// The latency of a poll thus overlaps the LDS rounds.  Waiting is capped:
+// a lane that waits TRSV_SPIN_CAP polling rounds sets the error flag, so
+// every wave exits.
+template <class T, int NW>
 __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
                                                   const T* val, int upper, const T* b, T* x,
                                                   TrsvCtl* ctl, const int32_t* done,
                                                   int sleep_cycles)
 {
     if (done && *done) return;
-    constexpr int WROWS = 64 * RPL;     // rows of one wave
-    constexpr int ROWS = NW * WROWS;    // rows of the workgroup's chunk
+    constexpr int ROWS = NW * 64;
     constexpr int DM = trsv_dmax<T>::v;
     __shared__ uint32_t s_chunk;
-    __shared__ T sx[ROWS];         // right-hand side, then the solution
-    __shared__ int sready[ROWS];
-    __shared__ T sdg[ROWS];        // diagonal entry of each row
-    __shared__ int snd[ROWS];      // off-diagonal entries held in LDS
-    __shared__ int sov[ROWS];      // first entry not held in LDS (= row end if none)
-    __shared__ int spe[ROWS];      // row end
-    __shared__ int sdc[NW * RPL * DM * 64];
-    __shared__ T sdv[NW * RPL * DM * 64];
+    __shared__ T sx[ROWS];            // solution of the chunk's rows (sentinel until known)
+    __shared__ int sl[NW * DM * 64];  // entry code: chunk-local index, or ~column
+    __shared__ T sv[NW * DM * 64];    // entry value
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid == 0) s_chunk = atomicAdd(&ctl->ticket, 1u);
-    for (int k = tid; k < ROWS; k += 64 * NW) sready[k] = 0;
-    __syncthreads();
-    const int base = (int)s_chunk * ROWS;
-    const int wbase = base + wv * WROWS;  // first row of this wave
-    const int lbase = wv * WROWS;         // its slot in the chunk arrays
-    const int dbase = wv * RPL;           // its rows in the entry lists
-    const auto wrong_tri = [&](int c, int r) { return upper ? (c < r) : (c > r); };
-
-    for (int qq = 0; qq < RPL; ++qq) {
-        const int ps = wbase + qq * 64 + lane;
-        if (ps >= n) break;
-        const int ii = upper ? n - 1 - ps : ps;
-        const int pe = rp[ii + 1];
-        T dg = num<T>::one();
-        int nd = 0, ov = pe;
-        for (int pp = rp[ii]; pp < pe; ++pp) {
-            const int c = ci[pp];
-            if (c == ii) { dg = val[pp]; continue; }
-            if (wrong_tri(c, ii)) continue;  // entries outside the triangle are ignored
-            if (nd < DM) {
-                sdc[((dbase + qq) * DM + nd) * 64 + lane] = c;
-                sdv[((dbase + qq) * DM + nd) * 64 + lane] = val[pp];
-                ++nd;
-            } else if (ov == pe) {
-                ov = pp;
-            }
-        }
-        sx[lbase + qq * 64 + lane] = b[ii];
-        sdg[lbase + qq * 64 + lane] = dg;
-        snd[lbase + qq * 64 + lane] = nd;
-        sov[lbase + qq * 64 + lane] = ov;
-        spe[lbase + qq * 64 + lane] = pe;
+    for (int k = tid; k < ROWS; k += 64 * NW) {
+        uint64_t* p = (uint64_t*)(sx + k);
+#pragma unroll
+        for (int q = 0; q < words<T>::W; ++q) p[q] = TRSV_SENTINEL;
     }
     __syncthreads();
-
-    int q = 0;
-    int pos = wbase + lane;
+    const int base = (int)s_chunk * ROWS;
+    const int me = wv * 64 + lane;  // chunk-local index of this lane's row
+    const int pos = base + me;
     bool fin = pos >= n;
-    int i = 0, d = 0, nd = 0, ov = 0, pe = 0;
-    T acc = num<T>::zero();
-    const auto start_row = [&]() {
-        const int k = lbase + q * 64 + lane;
-        i = upper ? n - 1 - pos : pos;
-        acc = sx[k];
-        d = 0;
-        nd = snd[k];
-        ov = sov[k];
-        pe = spe[k];
-    };
-    // next unconsumed dependency of the current row; false once none is left.
-    // Consumption reads LDS only: when a long row has used up its LDS list,
-    // the next entries are first copied there from global memory (so no
-    // wait for global loads sits on the common path).
-    const auto next_dep = [&](int& c, T& v) -> bool {
-        if (d == nd) {
-            if (ov >= pe) return false;
-            int cnt = 0;
-            for (; ov < pe && cnt < DM; ++ov) {
-                const int cc = ci[ov];
-                if (cc == i || wrong_tri(cc, i)) continue;
-                sdc[((dbase + q) * DM + cnt) * 64 + lane] = cc;
-                sdv[((dbase + q) * DM + cnt) * 64 + lane] = val[ov];
-                ++cnt;
-            }
-            d = 0;
-            nd = cnt;
-            if (cnt == 0) return false;
+    const int slot0 = wv * DM * 64 + lane;  // LDS entry e of this lane at slot0 + e * 64
+    const int step = upper ? -1 : 1;        // CSR order that visits dependencies ascending
+    int i = 0, d = 0, nd = 0, ov = 0, oend = 0;
+    T acc = num<T>::zero(), dg = num<T>::one();  // dg: the diagonal, then its reciprocal
+    // copies up to DM entries from CSR position ov on into the lane's LDS slots
+    const auto refill = [&]() {
+        int cnt = 0;
+        for (; ov != oend && cnt < DM; ov += step) {
+            const int c = ci[ov];
+            if (c == i || (upper ? (c < i) : (c > i))) continue;  // outside the triangle
+            const int cpos = upper ? n - 1 - c : c;
+            sl[slot0 + cnt * 64] = cpos >= base ? cpos - base : ~c;
+            sv[slot0 + cnt * 64] = val[ov];
+            ++cnt;
         }
-        c = sdc[((dbase + q) * DM + d) * 64 + lane];
-        v = sdv[((dbase + q) * DM + d) * 64 + lane];
-        return true;
+        d = 0;
+        nd = cnt;
     };
-    const auto consume = [&]() { ++d; };
-    if (!fin) start_row();
+    if (!fin) {
+        i = upper ? n - 1 - pos : pos;
+        acc = b[i];
+        const int pb = rp[i], pe = rp[i + 1];
+        for (int pp = pb; pp < pe; ++pp) {  // branch-free, so the loads overlap
+            const T vv = val[pp];
+            dg = ci[pp] == i ? vv : dg;
+        }
+        ov = upper ? pe - 1 : pb;
+        oend = upper ? pb - 1 : pe;
+        refill();
+    }
+    dg = recip_t(dg);
+    int cur = 0;
+    T cv = num<T>::zero();
+    // entry d into (cur, cv); past the end it reads the last slot, which is
+    // then never used (every use checks d < nd)
+    const auto load_cur = [&]() {
+        const int dd = d < DM ? d : DM - 1;
+        cur = sl[slot0 + dd * 64];
+        cv = sv[slot0 + dd * 64];
+    };
+    // after a consumed dependency: the next one, refilling from CSR if needed
+    const auto advance = [&]() {
+        ++d;
+        if (__builtin_expect(d == nd && ov != oend, 0)) refill();
+        load_cur();
+    };
+    load_cur();
+    // all set-up loads complete here (vmcnt(0); expcnt and lgkmcnt not
+    // waited on), so no wait for them is left inside the polling loop, where
+    // it would also wait for the polls in flight
+    __builtin_amdgcn_s_waitcnt(0xF70);
+    __syncthreads();
 
     int spins = 0;
     bool err = false;
     while (!__all(fin)) {
-        // (a) LDS rounds
+        // (b1)
+        int npend = 0;
+        uint64_t pw0[words<T>::W], pw1[words<T>::W];
+        T pv1 = num<T>::zero();
+        if (!fin && d < nd && cur < 0) {
+            poll_issue(x, ~cur, pw0);
+            npend = 1;
+            if (d + 1 < nd) {
+                const int c1 = sl[slot0 + (d + 1) * 64];
+                if (c1 < 0) {
+                    poll_issue(x, ~c1, pw1);
+                    pv1 = sv[slot0 + (d + 1) * 64];
+                    npend = 2;
+                }
+            }
+        }
+        // (a): each round tries two chunk-local dependencies per lane, as
+        // straight-line code (every lane reads a valid LDS slot; lanes with
+        // nothing to take read their own and ignore it), then finishes rows
+        // with none left
         for (;;) {
             bool prog = false;
-            int done_slot = -1;
-            if (!fin) {
-                int c;
-                T v;
-                bool more;
-                while ((more = next_dep(c, v))) {
-                    const int cpos = upper ? n - 1 - c : c;
-                    if (cpos < base) break;  // another chunk: polled in (b)
-                    if (!__hip_atomic_load(&sready[cpos - base], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP))
-                        break;
-                    // the row may belong to another wave of the workgroup: its
-                    // value is read only after its flag
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-                    acc -= v * sx[cpos - base];
-                    consume();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const bool want = !fin && npend == 0 && d < nd && cur >= 0;
+                T xv;
+                const bool ok = lds_take(sx, want ? cur : me, xv) && want;
+                if (ok) {
+                    acc = msub(acc, cv, xv);
+                    advance();
                 }
-                if (!more) {
-                    const int k = lbase + q * 64 + lane;
-                    const T xi = div_t(acc, sdg[k]);
-                    sx[k] = xi;
-                    store_ready(x, i, xi);
-                    done_slot = k;
-                    prog = true;
-                    spins = 0;
-                    ++q;
-                    pos += 64;
-                    if (q == RPL || pos >= n) fin = true;
-                    else start_row();
-                }
+                prog = prog || ok;
             }
-            wave_sync();
-            if (done_slot >= 0) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-                __hip_atomic_store(&sready[done_slot], 1, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (!fin && npend == 0 && d >= nd) {
+                const T xi = mul_t(acc, dg);
+                lds_put(sx, me, xi);
+                store_ready(x, i, xi);
+                fin = true;
+                prog = true;
             }
-            wave_sync();
             if (!__any(prog)) break;
         }
-        if (__all(fin)) break;
-        // (b) one polling round for rows waiting on another wave
+        // (b2)
         bool polled = false;
-        if (!fin) {
-            int c;
-            T v;
-            while (next_dep(c, v)) {
-                const int cpos = upper ? n - 1 - c : c;
-                if (cpos >= base) break;  // inside the chunk: back to (a)
-                T xc;
-                if (!load_ready(x, c, xc)) break;
-                acc -= v * xc;
-                consume();
+        if (npend > 0) {
+            T xc;
+            if (poll_value(pw0, xc)) {
+                acc = msub(acc, cv, xc);
+                advance();
                 polled = true;
+                if (npend == 2 && poll_value(pw1, xc)) {
+                    acc = msub(acc, pv1, xc);
+                    advance();
+                }
             }
-            if (!polled && ++spins > TRSV_SPIN_CAP) {
-                err = true;
-                fin = true;
-            }
+        }
+        if (!fin && !polled && ++spins > TRSV_SPIN_CAP) {
+            err = true;
+            fin = true;
         }
         if (!__any(polled) && sleep_cycles) __builtin_amdgcn_s_sleep(1);
     }
@@ -390,27 +443,22 @@ Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int u
     int64_t nw = (int64_t)n * words<T>::W;
     hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
                        n, x, done);
-    if (num<T>::is_complex && tune.waves > 8) tune.waves = 8;  // LDS holds 8 x 64 complex rows
-    if (tune.waves > 1) tune.rows_per_lane = 1;
-    const int rows = 64 * tune.rows_per_lane * tune.waves;
+    const int rows = 64 * tune.waves;
     const dim3 grid((n + rows - 1) / rows);
-#define TRSV_CASE(NW, RPL)                                                                       \
-    if (tune.waves == NW && tune.rows_per_lane == RPL) {                                          \
-        hipLaunchKernelGGL((trsv_kernel<T, NW, RPL>), grid, dim3(64 * NW), 0, st, n, rp, ci, val, \
-                           upper, b, x, ctl, done, tune.backoff);                                 \
-        DIAF_HIP_TRY(hipGetLastError());                                                          \
-        return {};                                                                                \
+#define TRSV_CASE(NW)                                                                         \
+    if (tune.waves == NW) {                                                                   \
+        hipLaunchKernelGGL((trsv_kernel<T, NW>), grid, dim3(64 * NW), 0, st, n, rp, ci, val, \
+                           upper, b, x, ctl, done, tune.backoff);                             \
+        DIAF_HIP_TRY(hipGetLastError());                                                      \
+        return {};                                                                            \
     }
-    TRSV_CASE(1, 1)
-    TRSV_CASE(1, 2)
-    TRSV_CASE(1, 4)
-    TRSV_CASE(4, 1)
-    TRSV_CASE(8, 1)
-    if constexpr (!num<T>::is_complex) {
-        TRSV_CASE(16, 1)
-    }
+    TRSV_CASE(1)
+    TRSV_CASE(2)
+    TRSV_CASE(4)
+    TRSV_CASE(8)
+    TRSV_CASE(16)
 #undef TRSV_CASE
-    return {DIAF_EINVAL, "triangular solve: unsupported waves x rows-per-lane combination"};
+    return {DIAF_EINVAL, "triangular solve: waves per workgroup must be 1, 2, 4, 8 or 16"};
 }
 
 // Level of every row in the triangular dependency DAG (same sync-free
