@@ -46,9 +46,21 @@ struct SmallLds {
     T eval[STM];  // gathered values, column by column in J order
     T Gk[MODE == 1 ? STRI : 1];  // unit-norm w: packed G, kept for two solves
     union {
-        int erow[STM];  // gathered global rows (until the shadow is built)
-        T Gt[STRI];     // packed upper triangle of G (until the sweep)
-        T bc[2][SKM];   // pivot row of the sweep (double-buffered)
+        struct {  // gather and shadow
+            int erow[STM];   // gathered global rows
+            int hkey[SHS];   // hash of the shadow rows
+            union {
+                int tmp[SMM];
+                int rcnt[SMM];
+            };
+            uint8_t eslot[STM];
+            uint8_t hval[SHS];
+        } sh;
+        struct {  // Gram matrix (until the sweep)
+            T Gt[STRI];            // packed upper triangle of G
+            uint64_t cmask[SKM];   // rows (local ids) of each column of B
+        } gr;
+        T bc[2][SKM];  // pivot row of the sweep (double-buffered)
         T Pm[MODE == 1 ? SKM * SKM : 1];  // unit-norm w: power being squared
         struct {
             union {
@@ -62,21 +74,13 @@ struct SmallLds {
             T w[SKM];
         } post;
     };
-    uint64_t cmask[SKM];  // rows (local ids) of each column of B
     int J[SKM];
     int off[SKM + 1];
-    int hkey[SHS];
-    int R[SMM];
-    union {
-        int tmp[SMM];
-        int rcnt[SMM];
-    };
+    int R[SMM];  // shadow rows, ascending
     int rptr[SMM + 1];
     int L[SLM];
     uint8_t eloc[STM];
     uint8_t ecol[STM];
-    uint8_t eslot[STM];
-    uint8_t hval[SHS];
     uint8_t csr[STM];
 };
 
@@ -277,7 +281,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
     if (lane < k && k <= SKM) S.off[lane + 1] = inc;
     if (lane == 0) S.off[0] = 0;
     const int Tn = __shfl(inc, 63);
-    for (int s = lane; s < SHS; s += 64) S.hkey[s] = -1;
+    for (int s = lane; s < SHS; s += 64) S.sh.hkey[s] = -1;
     __syncthreads();
     if (k > SKM || Tn > STM) {
         if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
@@ -291,31 +295,31 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
             if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
         }
         int p = A.Acp[S.J[lo]] + (t - S.off[lo]);
-        S.erow[t] = A.Ari[p];
+        S.sh.erow[t] = A.Ari[p];
         S.eval[t] = A.Aval[p];
         S.ecol[t] = (uint8_t)lo;
     }
     __syncthreads();
     // ---- 3. shadow: hash dedup, sort, local row ids ----
     for (int t = lane; t < Tn; t += 64) {
-        int row = S.erow[t];
+        int row = S.sh.erow[t];
         unsigned h = ((unsigned)row * 2654435761u) >> 24;
         for (;;) {
-            int prev = atomicCAS(&S.hkey[h], -1, row);
+            int prev = atomicCAS(&S.sh.hkey[h], -1, row);
             if (prev == -1 || prev == row) break;
             h = (h + 1) & (SHS - 1);
         }
-        S.eslot[t] = (uint8_t)h;
+        S.sh.eslot[t] = (uint8_t)h;
     }
     __syncthreads();
     int m = 0;
     for (int q = 0; q < SHS / 64; ++q) {
         int s = q * 64 + lane;
-        int key = S.hkey[s];
+        int key = S.sh.hkey[s];
         bool occ = key != -1;
         uint64_t mask = __ballot(occ);
         int pos = m + __popcll(mask & ((1ull << lane) - 1ull));
-        if (occ && pos < SMM) { S.R[pos] = key; S.tmp[pos] = s; }
+        if (occ && pos < SMM) { S.R[pos] = key; S.sh.tmp[pos] = s; }
         m += __popcll(mask);
     }
     __syncthreads();
@@ -324,7 +328,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
         return;
     }
     int myrow = lane < m ? S.R[lane] : 0x7fffffff;
-    int myslot = lane < m ? S.tmp[lane] : 0;
+    int myslot = lane < m ? S.sh.tmp[lane] : 0;
     for (int kk = 2; kk <= 64; kk <<= 1) {
         for (int jj = kk >> 1; jj > 0; jj >>= 1) {
             int orow = __shfl_xor(myrow, jj);
@@ -338,32 +342,32 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
     __syncthreads();
     if (lane < m) {
         S.R[lane] = myrow;
-        S.hval[myslot] = (uint8_t)lane;
+        S.sh.hval[myslot] = (uint8_t)lane;
     }
-    if (lane < SMM) S.rcnt[lane] = 0;
+    if (lane < SMM) S.sh.rcnt[lane] = 0;
     const uint64_t dmask = __ballot(lane < m && myrow == j);
     const int dj = dmask ? __ffsll((unsigned long long)dmask) - 1 : -1;
     __syncthreads();
     double bn2 = 0.0;
     for (int t = lane; t < Tn; t += 64) {
-        int lr = S.hval[S.eslot[t]];
+        int lr = S.sh.hval[S.sh.eslot[t]];
         S.eloc[t] = (uint8_t)lr;
-        atomicAdd(&S.rcnt[lr], 1);
+        atomicAdd(&S.sh.rcnt[lr], 1);
         bn2 += num<T>::abs2(S.eval[t]);
     }
     bn2 = wave_sum(bn2);
     __syncthreads();
     {
-        int rc = lane < m ? S.rcnt[lane] : 0;
+        int rc = lane < m ? S.sh.rcnt[lane] : 0;
         int ri = wave_incl_scan(rc, lane);
         S.rptr[lane + 1] = ri;
         if (lane == 0) S.rptr[0] = 0;
-        S.rcnt[lane] = 0;
+        S.sh.rcnt[lane] = 0;
     }
     __syncthreads();
     for (int t = lane; t < Tn; t += 64) {
         int lr = S.eloc[t];
-        int pos = S.rptr[lr] + atomicAdd(&S.rcnt[lr], 1);
+        int pos = S.rptr[lr] + atomicAdd(&S.sh.rcnt[lr], 1);
         S.csr[pos] = (uint8_t)t;
     }
     __syncthreads();
@@ -396,7 +400,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
     if (lane < k) {
         uint64_t msk = 0;
         for (int t = S.off[lane]; t < S.off[lane + 1]; ++t) msk |= 1ull << S.eloc[t];
-        S.cmask[lane] = msk;
+        S.gr.cmask[lane] = msk;
     }
     __syncthreads();
     const int npair = k * (k + 1) / 2;
@@ -405,7 +409,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
         while (bb * (bb + 1) / 2 > q) --bb;
         while ((bb + 1) * (bb + 2) / 2 <= q) ++bb;
         const int aa = q - bb * (bb + 1) / 2;
-        const uint64_t ma = S.cmask[aa], mb = S.cmask[bb];
+        const uint64_t ma = S.gr.cmask[aa], mb = S.gr.cmask[bb];
         uint64_t common = ma & mb;
         const int oa = S.off[aa], ob = S.off[bb];
         T acc = num<T>::zero();
@@ -416,7 +420,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
             common &= common - 1ull;
         }
         if constexpr (MODE == 1) S.Gk[q] = acc;
-        else S.Gt[q] = acc;
+        else S.gr.Gt[q] = acc;
     }
     __syncthreads();
     // ---- 5. unit-norm v: G^{-1} by the symmetric sweep ----
@@ -426,7 +430,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
     const int c = lane & (SKM - 1), hf = lane >> 5;
     constexpr int SKH = SKM / 2;
     T g[SKH];
-    const T* Gp = (MODE == 1) ? S.Gk : S.Gt;
+    const T* Gp = (MODE == 1) ? S.Gk : S.gr.Gt;
     double maxd = lane < k ? num<T>::re(Gp[tri(c, c)]) : 0.0;
     maxd = wave_max(maxd);
     // shift for unit-norm w: the downdated Gram matrix plus shift * I is
@@ -436,7 +440,7 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
 #pragma unroll
         for (int i = 0; i < SKH; ++i) {
             const int r = hf * SKH + i;
-            if (r < k && c < k) g[i] = r <= c ? S.Gt[tri(r, c)] : num<T>::conj(S.Gt[tri(c, r)]);
+            if (r < k && c < k) g[i] = r <= c ? S.gr.Gt[tri(r, c)] : num<T>::conj(S.gr.Gt[tri(c, r)]);
             else g[i] = (r == c) ? num<T>::one() : num<T>::zero();
         }
         __syncthreads();  // Gt is dead from here on; bc and post alias it
@@ -535,13 +539,14 @@ __device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S
                     int gi = rows[p];
                     bool keep = A.vrule == V_EXPLICIT || gi == j ||
                                 (A.vrule == V_GS_UPPER ? gi < j : gi > j);
-                    if (keep) {
-                        unsigned h = ((unsigned)gi * 2654435761u) >> 24;
-                        for (int probe = 0; probe < SHS; ++probe) {
-                            int key = S.hkey[h];
-                            if (key == gi) { lr = S.hval[h]; break; }
-                            if (key == -1) break;
-                            h = (h + 1) & (SHS - 1);
+                    if (keep) {  // local id = position in the sorted shadow
+                        int lo = 0, hi = m - 1;
+                        while (lo <= hi) {
+                            const int mid = (lo + hi) >> 1;
+                            const int rv = S.R[mid];
+                            if (rv == gi) { lr = mid; break; }
+                            if (rv < gi) lo = mid + 1;
+                            else hi = mid - 1;
                         }
                     }
                 }
