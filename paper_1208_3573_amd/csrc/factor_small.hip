@@ -38,6 +38,8 @@ static constexpr int SHS = 256;  // hash slots
 
 static constexpr int STRI = SKM * (SKM + 1) / 2;  // packed upper triangle of G
 
+static constexpr int PMS = SKM + 1;  // column stride of Pm (odd: no bank conflicts)
+
 // Packed upper-triangle index of G(a, b), a <= b (column b holds rows 0..b).
 __device__ inline int tri(int a, int b) { return b * (b + 1) / 2 + a; }
 
@@ -61,7 +63,7 @@ struct SmallLds {
             uint64_t cmask[SKM];   // rows (local ids) of each column of B
         } gr;
         T bc[2][SKM];  // pivot row of the sweep (double-buffered)
-        T Pm[MODE == 1 ? SKM * SKM : 1];  // unit-norm w: power being squared
+        T Pm[MODE == 1 ? SKM * PMS : 1];  // unit-norm w: power being squared
         struct {
             union {
                 T U[SLM * SKM];  // U[t][i] = conj(B(L_t, i)), dense k-vectors
@@ -190,19 +192,21 @@ __device__ __forceinline__ bool top_eig_k(T (&pv)[SKM / 2], int k, int c, int hf
         const double f = wave_sum(fs);
         conv = (1.0 - f) < 1e-12;
 #pragma unroll
-        for (int i = 0; i < SKH; ++i) Pm[c * SKM + hf * SKH + i] = pv[i];
+        for (int i = 0; i < SKH; ++i) Pm[c * PMS + hf * SKH + i] = pv[i];
         __syncthreads();
-        T colc[SKM];
+        // (P^2)(r, c) = sum_q conj(P(q, r)) P(q, c): q outer (entries beyond
+        // k are zero), the rows r of this lane's half in registers
+        T acc[SKH];
 #pragma unroll
-        for (int q = 0; q < SKM; ++q) colc[q] = Pm[c * SKM + q];
+        for (int i = 0; i < SKH; ++i) acc[i] = num<T>::zero();
+        for (int q = 0; q < k; ++q) {
+            const T pqc = Pm[c * PMS + q];
 #pragma unroll
-        for (int i = 0; i < SKH; ++i) {
-            const T* colr = Pm + (hf * SKH + i) * SKM;
-            T acc = num<T>::zero();
-#pragma unroll
-            for (int q = 0; q < SKM; ++q) acc += num<T>::conj(colr[q]) * colc[q];
-            pv[i] = num<T>::div(acc, f);
+            for (int i = 0; i < SKH; ++i)
+                acc[i] += num<T>::conj(Pm[(hf * SKH + i) * PMS + q]) * pqc;
         }
+#pragma unroll
+        for (int i = 0; i < SKH; ++i) pv[i] = num<T>::div(acc[i], f);
         __syncthreads();
     }
     double dg = -1.0;
@@ -260,8 +264,8 @@ __device__ __forceinline__ bool bottom_eig_w(SmallLds<T, MODE>& S, int k, int nt
 }
 
 template <class T, int MODE>
-__device__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S, int* deferred,
-                             int* ndeferred)
+__device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S,
+                                             int* deferred, int* ndeferred)
 {
     // opaque per call: keeps lane-derived addresses from being hoisted out of
     // the column loop (they would stay live in registers for the whole kernel)
@@ -732,16 +736,17 @@ __global__ void __launch_bounds__(64) factor_small_kernel(FactorArgs<T> A, int* 
     // correct; this one only helps locality.)
     constexpr int NX = 8;
     const int nper = gridDim.x / NX;
-    if (nper == 0) {
-        for (int q = blockIdx.x; q < A.ncols; q += gridDim.x)
-            small_column(A, A.cols[q], S, deferred, ndeferred);
-        return;
+    int q0 = blockIdx.x, qs = gridDim.x, qe = A.ncols;  // fewer than 8 workgroups: plain stride
+    if (nper > 0) {
+        if ((int)blockIdx.x >= nper * NX) return;
+        const int x = blockIdx.x % NX, w = blockIdx.x / NX;
+        const int chunk = (A.ncols + NX - 1) / NX;
+        q0 = x * chunk + w;
+        qs = nper;
+        qe = min(A.ncols, (x + 1) * chunk);
     }
-    if ((int)blockIdx.x >= nper * NX) return;
-    const int x = blockIdx.x % NX, w = blockIdx.x / NX;
-    const int chunk = (A.ncols + NX - 1) / NX;
-    const int qe = min(A.ncols, (x + 1) * chunk);
-    for (int q = x * chunk + w; q < qe; q += nper) small_column(A, A.cols[q], S, deferred, ndeferred);
+    // one call site, so the column body is inlined
+    for (int q = q0; q < qe; q += qs) small_column(A, A.cols[q], S, deferred, ndeferred);
 }
 
 template <class T>
