@@ -401,18 +401,28 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     }
     uint32_t flags = 0;
     // ---- 4. Gram matrix: G(a, b) over the rows common to columns a and b ----
+    // The diagonal G(a, a) comes from column a's own entries (ascending
+    // rows, as the pair loop would take them); the strictly upper pairs
+    // then loop only over their few common rows.
     if (lane < k) {
         uint64_t msk = 0;
-        for (int t = S.off[lane]; t < S.off[lane + 1]; ++t) msk |= 1ull << S.eloc[t];
+        T dacc = num<T>::zero();
+        for (int t = S.off[lane]; t < S.off[lane + 1]; ++t) {
+            msk |= 1ull << S.eloc[t];
+            dacc += num<T>::cmul(S.eval[t], S.eval[t]);
+        }
         S.gr.cmask[lane] = msk;
+        if constexpr (MODE == 1) S.Gk[tri(lane, lane)] = dacc;
+        else S.gr.Gt[tri(lane, lane)] = dacc;
     }
     __syncthreads();
-    const int npair = k * (k + 1) / 2;
+    const int npair = k * (k - 1) / 2;
     for (int q = lane; q < npair; q += 64) {
-        int bb = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
-        while (bb * (bb + 1) / 2 > q) --bb;
-        while ((bb + 1) * (bb + 2) / 2 <= q) ++bb;
-        const int aa = q - bb * (bb + 1) / 2;
+        // strictly upper pair q = bb (bb - 1) / 2 + aa, aa < bb
+        int bb = (int)((sqrtf(8.0f * (float)q + 1.0f) + 1.0f) * 0.5f);
+        while (bb * (bb - 1) / 2 > q) --bb;
+        while ((bb + 1) * bb / 2 <= q) ++bb;
+        const int aa = q - bb * (bb - 1) / 2;
         const uint64_t ma = S.gr.cmask[aa], mb = S.gr.cmask[bb];
         uint64_t common = ma & mb;
         const int oa = S.off[aa], ob = S.off[bb];
@@ -423,8 +433,8 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
             acc += num<T>::cmul(S.eval[oa + __popcll(ma & below)], S.eval[ob + __popcll(mb & below)]);
             common &= common - 1ull;
         }
-        if constexpr (MODE == 1) S.Gk[q] = acc;
-        else S.gr.Gt[q] = acc;
+        if constexpr (MODE == 1) S.Gk[tri(aa, bb)] = acc;
+        else S.gr.Gt[tri(aa, bb)] = acc;
     }
     __syncthreads();
     // ---- 5. unit-norm v: G^{-1} by the symmetric sweep ----
