@@ -23,6 +23,7 @@
 #define ORC_GAP_DEGENERATE 2u  /* extreme singular value not separated: vector not unique */
 #define ORC_SMALL_DIAG 4u      /* |v_jj| < 1e-2 ||v_j|| */
 #define ORC_TIE_EDGE 16u       /* a top-k score lies at the edge of the tie band */
+#define ORC_STABILIZED 32u     /* v_j replaced by the constrained solution of Section 3.2 */
 #define ORC_NO_DIAG_ROW 64u    /* row j does not occur in the shadow R_j */
 
 /* V pattern rules. */
