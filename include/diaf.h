@@ -88,6 +88,7 @@ typedef enum diaf_v_kind {
 #define DIAF_FLAG_SMALL_DIAG 4u     /* |v_jj| < 1e-2 ||v_j|| */
 #define DIAF_FLAG_FELL_BACK 8u      /* learned pattern rejected by the residual gate */
 #define DIAF_FLAG_TIE_EDGE 16u      /* a top-k score at the edge of the 1e-10 tie band */
+#define DIAF_FLAG_STABILIZED 32u    /* v_j computed under the constraint v_jj = stab_r (Section 3.2) */
 #define DIAF_FLAG_NO_DIAG_ROW 64u   /* row j not in the shadow of J_j: column left zero */
 
 typedef struct diaf_csc {
@@ -124,6 +125,14 @@ typedef struct diaf_spec {
                                         |v_jj| < gate_dom * sum_{i != j} |v_ij| for the
                                         proposal's V column: chains of such columns make the
                                         triangular solve with V grow exponentially (0 = off) */
+    double stab_r;                   /* Section 3.2, DIAF_UNIT_V with a triangular V rule
+                                        (DIAG, GS_*, TOPK_*): a column whose |v_jj| falls
+                                        below stab_tol * ||v_j|| is recomputed with
+                                        v_jj = stab_r, the other rows of L_j carrying the
+                                        unit vector of Section 3.2, w_j the least-squares
+                                        solution for that v_j; flag DIAF_FLAG_STABILIZED
+                                        (0 = off; the paper's experiment uses 2) */
+    double stab_tol;                 /* trigger of stab_r (the paper's experiment: 1e-2) */
 } diaf_spec;
 
 /* Borrowed device views of a factorization.  W has the pattern J (Wcp/Wri)
@@ -160,6 +169,7 @@ typedef struct diaf_stats {
     double nrm;                      /* ||A W - V||_F = sqrt(sum r_j^2) */
     double ms_pattern, ms_factor, ms_assemble;  /* device time of the phases */
     double ms_factor_kernels;        /* device time of the factor kernels alone */
+    int32_t count_stabilized;        /* columns computed under the Section 3.2 constraint */
 } diaf_stats;
 
 typedef struct diaf_solve_info {

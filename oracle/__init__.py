@@ -39,6 +39,7 @@ RANK_DEFICIENT = 1
 GAP_DEGENERATE = 2
 SMALL_DIAG = 4
 TIE_EDGE = 16
+STABILIZED = 32
 NO_DIAG_ROW = 64
 
 

@@ -129,6 +129,7 @@ struct FactorArgs {
     const int32_t* Vcp_in;
     const int32_t* Vri_in;
     int gram_fp32;
+    double stab_r, stab_tol;  // constrained v_jj of Section 3.2 (stab_r = 0: off)
     // outputs
     T* Wval;
     int32_t* Vrows;  // n * lmax, -1 padded, sorted by row

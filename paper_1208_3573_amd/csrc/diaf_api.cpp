@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -357,6 +358,8 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     fa.Vcp_in = spec->v_explicit ? spec->v_explicit->colptr : nullptr;
     fa.Vri_in = spec->v_explicit ? spec->v_explicit->rowidx : nullptr;
     fa.gram_fp32 = spec->gram_fp32;
+    fa.stab_r = spec->stab_r;
+    fa.stab_tol = spec->stab_tol;
     fa.Wval = (T*)F->Wval;
     fa.Vrows = F->Vrows;
     fa.Vvals = (T*)F->Vvals;
@@ -495,6 +498,7 @@ Err compute_stats(diaf_ctx* ctx, diaf_factors* F)
     F->stats.count_small_diag = c[2];
     F->stats.count_fell_back = c[3];
     F->stats.count_tie_edge = c[4];
+    F->stats.count_stabilized = c[5];
     F->stats.count_no_diag = c[6];
     F->stats.nrm = sqrt(s);
     F->stats.n = F->n;
@@ -694,6 +698,9 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
         return fail(ctx, DIAF_EINVAL, "bad v_kind");
     if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_LEARNED)
         return fail(ctx, DIAF_EINVAL, "bad w_kind");
+    if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
+        !std::isfinite(spec->stab_tol))
+        return fail(ctx, DIAF_EINVAL, "stab_r and stab_tol must be finite and >= 0");
     if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER) &&
         (spec->v_count < 1 || spec->v_count > 64))
         return fail(ctx, DIAF_EINVAL, "v_count must be in 1..64");

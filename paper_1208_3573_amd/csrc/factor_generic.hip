@@ -68,8 +68,9 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
 }
 
 // misc slots (int view / double view)
-enum { MI_T = 0, MI_M, MI_DJ, MI_FLAGS, MI_L, MI_NC, MI_ROT, MI_BEST, MI_Q, MI_EDGE, MI_NIN };
-enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2 };
+enum { MI_T = 0, MI_M, MI_DJ, MI_FLAGS, MI_L, MI_NC, MI_ROT, MI_BEST, MI_Q, MI_EDGE, MI_NIN,
+       MI_STAB, MI_DPOS };
+enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2, MD_ERE, MD_EIM };
 
 template <class T>
 struct GenCtx {
@@ -759,9 +760,83 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         if (!num<T>::iszero(c.sV[piv])) ph = unit_conj_phase(c.sV[piv]);
         for (int t = 0; t < l; ++t) c.sV[t] = ph * c.sV[t];
         for (int a = 0; a < k; ++a) c.sW[a] = ph * c.sW[a];
-        if (dpos < 0 || num<T>::abs(c.sV[dpos]) < 1e-2 * vn) c.mi[MI_FLAGS] |= DIAF_FLAG_SMALL_DIAG;
+        // Section 3.2 applies to unit-norm v with a triangular V
+        const bool vtri = A.vrule == V_DIAG || A.vrule == V_GS_UPPER || A.vrule == V_GS_LOWER ||
+                          A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER;
+        const bool stab = A.mode == 0 && A.stab_r > 0.0 && vtri && dpos >= 0 &&
+                          num<T>::abs(c.sV[dpos]) < A.stab_tol * vn;
+        c.mi[MI_STAB] = stab ? 1 : 0;
+        c.mi[MI_DPOS] = dpos;
+        if (stab)
+            c.mi[MI_FLAGS] = (c.mi[MI_FLAGS] | DIAF_FLAG_STABILIZED) & ~DIAF_FLAG_GAP_DEGENERATE;
+        else if (dpos < 0 || num<T>::abs(c.sV[dpos]) < 1e-2 * vn)
+            c.mi[MI_FLAGS] |= DIAF_FLAG_SMALL_DIAG;
     }
     __syncthreads();
+    if (c.mi[MI_STAB]) {
+        // v_jj = stab_r; on the other rows S of L the unit vector e^{i theta}
+        // v1, v1 the top right singular vector of Mh = the columns of
+        // M = L^{-1} B_L^* (the columns of Q^* up to a unitary factor) at S,
+        // theta the argument of u1^* p (p the column at row j); w the
+        // least-squares solution L^{-*} (M v) = L^{-*} (r p + e^{i theta} s1 u1).
+        const int dpos = c.mi[MI_DPOS];
+        const int ls = l - 1;
+        for (int idx = tid; idx < k * l; idx += c.nt) {
+            const int a = idx / l, t = idx % l;
+            const int src = t < ls ? (t < dpos ? t : t + 1) : dpos;  // p goes last
+            c.sX[a * c.xld + t] = num<T>::conj(bget(c, c.sL[src], a));
+        }
+        __syncthreads();
+        lsolve(c, G, k, c.sX, l);
+        if (ls > 0) jacobi_onesided(c, c.sX, k, ls, c.sVM);
+        for (int t = tid; t < ls; t += c.nt) {
+            double s2 = 0;
+            for (int a = 0; a < k; ++a) s2 += num<T>::abs2(c.sX[a * c.xld + t]);
+            c.sSig[t] = sqrt(s2);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int best = 0;
+            T e = num<T>::one();
+            if (ls > 0) {
+                for (int t = 1; t < ls; ++t) if (c.sSig[t] > c.sSig[best]) best = t;
+                const double s1 = c.sSig[best];
+                double s2 = 0;
+                for (int t = 0; t < ls; ++t) if (t != best && c.sSig[t] > s2) s2 = c.sSig[t];
+                if (ls >= 2 && (!(s1 > 0) || (s1 * s1 - s2 * s2) / (s1 * s1) < 1e-6))
+                    c.mi[MI_FLAGS] |= DIAF_FLAG_GAP_DEGENERATE;
+                T z = num<T>::zero();
+                for (int a = 0; a < k; ++a)
+                    z += num<T>::conj(c.sX[a * c.xld + best]) * c.sX[a * c.xld + ls];
+                const double az = num<T>::abs(z);
+                if (az > 0.0) e = num<T>::div(z, az);
+            }
+            c.mi[MI_BEST] = best;
+            c.md[MD_ERE] = num<T>::re(e);
+            c.md[MD_EIM] = num<T>::im(e);
+            c.sV[dpos] = num<T>::mk(A.stab_r);
+            for (int t = 0; t < ls; ++t)
+                c.sV[t < dpos ? t : t + 1] = e * c.sVM[t * ls + best];
+        }
+        __syncthreads();
+        {
+            const int best = c.mi[MI_BEST];
+            T e;
+            if constexpr (num<T>::is_complex) e = T{c.md[MD_ERE], c.md[MD_EIM]};
+            else e = c.md[MD_ERE];
+            for (int a = tid; a < k; a += c.nt) {
+                T u = num<T>::mk(A.stab_r) * c.sX[a * c.xld + ls];
+                if (ls > 0) u += e * c.sX[a * c.xld + best];
+                c.sX[a * c.xld + l] = u;
+            }
+        }
+        __syncthreads();
+        for (int a = tid; a < k; a += c.nt) c.sX[a * c.xld] = c.sX[a * c.xld + l];
+        __syncthreads();
+        lhsolve(c, G, k, c.sX, 1);
+        for (int a = tid; a < k; a += c.nt) c.sW[a] = c.sX[a * c.xld];
+        __syncthreads();
+    }
     bmul(c, m, c.sW, c.sY);
     if (tid == 0)
         for (int t = 0; t < l; ++t) c.sY[c.sL[t]] -= c.sV[t];

@@ -68,8 +68,10 @@ struct SmallLds {
             union {
                 T U[SLM * SKM];  // U[t][i] = conj(B(L_t, i)), dense k-vectors
                 struct {
-                    T P[SLM * SLM];  // power of H being squared (after Y)
+                    T P[SLM * SLM];   // power of H being squared (after Y)
                     T v[SLM];
+                    T Hs[SLM * SLM];  // H itself, for the constrained solve
+                    T vs[SLM];        // its top eigenvector on the rows S
                 };
             };
             T Y[SKM * SLM];  // Y[i][t] = (G^{-1} U)(i, t)
@@ -166,6 +168,55 @@ __device__ __forceinline__ void sweep_inverse(T (&g)[SKM / 2], int k, int c, int
         }
     }
     __syncthreads();
+}
+
+// Top eigenvector of the Hermitian positive semidefinite l x l matrix (l <=
+// 8) whose entry (hs, ht) lane hs * 8 + ht holds in h (zero outside l x l),
+// by repeated squaring: P = H / tr(H), then P <- P^2 / tr(P^2), with
+// tr(P^2) = ||P||_F^2.  For P = sum mu_i v_i v_i^* (sum mu_i = 1),
+// 1 - tr(P^2) ~ 2 mu_2, so the loop stops one squaring after
+// 1 - tr(P^2) < 1e-12.  The eigenvector is the column of the last power
+// with the largest diagonal entry (lowest index on ties), normalised, into
+// out[0..l).  Returns false when the trace is not positive or 25 squarings
+// did not reach rank one (the top eigenvalue is then separated from the
+// next by less than a relative 1e-6).  P is LDS scratch of 64 entries.
+template <class T>
+__device__ __forceinline__ bool top_eig_h(T h, int l, int hs, int ht, int lane, T* P, T* out)
+{
+    const double tr = wave_sum((hs == ht) ? num<T>::re(h) : 0.0);
+    bool conv = false, ok = true;
+    if (!(tr > 0.0) || !isfinite(tr)) {
+        h = (hs == 0 && ht == 0) ? num<T>::one() : num<T>::zero();
+        ok = false;
+        conv = true;
+    } else {
+        h = num<T>::div(h, tr);
+    }
+    for (int s = 0; s < 25 && !conv; ++s) {
+        const double f = wave_sum(num<T>::abs2(h));
+        conv = (1.0 - f) < 1e-12;
+        P[lane] = h;
+        __syncthreads();
+        T acc = num<T>::zero();
+#pragma unroll
+        for (int q = 0; q < SLM; ++q) acc += P[hs * SLM + q] * P[q * SLM + ht];
+        __syncthreads();
+        h = num<T>::div(acc, f);
+    }
+    if (!conv) ok = false;
+    const double dg = (hs == ht && hs < l) ? num<T>::re(h) : -1.0;
+    const double dmx = wave_max(dg);
+    const uint64_t cm = __ballot(hs == ht && hs < l && dg == dmx);
+    const int cstar = (__ffsll((unsigned long long)cm) - 1) >> 3;
+    if (ht == cstar && hs < SLM) out[hs] = h;
+    __syncthreads();
+    double nv = 0.0;
+    for (int t = 0; t < l; ++t) nv += num<T>::abs2(out[t]);
+    nv = sqrt(nv);
+    __syncthreads();
+    if (lane < l) out[lane] = num<T>::div(out[lane], nv);
+    __syncthreads();
+    return ok;
 }
 
 // Top eigenvector of a Hermitian positive semidefinite k x k matrix P held
@@ -618,50 +669,9 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
                 h += S.eval[e] * S.post.Y[S.ecol[e] * SLM + ht];
             }
         }
-        // ---- 8. top eigenvector of H by repeated squaring ----
-        // P = H / tr(H); each step P <- P^2 / tr(P^2), with tr(P^2) = ||P||_F^2.
-        // For P = sum mu_i v_i v_i^* (sum mu_i = 1), 1 - tr(P^2) ~ 2 mu_2, so the
-        // loop stops one squaring after 1 - tr(P^2) < 1e-12.  Not converging in
-        // 25 squarings means lambda_2 / lambda_1 > 1 - 1e-6: gap-degenerate.
-        {
-            double tr = wave_sum((hs == ht) ? num<T>::re(h) : 0.0);
-            bool conv = false;
-            if (!(tr > 0.0) || !isfinite(tr)) {
-                h = (hs == 0 && ht == 0) ? num<T>::one() : num<T>::zero();
-                flags |= DIAF_FLAG_GAP_DEGENERATE;
-                conv = true;
-            } else {
-                h = num<T>::div(h, tr);
-            }
-            for (int s = 0; s < 25 && !conv; ++s) {
-                const double f = wave_sum(num<T>::abs2(h));
-                conv = (1.0 - f) < 1e-12;
-                S.post.P[lane] = h;
-                __syncthreads();
-                T acc = num<T>::zero();
-#pragma unroll
-                for (int q = 0; q < SLM; ++q) acc += S.post.P[hs * SLM + q] * S.post.P[q * SLM + ht];
-                __syncthreads();
-                h = num<T>::div(acc, f);
-            }
-            if (!conv) flags |= DIAF_FLAG_GAP_DEGENERATE;
-        }
-        // eigenvector: the column of P with the largest diagonal entry (lowest
-        // index on ties), normalised
-        {
-            const double dg = (hs == ht && hs < l) ? num<T>::re(h) : -1.0;
-            const double dmx = wave_max(dg);
-            const uint64_t cm = __ballot(hs == ht && hs < l && dg == dmx);
-            const int cstar = (__ffsll((unsigned long long)cm) - 1) >> 3;
-            if (ht == cstar && hs < SLM) S.post.v[hs] = h;
-            __syncthreads();
-            double nv = 0.0;
-            for (int t = 0; t < l; ++t) nv += num<T>::abs2(S.post.v[t]);
-            nv = sqrt(nv);
-            __syncthreads();
-            if (lane < l) S.post.v[lane] = num<T>::div(S.post.v[lane], nv);
-        }
-        __syncthreads();
+        // ---- 8. top eigenvector of H ----
+        S.post.Hs[lane] = h;
+        if (!top_eig_h(h, l, hs, ht, lane, S.post.P, S.post.v)) flags |= DIAF_FLAG_GAP_DEGENERATE;
         // w = Y v
         if (lane < k) {
             T acc = num<T>::zero();
@@ -711,6 +721,43 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     if (lane < l) S.post.v[lane] = vt;
     if (lane < k) S.post.w[lane] = ph * S.post.w[lane];
     __syncthreads();
+    if constexpr (MODE == 0) {
+        // Section 3.2: with a triangular V and |v_jj| < stab_tol ||v||, fix
+        // v_jj = stab_r; on the other rows S of L put e^{i theta} vs, vs the
+        // top eigenvector of H(S, S) (= the top right singular vector of the
+        // columns of Q^* at S) and theta the argument of vs^* H(S, j) (the
+        // first component of U^* p in the paper's notation); w = Y v, the
+        // least-squares solution for that v (eq. 2.4).
+        const bool vtri = A.vrule == V_DIAG || A.vrule == V_GS_UPPER || A.vrule == V_GS_LOWER ||
+                          A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER;
+        if (A.stab_r > 0.0 && vtri && dpos >= 0 && num<T>::abs(shfl(vt, dpos)) < A.stab_tol * vn) {
+            flags = (flags | DIAF_FLAG_STABILIZED) & ~(DIAF_FLAG_SMALL_DIAG | DIAF_FLAG_GAP_DEGENERATE);
+            const int ls = l - 1;
+            const int hs = lane >> 3, ht = lane & 7;
+            const auto full = [&](int t) { return t < dpos ? t : t + 1; };  // position in L
+            if (ls > 0) {
+                const T h2 = (hs < ls && ht < ls) ? S.post.Hs[full(hs) * SLM + full(ht)]
+                                                  : num<T>::zero();
+                if (!top_eig_h(h2, ls, hs, ht, lane, S.post.P, S.post.vs))
+                    flags |= DIAF_FLAG_GAP_DEGENERATE;
+            }
+            T z = num<T>::zero();
+            for (int t = 0; t < ls; ++t)
+                z += num<T>::conj(S.post.vs[t]) * S.post.Hs[full(t) * SLM + dpos];
+            const double az = num<T>::abs(z);
+            const T e = az > 0.0 ? num<T>::div(z, az) : num<T>::one();
+            if (lane < l)
+                S.post.v[lane] = lane == dpos ? num<T>::mk(A.stab_r)
+                                              : e * S.post.vs[lane < dpos ? lane : lane - 1];
+            __syncthreads();
+            if (lane < k) {
+                T acc = num<T>::zero();
+                for (int t = 0; t < l; ++t) acc += S.post.Y[lane * SLM + t] * S.post.v[t];
+                S.post.w[lane] = acc;
+            }
+            __syncthreads();
+        }
+    }
     T res = num<T>::zero();
     if (lane < m)
         for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {

@@ -44,7 +44,8 @@ class diaf_spec(ctypes.Structure):
     _fields_ = [("w_kind", c_int32), ("w_topk", c_int32), ("w_explicit", POINTER(diaf_pattern)),
                 ("model", c_void_p), ("gate_tau", c_double), ("v_kind", c_int32),
                 ("v_count", c_int32), ("v_explicit", POINTER(diaf_pattern)),
-                ("gram_fp32", c_int32), ("gate_dom", c_double)]
+                ("gram_fp32", c_int32), ("gate_dom", c_double), ("stab_r", c_double),
+                ("stab_tol", c_double)]
 
 
 class diaf_view(ctypes.Structure):
@@ -63,7 +64,7 @@ class diaf_stats(ctypes.Structure):
                 ("count_zero_pivot", c_int32), ("factor_launches", c_int32),
                 ("count_deferred", c_int32), ("nrm", c_double),
                 ("ms_pattern", c_double), ("ms_factor", c_double), ("ms_assemble", c_double),
-                ("ms_factor_kernels", c_double)]
+                ("ms_factor_kernels", c_double), ("count_stabilized", c_int32)]
 
 
 class diaf_solve_info(ctypes.Structure):
@@ -232,7 +233,7 @@ MODES = {"unit_v": DIAF_UNIT_V, "unit_w": DIAF_UNIT_W}
 
 def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | None = None,
               v_explicit: DevicePattern | None = None, model=None, gate_tau=float("inf"),
-              gram_fp32=False, gate_dom=0.0):
+              gram_fp32=False, gate_dom=0.0, stab_r=0.0, stab_tol=1e-2):
     spec = diaf_spec()
     spec.w_kind = W_KINDS[w]
     spec.w_topk = w_topk
@@ -244,6 +245,8 @@ def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | 
     spec.v_explicit = ctypes.pointer(v_explicit.desc) if v_explicit is not None else None
     spec.gram_fp32 = int(bool(gram_fp32))
     spec.gate_dom = gate_dom
+    spec.stab_r = stab_r
+    spec.stab_tol = stab_tol
     spec._keep = (w_explicit, v_explicit, model)
     return spec
 
