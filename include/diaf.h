@@ -195,7 +195,9 @@ const char* diaf_last_error(const struct diaf_ctx* ctx);
  *                        128, 256)
  *   "solve_batch"        BiCGSTAB iterations between host polls (>= 1)
  *   "graph"              1: replay each batch from one captured hipGraph
- *   "trsv_backoff"       1: a waiting triangular-solve wave sleeps between polls
+ *   "trsv_backoff"       0..256: a triangular-solve wave that made no progress
+ *                        sleeps 64, 128, 256, ... cycles, up to 64 x the value,
+ *                        before polling again (0: never; default 1)
  *   "trsv_waves"         waves per workgroup of the triangular solve (1, 2, 4,
  *                        8, 16; default 16): the workgroup owns 64 x waves
  *                        consecutive rows, one per lane, sharing their values

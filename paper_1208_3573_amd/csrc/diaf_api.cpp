@@ -634,7 +634,11 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     std::string k(key);
     if (k == "generic_only") ctx->opt_generic_only = value;
     else if (k == "solve_batch") ctx->opt_batch = value < 1 ? 1 : value;
-    else if (k == "trsv_backoff") ctx->trsv.backoff = value ? 1 : 0;
+    else if (k == "trsv_backoff") {
+        if (value < 0 || value > 256)
+            return fail(ctx, DIAF_EINVAL, "trsv_backoff must be in 0..256");
+        ctx->trsv.backoff = (int)value;
+    }
     else if (k == "gate_small_diag") ctx->opt_gate_small_diag = value ? 1 : 0;
     else if (k == "graph") ctx->opt_graph = value ? 1 : 0;
     else if (k == "small_grid") ctx->ftune.small_grid = value < 0 ? 0 : (int)value;

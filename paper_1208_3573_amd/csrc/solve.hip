@@ -284,7 +284,7 @@ template <class T, int NW>
 __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp, const int32_t* ci,
                                                   const T* val, int upper, const T* b, T* x,
                                                   TrsvCtl* ctl, const int32_t* done,
-                                                  int sleep_cycles)
+                                                  int sleep_cap)
 {
     if (done && *done) return;
     constexpr int ROWS = NW * 64;
@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp,
     __builtin_amdgcn_s_waitcnt(0xF70);
     __syncthreads();
 
-    int spins = 0;
+    int spins = 0, nsleep = 0;
     bool err = false;
     while (!__all(fin)) {
         // (b1)
@@ -377,6 +377,7 @@ __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp,
                 }
             }
         }
+        bool aprog = false;  // some round of (a) made progress
         // (a): each round tries two chunk-local dependencies per lane, as
         // straight-line code (every lane reads a valid LDS slot; lanes with
         // nothing to take read their own and ignore it), then finishes rows
@@ -402,6 +403,7 @@ __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp,
                 prog = true;
             }
             if (!__any(prog)) break;
+            aprog = true;
         }
         // (b2)
         bool polled = false;
@@ -421,7 +423,16 @@ __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp,
             err = true;
             fin = true;
         }
-        if (!__any(polled) && sleep_cycles) __builtin_amdgcn_s_sleep(1);
+        // back-off: a wave that made no progress sleeps before polling again,
+        // twice as long as the time before, up to sleep_cap units of 64
+        // cycles (0: never), so that waves far from the dependency front
+        // leave the issue slots to the ones at it
+        if (aprog || __any(polled)) {
+            nsleep = 0;
+        } else if (sleep_cap > 0) {
+            nsleep = nsleep == 0 ? 1 : min(2 * nsleep, sleep_cap);
+            for (int z = 0; z < nsleep; ++z) __builtin_amdgcn_s_sleep(1);
+        }
     }
     if (err) atomicOr(&ctl->error, 1u);
     __syncthreads();
