@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 
 V_RULES = {"explicit": 0, "diag": 1, "gs_upper": 2, "gs_lower": 3, "topk_upper": 4,
-           "topk_lower": 5}
+           "topk_lower": 5, "lev_upper": 6, "lev_lower": 7}
 MODES = {"unit_v": 0, "unit_w": 1}
 
 RANK_DEFICIENT = 1
@@ -168,7 +168,7 @@ def factor(A, J: Pattern, mode: str, vrule: str, vcount: int = 0, Vexp: Pattern 
     aval = np.ascontiguousarray(A.val, dtype=dt)
     jcp, jri = _i32(J.colptr), _i32(J.rowidx)
     if lmax is None:
-        if vrule in ("topk_upper", "topk_lower"):
+        if vrule in ("topk_upper", "topk_lower", "lev_upper", "lev_lower"):
             lmax = max(1, vcount)
         elif vrule == "diag":
             lmax = 1
