@@ -73,13 +73,17 @@ typedef enum diaf_w_kind {
 } diaf_w_kind;
 
 /* V pattern L: explicit; diagonal; Gauss-Seidel structure (Definition 4.1:
- * diagonal plus the strictly upper / lower part of pattern(A)); or the
- * optimal choice for the seed w (Section 3.1): the diagonal plus the
- * v_count-1 rows of the upper / lower triangle of the shadow R_j with the
- * largest |A w0|, w0 being the solution for V_0 = diagonals. */
+ * diagonal plus the strictly upper / lower part of pattern(A)); the optimal
+ * choice for the seed w (Section 3.1): the diagonal plus the v_count-1 rows
+ * of the upper / lower triangle of the shadow R_j with the largest |A w0|,
+ * w0 being the solution for V_0 = diagonals (TOPK); or Section 3.1's own
+ * suboptimal rule for DIAF_UNIT_V: the diagonal plus the v_count-1 rows of
+ * the triangle whose columns of Q_j^* (A_j = Q_j R_j) have the largest norm,
+ * i.e. the largest leverage b_i (A_j^* A_j)^{-1} b_i^* (LEV; DIAF_EINVAL with
+ * DIAF_UNIT_W).  Ties within 1e-10 relative go to the lower row. */
 typedef enum diaf_v_kind {
     DIAF_V_EXPLICIT = 0, DIAF_V_DIAG = 1, DIAF_V_GS_UPPER = 2, DIAF_V_GS_LOWER = 3,
-    DIAF_V_TOPK_UPPER = 4, DIAF_V_TOPK_LOWER = 5
+    DIAF_V_TOPK_UPPER = 4, DIAF_V_TOPK_LOWER = 5, DIAF_V_LEV_UPPER = 6, DIAF_V_LEV_LOWER = 7
 } diaf_v_kind;
 
 /* Per-column flag bits (diaf_view.flags). */

@@ -111,7 +111,7 @@ struct Err {
 
 // V pattern rules as seen by the kernels.
 enum VRule { V_EXPLICIT = 0, V_DIAG = 1, V_GS_UPPER = 2, V_GS_LOWER = 3, V_TOPK_UPPER = 4,
-             V_TOPK_LOWER = 5 };
+             V_TOPK_LOWER = 5, V_LEV_UPPER = 6, V_LEV_LOWER = 7 };
 
 // Everything the factor kernels need about one launch.
 template <class T>

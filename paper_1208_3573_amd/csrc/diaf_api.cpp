@@ -295,9 +295,11 @@ int vtri_of(int v_kind)
 {
     switch (v_kind) {
     case DIAF_V_GS_UPPER:
-    case DIAF_V_TOPK_UPPER: return 1;
+    case DIAF_V_TOPK_UPPER:
+    case DIAF_V_LEV_UPPER: return 1;
     case DIAF_V_GS_LOWER:
-    case DIAF_V_TOPK_LOWER: return -1;
+    case DIAF_V_TOPK_LOWER:
+    case DIAF_V_LEV_LOWER: return -1;
     case DIAF_V_DIAG: return 0;
     default: return 2;  // determined from the explicit pattern
     }
@@ -698,14 +700,17 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     if (e.code) return fail(ctx, e);
     if (!spec) return fail(ctx, DIAF_EINVAL, "spec is NULL");
     if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return fail(ctx, DIAF_EINVAL, "bad norm mode");
-    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_TOPK_LOWER)
+    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_LEV_LOWER)
         return fail(ctx, DIAF_EINVAL, "bad v_kind");
+    const bool lev_rule = spec->v_kind == DIAF_V_LEV_UPPER || spec->v_kind == DIAF_V_LEV_LOWER;
+    if (lev_rule && mode != DIAF_UNIT_V)
+        return fail(ctx, DIAF_EINVAL, "the Section 3.1 V rule is defined for DIAF_UNIT_V");
     if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_LEARNED)
         return fail(ctx, DIAF_EINVAL, "bad w_kind");
     if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
         !std::isfinite(spec->stab_tol))
         return fail(ctx, DIAF_EINVAL, "stab_r and stab_tol must be finite and >= 0");
-    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER) &&
+    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER || lev_rule) &&
         (spec->v_count < 1 || spec->v_count > 64))
         return fail(ctx, DIAF_EINVAL, "v_count must be in 1..64");
     if (spec->w_kind == DIAF_W_A_1HOP_TOPK && (spec->w_topk < 0 || spec->w_topk > 256))
@@ -928,7 +933,8 @@ Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mod
     DIAF_HIP_TRY(hipEventRecord(ev[1], st));
     // ---- V pattern capacity ----
     int lmax = 1;
-    if (spec->v_kind == DIAF_V_TOPK_LOWER || spec->v_kind == DIAF_V_TOPK_UPPER) {
+    if (spec->v_kind == DIAF_V_TOPK_LOWER || spec->v_kind == DIAF_V_TOPK_UPPER ||
+        spec->v_kind == DIAF_V_LEV_LOWER || spec->v_kind == DIAF_V_LEV_UPPER) {
         lmax = spec->v_count;
     } else if (spec->v_kind == DIAF_V_GS_LOWER || spec->v_kind == DIAF_V_GS_UPPER) {
         std::vector<int32_t> cp(n + 1);

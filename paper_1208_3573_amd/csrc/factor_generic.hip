@@ -583,11 +583,33 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
 
     // ---- 6. V pattern ----
     const bool topk = (A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER);
+    const bool lev = A.mode == 0 && (A.vrule == V_LEV_LOWER || A.vrule == V_LEV_UPPER);
+    const bool lowerrule = A.vrule == V_TOPK_LOWER || A.vrule == V_LEV_LOWER;
     int l = 0;
     if (A.mode == 0) cholesky(c, G, k);
-    if (topk) {
+    if (topk || lev) {
         T* E = c.E; T* Z = c.Z;
-        if (A.mode == 0) {
+        if (lev) {
+            // Section 3.1's rule: the score of row i is the norm of its column
+            // of Q^*, ||L^{-1} b_i^*|| with G = L L^* (rows in batches of
+            // xld columns of X; non-admissible rows are scored and dropped)
+            const int nbmax = c.xld;
+            for (int base = 0; base < m; base += nbmax) {
+                const int nb = min(nbmax, m - base);
+                for (int idx = tid; idx < k * nb; idx += c.nt) {
+                    const int a = idx / nb, t = idx % nb;
+                    c.sX[a * c.xld + t] = num<T>::conj(bget(c, base + t, a));
+                }
+                __syncthreads();
+                lsolve(c, G, k, c.sX, nb);
+                for (int t = tid; t < nb; t += c.nt) {
+                    double h = 0;
+                    for (int a = 0; a < k; ++a) h += num<T>::abs2(c.sX[a * c.xld + t]);
+                    c.sY[base + t] = num<T>::mk(sqrt(h));
+                }
+                __syncthreads();
+            }
+        } else if (A.mode == 0) {
             // seed w0 = G^{-1} b_j^*  (V_0 = diagonals: the SPAI column)
             for (int a = tid; a < k; a += c.nt) c.sX[a * c.xld] = num<T>::zero();
             __syncthreads();
@@ -619,12 +641,12 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
             for (int a = tid; a < k; a += c.nt) c.sW[a] = Z[a * k + lo];
             __syncthreads();
         }
-        bmul(c, m, c.sW, c.sY);
+        if (topk) bmul(c, m, c.sW, c.sY);
         // scores of the admissible rows (ascending row order); -1 elsewhere
         int ncl = 0;
         for (int i = tid; i < m; i += c.nt) {
             int gi = c.sR[i];
-            int adm = (A.vrule == V_TOPK_LOWER) ? (gi > j) : (gi < j);
+            int adm = lowerrule ? (gi > j) : (gi < j);
             c.sScore[i] = adm ? num<T>::abs(c.sY[i]) : -1.0;
             ncl += adm;
         }
@@ -762,7 +784,8 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         for (int a = 0; a < k; ++a) c.sW[a] = ph * c.sW[a];
         // Section 3.2 applies to unit-norm v with a triangular V
         const bool vtri = A.vrule == V_DIAG || A.vrule == V_GS_UPPER || A.vrule == V_GS_LOWER ||
-                          A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER;
+                          A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER ||
+                          A.vrule == V_LEV_UPPER || A.vrule == V_LEV_LOWER;
         const bool stab = A.mode == 0 && A.stab_r > 0.0 && vtri && dpos >= 0 &&
                           num<T>::abs(c.sV[dpos]) < A.stab_tol * vn;
         c.mi[MI_STAB] = stab ? 1 : 0;

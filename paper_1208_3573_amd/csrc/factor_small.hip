@@ -524,8 +524,13 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     }
     // ---- 6. V pattern ----
     const bool topk = A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER;
+    const bool lev = MODE == 0 && (A.vrule == V_LEV_LOWER || A.vrule == V_LEV_UPPER);
+    const bool lowerrule = A.vrule == V_TOPK_LOWER || A.vrule == V_LEV_LOWER;
     int l = 0;
-    if (topk) {
+    if (topk || lev) {
+      const bool adm = lane < m && (lowerrule ? myrow > j : myrow < j);
+      double sc = -1.0;
+      if (topk) {
         // w0 = G^{-1} u with u = conj(B(j, :)): lane c takes the product of
         // its column of -G^{-1} (Hermitian) with u
         if (lane < SKM) S.post.U[lane] = num<T>::zero();
@@ -556,8 +561,55 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
                 int t = S.csr[pp];
                 yr += S.eval[t] * S.post.w[S.ecol[t]];
             }
-        const bool adm = lane < m && (A.vrule == V_TOPK_LOWER ? myrow > j : myrow < j);
-        const double sc = adm ? num<T>::abs(yr) : -1.0;
+        sc = adm ? num<T>::abs(yr) : -1.0;
+      } else {
+        if constexpr (MODE == 0) {
+            // Section 3.1's rule: the score of an admissible row i is the norm
+            // of its column of Q^*, sqrt(h_i) with h_i = b_i G^{-1} b_i^*.
+            // Batches of up to SLM rows go through U (conj rows, dense) and
+            // Y = G^{-1} U as for B_L^* below; the row's lane forms b_i y_i.
+            double hlev = 0.0;
+            uint64_t rem = __ballot(adm);
+            while (rem) {
+                uint64_t bmask = 0;
+                int nb = 0;
+                while (rem && nb < SLM) {
+                    bmask |= rem & (~rem + 1ull);
+                    rem &= rem - 1ull;
+                    ++nb;
+                }
+                for (int q2 = lane; q2 < SLM * SKM; q2 += 64) S.post.U[q2] = num<T>::zero();
+                __syncthreads();
+                const bool inb = (bmask >> lane) & 1ull;
+                const int slot = __popcll(bmask & ((1ull << lane) - 1ull));
+                if (inb)
+                    for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {
+                        const int e = S.csr[pp];
+                        S.post.U[slot * SKM + S.ecol[e]] = num<T>::conj(S.eval[e]);
+                    }
+                __syncthreads();
+                for (int t = 0; t < nb; ++t) {
+                    T acc = num<T>::zero();
+#pragma unroll
+                    for (int i = 0; i < SKH; ++i)
+                        acc -= num<T>::conj(g[i]) * S.post.U[t * SKM + hf * SKH + i];
+                    acc += shfl_xor32(acc);
+                    if (lane < k) S.post.Y[lane * SLM + t] = acc;
+                }
+                __syncthreads();
+                if (inb) {
+                    T h = num<T>::zero();
+                    for (int pp = S.rptr[lane]; pp < S.rptr[lane + 1]; ++pp) {
+                        const int e = S.csr[pp];
+                        h += S.eval[e] * S.post.Y[S.ecol[e] * SLM + slot];
+                    }
+                    hlev = num<T>::re(h);
+                }
+                __syncthreads();
+            }
+            sc = adm ? sqrt(fmax(hlev, 0.0)) : -1.0;
+        }
+      }
         const uint64_t amask = __ballot(adm);
         const int nc = __popcll(amask);
         int lj = A.vcount < 1 ? 1 : A.vcount;
@@ -729,7 +781,8 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
         // first component of U^* p in the paper's notation); w = Y v, the
         // least-squares solution for that v (eq. 2.4).
         const bool vtri = A.vrule == V_DIAG || A.vrule == V_GS_UPPER || A.vrule == V_GS_LOWER ||
-                          A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER;
+                          A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER ||
+                          A.vrule == V_LEV_UPPER || A.vrule == V_LEV_LOWER;
         if (A.stab_r > 0.0 && vtri && dpos >= 0 && num<T>::abs(shfl(vt, dpos)) < A.stab_tol * vn) {
             flags = (flags | DIAF_FLAG_STABILIZED) & ~(DIAF_FLAG_SMALL_DIAG | DIAF_FLAG_GAP_DEGENERATE);
             const int ls = l - 1;

@@ -24,7 +24,7 @@ DIAF_F64, DIAF_C128 = 0, 1
 DIAF_UNIT_V, DIAF_UNIT_W = 0, 1
 DIAF_W_A, DIAF_W_A2, DIAF_W_A_1HOP_TOPK, DIAF_W_EXPLICIT, DIAF_W_LEARNED = range(5)
 DIAF_V_EXPLICIT, DIAF_V_DIAG, DIAF_V_GS_UPPER, DIAF_V_GS_LOWER, DIAF_V_TOPK_UPPER, \
-    DIAF_V_TOPK_LOWER = range(6)
+    DIAF_V_TOPK_LOWER, DIAF_V_LEV_UPPER, DIAF_V_LEV_LOWER = range(8)
 FLAG_RANK_DEFICIENT, FLAG_GAP_DEGENERATE, FLAG_SMALL_DIAG, FLAG_FELL_BACK, FLAG_TIE_EDGE, \
     FLAG_NO_DIAG_ROW = 1, 2, 4, 8, 16, 64
 MLP_NFEAT, MLP_HIDDEN = 16, 64
@@ -227,7 +227,8 @@ W_KINDS = {"A": DIAF_W_A, "A2": DIAF_W_A2, "A_1hop_topk": DIAF_W_A_1HOP_TOPK,
            "explicit": DIAF_W_EXPLICIT, "learned": DIAF_W_LEARNED}
 V_KINDS = {"explicit": DIAF_V_EXPLICIT, "diag": DIAF_V_DIAG, "gs_upper": DIAF_V_GS_UPPER,
            "gs_lower": DIAF_V_GS_LOWER, "topk_upper": DIAF_V_TOPK_UPPER,
-           "topk_lower": DIAF_V_TOPK_LOWER}
+           "topk_lower": DIAF_V_TOPK_LOWER, "lev_upper": DIAF_V_LEV_UPPER,
+           "lev_lower": DIAF_V_LEV_LOWER}
 MODES = {"unit_v": DIAF_UNIT_V, "unit_w": DIAF_UNIT_W}
 
 
