@@ -107,6 +107,42 @@ def pattern_A2(A) -> Pattern:
     return Pattern(A.n, cp, ri)
 
 
+def pattern_alg2(A, v0: str) -> Pattern:
+    """Algorithm 2 (Section 4): the pattern of column j of W is that of
+    A^* v_j for a generic v_j in V_0, i.e. the union of the rows of A at the
+    rows of column j of V_0.  V_0: "diag" (diagonal matrices), "gs_upper" /
+    "gs_lower" (Definition 4.1: the diagonal plus the strictly upper / lower
+    part of pattern(A)).  No sparsification step.  Plain loops over columns."""
+    n = A.n
+    cp = np.asarray(A.colptr, dtype=np.int64)
+    ri = np.asarray(A.rowidx, dtype=np.int64)
+    # rows of A: the column indices of each row
+    order = np.argsort(ri, kind="stable")
+    col_of = np.repeat(np.arange(n), np.diff(cp))[order]
+    rstart = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rstart, ri + 1, 1)
+    rstart = np.cumsum(rstart)
+    out_cp = np.zeros(n + 1, dtype=np.int32)
+    out = []
+    for j in range(n):
+        rows = ri[cp[j]:cp[j + 1]]
+        if v0 == "diag":
+            v0rows = [j]
+        elif v0 == "gs_upper":
+            v0rows = [i for i in rows if i <= j]
+        elif v0 == "gs_lower":
+            v0rows = [i for i in rows if i >= j]
+        else:
+            raise KeyError(v0)
+        if j not in v0rows:
+            v0rows.append(j)
+        u = np.unique(np.concatenate([col_of[rstart[i]:rstart[i + 1]] for i in v0rows]))
+        out.append(u.astype(np.int32))
+        out_cp[j + 1] = out_cp[j] + len(u)
+    return Pattern(n=n, colptr=out_cp,
+                   rowidx=np.concatenate(out) if out else np.zeros(0, np.int32))
+
+
 def pattern_1hop(A, ptop: int) -> Pattern:
     """W pattern = pattern(A) plus the ``ptop`` two-hop rows with the largest
     |A|^2 path weight per column."""
