@@ -69,7 +69,14 @@ typedef enum diaf_norm_mode { DIAF_UNIT_V = 0, DIAF_UNIT_W = 1 } diaf_norm_mode;
  * sum_c |a_ic||a_cj| (dropping by count, Section 4.1); an explicit pattern;
  * or a learned proposal from the A^2 candidates (diaf_model, below). */
 typedef enum diaf_w_kind {
-    DIAF_W_A = 0, DIAF_W_A2 = 1, DIAF_W_A_1HOP_TOPK = 2, DIAF_W_EXPLICIT = 3, DIAF_W_LEARNED = 4
+    DIAF_W_A = 0, DIAF_W_A2 = 1, DIAF_W_A_1HOP_TOPK = 2, DIAF_W_EXPLICIT = 3, DIAF_W_LEARNED = 4,
+    /* Algorithm 2 (Section 4): column j of W has the pattern of A^* v_j for a
+     * generic v_j in V_0, i.e. the union of the rows of A at the pattern of
+     * column j of V_0; V_0 = diagonal matrices (W = pattern(A^*)), or the
+     * Gauss-Seidel structure of Definition 4.1 (diagonal plus the strictly
+     * upper / lower part of pattern(A)).  The optional sparsification step
+     * of the algorithm is not applied. */
+    DIAF_W_ALG2_DIAG = 5, DIAF_W_ALG2_GS_UPPER = 6, DIAF_W_ALG2_GS_LOWER = 7
 } diaf_w_kind;
 
 /* V pattern L: explicit; diagonal; Gauss-Seidel structure (Definition 4.1:
@@ -224,7 +231,7 @@ diaf_status diaf_autotune(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_sp
 
 /* ---- patterns (Section 4) ------------------------------------------------ */
 
-/* W pattern of kind w_kind for A, two-phase: with rowidx_out == NULL,
+/* W pattern of kind w_kind (A, A2, A_1HOP_TOPK, ALG2_*) for A, two-phase: with rowidx_out == NULL,
  * writes colptr_out[n+1] (device) and the total to *nnz_host; then call
  * again with rowidx_out of *nnz_host entries and the same colptr_out. */
 diaf_status diaf_pattern_build(struct diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,

@@ -205,13 +205,67 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
         }
         return {};
     }
+    if (w_kind == DIAF_W_ALG2_DIAG || w_kind == DIAF_W_ALG2_GS_UPPER ||
+        w_kind == DIAF_W_ALG2_GS_LOWER) {
+        // Algorithm 2: column j of W has the pattern of A^* v_j for a generic
+        // v_j in V_0, i.e. the union of the rows of A at the pattern of
+        // column j of V_0 (the union pattern with V_0 as the outer lists and
+        // the rows of A, from its CSR copy, as the inner lists)
+        const int v0 = w_kind - DIAF_W_ALG2_DIAG;
+        int32_t *vcnt = nullptr, *Vcp = nullptr, *Vri = nullptr, *rp = nullptr, *ci = nullptr;
+        int32_t *cnt = nullptr, *mx = nullptr;
+        T* cv = nullptr;
+        struct Free {
+            std::vector<void*> p;
+            ~Free() { for (void* q : p) dfree(q); }
+        } fr;
+        DIAF_TRY(dmalloc(&vcnt, sizeof(int32_t) * (n + 1)));
+        fr.p.push_back(vcnt);
+        DIAF_TRY(dmalloc(&Vcp, sizeof(int32_t) * (n + 1)));
+        fr.p.push_back(Vcp);
+        DIAF_TRY(launch_v0_pattern(n, A->colptr, A->rowidx, v0, vcnt, nullptr, nullptr, st));
+        DIAF_TRY(exclusive_scan_i32(vcnt, Vcp, n, st));
+        int32_t nv = 0;
+        DIAF_TRY(read1(Vcp + n, &nv, st));
+        DIAF_TRY(dmalloc(&Vri, sizeof(int32_t) * (size_t)(nv > 0 ? nv : 1)));
+        fr.p.push_back(Vri);
+        DIAF_TRY(launch_v0_pattern(n, A->colptr, A->rowidx, v0, nullptr, Vcp, Vri, st));
+        DIAF_TRY(dmalloc(&rp, sizeof(int32_t) * (n + 1)));
+        fr.p.push_back(rp);
+        DIAF_TRY(dmalloc(&ci, sizeof(int32_t) * (size_t)A->nnz));
+        fr.p.push_back(ci);
+        DIAF_TRY(dmalloc(&cv, sizeof(T) * (size_t)A->nnz));
+        fr.p.push_back(cv);
+        DIAF_TRY(csc_to_csr<T>(n, A->nnz, A->colptr, A->rowidx, (const T*)A->val, rp, ci, cv, st));
+        DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
+        fr.p.push_back(cnt);
+        DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
+        fr.p.push_back(mx);
+        DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
+        DIAF_TRY(launch_cand_count(n, Vcp, Vri, rp, cnt, mx, st));
+        int32_t maxcand = 0;
+        DIAF_TRY(read1(mx, &maxcand, st));
+        DIAF_TRY(launch_pattern_a2(n, Vcp, Vri, rp, ci, maxcand, cnt, nullptr, nullptr, st));
+        DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
+        int32_t tot = 0;
+        DIAF_TRY(read1(Jcp + n, &tot, st));
+        *nnz_out = tot;
+        int32_t* rows = rows_given;
+        if (!rows && alloc_rows) {
+            DIAF_TRY(dmalloc(Jri_out, sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1)));
+            rows = *Jri_out;
+        }
+        if (rows) DIAF_TRY(launch_pattern_a2(n, Vcp, Vri, rp, ci, maxcand, nullptr, Jcp, rows, st));
+        DIAF_TRY(sync(st));
+        return {};
+    }
     if (w_kind != DIAF_W_A2 && w_kind != DIAF_W_A_1HOP_TOPK)
         return {DIAF_EINVAL, "pattern kind not buildable here"};
     int32_t *cnt = nullptr, *mx = nullptr;
     DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
     DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
     DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
-    DIAF_TRY(launch_cand_count(n, A->colptr, A->rowidx, cnt, mx, st));
+    DIAF_TRY(launch_cand_count(n, A->colptr, A->rowidx, A->colptr, cnt, mx, st));
     int32_t maxcand = 0;
     DIAF_TRY(read1(mx, &maxcand, st));
     // 1-hop rule: columns grouped by their number of two-hop candidates, so
@@ -251,7 +305,8 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
         return {};
     };
     if (w_kind == DIAF_W_A2)
-        DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, maxcand, cnt, nullptr, nullptr, st));
+        DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, A->colptr, A->rowidx, maxcand, cnt,
+                                   nullptr, nullptr, st));
     else
         DIAF_TRY(run_1hop(cnt, nullptr, nullptr));
     DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
@@ -265,7 +320,8 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
     }
     if (rows) {
         if (w_kind == DIAF_W_A2)
-            DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, maxcand, nullptr, Jcp, rows, st));
+            DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, A->colptr, A->rowidx, maxcand,
+                                       nullptr, Jcp, rows, st));
         else
             DIAF_TRY(run_1hop(nullptr, Jcp, rows));
     }
@@ -675,8 +731,10 @@ diaf_status diaf_pattern_build(diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,
     Err e = check_csc_host(A);
     if (e.code) return fail(ctx, e);
     if (!colptr_out || !nnz_host) return fail(ctx, DIAF_EINVAL, "NULL output");
-    if (w_kind != DIAF_W_A && w_kind != DIAF_W_A2 && w_kind != DIAF_W_A_1HOP_TOPK)
-        return fail(ctx, DIAF_EINVAL, "w_kind must be A, A2 or A_1HOP_TOPK");
+    if (w_kind != DIAF_W_A && w_kind != DIAF_W_A2 && w_kind != DIAF_W_A_1HOP_TOPK &&
+        w_kind != DIAF_W_ALG2_DIAG && w_kind != DIAF_W_ALG2_GS_UPPER &&
+        w_kind != DIAF_W_ALG2_GS_LOWER)
+        return fail(ctx, DIAF_EINVAL, "w_kind must be A, A2, A_1HOP_TOPK or ALG2_*");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
     e = A->dtype == DIAF_F64 ? validate_A<double>(A, ctx->stream) : validate_A<zc>(A, ctx->stream);
     if (e.code) return fail(ctx, e);
@@ -705,7 +763,7 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     const bool lev_rule = spec->v_kind == DIAF_V_LEV_UPPER || spec->v_kind == DIAF_V_LEV_LOWER;
     if (lev_rule && mode != DIAF_UNIT_V)
         return fail(ctx, DIAF_EINVAL, "the Section 3.1 V rule is defined for DIAF_UNIT_V");
-    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_LEARNED)
+    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_ALG2_GS_LOWER)
         return fail(ctx, DIAF_EINVAL, "bad w_kind");
     if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
         !std::isfinite(spec->stab_tol))

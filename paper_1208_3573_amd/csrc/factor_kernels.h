@@ -6,12 +6,20 @@
 namespace diaf {
 
 // ---- patterns (pattern.hip) ----
-// cnt[j] = sum over c in rows(A(:,j)) of nnz(A(:,c)); *maxcnt_dev = max.
-Err launch_cand_count(int n, const int32_t* Acp, const int32_t* Ari, int32_t* cnt,
-                      int32_t* maxcnt_dev, hipStream_t st);
-// Symbolic pattern(A^2): count (rowidx == nullptr: writes cnt[j]) or fill.
-Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand, int32_t* cnt,
-                      const int32_t* Jcp, int32_t* Jri, hipStream_t st);
+// Union patterns: column j is the union of the inner lists (Icp/Iri) named
+// by the outer list of column j (Ocp/Ori); pattern(A^2) takes the columns of
+// A for both.  cnt[j] = the total length of those inner lists, *maxcnt_dev
+// the maximum.
+Err launch_cand_count(int n, const int32_t* Ocp, const int32_t* Ori, const int32_t* Icp,
+                      int32_t* cnt, int32_t* maxcnt_dev, hipStream_t st);
+// Symbolic union pattern: count (Jri == nullptr: writes cnt[j]) or fill.
+Err launch_pattern_a2(int n, const int32_t* Ocp, const int32_t* Ori, const int32_t* Icp,
+                      const int32_t* Iri, int maxcand, int32_t* cnt, const int32_t* Jcp,
+                      int32_t* Jri, hipStream_t st);
+// Pattern of V_0 for Algorithm 2 (v0 = 0 diagonal, 1 / 2 Gauss-Seidel upper /
+// lower): count (Vri == nullptr: writes cnt[j]) or fill.
+Err launch_v0_pattern(int n, const int32_t* Acp, const int32_t* Ari, int v0, int32_t* cnt,
+                      const int32_t* Vcp, int32_t* Vri, hipStream_t st);
 // pattern(A) plus the ptop two-hop rows of largest |A|^2 path weight.
 template <class T>
 Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,

@@ -17,15 +17,17 @@
 
 namespace diaf {
 
-__global__ void cand_count_kernel(int n, const int32_t* Acp, const int32_t* Ari, int32_t* cnt,
-                                  int32_t* maxcnt)
+// Candidates of column j of a union pattern: the total length of the inner
+// lists (Icp/Iri) named by the outer list of column j (Ocp/Ori).
+__global__ void cand_count_kernel(int n, const int32_t* Ocp, const int32_t* Ori,
+                                  const int32_t* Icp, int32_t* cnt, int32_t* maxcnt)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     int s = 0;
     if (j < n) {
-        for (int p = Acp[j]; p < Acp[j + 1]; ++p) {
-            int c = Ari[p];
-            s += Acp[c + 1] - Acp[c];
+        for (int p = Ocp[j]; p < Ocp[j + 1]; ++p) {
+            int c = Ori[p];
+            s += Icp[c + 1] - Icp[c];
         }
         cnt[j] = s;
     }
@@ -34,11 +36,11 @@ __global__ void cand_count_kernel(int n, const int32_t* Acp, const int32_t* Ari,
     if ((threadIdx.x & 63) == 0) atomicMax(maxcnt, s);
 }
 
-Err launch_cand_count(int n, const int32_t* Acp, const int32_t* Ari, int32_t* cnt,
-                      int32_t* maxcnt_dev, hipStream_t st)
+Err launch_cand_count(int n, const int32_t* Ocp, const int32_t* Ori, const int32_t* Icp,
+                      int32_t* cnt, int32_t* maxcnt_dev, hipStream_t st)
 {
-    hipLaunchKernelGGL(cand_count_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Ari, cnt,
-                       maxcnt_dev);
+    hipLaunchKernelGGL(cand_count_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Ocp, Ori, Icp,
+                       cnt, maxcnt_dev);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
@@ -112,8 +114,12 @@ __device__ inline int block_scan01(int32_t* f, int cnt, int32_t* red)
 
 // pattern(A^2), one block per column; cap candidates max (power of two),
 // dynamic LDS: keys[cap] u32, off[cap+1] i32, red[nthreads+1] i32.
-__global__ void pattern_a2_kernel(int n, const int32_t* Acp, const int32_t* Ari, int cap,
-                                  int32_t* cnt, const int32_t* Jcp, int32_t* Jri)
+// Column j of the union pattern: the sorted union of the inner lists
+// (Icp/Iri) named by the outer list of column j (Ocp/Ori).  pattern(A^2):
+// outer and inner lists are both the columns of A.
+__global__ void pattern_a2_kernel(int n, const int32_t* Ocp, const int32_t* Ori,
+                                  const int32_t* Icp, const int32_t* Iri, int cap, int32_t* cnt,
+                                  const int32_t* Jcp, int32_t* Jri)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint32_t* keys = (uint32_t*)lds;
@@ -122,12 +128,12 @@ __global__ void pattern_a2_kernel(int n, const int32_t* Acp, const int32_t* Ari,
     __shared__ int32_t s_tot;
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
-    const int a0 = Acp[j], na = Acp[j + 1] - a0;
+    const int a0 = Ocp[j], na = Ocp[j + 1] - a0;
     if (tid == 0) {
         off[0] = 0;
         for (int q = 0; q < na; ++q) {
-            int c = Ari[a0 + q];
-            off[q + 1] = off[q] + (Acp[c + 1] - Acp[c]);
+            int c = Ori[a0 + q];
+            off[q + 1] = off[q] + (Icp[c + 1] - Icp[c]);
         }
         s_tot = off[na];
     }
@@ -142,8 +148,8 @@ __global__ void pattern_a2_kernel(int n, const int32_t* Acp, const int32_t* Ari,
                 int mid = (lo + hi + 1) >> 1;
                 if (off[mid] <= t) lo = mid; else hi = mid - 1;
             }
-            int c = Ari[a0 + lo];
-            keys[t] = (uint32_t)Ari[Acp[c] + (t - off[lo])];
+            int c = Ori[a0 + lo];
+            keys[t] = (uint32_t)Iri[Icp[c] + (t - off[lo])];
         } else {
             keys[t] = 0xffffffffu;
         }
@@ -163,6 +169,36 @@ __global__ void pattern_a2_kernel(int n, const int32_t* Acp, const int32_t* Ari,
         if (t == 0 || keys[t] != keys[t - 1]) out[off[t]] = (int32_t)keys[t];
 }
 
+// Pattern of the initial subspace V_0 of Algorithm 2: the diagonal
+// (v0 = 0) or the Gauss-Seidel structure (Definition 4.1): the diagonal plus
+// the strictly upper (v0 = 1) or lower (v0 = 2) part of pattern(A), column
+// by column.  Counting pass (rows == nullptr) or filling pass.
+__global__ void v0_pattern_kernel(int n, const int32_t* Acp, const int32_t* Ari, int v0,
+                                  int32_t* cnt, const int32_t* Vcp, int32_t* Vri)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int c = 0;
+    for (int p = Acp[j]; p < Acp[j + 1]; ++p) {
+        const int i = Ari[p];
+        const bool keep = i == j || (v0 == 1 && i < j) || (v0 == 2 && i > j);
+        if (!keep) continue;
+        if (Vri) Vri[Vcp[j] + c] = i;
+        ++c;
+    }
+    if (!Vri) cnt[j] = c;
+}
+
+Err launch_v0_pattern(int n, const int32_t* Acp, const int32_t* Ari, int v0, int32_t* cnt,
+                      const int32_t* Vcp, int32_t* Vri, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(v0_pattern_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Ari, v0,
+                       cnt, Vcp, Vri);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
 static int pow2_at_least(int x)
 {
     int p = 1;
@@ -170,8 +206,9 @@ static int pow2_at_least(int x)
     return p;
 }
 
-Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand, int32_t* cnt,
-                      const int32_t* Jcp, int32_t* Jri, hipStream_t st)
+Err launch_pattern_a2(int n, const int32_t* Ocp, const int32_t* Ori, const int32_t* Icp,
+                      const int32_t* Iri, int maxcand, int32_t* cnt, const int32_t* Jcp,
+                      int32_t* Jri, hipStream_t st)
 {
     if (n == 0) return {};
     int cap = pow2_at_least(maxcand < 64 ? 64 : maxcand);
@@ -180,8 +217,8 @@ Err launch_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int maxcand
     size_t lds = sizeof(uint32_t) * cap + sizeof(int32_t) * (cap + 1) + sizeof(int32_t) * (nt + 1);
     DIAF_HIP_TRY(hipFuncSetAttribute((const void*)pattern_a2_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(pattern_a2_kernel, dim3(n), dim3(nt), lds, st, n, Acp, Ari, cap, cnt, Jcp,
-                       Jri);
+    hipLaunchKernelGGL(pattern_a2_kernel, dim3(n), dim3(nt), lds, st, n, Ocp, Ori, Icp, Iri, cap,
+                       cnt, Jcp, Jri);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }

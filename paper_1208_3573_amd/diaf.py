@@ -22,7 +22,8 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "EUNSUPPORTED", "ESINGULAR"
                 "EBREAKDOWN"]
 DIAF_F64, DIAF_C128 = 0, 1
 DIAF_UNIT_V, DIAF_UNIT_W = 0, 1
-DIAF_W_A, DIAF_W_A2, DIAF_W_A_1HOP_TOPK, DIAF_W_EXPLICIT, DIAF_W_LEARNED = range(5)
+DIAF_W_A, DIAF_W_A2, DIAF_W_A_1HOP_TOPK, DIAF_W_EXPLICIT, DIAF_W_LEARNED, DIAF_W_ALG2_DIAG, \
+    DIAF_W_ALG2_GS_UPPER, DIAF_W_ALG2_GS_LOWER = range(8)
 DIAF_V_EXPLICIT, DIAF_V_DIAG, DIAF_V_GS_UPPER, DIAF_V_GS_LOWER, DIAF_V_TOPK_UPPER, \
     DIAF_V_TOPK_LOWER, DIAF_V_LEV_UPPER, DIAF_V_LEV_LOWER = range(8)
 FLAG_RANK_DEFICIENT, FLAG_GAP_DEGENERATE, FLAG_SMALL_DIAG, FLAG_FELL_BACK, FLAG_TIE_EDGE, \
@@ -224,7 +225,8 @@ class DevicePattern:
 
 
 W_KINDS = {"A": DIAF_W_A, "A2": DIAF_W_A2, "A_1hop_topk": DIAF_W_A_1HOP_TOPK,
-           "explicit": DIAF_W_EXPLICIT, "learned": DIAF_W_LEARNED}
+           "explicit": DIAF_W_EXPLICIT, "learned": DIAF_W_LEARNED, "alg2_diag": DIAF_W_ALG2_DIAG,
+           "alg2_gs_upper": DIAF_W_ALG2_GS_UPPER, "alg2_gs_lower": DIAF_W_ALG2_GS_LOWER}
 V_KINDS = {"explicit": DIAF_V_EXPLICIT, "diag": DIAF_V_DIAG, "gs_upper": DIAF_V_GS_UPPER,
            "gs_lower": DIAF_V_GS_LOWER, "topk_upper": DIAF_V_TOPK_UPPER,
            "topk_lower": DIAF_V_TOPK_LOWER, "lev_upper": DIAF_V_LEV_UPPER,
