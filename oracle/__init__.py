@@ -143,6 +143,78 @@ def pattern_alg2(A, v0: str) -> Pattern:
                    rowidx=np.concatenate(out) if out else np.zeros(0, np.int32))
 
 
+def _drop(rows, vals, tau, p, keep):
+    """Numerical dropping by tolerance and count (Section 4): entries with
+    |v|^2 >= tau^2 max |v|^2 (tau > 0), then at most p of them, the largest
+    (p > 0; ties to the lower row); the entry of row `keep` (the diagonal of
+    the column) is never dropped and does not count against p.  Squared
+    magnitudes are formed as v * v."""
+    if not rows:
+        return rows, vals
+    mag = [v * v for v in vals]
+    mx = max(mag)
+    thr = tau * tau * mx if tau > 0 else None
+    cand = [t for t in range(len(rows)) if rows[t] != keep and (thr is None or mag[t] >= thr)]
+    if p > 0 and len(cand) > p:
+        cand = sorted(cand, key=lambda t: (-mag[t], rows[t]))[:p]
+    kept = set(cand) | {t for t in range(len(rows)) if rows[t] == keep}
+    idx = sorted(kept, key=lambda t: rows[t])
+    return [rows[t] for t in idx], [vals[t] for t in idx]
+
+
+def pattern_sparsified_powers(A, k: int = 3, tau_i: float = 0.1, p_i: int = 0,
+                              tau_l: float = 0.0, p_l: int = 0) -> Pattern:
+    """Algorithm 1 (Section 4) with V_0 = the diagonal matrices: S =
+    V_0^{-1}(I - P_{V_0})A, i.e. S(i, c) = a_ic / a_ii off the diagonal; its
+    columns dropped by (tau_i, p_i); then per column j, s = t = e_j and k
+    times t <- S t (products accumulated per row in ascending source row, as
+    separate multiplies and adds), dropped by (tau_l, p_l), s <- s + t; the
+    pattern of w_j is that of s, taken structurally (e_j and every kept entry
+    of every t).  With V_0 diagonal the final removal of V_0 minus the
+    identity removes nothing.  Real matrices with a nonzero diagonal; pure
+    Python, for small cases."""
+    if np.iscomplexobj(A.val):
+        raise ValueError("sparsified powers: real matrices only")
+    n = A.n
+    cp = [int(x) for x in A.colptr]
+    ri = [int(x) for x in A.rowidx]
+    va = [float(x) for x in A.val]
+    d = [0.0] * n
+    for c in range(n):
+        for q in range(cp[c], cp[c + 1]):
+            if ri[q] == c:
+                d[c] = va[q]
+    if any(x == 0.0 for x in d):
+        raise ValueError("sparsified powers: zero or missing diagonal entry")
+    S = []
+    for c in range(n):
+        rows, vals = [], []
+        for q in range(cp[c], cp[c + 1]):
+            i = ri[q]
+            if i != c:
+                rows.append(i)
+                vals.append(va[q] / d[i])
+        S.append(_drop(rows, vals, tau_i, p_i, keep=-1))
+    out_cp = np.zeros(n + 1, dtype=np.int32)
+    out = []
+    for j in range(n):
+        srows = {j}
+        t_rows, t_vals = [j], [1.0]
+        for _ in range(k):
+            acc = {}
+            for i, ti in zip(t_rows, t_vals):  # ascending source row
+                r_rows, r_vals = S[i]
+                for r, v in zip(r_rows, r_vals):
+                    acc[r] = acc[r] + v * ti if r in acc else v * ti
+            rows = sorted(acc)
+            t_rows, t_vals = _drop(rows, [acc[r] for r in rows], tau_l, p_l, keep=j)
+            srows.update(t_rows)
+        u = np.array(sorted(srows), dtype=np.int32)
+        out.append(u)
+        out_cp[j + 1] = out_cp[j] + len(u)
+    return Pattern(n=n, colptr=out_cp, rowidx=np.concatenate(out))
+
+
 def pattern_1hop(A, ptop: int) -> Pattern:
     """W pattern = pattern(A) plus the ``ptop`` two-hop rows with the largest
     |A|^2 path weight per column."""
