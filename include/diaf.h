@@ -76,8 +76,36 @@ typedef enum diaf_w_kind {
      * Gauss-Seidel structure of Definition 4.1 (diagonal plus the strictly
      * upper / lower part of pattern(A)).  The optional sparsification step
      * of the algorithm is not applied. */
-    DIAF_W_ALG2_DIAG = 5, DIAF_W_ALG2_GS_UPPER = 6, DIAF_W_ALG2_GS_LOWER = 7
+    DIAF_W_ALG2_DIAG = 5, DIAF_W_ALG2_GS_UPPER = 6, DIAF_W_ALG2_GS_LOWER = 7,
+    /* Algorithm 1 (Section 4), sparsified powers with V_0 the diagonal
+     * matrices, real A only (DIAF_EUNSUPPORTED for DIAF_C128): parameters in
+     * diaf_spec.sparsify / diaf_pattern_build_sparsified. */
+    DIAF_W_SPARSIFIED = 8
 } diaf_w_kind;
+
+/* Parameters of the sparsified powers W pattern (Section 4, Algorithm 1,
+ * V_0 = diagonal matrices).  With D = diag(A) and S = D^{-1}(A - D), i.e.
+ * S(i, c) = a_ic / a_ii off the diagonal: each column of S is first
+ * sparsified by (tau_i, p_i); then, for every column j, t = e_j is
+ * multiplied by S k times, each product sparsified by (tau_l, p_l) with its
+ * entry in row j never dropped, and the pattern of w_j is the union of e_j
+ * and every kept t.  Dropping by tolerance keeps the entries with
+ * v^2 >= tau^2 max v^2 over the vector; dropping by count then keeps the p
+ * largest (equal magnitudes: the lower rows); a zero parameter disables its
+ * rule.  Products are summed in ascending source row with round-to-nearest
+ * multiplies and adds, so the pattern is reproducible bit for bit.  k in
+ * 1..8; p_i, p_l in 0..2^20; tau_i, tau_l finite and >= 0 (else
+ * DIAF_EINVAL); a zero diagonal entry is DIAF_EINVAL; a column of A with
+ * more than 1024 entries, a power vector of more than 2048 rows or a
+ * pattern of more than 4096 rows is DIAF_EUNSUPPORTED. */
+typedef struct diaf_sparsify {
+    int32_t k;        /* truncation of the series I + S + ... + S^k */
+    int32_t p_i;      /* count limit on the columns of S */
+    int32_t p_l;      /* count limit on every power vector t */
+    int32_t reserved; /* 0 */
+    double tau_i;     /* relative tolerance on the columns of S */
+    double tau_l;     /* relative tolerance on every power vector t */
+} diaf_sparsify;
 
 /* V pattern L: explicit; diagonal; Gauss-Seidel structure (Definition 4.1:
  * diagonal plus the strictly upper / lower part of pattern(A)); the optimal
@@ -144,6 +172,7 @@ typedef struct diaf_spec {
                                         solution for that v_j; flag DIAF_FLAG_STABILIZED
                                         (0 = off; the paper's experiment uses 2) */
     double stab_tol;                 /* trigger of stab_r (the paper's experiment: 1e-2) */
+    diaf_sparsify sparsify;          /* DIAF_W_SPARSIFIED */
 } diaf_spec;
 
 /* Borrowed device views of a factorization.  W has the pattern J (Wcp/Wri)
@@ -237,6 +266,14 @@ diaf_status diaf_autotune(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_sp
 diaf_status diaf_pattern_build(struct diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,
                                int32_t w_topk, int32_t* colptr_out, int32_t* rowidx_out,
                                int64_t* nnz_host);
+
+/* The sparsified powers W pattern (Section 4, Algorithm 1; parameters and
+ * errors as for diaf_sparsify) for real A, two-phase like
+ * diaf_pattern_build: colptr_out[n+1] (device) and *nnz_host first, then
+ * rowidx_out (device, *nnz_host entries, ascending rows per column). */
+diaf_status diaf_pattern_build_sparsified(struct diaf_ctx* ctx, const diaf_csc* A,
+                                          const diaf_sparsify* prm, int32_t* colptr_out,
+                                          int32_t* rowidx_out, int64_t* nnz_host);
 
 /* ---- factoring (Sections 2-3) -------------------------------------------- */
 

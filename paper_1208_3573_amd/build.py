@@ -24,6 +24,7 @@ ARCH = os.environ.get("DIAF_ARCH", "gfx950")
 SOURCES = [
     "diaf_api.cpp",
     "pattern.hip",
+    "sparsify.hip",
     "factor_generic.hip",
     "factor_small.hip",
     "sparse.hip",

@@ -185,12 +185,105 @@ Err validate_pattern(const diaf_pattern* P, int64_t n, int need_diag, const char
     return {};
 }
 
+Err check_sparsify(const diaf_sparsify* sp)
+{
+    if (!sp) return {DIAF_EINVAL, "sparsified powers: parameters are NULL"};
+    if (sp->k < 1 || sp->k > 8) return {DIAF_EINVAL, "sparsified powers: k must be in 1..8"};
+    if (sp->p_i < 0 || sp->p_i > (1 << 20) || sp->p_l < 0 || sp->p_l > (1 << 20))
+        return {DIAF_EINVAL, "sparsified powers: p_i and p_l must be in 0..2^20"};
+    if (!(sp->tau_i >= 0.0) || !std::isfinite(sp->tau_i) || !(sp->tau_l >= 0.0) ||
+        !std::isfinite(sp->tau_l))
+        return {DIAF_EINVAL, "sparsified powers: tau_i and tau_l must be finite and >= 0"};
+    return {};
+}
+
+// Algorithm 1 (Section 4) with V_0 = diagonals: S built and sparsified once,
+// then the per-column level expansion, counted and filled; columns that
+// outgrow the small LDS tables are rerun with the large ones.
+Err build_sparsified(const diaf_csc* A, const diaf_sparsify* sp, int32_t* Jcp, int32_t** Jri_out,
+                     int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st)
+{
+    if (A->dtype != DIAF_F64)
+        return {DIAF_EUNSUPPORTED, "sparsified powers: real matrices only"};
+    DIAF_TRY(check_sparsify(sp));
+    const int n = (int)A->n;
+    const size_t nnz = (size_t)A->nnz;
+    struct Free {
+        std::vector<void*> p;
+        ~Free() { for (void* q : p) dfree(q); }
+    } fr;
+    double *d = nullptr, *Sval = nullptr;
+    int32_t *bad = nullptr, *Sri = nullptr, *scnt = nullptr, *cnt = nullptr, *lists = nullptr,
+            *nover = nullptr;
+    DIAF_TRY(dmalloc(&d, sizeof(double) * (size_t)n));
+    fr.p.push_back(d);
+    DIAF_TRY(dmalloc(&Sval, sizeof(double) * nnz));
+    fr.p.push_back(Sval);
+    DIAF_TRY(dmalloc(&Sri, sizeof(int32_t) * nnz));
+    fr.p.push_back(Sri);
+    DIAF_TRY(dmalloc(&scnt, sizeof(int32_t) * (size_t)n));
+    fr.p.push_back(scnt);
+    DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (size_t)(n + 1)));
+    fr.p.push_back(cnt);
+    DIAF_TRY(dmalloc(&lists, sizeof(int32_t) * 2 * (size_t)n));  // deferred, then failed columns
+    fr.p.push_back(lists);
+    DIAF_TRY(dmalloc(&bad, sizeof(int32_t) * 3));  // bad flags, #deferred, #failed
+    fr.p.push_back(bad);
+    nover = bad + 1;
+    int32_t* deferred = lists;
+    int32_t* failed = lists + n;
+    DIAF_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t) * 3, st));
+    const double* Aval = (const double*)A->val;
+    DIAF_TRY(launch_sp_diag(n, A->colptr, A->rowidx, Aval, d, bad, st));
+    DIAF_TRY(launch_sp_build_s(n, A->colptr, A->rowidx, Aval, d, sp->tau_i, sp->p_i, Sri, Sval,
+                               scnt, bad, st));
+    int32_t flags = 0;
+    DIAF_TRY(read1(bad, &flags, st));
+    if (flags & 1)
+        return {DIAF_EINVAL, "sparsified powers: A has a zero diagonal entry (D^{-1} undefined)"};
+    if (flags & 2)
+        return {DIAF_EUNSUPPORTED, "sparsified powers: a column of A has more than 1024 entries"};
+    DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l, nullptr, n,
+                              0, cnt, nullptr, nullptr, deferred, nover, st));
+    int32_t ndef = 0;
+    DIAF_TRY(read1(nover, &ndef, st));
+    if (ndef > 0) {
+        DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l,
+                                  deferred, ndef, 1, cnt, nullptr, nullptr, failed, nover + 1, st));
+        int32_t nfail = 0;
+        DIAF_TRY(read1(nover + 1, &nfail, st));
+        if (nfail > 0)
+            return {DIAF_EUNSUPPORTED, "sparsified powers: a power vector exceeds 2048 rows or a "
+                                       "pattern 4096 rows"};
+    }
+    DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
+    int32_t tot = 0;
+    DIAF_TRY(read1(Jcp + n, &tot, st));
+    *nnz_out = tot;
+    int32_t* rows = rows_given;
+    if (!rows && alloc_rows) {
+        DIAF_TRY(dmalloc(Jri_out, sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1)));
+        rows = *Jri_out;
+    }
+    if (rows) {
+        DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l,
+                                  nullptr, n, 0, nullptr, Jcp, rows, nullptr, nullptr, st));
+        DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l,
+                                  deferred, ndef, 1, nullptr, Jcp, rows, nullptr, nullptr, st));
+    }
+    DIAF_TRY(sync(st));
+    return {};
+}
+
 // Builds the W pattern (colptr, rowidx allocated here unless provided).
 template <class T>
 Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32_t** Jri_out,
-                  int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st)
+                  int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st,
+                  const diaf_sparsify* sp = nullptr)
 {
     const int n = (int)A->n;
+    if (w_kind == DIAF_W_SPARSIFIED)
+        return build_sparsified(A, sp, Jcp, Jri_out, nnz_out, alloc_rows, rows_given, st);
     if (w_kind == DIAF_W_A) {
         DIAF_HIP_TRY(hipMemcpyAsync(Jcp, A->colptr, sizeof(int32_t) * (n + 1),
                                     hipMemcpyDeviceToDevice, st));
@@ -734,7 +827,8 @@ diaf_status diaf_pattern_build(diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,
     if (w_kind != DIAF_W_A && w_kind != DIAF_W_A2 && w_kind != DIAF_W_A_1HOP_TOPK &&
         w_kind != DIAF_W_ALG2_DIAG && w_kind != DIAF_W_ALG2_GS_UPPER &&
         w_kind != DIAF_W_ALG2_GS_LOWER)
-        return fail(ctx, DIAF_EINVAL, "w_kind must be A, A2, A_1HOP_TOPK or ALG2_*");
+        return fail(ctx, DIAF_EINVAL, "w_kind must be A, A2, A_1HOP_TOPK or ALG2_* (the "
+                                      "sparsified powers: diaf_pattern_build_sparsified)");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
     e = A->dtype == DIAF_F64 ? validate_A<double>(A, ctx->stream) : validate_A<zc>(A, ctx->stream);
     if (e.code) return fail(ctx, e);
@@ -744,6 +838,27 @@ diaf_status diaf_pattern_build(diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,
                                     rowidx_out, ctx->stream)
             : build_pattern<zc>(A, w_kind, w_topk, colptr_out, &none, nnz_host, false, rowidx_out,
                                 ctx->stream);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_pattern_build_sparsified(diaf_ctx* ctx, const diaf_csc* A,
+                                          const diaf_sparsify* prm, int32_t* colptr_out,
+                                          int32_t* rowidx_out, int64_t* nnz_host)
+{
+    if (!ctx) return DIAF_EINVAL;
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (!colptr_out || !nnz_host) return fail(ctx, DIAF_EINVAL, "NULL output");
+    e = check_sparsify(prm);
+    if (e.code) return fail(ctx, e);
+    if (A->dtype != DIAF_F64)
+        return fail(ctx, DIAF_EUNSUPPORTED, "sparsified powers: real matrices only");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    e = validate_A<double>(A, ctx->stream);
+    if (e.code) return fail(ctx, e);
+    int32_t* none = nullptr;
+    e = build_sparsified(A, prm, colptr_out, &none, nnz_host, false, rowidx_out, ctx->stream);
     if (e.code) return fail(ctx, e);
     return DIAF_OK;
 }
@@ -763,8 +878,14 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     const bool lev_rule = spec->v_kind == DIAF_V_LEV_UPPER || spec->v_kind == DIAF_V_LEV_LOWER;
     if (lev_rule && mode != DIAF_UNIT_V)
         return fail(ctx, DIAF_EINVAL, "the Section 3.1 V rule is defined for DIAF_UNIT_V");
-    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_ALG2_GS_LOWER)
+    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_SPARSIFIED)
         return fail(ctx, DIAF_EINVAL, "bad w_kind");
+    if (spec->w_kind == DIAF_W_SPARSIFIED) {
+        Err es = check_sparsify(&spec->sparsify);
+        if (es.code) return fail(ctx, es);
+        if (A->dtype != DIAF_F64)
+            return fail(ctx, DIAF_EUNSUPPORTED, "sparsified powers: real matrices only");
+    }
     if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
         !std::isfinite(spec->stab_tol))
         return fail(ctx, DIAF_EINVAL, "stab_r and stab_tol must be finite and >= 0");
@@ -986,7 +1107,7 @@ Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mod
         DIAF_TRY(learned_pattern<T>(ctx, A, spec->model, F.get(), &Ccp, &Cri, &nnzC));
     } else {
         DIAF_TRY(build_pattern<T>(A, spec->w_kind, spec->w_topk, F->Jcp, &F->Jri, &F->nnzW, true,
-                                  nullptr, st));
+                                  nullptr, st, &spec->sparsify));
     }
     DIAF_HIP_TRY(hipEventRecord(ev[1], st));
     // ---- V pattern capacity ----

@@ -23,7 +23,7 @@ STATUS_NAMES = ["OK", "EINVAL", "ENOMEM", "EDEVICE", "EUNSUPPORTED", "ESINGULAR"
 DIAF_F64, DIAF_C128 = 0, 1
 DIAF_UNIT_V, DIAF_UNIT_W = 0, 1
 DIAF_W_A, DIAF_W_A2, DIAF_W_A_1HOP_TOPK, DIAF_W_EXPLICIT, DIAF_W_LEARNED, DIAF_W_ALG2_DIAG, \
-    DIAF_W_ALG2_GS_UPPER, DIAF_W_ALG2_GS_LOWER = range(8)
+    DIAF_W_ALG2_GS_UPPER, DIAF_W_ALG2_GS_LOWER, DIAF_W_SPARSIFIED = range(9)
 DIAF_V_EXPLICIT, DIAF_V_DIAG, DIAF_V_GS_UPPER, DIAF_V_GS_LOWER, DIAF_V_TOPK_UPPER, \
     DIAF_V_TOPK_LOWER, DIAF_V_LEV_UPPER, DIAF_V_LEV_LOWER = range(8)
 FLAG_RANK_DEFICIENT, FLAG_GAP_DEGENERATE, FLAG_SMALL_DIAG, FLAG_FELL_BACK, FLAG_TIE_EDGE, \
@@ -41,12 +41,17 @@ class diaf_pattern(ctypes.Structure):
     _fields_ = [("n", c_int64), ("nnz", c_int64), ("colptr", c_void_p), ("rowidx", c_void_p)]
 
 
+class diaf_sparsify(ctypes.Structure):
+    _fields_ = [("k", c_int32), ("p_i", c_int32), ("p_l", c_int32), ("reserved", c_int32),
+                ("tau_i", c_double), ("tau_l", c_double)]
+
+
 class diaf_spec(ctypes.Structure):
     _fields_ = [("w_kind", c_int32), ("w_topk", c_int32), ("w_explicit", POINTER(diaf_pattern)),
                 ("model", c_void_p), ("gate_tau", c_double), ("v_kind", c_int32),
                 ("v_count", c_int32), ("v_explicit", POINTER(diaf_pattern)),
                 ("gram_fp32", c_int32), ("gate_dom", c_double), ("stab_r", c_double),
-                ("stab_tol", c_double)]
+                ("stab_tol", c_double), ("sparsify", diaf_sparsify)]
 
 
 class diaf_view(ctypes.Structure):
@@ -83,6 +88,8 @@ _SIGS = {
     "diaf_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t]),
     "diaf_pattern_build": (c_int, [c_void_p, POINTER(diaf_csc), c_int32, c_int32, c_void_p,
                                    c_void_p, POINTER(c_int64)]),
+    "diaf_pattern_build_sparsified": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_sparsify),
+                                              c_void_p, c_void_p, POINTER(c_int64)]),
     "diaf_factor": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_spec), c_int32,
                             POINTER(c_void_p)]),
     "diaf_factors_view": (c_int, [c_void_p, POINTER(diaf_view)]),
@@ -226,7 +233,8 @@ class DevicePattern:
 
 W_KINDS = {"A": DIAF_W_A, "A2": DIAF_W_A2, "A_1hop_topk": DIAF_W_A_1HOP_TOPK,
            "explicit": DIAF_W_EXPLICIT, "learned": DIAF_W_LEARNED, "alg2_diag": DIAF_W_ALG2_DIAG,
-           "alg2_gs_upper": DIAF_W_ALG2_GS_UPPER, "alg2_gs_lower": DIAF_W_ALG2_GS_LOWER}
+           "alg2_gs_upper": DIAF_W_ALG2_GS_UPPER, "alg2_gs_lower": DIAF_W_ALG2_GS_LOWER,
+           "sparsified": DIAF_W_SPARSIFIED}
 V_KINDS = {"explicit": DIAF_V_EXPLICIT, "diag": DIAF_V_DIAG, "gs_upper": DIAF_V_GS_UPPER,
            "gs_lower": DIAF_V_GS_LOWER, "topk_upper": DIAF_V_TOPK_UPPER,
            "topk_lower": DIAF_V_TOPK_LOWER, "lev_upper": DIAF_V_LEV_UPPER,
@@ -236,7 +244,9 @@ MODES = {"unit_v": DIAF_UNIT_V, "unit_w": DIAF_UNIT_W}
 
 def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | None = None,
               v_explicit: DevicePattern | None = None, model=None, gate_tau=float("inf"),
-              gram_fp32=False, gate_dom=0.0, stab_r=0.0, stab_tol=1e-2):
+              gram_fp32=False, gate_dom=0.0, stab_r=0.0, stab_tol=1e-2, sparsify=None):
+    """sparsify: dict of k, tau_i, p_i, tau_l, p_l for w="sparsified"
+    (defaults k=3, tau_i=0.1, no other dropping)."""
     spec = diaf_spec()
     spec.w_kind = W_KINDS[w]
     spec.w_topk = w_topk
@@ -250,6 +260,7 @@ def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | 
     spec.gate_dom = gate_dom
     spec.stab_r = stab_r
     spec.stab_tol = stab_tol
+    spec.sparsify = make_sparsify(**(sparsify or {}))
     spec._keep = (w_explicit, v_explicit, model)
     return spec
 
@@ -336,6 +347,31 @@ def diaf_solve(ctx: Context, A: DeviceCSC, F: Factors | None, b, x, rtol=1e-8, m
         return info
     ctx.check(rc)
     return info
+
+
+def make_sparsify(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0) -> diaf_sparsify:
+    sp = diaf_sparsify()
+    sp.k, sp.p_i, sp.p_l, sp.reserved = k, p_i, p_l, 0
+    sp.tau_i, sp.tau_l = tau_i, tau_l
+    return sp
+
+
+def diaf_pattern_build_sparsified(ctx: Context, A: DeviceCSC, k=3, tau_i=0.1, p_i=0, tau_l=0.0,
+                                  p_l=0):
+    """Sparsified powers W pattern (Algorithm 1) on the device; returns
+    (colptr, rowidx) tensors."""
+    torch = _torch()
+    sp = make_sparsify(k, tau_i, p_i, tau_l, p_l)
+    cp = torch.empty(A.n + 1, dtype=torch.int32, device=A.colptr.device)
+    nnz = c_int64()
+    ctx.check(ctx.lib.diaf_pattern_build_sparsified(ctx.h, ctypes.byref(A.desc), ctypes.byref(sp),
+                                                    c_void_p(cp.data_ptr()), None,
+                                                    ctypes.byref(nnz)))
+    ri = torch.empty(max(1, nnz.value), dtype=torch.int32, device=A.colptr.device)
+    ctx.check(ctx.lib.diaf_pattern_build_sparsified(ctx.h, ctypes.byref(A.desc), ctypes.byref(sp),
+                                                    c_void_p(cp.data_ptr()),
+                                                    c_void_p(ri.data_ptr()), ctypes.byref(nnz)))
+    return cp, ri[: nnz.value]
 
 
 def diaf_pattern_build(ctx: Context, A: DeviceCSC, w_kind: str, w_topk: int = 0):
