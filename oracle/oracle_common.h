@@ -28,7 +28,8 @@
 
 /* V pattern rules. */
 enum { ORC_V_EXPLICIT = 0, ORC_V_DIAG = 1, ORC_V_GS_UPPER = 2, ORC_V_GS_LOWER = 3,
-       ORC_V_TOPK_UPPER = 4, ORC_V_TOPK_LOWER = 5, ORC_V_LEV_UPPER = 6, ORC_V_LEV_LOWER = 7 };
+       ORC_V_TOPK_UPPER = 4, ORC_V_TOPK_LOWER = 5, ORC_V_LEV_UPPER = 6, ORC_V_LEV_LOWER = 7,
+       ORC_V_TOPK_BLOCK = 8 };
 /* Norm modes: unit-norm columns of V (first basic algorithm, DIAF-Q) or of
  * W (second basic algorithm, DIAF-S). */
 enum { ORC_UNIT_V = 0, ORC_UNIT_W = 1 };
