@@ -118,7 +118,16 @@ typedef struct diaf_sparsify {
  * DIAF_UNIT_W).  Ties within 1e-10 relative go to the lower row. */
 typedef enum diaf_v_kind {
     DIAF_V_EXPLICIT = 0, DIAF_V_DIAG = 1, DIAF_V_GS_UPPER = 2, DIAF_V_GS_LOWER = 3,
-    DIAF_V_TOPK_UPPER = 4, DIAF_V_TOPK_LOWER = 5, DIAF_V_LEV_UPPER = 6, DIAF_V_LEV_LOWER = 7
+    DIAF_V_TOPK_UPPER = 4, DIAF_V_TOPK_LOWER = 5, DIAF_V_LEV_UPPER = 6, DIAF_V_LEV_LOWER = 7,
+    /* Block diagonal V (Section 5: V the block diagonal matrices of the
+     * splitting A = L + D + U; consecutive blocks given by diaf_spec.v_blocks,
+     * at most 64 rows each, else DIAF_EUNSUPPORTED): the pattern of D, i.e.
+     * the rows of A(:, j) inside j's block (BLOCK), or the diagonal plus the
+     * v_count-1 other rows of j's block with the largest |A w0|, w0 as for
+     * TOPK (TOPK_BLOCK).  V^{-1} is applied through an LU with partial
+     * pivoting of each block, computed on the first apply or solve; a
+     * singular block makes them return DIAF_ESINGULAR. */
+    DIAF_V_BLOCK = 8, DIAF_V_TOPK_BLOCK = 9
 } diaf_v_kind;
 
 /* Per-column flag bits (diaf_view.flags). */
@@ -173,12 +182,17 @@ typedef struct diaf_spec {
                                         (0 = off; the paper's experiment uses 2) */
     double stab_tol;                 /* trigger of stab_r (the paper's experiment: 1e-2) */
     diaf_sparsify sparsify;          /* DIAF_W_SPARSIFIED */
+    const int32_t* v_blocks;         /* DIAF_V_BLOCK / DIAF_V_TOPK_BLOCK: device array of
+                                        v_nblocks + 1 block starts, 0 = s_0 < ... = n */
+    int32_t v_nblocks;
 } diaf_spec;
 
 /* Borrowed device views of a factorization.  W has the pattern J (Wcp/Wri)
  * and values Wval; V is CSC with sorted rows.  r[j] = ||A w_j - v_j||_2,
  * flags[j] as above, lcount[j] = |L_j|.  vtri = 1 upper, -1 lower,
- * 0 diagonal. */
+ * 0 diagonal, 3 block diagonal (DIAF_V_BLOCK, DIAF_V_TOPK_BLOCK), 2 none of
+ * these (an explicit V pattern; diaf_apply and diaf_solve then return
+ * DIAF_EUNSUPPORTED). */
 typedef struct diaf_view {
     int64_t n, nnz_w, nnz_v;
     int32_t dtype, vtri;

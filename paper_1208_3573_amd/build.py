@@ -25,6 +25,7 @@ SOURCES = [
     "diaf_api.cpp",
     "pattern.hip",
     "sparsify.hip",
+    "blockv.hip",
     "factor_generic.hip",
     "factor_small.hip",
     "sparse.hip",

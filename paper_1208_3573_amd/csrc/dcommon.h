@@ -111,7 +111,7 @@ struct Err {
 
 // V pattern rules as seen by the kernels.
 enum VRule { V_EXPLICIT = 0, V_DIAG = 1, V_GS_UPPER = 2, V_GS_LOWER = 3, V_TOPK_UPPER = 4,
-             V_TOPK_LOWER = 5, V_LEV_UPPER = 6, V_LEV_LOWER = 7 };
+             V_TOPK_LOWER = 5, V_LEV_UPPER = 6, V_LEV_LOWER = 7, V_TOPK_BLOCK = 9 };
 
 // Everything the factor kernels need about one launch.
 template <class T>
@@ -128,6 +128,7 @@ struct FactorArgs {
     int vrule, vcount, lmax;
     const int32_t* Vcp_in;
     const int32_t* Vri_in;
+    const int32_t* vblk;   // V_TOPK_BLOCK: rows vblk[2j] .. vblk[2j+1]-1 form j's block
     int gram_fp32;
     double stab_r, stab_tol;  // constrained v_jj of Section 3.2 (stab_r = 0: off)
     // outputs

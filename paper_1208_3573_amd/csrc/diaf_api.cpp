@@ -69,6 +69,17 @@ struct diaf_factors {
     void *Wcv = nullptr, *Vcv = nullptr, *tmp = nullptr;
     TrsvCtl* ctl = nullptr;
     uint32_t* ready = nullptr;
+    // block diagonal V (vtri == 3): block bounds per column, block starts,
+    // offsets of the dense LU factors, the factors and row permutations, and
+    // the pattern of D for DIAF_V_BLOCK
+    int nblk = 0;
+    int32_t* vblk = nullptr;
+    int32_t* bstart = nullptr;
+    int64_t* boff = nullptr;
+    int64_t lu_elems = 0;
+    void* blu = nullptr;
+    int32_t* bperm = nullptr;
+    int32_t *vpat_cp = nullptr, *vpat_ri = nullptr;
 };
 
 namespace {
@@ -435,7 +446,9 @@ void free_factors(diaf_factors* F)
     for (void* p : {(void*)F->Jcp, (void*)F->Jri, F->Wval, (void*)F->Vcp, (void*)F->Vri, F->Vval,
                     (void*)F->Vrows, F->Vvals, (void*)F->r, (void*)F->bnorm, (void*)F->flags,
                     (void*)F->lcount, (void*)F->Wrp, (void*)F->Wci, (void*)F->Vrp, (void*)F->Vci,
-                    F->Wcv, F->Vcv, F->tmp, (void*)F->ctl, (void*)F->ready})
+                    F->Wcv, F->Vcv, F->tmp, (void*)F->ctl, (void*)F->ready, (void*)F->vblk,
+                    (void*)F->bstart, (void*)F->boff, F->blu, (void*)F->bperm,
+                    (void*)F->vpat_cp, (void*)F->vpat_ri})
         dfree(p);
     delete F;
 }
@@ -450,8 +463,50 @@ int vtri_of(int v_kind)
     case DIAF_V_TOPK_LOWER:
     case DIAF_V_LEV_LOWER: return -1;
     case DIAF_V_DIAG: return 0;
+    case DIAF_V_BLOCK:
+    case DIAF_V_TOPK_BLOCK: return 3;
     default: return 2;  // determined from the explicit pattern
     }
+}
+
+// Block diagonal V: checks the block starts (0 = s_0 < s_1 < ... < s_nb = n,
+// blocks of at most 64 rows) and stores the per-column bounds, the starts
+// and the offsets of the dense LU factors in F.
+Err setup_blocks(const diaf_spec* spec, int n, diaf_factors* F, hipStream_t st)
+{
+    const int nb = spec->v_nblocks;
+    if (!spec->v_blocks || nb < 1 || nb > n)
+        return {DIAF_EINVAL, "block V: v_blocks must hold v_nblocks + 1 starts, 1 <= v_nblocks <= n"};
+    std::vector<int32_t> s(nb + 1);
+    DIAF_HIP_TRY(hipMemcpyAsync(s.data(), spec->v_blocks, sizeof(int32_t) * (nb + 1),
+                                hipMemcpyDeviceToHost, st));
+    DIAF_TRY(sync(st));
+    if (s[0] != 0 || s[nb] != n) return {DIAF_EINVAL, "block V: the starts must run from 0 to n"};
+    std::vector<int32_t> bounds(2 * (size_t)n);
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) {
+        const int sz = s[b + 1] - s[b];
+        if (sz <= 0) return {DIAF_EINVAL, "block V: the starts must increase strictly"};
+        if (sz > 64) return {DIAF_EUNSUPPORTED, "block V: blocks of at most 64 rows"};
+        for (int j = s[b]; j < s[b + 1]; ++j) {
+            bounds[2 * (size_t)j] = s[b];
+            bounds[2 * (size_t)j + 1] = s[b + 1];
+        }
+        off[b + 1] = off[b] + (int64_t)sz * sz;
+    }
+    DIAF_TRY(dmalloc(&F->vblk, sizeof(int32_t) * bounds.size()));
+    DIAF_TRY(dmalloc(&F->bstart, sizeof(int32_t) * (nb + 1)));
+    DIAF_TRY(dmalloc(&F->boff, sizeof(int64_t) * (nb + 1)));
+    DIAF_HIP_TRY(hipMemcpyAsync(F->vblk, bounds.data(), sizeof(int32_t) * bounds.size(),
+                                hipMemcpyHostToDevice, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(F->bstart, s.data(), sizeof(int32_t) * (nb + 1),
+                                hipMemcpyHostToDevice, st));
+    DIAF_HIP_TRY(hipMemcpyAsync(F->boff, off.data(), sizeof(int64_t) * (nb + 1),
+                                hipMemcpyHostToDevice, st));
+    DIAF_TRY(sync(st));
+    F->nblk = nb;
+    F->lu_elems = off[nb];
+    return {};
 }
 
 // Factor the listed columns (all columns when cols is empty) into F's
@@ -503,11 +558,16 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     fa.Jcp = F->Jcp;
     fa.Jri = F->Jri;
     fa.mode = mode;
-    fa.vrule = spec->v_kind;
+    fa.vrule = spec->v_kind == DIAF_V_BLOCK ? V_EXPLICIT : spec->v_kind;
     fa.vcount = spec->v_count;
     fa.lmax = F->lmax;
     fa.Vcp_in = spec->v_explicit ? spec->v_explicit->colptr : nullptr;
     fa.Vri_in = spec->v_explicit ? spec->v_explicit->rowidx : nullptr;
+    if (spec->v_kind == DIAF_V_BLOCK) {  // the pattern of D, built by factor_impl
+        fa.Vcp_in = F->vpat_cp;
+        fa.Vri_in = F->vpat_ri;
+    }
+    fa.vblk = F->vblk;
     fa.gram_fp32 = spec->gram_fp32;
     fa.stab_r = spec->stab_r;
     fa.stab_tol = spec->stab_tol;
@@ -670,6 +730,26 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
     DIAF_TRY(dmalloc(&F->Wcv, sizeof(T) * (size_t)F->nnzW));
     DIAF_TRY(csc_to_csr<T>(n, F->nnzW, F->Jcp, F->Jri, (const T*)F->Wval, F->Wrp, F->Wci,
                            (T*)F->Wcv, st));
+    if (F->vtri == 3) {
+        // block diagonal V: LU with partial pivoting of every block
+        DIAF_TRY(dmalloc(&F->tmp, sizeof(T) * n));
+        DIAF_TRY(dmalloc(&F->blu, sizeof(T) * (size_t)F->lu_elems));
+        DIAF_TRY(dmalloc(&F->bperm, sizeof(int32_t) * n));
+        int32_t* bad = nullptr;
+        DIAF_TRY(dmalloc(&bad, sizeof(int32_t)));
+        DIAF_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+        Err e = launch_block_lu<T>(F->nblk, F->bstart, F->boff, F->Vcp, F->Vri, (const T*)F->Vval,
+                                   (T*)F->blu, F->bperm, bad, st);
+        int32_t nb = 0;
+        if (e.code == DIAF_OK) e = read1(bad, &nb, st);
+        dfree(bad);
+        DIAF_TRY(e);
+        if (nb & (1 << 30)) return {DIAF_EDEVICE, "block diagonal V has an entry outside its block"};
+        F->stats.count_zero_pivot = nb;
+        F->stats.v_levels = 1;
+        F->apply_ready = true;
+        return {};
+    }
     DIAF_TRY(dmalloc(&F->Vrp, sizeof(int32_t) * (n + 1)));
     DIAF_TRY(dmalloc(&F->Vci, sizeof(int32_t) * (size_t)F->nnzV));
     DIAF_TRY(dmalloc(&F->Vcv, sizeof(T) * (size_t)F->nnzV));
@@ -694,7 +774,7 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
     F->apply_ready = true;
     if (F->stats.count_zero_pivot) return {};
     // dependency depth of V
-    if (F->vtri != 0) {
+    if (F->vtri == 1 || F->vtri == -1) {
         int32_t *lvl = nullptr, *mx = nullptr;
         DIAF_TRY(dmalloc(&lvl, sizeof(int32_t) * n));
         DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
@@ -722,6 +802,9 @@ Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_
     const int n = (int)F->n;
     if (F->vtri == 0)
         DIAF_TRY(launch_diag_solve<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, x, (T*)F->tmp, done, st));
+    else if (F->vtri == 3)
+        DIAF_TRY(launch_block_solve<T>(F->nblk, F->bstart, F->boff, (const T*)F->blu, F->bperm, x,
+                                       (T*)F->tmp, done, st));
     else
         DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, x, (T*)F->tmp,
                                 F->ctl, done, ctx->trsv, st));
@@ -873,7 +956,7 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     if (e.code) return fail(ctx, e);
     if (!spec) return fail(ctx, DIAF_EINVAL, "spec is NULL");
     if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return fail(ctx, DIAF_EINVAL, "bad norm mode");
-    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_LEV_LOWER)
+    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_TOPK_BLOCK)
         return fail(ctx, DIAF_EINVAL, "bad v_kind");
     const bool lev_rule = spec->v_kind == DIAF_V_LEV_UPPER || spec->v_kind == DIAF_V_LEV_LOWER;
     if (lev_rule && mode != DIAF_UNIT_V)
@@ -889,7 +972,8 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
         !std::isfinite(spec->stab_tol))
         return fail(ctx, DIAF_EINVAL, "stab_r and stab_tol must be finite and >= 0");
-    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER || lev_rule) &&
+    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER || lev_rule ||
+         spec->v_kind == DIAF_V_TOPK_BLOCK) &&
         (spec->v_count < 1 || spec->v_count > 64))
         return fail(ctx, DIAF_EINVAL, "v_count must be in 1..64");
     if (spec->w_kind == DIAF_W_A_1HOP_TOPK && (spec->w_topk < 0 || spec->w_topk > 256))
@@ -908,7 +992,7 @@ diaf_status diaf_factors_view(const diaf_factors* F, diaf_view* v)
     v->nnz_w = F->nnzW;
     v->nnz_v = F->nnzV;
     v->dtype = F->dtype;
-    v->vtri = F->vtri == 2 ? 0 : F->vtri;
+    v->vtri = F->vtri;
     v->Wcp = F->Jcp;
     v->Wri = F->Jri;
     v->Wval = F->Wval;
@@ -950,7 +1034,7 @@ diaf_status diaf_apply(diaf_ctx* ctx, const diaf_factors* Fc, const void* x, voi
     if (F->stats.count_zero_pivot)
         return fail(ctx, DIAF_ESINGULAR, std::to_string(F->stats.count_zero_pivot) +
                                              " zero or non-finite pivots in V");
-    if (F->vtri != 0) {
+    if (F->vtri == 1 || F->vtri == -1) {
         TrsvCtl c{};
         e = read1(F->ctl, &c, ctx->stream);
         if (e.code) return fail(ctx, e);
@@ -1139,6 +1223,31 @@ Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mod
             }
         }
         F->vtri = dg ? 0 : (up ? 1 : (lo ? -1 : 2));
+    } else if (spec->v_kind == DIAF_V_BLOCK || spec->v_kind == DIAF_V_TOPK_BLOCK) {
+        DIAF_TRY(setup_blocks(spec, n, F.get(), st));
+        if (spec->v_kind == DIAF_V_TOPK_BLOCK) {
+            lmax = spec->v_count;
+        } else {
+            // the pattern of D: the rows of each column of A inside its block
+            int32_t* cnt = nullptr;
+            DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
+            Err e = launch_block_vpattern(n, A->colptr, A->rowidx, F->vblk, cnt, nullptr, nullptr,
+                                          st);
+            std::vector<int32_t> ch(n);
+            if (e.code == DIAF_OK) e = dmalloc(&F->vpat_cp, sizeof(int32_t) * (n + 1));
+            if (e.code == DIAF_OK) e = exclusive_scan_i32(cnt, F->vpat_cp, n, st);
+            if (e.code == DIAF_OK && hipMemcpyAsync(ch.data(), cnt, sizeof(int32_t) * n,
+                                                    hipMemcpyDeviceToHost, st) != hipSuccess)
+                e = {DIAF_EDEVICE, "copy of the block V counts"};
+            int32_t tot = 0;
+            if (e.code == DIAF_OK) e = read1(F->vpat_cp + n, &tot, st);
+            dfree(cnt);
+            DIAF_TRY(e);
+            for (int j = 0; j < n; ++j) lmax = std::max(lmax, ch[j]);
+            DIAF_TRY(dmalloc(&F->vpat_ri, sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1)));
+            DIAF_TRY(launch_block_vpattern(n, A->colptr, A->rowidx, F->vblk, nullptr, F->vpat_cp,
+                                           F->vpat_ri, st));
+        }
     }
     if (lmax > 256) return {DIAF_EUNSUPPORTED, "V pattern with more than 256 rows in a column"};
     F->lmax = lmax;
@@ -1268,7 +1377,7 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         if (use_graph) DIAF_HIP_TRY(hipGraphLaunch(gexec, st));
         else DIAF_TRY(enqueue_batch());
         DIAF_TRY(read1(V.st, &hs, st));
-        if (F && F->vtri != 0) {
+        if (F && (F->vtri == 1 || F->vtri == -1)) {
             TrsvCtl c{};
             DIAF_TRY(read1(F->ctl, &c, st));
             if (c.error) return {DIAF_EDEVICE, "triangular solve exceeded its wait budget"};

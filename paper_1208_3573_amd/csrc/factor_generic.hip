@@ -582,7 +582,8 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     __syncthreads();
 
     // ---- 6. V pattern ----
-    const bool topk = (A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER);
+    const bool topk =
+        (A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_BLOCK);
     const bool lev = A.mode == 0 && (A.vrule == V_LEV_LOWER || A.vrule == V_LEV_UPPER);
     const bool lowerrule = A.vrule == V_TOPK_LOWER || A.vrule == V_LEV_LOWER;
     int l = 0;
@@ -646,7 +647,9 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         int ncl = 0;
         for (int i = tid; i < m; i += c.nt) {
             int gi = c.sR[i];
-            int adm = lowerrule ? (gi > j) : (gi < j);
+            int adm = A.vrule == V_TOPK_BLOCK
+                          ? (gi != j && gi >= A.vblk[2 * j] && gi < A.vblk[2 * j + 1])
+                          : (lowerrule ? (gi > j) : (gi < j));
             c.sScore[i] = adm ? num<T>::abs(c.sY[i]) : -1.0;
             ncl += adm;
         }

@@ -92,6 +92,22 @@ template <class T>
 Err launch_col_dominance(int n, int lmax, const int32_t* Vrows, const T* Vvals,
                          const int32_t* lcount, double* dom, hipStream_t st);
 
+// ---- block diagonal V (blockv.hip) ----
+// vblk[2j], vblk[2j+1]: the rows of j's block.  Pattern of D (count with
+// Vri null, else fill); LU with partial pivoting of every block of V (at
+// most 64 rows), dense column-major at LU + boff[b], row permutation perm;
+// *bad += singular blocks (bit 30: an entry of V outside its block); the
+// block solve t = V^{-1} x, a no-op once *done.
+Err launch_block_vpattern(int n, const int32_t* Acp, const int32_t* Ari, const int32_t* vblk,
+                          int32_t* cnt, const int32_t* Vcp, int32_t* Vri, hipStream_t st);
+template <class T>
+Err launch_block_lu(int nblk, const int32_t* bstart, const int64_t* boff, const int32_t* Vcp,
+                    const int32_t* Vri, const T* Vval, T* LU, int32_t* perm, int32_t* bad,
+                    hipStream_t st);
+template <class T>
+Err launch_block_solve(int nblk, const int32_t* bstart, const int64_t* boff, const T* LU,
+                       const int32_t* perm, const T* x, T* t, const int32_t* done, hipStream_t st);
+
 // ---- solve (solve.hip) ----
 
 struct TrsvCtl {

@@ -523,12 +523,18 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
         sweep_inverse(g, k, c, hf, maxd, S.bc, flags);
     }
     // ---- 6. V pattern ----
-    const bool topk = A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER;
+    const bool topk =
+        A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_BLOCK;
     const bool lev = MODE == 0 && (A.vrule == V_LEV_LOWER || A.vrule == V_LEV_UPPER);
     const bool lowerrule = A.vrule == V_TOPK_LOWER || A.vrule == V_LEV_LOWER;
     int l = 0;
     if (topk || lev) {
-      const bool adm = lane < m && (lowerrule ? myrow > j : myrow < j);
+      // admissible: the strict triangle, or the other rows of j's diagonal
+      // block for a block diagonal V (Section 5)
+      const bool adm =
+          lane < m && (A.vrule == V_TOPK_BLOCK
+                           ? (myrow != j && myrow >= A.vblk[2 * j] && myrow < A.vblk[2 * j + 1])
+                           : (lowerrule ? myrow > j : myrow < j));
       double sc = -1.0;
       if (topk) {
         // w0 = G^{-1} u with u = conj(B(j, :)): lane c takes the product of

@@ -25,7 +25,8 @@ DIAF_UNIT_V, DIAF_UNIT_W = 0, 1
 DIAF_W_A, DIAF_W_A2, DIAF_W_A_1HOP_TOPK, DIAF_W_EXPLICIT, DIAF_W_LEARNED, DIAF_W_ALG2_DIAG, \
     DIAF_W_ALG2_GS_UPPER, DIAF_W_ALG2_GS_LOWER, DIAF_W_SPARSIFIED = range(9)
 DIAF_V_EXPLICIT, DIAF_V_DIAG, DIAF_V_GS_UPPER, DIAF_V_GS_LOWER, DIAF_V_TOPK_UPPER, \
-    DIAF_V_TOPK_LOWER, DIAF_V_LEV_UPPER, DIAF_V_LEV_LOWER = range(8)
+    DIAF_V_TOPK_LOWER, DIAF_V_LEV_UPPER, DIAF_V_LEV_LOWER, DIAF_V_BLOCK, \
+    DIAF_V_TOPK_BLOCK = range(10)
 FLAG_RANK_DEFICIENT, FLAG_GAP_DEGENERATE, FLAG_SMALL_DIAG, FLAG_FELL_BACK, FLAG_TIE_EDGE, \
     FLAG_NO_DIAG_ROW = 1, 2, 4, 8, 16, 64
 MLP_NFEAT, MLP_HIDDEN = 16, 64
@@ -51,7 +52,8 @@ class diaf_spec(ctypes.Structure):
                 ("model", c_void_p), ("gate_tau", c_double), ("v_kind", c_int32),
                 ("v_count", c_int32), ("v_explicit", POINTER(diaf_pattern)),
                 ("gram_fp32", c_int32), ("gate_dom", c_double), ("stab_r", c_double),
-                ("stab_tol", c_double), ("sparsify", diaf_sparsify)]
+                ("stab_tol", c_double), ("sparsify", diaf_sparsify), ("v_blocks", c_void_p),
+                ("v_nblocks", c_int32)]
 
 
 class diaf_view(ctypes.Structure):
@@ -238,15 +240,18 @@ W_KINDS = {"A": DIAF_W_A, "A2": DIAF_W_A2, "A_1hop_topk": DIAF_W_A_1HOP_TOPK,
 V_KINDS = {"explicit": DIAF_V_EXPLICIT, "diag": DIAF_V_DIAG, "gs_upper": DIAF_V_GS_UPPER,
            "gs_lower": DIAF_V_GS_LOWER, "topk_upper": DIAF_V_TOPK_UPPER,
            "topk_lower": DIAF_V_TOPK_LOWER, "lev_upper": DIAF_V_LEV_UPPER,
-           "lev_lower": DIAF_V_LEV_LOWER}
+           "lev_lower": DIAF_V_LEV_LOWER, "block": DIAF_V_BLOCK,
+           "topk_block": DIAF_V_TOPK_BLOCK}
 MODES = {"unit_v": DIAF_UNIT_V, "unit_w": DIAF_UNIT_W}
 
 
 def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | None = None,
               v_explicit: DevicePattern | None = None, model=None, gate_tau=float("inf"),
-              gram_fp32=False, gate_dom=0.0, stab_r=0.0, stab_tol=1e-2, sparsify=None):
+              gram_fp32=False, gate_dom=0.0, stab_r=0.0, stab_tol=1e-2, sparsify=None,
+              v_blocks=None):
     """sparsify: dict of k, tau_i, p_i, tau_l, p_l for w="sparsified"
-    (defaults k=3, tau_i=0.1, no other dropping)."""
+    (defaults k=3, tau_i=0.1, no other dropping).  v_blocks: int32 device
+    tensor of block starts (0 .. n) for v="block" / "topk_block"."""
     spec = diaf_spec()
     spec.w_kind = W_KINDS[w]
     spec.w_topk = w_topk
@@ -261,7 +266,11 @@ def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | 
     spec.stab_r = stab_r
     spec.stab_tol = stab_tol
     spec.sparsify = make_sparsify(**(sparsify or {}))
-    spec._keep = (w_explicit, v_explicit, model)
+    if v_blocks is not None:
+        assert v_blocks.dtype == _torch().int32 and v_blocks.is_cuda
+        spec.v_blocks = c_void_p(v_blocks.data_ptr())
+        spec.v_nblocks = v_blocks.numel() - 1
+    spec._keep = (w_explicit, v_explicit, model, v_blocks)
     return spec
 
 

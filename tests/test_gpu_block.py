@@ -1,0 +1,181 @@
+"""GPU block diagonal V (Section 5) against the oracle: factors with the
+pattern of D and with the top-k rule inside each block, the block LU apply
+of W V^{-1}, BiCGSTAB with it, graph replay, and the error paths."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests._gpu import compare, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1208_3573_amd import diaf
+    assert torch.cuda.is_available()
+    return diaf.Context(0)
+
+
+def _starts(n, sizes):
+    st = [0]
+    while st[-1] < n:
+        st.append(min(n, st[-1] + sizes[(len(st) - 1) % len(sizes)]))
+    return np.array(st, dtype=np.int32)
+
+
+CASES = {
+    # x-lines of the grid as blocks (12 rows), the tridiagonal part of A
+    "convdiff3d_12_lines": (lambda: synth.convdiff(12, 3, 7), lambda n: _starts(n, [12])),
+    # irregular block sizes, one-row blocks included
+    "random_small_mixed": (lambda: synth.random_small(400, 4, 3, diag_shift=1.0),
+                           lambda n: _starts(n, [7, 1, 16, 3, 64])),
+    "helmholtz_24_c": (lambda: synth.helmholtz(24, 5.0, 0.5), lambda n: _starts(n, [24])),
+}
+
+
+def _dev_blocks(st):
+    import torch
+    return torch.from_numpy(st).cuda()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("v,l", [("block", 0), ("topk_block", 3)])
+def test_block_factor_matches_oracle(ctx, name, v, l):
+    from paper_1208_3573_amd import diaf
+    mk, blocks = CASES[name]
+    A = mk()
+    st = blocks(A.n)
+    dA = diaf.DeviceCSC.from_host(A)
+    J = oracle.pattern_A2(A)
+    for mode in ("unit_v", "unit_w"):
+        say(f"case {name} V {v} mode {mode} n={A.n} blocks={len(st) - 1}")
+        spec = diaf.make_spec(w="A2", v=v, v_count=l, v_blocks=_dev_blocks(st))
+        F = diaf.diaf_factor(ctx, dA, spec, mode)
+        H = F.to_host()
+        assert H["vtri"] == 3
+        if v == "block":
+            O = oracle.factor(A, J, mode, "explicit", Vexp=oracle.pattern_vblock(A, st))
+        else:
+            O = oracle.factor(A, J, mode, "topk_block", l, vblocks=st)
+        compare(H, J, O, A, mode)
+        F.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_block_apply_matches_oracle(ctx, name):
+    """W V^{-1} x through the GPU block LU against the oracle's Gaussian
+    elimination on the GPU's own W and V (so that only the apply differs)."""
+    import torch
+    from types import SimpleNamespace
+    from paper_1208_3573_amd import diaf
+    mk, blocks = CASES[name]
+    A = mk()
+    st = blocks(A.n)
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_block", v_count=4,
+                                                 v_blocks=_dev_blocks(st)), "unit_v")
+    H = F.to_host()
+    O = SimpleNamespace(n=A.n, Jcp=H["Wcp"], Jri=H["Wri"], Wval=H["Wval"], Vcp=H["Vcp"],
+                        Vri=H["Vri"], Vval=H["Vval"])
+    rng = np.random.default_rng(1)
+    cplx = np.iscomplexobj(A.val)
+    for rep in range(2):
+        x = rng.standard_normal(A.n) + (1j * rng.standard_normal(A.n) if cplx else 0)
+        yo = oracle.apply(O, x, "block", st)
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.zeros_like(xd)
+        diaf.diaf_apply(ctx, F, xd, yd)
+        err = np.linalg.norm(yd.cpu().numpy() - yo) / np.linalg.norm(yo)
+        say(f"case {name} apply {rep} rel err {err:.3e}")
+        assert err < 1e-11
+    assert F.stats().v_levels == 1
+    F.close()
+
+
+@pytest.mark.parametrize("mode", ["unit_v", "unit_w"])
+def test_block_bicgstab_matches_oracle(ctx, mode):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(16, 3, 7)
+    st = _starts(A.n, [16])
+    b = synth.rhs_ones(A)
+    J = oracle.pattern_A2(A)
+    O = oracle.factor(A, J, mode, "topk_block", 3, vblocks=st)
+    _, oinfo = oracle.bicgstab(A, b, O, upper="block", tol=1e-8, maxit=1000, vblocks=st)
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_block", v_count=3,
+                                                 v_blocks=_dev_blocks(st)), mode)
+    db = torch.from_numpy(b).cuda()
+    for graph in (1, 0):
+        ctx.set_option("graph", graph)
+        x = torch.zeros_like(db)
+        info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
+        say(f"mode {mode} graph {graph}: gpu its={info.iters} oracle its={oinfo.iters} "
+            f"true={info.relres_true:.3e}")
+        assert info.flag == oinfo.flag == 0
+        assert abs(info.iters - oinfo.iters) <= max(1, int(0.05 * oinfo.iters))
+        assert info.relres_true <= 1e-7
+        assert np.max(np.abs(x.cpu().numpy() - 1.0)) < 1e-3
+    ctx.set_option("graph", 1)
+    F.close()
+
+
+def test_block_errors_and_singular_blocks(ctx):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(8, 2, 1)
+    dA = diaf.DeviceCSC.from_host(A)
+    for bad, code in ((np.array([0, 10, 10, A.n], np.int32), diaf.DIAF_EINVAL),
+                      (np.array([0, 5, A.n - 1], np.int32), diaf.DIAF_EINVAL),
+                      (np.array([1, A.n], np.int32), diaf.DIAF_EINVAL)):
+        say(f"case bad starts {bad}")
+        with pytest.raises(diaf.DiafError) as ei:
+            diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A", v="block", v_blocks=_dev_blocks(bad)),
+                             "unit_v")
+        assert ei.value.code == code
+    say("case block of 65 rows")
+    A2 = synth.convdiff(10, 2, 1)
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_factor(ctx, diaf.DeviceCSC.from_host(A2),
+                         diaf.make_spec(w="A", v="block",
+                                        v_blocks=_dev_blocks(np.array([0, 65, 100], np.int32))),
+                         "unit_v")
+    assert ei.value.code == diaf.DIAF_EUNSUPPORTED
+    say("case v_count out of range")
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A", v="topk_block", v_count=0,
+                                                 v_blocks=_dev_blocks(_starts(A.n, [8]))),
+                         "unit_v")
+    assert ei.value.code == diaf.DIAF_EINVAL
+    # A with a zero column: under unit-norm w that column of V is exactly
+    # zero (v = A w), so its block is singular; solve flag 3 and apply
+    # DIAF_ESINGULAR, like the triangular path
+    say("case singular block")
+    n = 16
+    rows = list(range(n)) + [3]
+    cols = list(range(n)) + [2]
+    vals = [2.0] * n + [1.0]
+    Az = synth._coo_to_csc(n, np.array(rows), np.array(cols), np.array(vals))
+    Az.val[Az.colptr[5]:Az.colptr[6]] = 0.0  # column 5 of A is zero
+    st = _starts(n, [4])
+    O = oracle.factor(Az, oracle.pattern_A(Az), "unit_w", "explicit",
+                      Vexp=oracle.pattern_vblock(Az, st))
+    b = np.ones(n)
+    _, oinfo = oracle.bicgstab(Az, b, O, upper="block", vblocks=st)
+    dAz = diaf.DeviceCSC.from_host(Az)
+    F = diaf.diaf_factor(ctx, dAz, diaf.make_spec(w="A", v="block", v_blocks=_dev_blocks(st)),
+                         "unit_w")
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dAz, F, db, x, 1e-8, 100)
+    say(f"singular: gpu flag {info.flag} oracle flag {oinfo.flag}, "
+        f"zero pivots {F.stats().count_zero_pivot}")
+    assert info.flag == oinfo.flag == 3
+    assert F.stats().count_zero_pivot == 1
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_apply(ctx, F, db, x)
+    assert ei.value.code == diaf.DIAF_ESINGULAR
+    F.close()
