@@ -185,6 +185,14 @@ typedef struct diaf_spec {
     const int32_t* v_blocks;         /* DIAF_V_BLOCK / DIAF_V_TOPK_BLOCK: device array of
                                         v_nblocks + 1 block starts, 0 = s_0 < ... = n */
     int32_t v_nblocks;
+    int32_t left;                    /* 1: the left variant (Section 4's remarks on left and
+                                        right approximate inverses): W A ~ V, found by the
+                                        columnwise method on A^* (every pattern and rule above
+                                        then applies to A^*, W^*, V^*; a lower rule gives an
+                                        upper V), M = V^{-1} W; diaf_apply computes V^{-1} W x
+                                        and diaf_solve runs BiCGSTAB on M A x = M b, stopped on
+                                        the preconditioned residual (relres), relres_true still
+                                        ||b - A x|| / ||b||.  0: right (eq. 2.1) */
 } diaf_spec;
 
 /* Borrowed device views of a factorization.  W has the pattern J (Wcp/Wri)
@@ -304,13 +312,16 @@ void diaf_factors_destroy(struct diaf_factors* F);
 
 /* ---- apply and solve (eq. 2.1, Section 5) -------------------------------- */
 
-/* y = W V^{-1} x for triangular or diagonal V (n entries each).
- * DIAF_ESINGULAR when V has a zero or non-finite diagonal entry. */
+/* y = W V^{-1} x for triangular, diagonal or block diagonal V (n entries
+ * each); y = V^{-1} W x for factors of the left variant (diaf_spec.left).
+ * DIAF_ESINGULAR when V has a zero or non-finite pivot. */
 diaf_status diaf_apply(struct diaf_ctx* ctx, const struct diaf_factors* F, const void* x,
                        void* y);
 
 /* Right-preconditioned BiCGSTAB on A M u = b, x = M u, M = W V^{-1}
- * (F == NULL: M = I), x0 = 0, stop when ||r|| <= rtol ||b||.  Returns
+ * (F == NULL: M = I), x0 = 0, stop when ||r|| <= rtol ||b||; for factors of
+ * the left variant, BiCGSTAB on M A x = M b, M = V^{-1} W, stop when the
+ * preconditioned residual ||M (b - A x)|| <= rtol ||M b||.  Returns
  * DIAF_OK, DIAF_ENOCONV, DIAF_EBREAKDOWN or DIAF_ESINGULAR (V has a zero
  * pivot: x = 0, info flag 3) with *info_host filled. */
 diaf_status diaf_solve(struct diaf_ctx* ctx, const diaf_csc* A, const struct diaf_factors* F,

@@ -80,6 +80,8 @@ struct diaf_factors {
     void* blu = nullptr;
     int32_t* bperm = nullptr;
     int32_t *vpat_cp = nullptr, *vpat_ri = nullptr;
+    // left variant: W, V above are those of W A ~ V (M = V^{-1} W)
+    int left = 0;
 };
 
 namespace {
@@ -794,25 +796,38 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
     return {};
 }
 
-// t = V^{-1} x ; y = W t   (all on stream st, no host sync)
+// Right: t = V^{-1} x ; y = W t.  Left: t = W x ; y = V^{-1} t.  All on
+// stream st, no host sync.
 template <class T>
 Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done,
                   hipStream_t st)
 {
     const int n = (int)F->n;
+    T* t = (T*)F->tmp;
+    const T* vin = x;
+    T* vout = t;
+    if (F->left) {
+        DIAF_TRY(launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, x, t, done, st));
+        vin = t;
+        vout = y;
+    }
     if (F->vtri == 0)
-        DIAF_TRY(launch_diag_solve<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, x, (T*)F->tmp, done, st));
+        DIAF_TRY(launch_diag_solve<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, vin, vout, done, st));
     else if (F->vtri == 3)
-        DIAF_TRY(launch_block_solve<T>(F->nblk, F->bstart, F->boff, (const T*)F->blu, F->bperm, x,
-                                       (T*)F->tmp, done, st));
+        DIAF_TRY(launch_block_solve<T>(F->nblk, F->bstart, F->boff, (const T*)F->blu, F->bperm, vin,
+                                       vout, done, st));
     else
-        DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, x, (T*)F->tmp,
+        DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, vin, vout,
                                 F->ctl, done, ctx->trsv, st));
-    return launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)F->tmp, y, done, st);
+    if (F->left) return {};
+    return launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)t, y, done, st);
 }
 
 template <class T>
 Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
+                diaf_factors** out);
+template <class T>
+Err factor_left(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
                 diaf_factors** out);
 
 }  // namespace
@@ -979,8 +994,13 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     if (spec->w_kind == DIAF_W_A_1HOP_TOPK && (spec->w_topk < 0 || spec->w_topk > 256))
         return fail(ctx, DIAF_EINVAL, "w_topk must be in 0..256");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
-    e = A->dtype == DIAF_F64 ? factor_impl<double>(ctx, A, spec, mode, out)
-                             : factor_impl<zc>(ctx, A, spec, mode, out);
+    if (spec->left != 0 && spec->left != 1) return fail(ctx, DIAF_EINVAL, "left must be 0 or 1");
+    if (spec->left)
+        e = A->dtype == DIAF_F64 ? factor_left<double>(ctx, A, spec, mode, out)
+                                 : factor_left<zc>(ctx, A, spec, mode, out);
+    else
+        e = A->dtype == DIAF_F64 ? factor_impl<double>(ctx, A, spec, mode, out)
+                                 : factor_impl<zc>(ctx, A, spec, mode, out);
     if (e.code) return fail(ctx, e);
     return DIAF_OK;
 }
@@ -1279,6 +1299,70 @@ Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mod
     return {};
 }
 
+// In-place conjugate transpose of a CSC matrix held in F (new arrays; the
+// CSR of X is the CSC of X^T).
+template <class T>
+Err conj_transpose_csc(int n, int64_t nnz, int32_t** cp, int32_t** ri, void** val, hipStream_t st)
+{
+    int32_t *rp = nullptr, *ci = nullptr;
+    T* cv = nullptr;
+    Err e = dmalloc(&rp, sizeof(int32_t) * (n + 1));
+    if (e.code == DIAF_OK) e = dmalloc(&ci, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    if (e.code == DIAF_OK) e = dmalloc(&cv, sizeof(T) * (size_t)(nnz > 0 ? nnz : 1));
+    if (e.code == DIAF_OK) e = csc_to_csr<T>(n, nnz, *cp, *ri, (const T*)*val, rp, ci, cv, st);
+    if (e.code == DIAF_OK) e = launch_conj<T>(nnz, cv, st);
+    if (e.code == DIAF_OK) e = sync(st);
+    if (e.code != DIAF_OK) {
+        dfree(rp); dfree(ci); dfree(cv);
+        return e;
+    }
+    dfree(*cp); dfree(*ri); dfree(*val);
+    *cp = rp;
+    *ri = ci;
+    *val = cv;
+    return {};
+}
+
+// Left variant (the remarks of Section 4 on left and right approximate
+// inverses): W A ~ V row by row is A^* W^* ~ V^* column by column, so the
+// columnwise method runs on A^* and its factors are conjugate-transposed:
+// W = W~^*, V = V~^* (the triangle of V flips), M = V^{-1} W.
+template <class T>
+Err factor_left(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
+                diaf_factors** out)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)A->n;
+    DIAF_TRY(validate_A<T>(A, st));
+    int32_t *rp = nullptr, *ci = nullptr;
+    T* cv = nullptr;
+    struct Free3 {
+        int32_t** a; int32_t** b; T** c;
+        ~Free3() { dfree(*a); dfree(*b); dfree(*c); }
+    } f3{&rp, &ci, &cv};
+    DIAF_TRY(dmalloc(&rp, sizeof(int32_t) * (n + 1)));
+    DIAF_TRY(dmalloc(&ci, sizeof(int32_t) * (size_t)A->nnz));
+    DIAF_TRY(dmalloc(&cv, sizeof(T) * (size_t)A->nnz));
+    DIAF_TRY(csc_to_csr<T>(n, A->nnz, A->colptr, A->rowidx, (const T*)A->val, rp, ci, cv, st));
+    DIAF_TRY(launch_conj<T>(A->nnz, cv, st));
+    diaf_csc Ah = *A;
+    Ah.colptr = rp;
+    Ah.rowidx = ci;
+    Ah.val = cv;
+    diaf_factors* F = nullptr;
+    DIAF_TRY(factor_impl<T>(ctx, &Ah, spec, mode, &F));
+    Err e = conj_transpose_csc<T>(n, F->nnzW, &F->Jcp, &F->Jri, &F->Wval, st);
+    if (e.code == DIAF_OK) e = conj_transpose_csc<T>(n, F->nnzV, &F->Vcp, &F->Vri, &F->Vval, st);
+    if (e.code != DIAF_OK) {
+        free_factors(F);
+        return e;
+    }
+    if (F->vtri == 1 || F->vtri == -1) F->vtri = -F->vtri;
+    F->left = 1;
+    *out = F;
+    return {};
+}
+
 template <class T>
 Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T* x, double rtol,
                int maxit, diaf_solve_info* info)
@@ -1332,6 +1416,24 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     DIAF_TRY(dmalloc(&V.st, sizeof(BicgState<T>)));
     DIAF_HIP_TRY(hipMemsetAsync(V.st, 0, sizeof(BicgState<T>), st));
     const int32_t* done = &V.st->done;
+    // Left preconditioning: BiCGSTAB on M A x = M b (the preconditioned
+    // residual drives the iteration and the stop test); the products are
+    // M (A p) and M (A s), and x advances along p and s themselves, so ph
+    // and sh alias p and s.  The true residual at the end uses b itself.
+    const bool left = F && F->left;
+    T *bl = nullptr, *av = nullptr;
+    struct FreeL {
+        T** a; T** b;
+        ~FreeL() { dfree(*a); dfree(*b); }
+    } freel{&bl, &av};
+    if (left) {
+        DIAF_TRY(dmalloc(&bl, sizeof(T) * n));
+        DIAF_TRY(dmalloc(&av, sizeof(T) * n));
+        DIAF_TRY(enqueue_apply<T>(ctx, F, b, bl, nullptr, st));
+        V.b = bl;
+        V.ph = V.p;
+        V.sh = V.s;
+    }
     DIAF_TRY(bicg_init<T>(V, rtol, maxit, st));
     BicgState<T> hs{};
     const int batch = (int)ctx->opt_batch;
@@ -1340,6 +1442,17 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         for (int q = 0; q < batch; ++q) {
             DIAF_TRY(bicg_rho<T>(V, st));
             DIAF_TRY(bicg_update_p<T>(V, st));
+            if (left) {
+                DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.p, av, done, st));
+                DIAF_TRY(enqueue_apply<T>(ctx, F, av, V.v, done, st));
+                DIAF_TRY(bicg_alpha<T>(V, st));
+                DIAF_TRY(bicg_s<T>(V, st));
+                DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.s, av, done, st));
+                DIAF_TRY(enqueue_apply<T>(ctx, F, av, V.t, done, st));
+                DIAF_TRY(bicg_omega<T>(V, st));
+                DIAF_TRY(bicg_xr<T>(V, st));
+                continue;
+            }
             if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.p, V.ph, done, st));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.ph, V.p, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
             DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.ph, V.v, done, st));
@@ -1387,6 +1500,7 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     }
     DIAF_TRY(bicg_half_fix<T>(V, st));
     DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.x, V.t, nullptr, st));
+    V.b = b;
     DIAF_TRY(bicg_true_residual<T>(V, st));
     DIAF_TRY(read1(V.st, &hs, st));
     auto t1 = std::chrono::steady_clock::now();

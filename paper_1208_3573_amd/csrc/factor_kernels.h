@@ -70,6 +70,9 @@ Err exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t st);
 template <class T>
 Err launch_compact_v(int n, int lmax, const int32_t* lcount, const int32_t* Vcp,
                      const int32_t* Vrows, const T* Vvals, int32_t* Vri, T* Vval, hipStream_t st);
+// v <- conj(v) (a no-op for double).
+template <class T>
+Err launch_conj(int64_t n, T* v, hipStream_t st);
 // CSC -> CSR transpose with rows sorted by column (deterministic).
 template <class T>
 Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T* val,

@@ -800,21 +800,24 @@ __global__ void __launch_bounds__(RNT) bicg_xr_kernel(BicgVecs<T> V)
 }
 
 // After the loop (and bicg_half_fix), with t = A x: ||b - A x|| / ||b||
-// into st->tt.
+// into st->tt (||b|| summed here: under left preconditioning st->bnorm is
+// the norm of M b).
 template <class T>
 __global__ void __launch_bounds__(RNT) bicg_true_res_kernel(BicgVecs<T> V)
 {
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     BICG_GRID_LOOP {
-        T d = V.b[i] - V.t[i];
+        const T bi = V.b[i];
+        T d = bi - V.t[i];
         acc[0] += num<T>::abs2(d);
+        acc[1] += num<T>::abs2(bi);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
-        double s[1];
-        sum_partials<1>(V.partial, gridDim.x, s);
+    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket)) {
+        double s[2];
+        sum_partials<2>(V.partial, gridDim.x, s);
         if (threadIdx.x != 0) return;
         V.st->red_ticket = 0;
-        V.st->tt = V.st->bnorm > 0 ? sqrt(s[0]) / V.st->bnorm : 0.0;
+        V.st->tt = s[1] > 0 ? sqrt(s[0]) / sqrt(s[1]) : 0.0;
     }
 }
 

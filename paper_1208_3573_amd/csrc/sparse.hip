@@ -310,4 +310,24 @@ template Err launch_diag_check<double>(int, const int32_t*, const int32_t*, cons
 template Err launch_diag_check<zc>(int, const int32_t*, const int32_t*, const zc*, int32_t*,
                                    hipStream_t);
 
+// v <- conj(v) (nothing to do for real values).
+__global__ void conj_kernel(int64_t n, zc* v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i].y = -v[i].y;
+}
+
+template <class T>
+Err launch_conj(int64_t n, T* v, hipStream_t st)
+{
+    if constexpr (num<T>::is_complex) {
+        if (n == 0) return {};
+        hipLaunchKernelGGL(conj_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, v);
+        DIAF_HIP_TRY(hipGetLastError());
+    }
+    return {};
+}
+template Err launch_conj<double>(int64_t, double*, hipStream_t);
+template Err launch_conj<zc>(int64_t, zc*, hipStream_t);
+
 }  // namespace diaf

@@ -53,7 +53,7 @@ class diaf_spec(ctypes.Structure):
                 ("v_count", c_int32), ("v_explicit", POINTER(diaf_pattern)),
                 ("gram_fp32", c_int32), ("gate_dom", c_double), ("stab_r", c_double),
                 ("stab_tol", c_double), ("sparsify", diaf_sparsify), ("v_blocks", c_void_p),
-                ("v_nblocks", c_int32)]
+                ("v_nblocks", c_int32), ("left", c_int32)]
 
 
 class diaf_view(ctypes.Structure):
@@ -248,10 +248,11 @@ MODES = {"unit_v": DIAF_UNIT_V, "unit_w": DIAF_UNIT_W}
 def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | None = None,
               v_explicit: DevicePattern | None = None, model=None, gate_tau=float("inf"),
               gram_fp32=False, gate_dom=0.0, stab_r=0.0, stab_tol=1e-2, sparsify=None,
-              v_blocks=None):
+              v_blocks=None, left=False):
     """sparsify: dict of k, tau_i, p_i, tau_l, p_l for w="sparsified"
     (defaults k=3, tau_i=0.1, no other dropping).  v_blocks: int32 device
-    tensor of block starts (0 .. n) for v="block" / "topk_block"."""
+    tensor of block starts (0 .. n) for v="block" / "topk_block".  left: the
+    left variant W A ~ V, M = V^{-1} W."""
     spec = diaf_spec()
     spec.w_kind = W_KINDS[w]
     spec.w_topk = w_topk
@@ -266,6 +267,7 @@ def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | 
     spec.stab_r = stab_r
     spec.stab_tol = stab_tol
     spec.sparsify = make_sparsify(**(sparsify or {}))
+    spec.left = int(bool(left))
     if v_blocks is not None:
         assert v_blocks.dtype == _torch().int32 and v_blocks.is_cuda
         spec.v_blocks = c_void_p(v_blocks.data_ptr())

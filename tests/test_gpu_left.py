@@ -1,0 +1,140 @@
+"""GPU left variant (W A ~ V by the columnwise method on A^*, M = V^{-1} W)
+against the oracle: the factors, the apply order and the left-preconditioned
+BiCGSTAB, with triangular and block diagonal V."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+from tests._gpu import compare, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1208_3573_amd import diaf
+    assert torch.cuda.is_available()
+    return diaf.Context(0)
+
+
+def _back(H):
+    """The GPU's W, V of the left factorization, conjugate-transposed back to
+    the factors of A^* (the layout the column comparison expects)."""
+    n = H["n"]
+    out = dict(H)
+    for cp, ri, va in (("Wcp", "Wri", "Wval"), ("Vcp", "Vri", "Vval")):
+        M = sp.csc_matrix((H[va], H[ri], H[cp]), shape=(n, n)).conj().T.tocsc()
+        M.sort_indices()
+        out[cp], out[ri], out[va] = M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data
+    return out
+
+
+CASES = {
+    "convdiff3d_12": (lambda: synth.convdiff(12, 3, 7), "topk_lower", 4),
+    "helmholtz_24_c": (lambda: synth.helmholtz(24, 5.0, 0.5), "gs_upper", 0),
+    "random_small": (lambda: synth.random_small(400, 4, 3, diag_shift=1.0), "topk_upper", 3),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_left_factors_match_oracle(ctx, name):
+    from paper_1208_3573_amd import diaf
+    mk, v, l = CASES[name]
+    A = mk()
+    Ah = oracle.conj_transpose(A)
+    J = oracle.pattern_A2(Ah)
+    dA = diaf.DeviceCSC.from_host(A)
+    for mode in ("unit_v", "unit_w"):
+        say(f"case {name} left V {v} mode {mode}")
+        F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=v, v_count=l, left=True), mode)
+        H = F.to_host()
+        want = {"topk_lower": 1, "gs_upper": -1, "topk_upper": -1}[v]
+        assert H["vtri"] == want  # the triangle flips
+        O = oracle.factor(Ah, J, mode, v, l)
+        compare(_back(H), J, O, Ah, mode)
+        F.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_left_apply_matches_oracle(ctx, name):
+    import torch
+    from types import SimpleNamespace
+    from paper_1208_3573_amd import diaf
+    mk, v, l = CASES[name]
+    A = mk()
+    dA = diaf.DeviceCSC.from_host(A)
+    # the Section 3.2 constraint keeps V's diagonal away from zero (without
+    # it two columns of the random case have |v_jj| ~ 1e-16, a V that is
+    # singular to working precision)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=v, v_count=l, left=True, stab_r=2.0),
+                         "unit_v")
+    H = F.to_host()
+    O = SimpleNamespace(n=A.n, Jcp=H["Wcp"], Jri=H["Wri"], Wval=H["Wval"], Vcp=H["Vcp"],
+                        Vri=H["Vri"], Vval=H["Vval"])
+    cplx = np.iscomplexobj(A.val)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(A.n) + (1j * rng.standard_normal(A.n) if cplx else 0)
+    yo = oracle.apply(O, x, H["vtri"] > 0, left=True)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.zeros_like(xd)
+    diaf.diaf_apply(ctx, F, xd, yd)
+    err = np.linalg.norm(yd.cpu().numpy() - yo) / np.linalg.norm(yo)
+    say(f"case {name} left apply rel err {err:.3e}")
+    assert err < 1e-9
+    F.close()
+
+
+@pytest.mark.parametrize("mode", ["unit_v", "unit_w"])
+@pytest.mark.parametrize("vk", ["topk_lower", "topk_block"])
+def test_left_bicgstab_matches_oracle(ctx, mode, vk):
+    import torch
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(16, 3, 7)
+    b = synth.rhs_ones(A)
+    st = np.arange(0, A.n + 1, 16, dtype=np.int32)
+    Ah = oracle.conj_transpose(A)
+    J = oracle.pattern_A2(Ah)
+    if vk == "topk_block":
+        Ot = oracle.factor(Ah, J, mode, vk, 3, vblocks=st)
+        upper, blocks = "block", st
+    else:
+        Ot = oracle.factor(Ah, J, mode, vk, 4)
+        upper, blocks = True, None
+    O = oracle.left_factors(Ot)
+    _, oinfo = oracle.bicgstab(A, b, O, upper=upper, tol=1e-8, maxit=1000, vblocks=blocks,
+                               left=True)
+    dA = diaf.DeviceCSC.from_host(A)
+    spec = diaf.make_spec(w="A2", v=vk, v_count=3 if vk == "topk_block" else 4, left=True,
+                          v_blocks=torch.from_numpy(st).cuda() if vk == "topk_block" else None)
+    F = diaf.diaf_factor(ctx, dA, spec, mode)
+    db = torch.from_numpy(b).cuda()
+    res = {}
+    for graph in (1, 0):
+        ctx.set_option("graph", graph)
+        x = torch.zeros_like(db)
+        info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
+        say(f"{vk} {mode} graph {graph}: gpu its={info.iters} relres={info.relres:.2e} "
+            f"true={info.relres_true:.2e}; oracle its={oinfo.iters} "
+            f"true={oinfo.relres_true:.2e}")
+        assert info.flag == oinfo.flag == 0
+        assert abs(info.iters - oinfo.iters) <= max(1, int(0.05 * oinfo.iters))
+        assert info.relres <= 1e-8
+        assert info.relres_true <= 10 * max(oinfo.relres_true, 1e-9)
+        res[graph] = x.cpu().numpy()
+    assert np.array_equal(res[0], res[1])
+    ctx.set_option("graph", 1)
+    F.close()
+
+
+def test_left_flag_validated(ctx):
+    from paper_1208_3573_amd import diaf
+    A = synth.random_small(30, 3, 0)
+    dA = diaf.DeviceCSC.from_host(A)
+    spec = diaf.make_spec(w="A", v="diag")
+    spec.left = 2
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_factor(ctx, dA, spec, "unit_v")
+    assert ei.value.code == diaf.DIAF_EINVAL
