@@ -124,6 +124,24 @@ def copy_calibration():
                       "launches": 3}), flush=True)
 
 
+# Method variants on the 64^3 matrix (the rows beyond the headline
+# configuration): Algorithm 1 with the paper's parameters (k = 3, tau_i = 0.1),
+# Algorithm 2 with the Gauss-Seidel V_0, the Section 3.2 constraint, the
+# Section 3.1 leverage rule, block diagonal V on the x-lines of the grid (64
+# rows per block) with the pattern of D or the top-k rows of the block, and
+# the left variant.
+VARIANTS = {
+    "alg1": dict(w="sparsified", v="topk_lower", v_count=5,
+                 sparsify=dict(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0)),
+    "alg2_gs": dict(w="alg2_gs_lower", v="topk_lower", v_count=5),
+    "stab": dict(w="A2", v="topk_lower", v_count=5, stab_r=2.0),
+    "lev": dict(w="A2", v="lev_lower", v_count=5),
+    "block_d": dict(w="A2", v="block", blocks=64),
+    "block_topk": dict(w="A2", v="topk_block", v_count=5, blocks=64),
+    "left": dict(w="A2", v="topk_lower", v_count=5, left=True),
+}
+
+
 def cpu_baseline(A, J, mode, v, l, upper, b):
     """The oracle as it stands, on all host cores, on the full workload once
     (factor + BiCGSTAB)."""
@@ -154,6 +172,9 @@ def main():
                     help="keep the built-in launch shapes instead of tuning them first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the known-size copy used to scale the HBM counters")
+    ap.add_argument("--variants", default="",
+                    help="comma-separated extra configurations timed on the same matrix after "
+                         "the main line (reported under 'variants'): " + ", ".join(VARIANTS))
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -299,6 +320,35 @@ def main():
                         "e2e_ms": factor_ms + solve_ms, "bicgstab_iters": iters,
                         "nnz_w": int(len(H["Wri"])), "v_levels": int(st.v_levels)}
         model.close()
+
+    if args.variants:
+        out["variants"] = {}
+        for name in [v.strip() for v in args.variants.split(",") if v.strip()]:
+            kw = dict(VARIANTS[name])
+            nb = kw.pop("blocks", None)
+            if nb:
+                kw["v_blocks"] = torch.arange(0, A.n + 1, nb, dtype=torch.int32, device="cuda")
+            vspec = diaf.make_spec(**kw)
+            rec = []
+            for it in range(args.warmup + args.steps):
+                F, vst, vinfo, vf, vs = step(vspec)
+                log(f"variant {name}: factor {vf:.1f} ms (pattern {vst.ms_pattern:.2f}, kernels "
+                    f"{vst.ms_factor_kernels:.2f}), solve {vs:.1f} ms, {vinfo.iters} its, "
+                    f"flag {vinfo.flag}, relres_true {vinfo.relres_true:.2e}")
+                if it >= args.warmup:
+                    rec.append((vf, vs, vst.ms_pattern, vst.ms_factor_kernels, vinfo.iters,
+                                vinfo.flag, vinfo.relres_true, vst.nnz_w, vst.v_levels, vst.nrm))
+                F.close()
+            Rv = np.array(rec, dtype=float)
+            out["variants"][name] = {
+                "spec": {k: (v if not hasattr(v, "shape") else f"blocks of {nb}")
+                         for k, v in kw.items()},
+                "factor_ms": float(Rv[:, 0].mean()), "solve_ms": float(Rv[:, 1].mean()),
+                "e2e_ms": float((Rv[:, 0] + Rv[:, 1]).mean()),
+                "pattern_ms": float(Rv[:, 2].mean()), "factor_kernel_ms": float(Rv[:, 3].mean()),
+                "bicgstab_iters": int(Rv[-1, 4]), "flag": int(Rv[-1, 5]),
+                "relres_true": float(Rv[-1, 6]), "nnz_w": int(Rv[-1, 7]),
+                "v_levels": int(Rv[-1, 8]), "nrm_AW_minus_V": float(Rv[-1, 9])}
 
     if not args.no_cpu:
         log("cpu baseline: oracle on host cores")

@@ -9,7 +9,8 @@
 // densely, column-major, so that every step of the block solve reads one
 // coalesced column.  The solve is again one wave per block: the permuted
 // right-hand side in registers, 2 b sequential steps that broadcast the
-// finished entry with a cross-lane shuffle.  Blocks are independent, so
+// finished entry with a cross-lane shuffle, the factor columns read from
+// global memory ahead of the chain.  Blocks are independent, so
 // unlike the triangular solve there is no cross-block dependency at all.
 #include "dcommon.h"
 #include "factor_kernels.h"
@@ -150,6 +151,15 @@ Err launch_block_lu(int nblk, const int32_t* bstart, const int64_t* boff, const 
 }
 
 // t = V^{-1} x block by block with the stored LU factors (no-op once *done).
+// Lane i keeps entry i of the permuted right-hand side in a register; step c
+// broadcasts the finished entry c and every lane below (forward) or above
+// (backward) subtracts its multiple.  The factor entries a lane needs do not
+// depend on the running values, so they are read straight from global
+// memory, one coalesced column per step, SB columns at a time into registers
+// and double-buffered: the loads of the next SB columns are in flight while
+// the shuffle chain works through the current ones.
+constexpr int SB = 8;
+
 template <class T>
 __global__ __launch_bounds__(64) void block_solve_kernel(const int32_t* bstart,
                                                          const int64_t* boff, const T* LU,
@@ -157,27 +167,59 @@ __global__ __launch_bounds__(64) void block_solve_kernel(const int32_t* bstart,
                                                          const int32_t* done)
 {
     if (done && *done) return;
-    __shared__ T F[BLD * BLD];
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = bstart[b], bs = bstart[b + 1] - b0;
-    const T* in = LU + boff[b];
-    for (int c = 0; c < bs; ++c)
-        if (lane < bs) F[lane + c * BLD] = in[lane + (size_t)c * bs];
-    T z = lane < bs ? x[b0 + perm[b0 + lane]] : num<T>::zero();
-    __syncthreads();
-    // L z = P x (unit lower triangular)
-    for (int c = 0; c + 1 < bs; ++c) {
-        const T zc = bshfl(z, c);
-        if (lane > c && lane < bs) z -= F[lane + c * BLD] * zc;
+    const bool act = lane < bs;
+    const T* F = LU + boff[b];
+    T z = act ? x[b0 + perm[b0 + lane]] : num<T>::zero();
+    T cur[SB], nxt[SB];
+    // L z = P x (unit lower triangular): columns 0 .. bs-2, below the diagonal
+    const auto load_l = [&](int c0, T (&buf)[SB]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int c = c0 + u;
+            buf[u] = act && lane > c && c < bs - 1 ? F[lane + (size_t)c * bs] : num<T>::zero();
+        }
+    };
+    load_l(0, cur);
+    for (int c0 = 0; c0 < bs - 1; c0 += SB) {
+        if (c0 + SB < bs - 1) load_l(c0 + SB, nxt);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int c = c0 + u;
+            if (c < bs - 1) {
+                const T zc = bshfl(z, c);
+                if (lane > c) z -= cur[u] * zc;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) cur[u] = nxt[u];
     }
-    // U t = z
-    for (int c = bs - 1; c >= 0; --c) {
-        if (lane == c) z = bdiv(z, F[c + c * BLD]);
-        const T tc = bshfl(z, c);
-        if (lane < c) z -= F[lane + c * BLD] * tc;
+    // U t = z: columns bs-1 down to 0, on and above the diagonal
+    const auto load_u = [&](int c0, T (&buf)[SB]) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int c = c0 - u;
+            buf[u] = act && c >= 0 && lane <= c ? F[lane + (size_t)c * bs] : num<T>::zero();
+        }
+    };
+    load_u(bs - 1, cur);
+    for (int c0 = bs - 1; c0 >= 0; c0 -= SB) {
+        if (c0 - SB >= 0) load_u(c0 - SB, nxt);
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int c = c0 - u;
+            if (c >= 0) {
+                if (lane == c) z = bdiv(z, cur[u]);
+                const T tc = bshfl(z, c);
+                if (lane < c) z -= cur[u] * tc;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) cur[u] = nxt[u];
     }
-    if (lane < bs) t[b0 + lane] = z;
+    if (act) t[b0 + lane] = z;
 }
 
 template <class T>
