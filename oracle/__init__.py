@@ -173,6 +173,27 @@ def pattern_sparsified_powers(A, k: int = 3, tau_i: float = 0.1, p_i: int = 0,
     of every t).  With V_0 diagonal the final removal of V_0 minus the
     identity removes nothing.  Real matrices with a nonzero diagonal; pure
     Python, for small cases."""
+    S = _sp_matrix(A, tau_i, p_i)
+    n = A.n
+    out_cp = np.zeros(n + 1, dtype=np.int32)
+    out = []
+    for j in range(n):
+        u = _sp_column(S, j, k, tau_l, p_l)
+        out.append(u)
+        out_cp[j + 1] = out_cp[j] + len(u)
+    return Pattern(n=n, colptr=out_cp, rowidx=np.concatenate(out))
+
+
+def sparsified_powers_columns(A, cols, k: int = 3, tau_i: float = 0.1, p_i: int = 0,
+                              tau_l: float = 0.0, p_l: int = 0) -> dict:
+    """The columns `cols` of pattern_sparsified_powers (same steps), as
+    {j: ascending rows}, for sampled checks of large matrices."""
+    S = _sp_matrix(A, tau_i, p_i)
+    return {int(j): _sp_column(S, int(j), k, tau_l, p_l) for j in cols}
+
+
+def _sp_matrix(A, tau_i, p_i):
+    """The columns of S = D^{-1}(A - D) after the initial dropping."""
     if np.iscomplexobj(A.val):
         raise ValueError("sparsified powers: real matrices only")
     n = A.n
@@ -195,24 +216,23 @@ def pattern_sparsified_powers(A, k: int = 3, tau_i: float = 0.1, p_i: int = 0,
                 rows.append(i)
                 vals.append(va[q] / d[i])
         S.append(_drop(rows, vals, tau_i, p_i, keep=-1))
-    out_cp = np.zeros(n + 1, dtype=np.int32)
-    out = []
-    for j in range(n):
-        srows = {j}
-        t_rows, t_vals = [j], [1.0]
-        for _ in range(k):
-            acc = {}
-            for i, ti in zip(t_rows, t_vals):  # ascending source row
-                r_rows, r_vals = S[i]
-                for r, v in zip(r_rows, r_vals):
-                    acc[r] = acc[r] + v * ti if r in acc else v * ti
-            rows = sorted(acc)
-            t_rows, t_vals = _drop(rows, [acc[r] for r in rows], tau_l, p_l, keep=j)
-            srows.update(t_rows)
-        u = np.array(sorted(srows), dtype=np.int32)
-        out.append(u)
-        out_cp[j + 1] = out_cp[j] + len(u)
-    return Pattern(n=n, colptr=out_cp, rowidx=np.concatenate(out))
+    return S
+
+
+def _sp_column(S, j, k, tau_l, p_l):
+    """Column j: k products t <- S t with dropping, s the union."""
+    srows = {j}
+    t_rows, t_vals = [j], [1.0]
+    for _ in range(k):
+        acc = {}
+        for i, ti in zip(t_rows, t_vals):  # ascending source row
+            r_rows, r_vals = S[i]
+            for r, v in zip(r_rows, r_vals):
+                acc[r] = acc[r] + v * ti if r in acc else v * ti
+        rows = sorted(acc)
+        t_rows, t_vals = _drop(rows, [acc[r] for r in rows], tau_l, p_l, keep=j)
+        srows.update(t_rows)
+    return np.array(sorted(srows), dtype=np.int32)
 
 
 def pattern_1hop(A, ptop: int) -> Pattern:
