@@ -73,23 +73,35 @@ __global__ __launch_bounds__(64) void block_lu_kernel(const int32_t* bstart, con
                                                       int32_t* bad)
 {
     __shared__ T M[BLD * BLD];
+    __shared__ T prow[BLD];
     __shared__ int32_t pv[BLD];
+    __shared__ int32_t cpl[BLD + 1];
     __shared__ int s_sing;
     const int b = blockIdx.x;
     const int lane = threadIdx.x;
     const int b0 = bstart[b], bs = bstart[b + 1] - b0;
     for (int c = 0; c < bs; ++c) M[lane + c * BLD] = num<T>::zero();
+    for (int i = lane; i <= bs; i += 64) cpl[i] = Vcp[b0 + i];
     pv[lane] = lane;
     if (lane == 0) s_sing = 0;
     __syncthreads();
-    for (int c = 0; c < bs; ++c) {
-        for (int p = Vcp[b0 + c] + lane; p < Vcp[b0 + c + 1]; p += 64) {
-            const int i = Vri[p] - b0;
-            if (i >= 0 && i < bs)
-                M[i + c * BLD] = Vval[p];
+    // the block's entries are contiguous in the CSC arrays: each lane takes
+    // every 64th and finds its column by bisection of the column starts, so
+    // all loads are independent
+    for (int p = cpl[0] + lane; p < cpl[bs]; p += 64) {
+        int lo = 0, hi = bs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cpl[mid] <= p)
+                lo = mid;
             else
-                atomicOr(bad, 1 << 30);
+                hi = mid - 1;
         }
+        const int i = Vri[p] - b0;
+        if (i >= 0 && i < bs)
+            M[i + lo * BLD] = Vval[p];
+        else
+            atomicOr(bad, 1 << 30);
     }
     __syncthreads();
     for (int c = 0; c < bs; ++c) {
@@ -123,10 +135,14 @@ __global__ __launch_bounds__(64) void block_lu_kernel(const int32_t* bstart, con
             }
         }
         __syncthreads();
+        // the pivot row in an array of its own, so that the update loop's
+        // loads do not wait on its stores
+        if (lane < bs) prow[lane] = M[c + lane * BLD];
+        __syncthreads();
         if (lane > c && lane < bs) {
-            const T l = bdiv(M[lane + c * BLD], M[c + c * BLD]);
+            const T l = bdiv(M[lane + c * BLD], prow[c]);
             M[lane + c * BLD] = l;
-            for (int q = c + 1; q < bs; ++q) M[lane + q * BLD] -= l * M[c + q * BLD];
+            for (int q = c + 1; q < bs; ++q) M[lane + q * BLD] -= l * prow[q];
         }
         __syncthreads();
     }

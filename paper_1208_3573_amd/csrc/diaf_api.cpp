@@ -210,6 +210,36 @@ Err check_sparsify(const diaf_sparsify* sp)
     return {};
 }
 
+// The spec checks shared by diaf_factor and diaf_autotune (host side, before
+// any device work).
+Err check_spec(const diaf_csc* A, const diaf_spec* spec, int mode)
+{
+    if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return {DIAF_EINVAL, "bad norm mode"};
+    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_TOPK_BLOCK)
+        return {DIAF_EINVAL, "bad v_kind"};
+    const bool lev_rule = spec->v_kind == DIAF_V_LEV_UPPER || spec->v_kind == DIAF_V_LEV_LOWER;
+    if (lev_rule && mode != DIAF_UNIT_V)
+        return {DIAF_EINVAL, "the Section 3.1 V rule is defined for DIAF_UNIT_V"};
+    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_SPARSIFIED)
+        return {DIAF_EINVAL, "bad w_kind"};
+    if (spec->w_kind == DIAF_W_SPARSIFIED) {
+        DIAF_TRY(check_sparsify(&spec->sparsify));
+        if (A->dtype != DIAF_F64)
+            return {DIAF_EUNSUPPORTED, "sparsified powers: real matrices only"};
+    }
+    if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
+        !std::isfinite(spec->stab_tol))
+        return {DIAF_EINVAL, "stab_r and stab_tol must be finite and >= 0"};
+    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER || lev_rule ||
+         spec->v_kind == DIAF_V_TOPK_BLOCK) &&
+        (spec->v_count < 1 || spec->v_count > 64))
+        return {DIAF_EINVAL, "v_count must be in 1..64"};
+    if (spec->w_kind == DIAF_W_A_1HOP_TOPK && (spec->w_topk < 0 || spec->w_topk > 256))
+        return {DIAF_EINVAL, "w_topk must be in 0..256"};
+    if (spec->left != 0 && spec->left != 1) return {DIAF_EINVAL, "left must be 0 or 1"};
+    return {};
+}
+
 // Algorithm 1 (Section 4) with V_0 = diagonals: S built and sparsified once,
 // then the per-column level expansion, counted and filled; columns that
 // outgrow the small LDS tables are rerun with the large ones.
@@ -971,30 +1001,9 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     if (e.code) return fail(ctx, e);
     if (!spec) return fail(ctx, DIAF_EINVAL, "spec is NULL");
     if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return fail(ctx, DIAF_EINVAL, "bad norm mode");
-    if (spec->v_kind < DIAF_V_EXPLICIT || spec->v_kind > DIAF_V_TOPK_BLOCK)
-        return fail(ctx, DIAF_EINVAL, "bad v_kind");
-    const bool lev_rule = spec->v_kind == DIAF_V_LEV_UPPER || spec->v_kind == DIAF_V_LEV_LOWER;
-    if (lev_rule && mode != DIAF_UNIT_V)
-        return fail(ctx, DIAF_EINVAL, "the Section 3.1 V rule is defined for DIAF_UNIT_V");
-    if (spec->w_kind < DIAF_W_A || spec->w_kind > DIAF_W_SPARSIFIED)
-        return fail(ctx, DIAF_EINVAL, "bad w_kind");
-    if (spec->w_kind == DIAF_W_SPARSIFIED) {
-        Err es = check_sparsify(&spec->sparsify);
-        if (es.code) return fail(ctx, es);
-        if (A->dtype != DIAF_F64)
-            return fail(ctx, DIAF_EUNSUPPORTED, "sparsified powers: real matrices only");
-    }
-    if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
-        !std::isfinite(spec->stab_tol))
-        return fail(ctx, DIAF_EINVAL, "stab_r and stab_tol must be finite and >= 0");
-    if ((spec->v_kind == DIAF_V_TOPK_UPPER || spec->v_kind == DIAF_V_TOPK_LOWER || lev_rule ||
-         spec->v_kind == DIAF_V_TOPK_BLOCK) &&
-        (spec->v_count < 1 || spec->v_count > 64))
-        return fail(ctx, DIAF_EINVAL, "v_count must be in 1..64");
-    if (spec->w_kind == DIAF_W_A_1HOP_TOPK && (spec->w_topk < 0 || spec->w_topk > 256))
-        return fail(ctx, DIAF_EINVAL, "w_topk must be in 0..256");
+    e = check_spec(A, spec, mode);
+    if (e.code) return fail(ctx, e);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
-    if (spec->left != 0 && spec->left != 1) return fail(ctx, DIAF_EINVAL, "left must be 0 or 1");
     if (spec->left)
         e = A->dtype == DIAF_F64 ? factor_left<double>(ctx, A, spec, mode, out)
                                  : factor_left<zc>(ctx, A, spec, mode, out);
@@ -1652,7 +1661,8 @@ extern "C" diaf_status diaf_autotune(diaf_ctx* ctx, const diaf_csc* A, const dia
     Err e = check_csc_host(A);
     if (e.code) return fail(ctx, e);
     if (!spec) return fail(ctx, DIAF_EINVAL, "spec is NULL");
-    if (mode != DIAF_UNIT_V && mode != DIAF_UNIT_W) return fail(ctx, DIAF_EINVAL, "bad norm mode");
+    e = check_spec(A, spec, mode);
+    if (e.code) return fail(ctx, e);
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
     e = A->dtype == DIAF_F64 ? autotune_impl<double>(ctx, A, spec, mode)
                              : autotune_impl<zc>(ctx, A, spec, mode);

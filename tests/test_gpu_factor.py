@@ -191,3 +191,16 @@ def test_autotune_keeps_results(ctx, mode):
     for k, v in (("small_grid", 0), ("generic_nt", 0), ("graph", 0), ("solve_batch", 8),
                  ("trsv_backoff", 1), ("trsv_waves", 16)):
         ctx.set_option(k, v)
+
+
+def test_autotune_validates_spec(ctx):
+    """diaf_autotune applies diaf_factor's spec checks before any device work."""
+    from paper_1208_3573_amd import diaf
+    A = synth.random_small(40, 3, 0)
+    dA = diaf.DeviceCSC.from_host(A)
+    for kw in (dict(w="A2", v="topk_lower", v_count=0), dict(w="A2", v="lev_lower", v_count=3),
+               dict(w="sparsified", v="diag", sparsify=dict(k=0))):
+        mode = "unit_w" if kw["v"] == "lev_lower" else "unit_v"
+        with pytest.raises(diaf.DiafError) as ei:
+            diaf.diaf_autotune(ctx, dA, diaf.make_spec(**kw), mode)
+        assert ei.value.code == diaf.DIAF_EINVAL, kw
