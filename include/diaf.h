@@ -254,7 +254,7 @@ const char* diaf_last_error(const struct diaf_ctx* ctx);
  *   "generic_only"       1: every column goes to the generic factor kernel
  *   "small_grid"         workgroups of the one-wave factor kernel (0 = 4096)
  *   "generic_nt"         threads per column of the generic kernel (0 auto, 64,
- *                        128, 256)
+ *                        128, 256, 512)
  *   "solve_batch"        BiCGSTAB iterations between host polls (>= 1)
  *   "graph"              1: replay each batch from one captured hipGraph
  *   "trsv_backoff"       0..256: a triangular-solve wave that made no progress

@@ -922,8 +922,8 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     else if (k == "graph") ctx->opt_graph = value ? 1 : 0;
     else if (k == "small_grid") ctx->ftune.small_grid = value < 0 ? 0 : (int)value;
     else if (k == "generic_nt") {
-        if (value != 0 && value != 64 && value != 128 && value != 256)
-            return fail(ctx, DIAF_EINVAL, "generic_nt must be 0, 64, 128 or 256");
+        if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512)
+            return fail(ctx, DIAF_EINVAL, "generic_nt must be 0, 64, 128, 256 or 512");
         ctx->ftune.generic_nt = (int)value;
     }
     else if (k == "trsv_waves") {
@@ -1557,7 +1557,7 @@ Err autotune_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int m
         ctx->ftune.small_grid = pick;
     }
     if (launches >= 2 || ctx->opt_generic_only || spec->gram_fp32) {
-        const int nts[] = {0, 64, 128, 256};
+        const int nts[] = {0, 64, 128, 256, 512};
         double best = INFINITY;
         int pick = 0;
         for (int t : nts) {

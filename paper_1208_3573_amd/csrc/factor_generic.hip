@@ -22,7 +22,7 @@
 
 namespace diaf {
 
-static constexpr int GNT = 256;  // largest workgroup (small size classes use one wave)
+static constexpr int GNT = 512;  // largest workgroup (small size classes use one wave)
 
 struct GenLayout {
     size_t oJ, oOff, oKey, oVal, oLrow, oCol, oPos, oRowptr, oR, oRank, oY, oW, oX, oVM, oSig,
@@ -964,8 +964,9 @@ GenPlan generic_plan(int kcap, int tcap, int lcap, int mode, int nt_override = 0
 {
     GenPlan P{};
     P.nmats = mode == 0 ? 1 : 3;
-    P.nt = kcap <= 32 ? 64 : GNT;
-    if (nt_override == 64 || nt_override == 128 || nt_override == GNT) P.nt = nt_override;
+    P.nt = kcap <= 32 ? 64 : 256;
+    if (nt_override == 64 || nt_override == 128 || nt_override == 256 || nt_override == GNT)
+        P.nt = nt_override;
     size_t with = generic_lds_bytes<T>(kcap, tcap, lcap, P.nmats);
     size_t without = generic_lds_bytes<T>(kcap, tcap, lcap, 0);
     if (with <= 64 * 1024) {

@@ -51,7 +51,7 @@ Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int
 // Launch shapes chosen by the autotuner (0 = built-in choice).
 struct FactorTune {
     int small_grid = 0;  // workgroups of the one-wave kernel (persistent over columns)
-    int generic_nt = 0;  // threads per column of the generic kernel (64, 128 or 256)
+    int generic_nt = 0;  // threads per column of the generic kernel (64, 128, 256 or 512)
 };
 template <class T>
 Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, void* gws,

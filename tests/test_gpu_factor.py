@@ -181,7 +181,7 @@ def test_autotune_keeps_results(ctx, mode):
     tuned = diaf.diaf_autotune(ctx, dA, spec, mode)
     say(f"{mode}: {tuned}")
     assert tuned["small_grid"] in (1024, 2048, 4096, 8192, 16384)
-    assert tuned["generic_nt"] in (0, 64, 128, 256)
+    assert tuned["generic_nt"] in (0, 64, 128, 256, 512)
     assert tuned["graph"] in (0, 1) and tuned["solve_batch"] in (8, 32)
     F = diaf.diaf_factor(ctx, dA, spec, mode)
     H = F.to_host()
