@@ -179,3 +179,35 @@ def test_block_errors_and_singular_blocks(ctx):
         diaf.diaf_apply(ctx, F, db, x)
     assert ei.value.code == diaf.DIAF_ESINGULAR
     F.close()
+
+
+@pytest.mark.parametrize("mode", ["unit_v", "unit_w"])
+def test_single_block_is_the_whole_matrix(ctx, mode):
+    """One block of all n <= 64 rows: V has the pattern of A (top-k: the
+    diagonal plus any rows of the shadow) and the block LU is a dense LU of V."""
+    import torch
+    from types import SimpleNamespace
+    from paper_1208_3573_amd import diaf
+    A = synth.random_small(60, 4, 13, diag_shift=1.5)
+    st = np.array([0, A.n], dtype=np.int32)
+    dA = diaf.DeviceCSC.from_host(A)
+    J = oracle.pattern_A2(A)
+    for v, l in (("block", 0), ("topk_block", 6)):
+        say(f"case one block of {A.n} rows, V {v}, mode {mode}")
+        F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=v, v_count=l,
+                                                     v_blocks=torch.from_numpy(st).cuda()), mode)
+        H = F.to_host()
+        if v == "block":
+            O = oracle.factor(A, J, mode, "explicit", Vexp=oracle.pattern_vblock(A, st))
+        else:
+            O = oracle.factor(A, J, mode, "topk_block", l, vblocks=st)
+        compare(H, J, O, A, mode)
+        G = SimpleNamespace(n=A.n, Jcp=H["Wcp"], Jri=H["Wri"], Wval=H["Wval"], Vcp=H["Vcp"],
+                            Vri=H["Vri"], Vval=H["Vval"])
+        x = np.random.default_rng(7).standard_normal(A.n)
+        yo = oracle.apply(G, x, "block", st)
+        xd = torch.from_numpy(x).cuda()
+        yd = torch.zeros_like(xd)
+        diaf.diaf_apply(ctx, F, xd, yd)
+        assert np.linalg.norm(yd.cpu().numpy() - yo) <= 1e-10 * np.linalg.norm(yo)
+        F.close()

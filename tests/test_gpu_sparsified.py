@@ -135,3 +135,13 @@ def test_sparsified_errors(ctx):
     with pytest.raises(diaf.DiafError) as ei:
         diaf.diaf_pattern_build_sparsified(ctx, diaf.DeviceCSC.from_host(Al), k=1)
     assert ei.value.code == diaf.DIAF_EUNSUPPORTED
+
+
+def test_sparsified_diagonal_matrix(ctx):
+    from paper_1208_3573_amd import diaf
+    n = 300
+    A = synth._coo_to_csc(n, np.arange(n), np.arange(n), np.linspace(1.0, 3.0, n))
+    dA = diaf.DeviceCSC.from_host(A)
+    say("case diagonal matrix")
+    P = _check(ctx, A, dA, dict(k=4, tau_i=0.0))
+    assert P.nnz == n

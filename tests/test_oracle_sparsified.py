@@ -184,3 +184,13 @@ def test_zero_diagonal_is_rejected():
     A.val[dpos] = 0.0
     with pytest.raises(ValueError):
         oracle.pattern_sparsified_powers(A, k=2)
+
+
+def test_diagonal_matrix_gives_diagonal_pattern():
+    """A diagonal A has S = 0: every power vector is empty after the first
+    product and the pattern is the identity's, for any parameters."""
+    n = 25
+    A = synth._coo_to_csc(n, np.arange(n), np.arange(n), np.linspace(1.0, 3.0, n))
+    for prm in (dict(k=1, tau_i=0.0), dict(k=4, tau_i=0.3, p_l=2)):
+        P = oracle.pattern_sparsified_powers(A, **prm)
+        assert np.array_equal(P.colptr, np.arange(n + 1)) and np.array_equal(P.rowidx, np.arange(n))
