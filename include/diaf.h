@@ -261,9 +261,10 @@ const char* diaf_last_error(const struct diaf_ctx* ctx);
  *                        sleeps 64, 128, 256, ... cycles, up to 64 x the value,
  *                        before polling again (0: never; default 1)
  *   "trsv_waves"         waves per workgroup of the triangular solve (1, 2, 4,
- *                        8, 16; default 16): the workgroup owns 64 x waves
+ *                        8, 16; default 8): the workgroup owns 64 x waves
  *                        consecutive rows, one per lane, sharing their values
- *                        through LDS
+ *                        through LDS; up to 8 waves each row keeps 16 (complex
+ *                        12) off-diagonal entries in LDS, at 16 waves 8 (6)
  *   "gate_small_diag"    1: the learned path also rejects proposals whose V
  *                        diagonal entry is flagged negligible
  * DIAF_EINVAL for an unknown key or value.  get_option reads a value. */

@@ -133,12 +133,13 @@ template <class T>
 Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
                     const int32_t* done, hipStream_t st);
 // Launch shape of the sync-free triangular solve: waves per workgroup (1, 2,
-// 4, 8 or 16; the workgroup owns 64 x waves consecutive rows, one per lane)
-// and whether a wave that found nothing ready sleeps briefly before polling
+// 4, 8 or 16; the workgroup owns 64 x waves consecutive rows, one per lane;
+// up to 8 waves the LDS has room for twice as many entries per row) and
+// whether a wave that found nothing ready sleeps briefly before polling
 // again.
 struct TrsvTune {
     int backoff = 1;
-    int waves = 16;
+    int waves = 8;
 };
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,

@@ -189,7 +189,7 @@ def test_autotune_keeps_results(ctx, mode):
     for key in ("Wcp", "Wri", "Wval", "Vcp", "Vri", "Vval", "r", "flags"):
         assert np.array_equal(R[key], H[key]), key
     for k, v in (("small_grid", 0), ("generic_nt", 0), ("graph", 0), ("solve_batch", 8),
-                 ("trsv_backoff", 1), ("trsv_waves", 16)):
+                 ("trsv_backoff", 1), ("trsv_waves", 8)):
         ctx.set_option(k, v)
 
 

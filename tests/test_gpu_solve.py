@@ -217,5 +217,5 @@ def test_trsv_launch_shapes_agree(ctx, cplx):
         if ref is None:
             ref = y
         assert np.array_equal(y, ref), waves
-    ctx.set_option("trsv_waves", 16)
+    ctx.set_option("trsv_waves", 8)
     F.close()
