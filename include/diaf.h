@@ -264,7 +264,7 @@ const char* diaf_last_error(const struct diaf_ctx* ctx);
  *                        8, 16; default 8): the workgroup owns 64 x waves
  *                        consecutive rows, one per lane, sharing their values
  *                        through LDS; up to 8 waves each row keeps 16 (complex
- *                        12) off-diagonal entries in LDS, at 16 waves 8 (6)
+ *                        12) off-diagonal entries in LDS, at 16 waves 12 (6)
  *   "gate_small_diag"    1: the learned path also rejects proposals whose V
  *                        diagonal entry is flagged negligible
  * DIAF_EINVAL for an unknown key or value.  get_option reads a value. */

@@ -288,8 +288,10 @@ __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp,
 {
     if (done && *done) return;
     constexpr int ROWS = NW * 64;
-    // up to 8 waves the LDS holds twice as many entries per row
-    constexpr int DM = trsv_dmax<T>::v * (NW <= 8 ? 2 : 1);
+    // up to 8 waves the LDS holds twice as many entries per row, at 16 waves
+    // half as many again for real values
+    constexpr int DM = NW <= 8 ? 2 * trsv_dmax<T>::v
+                               : (num<T>::is_complex ? trsv_dmax<T>::v : 3 * trsv_dmax<T>::v / 2);
     __shared__ uint32_t s_chunk;
     __shared__ T sx[ROWS];            // solution of the chunk's rows (sentinel until known)
     __shared__ int sl[NW * DM * 64];  // entry code: chunk-local index, or ~column
