@@ -669,6 +669,26 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     const int ncls = 7;
     std::vector<Bucket> B(ncls);
     for (int c = 0; c < ncls; ++c) { B[c].kcap = classes[c][0]; B[c].tcap = classes[c][1]; }
+    // class of every column (one pass, no per-column allocation), then the
+    // per-class lists at their final sizes
+    const size_t ntot = only ? only->size() : (size_t)n;
+    std::vector<uint8_t> cls_of(ntot);
+    std::vector<size_t> per(ncls, 0);
+    for (size_t q = 0; q < ntot; ++q) {
+        const int j = only ? (*only)[q] : (int)q;
+        const int k = kh[j], t = th[j];
+        int c = 0;
+        while (c < ncls && !(k <= B[c].kcap && t <= B[c].tcap)) ++c;
+        if (c == ncls)
+            return {DIAF_EUNSUPPORTED, "column " + std::to_string(j) + ": |J_j| = " +
+                                           std::to_string(k) + ", gathered entries = " +
+                                           std::to_string(t) + " exceed the limits (256, 8192)"};
+        cls_of[q] = (uint8_t)c;
+        ++per[c];
+    }
+    for (int c = 0; c < ncls; ++c) B[c].cols.reserve(per[c]);
+    for (size_t q = 0; q < ntot; ++q) B[cls_of[q]].cols.push_back(only ? (*only)[q] : (int)q);
+    // deferred columns of the one-wave kernel, placed one by one
     auto place = [&](int j) -> Err {
         int k = kh[j], t = th[j];
         for (int c = 0; c < ncls; ++c)
@@ -677,11 +697,6 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
                                        ", gathered entries = " + std::to_string(t) +
                                        " exceed the limits (256, 8192)"};
     };
-    if (only) {
-        for (int32_t j : *only) DIAF_TRY(place(j));
-    } else {
-        for (int j = 0; j < n; ++j) DIAF_TRY(place(j));
-    }
     int32_t kmax = 0, tmax = 0;
     for (int j = 0; j < n; ++j) { kmax = std::max(kmax, kh[j]); tmax = std::max(tmax, th[j]); }
     F->stats.kmax = kmax;
@@ -723,6 +738,10 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     // kernel only.
     if (!ctx->opt_generic_only && !spec->gram_fp32 && F->lmax <= 8) {
         std::vector<int32_t> small;
+        size_t nsmall = 0;
+        for (int c = 0; c < ncls; ++c)
+            if (B[c].kcap <= 32 && B[c].tcap <= 256) nsmall += B[c].cols.size();
+        small.reserve(nsmall);
         for (int c = 0; c < ncls; ++c) {
             if (B[c].kcap > 32 || B[c].tcap > 256) continue;
             small.insert(small.end(), B[c].cols.begin(), B[c].cols.end());
