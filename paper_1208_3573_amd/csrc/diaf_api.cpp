@@ -114,12 +114,27 @@ size_t scalar_size(int dtype) { return dtype == DIAF_C128 ? 16 : 8; }
 // kCacheCap bytes are kept per device; beyond that, and when hipMalloc runs
 // out of memory, kept blocks are released.  diaf_ctx_destroy releases the
 // blocks kept for its device.
+//
+// Temporaries of queued work (scan and sort workspaces, row counts) take
+// blocks with amalloc and give them back with afree(p, st) right after the
+// last launch that uses them: the block waits on a pending list until a
+// synchronization of st (sync) or of the device (dfree) has covered that
+// launch, and only then joins the kept blocks.  Neither call synchronizes,
+// so the queue keeps running behind the host (the runtime's stream-ordered
+// pool costs up to a millisecond of host time per call at the 64^3 sizes).
 constexpr size_t kCacheCap = size_t(32) << 30;
+
+struct Pending {
+    void* p;
+    size_t cls;
+    hipStream_t st;
+};
 
 struct MemCache {
     std::mutex mu;
     std::unordered_map<void*, size_t> live;               // block -> size class
     std::unordered_map<size_t, std::vector<void*>> kept;  // size class -> idle blocks
+    std::vector<Pending> pending;                         // freed, maybe still in use
     size_t kept_bytes = 0;
 };
 
@@ -144,9 +159,39 @@ int current_device()
     return dev;
 }
 
+// Pending blocks whose stream is st (all of them when all is set) join the
+// kept blocks, or go back to the driver beyond kCacheCap.  The caller has
+// synchronized st (the device).
+void reclaim(int dev, hipStream_t st, bool all)
+{
+    MemCache& c = mem_cache(dev);
+    std::vector<void*> drop;
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        size_t w = 0;
+        for (size_t q = 0; q < c.pending.size(); ++q) {
+            const Pending& e = c.pending[q];
+            if (!all && e.st != st) {
+                c.pending[w++] = e;
+                continue;
+            }
+            if (c.kept_bytes + e.cls <= kCacheCap) {
+                c.kept[e.cls].push_back(e.p);
+                c.kept_bytes += e.cls;
+            } else {
+                drop.push_back(e.p);
+            }
+        }
+        c.pending.resize(w);
+    }
+    for (void* q : drop) (void)hipFree(q);
+}
+
 void release_kept(int dev)
 {
     MemCache& c = mem_cache(dev);
+    (void)hipDeviceSynchronize();
+    reclaim(dev, nullptr, true);
     std::vector<void*> blocks;
     {
         std::lock_guard<std::mutex> g(c.mu);
@@ -209,6 +254,7 @@ void dfree(void* p)
         c.live.erase(it);
     }
     (void)hipDeviceSynchronize();
+    reclaim(current_device(), nullptr, true);
     {
         std::lock_guard<std::mutex> g(c.mu);
         if (c.kept_bytes + cls <= kCacheCap) {
@@ -220,9 +266,31 @@ void dfree(void* p)
     (void)hipFree(p);
 }
 
+}  // namespace
+
+Err diaf::amalloc(void** p, size_t bytes, hipStream_t)
+{
+    return dmalloc(p, bytes);
+}
+
+void diaf::afree(void* p, hipStream_t st)
+{
+    if (!p) return;
+    MemCache& c = mem_cache(current_device());
+    std::lock_guard<std::mutex> g(c.mu);
+    auto it = c.live.find(p);
+    if (it == c.live.end()) return;  // not a block of this cache
+    c.pending.push_back({p, it->second, st});
+    c.live.erase(it);
+}
+
+namespace {
+
+
 Err sync(hipStream_t st)
 {
     DIAF_HIP_TRY(hipStreamSynchronize(st));
+    reclaim(current_device(), st, false);
     return {};
 }
 
@@ -571,11 +639,6 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
     return {};
 }
 
-struct Bucket {
-    int kcap, tcap;
-    std::vector<int32_t> cols;
-};
-
 void free_factors(diaf_factors* F)
 {
     if (!F) return;
@@ -653,54 +716,74 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
 {
     hipStream_t st = ctx->stream;
     const int n = (int)A->n;
-    // per-column sizes
-    int32_t *kd = nullptr, *td = nullptr;
-    DIAF_TRY(dmalloc(&kd, sizeof(int32_t) * n));
-    DIAF_TRY(dmalloc(&td, sizeof(int32_t) * n));
-    DIAF_TRY(launch_column_sizes(n, A->colptr, F->Jcp, F->Jri, kd, td, st));
-    std::vector<int32_t> kh(n), th(n);
-    DIAF_HIP_TRY(hipMemcpyAsync(kh.data(), kd, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    DIAF_HIP_TRY(hipMemcpyAsync(th.data(), td, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
-    DIAF_TRY(sync(st));
-    dfree(kd);
-    dfree(td);
+    std::vector<void*> to_free;
+    struct FreeAll {
+        std::vector<void*>* v;
+        ~FreeAll() { for (void* p : *v) dfree(p); }
+    } free_all{&to_free};
+    const auto scratch = [&](int32_t** p, size_t count) -> Err {
+        DIAF_TRY(dmalloc(p, sizeof(int32_t) * std::max<size_t>(count, 1)));
+        to_free.push_back(*p);
+        return {};
+    };
+    // per-column sizes, then the columns sorted by size class on the device
+    // (stable: ascending columns, or the order of `only`, within a class)
     static const int classes[][2] = {{16, 128}, {32, 256}, {64, 512}, {64, 1024}, {128, 2048},
                                      {256, 4096}, {256, 8192}};
     const int ncls = 7;
-    std::vector<Bucket> B(ncls);
-    for (int c = 0; c < ncls; ++c) { B[c].kcap = classes[c][0]; B[c].tcap = classes[c][1]; }
-    // class of every column (one pass, no per-column allocation), then the
-    // per-class lists at their final sizes
-    const size_t ntot = only ? only->size() : (size_t)n;
-    std::vector<uint8_t> cls_of(ntot);
-    std::vector<size_t> per(ncls, 0);
-    for (size_t q = 0; q < ntot; ++q) {
-        const int j = only ? (*only)[q] : (int)q;
-        const int k = kh[j], t = th[j];
-        int c = 0;
-        while (c < ncls && !(k <= B[c].kcap && t <= B[c].tcap)) ++c;
-        if (c == ncls)
-            return {DIAF_EUNSUPPORTED, "column " + std::to_string(j) + ": |J_j| = " +
-                                           std::to_string(k) + ", gathered entries = " +
-                                           std::to_string(t) + " exceed the limits (256, 8192)"};
-        cls_of[q] = (uint8_t)c;
-        ++per[c];
+    ColumnClasses cc{};
+    cc.ncls = ncls;
+    for (int c = 0; c < ncls; ++c) { cc.kcap[c] = classes[c][0]; cc.tcap[c] = classes[c][1]; }
+    const int m = only ? (int)only->size() : n;
+    int32_t *kd = nullptr, *td = nullptr, *sel = nullptr, *sorted = nullptr, *meta = nullptr;
+    DIAF_TRY(scratch(&kd, n));
+    DIAF_TRY(scratch(&td, n));
+    DIAF_TRY(scratch(&sorted, m));
+    DIAF_TRY(scratch(&meta, 2 * (ColumnClasses::kMax + 1) + 2));
+    DIAF_TRY(launch_column_sizes(n, A->colptr, F->Jcp, F->Jri, kd, td, st));
+    if (only) {
+        DIAF_TRY(scratch(&sel, m));
+        DIAF_HIP_TRY(hipMemcpyAsync(sel, only->data(), sizeof(int32_t) * m, hipMemcpyHostToDevice,
+                                    st));
     }
-    for (int c = 0; c < ncls; ++c) B[c].cols.reserve(per[c]);
-    for (size_t q = 0; q < ntot; ++q) B[cls_of[q]].cols.push_back(only ? (*only)[q] : (int)q);
-    // deferred columns of the one-wave kernel, placed one by one
-    auto place = [&](int j) -> Err {
-        int k = kh[j], t = th[j];
-        for (int c = 0; c < ncls; ++c)
-            if (k <= B[c].kcap && t <= B[c].tcap) { B[c].cols.push_back(j); return {}; }
-        return {DIAF_EUNSUPPORTED, "column " + std::to_string(j) + ": |J_j| = " + std::to_string(k) +
-                                       ", gathered entries = " + std::to_string(t) +
-                                       " exceed the limits (256, 8192)"};
+    int32_t* dmeta = meta + ColumnClasses::kMax + 1;  // counts of the deferred columns
+    int32_t* maxes = meta + 2 * (ColumnClasses::kMax + 1);
+    DIAF_TRY(launch_classify_columns(n, m, sel, kd, td, cc, sorted, meta, maxes, st));
+    int32_t hm[2 * (ColumnClasses::kMax + 1) + 2] = {};
+    DIAF_HIP_TRY(hipMemcpyAsync(hm, meta, sizeof(hm), hipMemcpyDeviceToHost, st));
+    DIAF_TRY(sync(st));
+    if (hm[ncls] > 0) {
+        // a column beyond every class: name the first one
+        std::vector<int32_t> kh(n), th(n);
+        DIAF_HIP_TRY(hipMemcpyAsync(kh.data(), kd, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(th.data(), td, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        DIAF_TRY(sync(st));
+        for (int q = 0; q < m; ++q) {
+            const int j = only ? (*only)[q] : q;
+            if (kh[j] > cc.kcap[ncls - 1] || th[j] > cc.tcap[ncls - 1])
+                return {DIAF_EUNSUPPORTED, "column " + std::to_string(j) + ": |J_j| = " +
+                                               std::to_string(kh[j]) + ", gathered entries = " +
+                                               std::to_string(th[j]) +
+                                               " exceed the limits (256, 8192)"};
+        }
+        return {DIAF_EINVAL, "internal: column class counts"};
+    }
+    // launch list: (class, first entry, count) over `sorted`
+    struct Seg {
+        int c;
+        const int32_t* cols;
+        int count;
     };
-    int32_t kmax = 0, tmax = 0;
-    for (int j = 0; j < n; ++j) { kmax = std::max(kmax, kh[j]); tmax = std::max(tmax, th[j]); }
-    F->stats.kmax = kmax;
-    F->stats.mmax = tmax;
+    std::vector<Seg> segs;
+    {
+        int off = 0;
+        for (int c = 0; c < ncls; ++c) {
+            if (hm[c]) segs.push_back({c, sorted + off, hm[c]});
+            off += hm[c];
+        }
+    }
+    F->stats.kmax = hm[2 * (ColumnClasses::kMax + 1)];
+    F->stats.mmax = hm[2 * (ColumnClasses::kMax + 1) + 1];
     FactorArgs<T> fa{};
     fa.n = n;
     fa.Acp = A->colptr;
@@ -729,82 +812,86 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     fa.bnorm = F->bnorm;
     fa.flags = F->flags;
     fa.lcount = F->lcount;
-    std::vector<void*> to_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    int nb = 0;
-    // Small columns go to the one-wave kernel (both norm modes); columns it
-    // cannot hold (shadow above 64 rows) come back on a deferred list for the
-    // generic kernel.  The FP32-Gram variant is implemented by the generic
-    // kernel only.
-    if (!ctx->opt_generic_only && !spec->gram_fp32 && F->lmax <= 8) {
-        std::vector<int32_t> small;
-        size_t nsmall = 0;
-        for (int c = 0; c < ncls; ++c)
-            if (B[c].kcap <= 32 && B[c].tcap <= 256) nsmall += B[c].cols.size();
-        small.reserve(nsmall);
-        for (int c = 0; c < ncls; ++c) {
-            if (B[c].kcap > 32 || B[c].tcap > 256) continue;
-            small.insert(small.end(), B[c].cols.begin(), B[c].cols.end());
-            B[c].cols.clear();
+    struct FreeEvents {
+        std::vector<std::pair<hipEvent_t, hipEvent_t>>* v;
+        ~FreeEvents() {
+            for (auto& e : *v) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
         }
-        if (!small.empty()) {
-            int32_t *cols = nullptr, *defl = nullptr, *ndef = nullptr;
-            DIAF_TRY(dmalloc(&cols, sizeof(int32_t) * small.size()));
-            DIAF_TRY(dmalloc(&defl, sizeof(int32_t) * small.size()));
-            DIAF_TRY(dmalloc(&ndef, sizeof(int32_t)));
-            to_free.push_back(cols);
-            to_free.push_back(defl);
-            to_free.push_back(ndef);
-            DIAF_HIP_TRY(hipMemcpyAsync(cols, small.data(), sizeof(int32_t) * small.size(),
-                                        hipMemcpyHostToDevice, st));
+    } free_events{&events};
+    const auto timed = [&](auto&& launch) -> Err {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        DIAF_HIP_TRY(hipEventCreate(&e0));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return {DIAF_EDEVICE, "hipEventCreate"};
+        }
+        events.push_back({e0, e1});
+        DIAF_HIP_TRY(hipEventRecord(e0, st));
+        DIAF_TRY(launch());
+        DIAF_HIP_TRY(hipEventRecord(e1, st));
+        return {};
+    };
+    int nb = 0;
+    // Small columns (the classes within 32 rows of J_j and 256 gathered
+    // entries, which come first in `sorted`) go to the one-wave kernel (both
+    // norm modes); columns it cannot hold (shadow above 64 rows) come back on
+    // a deferred list, sorted and classified again for the generic kernel.
+    // The FP32-Gram variant is implemented by the generic kernel only.
+    if (!ctx->opt_generic_only && !spec->gram_fp32 && F->lmax <= 8) {
+        int nsmall = 0, nseg = 0;
+        while (nseg < (int)segs.size() && cc.kcap[segs[nseg].c] <= 32 && cc.tcap[segs[nseg].c] <= 256)
+            nsmall += segs[nseg++].count;
+        if (nsmall > 0) {
+            segs.erase(segs.begin(), segs.begin() + nseg);
+            int32_t *defl = nullptr, *ndef = nullptr, *dsorted = nullptr, *dtmp = nullptr;
+            DIAF_TRY(scratch(&defl, nsmall));
+            DIAF_TRY(scratch(&ndef, 1));
             DIAF_HIP_TRY(hipMemsetAsync(ndef, 0, sizeof(int32_t), st));
-            fa.cols = cols;
-            fa.ncols = (int)small.size();
-            hipEvent_t e0, e1;
-            DIAF_HIP_TRY(hipEventCreate(&e0));
-            DIAF_HIP_TRY(hipEventCreate(&e1));
-            DIAF_HIP_TRY(hipEventRecord(e0, st));
-            DIAF_TRY(launch_factor_small<T>(fa, defl, ndef, ctx->ftune, st));
-            DIAF_HIP_TRY(hipEventRecord(e1, st));
-            events.push_back({e0, e1});
+            fa.cols = sorted;
+            fa.ncols = nsmall;
+            DIAF_TRY(timed([&] { return launch_factor_small<T>(fa, defl, ndef, ctx->ftune, st); }));
             ++nb;
             int32_t nd = 0;
             DIAF_TRY(read1(ndef, &nd, st));
             if (nd > 0) {
-                std::vector<int32_t> dl(nd);
-                DIAF_HIP_TRY(hipMemcpyAsync(dl.data(), defl, sizeof(int32_t) * nd,
+                DIAF_TRY(scratch(&dtmp, nd));
+                DIAF_TRY(scratch(&dsorted, nd));
+                DIAF_TRY(sort_columns(n, nd, defl, dtmp, st));
+                DIAF_TRY(launch_classify_columns(n, nd, dtmp, kd, td, cc, dsorted, dmeta, nullptr, st));
+                int32_t dh[ColumnClasses::kMax + 1] = {};
+                DIAF_HIP_TRY(hipMemcpyAsync(dh, dmeta, sizeof(int32_t) * (ncls + 1),
                                             hipMemcpyDeviceToHost, st));
                 DIAF_TRY(sync(st));
-                std::sort(dl.begin(), dl.end());
-                for (int32_t j : dl) DIAF_TRY(place(j));
+                std::vector<Seg> d;
+                int off = 0;
+                for (int c = 0; c < ncls; ++c) {
+                    if (dh[c]) d.push_back({c, dsorted + off, dh[c]});
+                    off += dh[c];
+                }
+                segs.insert(segs.begin(), d.begin(), d.end());
             }
             F->stats.count_deferred += nd;
         }
     }
-    for (auto& b : B) {
-        if (b.cols.empty()) continue;
+    for (const Seg& g : segs) {
         ++nb;
-        int32_t* cols = nullptr;
-        DIAF_TRY(dmalloc(&cols, sizeof(int32_t) * b.cols.size()));
-        to_free.push_back(cols);
-        DIAF_HIP_TRY(hipMemcpyAsync(cols, b.cols.data(), sizeof(int32_t) * b.cols.size(),
-                                    hipMemcpyHostToDevice, st));
-        fa.cols = cols;
-        fa.ncols = (int)b.cols.size();
+        fa.cols = g.cols;
+        fa.ncols = g.count;
+        const int kcap = cc.kcap[g.c], tcap = cc.tcap[g.c];
         int nslots = 1024;
-        size_t gbytes = generic_global_bytes<T>(b.kcap, b.tcap, F->lmax, mode, nslots);
+        size_t gbytes = generic_global_bytes<T>(kcap, tcap, F->lmax, mode, nslots);
         void* gm = nullptr;
         if (gbytes) {
             DIAF_TRY(dmalloc((unsigned char**)&gm, gbytes));
             to_free.push_back(gm);
         }
-        hipEvent_t e0, e1;
-        DIAF_HIP_TRY(hipEventCreate(&e0));
-        DIAF_HIP_TRY(hipEventCreate(&e1));
-        DIAF_HIP_TRY(hipEventRecord(e0, st));
-        DIAF_TRY(launch_factor_generic<T>(fa, b.kcap, b.tcap, F->lmax, gm, nslots, ctx->ftune, st));
-        DIAF_HIP_TRY(hipEventRecord(e1, st));
-        events.push_back({e0, e1});
+        DIAF_TRY(timed([&] {
+            return launch_factor_generic<T>(fa, kcap, tcap, F->lmax, gm, nslots, ctx->ftune, st);
+        }));
     }
     DIAF_TRY(sync(st));
     double kms = 0;
@@ -812,12 +899,9 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         float ms = 0;
         DIAF_HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
         kms += ms;
-        (void)hipEventDestroy(ev.first);
-        (void)hipEventDestroy(ev.second);
     }
     F->stats.ms_factor_kernels += kms;
     F->stats.factor_launches += (int32_t)events.size();
-    for (void* p : to_free) dfree(p);
     if (nbuckets) *nbuckets = nb;
     return {};
 }

@@ -44,6 +44,22 @@ Err launch_sp_expand(int n, const int32_t* Acp, const int32_t* Sri, const double
 // Per-column sizes for bucketing: k[j] = |J_j|, t[j] = sum nnz(A(:, J_j)).
 Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int32_t* Jri,
                         int32_t* kout, int32_t* tout, hipStream_t st);
+// Size classes of the factor launches (capacity in |J_j| and in gathered
+// entries), smallest first.
+struct ColumnClasses {
+    static constexpr int kMax = 8;
+    int ncls;
+    int kcap[kMax];
+    int tcap[kMax];
+};
+// The m columns sel[0..m) (0..m-1 when sel is null) stably sorted by class
+// into sorted[0..m); counts[0..ncls] per class (ncls: fits none); maxes[0..1]
+// the largest k and t over all n columns (null: not taken).
+Err launch_classify_columns(int n, int m, const int32_t* sel, const int32_t* kk, const int32_t* tt,
+                            const ColumnClasses& cc, int32_t* sorted, int32_t* counts,
+                            int32_t* maxes, hipStream_t st);
+// Ascending sort of m column indices below n.
+Err sort_columns(int n, int m, const int32_t* in, int32_t* out, hipStream_t st);
 
 // ---- factoring (factor_generic.hip, factor_small.hip) ----
 // gws: global workspace of generic_global_bytes(...) bytes (may be null when
@@ -65,6 +81,11 @@ Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, F
                         hipStream_t st);
 
 // ---- assembly and sparse utilities (sparse.hip) ----
+// Temporary device block for work queued on st, released with afree(p, st)
+// after the last launch that uses it (no synchronization either way: the
+// block is reused only once a later synchronization of st has passed).
+Err amalloc(void** p, size_t bytes, hipStream_t st);
+void afree(void* p, hipStream_t st);
 // Exclusive scan of n ints into out[n+1] (out[n] = total); temp via hipcub.
 Err exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t st);
 template <class T>

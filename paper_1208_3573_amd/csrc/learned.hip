@@ -157,13 +157,13 @@ Err launch_features(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval
 {
     if (n == 0) return {};
     double* buf = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync((void**)&buf, sizeof(double) * 3 * (size_t)n, st));
+    DIAF_TRY(amalloc((void**)&buf, sizeof(double) * 3 * (size_t)n, st));
     hipLaunchKernelGGL(colstats_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Ari,
                        Aval, buf, buf + n, buf + 2 * (size_t)n);
     hipLaunchKernelGGL(features_kernel<T>, dim3(n), dim3(64), 0, st, n, Acp, Ari, Aval, Ccp, Cri,
                        buf, buf + n, buf + 2 * (size_t)n, feat);
     DIAF_HIP_TRY(hipGetLastError());
-    DIAF_HIP_TRY(hipFreeAsync(buf, st));
+    afree(buf, st);
     return {};
 }
 
@@ -194,13 +194,13 @@ Err launch_labels(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, 
 {
     if (n == 0) return {};
     double* buf = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync((void**)&buf, sizeof(double) * 3 * (size_t)n, st));
+    DIAF_TRY(amalloc((void**)&buf, sizeof(double) * 3 * (size_t)n, st));
     hipLaunchKernelGGL(colstats_kernel<T>, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Ari,
                        Aval, buf, buf + n, buf + 2 * (size_t)n);
     hipLaunchKernelGGL(labels_kernel<T>, dim3(n), dim3(64), 0, st, n, Jcp, Jri, Wval,
                        buf + 2 * (size_t)n, tau, labels);
     DIAF_HIP_TRY(hipGetLastError());
-    DIAF_HIP_TRY(hipFreeAsync(buf, st));
+    afree(buf, st);
     return {};
 }
 

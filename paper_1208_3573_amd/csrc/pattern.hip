@@ -12,6 +12,8 @@
 // Each column is one workgroup: candidates are gathered into LDS, sorted
 // with a bitonic network and deduplicated.  A first launch counts, a
 // second fills the rows at the scanned offsets.
+#include <hipcub/hipcub.hpp>
+
 #include "dcommon.h"
 #include "factor_kernels.h"
 
@@ -66,6 +68,101 @@ Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int
     hipLaunchKernelGGL(column_sizes_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Acp, Jcp,
                        Jri, kout, tout);
     DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+// Factor launch classes.  Column sel[i] (i when sel is null) goes to the
+// first class c with k <= kcap[c] and t <= tcap[c], ncls when none fits;
+// key/val receive (class, column) for a stable sort by class, counts[c] the
+// number of columns of class c, and maxes[0..1] the largest k and t over all
+// n columns (maxes null: not taken).  Per-workgroup tallies in LDS, one
+// global atomic per workgroup and class.
+__global__ void __launch_bounds__(256) classify_kernel(int n, int m, const int32_t* sel,
+                                                       const int32_t* kk, const int32_t* tt,
+                                                       ColumnClasses cc, int32_t* key,
+                                                       int32_t* val, int32_t* counts,
+                                                       int32_t* maxes)
+{
+    __shared__ int32_t tally[ColumnClasses::kMax + 1];
+    __shared__ int32_t mx[2];
+    const int tid = threadIdx.x;
+    if (tid <= cc.ncls) tally[tid] = 0;
+    if (tid < 2) mx[tid] = 0;
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + tid;
+    if (i < m) {
+        const int j = sel ? sel[i] : i;
+        const int k = kk[j], t = tt[j];
+        int c = 0;
+        while (c < cc.ncls && !(k <= cc.kcap[c] && t <= cc.tcap[c])) ++c;
+        key[i] = c;
+        val[i] = j;
+        atomicAdd(&tally[c], 1);
+    }
+    if (maxes) {
+        int km = 0, tm = 0;
+        if (i < n) { km = kk[i]; tm = tt[i]; }
+        for (int o = 32; o > 0; o >>= 1) {
+            km = max(km, __shfl_xor(km, o));
+            tm = max(tm, __shfl_xor(tm, o));
+        }
+        if ((tid & 63) == 0) {
+            atomicMax(&mx[0], km);
+            atomicMax(&mx[1], tm);
+        }
+    }
+    __syncthreads();
+    if (tid <= cc.ncls && tally[tid]) atomicAdd(&counts[tid], tally[tid]);
+    if (maxes && tid < 2 && mx[tid]) atomicMax(&maxes[tid], mx[tid]);
+}
+
+Err launch_classify_columns(int n, int m, const int32_t* sel, const int32_t* kk, const int32_t* tt,
+                            const ColumnClasses& cc, int32_t* sorted, int32_t* counts,
+                            int32_t* maxes, hipStream_t st)
+{
+    if (cc.ncls < 1 || cc.ncls > ColumnClasses::kMax) return {DIAF_EINVAL, "internal: column classes out of range"};
+    DIAF_HIP_TRY(hipMemsetAsync(counts, 0, sizeof(int32_t) * (cc.ncls + 1), st));
+    if (maxes) DIAF_HIP_TRY(hipMemsetAsync(maxes, 0, sizeof(int32_t) * 2, st));
+    const int cover = maxes ? std::max(n, m) : m;
+    if (cover == 0) return {};
+    int32_t *key = nullptr, *kout = nullptr, *val = nullptr;
+    const size_t mm = (size_t)std::max(m, 1);
+    DIAF_TRY(amalloc((void**)&key, sizeof(int32_t) * mm, st));
+    DIAF_TRY(amalloc((void**)&kout, sizeof(int32_t) * mm, st));
+    DIAF_TRY(amalloc((void**)&val, sizeof(int32_t) * mm, st));
+    hipLaunchKernelGGL(classify_kernel, dim3((unsigned)((cover + 255) / 256)), dim3(256), 0, st, n,
+                       m, sel, kk, tt, cc, key, val, counts, maxes);
+    DIAF_HIP_TRY(hipGetLastError());
+    if (m > 0) {
+        int bits = 1;
+        while ((1 << bits) <= cc.ncls) ++bits;
+        size_t tmp_bytes = 0;
+        DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, key, kout, val, sorted,
+                                                        m, 0, bits, st));
+        void* tmp = nullptr;
+        DIAF_TRY(amalloc(&tmp, tmp_bytes, st));
+        DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, kout, val, sorted, m,
+                                                        0, bits, st));
+        afree(tmp, st);
+    }
+    afree(key, st);
+    afree(kout, st);
+    afree(val, st);
+    return {};
+}
+
+// Ascending sort of m column indices (values below n).
+Err sort_columns(int n, int m, const int32_t* in, int32_t* out, hipStream_t st)
+{
+    if (m == 0) return {};
+    int bits = 1;
+    while ((1ll << bits) < (int64_t)n) ++bits;
+    size_t tmp_bytes = 0;
+    DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortKeys(nullptr, tmp_bytes, in, out, m, 0, bits, st));
+    void* tmp = nullptr;
+    DIAF_TRY(amalloc(&tmp, tmp_bytes, st));
+    DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortKeys(tmp, tmp_bytes, in, out, m, 0, bits, st));
+    afree(tmp, st);
     return {};
 }
 

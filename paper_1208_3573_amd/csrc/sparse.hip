@@ -22,15 +22,15 @@ Err exclusive_scan_i32(const int32_t* in, int32_t* out, int n, hipStream_t st)
     // out[0..n] = exclusive prefix sums of in[0..n) followed by the total:
     // scan n+1 values with a trailing zero.
     int32_t* tmp = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync((void**)&tmp, sizeof(int32_t) * (n + 1), st));
+    DIAF_TRY(amalloc((void**)&tmp, sizeof(int32_t) * (n + 1), st));
     hipLaunchKernelGGL(shift_kernel, dim3((n + 1 + 255) / 256), dim3(256), 0, st, in, tmp, n);
     size_t bytes = 0;
     DIAF_HIP_TRY(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, tmp, out, n + 1, st));
     void* ws = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync(&ws, bytes, st));
+    DIAF_TRY(amalloc(&ws, bytes, st));
     DIAF_HIP_TRY(hipcub::DeviceScan::ExclusiveSum(ws, bytes, tmp, out, n + 1, st));
-    DIAF_HIP_TRY(hipFreeAsync(ws, st));
-    DIAF_HIP_TRY(hipFreeAsync(tmp, st));
+    afree(ws, st);
+    afree(tmp, st);
     return {};
 }
 
@@ -105,18 +105,18 @@ Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T
                int32_t* rp, int32_t* ci, T* cval, hipStream_t st)
 {
     int32_t* cnt = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync((void**)&cnt, sizeof(int32_t) * (n + 1), st));
+    DIAF_TRY(amalloc((void**)&cnt, sizeof(int32_t) * (n + 1), st));
     DIAF_HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(int32_t) * (n + 1), st));
     if (nnz > 0)
         hipLaunchKernelGGL(row_count_kernel, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st,
                            nnz, ri, cnt);
     DIAF_TRY(exclusive_scan_i32(cnt, rp, n, st));
-    DIAF_HIP_TRY(hipFreeAsync(cnt, st));
+    afree(cnt, st);
     if (nnz == 0) return {};
     int32_t *kout = nullptr, *vin = nullptr, *vout = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync((void**)&kout, sizeof(int32_t) * nnz, st));
-    DIAF_HIP_TRY(hipMallocAsync((void**)&vin, sizeof(int32_t) * nnz, st));
-    DIAF_HIP_TRY(hipMallocAsync((void**)&vout, sizeof(int32_t) * nnz, st));
+    DIAF_TRY(amalloc((void**)&kout, sizeof(int32_t) * nnz, st));
+    DIAF_TRY(amalloc((void**)&vin, sizeof(int32_t) * nnz, st));
+    DIAF_TRY(amalloc((void**)&vout, sizeof(int32_t) * nnz, st));
     const unsigned blocks = (unsigned)((nnz + 255) / 256);
     hipLaunchKernelGGL(iota_kernel, dim3(blocks), dim3(256), 0, st, nnz, vin);
     int bits = 1;
@@ -125,16 +125,16 @@ Err csc_to_csr(int n, int64_t nnz, const int32_t* cp, const int32_t* ri, const T
     DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, ri, kout, vin, vout,
                                                     (int)nnz, 0, bits, st));
     void* tmp = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync(&tmp, tmp_bytes, st));
+    DIAF_TRY(amalloc(&tmp, tmp_bytes, st));
     DIAF_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, ri, kout, vin, vout, (int)nnz,
                                                     0, bits, st));
     hipLaunchKernelGGL(gather_csr_kernel<T>, dim3(blocks), dim3(256), 0, st, n, nnz, cp, val, vout,
                        ci, cval);
     DIAF_HIP_TRY(hipGetLastError());
-    DIAF_HIP_TRY(hipFreeAsync(tmp, st));
-    DIAF_HIP_TRY(hipFreeAsync(kout, st));
-    DIAF_HIP_TRY(hipFreeAsync(vin, st));
-    DIAF_HIP_TRY(hipFreeAsync(vout, st));
+    afree(tmp, st);
+    afree(kout, st);
+    afree(vin, st);
+    afree(vout, st);
     return {};
 }
 
@@ -224,12 +224,12 @@ Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* co
 {
     int nb = (n + 255) / 256;
     double* partial = nullptr;
-    DIAF_HIP_TRY(hipMallocAsync((void**)&partial, sizeof(double) * (nb + 1), st));
+    DIAF_TRY(amalloc((void**)&partial, sizeof(double) * (nb + 1), st));
     hipLaunchKernelGGL(flag_stats_kernel, dim3(nb), dim3(256), 0, st, n, flags, r, counts_dev,
                        partial);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, st, nb, partial, nrm2_dev);
     DIAF_HIP_TRY(hipGetLastError());
-    DIAF_HIP_TRY(hipFreeAsync(partial, st));
+    afree(partial, st);
     return {};
 }
 

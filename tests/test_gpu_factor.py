@@ -54,7 +54,33 @@ def test_factor_parity_small(ctx, name):
         st = F.stats()
         assert st.nnz_w == J.nnz and st.nnz_v == O.Vcp[-1]
         assert abs(st.nrm - np.sqrt(np.sum(H["r"] ** 2))) <= 1e-12 * max(1.0, st.nrm)
+        if name == "random_3k_1hop":
+            # every launch class occurs: one-wave columns, columns it hands
+            # back (shadow above 64 rows) and larger generic columns
+            small, deferred, generic = _launch_classes(A, J)
+            say(f"classes: one-wave {small} deferred {deferred} generic {generic}")
+            assert small > 0 and deferred > 0 and generic > 0
+            assert st.count_deferred == deferred
+            assert st.factor_launches >= 3
         F.close()
+
+
+def _launch_classes(A, J):
+    """Columns the one-wave kernel keeps (|J_j| <= 32, gathered entries
+    <= 256, shadow <= 64 rows), hands back (shadow above 64) and never gets."""
+    small = deferred = generic = 0
+    for j in range(A.n):
+        rows = J.rowidx[J.colptr[j]:J.colptr[j + 1]]
+        t = int(np.sum(A.colptr[rows + 1] - A.colptr[rows]))
+        if len(rows) > 32 or t > 256:
+            generic += 1
+            continue
+        shadow = np.unique(np.concatenate([A.rowidx[A.colptr[c]:A.colptr[c + 1]] for c in rows]))
+        if shadow.size > 64:
+            deferred += 1
+        else:
+            small += 1
+    return small, deferred, generic
 
 
 def _sample(n, k, seed):
