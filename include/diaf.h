@@ -245,8 +245,16 @@ typedef struct diaf_solve_info {
 /* ---- context ---------------------------------------------------------- */
 
 /* Create a context on HIP device `device` that orders all work on
- * `hip_stream` (a hipStream_t; NULL = the null stream). */
+ * `hip_stream` (a hipStream_t; NULL = the null stream).
+ *
+ * Device memory: the library keeps the blocks it frees (up to 32 GiB per
+ * device, shared by all contexts on that device) and reuses them in later
+ * calls instead of calling hipMalloc and hipFree each time; it releases them
+ * when hipMalloc runs out of memory.  Freeing a block waits for the device
+ * to be idle, as hipFree does. */
 diaf_status diaf_ctx_create(struct diaf_ctx** ctx, int device, void* hip_stream);
+/* Waits for the device, releases the device memory the library keeps for
+ * this context's device, and frees the context. */
 void diaf_ctx_destroy(struct diaf_ctx* ctx);
 const char* diaf_last_error(const struct diaf_ctx* ctx);
 /* Tunables of the context (not of the method: results are identical for

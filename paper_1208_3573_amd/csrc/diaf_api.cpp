@@ -1686,7 +1686,10 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         }
         return {};
     };
-    // captured once, replayed per batch (kernels only: no memset or copy nodes)
+    // captured once, replayed per batch (kernels only: no memset or copy
+    // nodes).  The first batch is launched directly and the capture and
+    // instantiation run on the host while the device works through it; the
+    // kernels and their order are the same either way.
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     struct GraphFree {
@@ -1696,7 +1699,7 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
             if (*g) (void)hipGraphDestroy(*g);
         }
     } gfree{&graph, &gexec};
-    if (use_graph) {
+    const auto capture = [&]() -> Err {
         DIAF_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         Err e = enqueue_batch();
         hipGraph_t g = nullptr;
@@ -1705,10 +1708,12 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         DIAF_TRY(e);
         DIAF_HIP_TRY(ec);
         DIAF_HIP_TRY(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-    }
+        return {};
+    };
     for (int it0 = 0;; it0 += batch) {
-        if (use_graph) DIAF_HIP_TRY(hipGraphLaunch(gexec, st));
+        if (gexec) DIAF_HIP_TRY(hipGraphLaunch(gexec, st));
         else DIAF_TRY(enqueue_batch());
+        if (use_graph && !gexec) DIAF_TRY(capture());
         DIAF_TRY(read1(V.st, &hs, st));
         if (F && (F->vtri == 1 || F->vtri == -1)) {
             TrsvCtl c{};
