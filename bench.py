@@ -245,6 +245,7 @@ def main():
     solve_ms = float(np.mean(R[:, 5]))
     iters = int(R[-1, 6])
     st = last.stats()
+    levels = last.levels()  # diagnostic depth of the V solve, taken after the timed steps
     H = last.to_host()
     sv = 16 if A.is_complex else 8
     bytes_alg, gathered = algorithmic_bytes(A, H["Wri"], H["lcount"], sv)
@@ -279,7 +280,7 @@ def main():
         "bicgstab_iters": iters,
         "relres_true": float(R[-1, 7]),
         "nrm": st.nrm,
-        "v_levels": st.v_levels,
+        "v_levels": levels,
         "autotuned": tuned,
         "roofline": ({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
@@ -308,7 +309,7 @@ def main():
         for _ in range(args.steps):
             F, lst, linfo, lf, ls = step(lspec)
             log(f"learned step: factor {lf:.1f} ms, solve {ls:.1f} ms, {linfo.iters} its")
-            lrec.append((lf, ls, linfo.iters, lst.count_fell_back, lst.nnz_w, lst.v_levels))
+            lrec.append((lf, ls, linfo.iters, lst.count_fell_back, lst.nnz_w, F.levels()))
             F.close()
         L_ = np.array(lrec, dtype=float)
         out["learned"] = {"factor_ms": float(L_[:, 0].mean()), "solve_ms": float(L_[:, 1].mean()),
@@ -318,7 +319,7 @@ def main():
                           "v_levels": int(L_[-1, 5])}
         out["plain"] = {"factor_ms": factor_ms, "solve_ms": solve_ms,
                         "e2e_ms": factor_ms + solve_ms, "bicgstab_iters": iters,
-                        "nnz_w": int(len(H["Wri"])), "v_levels": int(st.v_levels)}
+                        "nnz_w": int(len(H["Wri"])), "v_levels": int(levels)}
         model.close()
 
     if args.variants:
@@ -337,7 +338,7 @@ def main():
                     f"flag {vinfo.flag}, relres_true {vinfo.relres_true:.2e}")
                 if it >= args.warmup:
                     rec.append((vf, vs, vst.ms_pattern, vst.ms_factor_kernels, vinfo.iters,
-                                vinfo.flag, vinfo.relres_true, vst.nnz_w, vst.v_levels, vst.nrm))
+                                vinfo.flag, vinfo.relres_true, vst.nnz_w, F.levels(), vst.nrm))
                 F.close()
             Rv = np.array(rec, dtype=float)
             out["variants"][name] = {

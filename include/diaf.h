@@ -222,8 +222,10 @@ typedef struct diaf_stats {
     int32_t nbuckets;                /* size classes launched */
     int32_t count_rank_deficient, count_gap_degenerate, count_small_diag, count_tie_edge,
         count_fell_back, count_no_diag;
-    int32_t v_levels;                /* dependency depth of the triangular V solve
-                                        (filled by the first apply or solve) */
+    int32_t v_levels;                /* dependency depth of the V solve: 1 for a
+                                        (block) diagonal V after the first apply
+                                        or solve, for a triangular V after
+                                        diaf_factors_levels (0 before) */
     int32_t count_zero_pivot;        /* zero / non-finite diagonal entries of V (idem) */
     int32_t factor_launches;         /* factor kernel launches (one per size class) */
     int32_t count_deferred;          /* columns the small-column kernel handed to the
@@ -317,6 +319,18 @@ diaf_status diaf_factor(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_spec
                         int32_t mode, struct diaf_factors** out);
 diaf_status diaf_factors_view(const struct diaf_factors* F, diaf_view* out_host);
 diaf_status diaf_factors_stats(const struct diaf_factors* F, diaf_stats* out_host);
+/* Dependency depth of the V solve, a diagnostic of the sync-free
+ * triangular solve (the method only asks that V be easily invertible, as a
+ * triangular matrix is, Section 1): the number of steps of the longest
+ * chain of rows of a triangular V that each wait on the previous one, 1 for
+ * a diagonal or block diagonal V.  Builds the apply
+ * copies when no apply or solve has yet, then walks the rows of V on ctx's
+ * stream and waits for the result.  The value is kept in the statistics
+ * (v_levels, 0 for a triangular V until this call).  Errors: DIAF_EINVAL
+ * (NULL argument), DIAF_EUNSUPPORTED (V neither triangular nor (block)
+ * diagonal), DIAF_EDEVICE. */
+diaf_status diaf_factors_levels(struct diaf_ctx* ctx, const struct diaf_factors* F,
+                                int32_t* levels);
 void diaf_factors_destroy(struct diaf_factors* F);
 
 /* ---- apply and solve (eq. 2.1, Section 5) -------------------------------- */

@@ -70,7 +70,6 @@ struct diaf_factors {
     int32_t *Wrp = nullptr, *Wci = nullptr, *Vrp = nullptr, *Vci = nullptr;
     void *Wcv = nullptr, *Vcv = nullptr, *tmp = nullptr;
     TrsvCtl* ctl = nullptr;
-    uint32_t* ready = nullptr;
     // block diagonal V (vtri == 3): block bounds per column, block starts,
     // offsets of the dense LU factors, the factors and row permutations, and
     // the pattern of D for DIAF_V_BLOCK
@@ -645,7 +644,7 @@ void free_factors(diaf_factors* F)
     for (void* p : {(void*)F->Jcp, (void*)F->Jri, F->Wval, (void*)F->Vcp, (void*)F->Vri, F->Vval,
                     (void*)F->Vrows, F->Vvals, (void*)F->r, (void*)F->bnorm, (void*)F->flags,
                     (void*)F->lcount, (void*)F->Wrp, (void*)F->Wci, (void*)F->Vrp, (void*)F->Vci,
-                    F->Wcv, F->Vcv, F->tmp, (void*)F->ctl, (void*)F->ready, (void*)F->vblk,
+                    F->Wcv, F->Vcv, F->tmp, (void*)F->ctl, (void*)F->vblk,
                     (void*)F->bstart, (void*)F->boff, F->blu, (void*)F->bperm,
                     (void*)F->vpat_cp, (void*)F->vpat_ri})
         dfree(p);
@@ -996,9 +995,7 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
                            (T*)F->Vcv, st));
     DIAF_TRY(dmalloc(&F->tmp, sizeof(T) * n));
     DIAF_TRY(dmalloc(&F->ctl, sizeof(TrsvCtl)));
-    DIAF_TRY(dmalloc(&F->ready, sizeof(uint32_t) * n));
     DIAF_HIP_TRY(hipMemsetAsync(F->ctl, 0, sizeof(TrsvCtl), st));
-    DIAF_HIP_TRY(hipMemsetAsync(F->ready, 0, sizeof(uint32_t) * n, st));
     {
         int32_t* bad = nullptr;
         DIAF_TRY(dmalloc(&bad, sizeof(int32_t)));
@@ -1012,24 +1009,40 @@ Err ensure_apply(diaf_ctx* ctx, diaf_factors* F)
     DIAF_TRY(sync(st));
     F->apply_ready = true;
     if (F->stats.count_zero_pivot) return {};
-    // dependency depth of V
-    if (F->vtri == 1 || F->vtri == -1) {
-        int32_t *lvl = nullptr, *mx = nullptr;
-        DIAF_TRY(dmalloc(&lvl, sizeof(int32_t) * n));
-        DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
-        DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
-        DIAF_TRY(launch_trsv_levels(n, F->Vrp, F->Vci, F->vtri > 0, lvl, F->ready, F->ctl, mx, st));
-        int32_t depth = 0;
-        DIAF_TRY(read1(mx, &depth, st));
-        TrsvCtl c{};
-        DIAF_TRY(read1(F->ctl, &c, st));
-        dfree(lvl);
-        dfree(mx);
-        if (c.error) return {DIAF_EDEVICE, "triangular dependency walk exceeded its wait budget"};
-        F->stats.v_levels = depth;
-    } else {
-        F->stats.v_levels = 1;
+    // the dependency depth of a triangular V is a diagnostic, taken on
+    // request (diaf_factors_levels)
+    F->stats.v_levels = (F->vtri == 1 || F->vtri == -1) ? 0 : 1;
+    return {};
+}
+
+// Depth of the triangular dependency DAG of V (a sync-free level walk on the
+// CSR copy), kept in the statistics.
+template <class T>
+Err compute_levels(diaf_ctx* ctx, diaf_factors* F)
+{
+    DIAF_TRY(ensure_apply<T>(ctx, F));
+    if (!(F->vtri == 1 || F->vtri == -1)) {
+        F->stats.v_levels = 1;  // diagonal or block diagonal: one step
+        return {};
     }
+    if (F->stats.v_levels > 0) return {};
+    hipStream_t st = ctx->stream;
+    const int n = (int)F->n;
+    int32_t *lvl = nullptr, *mx = nullptr;
+    struct FreeL {
+        int32_t** a; int32_t** b;
+        ~FreeL() { dfree(*a); dfree(*b); }
+    } freel{&lvl, &mx};
+    DIAF_TRY(dmalloc(&lvl, sizeof(int32_t) * n));
+    DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
+    DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
+    DIAF_TRY(launch_trsv_levels(n, F->Vrp, F->Vci, F->vtri > 0, lvl, nullptr, F->ctl, mx, st));
+    int32_t depth = 0;
+    DIAF_TRY(read1(mx, &depth, st));
+    TrsvCtl c{};
+    DIAF_TRY(read1(F->ctl, &c, st));
+    if (c.error) return {DIAF_EDEVICE, "triangular dependency walk exceeded its wait budget"};
+    F->stats.v_levels = depth;
     return {};
 }
 
@@ -1249,6 +1262,18 @@ diaf_status diaf_factors_stats(const diaf_factors* F, diaf_stats* s)
 {
     if (!F || !s) return DIAF_EINVAL;
     *s = F->stats;
+    return DIAF_OK;
+}
+
+diaf_status diaf_factors_levels(diaf_ctx* ctx, const diaf_factors* Fc, int32_t* levels)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!Fc || !levels) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    auto* F = const_cast<diaf_factors*>(Fc);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    Err e = F->dtype == DIAF_F64 ? compute_levels<double>(ctx, F) : compute_levels<zc>(ctx, F);
+    if (e.code) return fail(ctx, e);
+    *levels = F->stats.v_levels;
     return DIAF_OK;
 }
 

@@ -96,6 +96,7 @@ _SIGS = {
                             POINTER(c_void_p)]),
     "diaf_factors_view": (c_int, [c_void_p, POINTER(diaf_view)]),
     "diaf_factors_stats": (c_int, [c_void_p, POINTER(diaf_stats)]),
+    "diaf_factors_levels": (c_int, [c_void_p, c_void_p, POINTER(c_int32)]),
     "diaf_factors_destroy": (None, [c_void_p]),
     "diaf_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "diaf_solve": (c_int, [c_void_p, POINTER(diaf_csc), c_void_p, c_void_p, c_void_p, c_double,
@@ -293,6 +294,12 @@ class Factors:
         s = diaf_stats()
         self.ctx.check(self.ctx.lib.diaf_factors_stats(self.h, ctypes.byref(s)))
         return s
+
+    def levels(self) -> int:
+        """Dependency depth of the V solve (diaf_factors_levels)."""
+        out = c_int32(0)
+        self.ctx.check(self.ctx.lib.diaf_factors_levels(self.ctx.h, self.h, ctypes.byref(out)))
+        return int(out.value)
 
     def to_host(self):
         """Copy W, V, residuals, flags and l_j to host numpy arrays."""

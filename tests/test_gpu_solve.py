@@ -57,7 +57,7 @@ def test_bicgstab_iterations_match_oracle(ctx, name):
     x = torch.zeros_like(db)
     info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
     say(f"case {name}: gpu its={info.iters} flag={info.flag} relres={info.relres:.3e} "
-        f"true={info.relres_true:.3e} levels={F.stats().v_levels}")
+        f"true={info.relres_true:.3e} levels={F.levels()}")
     assert info.flag == oinfo.flag == 0
     assert abs(info.iters - oinfo.iters) <= max(1, int(0.05 * oinfo.iters))
     assert info.relres <= 1e-8
@@ -218,4 +218,35 @@ def test_trsv_launch_shapes_agree(ctx, cplx):
             ref = y
         assert np.array_equal(y, ref), waves
     ctx.set_option("trsv_waves", 8)
+    F.close()
+
+
+def _depth(H, lower):
+    """Longest chain of rows of a triangular V (pattern of the GPU's own V,
+    plain dynamic programming in dependency order)."""
+    n = H["n"]
+    import scipy.sparse as sp
+    R = sp.csc_matrix((np.ones(len(H["Vri"])), H["Vri"], H["Vcp"]), shape=(n, n)).tocsr()
+    lev = np.zeros(n, dtype=np.int64)
+    order = range(n) if lower else range(n - 1, -1, -1)
+    for i in order:
+        cols = R.indices[R.indptr[i]:R.indptr[i + 1]]
+        deps = cols[cols < i] if lower else cols[cols > i]
+        lev[i] = 1 + (lev[deps].max() if deps.size else 0)
+    return int(lev.max()) if n else 0
+
+
+@pytest.mark.parametrize("v,l,lower", [("topk_lower", 5, True), ("gs_upper", 0, False),
+                                       ("topk_upper", 4, False), ("diag", 0, None)])
+def test_levels_are_the_longest_dependency_chain(ctx, v, l, lower):
+    from paper_1208_3573_amd import diaf
+    A = synth.convdiff(12, 3, 7)
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=v, v_count=l), "unit_v")
+    assert F.stats().v_levels == 0  # taken on request only
+    got = F.levels()
+    want = 1 if lower is None else _depth(F.to_host(), lower)
+    say(f"V {v}: depth {got}, host walk {want}")
+    assert got == want
+    assert F.stats().v_levels == got and F.levels() == got
     F.close()
