@@ -1833,7 +1833,7 @@ Err autotune_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int m
         return {};
     };
     double warm;
-    DIAF_TRY(time_solve(8, warm));  // first apply builds the CSR copies and levels
+    DIAF_TRY(time_solve(8, warm));  // the first apply builds the CSR copies
     {
         // waves per workgroup of the triangular solve
         double bw = INFINITY;

@@ -205,16 +205,19 @@ Err launch_labels(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, 
 }
 
 // ---------------------------------------------------------------------------
-// MLP forward: one thread per pair, parameters staged in LDS.
+// MLP forward: one thread per pair.  The parameters are read at indices
+// the same for every lane, so they come in through scalar loads and enter
+// the FMAs as scalar operands: no LDS traffic per multiply-add.  The
+// multiply-adds run in the same order as in the gradient kernel.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) mlp_forward_kernel(const float* params, const float* feat,
-                                                        int64_t npairs, float* scores)
+__global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restrict__ params,
+                                                        const float* __restrict__ feat,
+                                                        int64_t npairs, float* __restrict__ scores)
 {
-    __shared__ float P[NPARAM];
-    for (int q = threadIdx.x; q < NPARAM; q += blockDim.x) P[q] = params[q];
-    __syncthreads();
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npairs;
-         p += (int64_t)gridDim.x * blockDim.x) {
+    // one pair per thread and no loop around it, so the weights are not
+    // hoisted into registers for the whole kernel
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < npairs) {
         float x[NF];
         const float4* f4 = (const float4*)(feat + p * NF);
 #pragma unroll
@@ -225,17 +228,17 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float* params, c
         float h1[NH];
 #pragma unroll
         for (int o = 0; o < NH; ++o) {
-            float a = P[P_B1 + o];
+            float a = params[P_B1 + o];
 #pragma unroll
-            for (int q = 0; q < NF; ++q) a = fmaf(P[P_W1 + o * NF + q], x[q], a);
+            for (int q = 0; q < NF; ++q) a = fmaf(params[P_W1 + o * NF + q], x[q], a);
             h1[o] = fmaxf(a, 0.f);
         }
-        float sc = P[P_B3];
+        float sc = params[P_B3];
         for (int o = 0; o < NH; ++o) {
-            float a = P[P_B2 + o];
+            float a = params[P_B2 + o];
 #pragma unroll
-            for (int q = 0; q < NH; ++q) a = fmaf(P[P_W2 + o * NH + q], h1[q], a);
-            sc = fmaf(P[P_W3 + o], fmaxf(a, 0.f), sc);
+            for (int q = 0; q < NH; ++q) a = fmaf(params[P_W2 + o * NH + q], h1[q], a);
+            sc = fmaf(params[P_W3 + o], fmaxf(a, 0.f), sc);
         }
         scores[p] = sc;
     }
@@ -245,8 +248,8 @@ Err launch_mlp_forward(const float* params, const float* feat, int64_t npairs, f
                        hipStream_t st)
 {
     if (npairs <= 0) return {};
-    int64_t blocks = (npairs + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    const int64_t blocks = (npairs + 255) / 256;
+    if (blocks > 0x7fffffffll) return {DIAF_EUNSUPPORTED, "MLP forward: too many pairs"};
     hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)blocks), dim3(256), 0, st, params, feat,
                        npairs, scores);
     DIAF_HIP_TRY(hipGetLastError());
