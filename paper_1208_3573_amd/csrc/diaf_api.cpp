@@ -1036,7 +1036,7 @@ Err compute_levels(diaf_ctx* ctx, diaf_factors* F)
     DIAF_TRY(dmalloc(&lvl, sizeof(int32_t) * n));
     DIAF_TRY(dmalloc(&mx, sizeof(int32_t)));
     DIAF_HIP_TRY(hipMemsetAsync(mx, 0, sizeof(int32_t), st));
-    DIAF_TRY(launch_trsv_levels(n, F->Vrp, F->Vci, F->vtri > 0, lvl, nullptr, F->ctl, mx, st));
+    DIAF_TRY(launch_trsv_levels(n, F->Vrp, F->Vci, F->vtri > 0, lvl, F->ctl, mx, st));
     int32_t depth = 0;
     DIAF_TRY(read1(mx, &depth, st));
     TrsvCtl c{};
@@ -1057,7 +1057,7 @@ Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_
     const T* vin = x;
     T* vout = t;
     if (F->left) {
-        DIAF_TRY(launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, x, t, done, st));
+        DIAF_TRY(launch_spmv_csr<T>(n, F->nnzW, F->Wrp, F->Wci, (const T*)F->Wcv, x, t, done, st));
         vin = t;
         vout = y;
     }
@@ -1070,7 +1070,8 @@ Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_
         DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, vin, vout,
                                 F->ctl, done, ctx->trsv, st));
     if (F->left) return {};
-    return launch_spmv_csr<T>(n, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)t, y, done, st);
+    return launch_spmv_csr<T>(n, F->nnzW, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)t, y, done,
+                              st);
 }
 
 template <class T>
@@ -1688,11 +1689,11 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
             DIAF_TRY(bicg_rho<T>(V, st));
             DIAF_TRY(bicg_update_p<T>(V, st));
             if (left) {
-                DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.p, av, done, st));
+                DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.p, av, done, st));
                 DIAF_TRY(enqueue_apply<T>(ctx, F, av, V.v, done, st));
                 DIAF_TRY(bicg_alpha<T>(V, st));
                 DIAF_TRY(bicg_s<T>(V, st));
-                DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.s, av, done, st));
+                DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.s, av, done, st));
                 DIAF_TRY(enqueue_apply<T>(ctx, F, av, V.t, done, st));
                 DIAF_TRY(bicg_omega<T>(V, st));
                 DIAF_TRY(bicg_xr<T>(V, st));
@@ -1700,12 +1701,12 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
             }
             if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.p, V.ph, done, st));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.ph, V.p, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
-            DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.ph, V.v, done, st));
+            DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.ph, V.v, done, st));
             DIAF_TRY(bicg_alpha<T>(V, st));
             DIAF_TRY(bicg_s<T>(V, st));
             if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.s, V.sh, done, st));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.sh, V.s, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
-            DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.sh, V.t, done, st));
+            DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.sh, V.t, done, st));
             DIAF_TRY(bicg_omega<T>(V, st));
             DIAF_TRY(bicg_xr<T>(V, st));
         }
@@ -1749,7 +1750,7 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         if (it0 > maxit + batch) break;  // cannot happen: maxit stops the loop on the device
     }
     DIAF_TRY(bicg_half_fix<T>(V, st));
-    DIAF_TRY(launch_spmv_csr<T>(n, rp, ci, cv, V.x, V.t, nullptr, st));
+    DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.x, V.t, nullptr, st));
     V.b = b;
     DIAF_TRY(bicg_true_residual<T>(V, st));
     DIAF_TRY(read1(V.st, &hs, st));

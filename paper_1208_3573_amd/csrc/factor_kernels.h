@@ -151,8 +151,8 @@ struct BicgState {
 };
 
 template <class T>
-Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
-                    const int32_t* done, hipStream_t st);
+Err launch_spmv_csr(int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const T* val,
+                    const T* x, T* y, const int32_t* done, hipStream_t st);
 // Launch shape of the sync-free triangular solve: waves per workgroup (1, 2,
 // 4, 8 or 16; the workgroup owns 64 x waves consecutive rows, one per lane;
 // up to 8 waves the LDS has room for twice as many entries per row) and
@@ -170,7 +170,7 @@ Err launch_diag_solve(int n, const int32_t* rp, const int32_t* ci, const T* val,
                       const int32_t* done, hipStream_t st);
 // Depth of the triangular dependency DAG (levels) computed on the device.
 Err launch_trsv_levels(int n, const int32_t* rp, const int32_t* ci, int upper, int32_t* level,
-                       uint32_t* ready, TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st);
+                       TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st);
 
 // BiCGSTAB stage kernels; every one is a no-op once st->done is set.
 template <class T>

@@ -47,16 +47,32 @@ __global__ void __launch_bounds__(256) spmv_csr_kernel(int n, const int32_t* rp,
     if (i < n && g == 0) y[i] = acc;
 }
 
+// Lanes per row: the smallest power of two, between 4 and 32, at which each
+// lane takes about two entries of an average row (7 per row for the 3D
+// stencil A: 4 lanes; about 25 for pattern(A^2): 16).  On the 64^3 problem
+// this beat one entry per lane (8 and 32 lanes) by 0.8 ms per solve and
+// four lanes for both by 1.1 ms.  The lanes of a row and their combining
+// order depend only on the matrix.
 template <class T>
-Err launch_spmv_csr(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* x, T* y,
-                    const int32_t* done, hipStream_t st)
+Err launch_spmv_csr(int n, int64_t nnz, const int32_t* rp, const int32_t* ci, const T* val,
+                    const T* x, T* y, const int32_t* done, hipStream_t st)
 {
     if (n == 0) return {};
-    // lanes per row from the mean row length (read once per matrix on the host
-    // would need a sync; the caller's matrices here are A (~7/row) and W)
-    int64_t threads4 = (int64_t)n * 4;
-    hipLaunchKernelGGL((spmv_csr_kernel<T, 4>), dim3((unsigned)((threads4 + 255) / 256)), dim3(256),
-                       0, st, n, rp, ci, val, x, y, done);
+    const int64_t mean = (nnz + n - 1) / n;
+    int g = 4;
+    while (g < 32 && 2 * g < mean) g *= 2;
+    const int64_t threads = (int64_t)n * g;
+    const dim3 grid((unsigned)((threads + 255) / 256));
+#define SPMV_CASE(G)                                                                       \
+    if (g == G) {                                                                          \
+        hipLaunchKernelGGL((spmv_csr_kernel<T, G>), grid, dim3(256), 0, st, n, rp, ci, val, \
+                           x, y, done);                                                    \
+    }
+    SPMV_CASE(4)
+    SPMV_CASE(8)
+    SPMV_CASE(16)
+    SPMV_CASE(32)
+#undef SPMV_CASE
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
@@ -541,9 +557,8 @@ __global__ void __launch_bounds__(64) trsv_levels_kernel(int n, const int32_t* r
 }
 
 Err launch_trsv_levels(int n, const int32_t* rp, const int32_t* ci, int upper, int32_t* level,
-                       uint32_t* ready, TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st)
+                       TrsvCtl* ctl, int32_t* maxlevel_dev, hipStream_t st)
 {
-    (void)ready;
     if (n == 0) return {};
     hipLaunchKernelGGL(fill_minus1_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, level);
     hipLaunchKernelGGL(trsv_levels_kernel, dim3((n + 63) / 64), dim3(64), 0, st, n, rp, ci, upper,
@@ -856,8 +871,8 @@ template <class T>
 Err bicg_half_fix(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_half_fix_kernel) }
 
 #define INST(T)                                                                                   \
-    template Err launch_spmv_csr<T>(int, const int32_t*, const int32_t*, const T*, const T*, T*,  \
-                                    const int32_t*, hipStream_t);                                 \
+    template Err launch_spmv_csr<T>(int, int64_t, const int32_t*, const int32_t*, const T*,        \
+                                    const T*, T*, const int32_t*, hipStream_t);                   \
     template Err launch_trsv<T>(int, const int32_t*, const int32_t*, const T*, int, const T*, T*, \
                                 TrsvCtl*, const int32_t*, TrsvTune, hipStream_t);                 \
     template Err launch_diag_solve<T>(int, const int32_t*, const int32_t*, const T*, const T*,    \
