@@ -579,22 +579,37 @@ __host__ __device__ inline int red_blocks(int n)
     return b < 1 ? 1 : (b > RBMAX ? RBMAX : b);
 }
 
+// Sum over the block of NV doubles per thread, the same value in every
+// thread: a butterfly of shuffles inside each wave (its lane 0 keeps the
+// result), then the four wave sums in wave order.  Fixed order, one barrier.
+template <int NV>
+__device__ inline void block_sum(const double (&vals)[NV], double (&out)[NV])
+{
+    constexpr int NWV = RNT / 64;
+    __shared__ double wsum[NV][NWV];
+    for (int v = 0; v < NV; ++v) {
+        double a = vals[v];
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+        if ((threadIdx.x & 63) == 0) wsum[v][threadIdx.x >> 6] = a;
+    }
+    __syncthreads();
+    for (int v = 0; v < NV; ++v) {
+        double a = wsum[v][0];
+        for (int w = 1; w < NWV; ++w) a += wsum[v][w];
+        out[v] = a;
+    }
+}
+
 // Block-reduce NV doubles per thread into partial[blockIdx * NV + v]; returns
 // true in the block that finished last (its threads then see all partials).
 template <int NV>
 __device__ inline bool reduce_partials(double (&vals)[NV], double* partial, uint32_t* ticket)
 {
-    __shared__ double red[NV][RNT];
     __shared__ bool last;
-    for (int v = 0; v < NV; ++v) red[v][threadIdx.x] = vals[v];
-    __syncthreads();
-    for (int o = RNT / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
-            for (int v = 0; v < NV; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + o];
-        __syncthreads();
-    }
+    double tot[NV];
+    block_sum<NV>(vals, tot);
     if (threadIdx.x == 0) {
-        for (int v = 0; v < NV; ++v) partial[blockIdx.x * NV + v] = red[v][0];
+        for (int v = 0; v < NV; ++v) partial[blockIdx.x * NV + v] = tot[v];
         __threadfence();
         uint32_t t = atomicAdd(ticket, 1u);
         last = (t == gridDim.x - 1);
@@ -605,24 +620,17 @@ __device__ inline bool reduce_partials(double (&vals)[NV], double* partial, uint
 }
 
 // Sum of the per-block partials by the whole (last) block: a strided load
-// per thread and a tree in LDS, both in a fixed order.
+// per thread, then block_sum, both in a fixed order.
 template <int NV>
 __device__ inline void sum_partials(const double* partial, int nb, double (&out)[NV])
 {
-    __shared__ double red2[NV][RNT];
+    double a[NV];
     for (int v = 0; v < NV; ++v) {
-        double a = 0.0;
+        a[v] = 0.0;
         for (int b = threadIdx.x; b < nb; b += RNT)
-            a += __hip_atomic_load(&partial[b * NV + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        red2[v][threadIdx.x] = a;
+            a[v] += __hip_atomic_load(&partial[b * NV + v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    for (int o = RNT / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
-            for (int v = 0; v < NV; ++v) red2[v][threadIdx.x] += red2[v][threadIdx.x + o];
-        __syncthreads();
-    }
-    for (int v = 0; v < NV; ++v) out[v] = red2[v][0];
+    block_sum<NV>(a, out);
 }
 
 template <class T>
