@@ -41,6 +41,8 @@ SMALL_DIAG = 4
 TIE_EDGE = 16
 STABILIZED = 32
 NO_DIAG_ROW = 64
+NULL_CHOICE = 128
+RANK_EDGE = 256
 
 
 def build(force: bool = True) -> str:

@@ -101,6 +101,8 @@ int orc_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int32_t* Jcp, 
 #define SFX(name) name##_d
 #define CONJ(x) (x)
 #define RE(x) (x)
+#define IMP(x) (0.0)
+#define MK2(re, im) (re)
 #define ABS2(x) ((x) * (x))
 #define ABS(x) fabs(x)
 #define ABSR(x) fabs(x)
@@ -109,6 +111,8 @@ int orc_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int32_t* Jcp, 
 #undef SFX
 #undef CONJ
 #undef RE
+#undef IMP
+#undef MK2
 #undef ABS2
 #undef ABS
 #undef ABSR
@@ -118,6 +122,8 @@ int orc_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int32_t* Jcp, 
 #define SFX(name) name##_z
 #define CONJ(x) conj(x)
 #define RE(x) creal(x)
+#define IMP(x) cimag(x)
+#define MK2(re, im) CMPLX(re, im)
 #define ABS2(x) (creal(x) * creal(x) + cimag(x) * cimag(x))
 #define ABS(x) sqrt(creal(x) * creal(x) + cimag(x) * cimag(x))
 #define ABSR(x) cabs(x)
@@ -126,6 +132,8 @@ int orc_pattern_a2(int n, const int32_t* Acp, const int32_t* Ari, int32_t* Jcp, 
 #undef SFX
 #undef CONJ
 #undef RE
+#undef IMP
+#undef MK2
 #undef ABS2
 #undef ABS
 #undef ABSR

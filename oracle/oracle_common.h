@@ -25,6 +25,8 @@
 #define ORC_TIE_EDGE 16u       /* a top-k score lies at the edge of the tie band */
 #define ORC_STABILIZED 32u     /* v_j replaced by the constrained solution of Section 3.2 */
 #define ORC_NO_DIAG_ROW 64u    /* row j does not occur in the shadow R_j */
+#define ORC_NULL_CHOICE 128u   /* unit-norm w chosen in a null space of dimension >= 2 */
+#define ORC_RANK_EDGE 256u     /* a rank test quantity within a factor 100 of its threshold */
 
 /* V pattern rules. */
 enum { ORC_V_EXPLICIT = 0, ORC_V_DIAG = 1, ORC_V_GS_UPPER = 2, ORC_V_GS_LOWER = 3,

@@ -61,6 +61,19 @@ def test_features_on_a_hand_checked_matrix():
     assert np.allclose(f[:, 9], [0, 1, 1])
     assert np.allclose(f[:, 12], [16 / 18, 10 / 18, 1.0])
     assert np.allclose(f[:, 15], [0, 0, 1.0])          # two candidates beat pw2
+    # degrees 2, 3, 2; diagonals 4, 5, 3; off-diagonal column sums 2, 2, 1;
+    # column norms sqrt(20), sqrt(27), sqrt(10)
+    assert np.allclose(f[:, 5], [2 / 8] * 3)           # deg_j / 8
+    assert np.allclose(f[:, 6], [2 / 8, 3 / 8, 2 / 8])  # deg_i / 8
+    assert np.allclose(f[:, 7], [4 / 6] * 3)           # d_j / (d_j + s_j)
+    assert np.allclose(f[:, 8], [4 / 6, 5 / 7, 3 / 4])  # d_i / (d_i + s_i)
+    assert np.allclose(f[:, 10], [0, 1 / 24, np.log2(3) / 24])
+    assert np.allclose(f[:, 11], [1, np.sqrt(27 / 20), np.sqrt(10 / 20)])
+    assert np.allclose(f[:, 13], [18 / 16, 18 / 20, 2 / 12])  # pw / (d_i d_j)
+    assert np.allclose(f[:, 14], [3 / 32] * 3)
+    f2 = F[C.indptr[2]:C.indptr[3]]
+    assert np.allclose(f2[:, 5], 2 / 8) and np.allclose(f2[:, 7], 3 / 4)
+    assert np.allclose(f2[:, 10], [np.log2(3) / 24, 1 / 24, 0])
 
 
 def test_labels_keep_diagonal_and_large_entries():
