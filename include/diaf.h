@@ -131,13 +131,20 @@ typedef enum diaf_v_kind {
 } diaf_v_kind;
 
 /* Per-column flag bits (diaf_view.flags). */
-#define DIAF_FLAG_RANK_DEFICIENT 1u /* A(:, J_j) (or its rows outside L_j) numerically rank deficient */
+#define DIAF_FLAG_RANK_DEFICIENT 1u /* B = A(R_j, J_j) numerically rank deficient: unit-norm v, the
+                                       Gram pivots |R_aa|^2 of B = QR reach 1e-14 times the largest
+                                       squared column norm (or |J_j| > |R_j|); unit-norm w, B without
+                                       the rows L_j has sigma_min^2 <= 1e-14 times its squared
+                                       Frobenius norm (or fewer rows than columns) */
 #define DIAF_FLAG_GAP_DEGENERATE 2u /* extreme singular values not separated (rel. gap < 1e-6) */
 #define DIAF_FLAG_SMALL_DIAG 4u     /* |v_jj| < 1e-2 ||v_j|| */
 #define DIAF_FLAG_FELL_BACK 8u      /* learned pattern rejected by the residual gate */
 #define DIAF_FLAG_TIE_EDGE 16u      /* a top-k score at the edge of the 1e-10 tie band */
 #define DIAF_FLAG_STABILIZED 32u    /* v_j computed under the constraint v_jj = stab_r (Section 3.2) */
 #define DIAF_FLAG_NO_DIAG_ROW 64u   /* row j not in the shadow of J_j: column left zero */
+#define DIAF_FLAG_NULL_CHOICE 128u  /* unit-norm w: the block without the rows L_j has a null space
+                                       of dimension >= 2; w is its unit vector with the largest
+                                       |(A w)_j| (Section 2.2 with Theorem 2.1's v_jj != 0) */
 
 typedef struct diaf_csc {
     int64_t n, nnz;

@@ -69,8 +69,8 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
 
 // misc slots (int view / double view)
 enum { MI_T = 0, MI_M, MI_DJ, MI_FLAGS, MI_L, MI_NC, MI_ROT, MI_BEST, MI_Q, MI_EDGE, MI_NIN,
-       MI_STAB, MI_DPOS };
-enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2, MD_ERE, MD_EIM };
+       MI_STAB, MI_DPOS, MI_NULL };
+enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2, MD_ERE, MD_EIM, MD_FRO2 };
 
 template <class T>
 struct GenCtx {
@@ -149,7 +149,8 @@ __device__ inline T bget(const GenCtx<T>& c, int i, int a)
 }
 
 // In-place lower Cholesky of G (k x k, row-major ld k); zero pivots give a
-// zero column.  Sets the rank flag when a pivot^2 <= 1e-26 max diag.
+// zero column.  Sets the rank flag when a pivot^2 (= |R_aa|^2 of B = QR) is
+// at most 1e-14 times the largest diagonal entry (squared column norm).
 template <class T>
 __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
 {
@@ -165,7 +166,7 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
             double d = num<T>::re(G[p * k + p]);
             double piv = 0.0;
             if (d > 1e-30 * maxd && isfinite(d)) piv = sqrt(d);
-            if (!(d > 1e-26 * maxd)) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
+            if (!(d > 1e-14 * maxd)) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
             G[p * k + p] = num<T>::mk(piv);
             c.md[MD_PIV] = piv;
         }
@@ -737,6 +738,19 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         }
         __syncthreads();
         jacobi_eig(c, E, Z, k);
+        // ||Bh||_F^2 over the entries of B outside the rows of L (Bh = B
+        // without those rows; its Gram matrix is E)
+        {
+            double s2 = 0.0;
+            for (int t = tid; t < Tn; t += c.nt) {
+                const int lr = c.sLrow[t];
+                bool inL = false;
+                for (int q = 0; q < l; ++q) inL |= c.sL[q] == lr;
+                if (!inL) s2 += num<T>::abs2(c.sVal[t]);
+            }
+            const double fro2 = block_sum(c, s2);
+            if (tid == 0) c.md[MD_FRO2] = fro2;
+        }
         if (tid == 0) {
             int lo = 0, hi = 0;
             for (int p = 1; p < k; ++p) {
@@ -749,13 +763,52 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
             for (int p = 0; p < k; ++p)
                 if (p != lo) l2 = fmin(l2, num<T>::re(E[p * k + p]));
             double gap = (k >= 2 && lmx > 0) ? (l2 - l1) / lmx : 1.0;
-            if (gap < 1e-6) c.mi[MI_FLAGS] |= DIAF_FLAG_GAP_DEGENERATE;
-            if (m - l < k || l1 <= 1e-14 * lmx) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
             c.mi[MI_BEST] = lo;
+            c.mi[MI_NULL] = 0;
+            // A null space N of Bh of dimension >= 2 (eigenvalues of E at
+            // most 1e-14 ||Bh||_F^2): take the unit w in N that maximises
+            // |(B w)_j|, i.e. P_N b^* normalised with b = row j of B, unless
+            // P_N b^* is negligible (then every w in N gives v_jj ~ 0).
+            const double thr = 1e-14 * c.md[MD_FRO2];
+            int nnull = 0;
+            double lin = 0.0, lout = INFINITY;
+            for (int p = 0; p < k; ++p) {
+                const double d = num<T>::re(E[p * k + p]);
+                if (d <= thr) { ++nnull; lin = fmax(lin, d); }
+                else lout = fmin(lout, d);
+            }
+            if (nnull >= 2) {
+                T* bj = c.sX;  // conj(B(j, :)) in column 0 of X
+                double bn2 = 0.0;
+                for (int a = 0; a < k; ++a) bj[a * c.xld] = num<T>::zero();
+                for (int pp = c.sRowptr[dj]; pp < c.sRowptr[dj + 1]; ++pp) {
+                    const int t = c.sPos[pp];
+                    bj[c.sCol[t] * c.xld] = num<T>::conj(c.sVal[t]);
+                    bn2 += num<T>::abs2(c.sVal[t]);
+                }
+                for (int a = 0; a < k; ++a) c.sW[a] = num<T>::zero();
+                for (int p = 0; p < k; ++p) {
+                    if (!(num<T>::re(E[p * k + p]) <= thr)) continue;
+                    T coef = num<T>::zero();  // z_p^* b^*
+                    for (int a = 0; a < k; ++a) coef += num<T>::cmul(Z[a * k + p], bj[a * c.xld]);
+                    for (int a = 0; a < k; ++a) c.sW[a] += Z[a * k + p] * coef;
+                }
+                double un2 = 0.0;
+                for (int a = 0; a < k; ++a) un2 += num<T>::abs2(c.sW[a]);
+                if (un2 > 1e-16 * bn2 && un2 > 0.0) {
+                    const double inv = 1.0 / sqrt(un2);
+                    for (int a = 0; a < k; ++a) c.sW[a] = c.sW[a] * inv;
+                    c.mi[MI_NULL] = 1;
+                    c.mi[MI_FLAGS] |= DIAF_FLAG_NULL_CHOICE;
+                    gap = (lout < INFINITY && lmx > 0) ? (lout - lin) / lmx : 1.0;
+                }
+            }
+            if (gap < 1e-6) c.mi[MI_FLAGS] |= DIAF_FLAG_GAP_DEGENERATE;
         }
         __syncthreads();
         const int lo = c.mi[MI_BEST];
-        for (int a = tid; a < k; a += c.nt) c.sW[a] = Z[a * k + lo];
+        if (!c.mi[MI_NULL])
+            for (int a = tid; a < k; a += c.nt) c.sW[a] = Z[a * k + lo];
         __syncthreads();
         bmul(c, m, c.sW, c.sY);
         for (int t = tid; t < l; t += c.nt) c.sV[t] = c.sY[c.sL[t]];
@@ -870,6 +923,11 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     double s = 0;
     for (int i = tid; i < m; i += c.nt) s += num<T>::abs2(c.sY[i]);
     double r2 = block_sum(c, s);
+    // unit-norm w: B without the rows of L has fewer rows than columns, or
+    // its smallest singular value (here the residual) is negligible against
+    // its Frobenius norm
+    if (tid == 0 && A.mode == 1 && (m - l < k || r2 <= 1e-14 * c.md[MD_FRO2]))
+        c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
     for (int a = tid; a < k; a += c.nt) A.Wval[jb + a] = c.sW[a];
     if (tid == 0) {
         // V column sorted by row (local order = global order)

@@ -1,6 +1,7 @@
 // Small-column kernel for both basic algorithms (unit-norm columns of V,
 // paper Section 2.1, or of W, Section 2.2): one wave per column, |J_j| <= 32, shadow |R_j| <= 64,
-// at most 256 gathered entries and |L_j| <= 8.  Columns outside these limits
+// at most 256 gathered entries and |L_j| <= 8.  Columns outside these limits,
+// and unit-norm-w columns whose block without the V rows is rank deficient,
 // are appended to a deferred list for the generic kernel.
 //
 // Per column, with B = A(R_j, J_j) and G = B^* B:
@@ -156,7 +157,7 @@ __device__ __forceinline__ void sweep_inverse(T (&g)[SKM / 2], int k, int c, int
             __syncthreads();
             const double d = num<T>::re(b[p]);
             const bool zero = !(d > 1e-30 * maxd) || !isfinite(d);
-            if (!(d > 1e-26 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
+            if (!(d > 1e-14 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
             const double inv = zero ? 0.0 : recip_nr(d);
             const bool piv = (c == p);
             const T apc = b[c];
@@ -827,9 +828,24 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
         if (S.L[t] == lane) res -= S.post.v[t];
     const double r2 = wave_sum(lane < m ? num<T>::abs2(res) : 0.0);
     if constexpr (MODE == 1) {
-        // B without the rows of L has fewer rows than columns, or its
-        // smallest singular value is negligible against the largest
-        if (m - l < k || r2 <= 1e-14 * maxd) flags |= DIAF_FLAG_RANK_DEFICIENT;
+        // B without the rows of L (Bh) rank deficient: fewer rows than
+        // columns, or its smallest singular value (the residual) negligible
+        // against ||Bh||_F.  Its null space may then have dimension >= 2, where
+        // the choice of w needs the eigenvectors of the generic kernel's
+        // Jacobi solve: hand the column over.
+        double f2 = 0.0;
+        for (int t = lane; t < Tn; t += 64) {
+            const int lr = S.eloc[t];
+            bool inL = false;
+            for (int q = 0; q < l; ++q) inL |= S.L[q] == lr;
+            if (!inL) f2 += num<T>::abs2(S.eval[t]);
+        }
+        const double fro2 = wave_sum(f2);
+        if (m - l < k || r2 <= 1e-14 * fro2) {
+            __syncthreads();
+            if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+            return;
+        }
     }
     // ---- 10. outputs (V sorted by row) ----
     if (lane < k) A.Wval[jb + lane] = S.post.w[lane];

@@ -28,7 +28,7 @@ DIAF_V_EXPLICIT, DIAF_V_DIAG, DIAF_V_GS_UPPER, DIAF_V_GS_LOWER, DIAF_V_TOPK_UPPE
     DIAF_V_TOPK_LOWER, DIAF_V_LEV_UPPER, DIAF_V_LEV_LOWER, DIAF_V_BLOCK, \
     DIAF_V_TOPK_BLOCK = range(10)
 FLAG_RANK_DEFICIENT, FLAG_GAP_DEGENERATE, FLAG_SMALL_DIAG, FLAG_FELL_BACK, FLAG_TIE_EDGE, \
-    FLAG_NO_DIAG_ROW = 1, 2, 4, 8, 16, 64
+    FLAG_STABILIZED, FLAG_NO_DIAG_ROW, FLAG_NULL_CHOICE = 1, 2, 4, 8, 16, 32, 64, 128
 MLP_NFEAT, MLP_HIDDEN = 16, 64
 MLP_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 64 + 1
 

@@ -60,7 +60,11 @@ def test_factor_parity_small(ctx, name):
             small, deferred, generic = _launch_classes(A, J)
             say(f"classes: one-wave {small} deferred {deferred} generic {generic}")
             assert small > 0 and deferred > 0 and generic > 0
-            assert st.count_deferred == deferred
+            # unit-norm w also hands over rank-deficient columns
+            if mode == "unit_v":
+                assert st.count_deferred == deferred
+            else:
+                assert st.count_deferred >= deferred
             assert st.factor_launches >= 3
         F.close()
 
@@ -83,35 +87,70 @@ def _launch_classes(A, J):
     return small, deferred, generic
 
 
-def _sample(n, k, seed):
+def _stratified(A, J, per_class, seed):
+    """Columns of every launch size class of the factor kernels (capacities
+    in |J_j| and gathered entries: 16/128, 32/256, 64/512, 64/1024,
+    128/2048, 256/4096, 256/8192): all columns of a class with at most
+    per_class of them, else per_class drawn uniformly, plus the first, last
+    and middle columns."""
     rng = np.random.default_rng(seed)
-    s = set(rng.choice(n, size=min(k, n), replace=False).tolist())
-    s |= {0, 1, n - 2, n - 1, n // 2}
-    return np.array(sorted(s))
+    k = np.diff(J.colptr)
+    t = np.add.reduceat(np.diff(A.colptr)[J.rowidx], J.colptr[:-1])
+    caps = [(16, 128), (32, 256), (64, 512), (64, 1024), (128, 2048), (256, 4096), (256, 8192)]
+    cls = np.full(A.n, len(caps))
+    for c in range(len(caps) - 1, -1, -1):
+        cls[(k <= caps[c][0]) & (t <= caps[c][1])] = c
+    out = {0, 1, A.n // 2, A.n - 2, A.n - 1}
+    counts = {}
+    for c in range(len(caps)):
+        idx = np.flatnonzero(cls == c)
+        counts[c] = int(idx.size)
+        if idx.size > per_class:
+            idx = rng.choice(idx, per_class, replace=False)
+        out |= set(idx.tolist())
+    return np.array(sorted(out)), counts
 
 
 FULL = {
-    "convdiff3d_64": ("unit_v", "unit_w"),
-    "helmholtz2d_512": ("unit_w",),
-    "random_1m": ("unit_v", "unit_w"),
+    # name: (modes, column selection: None = every column)
+    "convdiff3d_64": (("unit_v", "unit_w"), None),
+    "helmholtz2d_512": (("unit_w",), None),
+    "random_1m": (("unit_v", "unit_w"), 6000),
 }
 
 
 @pytest.mark.parametrize("name", list(FULL))
-def test_factor_parity_full_size_sampled(ctx, name):
-    """The full workloads in the benchmark's launch configuration; the oracle
-    recomputes a sample of columns one by one."""
+def test_factor_parity_full_size(ctx, name):
+    """The full workloads in the benchmark's launch configuration: every
+    column of the 64^3 and Helmholtz workloads, and at least 20 000 columns
+    of the 10^6 one spread over every size class, against the oracle."""
     cfg = synth.WORKLOADS[name]
     A = synth.workload_matrix(name)
     J = oracle_pattern(A, cfg["w"], cfg.get("w_topk", 0))
-    cols = _sample(A.n, 1500, 1)
+    modes, per_class = FULL[name]
+    cols = None
+    if per_class:
+        cols, counts = _stratified(A, J, per_class, 1)
+        say(f"{name}: {cols.size} sampled columns, class sizes {counts}")
+        assert cols.size >= 20000
     dA = None
-    for mode in FULL[name]:
+    for mode in modes:
         say(f"case {name} mode {mode} n={A.n}")
         F, H, dA = run_gpu(ctx, A, cfg["w"], cfg["v"], cfg["v_count"], mode,
                            wtopk=cfg.get("w_topk", 0), dA=dA)
         O = oracle.factor(A, J, mode, cfg["v"], cfg["v_count"], cols=cols)
-        compare(H, J, O, A, mode, cols=cols)
+        summ = compare(H, J, O, A, mode, cols=cols)
+        # the oracle excludes few columns from the angle check, and the
+        # near-exact residual allowance stays rare
+        assert summ["excluded"] <= 0.01 * summ["cols"], summ
+        assert summ["gap_floor"] <= 1e-3 * summ["cols"], summ
+        assert summ["degenerate_res"] <= summ["excluded"], summ
+        if name == "helmholtz2d_512":
+            # the boundary columns whose block without the V rows has a
+            # two-dimensional null space (508 at 512^2) take the null-space
+            # choice on both sides
+            assert summ["null_choice"] == 508, summ
+            assert int(np.sum((H["flags"] & oracle.NULL_CHOICE) != 0)) == 508
         F.close()
 
 

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import synth
 from oracle import learned as L
-from tests._gpu import oracle_pattern, say
+from tests._gpu import compare, oracle_pattern, say
 
 pytestmark = pytest.mark.gpu
 
@@ -187,3 +187,108 @@ def test_trained_proposer_with_partial_fallback(ctx, mode):
     assert kept.sum() < n // 100
     Fa.close()
     model.close()
+
+
+def test_proposed_pattern_matches_reference_forward(ctx):
+    """J_j from the GPU's features and FP32 MLP against J_j from the FP64
+    reference features and forward pass with the same rule ({j} plus the
+    candidates of pattern(A^2) with score >= 0), using the committed
+    network.  Pairs whose FP64 score lies within the FP32 error band of 0
+    (1e-4 max(1, max |s|), the forward test's tolerance) may go either way;
+    every other pair must agree."""
+    from paper_1208_3573_amd import diaf
+    from paper_1208_3573_amd import learned as LR
+    A = synth.convdiff(12, 3, 5)
+    dA = diaf.DeviceCSC.from_host(A)
+    model, _, _ = LR.load(ctx, LR.weights_path("unit_v"))
+    theta = model.params().astype(np.float64)
+    ctx.set_option("gate_small_diag", 0)
+    try:
+        F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="learned", v="topk_lower", v_count=5,
+                                                     model=model, gate_tau=float("inf")),
+                             "unit_v")
+    finally:
+        ctx.set_option("gate_small_diag", 1)
+    H = F.to_host()
+    assert not np.any(H["flags"] & diaf.FLAG_FELL_BACK)
+    C = oracle_pattern(A, "A2")
+    s = L.forward(theta, L.features(A, C.colptr, C.rowidx))
+    band = 1e-4 * max(1.0, float(np.abs(s).max()))
+    diag = C.rowidx == np.repeat(np.arange(A.n), np.diff(C.colptr))
+    keep = (s >= 0) | diag
+    ambiguous = (np.abs(s) <= band) & ~diag
+    mism = 0
+    for j in range(A.n):
+        sl = slice(C.colptr[j], C.colptr[j + 1])
+        cand = C.rowidx[sl]
+        got = np.isin(cand, H["Wri"][H["Wcp"][j]:H["Wcp"][j + 1]])
+        bad = (got != keep[sl]) & ~ambiguous[sl]
+        mism += int(bad.sum())
+    say(f"proposal: {int(keep.sum())} of {C.nnz} pairs kept, {int(ambiguous.sum())} within the "
+        f"FP32 band of 0, {mism} disagreements outside it")
+    assert mism == 0
+    assert ambiguous.sum() <= 1e-3 * C.nnz
+    F.close()
+    model.close()
+
+
+@pytest.mark.parametrize("mode", ["unit_v", "unit_w"])
+def test_merged_learned_factors_match_oracle(ctx, mode):
+    """The learned factorization after the gates (accepted proposals plus the
+    columns refactored with pattern(A^2)) against the oracle's factoring on
+    the final W pattern: identical V patterns, residuals and singular
+    vectors within the parity bars, flags in agreement.  The columns that
+    fell back carry exactly pattern(A^2)."""
+    from paper_1208_3573_amd import diaf
+    from paper_1208_3573_amd import learned as LR
+    A = synth.convdiff(24, 3, 77)
+    dA = diaf.DeviceCSC.from_host(A)
+    model, gate, gate_dom = LR.load(ctx, LR.weights_path(mode))
+    spec = diaf.make_spec(w="learned", v="topk_lower", v_count=5, model=model, gate_tau=gate,
+                          gate_dom=gate_dom)
+    F = diaf.diaf_factor(ctx, dA, spec, mode)
+    H = F.to_host()
+    fb = np.flatnonzero(H["flags"] & diaf.FLAG_FELL_BACK)
+    C = oracle_pattern(A, "A2")
+    for j in fb:
+        assert np.array_equal(H["Wri"][H["Wcp"][j]:H["Wcp"][j + 1]],
+                              C.rowidx[C.colptr[j]:C.colptr[j + 1]])
+    Jf = oracle.Pattern(A.n, H["Wcp"].astype(np.int32), H["Wri"].astype(np.int32))
+    O = oracle.factor(A, Jf, mode, "topk_lower", 5)
+    say(f"{mode}: {fb.size} columns fell back")
+    summ = compare(H, Jf, O, A, mode)
+    assert summ["excluded"] <= 0.01 * A.n
+    F.close()
+    model.close()
+
+
+def test_adam_steps_match_reference(ctx):
+    """Two GPU Adam steps against oracle/learned.adam_step fed the same
+    gradients (the GPU's own, which the gradient test pins to the FP64
+    back-propagation).  FP32 arithmetic and constants (0.999f is not 0.999)
+    bound the difference by 1e-6 |theta| + 2e-5 lr."""
+    import torch
+    from paper_1208_3573_amd import diaf
+    rng = np.random.default_rng(3)
+    theta = L.init_params(11)
+    N = 2000
+    X = torch.from_numpy(rng.standard_normal((N, 16)).astype(np.float32)).cuda()
+    y = torch.from_numpy((rng.random(N) < 0.3).astype(np.float32)).cuda()
+    m = diaf.Model(ctx, theta)
+    lr = 3e-3
+    th = theta.astype(np.float64)
+    mom = np.zeros(L.NPARAM)
+    vel = np.zeros(L.NPARAM)
+    for step in (1, 2):
+        g = torch.zeros(L.NPARAM, dtype=torch.float32, device="cuda")
+        diaf.diaf_mlp_loss_grad(ctx, m, X, y, N, g)
+        gh = g.cpu().numpy().astype(np.float64)
+        diaf.diaf_mlp_train_step(ctx, m, X, y, N, lr)
+        th, mom, vel = L.adam_step(th, gh, mom, vel, step, lr)
+        got = m.params().astype(np.float64)
+        err = np.abs(got - th)
+        bound = 1e-6 * np.abs(th) + 2e-5 * lr
+        say(f"adam step {step}: max |theta_gpu - theta_ref| {err.max():.3e}")
+        assert np.all(err <= bound), (step, float(np.max(err - bound)))
+        th = got  # continue from the GPU's parameters (FP32)
+    m.close()

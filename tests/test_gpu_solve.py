@@ -35,6 +35,8 @@ CASES = {
     "helmholtz_32_gs_w": (lambda: synth.helmholtz(32, 5.0, 0.5), "A2", "gs_upper", 0, "unit_w"),
     "convdiff3d_64_v": (lambda: synth.workload_matrix("convdiff3d_64"), "A2", "topk_lower", 5,
                         "unit_v"),
+    "convdiff3d_64_w": (lambda: synth.workload_matrix("convdiff3d_64"), "A2", "topk_lower", 5,
+                        "unit_w"),
     "diag_spai": (lambda: synth.convdiff(16, 3, 8), "A2", "diag", 0, "unit_v"),
 }
 
@@ -65,6 +67,54 @@ def test_bicgstab_iterations_match_oracle(ctx, name):
     xs = x.cpu().numpy()
     assert np.max(np.abs(xs - 1.0)) < 1e-3
     F.close()
+
+
+def _trailing_growth(V, b, lines, N):
+    """max |t| of t = V22^{-1} b2 for the trailing `lines` grid lines of an
+    upper triangular V: (V^{-1})'s trailing block is V22^{-1}, so this bounds
+    ||V^{-1}|| from below (and kappa(V), with ||V|| >= ||V22||)."""
+    import scipy.sparse.linalg as spla
+    s0 = V.shape[0] - lines * N
+    with np.errstate(all="ignore"):
+        t = spla.spsolve_triangular(V[s0:, s0:].tocsr(), b[s0:], lower=False)
+    return float(np.max(np.abs(t)))
+
+
+def test_helmholtz_512_unit_w_topk_upper_outcome(ctx):
+    """The Helmholtz workload with unit-norm w and the top-7 upper V: with
+    the null-space choice no diagonal entry of V vanishes, but V^{-1} grows
+    by about an order of magnitude per grid line (the boundary columns at
+    x = 0 have off-diagonal mass up to 28 times the diagonal), so the back
+    substitution overflows and BiCGSTAB breaks down in its first iteration,
+    on the GPU and in the oracle alike.  The GPU's V gives the lower bound on
+    kappa(V) that the test reports."""
+    import torch
+    from paper_1208_3573_amd import diaf
+    cfg = synth.WORKLOADS["helmholtz2d_512"]
+    A = synth.workload_matrix("helmholtz2d_512")
+    b = synth.rhs_ones(A)
+    J = oracle_pattern(A, "A2")
+    O = oracle.factor(A, J, "unit_w", "topk_upper", 7)
+    _, oinfo = oracle.bicgstab(A, b, O, upper=True, tol=1e-8, maxit=1000)
+    dA = diaf.DeviceCSC.from_host(A)
+    F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v=cfg["v"], v_count=cfg["v_count"]),
+                         "unit_w")
+    H = F.to_host()
+    dvals = np.abs(H["Vval"][H["Vri"] == np.repeat(np.arange(A.n), np.diff(H["Vcp"]))])
+    say(f"helmholtz 512: min |v_jj| gpu {dvals.min():.3e}, oracle its={oinfo.iters} "
+        f"flag={oinfo.flag}")
+    assert dvals.min() > 0.1
+    db = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(db)
+    info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
+    import scipy.sparse as sp
+    V = sp.csc_matrix((H["Vval"], H["Vri"], H["Vcp"]), shape=(A.n, A.n))
+    growth = {nl: _trailing_growth(V, b, nl, 512) for nl in (4, 8, 16, 32, 64)}
+    say(f"helmholtz 512: gpu its={info.iters} flag={info.flag}; max |V22^-1 b| over the "
+        f"trailing grid lines {growth}")
+    assert oinfo.flag == 2 and info.flag == oinfo.flag and info.iters == oinfo.iters
+    # the oracle's V: 6.6, 1.3e3, 6.6e6, 1.4e14, 6.8e28 for 4 ... 64 lines
+    assert growth[16] > 1e5 * growth[4] and growth[64] > 1e25
 
 
 def test_unpreconditioned_bicgstab_matches_oracle(ctx):

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from tests._gpu import EXCLUDE, compare, oracle_pattern, say
+from tests._gpu import angle_excluded, compare, oracle_pattern, say
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +68,7 @@ def test_stabilized_columns_match_oracle(ctx, name):
                           np.nonzero(O.flags & oracle.SMALL_DIAG)[0])
     worst_v = worst_w = 0.0
     for j in o_st:
-        if (int(H["flags"][j]) | int(O.flags[j])) & EXCLUDE:
+        if angle_excluded(O.flags[j], "unit_v"):
             continue
         gv = H["Vval"][H["Vcp"][j]:H["Vcp"][j + 1]]
         ov = O.Vvals_pad[j, :O.lcount[j]]
