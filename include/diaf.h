@@ -348,6 +348,22 @@ void diaf_factors_destroy(struct diaf_factors* F);
 diaf_status diaf_apply(struct diaf_ctx* ctx, const struct diaf_factors* F, const void* x,
                        void* y);
 
+/* diaf_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bit for bit, with the intermediate
+ * vector and the triangular solve's control words in a fixed scratch array
+ * of 16 MiB that each device holds from diaf_ctx_create until the process
+ * ends; it calls no hipMalloc or hipFree.  x, y: n entries each, caller
+ * owned.  Limits and errors: n * (8 or 16 bytes) must fit in 16 MiB - 256 B
+ * (n <= 2 097 120 real, 1 048 560 complex), else DIAF_EINVAL; the factors
+ * must have been prepared by one diaf_apply or diaf_solve (which build
+ * their row-oriented copies), else DIAF_EINVAL; DIAF_ESINGULAR as for
+ * diaf_apply.  All calls on one device share its scratch array: calls that
+ * overlap in time on one device (other streams, other threads) race, and
+ * must be ordered by the caller. */
+diaf_status diaf_apply_noalloc(struct diaf_ctx* ctx, const struct diaf_factors* F,
+                               const void* x, void* y);
+
 /* Right-preconditioned BiCGSTAB on A M u = b, x = M u, M = W V^{-1}
  * (F == NULL: M = I), x0 = 0, stop when ||r|| <= rtol ||b||; for factors of
  * the left variant, BiCGSTAB on M A x = M b, M = V^{-1} W, stop when the

@@ -31,6 +31,7 @@ SOURCES = [
     "sparse.hip",
     "solve.hip",
     "learned.hip",
+    "noalloc.hip",
 ]
 
 

@@ -15,6 +15,7 @@
 
 #include "dcommon.h"
 #include "factor_kernels.h"
+#include "noalloc.h"
 
 using namespace diaf;
 
@@ -1047,13 +1048,13 @@ Err compute_levels(diaf_ctx* ctx, diaf_factors* F)
 }
 
 // Right: t = V^{-1} x ; y = W t.  Left: t = W x ; y = V^{-1} t.  All on
-// stream st, no host sync.
+// stream st, no host sync.  t (n entries) and ctl (the triangular solve's
+// control words) are the factors' own buffers, or the caller's.
 template <class T>
-Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done,
-                  hipStream_t st)
+Err enqueue_apply_with(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done,
+                       hipStream_t st, T* t, TrsvCtl* ctl)
 {
     const int n = (int)F->n;
-    T* t = (T*)F->tmp;
     const T* vin = x;
     T* vout = t;
     if (F->left) {
@@ -1068,10 +1069,45 @@ Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_
                                        vout, done, st));
     else
         DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, vin, vout,
-                                F->ctl, done, ctx->trsv, st));
+                                ctl, done, ctx->trsv, st));
     if (F->left) return {};
     return launch_spmv_csr<T>(n, F->nnzW, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)t, y, done,
                               st);
+}
+
+template <class T>
+Err enqueue_apply(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done,
+                  hipStream_t st)
+{
+    return enqueue_apply_with<T>(ctx, F, x, y, done, st, (T*)F->tmp, F->ctl);
+}
+
+// The allocation-free apply: the same kernels as diaf_apply, with t and the
+// control words in the device's fixed scratch array (cleared by a kernel),
+// then a read of the control words' error flag.
+template <class T>
+Err apply_noalloc(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y)
+{
+    const int n = (int)F->n;
+    if ((size_t)n * sizeof(T) > NOALLOC_SCRATCH_BYTES - NOALLOC_CTL_BYTES)
+        return {DIAF_EINVAL, "diaf_apply_noalloc: n = " + std::to_string(n) + " needs " +
+                                 std::to_string((size_t)n * sizeof(T)) +
+                                 " bytes of scratch; the limit is " +
+                                 std::to_string(NOALLOC_SCRATCH_BYTES - NOALLOC_CTL_BYTES)};
+    void* base = nullptr;
+    DIAF_TRY(noalloc_scratch(ctx->device, &base));
+    TrsvCtl* ctl = (TrsvCtl*)base;
+    T* t = (T*)((unsigned char*)base + NOALLOC_CTL_BYTES);
+    hipStream_t st = ctx->stream;
+    DIAF_TRY(noalloc_clear(ctl, sizeof(TrsvCtl), st));
+    DIAF_TRY(enqueue_apply_with<T>(ctx, F, x, y, nullptr, st, t, ctl));
+    if (F->vtri == 1 || F->vtri == -1) {
+        TrsvCtl c{};
+        DIAF_HIP_TRY(hipMemcpyAsync(&c, ctl, sizeof(TrsvCtl), hipMemcpyDeviceToHost, st));
+        DIAF_HIP_TRY(hipStreamSynchronize(st));
+        if (c.error) return {DIAF_EDEVICE, "triangular solve exceeded its wait budget"};
+    }
+    return {};
 }
 
 template <class T>
@@ -1096,6 +1132,8 @@ diaf_status diaf_ctx_create(diaf_ctx** ctx, int device, void* hip_stream)
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return DIAF_EDEVICE;
     if (device < 0 || device >= ndev) return DIAF_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return DIAF_EDEVICE;
+    // the allocation-free apply's scratch array: its address on this device
+    if (diaf::noalloc_init(device).code != DIAF_OK) return DIAF_EDEVICE;
     auto* c = new diaf_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
@@ -1279,6 +1317,26 @@ diaf_status diaf_factors_levels(diaf_ctx* ctx, const diaf_factors* Fc, int32_t* 
 }
 
 void diaf_factors_destroy(diaf_factors* F) { free_factors(F); }
+
+diaf_status diaf_apply_noalloc(diaf_ctx* ctx, const diaf_factors* Fc, const void* x, void* y)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!Fc || !x || !y) return fail(ctx, DIAF_EINVAL, "NULL argument");
+    auto* F = const_cast<diaf_factors*>(Fc);
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    if (!F->apply_ready)
+        return fail(ctx, DIAF_EINVAL,
+                    "diaf_apply_noalloc: the factors are not prepared for applying (their "
+                    "row-oriented copies are built by the first diaf_apply or diaf_solve)");
+    if (F->stats.count_zero_pivot)
+        return fail(ctx, DIAF_ESINGULAR, std::to_string(F->stats.count_zero_pivot) +
+                                             " zero or non-finite pivots in V");
+    Err e = F->dtype == DIAF_F64
+                ? apply_noalloc<double>(ctx, F, (const double*)x, (double*)y)
+                : apply_noalloc<zc>(ctx, F, (const zc*)x, (zc*)y);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
 
 diaf_status diaf_apply(diaf_ctx* ctx, const diaf_factors* Fc, const void* x, void* y)
 {

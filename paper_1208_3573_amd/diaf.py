@@ -99,6 +99,7 @@ _SIGS = {
     "diaf_factors_levels": (c_int, [c_void_p, c_void_p, POINTER(c_int32)]),
     "diaf_factors_destroy": (None, [c_void_p]),
     "diaf_apply": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "diaf_apply_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "diaf_solve": (c_int, [c_void_p, POINTER(diaf_csc), c_void_p, c_void_p, c_void_p, c_double,
                            c_int32, POINTER(diaf_solve_info)]),
     "diaf_model_create": (c_int, [c_void_p, c_void_p, POINTER(c_void_p)]),
@@ -353,6 +354,11 @@ def diaf_autotune(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode) -> dict:
 
 def diaf_apply(ctx: Context, F: Factors, x, y):
     ctx.check(ctx.lib.diaf_apply(ctx.h, F.h, c_void_p(x.data_ptr()), c_void_p(y.data_ptr())))
+
+
+def diaf_apply_noalloc(ctx: Context, F: Factors, x, y):
+    ctx.check(ctx.lib.diaf_apply_noalloc(ctx.h, F.h, c_void_p(x.data_ptr()),
+                                         c_void_p(y.data_ptr())))
 
 
 def diaf_solve(ctx: Context, A: DeviceCSC, F: Factors | None, b, x, rtol=1e-8, maxit=1000,
