@@ -4,6 +4,7 @@ pattern(A^2), V = diagonal + top-4 |A w0| rows of the lower triangle of the
 shadow, unit-norm-v mode), learned vs plain W pattern, one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode unit_v|unit_w]
+                    [--workload convdiff3d_64|random_1m]
 
 A step is one pass of the hot path on device-resident A and b: W pattern ->
 factor (all columns) -> V assembly -> BiCGSTAB to 1e-8.  `value` is
@@ -11,6 +12,13 @@ columns factored and solved per second over the step; the factoring pass
 alone, the solve, BiCGSTAB iterations and the learned-pattern variant are
 reported beside it, with the factor kernel's roofline and the CPU oracle's
 rate on the host cores.
+
+--workload random_1m: the random n = 10^6 matrix (lognormal column degrees,
+W = pattern(A) plus the top-8 two-hop rows, V = diagonal + top-4 lower).
+Its BiCGSTAB does not converge (30 % of the rows are not diagonally
+dominant), so there a step is the factoring pass alone (W pattern ->
+factor -> V assembly) and `value` is columns factored per second; the
+solve is run once, outside the timed steps, only with --solve-maxit.
 """
 from __future__ import annotations
 
@@ -142,20 +150,137 @@ VARIANTS = {
 }
 
 
-def cpu_baseline(A, J, mode, v, l, upper, b):
-    """The oracle as it stands, on all host cores, on the full workload once
-    (factor + BiCGSTAB)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A, J, mode, v, l, upper, b, solve, runs=3, sample_all=None, sample_1=32768):
+    """The oracle as it stands on the host cores: all cores, median of `runs`
+    runs on the full workload (factor + BiCGSTAB when the workload solves)
+    or on `sample_all` evenly spaced columns; and one core on `sample_1`
+    evenly spaced columns (factoring only)."""
     import oracle
     nth = oracle.nthreads_default()
+    cols_all = None if sample_all is None else np.linspace(0, A.n - 1, sample_all).astype(np.int32)
+    ncols = A.n if cols_all is None else len(cols_all)
+    rates, frates, its, fsec, ssec = [], [], None, [], []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        F = oracle.factor(A, J, mode, v, l, nthreads=nth, cols=cols_all)
+        t1 = time.perf_counter()
+        if solve:
+            _, info = oracle.bicgstab(A, b, F, upper=upper)
+            its = info.iters
+        t2 = time.perf_counter()
+        rates.append(ncols / (t2 - t0))
+        frates.append(ncols / (t1 - t0))
+        fsec.append(t1 - t0)
+        ssec.append(t2 - t1)
+    cols_1 = np.linspace(0, A.n - 1, min(sample_1, A.n)).astype(np.int32)
     t0 = time.perf_counter()
-    F = oracle.factor(A, J, mode, v, l, nthreads=nth)
-    t1 = time.perf_counter()
-    _, info = oracle.bicgstab(A, b, F, upper=upper)
-    t2 = time.perf_counter()
-    return dict(value=A.n / (t2 - t0), unit="columns/s", cores=nth, kind="oracle",
-                sample=f"full {WORKLOAD} workload once: factor {t1 - t0:.2f} s + "
-                       f"BiCGSTAB {t2 - t1:.2f} s ({info.iters} its)",
-                factor_cols_per_s=A.n / (t1 - t0), iters=info.iters)
+    oracle.factor(A, J, mode, v, l, nthreads=1, cols=cols_1)
+    one = len(cols_1) / (time.perf_counter() - t0)
+    what = "full workload" if cols_all is None else f"{ncols} evenly spaced columns"
+    sample = (f"{what}, median of {runs} runs on {nth} threads: factor "
+              f"{float(np.median(fsec)):.2f} s" +
+              (f" + BiCGSTAB {float(np.median(ssec)):.2f} s ({its} its)" if solve else "") +
+              f"; 1 thread: factoring {len(cols_1)} evenly spaced columns")
+    return dict(value=float(np.median(rates)), unit="columns/s", cores=nth, kind="oracle",
+                sample=sample, cpu=cpu_model(), factor_cols_per_s=float(np.median(frates)),
+                factor_cols_per_s_1core=one, iters=its)
+
+
+CLASS_CAPS = [(16, 128), (32, 256), (64, 512), (64, 1024), (128, 2048), (256, 4096), (256, 8192)]
+
+
+def column_stats(A, Jcp, Jri, lcount, mode, sv):
+    """Per column: algorithmic bytes and flops (as algorithmic_bytes and
+    algorithmic_flops count them), |J_j|, gathered entries and the shadow
+    size m_j, from the symbolic product pattern(A) pattern(J)."""
+    import scipy.sparse as sp
+    n = A.n
+    cn = np.diff(A.colptr).astype(np.int64)
+    k = np.diff(Jcp).astype(np.int64)
+    col = np.repeat(np.arange(n), k)
+    t = np.bincount(col, weights=cn[Jri], minlength=n).astype(np.int64)
+    l = np.asarray(lcount, dtype=np.int64)
+    byt = t * (sv + 4) + 8 * k + 4 * k + k * (sv + 4) + l * (sv + 4) + 8
+    P = sp.csc_matrix((np.ones(A.nnz), A.rowidx, A.colptr), shape=(n, n))
+    S = sp.csc_matrix((np.ones(len(Jri)), Jri, Jcp), shape=(n, n))
+    C = (P @ S).tocsc()
+    m = np.diff(C.indptr).astype(np.int64)
+    c = C.data
+    ccol = np.repeat(np.arange(n), m)
+    gram = np.bincount(ccol, weights=c * (c + 1.0), minlength=n)
+    nnzb = np.bincount(ccol, weights=c, minlength=n)
+    kf, lf = k.astype(np.float64), l.astype(np.float64)
+    if mode == "unit_v":
+        fl = gram + kf ** 3 / 3 + 2 * kf ** 2 * (1 + lf) + 2 * lf ** 2 * kf + 42 * lf ** 3 + 2 * nnzb
+    else:
+        fl = gram + 2 * lf * kf ** 2 + 84 * kf ** 3 + 2 * nnzb
+    fl = fl * (4.0 if A.is_complex else 1.0)
+    cls = np.full(n, len(CLASS_CAPS))
+    for q in range(len(CLASS_CAPS) - 1, -1, -1):
+        cls[(k <= CLASS_CAPS[q][0]) & (t <= CLASS_CAPS[q][1])] = q
+    return dict(bytes=byt, flops=fl, k=k, t=t, m=m, cls=cls)
+
+
+def kernel_rooflines(cs, st, flags, mode, lmax, steps_factor):
+    """Per factor kernel: the columns it finished (the one-wave kernel keeps
+    the columns of classes 0-1 with a shadow of at most 64 rows, and for
+    unit-norm w those whose block is not rank deficient; the generic kernel
+    takes the rest, per size class), their algorithmic bytes and flops, its
+    device time per pass, and the fractions of the HBM and FP64 peaks."""
+    small = (cs["cls"] <= 1) & (cs["m"] <= 64) & (lmax <= 8)
+    if mode == "unit_w":
+        small &= (flags & 1) == 0
+    out = {}
+    ms_small = st.ms_small_kernel / steps_factor
+    if st.launches_small:
+        b = float(cs["bytes"][small].sum())
+        f = float(cs["flops"][small].sum())
+        out["factor_small_kernel"] = dict(
+            cols=int(small.sum()), cols_reported=int(st.cols_small / steps_factor), ms=ms_small,
+            bytes=b, flops=f, gbs=b / (ms_small * 1e-3) / 1e9,
+            hbm_frac=b / (ms_small * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            fp64_frac=f / (ms_small * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
+            waves_per_simd=st.occ_small, launches=1)
+    gen = ~small
+    ms_gen = sum(st.ms_generic_class[q] for q in range(8)) / steps_factor
+    if ms_gen > 0:
+        per = {}
+        for q in range(len(CLASS_CAPS)):
+            if not st.launches_generic_class[q]:
+                continue
+            sel = gen & (cs["cls"] == q)
+            msq = st.ms_generic_class[q] / steps_factor
+            bq = float(cs["bytes"][sel].sum())
+            per[str(q)] = dict(caps=CLASS_CAPS[q], cols=int(sel.sum()),
+                               cols_reported=int(st.cols_generic_class[q] / steps_factor),
+                               ms=msq, gbs=bq / (msq * 1e-3) / 1e9,
+                               waves_per_simd=st.occ_generic_class[q])
+        b = float(cs["bytes"][gen].sum())
+        f = float(cs["flops"][gen].sum())
+        out["factor_generic_kernel"] = dict(
+            cols=int(gen.sum()), ms=ms_gen, bytes=b, flops=f, gbs=b / (ms_gen * 1e-3) / 1e9,
+            hbm_frac=b / (ms_gen * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            fp64_frac=f / (ms_gen * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
+            launches=len(per), classes=per)
+    return out
+
+
+def density(H, nnzA):
+    """rho = (nnz(W) + nnz(L_V) + nnz(U_V)) / nnz(A), the density the paper
+    reports with its tables; a triangular V is its own LU factor, so the V
+    part is nnz(V)."""
+    return (len(H["Wri"]) + len(H["Vri"])) / nnzA
 
 
 def main():
@@ -164,6 +289,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", default="unit_v", choices=["unit_v", "unit_w"])
+    ap.add_argument("--workload", default=WORKLOAD, choices=["convdiff3d_64", "random_1m"])
+    ap.add_argument("--solve-maxit", type=int, default=0,
+                    help="random_1m: run BiCGSTAB once after the timed steps with this maxit")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
@@ -190,8 +318,10 @@ def main():
     from paper_1208_3573_amd import diaf
     from paper_1208_3573_amd import learned as LR
 
-    cfg = synth.WORKLOADS[WORKLOAD]
-    A = synth.workload_matrix(WORKLOAD)
+    workload = args.workload
+    solves = workload == "convdiff3d_64"
+    cfg = synth.WORKLOADS[workload]
+    A = synth.workload_matrix(workload)
     b = synth.rhs_ones(A)
     upper = cfg["v"].endswith("upper")
     ctx = diaf.Context(0)
@@ -201,7 +331,8 @@ def main():
     dA = diaf.DeviceCSC.from_host(A)
     db = torch.from_numpy(b).cuda()
     x = torch.zeros_like(db)
-    spec = diaf.make_spec(w=cfg["w"], v=cfg["v"], v_count=cfg["v_count"])
+    spec = diaf.make_spec(w=cfg["w"], v=cfg["v"], v_count=cfg["v_count"],
+                          w_topk=cfg.get("w_topk", 0))
     tuned = None
     if not args.no_autotune:
         # launch shapes picked on this problem, before (and outside) the timed steps
@@ -210,29 +341,35 @@ def main():
         tuned["seconds"] = time.perf_counter() - t0
         log(f"autotune: {tuned}")
 
-    def step(spec_):
+    def step(spec_, solve=solves, maxit=1000):
         t0 = time.perf_counter()
         F = diaf.diaf_factor(ctx, dA, spec_, args.mode)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
-        torch.cuda.synchronize()
+        info = None
+        if solve:
+            info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, maxit)
+            torch.cuda.synchronize()
         t2 = time.perf_counter()
         st = F.stats()
         return F, st, info, (t1 - t0) * 1e3, (t2 - t1) * 1e3
 
+    def its(info):
+        return f", {info.iters} its" if info is not None else ""
+
     for _ in range(args.warmup):
         F, st, info, fms, sms = step(spec)
-        log(f"warmup: factor {fms:.1f} ms, solve {sms:.1f} ms, {info.iters} its")
+        log(f"warmup: factor {fms:.1f} ms, solve {sms:.1f} ms{its(info)}")
         F.close()
     torch.cuda.synchronize()
     recs = []
     t_start = time.perf_counter()
     for _ in range(args.steps):
         F, st, info, fms, sms = step(spec)
-        log(f"step: factor {fms:.1f} ms, solve {sms:.1f} ms, {info.iters} its")
+        log(f"step: factor {fms:.1f} ms, solve {sms:.1f} ms{its(info)}")
         recs.append((st.ms_factor_kernels, st.ms_pattern, st.ms_factor, st.ms_assemble, fms, sms,
-                     info.iters, info.relres_true, st.factor_launches))
+                     info.iters if info else 0, info.relres_true if info else np.nan,
+                     st.factor_launches))
         last = F
         if len(recs) < args.steps:
             F.close()
@@ -245,7 +382,7 @@ def main():
     solve_ms = float(np.mean(R[:, 5]))
     iters = int(R[-1, 6])
     st = last.stats()
-    levels = last.levels()  # diagnostic depth of the V solve, taken after the timed steps
+    levels = last.levels() if solves else None  # diagnostic, after the timed steps
     H = last.to_host()
     sv = 16 if A.is_complex else 8
     bytes_alg, gathered = algorithmic_bytes(A, H["Wri"], H["lcount"], sv)
@@ -253,9 +390,30 @@ def main():
     achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
     flops_alg = algorithmic_flops(A, H["Wcp"], H["Wri"], H["lcount"], args.mode)
     tflops = flops_alg / (kern_ms * 1e-3) / 1e12
-    kname = "factor_small_kernel" if (st.count_deferred == 0 and launches == 1) \
-        else "factor_generic_kernel"
-    traffic = measured_traffic(kname, WORKLOAD, args.mode)
+    cs = column_stats(A, H["Wcp"], H["Wri"], H["lcount"], args.mode, sv)
+    kr = kernel_rooflines(cs, st, H["flags"], args.mode, int(H["lcount"].max()), 1)
+    # the dominant factor kernel of the pass and its roofline
+    kname = max(kr, key=lambda q: kr[q]["ms"])
+    K = kr[kname]
+    hbm_bound = K["bytes"] / (HBM_PEAK_GBS * 1e9) >= K["flops"] / (FP64_PEAK_TFLOPS * 1e12)
+    traffic = measured_traffic(kname, workload, args.mode)
+    kach = K["bytes"] / (K["ms"] * 1e-3) / 1e9
+    ktf = K["flops"] / (K["ms"] * 1e-3) / 1e12
+    roof = ({"bound": "hbm", "achieved": kach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": kach / HBM_PEAK_GBS, "traffic": traffic} if hbm_bound else
+            {"bound": "alu", "achieved": ktf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": ktf / FP64_PEAK_TFLOPS, "traffic": traffic})
+    roof |= {"kernel": kname, "bytes_per_pass": K["bytes"], "flops_per_pass": K["flops"],
+             "ms_per_pass": K["ms"], "hbm_frac": K["hbm_frac"], "fp64_frac": K["fp64_frac"],
+             "launches_per_pass": K["launches"],
+             "waves_per_simd": K.get("waves_per_simd")}
+    if traffic:
+        roof["traffic_frac"] = traffic / (K["ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    cfgd = {"workload": workload, "n": A.n, "nnz": A.nnz, "w_pattern": cfg["w"]
+            + (f" top-{cfg['w_topk']}" if cfg.get("w_topk") else ""),
+            "v_pattern": f"{cfg['v']} l={cfg['v_count']}", "mode": args.mode}
+    if solves:
+        cfgd |= {"rhs": "A*ones", "rtol": 1e-8}
     out = {
         "metric": "columns factored/s + factor+solve time to 1e-8, learned vs plain, 1 GPU",
         "value": A.n / (ms_step * 1e-3),
@@ -269,33 +427,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": A.n, "nnz": A.nnz, "w_pattern": cfg["w"],
-                   "v_pattern": f"{cfg['v']} l={cfg['v_count']}", "mode": args.mode,
-                   "rhs": "A*ones", "rtol": 1e-8},
+        "config": cfgd,
+        "step": "W pattern + factor + V assembly + BiCGSTAB to 1e-8" if solves
+                else "W pattern + factor + V assembly (the solve does not converge on this matrix)",
         "factor_ms": factor_ms,
         "factor_kernel_ms": kern_ms,
+        "pattern_ms": float(np.mean(R[:, 1])),
+        "assemble_ms": float(np.mean(R[:, 3])),
         "factor_cols_per_s": A.n / (factor_ms * 1e-3),
         "factor_kernel_cols_per_s": A.n / (kern_ms * 1e-3),
-        "solve_ms": solve_ms,
-        "bicgstab_iters": iters,
-        "relres_true": float(R[-1, 7]),
         "nrm": st.nrm,
-        "v_levels": levels,
+        "rho": density(H, A.nnz),
         "autotuned": tuned,
-        "roofline": ({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
-                     if bytes_alg / (HBM_PEAK_GBS * 1e9) >= flops_alg / (FP64_PEAK_TFLOPS * 1e12)
-                     else {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS,
-                           "unit": "TFLOP/s", "frac": tflops / FP64_PEAK_TFLOPS,
-                           "traffic": traffic}) | {
-                     "kernel": kname, "bytes_per_pass": bytes_alg, "flops_per_pass": flops_alg,
-                     "hbm_frac": achieved / HBM_PEAK_GBS,
-                     "fp64_frac": tflops / FP64_PEAK_TFLOPS,
-                     "launches_per_pass": launches},
+        "roofline": roof,
+        "pass_roofline": {"bytes": bytes_alg, "gathered_entries": gathered, "flops": flops_alg,
+                          "kernel_ms": kern_ms, "hbm_frac": achieved / HBM_PEAK_GBS,
+                          "fp64_frac": tflops / FP64_PEAK_TFLOPS, "launches": launches},
+        "kernels": kr,
     }
+    if solves:
+        out |= {"solve_ms": solve_ms, "bicgstab_iters": iters, "relres_true": float(R[-1, 7]),
+                "v_levels": levels}
     last.close()
 
-    if not args.no_learned:
+    if solves and not args.no_learned:
         log("learned: preparing model")
         model, gate, gate_dom = LR.load_or_train(ctx, args.mode, log=log)
         lspec = diaf.make_spec(w="learned", v=cfg["v"], v_count=cfg["v_count"], model=model,
@@ -322,6 +477,13 @@ def main():
                         "nnz_w": int(len(H["Wri"])), "v_levels": int(levels)}
         model.close()
 
+    if not solves and args.solve_maxit > 0:
+        F, _, info, fms, sms = step(spec, solve=True, maxit=args.solve_maxit)
+        out["solve_once"] = {"maxit": args.solve_maxit, "iters": info.iters, "flag": info.flag,
+                             "relres": info.relres, "relres_true": info.relres_true,
+                             "ms": sms}
+        F.close()
+
     if args.variants:
         out["variants"] = {}
         for name in [v.strip() for v in args.variants.split(",") if v.strip()]:
@@ -332,7 +494,7 @@ def main():
             vspec = diaf.make_spec(**kw)
             rec = []
             for it in range(args.warmup + args.steps):
-                F, vst, vinfo, vf, vs = step(vspec)
+                F, vst, vinfo, vf, vs = step(vspec, solve=True)
                 log(f"variant {name}: factor {vf:.1f} ms (pattern {vst.ms_pattern:.2f}, kernels "
                     f"{vst.ms_factor_kernels:.2f}), solve {vs:.1f} ms, {vinfo.iters} its, "
                     f"flag {vinfo.flag}, relres_true {vinfo.relres_true:.2e}")
@@ -354,8 +516,14 @@ def main():
     if not args.no_cpu:
         log("cpu baseline: oracle on host cores")
         import oracle
-        Jo = oracle.pattern_A2(A)
-        out["cpu_baseline"] = cpu_baseline(A, Jo, args.mode, cfg["v"], cfg["v_count"], upper, b)
+        if workload == "convdiff3d_64":
+            Jo = oracle.pattern_A2(A)
+            out["cpu_baseline"] = cpu_baseline(A, Jo, args.mode, cfg["v"], cfg["v_count"], upper,
+                                               b, True)
+        else:
+            Jo = oracle.pattern_1hop(A, cfg["w_topk"])
+            out["cpu_baseline"] = cpu_baseline(A, Jo, args.mode, cfg["v"], cfg["v_count"], upper,
+                                               b, False, sample_all=200000, sample_1=20000)
     print(json.dumps(out), flush=True)
 
 

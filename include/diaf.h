@@ -241,6 +241,24 @@ typedef struct diaf_stats {
     double ms_pattern, ms_factor, ms_assemble;  /* device time of the phases */
     double ms_factor_kernels;        /* device time of the factor kernels alone */
     int32_t count_stabilized;        /* columns computed under the Section 3.2 constraint */
+    int32_t count_null_choice;       /* columns with DIAF_FLAG_NULL_CHOICE */
+    /* Device time and columns per factor kernel, summed over the factoring
+     * passes of these factors (the fallback pass of a learned pattern
+     * included): the one-wave kernel (the columns it finished, not those it
+     * handed on), and the generic kernel per size class, classes 0..6 holding
+     * |J_j| <= 16/32/64/64/128/256/256 and gathered entries <= 128/256/512/
+     * 1024/2048/4096/8192 (class 7 unused). */
+    double ms_small_kernel;
+    double ms_generic_class[8];
+    int32_t cols_small;
+    int32_t launches_small;
+    int32_t cols_generic_class[8];
+    int32_t launches_generic_class[8];
+    /* Theoretical occupancy of those launches, in waves per SIMD (the
+     * runtime's occupancy calculator with the kernels' register and LDS
+     * use; 0 where nothing ran). */
+    double occ_small;
+    double occ_generic_class[8];
 } diaf_stats;
 
 typedef struct diaf_solve_info {

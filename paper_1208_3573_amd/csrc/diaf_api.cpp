@@ -813,6 +813,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     fa.flags = F->flags;
     fa.lcount = F->lcount;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+    std::vector<int> ev_class;  // -1: the one-wave kernel, else the generic size class
     struct FreeEvents {
         std::vector<std::pair<hipEvent_t, hipEvent_t>>* v;
         ~FreeEvents() {
@@ -822,7 +823,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             }
         }
     } free_events{&events};
-    const auto timed = [&](auto&& launch) -> Err {
+    const auto timed = [&](int cls, auto&& launch) -> Err {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         DIAF_HIP_TRY(hipEventCreate(&e0));
         if (hipEventCreate(&e1) != hipSuccess) {
@@ -830,6 +831,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             return {DIAF_EDEVICE, "hipEventCreate"};
         }
         events.push_back({e0, e1});
+        ev_class.push_back(cls);
         DIAF_HIP_TRY(hipEventRecord(e0, st));
         DIAF_TRY(launch());
         DIAF_HIP_TRY(hipEventRecord(e1, st));
@@ -853,10 +855,14 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             DIAF_HIP_TRY(hipMemsetAsync(ndef, 0, sizeof(int32_t), st));
             fa.cols = sorted;
             fa.ncols = nsmall;
-            DIAF_TRY(timed([&] { return launch_factor_small<T>(fa, defl, ndef, ctx->ftune, st); }));
+            DIAF_TRY(timed(-1, [&] {
+                return launch_factor_small<T>(fa, defl, ndef, ctx->ftune, st);
+            }));
             ++nb;
             int32_t nd = 0;
             DIAF_TRY(read1(ndef, &nd, st));
+            F->stats.cols_small += nsmall - nd;
+            F->stats.occ_small = small_occupancy<T>(mode);
             if (nd > 0) {
                 DIAF_TRY(scratch(&dtmp, nd));
                 DIAF_TRY(scratch(&dsorted, nd));
@@ -889,16 +895,26 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             DIAF_TRY(dmalloc((unsigned char**)&gm, gbytes));
             to_free.push_back(gm);
         }
-        DIAF_TRY(timed([&] {
+        DIAF_TRY(timed(g.c, [&] {
             return launch_factor_generic<T>(fa, kcap, tcap, F->lmax, gm, nslots, ctx->ftune, st);
         }));
+        F->stats.cols_generic_class[g.c] += g.count;
+        F->stats.occ_generic_class[g.c] = generic_occupancy<T>(kcap, tcap, F->lmax, mode,
+                                                               ctx->ftune);
     }
     DIAF_TRY(sync(st));
     double kms = 0;
-    for (auto& ev : events) {
+    for (size_t q = 0; q < events.size(); ++q) {
         float ms = 0;
-        DIAF_HIP_TRY(hipEventElapsedTime(&ms, ev.first, ev.second));
+        DIAF_HIP_TRY(hipEventElapsedTime(&ms, events[q].first, events[q].second));
         kms += ms;
+        if (ev_class[q] < 0) {
+            F->stats.ms_small_kernel += ms;
+            F->stats.launches_small += 1;
+        } else {
+            F->stats.ms_generic_class[ev_class[q]] += ms;
+            F->stats.launches_generic_class[ev_class[q]] += 1;
+        }
     }
     F->stats.ms_factor_kernels += kms;
     F->stats.factor_launches += (int32_t)events.size();
@@ -950,6 +966,7 @@ Err compute_stats(diaf_ctx* ctx, diaf_factors* F)
     F->stats.count_tie_edge = c[4];
     F->stats.count_stabilized = c[5];
     F->stats.count_no_diag = c[6];
+    F->stats.count_null_choice = c[7];
     F->stats.nrm = sqrt(s);
     F->stats.n = F->n;
     F->stats.nnz_w = F->nnzW;

@@ -1078,6 +1078,26 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
     return {};
 }
 
+template <class T>
+double generic_occupancy(int kcap, int tcap, int lcap, int mode, FactorTune tune)
+{
+    GenPlan P = generic_plan<T>(kcap, tcap, lcap, mode, tune.generic_nt);
+    int nb = 0;
+    const void* k = P.in_lds ? (const void*)factor_generic_kernel<T, true>
+                             : (const void*)factor_generic_kernel<T, false>;
+    if (P.in_lds &&
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes) !=
+            hipSuccess)
+        return 0.0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, P.nt, P.in_lds ? P.lds_bytes : 0) !=
+        hipSuccess)
+        return 0.0;
+    return nb * (P.nt / 64) / 4.0;
+}
+
+template double generic_occupancy<double>(int, int, int, int, FactorTune);
+template double generic_occupancy<zc>(int, int, int, int, FactorTune);
+
 template Err launch_factor_generic<double>(const FactorArgs<double>&, int, int, int, void*, int,
                                            FactorTune, hipStream_t);
 template Err launch_factor_generic<zc>(const FactorArgs<zc>&, int, int, int, void*, int, FactorTune,

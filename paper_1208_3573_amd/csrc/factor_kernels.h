@@ -79,6 +79,13 @@ size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots);
 template <class T>
 Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, FactorTune tune,
                         hipStream_t st);
+// Theoretical waves per SIMD of the factor kernels (the runtime's occupancy
+// calculator): the one-wave kernel, and the generic kernel for a size class
+// as launch_factor_generic would place it.
+template <class T>
+double small_occupancy(int mode);
+template <class T>
+double generic_occupancy(int kcap, int tcap, int lcap, int mode, FactorTune tune);
 
 // ---- assembly and sparse utilities (sparse.hip) ----
 // Temporary device block for work queued on st, released with afree(p, st)

@@ -909,6 +909,19 @@ Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, F
     return {};
 }
 
+template <class T>
+double small_occupancy(int mode)
+{
+    int nb = 0;
+    const void* k = mode == 0 ? (const void*)factor_small_kernel<T, 0>
+                              : (const void*)factor_small_kernel<T, 1>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0) != hipSuccess) return 0.0;
+    return nb / 4.0;  // one wave per workgroup, four SIMDs per compute unit
+}
+
+template double small_occupancy<double>(int);
+template double small_occupancy<zc>(int);
+
 template Err launch_factor_small<double>(const FactorArgs<double>&, int*, int*, FactorTune,
                                          hipStream_t);
 template Err launch_factor_small<zc>(const FactorArgs<zc>&, int*, int*, FactorTune, hipStream_t);

@@ -196,7 +196,7 @@ __global__ void flag_stats_kernel(int n, const uint32_t* flags, const double* r,
     double s = 0.0;
     if (j < n) {
         uint32_t f = flags[j];
-        for (int b = 0; b < 7; ++b)
+        for (int b = 0; b < 8; ++b)
             if (f & (1u << b)) atomicAdd(&counts[b], 1);
         s = r[j] * r[j];
     }

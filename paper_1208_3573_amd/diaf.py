@@ -72,7 +72,12 @@ class diaf_stats(ctypes.Structure):
                 ("count_zero_pivot", c_int32), ("factor_launches", c_int32),
                 ("count_deferred", c_int32), ("nrm", c_double),
                 ("ms_pattern", c_double), ("ms_factor", c_double), ("ms_assemble", c_double),
-                ("ms_factor_kernels", c_double), ("count_stabilized", c_int32)]
+                ("ms_factor_kernels", c_double), ("count_stabilized", c_int32),
+                ("count_null_choice", c_int32), ("ms_small_kernel", c_double),
+                ("ms_generic_class", c_double * 8), ("cols_small", c_int32),
+                ("launches_small", c_int32), ("cols_generic_class", c_int32 * 8),
+                ("launches_generic_class", c_int32 * 8), ("occ_small", c_double),
+                ("occ_generic_class", c_double * 8)]
 
 
 class diaf_solve_info(ctypes.Structure):

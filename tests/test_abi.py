@@ -83,3 +83,31 @@ def test_null_arguments_are_rejected_without_a_device():
         lib.diaf_ctx_destroy(h)
     else:
         assert rc == diaf.DIAF_EDEVICE
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Sizes and field offsets of the ctypes mirrors against the C compiler's
+    own layout of include/diaf.h (gcc, host code only)."""
+    import ctypes
+    from paper_1208_3573_amd import diaf
+    structs = {"diaf_csc": diaf.diaf_csc, "diaf_pattern": diaf.diaf_pattern,
+               "diaf_solve_info": diaf.diaf_solve_info, "diaf_stats": diaf.diaf_stats,
+               "diaf_spec": diaf.diaf_spec, "diaf_view": diaf.diaf_view,
+               "diaf_sparsify": diaf.diaf_sparsify}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "diaf.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)

@@ -195,6 +195,56 @@ def test_gram_fp32_variant_reports_error(ctx):
     F.close()
 
 
+def test_gram_fp32_error_report_random_1m(ctx):
+    """The FP32-Gram variant on the 10^6 workload (unit-norm v): its residual
+    and singular-vector errors against the FP64 oracle as a function of
+    kappa(B_j), on 4 000 columns spread over the size classes.  Reported, not
+    gated (the variant squares the condition number in FP32: errors grow like
+    kappa(B_j)^2 * 6e-8); the test only checks that the report is complete."""
+    from tests._gpu import sin_angle
+    cfg = synth.WORKLOADS["random_1m"]
+    A = synth.workload_matrix("random_1m")
+    J = oracle_pattern(A, cfg["w"], cfg["w_topk"])
+    cols, _ = _stratified(A, J, 700, 7)
+    F, H, _ = run_gpu(ctx, A, cfg["w"], cfg["v"], cfg["v_count"], "unit_v", wtopk=cfg["w_topk"],
+                      gram_fp32=True)
+    F.close()
+    O = oracle.factor(A, J, "unit_v", cfg["v"], cfg["v_count"], cols=cols)
+    Ad = A.to_scipy().tocsc()
+    kap, rerr, aerr, same = [], [], [], 0
+    for j in cols:
+        Jj = J.rowidx[J.colptr[j]:J.colptr[j + 1]]
+        B = Ad[:, Jj]
+        R = np.unique(B.indices)
+        s = np.linalg.svd(B[R, :].toarray(), compute_uv=False)
+        kap.append(s[0] / s[-1] if s[-1] > 0 else np.inf)
+        rerr.append(abs(H["r"][j] - O.r[j]) / max(O.r[j], 1e-300))
+        g_rows = H["Vri"][H["Vcp"][j]:H["Vcp"][j + 1]]
+        o_rows = O.Vrows_pad[j, :O.lcount[j]]
+        if np.array_equal(g_rows, o_rows):
+            same += 1
+            aerr.append(sin_angle(H["Vval"][H["Vcp"][j]:H["Vcp"][j + 1]],
+                                  O.Vvals_pad[j, :O.lcount[j]]))
+        else:
+            aerr.append(np.nan)
+    kap, rerr, aerr = np.array(kap), np.array(rerr), np.array(aerr)
+    say(f"fp32 Gram on random_1m: {len(cols)} columns, V pattern identical on {same}")
+    say("  log10 kappa(B_j) | columns | residual rel. err median / max | "
+        "sin angle of v median / max")
+    edges = [0, 1, 2, 3, 4, 6, np.inf]
+    rows = 0
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = (np.log10(kap) >= lo) & (np.log10(kap) < hi)
+        if not sel.any():
+            continue
+        rows += 1
+        a = aerr[sel][np.isfinite(aerr[sel])]
+        say(f"  [{lo}, {hi}) | {int(sel.sum())} | {np.median(rerr[sel]):.2e} / "
+            f"{np.max(rerr[sel]):.2e} | "
+            + (f"{np.median(a):.2e} / {np.max(a):.2e}" if a.size else "-"))
+    assert rows >= 2 and np.all(np.isfinite(rerr)) and same > 0.5 * len(cols)
+
+
 def test_invalid_inputs_are_rejected(ctx):
     import torch
     from paper_1208_3573_amd import diaf
