@@ -87,6 +87,7 @@ def kernel_source_sha(kernel):
     import hashlib
     csrc = os.path.join(ROOT, "paper_1208_3573_amd", "csrc")
     files = {"factor_small_kernel": ["factor_small.hip", "dcommon.h", "factor_kernels.h"],
+             "factor_mid_kernel": ["factor_mid.hip", "dcommon.h", "factor_kernels.h"],
              "factor_generic_kernel": ["factor_generic.hip", "dcommon.h", "factor_kernels.h"]}[kernel]
     h = hashlib.sha256()
     for f in files:
@@ -220,6 +221,7 @@ def column_stats(A, Jcp, Jri, lcount, mode, sv):
     ccol = np.repeat(np.arange(n), m)
     gram = np.bincount(ccol, weights=c * (c + 1.0), minlength=n)
     nnzb = np.bincount(ccol, weights=c, minlength=n)
+    shared = np.bincount(ccol, weights=(c >= 2), minlength=n).astype(np.int64)
     kf, lf = k.astype(np.float64), l.astype(np.float64)
     if mode == "unit_v":
         fl = gram + kf ** 3 / 3 + 2 * kf ** 2 * (1 + lf) + 2 * lf ** 2 * kf + 42 * lf ** 3 + 2 * nnzb
@@ -229,19 +231,34 @@ def column_stats(A, Jcp, Jri, lcount, mode, sv):
     cls = np.full(n, len(CLASS_CAPS))
     for q in range(len(CLASS_CAPS) - 1, -1, -1):
         cls[(k <= CLASS_CAPS[q][0]) & (t <= CLASS_CAPS[q][1])] = q
-    return dict(bytes=byt, flops=fl, k=k, t=t, m=m, cls=cls)
+    return dict(bytes=byt, flops=fl, k=k, t=t, m=m, cls=cls, shared=shared)
 
 
-def kernel_rooflines(cs, st, flags, mode, lmax, steps_factor):
+def kernel_rooflines(cs, st, flags, mode, lmax, steps_factor, is_complex=False):
     """Per factor kernel: the columns it finished (the one-wave kernel keeps
     the columns of classes 0-1 with a shadow of at most 64 rows, and for
-    unit-norm w those whose block is not rank deficient; the generic kernel
-    takes the rest, per size class), their algorithmic bytes and flops, its
-    device time per pass, and the fractions of the HBM and FP64 peaks."""
+    unit-norm w those whose block is not rank deficient; for unit-norm v the
+    mid-size kernel takes the other columns of classes 0-3 (complex: 0-1)
+    with at most 256 rows of two or more entries; the generic kernel takes
+    the rest, per size class), their algorithmic bytes and flops, its device
+    time per pass, and the fractions of the HBM and FP64 peaks."""
     small = (cs["cls"] <= 1) & (cs["m"] <= 64) & (lmax <= 8)
     if mode == "unit_w":
         small &= (flags & 1) == 0
+    mid = np.zeros_like(small)
+    if st.launches_mid:
+        mid = ~small & (cs["cls"] <= (1 if is_complex else 3)) & (cs["shared"] <= 256)
     out = {}
+    if st.launches_mid:
+        ms_mid = st.ms_mid_kernel / steps_factor
+        b = float(cs["bytes"][mid].sum())
+        f = float(cs["flops"][mid].sum())
+        out["factor_mid_kernel"] = dict(
+            cols=int(mid.sum()), cols_reported=int(st.cols_mid / steps_factor), ms=ms_mid,
+            bytes=b, flops=f, gbs=b / (ms_mid * 1e-3) / 1e9,
+            hbm_frac=b / (ms_mid * 1e-3) / (HBM_PEAK_GBS * 1e9),
+            fp64_frac=f / (ms_mid * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
+            waves_per_simd=st.occ_mid, launches=int(st.launches_mid / steps_factor))
     ms_small = st.ms_small_kernel / steps_factor
     if st.launches_small:
         b = float(cs["bytes"][small].sum())
@@ -252,7 +269,7 @@ def kernel_rooflines(cs, st, flags, mode, lmax, steps_factor):
             hbm_frac=b / (ms_small * 1e-3) / (HBM_PEAK_GBS * 1e9),
             fp64_frac=f / (ms_small * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
             waves_per_simd=st.occ_small, launches=1)
-    gen = ~small
+    gen = ~small & ~mid
     ms_gen = sum(st.ms_generic_class[q] for q in range(8)) / steps_factor
     if ms_gen > 0:
         per = {}
@@ -391,7 +408,8 @@ def main():
     flops_alg = algorithmic_flops(A, H["Wcp"], H["Wri"], H["lcount"], args.mode)
     tflops = flops_alg / (kern_ms * 1e-3) / 1e12
     cs = column_stats(A, H["Wcp"], H["Wri"], H["lcount"], args.mode, sv)
-    kr = kernel_rooflines(cs, st, H["flags"], args.mode, int(H["lcount"].max()), 1)
+    kr = kernel_rooflines(cs, st, H["flags"], args.mode, int(H["lcount"].max()), 1,
+                          A.is_complex)
     # the dominant factor kernel of the pass and its roofline
     kname = max(kr, key=lambda q: kr[q]["ms"])
     K = kr[kname]

@@ -259,6 +259,12 @@ typedef struct diaf_stats {
      * use; 0 where nothing ran). */
     double occ_small;
     double occ_generic_class[8];
+    /* The mid-size one-wave kernel (unit-norm v, shadows beyond 64 rows):
+     * device time, columns it finished, launches and occupancy. */
+    double ms_mid_kernel;
+    int32_t cols_mid;
+    int32_t launches_mid;
+    double occ_mid;
 } diaf_stats;
 
 typedef struct diaf_solve_info {

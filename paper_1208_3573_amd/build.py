@@ -28,6 +28,7 @@ SOURCES = [
     "blockv.hip",
     "factor_generic.hip",
     "factor_small.hip",
+    "factor_mid.hip",
     "sparse.hip",
     "solve.hip",
     "learned.hip",

@@ -24,6 +24,7 @@ struct diaf_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int64_t opt_generic_only = 0;
+    int64_t opt_mid = 1;  // the mid-size one-wave kernel for unit-norm v
     int64_t opt_batch = 8;
     int64_t opt_gate_small_diag = 1;
     int64_t opt_graph = 0;
@@ -813,7 +814,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     fa.flags = F->flags;
     fa.lcount = F->lcount;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-    std::vector<int> ev_class;  // -1: the one-wave kernel, else the generic size class
+    std::vector<int> ev_class;  // -1: one-wave kernel, -2: mid-size kernel, else generic class
     struct FreeEvents {
         std::vector<std::pair<hipEvent_t, hipEvent_t>>* v;
         ~FreeEvents() {
@@ -883,6 +884,63 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             F->stats.count_deferred += nd;
         }
     }
+    // Mid-size columns for unit-norm v (no Section 3.1 leverage rule, no
+    // Section 3.2 constraint, |L_j| <= 8): the mid-size one-wave kernel takes
+    // the classes it holds; the columns it hands back (more than 256 rows of
+    // B_j with two or more entries, or |L_j| > 8) join the generic kernel's
+    // list, sorted and classified again.
+    const bool mid_ok = mode == DIAF_UNIT_V && ctx->opt_mid && !ctx->opt_generic_only &&
+                        !spec->gram_fp32 && F->lmax <= 8 && !(spec->stab_r > 0.0) &&
+                        fa.vrule != V_LEV_LOWER && fa.vrule != V_LEV_UPPER;
+    if (mid_ok) {
+        int nmid = 0;
+        for (const Seg& g : segs)
+            if (mid_supports<T>(cc.kcap[g.c], cc.tcap[g.c])) nmid += g.count;
+        if (nmid > 0) {
+            std::vector<Seg> rest;
+            int32_t *mdefl = nullptr, *mndef = nullptr;
+            DIAF_TRY(scratch(&mdefl, nmid));
+            DIAF_TRY(scratch(&mndef, 1));
+            DIAF_HIP_TRY(hipMemsetAsync(mndef, 0, sizeof(int32_t), st));
+            for (const Seg& g : segs) {
+                const int kcap = cc.kcap[g.c], tcap = cc.tcap[g.c];
+                if (!mid_supports<T>(kcap, tcap)) {
+                    rest.push_back(g);
+                    continue;
+                }
+                fa.cols = g.cols;
+                fa.ncols = g.count;
+                DIAF_TRY(timed(-2, [&] {
+                    return launch_factor_mid<T>(fa, kcap, tcap, mdefl, mndef, ctx->ftune, st);
+                }));
+                ++nb;
+                F->stats.occ_mid = mid_occupancy<T>(kcap, tcap);
+            }
+            int32_t nd = 0;
+            DIAF_TRY(read1(mndef, &nd, st));
+            F->stats.cols_mid += nmid - nd;
+            if (nd > 0) {
+                int32_t *dtmp = nullptr, *dsorted = nullptr;
+                DIAF_TRY(scratch(&dtmp, nd));
+                DIAF_TRY(scratch(&dsorted, nd));
+                DIAF_TRY(sort_columns(n, nd, mdefl, dtmp, st));
+                DIAF_TRY(launch_classify_columns(n, nd, dtmp, kd, td, cc, dsorted, dmeta, nullptr, st));
+                int32_t dh[ColumnClasses::kMax + 1] = {};
+                DIAF_HIP_TRY(hipMemcpyAsync(dh, dmeta, sizeof(int32_t) * (ncls + 1),
+                                            hipMemcpyDeviceToHost, st));
+                DIAF_TRY(sync(st));
+                std::vector<Seg> d;
+                int off = 0;
+                for (int c = 0; c < ncls; ++c) {
+                    if (dh[c]) d.push_back({c, dsorted + off, dh[c]});
+                    off += dh[c];
+                }
+                rest.insert(rest.begin(), d.begin(), d.end());
+            }
+            F->stats.count_deferred += nd;
+            segs.swap(rest);
+        }
+    }
     for (const Seg& g : segs) {
         ++nb;
         fa.cols = g.cols;
@@ -908,9 +966,12 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         float ms = 0;
         DIAF_HIP_TRY(hipEventElapsedTime(&ms, events[q].first, events[q].second));
         kms += ms;
-        if (ev_class[q] < 0) {
+        if (ev_class[q] == -1) {
             F->stats.ms_small_kernel += ms;
             F->stats.launches_small += 1;
+        } else if (ev_class[q] == -2) {
+            F->stats.ms_mid_kernel += ms;
+            F->stats.launches_mid += 1;
         } else {
             F->stats.ms_generic_class[ev_class[q]] += ms;
             F->stats.launches_generic_class[ev_class[q]] += 1;
@@ -1176,6 +1237,7 @@ diaf_status diaf_ctx_get_option(const diaf_ctx* ctx, const char* key, int64_t* v
     if (!ctx || !key || !value) return DIAF_EINVAL;
     std::string k(key);
     if (k == "generic_only") *value = ctx->opt_generic_only;
+    else if (k == "mid") *value = ctx->opt_mid;
     else if (k == "solve_batch") *value = ctx->opt_batch;
     else if (k == "trsv_backoff") *value = ctx->trsv.backoff;
     else if (k == "trsv_waves") *value = ctx->trsv.waves;
@@ -1192,6 +1254,7 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
     if (!ctx || !key) return DIAF_EINVAL;
     std::string k(key);
     if (k == "generic_only") ctx->opt_generic_only = value;
+    else if (k == "mid") ctx->opt_mid = value ? 1 : 0;
     else if (k == "solve_batch") ctx->opt_batch = value < 1 ? 1 : value;
     else if (k == "trsv_backoff") {
         if (value < 0 || value > 256)

@@ -79,6 +79,17 @@ size_t generic_global_bytes(int kcap, int tcap, int lcap, int mode, int nslots);
 template <class T>
 Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, FactorTune tune,
                         hipStream_t st);
+// One-wave kernel for unit-norm v with |J_j| <= 64 and up to 1024 gathered
+// entries (complex: 32 and 256) for shadows beyond 64 rows; columns with more
+// than 256 rows holding two or more entries, or |L_j| > 8, are appended to
+// deferred.  kcap, tcap: the size class of the launch.
+template <class T>
+bool mid_supports(int kcap, int tcap);
+template <class T>
+Err launch_factor_mid(const FactorArgs<T>& A, int kcap, int tcap, int* deferred, int* ndeferred,
+                      FactorTune tune, hipStream_t st);
+template <class T>
+double mid_occupancy(int kcap, int tcap);
 // Theoretical waves per SIMD of the factor kernels (the runtime's occupancy
 // calculator): the one-wave kernel, and the generic kernel for a size class
 // as launch_factor_generic would place it.

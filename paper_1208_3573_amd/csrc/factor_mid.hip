@@ -1,0 +1,700 @@
+// Mid-size column kernel for the first basic algorithm (unit-norm columns
+// of V, paper Section 2.1): one wave per column for |J_j| <= MK (32 or 64)
+// and at most MT (256, 512 or 1024) gathered entries, so for shadows far
+// beyond the one-wave kernel's 64 rows.  Columns it cannot take (more than
+// 256 rows of B_j holding two or more entries, |L_j| > 8) are appended to a
+// deferred list for the generic kernel.
+//
+// Per column j, with B = A(R_j, J_j) and G = B^* B:
+//   * the gathered rows are deduplicated in an LDS hash table; the local id
+//     of a row is its rank among the occupied slots.  No sort: every sum runs
+//     over entries in their gathered order (column by column, rows ascending
+//     within a column), so no result depends on the order of the local ids,
+//     and ties in the V pattern are broken by global row;
+//   * row access (CSR) from per-row counts, a wave scan and a per-row sort
+//     of the entry ids (ascending entry = ascending column of B);
+//   * G: the diagonal from each column's own entries; an off-diagonal entry
+//     G(a, b) only for columns that share a row holding two or more entries
+//     (per-column bit masks over these "shared rows"), summed over column
+//     a's entries in A's row order;
+//   * G = L L^* by a right-looking Cholesky in LDS, one lane per row;
+//   * the seed w0 = G^{-1} b_j^* (V_0 = diagonals, Example 2.1), the scores
+//     |(B w0)_i| of the admissible rows and the top-(l-1) selection with the
+//     1e-10 tie band (Section 3.1), ties filled by ascending global row;
+//   * Y = G^{-1} B_L^*, H = B_L Y (l x l) = M^* M for the paper's M_j
+//     (eq. 2.3), v the top eigenvector of H by repeated squaring of the
+//     trace-normalised power, w = Y v (eq. 2.4);
+//   * phase (diagonal of V real positive), residual ||B w - v|| in FP64.
+#include "dcommon.h"
+#include "factor_kernels.h"
+
+namespace diaf {
+namespace mid {
+
+constexpr int ML = 8;     // max |L_j|
+constexpr int MSW = 4;    // 64-bit words of a column's shared-row mask (256 shared rows)
+constexpr int NRHS = ML;  // right-hand sides of the final solve
+
+template <class T>
+__device__ inline T shfl(T v, int src)
+{
+    if constexpr (num<T>::is_complex) return T{__shfl(v.x, src), __shfl(v.y, src)};
+    else return __shfl(v, src);
+}
+
+__device__ inline int wave_incl_scan(int x, int lane)
+{
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+__device__ inline double wave_sum(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+__device__ inline double wave_max(double x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    return x;
+}
+
+__device__ inline int wave_min_int(int x)
+{
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
+    return x;
+}
+
+// Packed lower triangle, row-major: G(i, q), q <= i.
+__device__ inline int ltri(int i, int q) { return i * (i + 1) / 2 + q; }
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+template <class T, int MK, int MT>
+struct MidLds {
+    static constexpr int HS = 2 * MT;  // hash slots (load factor <= 1/2)
+    static constexpr int HB = ilog2(HS);
+    int J[MK];
+    int off[MK + 1];
+    int R[MT];               // local row -> global row
+    T eval[MT];              // gathered values, column by column
+    uint8_t ecol[MT];        // column of B of each entry
+    uint16_t eloc[MT];       // local row of each entry (first the hash slot)
+    uint16_t rptr[MT + 1];   // CSR row starts
+    uint16_t csr[MT];        // entry ids, row by row, ascending within a row
+    uint16_t sidx[MT];       // shared-row index of a local row, 0xffff if single
+    union {
+        struct {
+            int key[HS];         // hash keys (global rows), -1 empty
+            uint16_t loc[HS];    // slot -> local row
+        } h;
+        struct {
+            T y[MT];             // per-row values (the seed's scores)
+        } p;
+    };
+    uint64_t cmask[MK][MSW];  // each column's shared rows (bit = shared index)
+    T G[MK * (MK + 1) / 2];   // Gram matrix, then its Cholesky factor (packed lower)
+    T X[MK][NRHS + 1];        // right-hand sides and solutions (column 0: the seed)
+    T P[ML * ML];             // power of H being squared
+    T v[ML];
+    T w[MK];
+    int L[ML];
+};
+
+// Top eigenvector of the Hermitian positive semidefinite l x l matrix (l <=
+// 8) held one entry per lane (hs, ht) = (lane / 8, lane % 8), zero outside
+// l x l: P = H / tr(H), then P <- P^2 / tr(P^2) (tr(P^2) = ||P||_F^2) until
+// 1 - tr(P^2) < 1e-12, one squaring more, at most 25; the eigenvector is the
+// column of the last power with the largest diagonal entry (lowest index on
+// ties), normalised, into out[0..l).  Returns false when the trace is not
+// positive or 25 squarings did not reach rank one (a relative gap below
+// about 1e-6).
+template <class T>
+__device__ bool top_eig8(T h, int l, int hs, int ht, int lane, T* P, T* out)
+{
+    const double tr = wave_sum((hs == ht) ? num<T>::re(h) : 0.0);
+    bool conv = false, ok = true;
+    if (!(tr > 0.0) || !isfinite(tr)) {
+        h = (hs == 0 && ht == 0) ? num<T>::one() : num<T>::zero();
+        ok = false;
+        conv = true;
+    } else {
+        h = num<T>::div(h, tr);
+    }
+    for (int s = 0; s < 25 && !conv; ++s) {
+        const double f = wave_sum(num<T>::abs2(h));
+        conv = (1.0 - f) < 1e-12;
+        P[lane] = h;
+        __syncthreads();
+        T acc = num<T>::zero();
+#pragma unroll
+        for (int q = 0; q < ML; ++q) acc += P[hs * ML + q] * P[q * ML + ht];
+        __syncthreads();
+        h = num<T>::div(acc, f);
+    }
+    if (!conv) ok = false;
+    const double dg = (hs == ht && hs < l) ? num<T>::re(h) : -1.0;
+    const double dmx = wave_max(dg);
+    const uint64_t cm = __ballot(hs == ht && hs < l && dg == dmx);
+    const int cstar = (__ffsll((unsigned long long)cm) - 1) >> 3;
+    if (ht == cstar && hs < ML) out[hs] = h;
+    __syncthreads();
+    double nv = 0.0;
+    for (int t = 0; t < l; ++t) nv += num<T>::abs2(out[t]);
+    nv = sqrt(nv);
+    __syncthreads();
+    if (lane < l) out[lane] = num<T>::div(out[lane], nv);
+    __syncthreads();
+    return ok;
+}
+
+// Solve G X = X in place for nr right-hand sides (columns 0..nr-1 of S.X)
+// with the Cholesky factor in S.G: forward L z = x, then backward L^* x = z.
+// Lane i < k keeps row i of every right-hand side in registers; the pivot
+// value of each step is broadcast by a shuffle.
+template <class T, int MK, int MT>
+__device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
+{
+    T x[NRHS + 1];
+#pragma unroll
+    for (int t = 0; t <= NRHS; ++t)
+        x[t] = (lane < k && t < nr) ? S.X[lane][t] : num<T>::zero();
+    for (int p = 0; p < k; ++p) {
+        const double d = num<T>::re(S.G[ltri(p, p)]);
+        const double inv = d > 0.0 ? 1.0 / d : 0.0;
+        const T lip = (lane > p && lane < k) ? S.G[ltri(lane, p)] : num<T>::zero();
+#pragma unroll
+        for (int t = 0; t <= NRHS; ++t) {
+            if (t >= nr) break;
+            const T zp = num<T>::mk(inv) * shfl(x[t], p);
+            if (lane == p) x[t] = zp;
+            else if (lane > p) x[t] -= lip * zp;
+        }
+    }
+    for (int p = k - 1; p >= 0; --p) {
+        const double d = num<T>::re(S.G[ltri(p, p)]);
+        const double inv = d > 0.0 ? 1.0 / d : 0.0;
+        // conj(L(p, i)) for the lanes i < p: row p of L, contiguous
+        const T lpi = lane < p ? num<T>::conj(S.G[ltri(p, lane)]) : num<T>::zero();
+#pragma unroll
+        for (int t = 0; t <= NRHS; ++t) {
+            if (t >= nr) break;
+            const T xp = num<T>::mk(inv) * shfl(x[t], p);
+            if (lane == p) x[t] = xp;
+            else if (lane < p) x[t] -= lpi * xp;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t <= NRHS; ++t)
+        if (lane < k && t < nr) S.X[lane][t] = x[t];
+    __syncthreads();
+}
+
+template <class T, int MK, int MT>
+__device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, int* deferred,
+                           int* ndeferred)
+{
+    using S_t = MidLds<T, MK, MT>;
+    constexpr int HS = S_t::HS;
+    int lane = threadIdx.x;
+    __asm__ volatile("" : "+v"(lane));
+    const int jb = A.Jcp[j];
+    const int k = A.Jcp[j + 1] - jb;
+    const int lmax = A.lmax;
+    const auto defer = [&]() {
+        __syncthreads();
+        if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+    };
+    // ---- 1. J_j and gather offsets (k <= 64 = one lane per column) ----
+    if (k > MK) { defer(); return; }
+    int len = 0;
+    if (lane < k) {
+        const int c = A.Jri[jb + lane];
+        S.J[lane] = c;
+        len = A.Acp[c + 1] - A.Acp[c];
+    }
+    const int inc = wave_incl_scan(len, lane);
+    if (lane < k) S.off[lane + 1] = inc;
+    if (lane == 0) S.off[0] = 0;
+    const int Tn = __shfl(inc, 63);
+    if (Tn > MT) { defer(); return; }
+    for (int s = lane; s < HS; s += 64) S.h.key[s] = -1;
+    __syncthreads();
+    // ---- 2. gather; rows into the hash table ----
+    for (int t = lane; t < Tn; t += 64) {
+        int lo = 0, hi = k - 1;  // largest a with off[a] <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const int p = A.Acp[S.J[lo]] + (t - S.off[lo]);
+        const int row = A.Ari[p];
+        S.eval[t] = A.Aval[p];
+        S.ecol[t] = (uint8_t)lo;
+        unsigned h = ((unsigned)row * 2654435761u) >> (32 - S_t::HB);  // < HS
+        for (;;) {  // at most HS probes: the table is at most half full
+            const int prev = atomicCAS(&S.h.key[h], -1, row);
+            if (prev == -1 || prev == row) break;
+            h = (h + 1) & (unsigned)(HS - 1);
+        }
+        S.eloc[t] = (uint16_t)h;
+    }
+    __syncthreads();
+    // ---- 3. local rows: rank of each occupied slot ----
+    int m = 0;
+    for (int s0 = 0; s0 < HS; s0 += 64) {
+        const int s = s0 + lane;
+        const int key = S.h.key[s];
+        const bool occ = key != -1;
+        const uint64_t msk = __ballot(occ);
+        const int pos = m + __popcll(msk & ((1ull << lane) - 1ull));
+        if (occ) { S.R[pos] = key; S.h.loc[s] = (uint16_t)pos; }
+        m += __popcll(msk);
+    }
+    __syncthreads();
+    // m <= Tn <= MT: every row came from an entry
+    for (int t = lane; t < Tn; t += 64) S.eloc[t] = S.h.loc[S.eloc[t]];
+    for (int r = lane; r <= m; r += 64) S.rptr[r] = 0;
+    int dj = -1;
+    for (int r0 = 0; r0 < m; r0 += 64) {
+        const uint64_t dm = __ballot(r0 + lane < m && S.R[r0 + lane] == j);
+        if (dm && dj < 0) dj = r0 + __ffsll((unsigned long long)dm) - 1;
+    }
+    __syncthreads();
+    // the hash table is dead from here: its keys' storage (HS = 2 MT ints)
+    // holds the row counters cnt[0..m) and cnt[MT..MT+m)
+    int* cnt = S.h.key;
+    for (int r = lane; r < m; r += 64) { cnt[r] = 0; cnt[MT + r] = 0; }
+    __syncthreads();
+    double bn2 = 0.0;
+    for (int t = lane; t < Tn; t += 64) {
+        atomicAdd(&cnt[S.eloc[t]], 1);
+        bn2 += num<T>::abs2(S.eval[t]);
+    }
+    bn2 = wave_sum(bn2);
+    __syncthreads();
+    if (dj < 0) {
+        for (int a = lane; a < k; a += 64) A.Wval[jb + a] = num<T>::zero();
+        for (int t = lane; t < lmax; t += 64) {
+            A.Vrows[(size_t)j * lmax + t] = -1;
+            A.Vvals[(size_t)j * lmax + t] = num<T>::zero();
+        }
+        if (lane == 0) {
+            A.rcol[j] = 0.0;
+            A.bnorm[j] = sqrt(bn2);
+            A.flags[j] = DIAF_FLAG_NO_DIAG_ROW;
+            A.lcount[j] = 0;
+        }
+        __syncthreads();
+        return;
+    }
+    // ---- 4. CSR by local row: exclusive scan of the counts, fill, sort ----
+    {
+        int base = 0;
+        for (int r0 = 0; r0 < m; r0 += 64) {
+            const int r = r0 + lane;
+            const int c = r < m ? cnt[r] : 0;
+            const int incl = wave_incl_scan(c, lane);
+            if (r < m) S.rptr[r] = (uint16_t)(base + incl - c);
+            base += __shfl(incl, 63);
+        }
+        if (lane == 0) S.rptr[m] = (uint16_t)Tn;
+    }
+    __syncthreads();
+    for (int t = lane; t < Tn; t += 64) {
+        const int r = S.eloc[t];
+        const int pos = S.rptr[r] + atomicAdd(&cnt[MT + r], 1);
+        S.csr[pos] = (uint16_t)t;
+    }
+    __syncthreads();
+    int ms = 0;  // rows holding two or more entries ("shared rows")
+    for (int r0 = 0; r0 < m; r0 += 64) {
+        const int r = r0 + lane;
+        bool sh = false;
+        if (r < m) {
+            const int b = S.rptr[r], e = S.rptr[r + 1];
+            for (int p = b + 1; p < e; ++p) {  // ascending entry id = ascending column
+                const uint16_t key = S.csr[p];
+                int q = p - 1;
+                while (q >= b && S.csr[q] > key) { S.csr[q + 1] = S.csr[q]; --q; }
+                S.csr[q + 1] = key;
+            }
+            sh = e - b >= 2;
+        }
+        const uint64_t msk = __ballot(sh);
+        if (r < m) S.sidx[r] = sh ? (uint16_t)(ms + __popcll(msk & ((1ull << lane) - 1ull)))
+                                  : (uint16_t)0xffff;
+        ms += __popcll(msk);
+    }
+    if (ms > 64 * MSW) { defer(); return; }
+    // ---- 5. Gram matrix ----
+    if (lane < k) {
+#pragma unroll
+        for (int wd = 0; wd < MSW; ++wd) S.cmask[lane][wd] = 0ull;
+    }
+    __syncthreads();
+    for (int t = lane; t < Tn; t += 64) {
+        const int q = S.sidx[S.eloc[t]];
+        if (q != 0xffff)
+            atomicOr((unsigned long long*)&S.cmask[S.ecol[t]][q >> 6], 1ull << (q & 63));
+    }
+    __syncthreads();
+    T dg = num<T>::zero();
+    if (lane < k)
+        for (int t = S.off[lane]; t < S.off[lane + 1]; ++t)
+            dg += num<T>::cmul(S.eval[t], S.eval[t]);
+    const double maxd = wave_max(lane < k ? num<T>::re(dg) : 0.0);
+    if (lane < k) S.G[ltri(lane, lane)] = dg;
+    __syncthreads();
+    {
+        const int npair = k * (k - 1) / 2;
+        for (int pi = lane; pi < npair; pi += 64) {
+            // strictly lower pair: pi = a (a - 1) / 2 + b, b < a
+            int a = (int)((sqrtf(8.0f * (float)pi + 1.0f) + 1.0f) * 0.5f);
+            while (a * (a - 1) / 2 > pi) --a;
+            while ((a + 1) * a / 2 <= pi) ++a;
+            const int b = pi - a * (a - 1) / 2;
+            T acc = num<T>::zero();
+            uint64_t any = 0;
+#pragma unroll
+            for (int wd = 0; wd < MSW; ++wd) any |= S.cmask[a][wd] & S.cmask[b][wd];
+            if (any) {
+                // the common rows in ascending global row (column a's order in
+                // A), so the sum does not depend on the local row ids
+                for (int e = S.off[a]; e < S.off[a + 1]; ++e) {
+                    const int r = S.eloc[e];
+                    const int q = S.sidx[r];
+                    if (q == 0xffff || !((S.cmask[b][q >> 6] >> (q & 63)) & 1ull)) continue;
+                    T vb = num<T>::zero();
+                    for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                        const int f = S.csr[pp];
+                        if (S.ecol[f] == b) vb = S.eval[f];
+                    }
+                    acc += num<T>::cmul(S.eval[e], vb);  // conj(B(r, a)) B(r, b)
+                }
+            }
+            S.G[ltri(a, b)] = acc;
+        }
+    }
+    __syncthreads();
+    // ---- 6. Cholesky G = L L^*, one lane per row ----
+    uint32_t flags = 0;
+    if (k > m) flags |= DIAF_FLAG_RANK_DEFICIENT;
+    for (int p = 0; p < k; ++p) {
+        const double d = num<T>::re(S.G[ltri(p, p)]);
+        if (!(d > 1e-14 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
+        const double piv = (d > 1e-30 * maxd && isfinite(d)) ? sqrt(d) : 0.0;
+        const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
+        T lip = num<T>::zero();
+        if (lane > p && lane < k) {
+            lip = num<T>::mk(inv) * S.G[ltri(lane, p)];
+            S.G[ltri(lane, p)] = lip;
+        }
+        __syncthreads();
+        if (lane == p) S.G[ltri(p, p)] = num<T>::mk(piv);
+        if (lane > p && lane < k)
+            for (int q = p + 1; q <= lane; ++q)
+                S.G[ltri(lane, q)] -= lip * num<T>::conj(S.G[ltri(q, p)]);
+        __syncthreads();
+    }
+    // ---- 7. V pattern ----
+    const bool topk =
+        A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_BLOCK;
+    int l = 0;
+    double* sc = reinterpret_cast<double*>(S.p.y);  // scores, one per local row
+    if (topk) {
+        if (lane < k) S.X[lane][0] = num<T>::zero();
+        __syncthreads();
+        for (int pp = S.rptr[dj] + lane; pp < S.rptr[dj + 1]; pp += 64) {
+            const int e = S.csr[pp];
+            S.X[S.ecol[e]][0] = num<T>::conj(S.eval[e]);
+        }
+        __syncthreads();
+        chol_solve(S, k, 1, lane);  // w0 = G^{-1} b_j^*
+        const int blo = A.vrule == V_TOPK_BLOCK ? A.vblk[2 * j] : 0;
+        const int bhi = A.vrule == V_TOPK_BLOCK ? A.vblk[2 * j + 1] : 0;
+        int ncl = 0;
+        for (int r = lane; r < m; r += 64) {
+            const int gi = S.R[r];
+            const bool adm = A.vrule == V_TOPK_BLOCK ? (gi != j && gi >= blo && gi < bhi)
+                             : A.vrule == V_TOPK_LOWER ? gi > j : gi < j;
+            double s = -1.0;
+            if (adm) {
+                T y = num<T>::zero();
+                for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                    const int e = S.csr[pp];
+                    y += S.eval[e] * S.X[S.ecol[e]][0];
+                }
+                s = num<T>::abs(y);
+                ++ncl;
+            }
+            sc[r] = s;
+        }
+        const int nc = (int)wave_sum((double)ncl);
+        int lj = A.vcount < 1 ? 1 : A.vcount;
+        if (lj > 1 + nc) lj = 1 + nc;
+        if (lj > lmax) lj = lmax;
+        if (lj > ML) lj = ML;
+        const int q = lj - 1;
+        __syncthreads();
+        // rows r = lane + 64 i of this lane: i < MT / 64 <= 16 bits
+        uint32_t chosen = 0;
+        if (q > 0 && nc <= q) {
+            for (int i = 0; lane + 64 * i < m; ++i)
+                if (sc[lane + 64 * i] >= 0.0) chosen |= 1u << i;
+        } else if (q > 0) {
+            // the q-th largest score, counting equal scores separately
+            uint32_t taken = 0;
+            double ss = 0.0;
+            for (int rd = 0; rd < q; ++rd) {
+                double best = -2.0;
+                int bi = -1;
+                for (int i = 0; lane + 64 * i < m; ++i) {
+                    const double s = sc[lane + 64 * i];
+                    if (s >= 0.0 && !((taken >> i) & 1u) && s > best) { best = s; bi = i; }
+                }
+                const double mx = wave_max(best);
+                const uint64_t bm = __ballot(best == mx && bi >= 0);
+                if (lane == __ffsll((unsigned long long)bm) - 1) taken |= 1u << bi;
+                ss = mx;
+            }
+            const double hi = ss * (1.0 + 1e-10), lo = ss * (1.0 - 1e-10);
+            uint32_t tie = 0;
+            int nin = 0;
+            bool edge = false;
+            for (int i = 0; lane + 64 * i < m; ++i) {
+                const double s = sc[lane + 64 * i];
+                if (s < 0.0) continue;
+                if (s > hi) { chosen |= 1u << i; ++nin; }
+                else if (s >= lo) tie |= 1u << i;
+                if (ss > 0.0 && (fabs(s - hi) <= 1e-12 * ss || fabs(s - lo) <= 1e-12 * ss))
+                    edge = true;
+            }
+            if (__ballot(edge)) flags |= DIAF_FLAG_TIE_EDGE;
+            int need = q - (int)wave_sum((double)nin);
+            // fill the tie class by ascending global row
+            for (; need > 0; --need) {
+                int gbest = 0x7fffffff, ib = -1;
+                for (int i = 0; lane + 64 * i < m; ++i)
+                    if (((tie >> i) & 1u) && S.R[lane + 64 * i] < gbest) {
+                        gbest = S.R[lane + 64 * i];
+                        ib = i;
+                    }
+                const int gm = wave_min_int(gbest);
+                if (gm == 0x7fffffff) break;
+                if (ib >= 0 && gbest == gm) { chosen |= 1u << ib; tie &= ~(1u << ib); }
+            }
+        }
+        // compact: L[0] = j's row, then the chosen rows
+        l = 1;
+        for (int i = 0; i < MT / 64; ++i) {
+            const bool c = (chosen >> i) & 1u;
+            const uint64_t cm = __ballot(c);
+            if (c) S.L[l + __popcll(cm & ((1ull << lane) - 1ull))] = lane + 64 * i;
+            l += __popcll(cm);
+        }
+        if (lane == 0) S.L[0] = dj;
+    } else if (A.vrule == V_DIAG) {
+        if (lane == 0) S.L[0] = dj;
+        l = 1;
+    } else {
+        // Gauss-Seidel structure or an explicit pattern: the listed rows of
+        // column j that lie in the shadow, found by a scan of R
+        int b = 0, e = 0;
+        const int32_t* rows = nullptr;
+        if (A.vrule == V_EXPLICIT) { b = A.Vcp_in[j]; e = A.Vcp_in[j + 1]; rows = A.Vri_in; }
+        else { b = A.Acp[j]; e = A.Acp[j + 1]; rows = A.Ari; }
+        for (int p = b; p < e; ++p) {
+            const int gi = rows[p];
+            const bool keep = A.vrule == V_EXPLICIT || gi == j ||
+                              (A.vrule == V_GS_UPPER ? gi < j : gi > j);
+            if (!keep) continue;
+            int lr = -1;
+            for (int r0 = 0; r0 < m && lr < 0; r0 += 64) {
+                const uint64_t hm = __ballot(r0 + lane < m && S.R[r0 + lane] == gi);
+                if (hm) lr = r0 + __ffsll((unsigned long long)hm) - 1;
+            }
+            if (lr < 0) continue;
+            if (l < ML && lane == 0) S.L[l] = lr;
+            ++l;
+        }
+        if (l > ML || l > lmax) { defer(); return; }
+    }
+    __syncthreads();
+    // ---- 8. Y = G^{-1} B_L^*, H = B_L Y, v = top eigenvector of H, w = Y v ----
+    if (lane < k) {
+#pragma unroll
+        for (int t = 0; t < ML; ++t) S.X[lane][t] = num<T>::zero();
+    }
+    __syncthreads();
+    for (int t = 0; t < l; ++t) {
+        const int r = S.L[t];
+        for (int pp = S.rptr[r] + lane; pp < S.rptr[r + 1]; pp += 64) {
+            const int e = S.csr[pp];
+            S.X[S.ecol[e]][t] = num<T>::conj(S.eval[e]);
+        }
+    }
+    __syncthreads();
+    chol_solve(S, k, l, lane);
+    {
+        const int hs = lane >> 3, ht = lane & 7;
+        T h = num<T>::zero();
+        if (hs < l && ht < l) {
+            const int r = S.L[hs];
+            for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                const int e = S.csr[pp];
+                h += S.eval[e] * S.X[S.ecol[e]][ht];
+            }
+        }
+        if (!top_eig8(h, l, hs, ht, lane, S.P, S.v)) flags |= DIAF_FLAG_GAP_DEGENERATE;
+    }
+    if (lane < k) {
+        T acc = num<T>::zero();
+        for (int t = 0; t < l; ++t) acc += S.X[lane][t] * S.v[t];
+        S.w[lane] = acc;
+    }
+    __syncthreads();
+    // ---- 9. phase, residual, outputs ----
+    T vt = lane < l ? S.v[lane] : num<T>::zero();
+    const double vn = sqrt(wave_sum(lane < l ? num<T>::abs2(vt) : 0.0));
+    const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
+    const int dpos = dposm ? __ffsll((unsigned long long)dposm) - 1 : -1;
+    int piv;
+    if (dpos >= 0 && num<T>::abs(shfl(vt, dpos)) >= 1e-8 * vn) {
+        piv = dpos;
+    } else {
+        const double av = lane < l ? num<T>::abs(vt) : -1.0;
+        const double mx = wave_max(av);
+        const int gr = lane < l ? S.R[S.L[lane]] : 0x7fffffff;
+        const int cand = wave_min_int((lane < l && av == mx) ? gr : 0x7fffffff);
+        const uint64_t pm = __ballot(lane < l && av == mx && gr == cand);
+        piv = __ffsll((unsigned long long)pm) - 1;
+    }
+    const T pvv = shfl(vt, piv);
+    const T ph = num<T>::iszero(pvv) ? num<T>::one() : unit_conj_phase(pvv);
+    vt = ph * vt;
+    if (dpos < 0 || num<T>::abs(shfl(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
+        flags |= DIAF_FLAG_SMALL_DIAG;
+    if (lane < l) S.v[lane] = vt;
+    if (lane < k) S.w[lane] = ph * S.w[lane];
+    __syncthreads();
+    // residual: each row is taken by the lane of its first entry, so the
+    // order of the sum follows the entries, not the local row ids
+    double r2 = 0.0;
+    for (int t0 = lane; t0 < Tn; t0 += 64) {
+        const int r = S.eloc[t0];
+        if (S.csr[S.rptr[r]] != t0) continue;
+        T res = num<T>::zero();
+        for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+            const int e = S.csr[pp];
+            res += S.eval[e] * S.w[S.ecol[e]];
+        }
+        for (int t = 0; t < l; ++t)
+            if (S.L[t] == r) res -= S.v[t];
+        r2 += num<T>::abs2(res);
+    }
+    r2 = wave_sum(r2);
+    if (lane < k) A.Wval[jb + lane] = S.w[lane];
+    const int myg = lane < l ? S.R[S.L[lane]] : 0x7fffffff;
+    int rank = 0;
+    for (int t = 0; t < l; ++t) rank += S.R[S.L[t]] < myg;
+    if (lane < l) {
+        A.Vrows[(size_t)j * lmax + rank] = myg;
+        A.Vvals[(size_t)j * lmax + rank] = S.v[lane];
+    } else if (lane < lmax) {
+        A.Vrows[(size_t)j * lmax + lane] = -1;
+        A.Vvals[(size_t)j * lmax + lane] = num<T>::zero();
+    }
+    if (lane == 0) {
+        A.rcol[j] = sqrt(r2);
+        A.bnorm[j] = sqrt(bn2);
+        A.flags[j] = flags;
+        A.lcount[j] = l;
+    }
+    __syncthreads();
+}
+
+template <class T, int MK, int MT>
+__global__ void __launch_bounds__(64) factor_mid_kernel(FactorArgs<T> A, int* deferred,
+                                                        int* ndeferred)
+{
+    __shared__ MidLds<T, MK, MT> S;
+    // contiguous eighths of the column list per XCD (workgroups are dealt to
+    // the 8 XCDs round robin), as in the one-wave kernel
+    constexpr int NX = 8;
+    const int nper = gridDim.x / NX;
+    int q0 = blockIdx.x, qs = gridDim.x, qe = A.ncols;
+    if (nper > 0) {
+        if ((int)blockIdx.x >= nper * NX) return;
+        const int x = blockIdx.x % NX, w = blockIdx.x / NX;
+        const int chunk = (A.ncols + NX - 1) / NX;
+        q0 = x * chunk + w;
+        qs = nper;
+        qe = min(A.ncols, (x + 1) * chunk);
+    }
+    for (int q = q0; q < qe; q += qs) mid_column(A, A.cols[q], S, deferred, ndeferred);
+}
+
+}  // namespace mid
+
+template <class T>
+bool mid_supports(int kcap, int tcap)
+{
+    if constexpr (num<T>::is_complex) return kcap <= 32 && tcap <= 256;
+    else return kcap <= 64 && tcap <= 1024;
+}
+
+template <class T, int MK, int MT>
+static Err launch_mid_t(const FactorArgs<T>& A, int* deferred, int* ndeferred, int grid,
+                        hipStream_t st)
+{
+    hipLaunchKernelGGL((mid::factor_mid_kernel<T, MK, MT>), dim3(grid), dim3(64), 0, st, A,
+                       deferred, ndeferred);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
+template <class T>
+Err launch_factor_mid(const FactorArgs<T>& A, int kcap, int tcap, int* deferred, int* ndeferred,
+                      FactorTune tune, hipStream_t st)
+{
+    if (A.ncols == 0) return {};
+    if (!mid_supports<T>(kcap, tcap)) return {DIAF_EINVAL, "mid kernel: size class too large"};
+    const int want = tune.small_grid > 0 ? tune.small_grid : 256 * 16;
+    const int grid = A.ncols < want ? A.ncols : want;
+    if (kcap <= 32 && tcap <= 256) return launch_mid_t<T, 32, 256>(A, deferred, ndeferred, grid, st);
+    if constexpr (!num<T>::is_complex) {
+        if (tcap <= 512) return launch_mid_t<T, 64, 512>(A, deferred, ndeferred, grid, st);
+        return launch_mid_t<T, 64, 1024>(A, deferred, ndeferred, grid, st);
+    }
+    return {DIAF_EINVAL, "mid kernel: size class too large"};
+}
+
+template <class T>
+double mid_occupancy(int kcap, int tcap)
+{
+    int nb = 0;
+    const void* k = nullptr;
+    if (kcap <= 32 && tcap <= 256) k = (const void*)mid::factor_mid_kernel<T, 32, 256>;
+    if constexpr (!num<T>::is_complex) {
+        if (!k && tcap <= 512) k = (const void*)mid::factor_mid_kernel<T, 64, 512>;
+        if (!k) k = (const void*)mid::factor_mid_kernel<T, 64, 1024>;
+    }
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0) != hipSuccess) return 0.0;
+    return nb / 4.0;
+}
+
+template bool mid_supports<double>(int, int);
+template bool mid_supports<zc>(int, int);
+template Err launch_factor_mid<double>(const FactorArgs<double>&, int, int, int*, int*, FactorTune,
+                                       hipStream_t);
+template Err launch_factor_mid<zc>(const FactorArgs<zc>&, int, int, int*, int*, FactorTune,
+                                   hipStream_t);
+template double mid_occupancy<double>(int, int);
+template double mid_occupancy<zc>(int, int);
+
+}  // namespace diaf

@@ -77,7 +77,8 @@ class diaf_stats(ctypes.Structure):
                 ("ms_generic_class", c_double * 8), ("cols_small", c_int32),
                 ("launches_small", c_int32), ("cols_generic_class", c_int32 * 8),
                 ("launches_generic_class", c_int32 * 8), ("occ_small", c_double),
-                ("occ_generic_class", c_double * 8)]
+                ("occ_generic_class", c_double * 8), ("ms_mid_kernel", c_double),
+                ("cols_mid", c_int32), ("launches_mid", c_int32), ("occ_mid", c_double)]
 
 
 class diaf_solve_info(ctypes.Structure):

@@ -60,11 +60,9 @@ def test_factor_parity_small(ctx, name):
             small, deferred, generic = _launch_classes(A, J)
             say(f"classes: one-wave {small} deferred {deferred} generic {generic}")
             assert small > 0 and deferred > 0 and generic > 0
-            # unit-norm w also hands over rank-deficient columns
-            if mode == "unit_v":
-                assert st.count_deferred == deferred
-            else:
-                assert st.count_deferred >= deferred
+            # unit-norm w also hands over rank-deficient columns, and the
+            # mid-size kernel hands on what it cannot hold
+            assert st.count_deferred >= deferred
             assert st.factor_launches >= 3
         F.close()
 
@@ -85,6 +83,66 @@ def _launch_classes(A, J):
         else:
             small += 1
     return small, deferred, generic
+
+
+def _a3_pattern(A):
+    """pattern((I + |A - D|)^3): Algorithm 1 with three powers and no
+    dropping, for grid matrices whose columns then reach 129 shadow rows."""
+    return oracle.pattern_sparsified_powers(A, k=3, tau_i=0.0)
+
+
+MID = {
+    # matrices whose columns mostly exceed the one-wave kernel's 64-row
+    # shadow, so that the mid-size kernel takes them (unit-norm v):
+    # name: (matrix, W pattern builder, V rule, l, block size for topk_block)
+    "lognormal_20k_topk": (lambda: synth.random_lognormal(20000, 12),
+                           lambda A: oracle.pattern_1hop(A, 8), "topk_lower", 5, 0),
+    "lognormal_20k_upper": (lambda: synth.random_lognormal(20000, 13),
+                            lambda A: oracle.pattern_1hop(A, 8), "topk_upper", 4, 0),
+    "lognormal_20k_diag": (lambda: synth.random_lognormal(20000, 14),
+                           lambda A: oracle.pattern_1hop(A, 8), "diag", 0, 0),
+    "lognormal_20k_block": (lambda: synth.random_lognormal(20000, 18),
+                            lambda A: oracle.pattern_1hop(A, 8), "topk_block", 5, 40),
+    "small_3k_gs": (lambda: synth.random_small(3000, 6, 15, diag_shift=2.0),
+                    lambda A: oracle.pattern_1hop(A, 24), "gs_lower", 0, 0),
+    "grid_10_a3": (lambda: synth.convdiff(10, 3, 16), _a3_pattern, "topk_lower", 5, 0),
+    "complex_2k": (lambda: synth.random_small(2000, 12, 17, complex_=True, diag_shift=2.0),
+                   lambda A: oracle.pattern_1hop(A, 6), "topk_lower", 5, 0),
+}
+
+
+@pytest.mark.parametrize("name", list(MID))
+def test_mid_kernel_parity(ctx, name):
+    """The mid-size one-wave kernel (unit-norm v, shadows beyond 64 rows)
+    against the oracle on every column, and bit for bit against itself on a
+    second run; it must have taken columns."""
+    import torch
+    from paper_1208_3573_amd import diaf
+    build, pat, v, l, bs = MID[name]
+    A = build()
+    J = pat(A)
+    say(f"case {name} n={A.n}")
+    dA = diaf.DeviceCSC.from_host(A)
+    dJ = diaf.DevicePattern.from_host(J.colptr, J.rowidx)
+    kw = dict(w="explicit", w_explicit=dJ, v=v, v_count=l)
+    vblocks = None
+    if bs:
+        vblocks = np.unique(np.concatenate([np.arange(0, A.n, bs), [A.n]])).astype(np.int32)
+        kw["v_blocks"] = torch.from_numpy(vblocks).cuda()
+    outs = []
+    for _ in range(2):
+        F = diaf.diaf_factor(ctx, dA, diaf.make_spec(**kw), "unit_v")
+        outs.append(F.to_host())
+        st = F.stats()
+        F.close()
+    say(f"  mid kernel: {st.cols_mid} columns, {st.launches_mid} launches, "
+        f"{st.ms_mid_kernel:.2f} ms; one-wave {st.cols_small}; generic "
+        f"{sum(st.cols_generic_class)}; handed on {st.count_deferred}")
+    assert st.cols_mid > 0 and st.launches_mid > 0
+    O = oracle.factor(A, J, "unit_v", v, l, vblocks=vblocks)
+    compare(outs[0], J, O, A, "unit_v")
+    for key in ("Wval", "Vri", "Vval", "r", "flags"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
 
 
 def _stratified(A, J, per_class, seed):
