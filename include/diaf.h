@@ -192,7 +192,7 @@ typedef struct diaf_spec {
     const int32_t* v_blocks;         /* DIAF_V_BLOCK / DIAF_V_TOPK_BLOCK: device array of
                                         v_nblocks + 1 block starts, 0 = s_0 < ... = n */
     int32_t v_nblocks;
-    int32_t left;                    /* 1: the left variant (Section 4's remarks on left and
+    int32_t left;                    /* 1: the left variant (Section 2.3's remarks on left and
                                         right approximate inverses): W A ~ V, found by the
                                         columnwise method on A^* (every pattern and rule above
                                         then applies to A^*, W^*, V^*; a lower rule gives an
@@ -290,6 +290,13 @@ diaf_status diaf_ctx_create(struct diaf_ctx** ctx, int device, void* hip_stream)
  * this context's device, and frees the context. */
 void diaf_ctx_destroy(struct diaf_ctx* ctx);
 const char* diaf_last_error(const struct diaf_ctx* ctx);
+
+/* Copy `bytes` between two buffers of any kind (device or host, the
+ * runtime tells which) in the context's stream order, then synchronise the
+ * stream: a helper for bindings that marshal host arrays into the device
+ * buffers the other calls take.  Errors: DIAF_EINVAL (NULL context, or a
+ * NULL buffer with bytes > 0), DIAF_EDEVICE. */
+diaf_status diaf_copy(struct diaf_ctx* ctx, void* dst, const void* src, size_t bytes);
 /* Tunables of the context (not of the method: results are identical for
  * every setting).  Keys:
  *   "generic_only"       1: every column goes to the generic factor kernel

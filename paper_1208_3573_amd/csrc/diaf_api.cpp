@@ -267,6 +267,19 @@ void dfree(void* p)
     (void)hipFree(p);
 }
 
+// Device blocks freed when the scope ends, on every return path; release()
+// keeps a block whose ownership moved elsewhere.
+struct DevBlocks {
+    std::vector<void*> p;
+    ~DevBlocks() { for (void* q : p) dfree(q); }
+    void keep(void* q) { p.push_back(q); }
+    void release(void* q)
+    {
+        for (void*& r : p)
+            if (r == q) r = nullptr;
+    }
+};
+
 }  // namespace
 
 Err diaf::amalloc(void** p, size_t bytes, hipStream_t)
@@ -897,19 +910,41 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         for (const Seg& g : segs)
             if (mid_supports<T>(cc.kcap[g.c], cc.tcap[g.c])) nmid += g.count;
         if (nmid > 0) {
+            // the mid-size columns, gathered and sorted by the kernel's own
+            // size classes (smaller LDS, higher occupancy, for |J_j| <= 32)
             std::vector<Seg> rest;
-            int32_t *mdefl = nullptr, *mndef = nullptr;
+            int32_t *mdefl = nullptr, *mndef = nullptr, *mcols = nullptr, *msorted = nullptr;
             DIAF_TRY(scratch(&mdefl, nmid));
             DIAF_TRY(scratch(&mndef, 1));
+            DIAF_TRY(scratch(&mcols, nmid));
+            DIAF_TRY(scratch(&msorted, nmid));
             DIAF_HIP_TRY(hipMemsetAsync(mndef, 0, sizeof(int32_t), st));
+            int moff = 0;
             for (const Seg& g : segs) {
-                const int kcap = cc.kcap[g.c], tcap = cc.tcap[g.c];
-                if (!mid_supports<T>(kcap, tcap)) {
+                if (!mid_supports<T>(cc.kcap[g.c], cc.tcap[g.c])) {
                     rest.push_back(g);
                     continue;
                 }
-                fa.cols = g.cols;
-                fa.ncols = g.count;
+                DIAF_HIP_TRY(hipMemcpyAsync(mcols + moff, g.cols, sizeof(int32_t) * g.count,
+                                            hipMemcpyDeviceToDevice, st));
+                moff += g.count;
+            }
+            ColumnClasses mcc{};
+            mcc.ncls = mid_classes<T>(mcc.kcap, mcc.tcap);
+            DIAF_TRY(launch_classify_columns(n, nmid, mcols, kd, td, mcc, msorted, dmeta, nullptr,
+                                             st));
+            int32_t mh[ColumnClasses::kMax + 1] = {};
+            DIAF_HIP_TRY(hipMemcpyAsync(mh, dmeta, sizeof(int32_t) * (mcc.ncls + 1),
+                                        hipMemcpyDeviceToHost, st));
+            DIAF_TRY(sync(st));
+            if (mh[mcc.ncls] != 0) return {DIAF_EINVAL, "internal: mid-size column classes"};
+            int mo = 0;
+            for (int c = 0; c < mcc.ncls; ++c) {
+                if (mh[c] == 0) continue;
+                fa.cols = msorted + mo;
+                fa.ncols = mh[c];
+                mo += mh[c];
+                const int kcap = mcc.kcap[c], tcap = mcc.tcap[c];
                 DIAF_TRY(timed(-2, [&] {
                     return launch_factor_mid<T>(fa, kcap, tcap, mdefl, mndef, ctx->ftune, st);
                 }));
@@ -1499,15 +1534,16 @@ Err gate_and_fallback(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, i
     DIAF_HIP_TRY(hipMemcpyAsync(bn.data(), F->bnorm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
     DIAF_HIP_TRY(hipMemcpyAsync(fl0.data(), F->flags, sizeof(uint32_t) * n, hipMemcpyDeviceToHost,
                                 st));
+    DevBlocks blocks;  // freed on every return path
     if (spec->gate_dom > 0.0) {
         double* domd = nullptr;
         DIAF_TRY(dmalloc(&domd, sizeof(double) * n));
+        blocks.keep(domd);
         DIAF_TRY(launch_col_dominance<T>(n, F->lmax, F->Vrows, (const T*)F->Vvals, F->lcount,
                                          domd, st));
         DIAF_HIP_TRY(hipMemcpyAsync(dom.data(), domd, sizeof(double) * n, hipMemcpyDeviceToHost,
                                     st));
         DIAF_TRY(sync(st));
-        dfree(domd);
     }
     DIAF_TRY(sync(st));
     std::vector<uint8_t> fb(n, 0);
@@ -1530,22 +1566,28 @@ Err gate_and_fallback(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, i
     int32_t *cnt = nullptr, *Jcp2 = nullptr, *Jri2 = nullptr;
     T* W2 = nullptr;
     DIAF_TRY(dmalloc(&fbd, n));
+    blocks.keep(fbd);
     DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (n + 1)));
+    blocks.keep(cnt);
     DIAF_TRY(dmalloc(&Jcp2, sizeof(int32_t) * (n + 1)));
+    blocks.keep(Jcp2);
     DIAF_HIP_TRY(hipMemcpyAsync(fbd, fb.data(), n, hipMemcpyHostToDevice, st));
     DIAF_TRY(launch_fallback_count(n, F->Jcp, Ccp, fbd, cnt, st));
     DIAF_TRY(exclusive_scan_i32(cnt, Jcp2, n, st));
     int32_t tot = 0;
     DIAF_TRY(read1(Jcp2 + n, &tot, st));
     DIAF_TRY(dmalloc(&Jri2, sizeof(int32_t) * (size_t)tot));
+    blocks.keep(Jri2);
     DIAF_TRY(dmalloc(&W2, sizeof(T) * (size_t)tot));
+    blocks.keep(W2);
     DIAF_TRY(launch_fallback_fill<T>(n, F->Jcp, F->Jri, (const T*)F->Wval, Ccp, Cri, fbd, Jcp2,
                                      Jri2, W2, F->flags, st));
     DIAF_TRY(sync(st));
     dfree(F->Jcp); dfree(F->Jri); dfree(F->Wval);
     F->Jcp = Jcp2; F->Jri = Jri2; F->Wval = W2; F->nnzW = tot;
-    dfree(fbd);
-    dfree(cnt);
+    blocks.release(Jcp2);  // now owned by the factors
+    blocks.release(Jri2);
+    blocks.release(W2);
     DIAF_TRY(factor_columns<T>(ctx, A, spec, mode, F, &list, nullptr));
     // the refactor rewrote the flags of these columns: mark them again
     std::vector<uint32_t> fl(n);
@@ -1780,11 +1822,15 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         }
     }
     // CSR copy of A
+    DevBlocks blocks;  // everything below is freed on every return path
     int32_t *rp = nullptr, *ci = nullptr;
     T* cv = nullptr;
     DIAF_TRY(dmalloc(&rp, sizeof(int32_t) * (n + 1)));
+    blocks.keep(rp);
     DIAF_TRY(dmalloc(&ci, sizeof(int32_t) * (size_t)A->nnz));
+    blocks.keep(ci);
     DIAF_TRY(dmalloc(&cv, sizeof(T) * (size_t)A->nnz));
+    blocks.keep(cv);
     DIAF_TRY(csc_to_csr<T>(n, A->nnz, A->colptr, A->rowidx, (const T*)A->val, rp, ci, cv, st));
     // work vectors
     BicgVecs<T> V{};
@@ -1793,11 +1839,14 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     V.x = x;
     T* buf = nullptr;
     DIAF_TRY(dmalloc(&buf, sizeof(T) * (size_t)n * 8));
+    blocks.keep(buf);
     V.r = buf; V.rh = buf + n; V.p = buf + 2 * (size_t)n; V.v = buf + 3 * (size_t)n;
     V.ph = buf + 4 * (size_t)n; V.s = buf + 5 * (size_t)n; V.sh = buf + 6 * (size_t)n;
     V.t = buf + 7 * (size_t)n;
     DIAF_TRY(dmalloc(&V.partial, sizeof(double) * 4 * 1024));
+    blocks.keep(V.partial);
     DIAF_TRY(dmalloc(&V.st, sizeof(BicgState<T>)));
+    blocks.keep(V.st);
     DIAF_HIP_TRY(hipMemsetAsync(V.st, 0, sizeof(BicgState<T>), st));
     const int32_t* done = &V.st->done;
     // Left preconditioning: BiCGSTAB on M A x = M b (the preconditioned
@@ -1898,7 +1947,6 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     info->relres = hs.res;
     info->relres_true = hs.tt;
     info->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    dfree(rp); dfree(ci); dfree(cv); dfree(buf); dfree(V.partial); dfree(V.st);
     return {};
 }
 

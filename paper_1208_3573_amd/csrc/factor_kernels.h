@@ -85,6 +85,10 @@ Err launch_factor_small(const FactorArgs<T>& A, int* deferred, int* ndeferred, F
 // deferred.  kcap, tcap: the size class of the launch.
 template <class T>
 bool mid_supports(int kcap, int tcap);
+// The mid-size kernel's own size classes (capacities in |J_j| and gathered
+// entries, at most ColumnClasses::kMax); returns their number.
+template <class T>
+int mid_classes(int* kcap, int* tcap);
 template <class T>
 Err launch_factor_mid(const FactorArgs<T>& A, int kcap, int tcap, int* deferred, int* ndeferred,
                       FactorTune tune, hipStream_t st);

@@ -31,9 +31,8 @@
 namespace diaf {
 namespace mid {
 
-constexpr int ML = 8;     // max |L_j|
+constexpr int ML = 8;     // max |L_j| (and right-hand sides of a solve)
 constexpr int MSW = 4;    // 64-bit words of a column's shared-row mask (256 shared rows)
-constexpr int NRHS = ML;  // right-hand sides of the final solve
 
 template <class T>
 __device__ inline T shfl(T v, int src)
@@ -87,21 +86,26 @@ struct MidLds {
     uint16_t rptr[MT + 1];   // CSR row starts
     uint16_t csr[MT];        // entry ids, row by row, ascending within a row
     uint16_t sidx[MT];       // shared-row index of a local row, 0xffff if single
+    uint16_t she[MT];        // each column's entries in shared rows, in A's row order
+    uint16_t soff[MK + 1];   // start of each column's list in she
+    // storage reused by phase: the hash table (steps 2-4), the Gram matrix
+    // and its Cholesky factor (steps 5-8), then the last step's vectors
     union {
         struct {
-            int key[HS];         // hash keys (global rows), -1 empty
-            uint16_t loc[HS];    // slot -> local row
+            int key[HS];  // hash keys (global rows), -1 empty; then each
+                          // occupied slot's local row; then row counters
         } h;
+        T G[MK * (MK + 1) / 2];  // packed lower triangle
         struct {
-            T y[MT];             // per-row values (the seed's scores)
-        } p;
+            T P[ML * ML];        // power of H being squared
+            T v[ML];
+            T w[MK];
+        } f;
     };
-    uint64_t cmask[MK][MSW];  // each column's shared rows (bit = shared index)
-    T G[MK * (MK + 1) / 2];   // Gram matrix, then its Cholesky factor (packed lower)
-    T X[MK][NRHS + 1];        // right-hand sides and solutions (column 0: the seed)
-    T P[ML * ML];             // power of H being squared
-    T v[ML];
-    T w[MK];
+    union {
+        uint64_t cmask[MK][MSW];  // each column's shared rows (step 5)
+        T X[MK][ML];              // right-hand sides and solutions (steps 7-8)
+    };
     int L[ML];
 };
 
@@ -159,16 +163,16 @@ __device__ bool top_eig8(T h, int l, int hs, int ht, int lane, T* P, T* out)
 template <class T, int MK, int MT>
 __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
 {
-    T x[NRHS + 1];
+    T x[ML];
 #pragma unroll
-    for (int t = 0; t <= NRHS; ++t)
+    for (int t = 0; t < ML; ++t)
         x[t] = (lane < k && t < nr) ? S.X[lane][t] : num<T>::zero();
     for (int p = 0; p < k; ++p) {
         const double d = num<T>::re(S.G[ltri(p, p)]);
         const double inv = d > 0.0 ? 1.0 / d : 0.0;
         const T lip = (lane > p && lane < k) ? S.G[ltri(lane, p)] : num<T>::zero();
 #pragma unroll
-        for (int t = 0; t <= NRHS; ++t) {
+        for (int t = 0; t < ML; ++t) {
             if (t >= nr) break;
             const T zp = num<T>::mk(inv) * shfl(x[t], p);
             if (lane == p) x[t] = zp;
@@ -181,7 +185,7 @@ __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
         // conj(L(p, i)) for the lanes i < p: row p of L, contiguous
         const T lpi = lane < p ? num<T>::conj(S.G[ltri(p, lane)]) : num<T>::zero();
 #pragma unroll
-        for (int t = 0; t <= NRHS; ++t) {
+        for (int t = 0; t < ML; ++t) {
             if (t >= nr) break;
             const T xp = num<T>::mk(inv) * shfl(x[t], p);
             if (lane == p) x[t] = xp;
@@ -189,7 +193,7 @@ __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
         }
     }
 #pragma unroll
-    for (int t = 0; t <= NRHS; ++t)
+    for (int t = 0; t < ML; ++t)
         if (lane < k && t < nr) S.X[lane][t] = x[t];
     __syncthreads();
 }
@@ -252,12 +256,12 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
         const bool occ = key != -1;
         const uint64_t msk = __ballot(occ);
         const int pos = m + __popcll(msk & ((1ull << lane) - 1ull));
-        if (occ) { S.R[pos] = key; S.h.loc[s] = (uint16_t)pos; }
+        if (occ) { S.R[pos] = key; S.h.key[s] = pos; }
         m += __popcll(msk);
     }
     __syncthreads();
     // m <= Tn <= MT: every row came from an entry
-    for (int t = lane; t < Tn; t += 64) S.eloc[t] = S.h.loc[S.eloc[t]];
+    for (int t = lane; t < Tn; t += 64) S.eloc[t] = (uint16_t)S.h.key[S.eloc[t]];
     for (int r = lane; r <= m; r += 64) S.rptr[r] = 0;
     int dj = -1;
     for (int r0 = 0; r0 < m; r0 += 64) {
@@ -332,24 +336,39 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
     }
     if (ms > 64 * MSW) { defer(); return; }
     // ---- 5. Gram matrix ----
+    // lane a < k walks column a's entries (ascending global row): its mask
+    // over the shared rows and its list of entries in shared rows
+    int ncs = 0;
     if (lane < k) {
+        uint64_t mk_[MSW] = {};
+        for (int t = S.off[lane]; t < S.off[lane + 1]; ++t) {
+            const int q = S.sidx[S.eloc[t]];
+            if (q != 0xffff) {
+                mk_[q >> 6] |= 1ull << (q & 63);
+                ++ncs;
+            }
+        }
 #pragma unroll
-        for (int wd = 0; wd < MSW; ++wd) S.cmask[lane][wd] = 0ull;
+        for (int wd = 0; wd < MSW; ++wd) S.cmask[lane][wd] = mk_[wd];
     }
-    __syncthreads();
-    for (int t = lane; t < Tn; t += 64) {
-        const int q = S.sidx[S.eloc[t]];
-        if (q != 0xffff)
-            atomicOr((unsigned long long*)&S.cmask[S.ecol[t]][q >> 6], 1ull << (q & 63));
+    {
+        const int incl = wave_incl_scan(ncs, lane);
+        if (lane < k) S.soff[lane] = (uint16_t)(incl - ncs);
+        if (lane == k - 1) S.soff[k] = (uint16_t)incl;
+        __syncthreads();
+        if (lane < k) {
+            int pos = incl - ncs;
+            for (int t = S.off[lane]; t < S.off[lane + 1]; ++t)
+                if (S.sidx[S.eloc[t]] != 0xffff) S.she[pos++] = (uint16_t)t;
+        }
     }
-    __syncthreads();
     T dg = num<T>::zero();
     if (lane < k)
         for (int t = S.off[lane]; t < S.off[lane + 1]; ++t)
             dg += num<T>::cmul(S.eval[t], S.eval[t]);
     const double maxd = wave_max(lane < k ? num<T>::re(dg) : 0.0);
+    __syncthreads();  // the hash table's storage becomes G
     if (lane < k) S.G[ltri(lane, lane)] = dg;
-    __syncthreads();
     {
         const int npair = k * (k - 1) / 2;
         for (int pi = lane; pi < npair; pi += 64) {
@@ -363,49 +382,54 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
 #pragma unroll
             for (int wd = 0; wd < MSW; ++wd) any |= S.cmask[a][wd] & S.cmask[b][wd];
             if (any) {
-                // the common rows in ascending global row (column a's order in
-                // A), so the sum does not depend on the local row ids
-                for (int e = S.off[a]; e < S.off[a + 1]; ++e) {
-                    const int r = S.eloc[e];
-                    const int q = S.sidx[r];
-                    if (q == 0xffff || !((S.cmask[b][q >> 6] >> (q & 63)) & 1ull)) continue;
-                    T vb = num<T>::zero();
-                    for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
-                        const int f = S.csr[pp];
-                        if (S.ecol[f] == b) vb = S.eval[f];
+                // merge of the two columns' shared entries by global row
+                // (ascending in both), so the sum does not depend on the
+                // local row ids
+                int ia = S.soff[a], ib = S.soff[b];
+                const int ea = S.soff[a + 1], eb = S.soff[b + 1];
+                while (ia < ea && ib < eb) {
+                    const int ta = S.she[ia], tb = S.she[ib];
+                    const int ra = S.R[S.eloc[ta]], rb = S.R[S.eloc[tb]];
+                    if (ra == rb) {
+                        acc += num<T>::cmul(S.eval[ta], S.eval[tb]);  // conj(B(r, a)) B(r, b)
+                        ++ia;
+                        ++ib;
+                    } else if (ra < rb) {
+                        ++ia;
+                    } else {
+                        ++ib;
                     }
-                    acc += num<T>::cmul(S.eval[e], vb);  // conj(B(r, a)) B(r, b)
                 }
             }
             S.G[ltri(a, b)] = acc;
         }
     }
     __syncthreads();
-    // ---- 6. Cholesky G = L L^*, one lane per row ----
+    // ---- 6. Cholesky G = L L^*, left-looking, one lane per row ----
+    // step p: every row i >= p takes G(i, p) - sum_{q<p} L(i, q) conj(L(p, q))
+    // (independent loads of its own row and of row p); row p's value is the
+    // pivot, the rows below divide by its square root
     uint32_t flags = 0;
     if (k > m) flags |= DIAF_FLAG_RANK_DEFICIENT;
     for (int p = 0; p < k; ++p) {
-        const double d = num<T>::re(S.G[ltri(p, p)]);
+        T sp = num<T>::zero();
+        if (lane >= p && lane < k) {
+            sp = S.G[ltri(lane, p)];
+            for (int q = 0; q < p; ++q)
+                sp -= S.G[ltri(lane, q)] * num<T>::conj(S.G[ltri(p, q)]);
+        }
+        const double d = num<T>::re(shfl(sp, p));
         if (!(d > 1e-14 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
         const double piv = (d > 1e-30 * maxd && isfinite(d)) ? sqrt(d) : 0.0;
         const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
-        T lip = num<T>::zero();
-        if (lane > p && lane < k) {
-            lip = num<T>::mk(inv) * S.G[ltri(lane, p)];
-            S.G[ltri(lane, p)] = lip;
-        }
-        __syncthreads();
         if (lane == p) S.G[ltri(p, p)] = num<T>::mk(piv);
-        if (lane > p && lane < k)
-            for (int q = p + 1; q <= lane; ++q)
-                S.G[ltri(lane, q)] -= lip * num<T>::conj(S.G[ltri(q, p)]);
+        else if (lane > p && lane < k) S.G[ltri(lane, p)] = num<T>::mk(inv) * sp;
         __syncthreads();
     }
     // ---- 7. V pattern ----
     const bool topk =
         A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_BLOCK;
     int l = 0;
-    double* sc = reinterpret_cast<double*>(S.p.y);  // scores, one per local row
     if (topk) {
         if (lane < k) S.X[lane][0] = num<T>::zero();
         __syncthreads();
@@ -417,22 +441,30 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
         chol_solve(S, k, 1, lane);  // w0 = G^{-1} b_j^*
         const int blo = A.vrule == V_TOPK_BLOCK ? A.vblk[2 * j] : 0;
         const int bhi = A.vrule == V_TOPK_BLOCK ? A.vblk[2 * j + 1] : 0;
+        // scores of this lane's rows r = lane + 64 i in registers (-1: not
+        // admissible)
+        constexpr int RPL = MT / 64;
+        double sc[RPL];
         int ncl = 0;
-        for (int r = lane; r < m; r += 64) {
-            const int gi = S.R[r];
-            const bool adm = A.vrule == V_TOPK_BLOCK ? (gi != j && gi >= blo && gi < bhi)
-                             : A.vrule == V_TOPK_LOWER ? gi > j : gi < j;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+            const int r = lane + 64 * i;
             double s = -1.0;
-            if (adm) {
-                T y = num<T>::zero();
-                for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
-                    const int e = S.csr[pp];
-                    y += S.eval[e] * S.X[S.ecol[e]][0];
+            if (r < m) {
+                const int gi = S.R[r];
+                const bool adm = A.vrule == V_TOPK_BLOCK ? (gi != j && gi >= blo && gi < bhi)
+                                 : A.vrule == V_TOPK_LOWER ? gi > j : gi < j;
+                if (adm) {
+                    T y = num<T>::zero();
+                    for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
+                        const int e = S.csr[pp];
+                        y += S.eval[e] * S.X[S.ecol[e]][0];
+                    }
+                    s = num<T>::abs(y);
+                    ++ncl;
                 }
-                s = num<T>::abs(y);
-                ++ncl;
             }
-            sc[r] = s;
+            sc[i] = s;
         }
         const int nc = (int)wave_sum((double)ncl);
         int lj = A.vcount < 1 ? 1 : A.vcount;
@@ -440,12 +472,12 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
         if (lj > lmax) lj = lmax;
         if (lj > ML) lj = ML;
         const int q = lj - 1;
-        __syncthreads();
-        // rows r = lane + 64 i of this lane: i < MT / 64 <= 16 bits
+        // bit i of these masks: row lane + 64 i
         uint32_t chosen = 0;
         if (q > 0 && nc <= q) {
-            for (int i = 0; lane + 64 * i < m; ++i)
-                if (sc[lane + 64 * i] >= 0.0) chosen |= 1u << i;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i)
+                if (sc[i] >= 0.0) chosen |= 1u << i;
         } else if (q > 0) {
             // the q-th largest score, counting equal scores separately
             uint32_t taken = 0;
@@ -453,10 +485,12 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
             for (int rd = 0; rd < q; ++rd) {
                 double best = -2.0;
                 int bi = -1;
-                for (int i = 0; lane + 64 * i < m; ++i) {
-                    const double s = sc[lane + 64 * i];
-                    if (s >= 0.0 && !((taken >> i) & 1u) && s > best) { best = s; bi = i; }
-                }
+#pragma unroll
+                for (int i = 0; i < RPL; ++i)
+                    if (sc[i] >= 0.0 && !((taken >> i) & 1u) && sc[i] > best) {
+                        best = sc[i];
+                        bi = i;
+                    }
                 const double mx = wave_max(best);
                 const uint64_t bm = __ballot(best == mx && bi >= 0);
                 if (lane == __ffsll((unsigned long long)bm) - 1) taken |= 1u << bi;
@@ -466,12 +500,13 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
             uint32_t tie = 0;
             int nin = 0;
             bool edge = false;
-            for (int i = 0; lane + 64 * i < m; ++i) {
-                const double s = sc[lane + 64 * i];
-                if (s < 0.0) continue;
-                if (s > hi) { chosen |= 1u << i; ++nin; }
-                else if (s >= lo) tie |= 1u << i;
-                if (ss > 0.0 && (fabs(s - hi) <= 1e-12 * ss || fabs(s - lo) <= 1e-12 * ss))
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const double sv = sc[i];
+                if (sv < 0.0) continue;
+                if (sv > hi) { chosen |= 1u << i; ++nin; }
+                else if (sv >= lo) tie |= 1u << i;
+                if (ss > 0.0 && (fabs(sv - hi) <= 1e-12 * ss || fabs(sv - lo) <= 1e-12 * ss))
                     edge = true;
             }
             if (__ballot(edge)) flags |= DIAF_FLAG_TIE_EDGE;
@@ -550,16 +585,17 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
                 h += S.eval[e] * S.X[S.ecol[e]][ht];
             }
         }
-        if (!top_eig8(h, l, hs, ht, lane, S.P, S.v)) flags |= DIAF_FLAG_GAP_DEGENERATE;
+        __syncthreads();  // G is dead: its storage holds P, v and w
+        if (!top_eig8(h, l, hs, ht, lane, S.f.P, S.f.v)) flags |= DIAF_FLAG_GAP_DEGENERATE;
     }
     if (lane < k) {
         T acc = num<T>::zero();
-        for (int t = 0; t < l; ++t) acc += S.X[lane][t] * S.v[t];
-        S.w[lane] = acc;
+        for (int t = 0; t < l; ++t) acc += S.X[lane][t] * S.f.v[t];
+        S.f.w[lane] = acc;
     }
     __syncthreads();
     // ---- 9. phase, residual, outputs ----
-    T vt = lane < l ? S.v[lane] : num<T>::zero();
+    T vt = lane < l ? S.f.v[lane] : num<T>::zero();
     const double vn = sqrt(wave_sum(lane < l ? num<T>::abs2(vt) : 0.0));
     const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
     const int dpos = dposm ? __ffsll((unsigned long long)dposm) - 1 : -1;
@@ -579,8 +615,8 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
     vt = ph * vt;
     if (dpos < 0 || num<T>::abs(shfl(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
         flags |= DIAF_FLAG_SMALL_DIAG;
-    if (lane < l) S.v[lane] = vt;
-    if (lane < k) S.w[lane] = ph * S.w[lane];
+    if (lane < l) S.f.v[lane] = vt;
+    if (lane < k) S.f.w[lane] = ph * S.f.w[lane];
     __syncthreads();
     // residual: each row is taken by the lane of its first entry, so the
     // order of the sum follows the entries, not the local row ids
@@ -591,20 +627,20 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
         T res = num<T>::zero();
         for (int pp = S.rptr[r]; pp < S.rptr[r + 1]; ++pp) {
             const int e = S.csr[pp];
-            res += S.eval[e] * S.w[S.ecol[e]];
+            res += S.eval[e] * S.f.w[S.ecol[e]];
         }
         for (int t = 0; t < l; ++t)
-            if (S.L[t] == r) res -= S.v[t];
+            if (S.L[t] == r) res -= S.f.v[t];
         r2 += num<T>::abs2(res);
     }
     r2 = wave_sum(r2);
-    if (lane < k) A.Wval[jb + lane] = S.w[lane];
+    if (lane < k) A.Wval[jb + lane] = S.f.w[lane];
     const int myg = lane < l ? S.R[S.L[lane]] : 0x7fffffff;
     int rank = 0;
     for (int t = 0; t < l; ++t) rank += S.R[S.L[t]] < myg;
     if (lane < l) {
         A.Vrows[(size_t)j * lmax + rank] = myg;
-        A.Vvals[(size_t)j * lmax + rank] = S.v[lane];
+        A.Vvals[(size_t)j * lmax + rank] = S.f.v[lane];
     } else if (lane < lmax) {
         A.Vrows[(size_t)j * lmax + lane] = -1;
         A.Vvals[(size_t)j * lmax + lane] = num<T>::zero();
@@ -648,6 +684,17 @@ bool mid_supports(int kcap, int tcap)
     else return kcap <= 64 && tcap <= 1024;
 }
 
+template <class T>
+int mid_classes(int* kcap, int* tcap)
+{
+    // capacities of the kernel instances, smallest LDS first (a column takes
+    // the first that holds it)
+    static const int cls[][2] = {{32, 256}, {32, 512}, {64, 512}, {32, 1024}, {64, 1024}};
+    const int nc = num<T>::is_complex ? 1 : 5;
+    for (int c = 0; c < nc; ++c) { kcap[c] = cls[c][0]; tcap[c] = cls[c][1]; }
+    return nc;
+}
+
 template <class T, int MK, int MT>
 static Err launch_mid_t(const FactorArgs<T>& A, int* deferred, int* ndeferred, int grid,
                         hipStream_t st)
@@ -668,7 +715,9 @@ Err launch_factor_mid(const FactorArgs<T>& A, int kcap, int tcap, int* deferred,
     const int grid = A.ncols < want ? A.ncols : want;
     if (kcap <= 32 && tcap <= 256) return launch_mid_t<T, 32, 256>(A, deferred, ndeferred, grid, st);
     if constexpr (!num<T>::is_complex) {
+        if (kcap <= 32 && tcap <= 512) return launch_mid_t<T, 32, 512>(A, deferred, ndeferred, grid, st);
         if (tcap <= 512) return launch_mid_t<T, 64, 512>(A, deferred, ndeferred, grid, st);
+        if (kcap <= 32) return launch_mid_t<T, 32, 1024>(A, deferred, ndeferred, grid, st);
         return launch_mid_t<T, 64, 1024>(A, deferred, ndeferred, grid, st);
     }
     return {DIAF_EINVAL, "mid kernel: size class too large"};
@@ -681,7 +730,9 @@ double mid_occupancy(int kcap, int tcap)
     const void* k = nullptr;
     if (kcap <= 32 && tcap <= 256) k = (const void*)mid::factor_mid_kernel<T, 32, 256>;
     if constexpr (!num<T>::is_complex) {
+        if (!k && kcap <= 32 && tcap <= 512) k = (const void*)mid::factor_mid_kernel<T, 32, 512>;
         if (!k && tcap <= 512) k = (const void*)mid::factor_mid_kernel<T, 64, 512>;
+        if (!k && kcap <= 32) k = (const void*)mid::factor_mid_kernel<T, 32, 1024>;
         if (!k) k = (const void*)mid::factor_mid_kernel<T, 64, 1024>;
     }
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0) != hipSuccess) return 0.0;
@@ -690,6 +741,8 @@ double mid_occupancy(int kcap, int tcap)
 
 template bool mid_supports<double>(int, int);
 template bool mid_supports<zc>(int, int);
+template int mid_classes<double>(int*, int*);
+template int mid_classes<zc>(int*, int*);
 template Err launch_factor_mid<double>(const FactorArgs<double>&, int, int, int*, int*, FactorTune,
                                        hipStream_t);
 template Err launch_factor_mid<zc>(const FactorArgs<zc>&, int, int, int*, int*, FactorTune,

@@ -36,8 +36,8 @@ def test_library_exports_every_declared_symbol():
                          text=True, check=True).stdout
     exported = set(re.findall(r"\bT (diaf_\w+)", out))
     assert set(declared_functions()) <= exported
-    # the binding marshals exactly the declared API (plus the copy helper)
-    assert set(diaf.EXPORTED) == set(declared_functions()) | {"diaf_copy"}
+    # the binding marshals exactly the declared API
+    assert set(diaf.EXPORTED) == set(declared_functions())
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
