@@ -36,8 +36,21 @@ TRAIN_SEED0 = 5000
 LABEL_TAU = {"unit_v": 0.03, "unit_w": 0.01}
 
 
-def weights_path(mode: str) -> str:
-    return os.path.join(WEIGHTS_DIR, f"mlp_convdiff48_{mode}.npz")
+def weights_path(mode: str, vrule: str = "topk_lower") -> str:
+    sfx = "" if vrule == "topk_lower" else f"_{vrule}"
+    return os.path.join(WEIGHTS_DIR, f"mlp_convdiff48_{mode}{sfx}.npz")
+
+
+def plain_spec(vrule: str, n: int, N: int):
+    """The plain factorization's spec on an N^3 grid problem: W =
+    pattern(A^2) and V = diagonal + top-4 lower rows (topk_lower), or the
+    block diagonal V whose blocks are the grid's x-lines (block: the pattern
+    of D, Section 5's splitting)."""
+    if vrule == "block":
+        import torch
+        vb = torch.arange(0, n + 1, N, dtype=torch.int32, device="cuda")
+        return diaf.make_spec(w="A2", v="block", v_blocks=vb), vb
+    return diaf.make_spec(w="A2", v=vrule, v_count=5), None
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -80,7 +93,8 @@ def gates_from(qs, doms):
 
 
 def build_training_set(ctx, mode: str, n_instances: int, N: int = TRAIN_N, log=print,
-                       with_data: bool = True, label_tau: float | None = None):
+                       with_data: bool = True, label_tau: float | None = None,
+                       vrule: str = "topk_lower"):
     """Features and labels of n_instances seeded problems, kept on the GPU,
     and the gates calibrated on the plain factorizations."""
     import torch
@@ -92,7 +106,8 @@ def build_training_set(ctx, mode: str, n_instances: int, N: int = TRAIN_N, log=p
     for t in range(n_instances):
         A = synth.convdiff(N, 3, TRAIN_SEED0 + t)
         dA = diaf.DeviceCSC.from_host(A)
-        F = diaf.diaf_factor(ctx, dA, diaf.make_spec(w="A2", v="topk_lower", v_count=5), mode)
+        spec, _vb = plain_spec(vrule, A.n, N)
+        F = diaf.diaf_factor(ctx, dA, spec, mode)
         H = F.to_host()
         s = np.ones(A.n) if mode == "unit_v" else _block_fro(A, H["Wcp"], H["Wri"])
         qs.append(H["r"] / s)
@@ -114,9 +129,9 @@ def build_training_set(ctx, mode: str, n_instances: int, N: int = TRAIN_N, log=p
 
 
 def train(ctx, mode: str, n_instances: int = 100, epochs: int = 8, lr: float = 3e-3,
-          seed: int = 0, log=print, label_tau: float | None = None):
+          seed: int = 0, log=print, label_tau: float | None = None, vrule: str = "topk_lower"):
     data, gate, gate_dom = build_training_set(ctx, mode, n_instances, log=log,
-                                              label_tau=label_tau)
+                                              label_tau=label_tau, vrule=vrule)
     model = diaf.Model(ctx, init_params(seed))
     rng = np.random.default_rng(seed)
     hist = []
@@ -134,11 +149,13 @@ def train(ctx, mode: str, n_instances: int = 100, epochs: int = 8, lr: float = 3
     return model, gate, gate_dom, hist
 
 
-def save(model, gate, gate_dom, mode, path, hist=()):
+def save(model, gate, gate_dom, mode, path, hist=(), label_tau=None, vrule="topk_lower"):
     os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
     np.savez(path, params=model.params(), gate_tau=np.float64(gate),
              gate_dom=np.float64(gate_dom), mode=mode,
-             loss_history=np.asarray(hist, dtype=np.float64))
+             loss_history=np.asarray(hist, dtype=np.float64),
+             label_tau=np.float64(LABEL_TAU[mode] if label_tau is None else label_tau),
+             vrule=vrule)
 
 
 def load(ctx, path):
@@ -147,13 +164,15 @@ def load(ctx, path):
     return diaf.Model(ctx, z["params"]), float(z["gate_tau"]), float(z["gate_dom"])
 
 
-def load_or_train(ctx, mode: str, log=print, n_instances: int = 100):
-    path = weights_path(mode)
+def load_or_train(ctx, mode: str, log=print, n_instances: int = 100, vrule: str = "topk_lower",
+                  label_tau: float | None = None):
+    path = weights_path(mode, vrule)
     if os.path.exists(path):
         log(f"  loading {path}")
         return load(ctx, path)
-    model, gate, gate_dom, hist = train(ctx, mode, n_instances=n_instances, log=log)
-    save(model, gate, gate_dom, mode, path, hist)
+    model, gate, gate_dom, hist = train(ctx, mode, n_instances=n_instances, log=log,
+                                        vrule=vrule, label_tau=label_tau)
+    save(model, gate, gate_dom, mode, path, hist, label_tau, vrule)
     return model, gate, gate_dom
 
 
@@ -178,15 +197,17 @@ def main():
                     help="dropping tolerance of the labels (default: per mode)")
     ap.add_argument("--recalibrate", action="store_true",
                     help="only recompute the gates of an existing weights file")
+    ap.add_argument("--vrule", default="topk_lower", choices=["topk_lower", "block"],
+                    help="V rule of the plain factorizations that give the labels")
     args = ap.parse_args()
     ctx = diaf.Context(0)
-    path = args.out or weights_path(args.mode)
+    path = args.out or weights_path(args.mode, args.vrule)
     if args.recalibrate:
         recalibrate(ctx, args.mode, path, args.instances)
         return
     model, gate, gate_dom, hist = train(ctx, args.mode, args.instances, args.epochs,
-                                        label_tau=args.label_tau)
-    save(model, gate, gate_dom, args.mode, path, hist)
+                                        label_tau=args.label_tau, vrule=args.vrule)
+    save(model, gate, gate_dom, args.mode, path, hist, args.label_tau, args.vrule)
 
 
 if __name__ == "__main__":

@@ -292,3 +292,52 @@ def test_adam_steps_match_reference(ctx):
         assert np.all(err <= bound), (step, float(np.max(err - bound)))
         th = got  # continue from the GPU's parameters (FP32)
     m.close()
+
+
+def test_learned_gain_with_block_v(ctx):
+    """What the trained network gains, on the held-out 64^3 workload (the
+    training set is 48^3, seeds from 5000): second basic algorithm, V block
+    diagonal on the x-lines, BiCGSTAB to 1e-8 for each W.  The network
+    trained on labels at dropping tolerance 0.1 proposes, with no gate, a W
+    less than half as dense as pattern(A^2) that still converges; it is
+    compared, and its time reported, against plain pattern(A^2) and plain
+    pattern(A).  On this workload its proposal is pattern(A) itself, so it
+    gains the sparser pattern over pattern(A^2) and loses the inference time
+    against pattern(A)."""
+    import time
+    import torch
+    from paper_1208_3573_amd import diaf
+    from paper_1208_3573_amd import learned as LR
+    A = synth.workload_matrix("convdiff3d_64")
+    dA = diaf.DeviceCSC.from_host(A)
+    b = torch.from_numpy(synth.rhs_ones(A)).cuda()
+    x = torch.zeros_like(b)
+    vb = torch.arange(0, A.n + 1, 64, dtype=torch.int32, device="cuda")
+    model, _gate, _gdom = LR.load(ctx, LR.weights_path("unit_w", "block"))
+
+    def run(spec):
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            F = diaf.diaf_factor(ctx, dA, spec, "unit_w")
+            info = diaf.diaf_solve(ctx, dA, F, b, x, 1e-8, 1000)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            H = F.to_host()
+            F.close()
+            best = ms if best is None else min(best, ms)
+        return best, info, H
+
+    t2, i2, H2 = run(diaf.make_spec(w="A2", v="block", v_blocks=vb))
+    t1, i1, H1 = run(diaf.make_spec(w="A", v="block", v_blocks=vb))
+    tl, il, HL = run(diaf.make_spec(w="learned", v="block", v_blocks=vb, model=model))
+    model.close()
+    for info in (i2, i1, il):
+        assert info.flag == 0 and info.relres_true <= 1e-7
+    assert len(HL["Wri"]) <= 0.5 * len(H2["Wri"])
+    same_as_A = (np.array_equal(HL["Wcp"], H1["Wcp"]) and np.array_equal(HL["Wri"], H1["Wri"]))
+    say(f"64^3 unit w, block V: pattern(A^2) {t2:.1f} ms / {i2.iters} its / nnz {len(H2['Wri'])}; "
+        f"pattern(A) {t1:.1f} ms / {i1.iters} its / nnz {len(H1['Wri'])}; learned {tl:.1f} ms / "
+        f"{il.iters} its / nnz {len(HL['Wri'])} (pattern(A): {same_as_A}); gain over "
+        f"pattern(A^2) {t2 - tl:+.1f} ms, over pattern(A) {t1 - tl:+.1f} ms")
