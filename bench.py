@@ -198,10 +198,14 @@ def cpu_baseline(A, J, mode, v, l, upper, b, solve, runs=3, sample_all=None, sam
                 factor_cols_per_s_1core=one, iters=its)
 
 
-CLASS_CAPS = [(16, 128), (32, 256), (64, 512), (64, 1024), (128, 2048), (256, 4096), (256, 8192)]
+def class_caps(st):
+    """(|J_j|, gathered entries) capacities of the size classes the factoring
+    pass used (the context's class table)."""
+    return [(int(st.class_kcap[q]), int(st.class_tcap[q])) for q in range(8)
+            if st.class_kcap[q] > 0]
 
 
-def column_stats(A, Jcp, Jri, lcount, mode, sv):
+def column_stats(A, Jcp, Jri, lcount, mode, sv, caps):
     """Per column: algorithmic bytes and flops (as algorithmic_bytes and
     algorithmic_flops count them), |J_j|, gathered entries and the shadow
     size m_j, from the symbolic product pattern(A) pattern(J)."""
@@ -228,26 +232,29 @@ def column_stats(A, Jcp, Jri, lcount, mode, sv):
     else:
         fl = gram + 2 * lf * kf ** 2 + 84 * kf ** 3 + 2 * nnzb
     fl = fl * (4.0 if A.is_complex else 1.0)
-    cls = np.full(n, len(CLASS_CAPS))
-    for q in range(len(CLASS_CAPS) - 1, -1, -1):
-        cls[(k <= CLASS_CAPS[q][0]) & (t <= CLASS_CAPS[q][1])] = q
-    return dict(bytes=byt, flops=fl, k=k, t=t, m=m, cls=cls, shared=shared)
+    cls = np.full(n, len(caps))
+    for q in range(len(caps) - 1, -1, -1):
+        cls[(k <= caps[q][0]) & (t <= caps[q][1])] = q
+    return dict(bytes=byt, flops=fl, k=k, t=t, m=m, cls=cls, shared=shared, caps=caps)
 
 
 def kernel_rooflines(cs, st, flags, mode, lmax, steps_factor, is_complex=False):
     """Per factor kernel: the columns it finished (the one-wave kernel keeps
-    the columns of classes 0-1 with a shadow of at most 64 rows, and for
-    unit-norm w those whose block is not rank deficient; for unit-norm v the
-    mid-size kernel takes the other columns of classes 0-3 (complex: 0-1)
-    with at most 256 rows of two or more entries; the generic kernel takes
+    the columns with |J_j| <= 32, at most 256 gathered entries and a shadow
+    of at most 64 rows, and for unit-norm w those whose block is not rank
+    deficient; for unit-norm v the mid-size kernel takes the other columns
+    with |J_j| <= 64 and at most 1024 gathered entries (complex: 32, 256)
+    and at most 256 rows of two or more entries; the generic kernel takes
     the rest, per size class), their algorithmic bytes and flops, its device
     time per pass, and the fractions of the HBM and FP64 peaks."""
-    small = (cs["cls"] <= 1) & (cs["m"] <= 64) & (lmax <= 8)
+    k, t = cs["k"], cs["t"]
+    small = (k <= 32) & (t <= 256) & (cs["m"] <= 64) & (lmax <= 8)
     if mode == "unit_w":
         small &= (flags & 1) == 0
     mid = np.zeros_like(small)
     if st.launches_mid:
-        mid = ~small & (cs["cls"] <= (1 if is_complex else 3)) & (cs["shared"] <= 256)
+        mk, mt = (32, 256) if is_complex else (64, 1024)
+        mid = ~small & (k <= mk) & (t <= mt) & (cs["shared"] <= 256)
     out = {}
     if st.launches_mid:
         ms_mid = st.ms_mid_kernel / steps_factor
@@ -273,13 +280,13 @@ def kernel_rooflines(cs, st, flags, mode, lmax, steps_factor, is_complex=False):
     ms_gen = sum(st.ms_generic_class[q] for q in range(8)) / steps_factor
     if ms_gen > 0:
         per = {}
-        for q in range(len(CLASS_CAPS)):
+        for q in range(len(cs["caps"])):
             if not st.launches_generic_class[q]:
                 continue
             sel = gen & (cs["cls"] == q)
             msq = st.ms_generic_class[q] / steps_factor
             bq = float(cs["bytes"][sel].sum())
-            per[str(q)] = dict(caps=CLASS_CAPS[q], cols=int(sel.sum()),
+            per[str(q)] = dict(caps=cs["caps"][q], cols=int(sel.sum()),
                                cols_reported=int(st.cols_generic_class[q] / steps_factor),
                                ms=msq, gbs=bq / (msq * 1e-3) / 1e9,
                                waves_per_simd=st.occ_generic_class[q])
@@ -298,6 +305,55 @@ def density(H, nnzA):
     reports with its tables; a triangular V is its own LU factor, so the V
     part is nnz(V)."""
     return (len(H["Wri"]) + len(H["Vri"])) / nnzA
+
+
+def learned_block_comparison(ctx, dA, db, x, n, steps, warmup, LR, diaf, torch):
+    """Second basic algorithm (unit-norm w) with V block diagonal on the
+    grid's x-lines (64-row blocks): plain pattern(A^2), plain pattern(A),
+    the network trained on labels at dropping tolerance 0.1 with no gate
+    and with its calibrated gates, and the 1-hop top-p rule at the learned
+    mean |J_j| (p = mean |J_j| - 7 beyond pattern(A)).  Same tolerance 1e-8
+    for all; medians over the timed steps."""
+    N = round(n ** (1.0 / 3.0))
+    vb = torch.arange(0, n + 1, N, dtype=torch.int32, device="cuda")
+    model, gate, gate_dom = LR.load(ctx, LR.weights_path("unit_w", "block"))
+
+    def run(spec_):
+        rec = []
+        for it in range(warmup + steps):
+            t0 = time.perf_counter()
+            F = diaf.diaf_factor(ctx, dA, spec_, "unit_w")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            info = diaf.diaf_solve(ctx, dA, F, db, x, 1e-8, 1000)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            st = F.stats()
+            if it >= warmup:
+                rec.append(((t1 - t0) * 1e3, (t2 - t1) * 1e3, st.ms_factor_kernels))
+            F.close()
+        R = np.median(np.array(rec), axis=0)
+        return {"factor_ms": float(R[0]), "solve_ms": float(R[1]), "e2e_ms": float(R[0] + R[1]),
+                "factor_kernel_ms": float(R[2]), "bicgstab_iters": int(info.iters),
+                "flag": int(info.flag), "relres_true": float(info.relres_true),
+                "nnz_w": int(st.nnz_w), "fell_back": int(st.count_fell_back)}
+
+    res = {"plain_A2": run(diaf.make_spec(w="A2", v="block", v_blocks=vb)),
+           "plain_A": run(diaf.make_spec(w="A", v="block", v_blocks=vb))}
+    res["learned_ungated"] = run(diaf.make_spec(w="learned", v="block", v_blocks=vb,
+                                                model=model))
+    res["learned_gated"] = run(diaf.make_spec(w="learned", v="block", v_blocks=vb, model=model,
+                                              gate_tau=gate, gate_dom=gate_dom))
+    p = max(0, int(round(res["learned_ungated"]["nnz_w"] / n - 7)))
+    res["ablation_1hop"] = run(diaf.make_spec(w="A_1hop_topk", w_topk=p, v="block",
+                                              v_blocks=vb)) | {"p": p}
+    res |= {"label_tau": 0.1, "gate_tau": gate, "gate_dom": gate_dom}
+    model.close()
+    for k, v in res.items():
+        if isinstance(v, dict):
+            log(f"learned unit_w block: {k}: e2e {v['e2e_ms']:.1f} ms, "
+                f"{v['bicgstab_iters']} its, nnz(W) {v['nnz_w']}, fell back {v['fell_back']}")
+    return res
 
 
 def main():
@@ -407,7 +463,7 @@ def main():
     achieved = bytes_alg / (kern_ms * 1e-3) / 1e9
     flops_alg = algorithmic_flops(A, H["Wcp"], H["Wri"], H["lcount"], args.mode)
     tflops = flops_alg / (kern_ms * 1e-3) / 1e12
-    cs = column_stats(A, H["Wcp"], H["Wri"], H["lcount"], args.mode, sv)
+    cs = column_stats(A, H["Wcp"], H["Wri"], H["lcount"], args.mode, sv, class_caps(st))
     kr = kernel_rooflines(cs, st, H["flags"], args.mode, int(H["lcount"].max()), 1,
                           A.is_complex)
     # the dominant factor kernel of the pass and its roofline
@@ -494,6 +550,8 @@ def main():
                         "e2e_ms": factor_ms + solve_ms, "bicgstab_iters": iters,
                         "nnz_w": int(len(H["Wri"])), "v_levels": int(levels)}
         model.close()
+        out["learned_unit_w_block"] = learned_block_comparison(
+            ctx, dA, db, x, A.n, args.steps, args.warmup, LR, diaf, torch)
 
     if not solves and args.solve_maxit > 0:
         F, _, info, fms, sms = step(spec, solve=True, maxit=args.solve_maxit)

@@ -245,9 +245,10 @@ typedef struct diaf_stats {
     /* Device time and columns per factor kernel, summed over the factoring
      * passes of these factors (the fallback pass of a learned pattern
      * included): the one-wave kernel (the columns it finished, not those it
-     * handed on), and the generic kernel per size class, classes 0..6 holding
-     * |J_j| <= 16/32/64/64/128/256/256 and gathered entries <= 128/256/512/
-     * 1024/2048/4096/8192 (class 7 unused). */
+     * handed on), and the generic kernel per size class (the capacities of
+     * class c are class_kcap[c] and class_tcap[c] below; with the default
+     * table, classes 0..6 hold |J_j| <= 16/32/64/64/128/256/256 and gathered
+     * entries <= 128/256/512/1024/2048/4096/8192). */
     double ms_small_kernel;
     double ms_generic_class[8];
     int32_t cols_small;
@@ -265,6 +266,10 @@ typedef struct diaf_stats {
     int32_t cols_mid;
     int32_t launches_mid;
     double occ_mid;
+    /* Capacities (|J_j|, gathered entries) of the size classes of the last
+     * factoring pass (the context option "class_table"); 0 past the last. */
+    int32_t class_kcap[8];
+    int32_t class_tcap[8];
 } diaf_stats;
 
 typedef struct diaf_solve_info {
@@ -298,8 +303,14 @@ const char* diaf_last_error(const struct diaf_ctx* ctx);
  * NULL buffer with bytes > 0), DIAF_EDEVICE. */
 diaf_status diaf_copy(struct diaf_ctx* ctx, void* dst, const void* src, size_t bytes);
 /* Tunables of the context (not of the method: results are identical for
- * every setting).  Keys:
+ * every setting of the launch shapes; "generic_only" and "mid" route columns
+ * to another kernel of the same method, whose results agree to rounding).
+ * Keys:
  *   "generic_only"       1: every column goes to the generic factor kernel
+ *   "mid"                0: no mid-size one-wave kernel (unit-norm v columns
+ *                        with shadows beyond 64 rows go to the generic kernel)
+ *   "class_table"        size classes of the factor launches (0 default, 0..3;
+ *                        every table sends the same columns to each kernel)
  *   "small_grid"         workgroups of the one-wave factor kernel (0 = 4096)
  *   "generic_nt"         threads per column of the generic kernel (0 auto, 64,
  *                        128, 256, 512)
@@ -321,13 +332,24 @@ diaf_status diaf_ctx_get_option(const struct diaf_ctx* ctx, const char* key, int
 
 /* Autotuner for the batched factoring and the solve: times the candidate
  * launch shapes on this problem (A, spec, mode, as for diaf_factor) and keeps
- * the fastest in ctx: "small_grid" (1024 ... 16384), "generic_nt" (when
- * generic buckets occur), then "graph", "solve_batch" and "trsv_backoff" by
- * the wall time per iteration of 32-iteration solves with b = ones.  Runs
- * about a dozen factorizations and solves; blocks until done.  Leaves the
- * method's results unchanged. */
+ * the fastest in ctx: "small_grid" (1024 ... 16384), "class_table" and
+ * "generic_nt" (when generic buckets occur), "trsv_waves", then "graph",
+ * "solve_batch" and "trsv_backoff" by the wall time per iteration of
+ * 32-iteration solves with b = ones.  Runs a few dozen factorizations and
+ * solves; blocks until done.  Leaves the method's results unchanged. */
 diaf_status diaf_autotune(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
                           int32_t mode);
+/* diaf_autotune with a persistent store: `path` names a JSON file (one object
+ * per line) keyed by the device architecture (gcnArchName) and the problem's
+ * shape (mode, dtype, n, nnz, W and V kinds and counts, left, FP32 Gram).  A
+ * stored entry for this key is applied to ctx without timing anything
+ * (*from_cache = 1); otherwise diaf_autotune runs and its choice is added to
+ * the file (*from_cache = 0), written to path + ".tmp" and renamed.  A missing
+ * file counts as empty.  Errors: DIAF_EINVAL for a file that is not in this
+ * format (it is left untouched) or cannot be written, and those of
+ * diaf_autotune.  Concurrent writers of one file: the last rename wins. */
+diaf_status diaf_autotune_cached(struct diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
+                                 int32_t mode, const char* path, int32_t* from_cache);
 
 /* ---- patterns (Section 4) ------------------------------------------------ */
 

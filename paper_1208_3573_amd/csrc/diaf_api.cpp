@@ -5,6 +5,10 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -28,6 +32,7 @@ struct diaf_ctx {
     int64_t opt_batch = 8;
     int64_t opt_gate_small_diag = 1;
     int64_t opt_graph = 0;
+    int64_t opt_class_table = 0;  // index into kClassTables
     diaf::TrsvTune trsv;
     diaf::FactorTune ftune;
     hipStream_t gstream = nullptr;  // library stream for captured solve batches
@@ -724,6 +729,26 @@ Err setup_blocks(const diaf_spec* spec, int n, diaf_factors* F, hipStream_t st)
 
 // Factor the listed columns (all columns when cols is empty) into F's
 // buffers, which must already be allocated.
+// Size classes (|J_j| capacity, gathered-entry capacity) of the factor
+// launches; a column takes the first class that holds it.  Every table has
+// (32, 256) and (64, 1024) among its classes, with the classes before each of
+// them inside it, so the columns that reach the one-wave and mid-size
+// kernels are the same for every table; the generic kernel's results do not
+// depend on the capacities either.  The autotuner picks the table.
+struct ClassTable {
+    int n;
+    int cap[ColumnClasses::kMax][2];
+};
+const ClassTable kClassTables[] = {
+    {7, {{16, 128}, {32, 256}, {64, 512}, {64, 1024}, {128, 2048}, {256, 4096}, {256, 8192}}},
+    {8, {{16, 128}, {32, 256}, {48, 512}, {64, 1024}, {96, 2048}, {128, 3072}, {192, 4096},
+         {256, 8192}}},
+    {4, {{32, 256}, {64, 1024}, {128, 4096}, {256, 8192}}},
+    {8, {{16, 128}, {32, 256}, {64, 512}, {64, 1024}, {128, 1536}, {128, 2048}, {192, 4096},
+         {256, 8192}}},
+};
+constexpr int kNumClassTables = (int)(sizeof(kClassTables) / sizeof(kClassTables[0]));
+
 template <class T>
 Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
                    diaf_factors* F, const std::vector<int32_t>* only, int* nbuckets)
@@ -742,12 +767,15 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
     };
     // per-column sizes, then the columns sorted by size class on the device
     // (stable: ascending columns, or the order of `only`, within a class)
-    static const int classes[][2] = {{16, 128}, {32, 256}, {64, 512}, {64, 1024}, {128, 2048},
-                                     {256, 4096}, {256, 8192}};
-    const int ncls = 7;
+    const ClassTable& tab = kClassTables[ctx->opt_class_table];
+    const int ncls = tab.n;
     ColumnClasses cc{};
     cc.ncls = ncls;
-    for (int c = 0; c < ncls; ++c) { cc.kcap[c] = classes[c][0]; cc.tcap[c] = classes[c][1]; }
+    for (int c = 0; c < ncls; ++c) { cc.kcap[c] = tab.cap[c][0]; cc.tcap[c] = tab.cap[c][1]; }
+    for (int c = 0; c < ncls; ++c) {
+        F->stats.class_kcap[c] = cc.kcap[c];
+        F->stats.class_tcap[c] = cc.tcap[c];
+    }
     const int m = only ? (int)only->size() : n;
     int32_t *kd = nullptr, *td = nullptr, *sel = nullptr, *sorted = nullptr, *meta = nullptr;
     DIAF_TRY(scratch(&kd, n));
@@ -1280,6 +1308,7 @@ diaf_status diaf_ctx_get_option(const diaf_ctx* ctx, const char* key, int64_t* v
     else if (k == "graph") *value = ctx->opt_graph;
     else if (k == "small_grid") *value = ctx->ftune.small_grid;
     else if (k == "generic_nt") *value = ctx->ftune.generic_nt;
+    else if (k == "class_table") *value = ctx->opt_class_table;
     else return DIAF_EINVAL;
     return DIAF_OK;
 }
@@ -1308,6 +1337,12 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
         if (value != 1 && value != 2 && value != 4 && value != 8 && value != 16)
             return fail(ctx, DIAF_EINVAL, "trsv_waves must be 1, 2, 4, 8 or 16");
         ctx->trsv.waves = (int)value;
+    }
+    else if (k == "class_table") {
+        if (value < 0 || value >= kNumClassTables)
+            return fail(ctx, DIAF_EINVAL,
+                        "class_table must be in 0.." + std::to_string(kNumClassTables - 1));
+        ctx->opt_class_table = value;
     }
     else return fail(ctx, DIAF_EINVAL, "unknown option " + k);
     return DIAF_OK;
@@ -1985,6 +2020,17 @@ Err autotune_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int m
         ctx->ftune.small_grid = pick;
     }
     if (launches >= 2 || ctx->opt_generic_only || spec->gram_fp32) {
+        double best = INFINITY;
+        int pick = 0;
+        for (int t = 0; t < kNumClassTables; ++t) {
+            ctx->opt_class_table = t;
+            double ms;
+            DIAF_TRY(time_factor(ms));
+            if (ms < best) { best = ms; pick = t; }
+        }
+        ctx->opt_class_table = pick;
+    }
+    if (launches >= 2 || ctx->opt_generic_only || spec->gram_fp32) {
         const int nts[] = {0, 64, 128, 256, 512};
         double best = INFINITY;
         int pick = 0;
@@ -2079,6 +2125,131 @@ extern "C" diaf_status diaf_solve(diaf_ctx* ctx, const diaf_csc* A, const diaf_f
     if (info->flag == 1) return fail(ctx, DIAF_ENOCONV, "BiCGSTAB: no convergence within maxit");
     if (info->flag == 2) return fail(ctx, DIAF_EBREAKDOWN, "BiCGSTAB: breakdown");
     if (info->flag == 3) return fail(ctx, DIAF_ESINGULAR, "V has a zero or non-finite pivot");
+    return DIAF_OK;
+}
+
+namespace {
+
+// Persistent autotuning: one JSON object per line of the file, keyed by the
+// device architecture and the problem's shape.
+const char* const kTuneKeys[] = {"small_grid", "generic_nt", "class_table", "trsv_waves",
+                                 "graph", "solve_batch", "trsv_backoff"};
+constexpr int kNumTuneKeys = 7;
+
+std::string tune_key(const diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode)
+{
+    hipDeviceProp_t prop{};
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) arch = prop.gcnArchName;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s|%s|%s|n=%lld|nnz=%lld|w=%d:%d|v=%d:%d|left=%d|fp32=%d",
+             arch.c_str(), mode == DIAF_UNIT_V ? "unit_v" : "unit_w",
+             A->dtype == DIAF_C128 ? "c128" : "f64", (long long)A->n, (long long)A->nnz,
+             (int)spec->w_kind, (int)spec->w_topk, (int)spec->v_kind, (int)spec->v_count,
+             (int)spec->left, (int)spec->gram_fp32);
+    return buf;
+}
+
+void tune_get(const diaf_ctx* ctx, int64_t* v)
+{
+    v[0] = ctx->ftune.small_grid;
+    v[1] = ctx->ftune.generic_nt;
+    v[2] = ctx->opt_class_table;
+    v[3] = ctx->trsv.waves;
+    v[4] = ctx->opt_graph;
+    v[5] = ctx->opt_batch;
+    v[6] = ctx->trsv.backoff;
+}
+
+// Reads the file (a missing file is empty).  Lines other than "{", "}" and
+// entries written by tune_write are an error, so a foreign file is never
+// overwritten.
+Err tune_read(const char* path, std::vector<std::pair<std::string, std::vector<int64_t>>>& out)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return {};
+    char line[4096];
+    int ln = 0;
+    Err err{};
+    while (fgets(line, sizeof line, f)) {
+        ++ln;
+        std::string t(line);
+        while (!t.empty() && (t.back() == '\n' || t.back() == '\r' || t.back() == ' ')) t.pop_back();
+        if (t.empty() || t == "{" || t == "}") continue;
+        const size_t q0 = t.find('"'), q1 = q0 == std::string::npos ? q0 : t.find('"', q0 + 1);
+        const size_t br = q1 == std::string::npos ? q1 : t.find('{', q1);
+        if (q0 != 0 || br == std::string::npos) {
+            err = {DIAF_EINVAL, std::string("tune file ") + path + ": unrecognised line " +
+                                    std::to_string(ln)};
+            break;
+        }
+        std::vector<int64_t> vals(kNumTuneKeys, INT64_MIN);
+        for (int q = 0; q < kNumTuneKeys; ++q) {
+            const std::string pat = std::string("\"") + kTuneKeys[q] + "\": ";
+            const size_t p = t.find(pat, br);
+            if (p != std::string::npos) vals[q] = strtoll(t.c_str() + p + pat.size(), nullptr, 10);
+        }
+        out.push_back({t.substr(q0 + 1, q1 - q0 - 1), vals});
+    }
+    fclose(f);
+    return err;
+}
+
+Err tune_write(const char* path,
+               const std::vector<std::pair<std::string, std::vector<int64_t>>>& entries)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return {DIAF_EINVAL, std::string("tune file ") + path + ": cannot write"};
+    fprintf(f, "{\n");
+    for (size_t e = 0; e < entries.size(); ++e) {
+        fprintf(f, "\"%s\": {", entries[e].first.c_str());
+        for (int q = 0; q < kNumTuneKeys; ++q)
+            fprintf(f, "%s\"%s\": %lld", q ? ", " : "", kTuneKeys[q],
+                    (long long)entries[e].second[q]);
+        fprintf(f, "}%s\n", e + 1 < entries.size() ? "," : "");
+    }
+    fprintf(f, "}\n");
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path) != 0)
+        return {DIAF_EINVAL, std::string("tune file ") + path + ": cannot write"};
+    return {};
+}
+
+}  // namespace
+
+extern "C" diaf_status diaf_autotune_cached(diaf_ctx* ctx, const diaf_csc* A,
+                                            const diaf_spec* spec, int32_t mode, const char* path,
+                                            int32_t* from_cache)
+{
+    if (!ctx || !A || !spec || !path || !from_cache) return DIAF_EINVAL;
+    *from_cache = 0;
+    std::vector<std::pair<std::string, std::vector<int64_t>>> entries;
+    Err e = tune_read(path, entries);
+    if (e.code) return fail(ctx, e);
+    const std::string key = tune_key(ctx, A, spec, mode);
+    for (auto& en : entries) {
+        if (en.first != key) continue;
+        bool whole = true;
+        for (int64_t v : en.second) whole = whole && v != INT64_MIN;
+        if (!whole) break;
+        for (int q = 0; q < kNumTuneKeys; ++q) {
+            const diaf_status s = diaf_ctx_set_option(ctx, kTuneKeys[q], en.second[q]);
+            if (s != DIAF_OK) return s;
+        }
+        *from_cache = 1;
+        return DIAF_OK;
+    }
+    const diaf_status s = diaf_autotune(ctx, A, spec, mode);
+    if (s != DIAF_OK) return s;
+    std::vector<int64_t> vals(kNumTuneKeys);
+    tune_get(ctx, vals.data());
+    bool found = false;
+    for (auto& en : entries)
+        if (en.first == key) { en.second = vals; found = true; }
+    if (!found) entries.push_back({key, vals});
+    e = tune_write(path, entries);
+    if (e.code) return fail(ctx, e);
     return DIAF_OK;
 }
 

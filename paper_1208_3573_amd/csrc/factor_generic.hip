@@ -97,6 +97,22 @@ __device__ inline double block_sum(GenCtx<T>& c, double x)
     return r;
 }
 
+// Sum of x over the first wave (the other threads pass 0), by a butterfly
+// in a fixed order: callers accumulate per lane with stride 64, so the
+// result does not depend on the workgroup size.
+template <class T>
+__device__ inline double wave0_sum(GenCtx<T>& c, double x)
+{
+    if (c.tid < 64) {
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (c.tid == 0) c.sRed[0] = x;
+    }
+    __syncthreads();
+    const double r = c.sRed[0];
+    __syncthreads();
+    return r;
+}
+
 // Inclusive scan of flags[0..cnt) (0/1) into out (ranks), returns total.
 template <class T>
 __device__ inline int block_scan_flags(GenCtx<T>& c, const int32_t* flags, int32_t* out, int cnt)
@@ -527,8 +543,9 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     // ||B||_F
     {
         double s = 0;
-        for (int t = tid; t < Tn; t += c.nt) s += num<T>::abs2(c.sVal[t]);
-        double bn2 = block_sum(c, s);
+        if (tid < 64)
+            for (int t = tid; t < Tn; t += 64) s += num<T>::abs2(c.sVal[t]);
+        double bn2 = wave0_sum(c, s);
         if (tid == 0) c.md[MD_BN2] = bn2;
     }
     const int lmax = A.lmax;
@@ -742,13 +759,14 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         // without those rows; its Gram matrix is E)
         {
             double s2 = 0.0;
-            for (int t = tid; t < Tn; t += c.nt) {
-                const int lr = c.sLrow[t];
-                bool inL = false;
-                for (int q = 0; q < l; ++q) inL |= c.sL[q] == lr;
-                if (!inL) s2 += num<T>::abs2(c.sVal[t]);
-            }
-            const double fro2 = block_sum(c, s2);
+            if (tid < 64)
+                for (int t = tid; t < Tn; t += 64) {
+                    const int lr = c.sLrow[t];
+                    bool inL = false;
+                    for (int q = 0; q < l; ++q) inL |= c.sL[q] == lr;
+                    if (!inL) s2 += num<T>::abs2(c.sVal[t]);
+                }
+            const double fro2 = wave0_sum(c, s2);
             if (tid == 0) c.md[MD_FRO2] = fro2;
         }
         if (tid == 0) {
@@ -921,8 +939,9 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         for (int t = 0; t < l; ++t) c.sY[c.sL[t]] -= c.sV[t];
     __syncthreads();
     double s = 0;
-    for (int i = tid; i < m; i += c.nt) s += num<T>::abs2(c.sY[i]);
-    double r2 = block_sum(c, s);
+    if (tid < 64)
+        for (int i = tid; i < m; i += 64) s += num<T>::abs2(c.sY[i]);
+    double r2 = wave0_sum(c, s);
     // unit-norm w: B without the rows of L has fewer rows than columns, or
     // its smallest singular value (here the residual) is negligible against
     // its Frobenius norm

@@ -78,7 +78,8 @@ class diaf_stats(ctypes.Structure):
                 ("launches_small", c_int32), ("cols_generic_class", c_int32 * 8),
                 ("launches_generic_class", c_int32 * 8), ("occ_small", c_double),
                 ("occ_generic_class", c_double * 8), ("ms_mid_kernel", c_double),
-                ("cols_mid", c_int32), ("launches_mid", c_int32), ("occ_mid", c_double)]
+                ("cols_mid", c_int32), ("launches_mid", c_int32), ("occ_mid", c_double),
+                ("class_kcap", c_int32 * 8), ("class_tcap", c_int32 * 8)]
 
 
 class diaf_solve_info(ctypes.Structure):
@@ -93,6 +94,8 @@ _SIGS = {
     "diaf_ctx_set_option": (c_int, [c_void_p, ctypes.c_char_p, c_int64]),
     "diaf_ctx_get_option": (c_int, [c_void_p, ctypes.c_char_p, POINTER(c_int64)]),
     "diaf_autotune": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_spec), c_int32]),
+    "diaf_autotune_cached": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_spec), c_int32,
+                                     ctypes.c_char_p, POINTER(c_int32)]),
     "diaf_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t]),
     "diaf_pattern_build": (c_int, [c_void_p, POINTER(diaf_csc), c_int32, c_int32, c_void_p,
                                    c_void_p, POINTER(c_int64)]),
@@ -350,12 +353,26 @@ def diaf_factor(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode) -> Factors:
     return Factors(ctx, h, A)
 
 
-def diaf_autotune(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode) -> dict:
-    """Tune the context's launch shapes on this problem; returns the choices."""
+TUNE_KEYS = ("small_grid", "generic_nt", "class_table", "trsv_waves", "graph", "solve_batch",
+             "trsv_backoff")
+
+
+def diaf_autotune(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode, cache: str | None = None
+                  ) -> dict:
+    """Tune the context's launch shapes on this problem; returns the choices.
+    With `cache` (a file path), a stored choice for this device architecture
+    and problem shape is applied instead, and a new one is stored
+    (``from_cache`` in the result tells which)."""
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    ctx.check(ctx.lib.diaf_autotune(ctx.h, ctypes.byref(A.desc), ctypes.byref(spec), m))
-    return {k: ctx.get_option(k) for k in ("small_grid", "generic_nt", "trsv_waves", "graph",
-                                           "solve_batch", "trsv_backoff")}
+    out = {}
+    if cache is None:
+        ctx.check(ctx.lib.diaf_autotune(ctx.h, ctypes.byref(A.desc), ctypes.byref(spec), m))
+    else:
+        hit = c_int32(0)
+        ctx.check(ctx.lib.diaf_autotune_cached(ctx.h, ctypes.byref(A.desc), ctypes.byref(spec), m,
+                                               os.fsencode(cache), ctypes.byref(hit)))
+        out["from_cache"] = bool(hit.value)
+    return {k: ctx.get_option(k) for k in TUNE_KEYS} | out
 
 
 def diaf_apply(ctx: Context, F: Factors, x, y):
