@@ -145,95 +145,224 @@ def pattern_alg2(A, v0: str) -> Pattern:
                    rowidx=np.concatenate(out) if out else np.zeros(0, np.int32))
 
 
-def _drop(rows, vals, tau, p, keep):
+def _mag(v):
+    """|v|^2 as the products and sum are written: v*v, or re*re + im*im."""
+    if isinstance(v, complex):
+        return v.real * v.real + v.imag * v.imag
+    return v * v
+
+
+def _cmul(a, b):
+    """a * b with each real product and sum rounded once, in this order."""
+    if isinstance(a, complex) or isinstance(b, complex):
+        a, b = complex(a), complex(b)
+        return complex(a.real * b.real - a.imag * b.imag, a.real * b.imag + a.imag * b.real)
+    return a * b
+
+
+def _cdiv(a, d):
+    """a / d: for complex values the textbook formula a conj(d) / |d|^2 with
+    each real operation rounded once, in this order."""
+    if isinstance(a, complex) or isinstance(d, complex):
+        a, d = complex(a), complex(d)
+        den = d.real * d.real + d.imag * d.imag
+        return complex((a.real * d.real + a.imag * d.imag) / den,
+                       (a.imag * d.real - a.real * d.imag) / den)
+    return a / d
+
+
+def _drop(rows, vals, tau, p, keep, margin=None):
     """Numerical dropping by tolerance and count (Section 4): entries with
     |v|^2 >= tau^2 max |v|^2 (tau > 0), then at most p of them, the largest
     (p > 0; ties to the lower row); the entry of row `keep` (the diagonal of
-    the column) is never dropped and does not count against p.  Squared
-    magnitudes are formed as v * v."""
+    the column) is never dropped and does not count against p.  `margin`
+    (a one-element list) receives the smallest relative distance of a
+    decision from its boundary: |m - thr| / thr for the tolerance, and the
+    relative gap between the last kept and the first dropped magnitude for
+    the count (0 for an exact tie)."""
     if not rows:
         return rows, vals
-    mag = [v * v for v in vals]
+    mag = [_mag(v) for v in vals]
     mx = max(mag)
     thr = tau * tau * mx if tau > 0 else None
+    if margin is not None and thr is not None:
+        for t in range(len(rows)):
+            if rows[t] != keep:
+                margin[0] = min(margin[0], abs(mag[t] - thr) / thr if thr > 0 else 0.0)
     cand = [t for t in range(len(rows)) if rows[t] != keep and (thr is None or mag[t] >= thr)]
     if p > 0 and len(cand) > p:
-        cand = sorted(cand, key=lambda t: (-mag[t], rows[t]))[:p]
+        cand = sorted(cand, key=lambda t: (-mag[t], rows[t]))
+        if margin is not None:
+            a, b = mag[cand[p - 1]], mag[cand[p]]
+            margin[0] = min(margin[0], (a - b) / a if a > 0 else 0.0)
+        cand = cand[:p]
     kept = set(cand) | {t for t in range(len(rows)) if rows[t] == keep}
     idx = sorted(kept, key=lambda t: rows[t])
     return [rows[t] for t in idx], [vals[t] for t in idx]
 
 
+def _v0_bounds(A, v0_blocks):
+    """Per column j the rows [lo, hi) of its diagonal block of V_0 (the
+    block starts 0 = s_0 < ... < s_m = n; None: the diagonal matrices)."""
+    n = A.n
+    if v0_blocks is None:
+        ar = np.arange(n)
+        return ar, ar + 1
+    s = [int(x) for x in v0_blocks]
+    if s[0] != 0 or s[-1] != n or any(b <= a for a, b in zip(s, s[1:])):
+        raise ValueError("V_0 blocks: the starts must increase strictly from 0 to n")
+    lo = np.zeros(n, dtype=np.int64)
+    hi = np.zeros(n, dtype=np.int64)
+    for a, b in zip(s, s[1:]):
+        lo[a:b] = a
+        hi[a:b] = b
+    return lo, hi
+
+
 def pattern_sparsified_powers(A, k: int = 3, tau_i: float = 0.1, p_i: int = 0,
-                              tau_l: float = 0.0, p_l: int = 0) -> Pattern:
-    """Algorithm 1 (Section 4) with V_0 = the diagonal matrices: S =
-    V_0^{-1}(I - P_{V_0})A, i.e. S(i, c) = a_ic / a_ii off the diagonal; its
-    columns dropped by (tau_i, p_i); then per column j, s = t = e_j and k
-    times t <- S t (products accumulated per row in ascending source row, as
-    separate multiplies and adds), dropped by (tau_l, p_l), s <- s + t; the
-    pattern of w_j is that of s, taken structurally (e_j and every kept entry
-    of every t).  With V_0 diagonal the final removal of V_0 minus the
-    identity removes nothing.  Real matrices with a nonzero diagonal; pure
-    Python, for small cases."""
-    S = _sp_matrix(A, tau_i, p_i)
+                              tau_l: float = 0.0, p_l: int = 0, v0_blocks=None) -> Pattern:
+    """Algorithm 1 (Section 4): S = V_0^{-1}(I - P_{V_0})A with V_0 = P_{V_0}A;
+    the columns of S dropped by (tau_i, p_i); then per column j, s = t = e_j
+    and k times t <- S t (products accumulated per row in ascending source
+    row, as separate multiplies and adds), dropped by (tau_l, p_l), s <- s + t;
+    the pattern of w_j is that of s, taken structurally (e_j and every kept
+    entry of every t), less the rows of V_0's pattern in column j other than
+    j (the final removal of V_0 minus the identity).
+
+    V_0: the diagonal matrices (v0_blocks None), where S(i, c) = a_ic / a_ii
+    off the diagonal and the removal removes nothing; or the block diagonal
+    matrices with the blocks given by their starts (Section 4's other
+    inexpensive choice), where V_0 is A's block diagonal part, each block
+    factored by LAPACK's LU with partial pivoting, and column c of S is the
+    block solve of A(:, c) outside c's block, every row of every block it
+    reaches being an entry of S.  Real or complex A; pure Python, for small
+    cases."""
+    S = _sp_matrix(A, tau_i, p_i, v0_blocks)
+    lo, hi = _v0_bounds(A, v0_blocks)
     n = A.n
     out_cp = np.zeros(n + 1, dtype=np.int32)
     out = []
     for j in range(n):
-        u = _sp_column(S, j, k, tau_l, p_l)
+        u = _sp_column(S, j, k, tau_l, p_l, lo[j], hi[j])
         out.append(u)
         out_cp[j + 1] = out_cp[j] + len(u)
     return Pattern(n=n, colptr=out_cp, rowidx=np.concatenate(out))
 
 
 def sparsified_powers_columns(A, cols, k: int = 3, tau_i: float = 0.1, p_i: int = 0,
-                              tau_l: float = 0.0, p_l: int = 0) -> dict:
+                              tau_l: float = 0.0, p_l: int = 0, v0_blocks=None,
+                              with_margin: bool = False) -> dict:
     """The columns `cols` of pattern_sparsified_powers (same steps), as
-    {j: ascending rows}, for sampled checks of large matrices."""
-    S = _sp_matrix(A, tau_i, p_i)
-    return {int(j): _sp_column(S, int(j), k, tau_l, p_l) for j in cols}
+    {j: ascending rows}; with_margin: {j: (rows, margin)}, the margin being
+    the smallest relative distance of any dropping decision taken for
+    column j (those of the columns of S it reads included) from its
+    boundary."""
+    mS = {} if with_margin else None
+    S = _sp_matrix(A, tau_i, p_i, v0_blocks, margins=mS)
+    lo, hi = _v0_bounds(A, v0_blocks)
+    out = {}
+    for j in cols:
+        j = int(j)
+        if with_margin:
+            m = [float("inf")]
+            rows = _sp_column(S, j, k, tau_l, p_l, lo[j], hi[j], margin=m, smargin=mS)
+            out[j] = (rows, m[0])
+        else:
+            out[j] = _sp_column(S, j, k, tau_l, p_l, lo[j], hi[j])
+    return out
 
 
-def _sp_matrix(A, tau_i, p_i):
-    """The columns of S = D^{-1}(A - D) after the initial dropping."""
-    if np.iscomplexobj(A.val):
-        raise ValueError("sparsified powers: real matrices only")
+def sparsified_S(A, v0_blocks=None):
+    """S = V_0^{-1}(I - P_{V_0})A before any dropping, as per-column (rows,
+    values) lists: the first step of Algorithm 1."""
+    return _sp_matrix(A, 0.0, 0, v0_blocks)
+
+
+def _sp_matrix(A, tau_i, p_i, v0_blocks=None, margins=None):
+    """The columns of S = V_0^{-1}(I - P_{V_0})A after the initial dropping."""
+    import scipy.linalg as sla
     n = A.n
+    cplx = np.iscomplexobj(A.val)
     cp = [int(x) for x in A.colptr]
     ri = [int(x) for x in A.rowidx]
-    va = [float(x) for x in A.val]
-    d = [0.0] * n
-    for c in range(n):
-        for q in range(cp[c], cp[c + 1]):
-            if ri[q] == c:
-                d[c] = va[q]
-    if any(x == 0.0 for x in d):
-        raise ValueError("sparsified powers: zero or missing diagonal entry")
+    va = [complex(x) for x in A.val] if cplx else [float(x) for x in A.val]
+    lo, hi = _v0_bounds(A, v0_blocks)
     S = []
+    if v0_blocks is None:
+        d = [0.0] * n
+        for c in range(n):
+            for q in range(cp[c], cp[c + 1]):
+                if ri[q] == c:
+                    d[c] = va[q]
+        if any(x == 0 for x in d):
+            raise ValueError("sparsified powers: zero or missing diagonal entry")
+        for c in range(n):
+            rows, vals = [], []
+            for q in range(cp[c], cp[c + 1]):
+                i = ri[q]
+                if i != c:
+                    rows.append(i)
+                    vals.append(_cdiv(va[q], d[i]))
+            m = [float("inf")]
+            S.append(_drop(rows, vals, tau_i, p_i, keep=-1, margin=m))
+            if margins is not None:
+                margins[c] = m[0]
+        return S
+    # block diagonal V_0: LU of every diagonal block of A
+    starts = [int(x) for x in v0_blocks]
+    lus = {}
+    for a, b in zip(starts, starts[1:]):
+        B = np.zeros((b - a, b - a), dtype=complex if cplx else float)
+        for c in range(a, b):
+            for q in range(cp[c], cp[c + 1]):
+                if a <= ri[q] < b:
+                    B[ri[q] - a, c - a] = va[q]
+        lu, piv = sla.lu_factor(B, check_finite=True)
+        if np.any(np.diag(lu) == 0):
+            raise ValueError("sparsified powers: a diagonal block of A is singular")
+        lus[a] = (b, lu, piv)
     for c in range(n):
-        rows, vals = [], []
+        by_block = {}
         for q in range(cp[c], cp[c + 1]):
             i = ri[q]
-            if i != c:
-                rows.append(i)
-                vals.append(va[q] / d[i])
-        S.append(_drop(rows, vals, tau_i, p_i, keep=-1))
+            if lo[c] <= i < hi[c]:
+                continue  # P_{V_0} A: c's own block
+            by_block.setdefault(int(lo[i]), []).append((i, va[q]))
+        rows, vals = [], []
+        for a in sorted(by_block):
+            b, lu, piv = lus[a]
+            r = np.zeros(b - a, dtype=complex if cplx else float)
+            for i, v in by_block[a]:
+                r[i - a] = v
+            y = sla.lu_solve((lu, piv), r)
+            rows.extend(range(a, b))
+            vals.extend(complex(x) for x in y) if cplx else vals.extend(float(x) for x in y)
+        m = [float("inf")]
+        S.append(_drop(rows, vals, tau_i, p_i, keep=-1, margin=m))
+        if margins is not None:
+            margins[c] = m[0]
     return S
 
 
-def _sp_column(S, j, k, tau_l, p_l):
-    """Column j: k products t <- S t with dropping, s the union."""
+def _sp_column(S, j, k, tau_l, p_l, lo=None, hi=None, margin=None, smargin=None):
+    """Column j: k products t <- S t with dropping, s the union, then the
+    rows of [lo, hi) other than j removed."""
     srows = {j}
     t_rows, t_vals = [j], [1.0]
     for _ in range(k):
         acc = {}
         for i, ti in zip(t_rows, t_vals):  # ascending source row
+            if smargin is not None and margin is not None:
+                margin[0] = min(margin[0], smargin[i])
             r_rows, r_vals = S[i]
             for r, v in zip(r_rows, r_vals):
-                acc[r] = acc[r] + v * ti if r in acc else v * ti
+                pr = _cmul(v, ti)
+                acc[r] = acc[r] + pr if r in acc else pr
         rows = sorted(acc)
-        t_rows, t_vals = _drop(rows, [acc[r] for r in rows], tau_l, p_l, keep=j)
+        t_rows, t_vals = _drop(rows, [acc[r] for r in rows], tau_l, p_l, keep=j, margin=margin)
         srows.update(t_rows)
+    if lo is not None:
+        srows = {r for r in srows if r == j or r < lo or r >= hi}
     return np.array(sorted(srows), dtype=np.int32)
 
 

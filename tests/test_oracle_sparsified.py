@@ -194,3 +194,127 @@ def test_diagonal_matrix_gives_diagonal_pattern():
     for prm in (dict(k=1, tau_i=0.0), dict(k=4, tau_i=0.3, p_l=2)):
         P = oracle.pattern_sparsified_powers(A, **prm)
         assert np.array_equal(P.colptr, np.arange(n + 1)) and np.array_equal(P.rowidx, np.arange(n))
+
+
+# ---- block diagonal V_0, the final removal and complex A --------------------
+
+def _blocks(n, sizes):
+    s = [0]
+    q = 0
+    while s[-1] < n:
+        s.append(min(n, s[-1] + sizes[q % len(sizes)]))
+        q += 1
+    return np.array(s, dtype=np.int32)
+
+
+def _block_mask(n, starts):
+    M = np.zeros((n, n), dtype=bool)
+    for a, b in zip(starts, starts[1:]):
+        M[a:b, a:b] = True
+    return M
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_unit_blocks_reduce_to_the_diagonal_v0(cplx):
+    """Blocks of one row are the diagonal matrices: the block route (LU
+    solves) must give the diagonal route's pattern."""
+    A = synth.random_small(70, 4, 21, complex_=cplx)
+    prm = dict(k=3, tau_i=0.2, p_i=3, tau_l=0.1, p_l=6)
+    P0 = oracle.pattern_sparsified_powers(A, **prm)
+    P1 = oracle.pattern_sparsified_powers(A, **prm, v0_blocks=np.arange(A.n + 1))
+    assert np.array_equal(P0.colptr, P1.colptr) and np.array_equal(P0.rowidx, P1.rowidx)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_block_S_is_the_dense_inverse_product(cplx):
+    """S = V_0^{-1}(A - P_{V_0} A) against a dense inverse (NumPy inv, not
+    the oracle's LU solves): column c's rows are every row of the blocks
+    its entries outside c's block reach, and nothing in c's own block."""
+    A = synth.random_small(48, 5, 8, complex_=cplx)
+    starts = _blocks(A.n, [5, 7, 3, 8])
+    Ad = dense(A)
+    M = _block_mask(A.n, starts)
+    V0 = np.where(M, Ad, 0)
+    Sd = np.linalg.inv(V0) @ (Ad - V0)
+    S = oracle.sparsified_S(A, starts)
+    off = (Ad != 0) & ~M
+    for c in range(A.n):
+        rows, vals = S[c]
+        reach = np.zeros(A.n, dtype=bool)
+        for i in np.nonzero(off[:, c])[0]:
+            reach |= M[i]
+        assert list(rows) == list(np.nonzero(reach)[0]), c
+        np.testing.assert_allclose(np.array(vals), Sd[rows, c], rtol=0,
+                                   atol=1e-11 * max(1.0, np.abs(Sd[:, c]).max()))
+        assert np.all(np.abs(Sd[~reach, c]) <= 1e-11 * max(1.0, np.abs(Sd[:, c]).max()))
+
+
+def test_block_series_without_dropping_is_structural():
+    """No dropping: the pattern is that of (I + S)^k, S's structure being the
+    blocks reached by the entries outside each column's block, less the rows
+    of the column's own block other than j (boolean matrix powers)."""
+    A = synth.random_small(60, 3, 4)
+    starts = _blocks(A.n, [4, 6])
+    M = _block_mask(A.n, starts)
+    off = (dense(A) != 0) & ~M
+    Sst = (M.astype(np.int64) @ off.astype(np.int64)) > 0
+    for k in (1, 2, 3):
+        R = np.eye(A.n, dtype=bool)
+        acc = R.copy()
+        for _ in range(k):
+            R = (Sst.astype(np.int64) @ R.astype(np.int64)) > 0
+            acc |= R
+        acc &= ~M | np.eye(A.n, dtype=bool)
+        P = oracle.pattern_sparsified_powers(A, k=k, tau_i=0.0, v0_blocks=starts)
+        assert _cols(P) == [list(np.nonzero(acc[:, j])[0]) for j in range(A.n)], k
+
+
+def test_removal_leaves_only_the_diagonal_inside_each_block():
+    """The final step removes V_0's pattern minus the identity: inside its
+    block, column j keeps row j only; outside, the rows are those of the
+    same run without the removal."""
+    A = synth.convdiff(8, 2, 3)
+    starts = np.arange(0, A.n + 1, 8, dtype=np.int32)
+    lo, hi = starts[:-1].repeat(8), starts[1:].repeat(8)
+    prm = dict(k=3, tau_i=0.05, tau_l=0.02)
+    got = oracle.sparsified_powers_columns(A, range(A.n), **prm, v0_blocks=starts)
+    S = oracle._sp_matrix(A, prm["tau_i"], 0, starts)
+    for j in range(A.n):
+        rows = list(got[j])
+        inside = [r for r in rows if lo[j] <= r < hi[j]]
+        assert inside == [j]
+        raw = oracle._sp_column(S, j, prm["k"], prm["tau_l"], 0)
+        assert [r for r in rows if r != j] == [r for r in raw if not lo[j] <= r < hi[j]]
+
+
+def test_complex_imaginary_couplings_match_the_real_case():
+    """A = I + iB against A = I + B (B without diagonal): S = iB, so every
+    magnitude of every power is the real case's exactly (products of
+    imaginary units are exact) and the patterns agree, dropping included."""
+    R = synth.random_small(80, 4, 13)
+    val = R.val.copy()
+    diag = R.rowidx == np.repeat(np.arange(R.n), np.diff(R.colptr))
+    val[diag] = 1.0
+    Ar = synth._coo_to_csc(R.n, R.rowidx, np.repeat(np.arange(R.n), np.diff(R.colptr)), val)
+    cval = np.where(diag, 1.0 + 0j, 1j * val)
+    Ac = synth._coo_to_csc(R.n, R.rowidx, np.repeat(np.arange(R.n), np.diff(R.colptr)), cval)
+    prm = dict(k=3, tau_i=0.15, p_i=3, tau_l=0.05, p_l=5)
+    Pr = oracle.pattern_sparsified_powers(Ar, **prm)
+    Pc = oracle.pattern_sparsified_powers(Ac, **prm)
+    assert _cols(Pr) == _cols(Pc)
+
+
+def test_margin_is_zero_on_an_exact_tie_and_positive_otherwise():
+    """Two off-diagonal entries of equal magnitude compete for one place
+    (count rule): the decision is a tie (margin 0, the lower row wins);
+    unequal magnitudes give the relative gap."""
+    n = 4
+    rows = [0, 1, 2, 3, 1, 2, 0, 3]
+    cols = [0, 1, 2, 3, 0, 0, 3, 2]
+    for v, want in ((0.5, 0.0), (0.25, 0.75)):
+        vals = [1.0, 1.0, 1.0, 1.0, 0.5, v, 0.1, 0.1]
+        A = synth._coo_to_csc(n, np.array(rows), np.array(cols), np.array(vals))
+        out = oracle.sparsified_powers_columns(A, [0], k=1, tau_i=0.0, p_i=1, with_margin=True)
+        r, m = out[0]
+        assert list(r) == [0, 1]
+        assert m == pytest.approx(want)
