@@ -134,7 +134,9 @@ def copy_calibration():
 
 
 # Method variants on the 64^3 matrix (the rows beyond the headline
-# configuration): Algorithm 1 with the paper's parameters (k = 3, tau_i = 0.1),
+# configuration): Algorithm 1 with the paper's parameters (k = 3, tau_i = 0.1)
+# and V_0 diagonal, or block diagonal on the x-lines (64 rows per block) with
+# V block diagonal on the same blocks or the top-k lower rule,
 # Algorithm 2 with the Gauss-Seidel V_0, the Section 3.2 constraint, the
 # Section 3.1 leverage rule, block diagonal V on the x-lines of the grid (64
 # rows per block) with the pattern of D or the top-k rows of the block, and
@@ -142,6 +144,10 @@ def copy_calibration():
 VARIANTS = {
     "alg1": dict(w="sparsified", v="topk_lower", v_count=5,
                  sparsify=dict(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0)),
+    "alg1_block": dict(w="sparsified", v="block", blocks=64, v0_blocks=64,
+                       sparsify=dict(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0)),
+    "alg1_block_topk": dict(w="sparsified", v="topk_lower", v_count=5, v0_blocks=64,
+                            sparsify=dict(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0)),
     "alg2_gs": dict(w="alg2_gs_lower", v="topk_lower", v_count=5),
     "stab": dict(w="A2", v="topk_lower", v_count=5, stab_r=2.0),
     "lev": dict(w="A2", v="lev_lower", v_count=5),
@@ -567,6 +573,10 @@ def main():
             nb = kw.pop("blocks", None)
             if nb:
                 kw["v_blocks"] = torch.arange(0, A.n + 1, nb, dtype=torch.int32, device="cuda")
+            nb0 = kw.pop("v0_blocks", None)
+            if nb0:
+                kw["sparsify"] = dict(kw["sparsify"], v0_blocks=torch.arange(
+                    0, A.n + 1, nb0, dtype=torch.int32, device="cuda"))
             vspec = diaf.make_spec(**kw)
             rec = []
             for it in range(args.warmup + args.steps):
@@ -580,7 +590,9 @@ def main():
                 F.close()
             Rv = np.array(rec, dtype=float)
             out["variants"][name] = {
-                "spec": {k: (v if not hasattr(v, "shape") else f"blocks of {nb}")
+                "spec": {k: (f"blocks of {nb}" if hasattr(v, "shape") else
+                             {a: (f"blocks of {nb0}" if hasattr(b, "shape") else b)
+                              for a, b in v.items()} if isinstance(v, dict) else v)
                          for k, v in kw.items()},
                 "factor_ms": float(Rv[:, 0].mean()), "solve_ms": float(Rv[:, 1].mean()),
                 "e2e_ms": float((Rv[:, 0] + Rv[:, 1]).mean()),

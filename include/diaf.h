@@ -83,28 +83,44 @@ typedef enum diaf_w_kind {
     DIAF_W_SPARSIFIED = 8
 } diaf_w_kind;
 
-/* Parameters of the sparsified powers W pattern (Section 4, Algorithm 1,
- * V_0 = diagonal matrices).  With D = diag(A) and S = D^{-1}(A - D), i.e.
- * S(i, c) = a_ic / a_ii off the diagonal: each column of S is first
- * sparsified by (tau_i, p_i); then, for every column j, t = e_j is
- * multiplied by S k times, each product sparsified by (tau_l, p_l) with its
- * entry in row j never dropped, and the pattern of w_j is the union of e_j
- * and every kept t.  Dropping by tolerance keeps the entries with
- * v^2 >= tau^2 max v^2 over the vector; dropping by count then keeps the p
- * largest (equal magnitudes: the lower rows); a zero parameter disables its
- * rule.  Products are summed in ascending source row with round-to-nearest
- * multiplies and adds, so the pattern is reproducible bit for bit.  k in
- * 1..8; p_i, p_l in 0..2^20; tau_i, tau_l finite and >= 0 (else
- * DIAF_EINVAL); a zero diagonal entry is DIAF_EINVAL; a column of A with
- * more than 1024 entries, a power vector of more than 2048 rows or a
- * pattern of more than 4096 rows is DIAF_EUNSUPPORTED. */
+/* Parameters of the sparsified powers W pattern (Section 4, Algorithm 1),
+ * real or complex A.  The splitting A = V_0 (I - S) with V_0 = P_{V_0} A
+ * gives S = V_0^{-1}(A - P_{V_0} A): for V_0 the diagonal matrices
+ * (v0_nblocks = 0), S(i, c) = a_ic / a_ii off the diagonal; for V_0 the
+ * block diagonal matrices with the given blocks (Section 4's other
+ * inexpensive choice), V_0 is A's block diagonal part, each block is
+ * factored with partial pivoting, and column c of S is the block solve of
+ * A(:, c) outside c's block, every row of every block it reaches being an
+ * entry.  Each column of S is first sparsified by (tau_i, p_i); then, for
+ * every column j, t = e_j is multiplied by S k times, each product
+ * sparsified by (tau_l, p_l) with its entry in row j never dropped, and the
+ * pattern of w_j is the union of e_j and every kept t, less the rows of
+ * j's block other than j (the algorithm's final removal of V_0 minus the
+ * identity).  Dropping by tolerance keeps the entries with |v|^2 >= tau^2
+ * max |v|^2 over the vector; dropping by count then keeps the p largest
+ * (equal magnitudes: the lower rows); a zero parameter disables its rule.
+ * Products are summed in ascending source row with round-to-nearest
+ * operations (complex: (ar br - ai bi, ar bi + ai br), and a / d as
+ * a conj(d) / |d|^2), so with the diagonal V_0 the pattern is reproducible
+ * bit for bit; with blocks the LU solves round differently from other LU
+ * codes, and only decisions within rounding of a dropping boundary can
+ * differ.  k in 1..8; p_i, p_l in 0..2^20; tau_i, tau_l finite and >= 0;
+ * v0_blocks given exactly when v0_nblocks > 0, its starts running from 0 to
+ * n and increasing (else DIAF_EINVAL); a zero diagonal entry or a singular
+ * diagonal block is DIAF_EINVAL; a block of more than 64 rows, a column of
+ * A or of S before dropping with more than 1024 entries, a power vector of
+ * more than 2048 rows (complex 1024) or a pattern of more than 4096 rows
+ * (complex 2048) is DIAF_EUNSUPPORTED. */
 typedef struct diaf_sparsify {
-    int32_t k;        /* truncation of the series I + S + ... + S^k */
-    int32_t p_i;      /* count limit on the columns of S */
-    int32_t p_l;      /* count limit on every power vector t */
-    int32_t reserved; /* 0 */
-    double tau_i;     /* relative tolerance on the columns of S */
-    double tau_l;     /* relative tolerance on every power vector t */
+    int32_t k;          /* truncation of the series I + S + ... + S^k */
+    int32_t p_i;        /* count limit on the columns of S */
+    int32_t p_l;        /* count limit on every power vector t */
+    int32_t v0_nblocks; /* 0: V_0 diagonal; else the number of diagonal blocks of V_0 */
+    double tau_i;       /* relative tolerance on the columns of S */
+    double tau_l;       /* relative tolerance on every power vector t */
+    const int32_t* v0_blocks; /* device array of v0_nblocks + 1 block starts
+                                 0 = s_0 < ... < s_m = n (blocks of at most
+                                 64 rows), or NULL */
 } diaf_sparsify;
 
 /* V pattern L: explicit; diagonal; Gauss-Seidel structure (Definition 4.1:

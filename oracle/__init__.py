@@ -256,16 +256,16 @@ def sparsified_powers_columns(A, cols, k: int = 3, tau_i: float = 0.1, p_i: int 
     {j: ascending rows}; with_margin: {j: (rows, margin)}, the margin being
     the smallest relative distance of any dropping decision taken for
     column j (those of the columns of S it reads included) from its
-    boundary."""
-    mS = {} if with_margin else None
-    S = _sp_matrix(A, tau_i, p_i, v0_blocks, margins=mS)
+    boundary.  Columns of S are formed when first read, so sampled columns
+    of large matrices stay cheap."""
+    S = _sp_matrix(A, tau_i, p_i, v0_blocks)
     lo, hi = _v0_bounds(A, v0_blocks)
     out = {}
     for j in cols:
         j = int(j)
         if with_margin:
             m = [float("inf")]
-            rows = _sp_column(S, j, k, tau_l, p_l, lo[j], hi[j], margin=m, smargin=mS)
+            rows = _sp_column(S, j, k, tau_l, p_l, lo[j], hi[j], margin=m, smargin=S.margins)
             out[j] = (rows, m[0])
         else:
             out[j] = _sp_column(S, j, k, tau_l, p_l, lo[j], hi[j])
@@ -275,73 +275,89 @@ def sparsified_powers_columns(A, cols, k: int = 3, tau_i: float = 0.1, p_i: int 
 def sparsified_S(A, v0_blocks=None):
     """S = V_0^{-1}(I - P_{V_0})A before any dropping, as per-column (rows,
     values) lists: the first step of Algorithm 1."""
-    return _sp_matrix(A, 0.0, 0, v0_blocks)
+    S = _sp_matrix(A, 0.0, 0, v0_blocks)
+    return [S[c] for c in range(A.n)]
 
 
-def _sp_matrix(A, tau_i, p_i, v0_blocks=None, margins=None):
-    """The columns of S = V_0^{-1}(I - P_{V_0})A after the initial dropping."""
-    import scipy.linalg as sla
-    n = A.n
-    cplx = np.iscomplexobj(A.val)
-    cp = [int(x) for x in A.colptr]
-    ri = [int(x) for x in A.rowidx]
-    va = [complex(x) for x in A.val] if cplx else [float(x) for x in A.val]
-    lo, hi = _v0_bounds(A, v0_blocks)
-    S = []
-    if v0_blocks is None:
-        d = [0.0] * n
-        for c in range(n):
-            for q in range(cp[c], cp[c + 1]):
-                if ri[q] == c:
-                    d[c] = va[q]
-        if any(x == 0 for x in d):
-            raise ValueError("sparsified powers: zero or missing diagonal entry")
-        for c in range(n):
-            rows, vals = [], []
+class _SColumns:
+    """The columns of S = V_0^{-1}(I - P_{V_0})A after the initial dropping
+    by (tau_i, p_i), each formed when first read; margins[c] is the margin
+    of column c's dropping."""
+
+    def __init__(self, A, tau_i, p_i, v0_blocks):
+        import scipy.linalg as sla
+        self.n = A.n
+        self.cplx = np.iscomplexobj(A.val)
+        self.cp = [int(x) for x in A.colptr]
+        self.ri = [int(x) for x in A.rowidx]
+        self.va = [complex(x) for x in A.val] if self.cplx else [float(x) for x in A.val]
+        self.tau, self.p = tau_i, p_i
+        self.lo, self.hi = _v0_bounds(A, v0_blocks)
+        self.cols = {}
+        self.margins = {}
+        self.blocks = v0_blocks is not None
+        cp, ri, va = self.cp, self.ri, self.va
+        if not self.blocks:
+            d = [0.0] * self.n
+            for c in range(self.n):
+                for q in range(cp[c], cp[c + 1]):
+                    if ri[q] == c:
+                        d[c] = va[q]
+            if any(x == 0 for x in d):
+                raise ValueError("sparsified powers: zero or missing diagonal entry")
+            self.d = d
+            return
+        # block diagonal V_0: LU of every diagonal block of A
+        starts = [int(x) for x in v0_blocks]
+        self.lus = {}
+        for a, b in zip(starts, starts[1:]):
+            B = np.zeros((b - a, b - a), dtype=complex if self.cplx else float)
+            for c in range(a, b):
+                for q in range(cp[c], cp[c + 1]):
+                    if a <= ri[q] < b:
+                        B[ri[q] - a, c - a] = va[q]
+            lu, piv = sla.lu_factor(B, check_finite=True)
+            if np.any(np.diag(lu) == 0):
+                raise ValueError("sparsified powers: a diagonal block of A is singular")
+            self.lus[a] = (b, lu, piv)
+
+    def __getitem__(self, c):
+        if c in self.cols:
+            return self.cols[c]
+        import scipy.linalg as sla
+        cp, ri, va = self.cp, self.ri, self.va
+        rows, vals = [], []
+        if not self.blocks:
             for q in range(cp[c], cp[c + 1]):
                 i = ri[q]
                 if i != c:
                     rows.append(i)
-                    vals.append(_cdiv(va[q], d[i]))
-            m = [float("inf")]
-            S.append(_drop(rows, vals, tau_i, p_i, keep=-1, margin=m))
-            if margins is not None:
-                margins[c] = m[0]
-        return S
-    # block diagonal V_0: LU of every diagonal block of A
-    starts = [int(x) for x in v0_blocks]
-    lus = {}
-    for a, b in zip(starts, starts[1:]):
-        B = np.zeros((b - a, b - a), dtype=complex if cplx else float)
-        for c in range(a, b):
+                    vals.append(_cdiv(va[q], self.d[i]))
+        else:
+            by_block = {}
             for q in range(cp[c], cp[c + 1]):
-                if a <= ri[q] < b:
-                    B[ri[q] - a, c - a] = va[q]
-        lu, piv = sla.lu_factor(B, check_finite=True)
-        if np.any(np.diag(lu) == 0):
-            raise ValueError("sparsified powers: a diagonal block of A is singular")
-        lus[a] = (b, lu, piv)
-    for c in range(n):
-        by_block = {}
-        for q in range(cp[c], cp[c + 1]):
-            i = ri[q]
-            if lo[c] <= i < hi[c]:
-                continue  # P_{V_0} A: c's own block
-            by_block.setdefault(int(lo[i]), []).append((i, va[q]))
-        rows, vals = [], []
-        for a in sorted(by_block):
-            b, lu, piv = lus[a]
-            r = np.zeros(b - a, dtype=complex if cplx else float)
-            for i, v in by_block[a]:
-                r[i - a] = v
-            y = sla.lu_solve((lu, piv), r)
-            rows.extend(range(a, b))
-            vals.extend(complex(x) for x in y) if cplx else vals.extend(float(x) for x in y)
+                i = ri[q]
+                if self.lo[c] <= i < self.hi[c]:
+                    continue  # P_{V_0} A: c's own block
+                by_block.setdefault(int(self.lo[i]), []).append((i, va[q]))
+            for a in sorted(by_block):
+                b, lu, piv = self.lus[a]
+                r = np.zeros(b - a, dtype=complex if self.cplx else float)
+                for i, v in by_block[a]:
+                    r[i - a] = v
+                y = sla.lu_solve((lu, piv), r)
+                rows.extend(range(a, b))
+                vals.extend(complex(x) for x in y) if self.cplx else vals.extend(float(x) for x in y)
         m = [float("inf")]
-        S.append(_drop(rows, vals, tau_i, p_i, keep=-1, margin=m))
-        if margins is not None:
-            margins[c] = m[0]
-    return S
+        col = _drop(rows, vals, self.tau, self.p, keep=-1, margin=m)
+        self.cols[c] = col
+        self.margins[c] = m[0]
+        return col
+
+
+def _sp_matrix(A, tau_i, p_i, v0_blocks=None):
+    """The columns of S = V_0^{-1}(I - P_{V_0})A after the initial dropping."""
+    return _SColumns(A, tau_i, p_i, v0_blocks)
 
 
 def _sp_column(S, j, k, tau_l, p_l, lo=None, hi=None, margin=None, smargin=None):
@@ -352,9 +368,9 @@ def _sp_column(S, j, k, tau_l, p_l, lo=None, hi=None, margin=None, smargin=None)
     for _ in range(k):
         acc = {}
         for i, ti in zip(t_rows, t_vals):  # ascending source row
+            r_rows, r_vals = S[i]
             if smargin is not None and margin is not None:
                 margin[0] = min(margin[0], smargin[i])
-            r_rows, r_vals = S[i]
             for r, v in zip(r_rows, r_vals):
                 pr = _cmul(v, ti)
                 acc[r] = acc[r] + pr if r in acc else pr

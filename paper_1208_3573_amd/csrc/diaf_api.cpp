@@ -398,6 +398,9 @@ Err check_sparsify(const diaf_sparsify* sp)
     if (!(sp->tau_i >= 0.0) || !std::isfinite(sp->tau_i) || !(sp->tau_l >= 0.0) ||
         !std::isfinite(sp->tau_l))
         return {DIAF_EINVAL, "sparsified powers: tau_i and tau_l must be finite and >= 0"};
+    if (sp->v0_nblocks < 0 || (sp->v0_nblocks > 0) != (sp->v0_blocks != nullptr))
+        return {DIAF_EINVAL, "sparsified powers: v0_blocks must be given exactly when "
+                             "v0_nblocks > 0"};
     return {};
 }
 
@@ -415,8 +418,6 @@ Err check_spec(const diaf_csc* A, const diaf_spec* spec, int mode)
         return {DIAF_EINVAL, "bad w_kind"};
     if (spec->w_kind == DIAF_W_SPARSIFIED) {
         DIAF_TRY(check_sparsify(&spec->sparsify));
-        if (A->dtype != DIAF_F64)
-            return {DIAF_EUNSUPPORTED, "sparsified powers: real matrices only"};
     }
     if (!(spec->stab_r >= 0.0) || !std::isfinite(spec->stab_r) || !(spec->stab_tol >= 0.0) ||
         !std::isfinite(spec->stab_tol))
@@ -434,61 +435,145 @@ Err check_spec(const diaf_csc* A, const diaf_spec* spec, int mode)
 // Algorithm 1 (Section 4) with V_0 = diagonals: S built and sparsified once,
 // then the per-column level expansion, counted and filled; columns that
 // outgrow the small LDS tables are rerun with the large ones.
-Err build_sparsified(const diaf_csc* A, const diaf_sparsify* sp, int32_t* Jcp, int32_t** Jri_out,
-                     int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st)
+template <class T>
+Err build_sparsified_t(const diaf_csc* A, const diaf_sparsify* sp, int32_t* Jcp, int32_t** Jri_out,
+                       int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st)
 {
-    if (A->dtype != DIAF_F64)
-        return {DIAF_EUNSUPPORTED, "sparsified powers: real matrices only"};
-    DIAF_TRY(check_sparsify(sp));
     const int n = (int)A->n;
     const size_t nnz = (size_t)A->nnz;
     struct Free {
         std::vector<void*> p;
         ~Free() { for (void* q : p) dfree(q); }
     } fr;
-    double *d = nullptr, *Sval = nullptr;
+    const auto take = [&](auto** ptr, size_t bytes) -> Err {
+        DIAF_TRY(dmalloc(ptr, bytes > 0 ? bytes : 1));
+        fr.p.push_back(*ptr);
+        return {};
+    };
+    T* Sval = nullptr;
     int32_t *bad = nullptr, *Sri = nullptr, *scnt = nullptr, *cnt = nullptr, *lists = nullptr,
-            *nover = nullptr;
-    DIAF_TRY(dmalloc(&d, sizeof(double) * (size_t)n));
-    fr.p.push_back(d);
-    DIAF_TRY(dmalloc(&Sval, sizeof(double) * nnz));
-    fr.p.push_back(Sval);
-    DIAF_TRY(dmalloc(&Sri, sizeof(int32_t) * nnz));
-    fr.p.push_back(Sri);
-    DIAF_TRY(dmalloc(&scnt, sizeof(int32_t) * (size_t)n));
-    fr.p.push_back(scnt);
-    DIAF_TRY(dmalloc(&cnt, sizeof(int32_t) * (size_t)(n + 1)));
-    fr.p.push_back(cnt);
-    DIAF_TRY(dmalloc(&lists, sizeof(int32_t) * 2 * (size_t)n));  // deferred, then failed columns
-    fr.p.push_back(lists);
-    DIAF_TRY(dmalloc(&bad, sizeof(int32_t) * 3));  // bad flags, #deferred, #failed
-    fr.p.push_back(bad);
+            *nover = nullptr, *rb = nullptr;
+    const int32_t* Scp = A->colptr;
+    const T* Aval = (const T*)A->val;
+    DIAF_TRY(take(&scnt, sizeof(int32_t) * (size_t)n));
+    DIAF_TRY(take(&cnt, sizeof(int32_t) * (size_t)(n + 1)));
+    DIAF_TRY(take(&lists, sizeof(int32_t) * 2 * (size_t)n));  // deferred, then failed columns
+    DIAF_TRY(take(&bad, sizeof(int32_t) * 3));  // bad flags, #deferred, #failed
     nover = bad + 1;
     int32_t* deferred = lists;
     int32_t* failed = lists + n;
     DIAF_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t) * 3, st));
-    const double* Aval = (const double*)A->val;
-    DIAF_TRY(launch_sp_diag(n, A->colptr, A->rowidx, Aval, d, bad, st));
-    DIAF_TRY(launch_sp_build_s(n, A->colptr, A->rowidx, Aval, d, sp->tau_i, sp->p_i, Sri, Sval,
-                               scnt, bad, st));
-    int32_t flags = 0;
-    DIAF_TRY(read1(bad, &flags, st));
-    if (flags & 1)
-        return {DIAF_EINVAL, "sparsified powers: A has a zero diagonal entry (D^{-1} undefined)"};
-    if (flags & 2)
-        return {DIAF_EUNSUPPORTED, "sparsified powers: a column of A has more than 1024 entries"};
-    DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l, nullptr, n,
-                              0, cnt, nullptr, nullptr, deferred, nover, st));
+    if (sp->v0_nblocks == 0) {
+        // V_0 the diagonal matrices: S in A's column layout
+        T* d = nullptr;
+        DIAF_TRY(take(&d, sizeof(T) * (size_t)n));
+        DIAF_TRY(take(&Sval, sizeof(T) * nnz));
+        DIAF_TRY(take(&Sri, sizeof(int32_t) * nnz));
+        DIAF_TRY(launch_sp_diag<T>(n, A->colptr, A->rowidx, Aval, d, bad, st));
+        DIAF_TRY(launch_sp_build_s<T>(n, A->colptr, A->rowidx, Aval, d, sp->tau_i, sp->p_i, Sri,
+                                      Sval, scnt, bad, st));
+        int32_t flags = 0;
+        DIAF_TRY(read1(bad, &flags, st));
+        if (flags & 1)
+            return {DIAF_EINVAL,
+                    "sparsified powers: A has a zero diagonal entry (D^{-1} undefined)"};
+        if (flags & 2)
+            return {DIAF_EUNSUPPORTED,
+                    "sparsified powers: a column of A has more than 1024 entries"};
+    } else {
+        // V_0 block diagonal: the blocks, A's block diagonal part D, its LU
+        const int nb = sp->v0_nblocks;
+        std::vector<int32_t> s(nb + 1);
+        DIAF_HIP_TRY(hipMemcpyAsync(s.data(), sp->v0_blocks, sizeof(int32_t) * (nb + 1),
+                                    hipMemcpyDeviceToHost, st));
+        DIAF_TRY(sync(st));
+        if (s[0] != 0 || s[nb] != n)
+            return {DIAF_EINVAL, "sparsified powers: the V_0 block starts must run from 0 to n"};
+        std::vector<int32_t> bounds(2 * (size_t)n), bidh(n);
+        std::vector<int64_t> off(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) {
+            const int sz = s[b + 1] - s[b];
+            if (sz <= 0)
+                return {DIAF_EINVAL, "sparsified powers: the V_0 block starts must increase"};
+            if (sz > 64)
+                return {DIAF_EUNSUPPORTED, "sparsified powers: V_0 blocks of at most 64 rows"};
+            for (int j = s[b]; j < s[b + 1]; ++j) {
+                bounds[2 * (size_t)j] = s[b];
+                bounds[2 * (size_t)j + 1] = s[b + 1];
+                bidh[j] = b;
+            }
+            off[b + 1] = off[b] + (int64_t)sz * sz;
+        }
+        int32_t *bid = nullptr, *bstart = nullptr, *Dcp = nullptr, *Dri = nullptr, *perm = nullptr;
+        int64_t* boff = nullptr;
+        T *Dval = nullptr, *LU = nullptr;
+        DIAF_TRY(take(&rb, sizeof(int32_t) * bounds.size()));
+        DIAF_TRY(take(&bid, sizeof(int32_t) * (size_t)n));
+        DIAF_TRY(take(&bstart, sizeof(int32_t) * (nb + 1)));
+        DIAF_TRY(take(&boff, sizeof(int64_t) * (nb + 1)));
+        DIAF_HIP_TRY(hipMemcpyAsync(rb, bounds.data(), sizeof(int32_t) * bounds.size(),
+                                    hipMemcpyHostToDevice, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(bid, bidh.data(), sizeof(int32_t) * (size_t)n,
+                                    hipMemcpyHostToDevice, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(bstart, s.data(), sizeof(int32_t) * (nb + 1),
+                                    hipMemcpyHostToDevice, st));
+        DIAF_HIP_TRY(hipMemcpyAsync(boff, off.data(), sizeof(int64_t) * (nb + 1),
+                                    hipMemcpyHostToDevice, st));
+        DIAF_TRY(take(&Dcp, sizeof(int32_t) * (size_t)(n + 1)));
+        DIAF_TRY(launch_sp_block_d<T>(n, A->colptr, A->rowidx, Aval, rb, cnt, nullptr, nullptr,
+                                      nullptr, st));
+        DIAF_TRY(exclusive_scan_i32(cnt, Dcp, n, st));
+        int32_t dn = 0;
+        DIAF_TRY(read1(Dcp + n, &dn, st));
+        DIAF_TRY(take(&Dri, sizeof(int32_t) * (size_t)dn));
+        DIAF_TRY(take(&Dval, sizeof(T) * (size_t)dn));
+        DIAF_TRY(launch_sp_block_d<T>(n, A->colptr, A->rowidx, Aval, rb, nullptr, Dcp, Dri, Dval,
+                                      st));
+        DIAF_TRY(take(&LU, sizeof(T) * (size_t)off[nb]));
+        DIAF_TRY(take(&perm, sizeof(int32_t) * (size_t)n));
+        DIAF_TRY(launch_block_lu<T>(nb, bstart, boff, Dcp, Dri, Dval, LU, perm, bad, st));
+        int32_t nsing = 0;
+        DIAF_TRY(read1(bad, &nsing, st));
+        if (nsing & ((1 << 30) - 1))
+            return {DIAF_EINVAL, "sparsified powers: a diagonal block of A (V_0) is singular"};
+        DIAF_HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int32_t), st));
+        // S: count, layout, fill
+        int32_t* Scp_own = nullptr;
+        DIAF_TRY(take(&Scp_own, sizeof(int32_t) * (size_t)(n + 1)));
+        DIAF_TRY(launch_sp_build_s_block<T>(n, A->colptr, A->rowidx, Aval, rb, bid, bstart, boff,
+                                            LU, perm, sp->tau_i, sp->p_i, scnt, nullptr, nullptr,
+                                            nullptr, bad, st));
+        int32_t flags = 0;
+        DIAF_TRY(read1(bad, &flags, st));
+        if (flags & 2)
+            return {DIAF_EUNSUPPORTED, "sparsified powers: a column of A, or of S before "
+                                       "dropping, has more than 1024 entries"};
+        DIAF_TRY(exclusive_scan_i32(scnt, Scp_own, n, st));
+        int32_t sn = 0;
+        DIAF_TRY(read1(Scp_own + n, &sn, st));
+        DIAF_TRY(take(&Sri, sizeof(int32_t) * (size_t)sn));
+        DIAF_TRY(take(&Sval, sizeof(T) * (size_t)sn));
+        DIAF_TRY(launch_sp_build_s_block<T>(n, A->colptr, A->rowidx, Aval, rb, bid, bstart, boff,
+                                            LU, perm, sp->tau_i, sp->p_i, scnt, Scp_own, Sri,
+                                            Sval, bad, st));
+        Scp = Scp_own;
+    }
+    DIAF_TRY(launch_sp_expand<T>(n, Scp, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l, rb, nullptr,
+                                 n, 0, cnt, nullptr, nullptr, deferred, nover, st));
     int32_t ndef = 0;
     DIAF_TRY(read1(nover, &ndef, st));
     if (ndef > 0) {
-        DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l,
-                                  deferred, ndef, 1, cnt, nullptr, nullptr, failed, nover + 1, st));
+        DIAF_TRY(launch_sp_expand<T>(n, Scp, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l, rb,
+                                     deferred, ndef, 1, cnt, nullptr, nullptr, failed, nover + 1,
+                                     st));
         int32_t nfail = 0;
         DIAF_TRY(read1(nover + 1, &nfail, st));
         if (nfail > 0)
-            return {DIAF_EUNSUPPORTED, "sparsified powers: a power vector exceeds 2048 rows or a "
-                                       "pattern 4096 rows"};
+            return {DIAF_EUNSUPPORTED, SpCaps<T>::TL == 2048
+                                           ? "sparsified powers: a power vector exceeds 2048 "
+                                             "rows or a pattern 4096 rows"
+                                           : "sparsified powers: a power vector exceeds 1024 "
+                                             "rows or a pattern 2048 rows (complex)"};
     }
     DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
     int32_t tot = 0;
@@ -500,13 +585,23 @@ Err build_sparsified(const diaf_csc* A, const diaf_sparsify* sp, int32_t* Jcp, i
         rows = *Jri_out;
     }
     if (rows) {
-        DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l,
-                                  nullptr, n, 0, nullptr, Jcp, rows, nullptr, nullptr, st));
-        DIAF_TRY(launch_sp_expand(n, A->colptr, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l,
-                                  deferred, ndef, 1, nullptr, Jcp, rows, nullptr, nullptr, st));
+        DIAF_TRY(launch_sp_expand<T>(n, Scp, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l, rb,
+                                     nullptr, n, 0, nullptr, Jcp, rows, nullptr, nullptr, st));
+        DIAF_TRY(launch_sp_expand<T>(n, Scp, Sri, Sval, scnt, sp->k, sp->tau_l, sp->p_l, rb,
+                                     deferred, ndef, 1, nullptr, Jcp, rows, nullptr, nullptr, st));
     }
     DIAF_TRY(sync(st));
     return {};
+}
+
+Err build_sparsified(const diaf_csc* A, const diaf_sparsify* sp, int32_t* Jcp, int32_t** Jri_out,
+                     int64_t* nnz_out, bool alloc_rows, int32_t* rows_given, hipStream_t st)
+{
+    DIAF_TRY(check_sparsify(sp));
+    return A->dtype == DIAF_F64
+               ? build_sparsified_t<double>(A, sp, Jcp, Jri_out, nnz_out, alloc_rows, rows_given,
+                                            st)
+               : build_sparsified_t<zc>(A, sp, Jcp, Jri_out, nnz_out, alloc_rows, rows_given, st);
 }
 
 // Builds the W pattern (colptr, rowidx allocated here unless provided).
@@ -1393,10 +1488,8 @@ diaf_status diaf_pattern_build_sparsified(diaf_ctx* ctx, const diaf_csc* A,
     if (!colptr_out || !nnz_host) return fail(ctx, DIAF_EINVAL, "NULL output");
     e = check_sparsify(prm);
     if (e.code) return fail(ctx, e);
-    if (A->dtype != DIAF_F64)
-        return fail(ctx, DIAF_EUNSUPPORTED, "sparsified powers: real matrices only");
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
-    e = validate_A<double>(A, ctx->stream);
+    e = A->dtype == DIAF_F64 ? validate_A<double>(A, ctx->stream) : validate_A<zc>(A, ctx->stream);
     if (e.code) return fail(ctx, e);
     int32_t* none = nullptr;
     e = build_sparsified(A, prm, colptr_out, &none, nnz_host, false, rowidx_out, ctx->stream);

@@ -25,22 +25,45 @@ template <class T>
 Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
                         int cand_max, const int32_t* cols, int ncols, int32_t* cnt,
                         const int32_t* Jcp, int32_t* Jri, hipStream_t st);
-// Sparsified powers (Algorithm 1, real A): d = diag(A) (bit 0 of *bad on a
-// zero); S = D^{-1}(A - D) sparsified by (tau, p) per column in A's column
-// layout with scnt[c] entries (bit 1 of *bad for a column of A longer than
-// 1024); the level expansion for cols (null: all n columns), count (Jri
-// null: cnt[j]) or fill, columns outgrowing the LDS tables appended to over.
+// Sparsified powers (Algorithm 1, real or complex A).  Diagonal V_0: d =
+// diag(A) (bit 0 of *bad on a zero); S = D^{-1}(A - D) sparsified by (tau,
+// p) per column in A's column layout with scnt[c] entries.  Block diagonal
+// V_0 (rb: per row its block's rows [rb[2i], rb[2i+1]); bid: its block):
+// D = A's block diagonal part in CSC (count pass, then fill), its blocks
+// factored by launch_block_lu, and S built by block solves in its own
+// layout Scp (count pass, then fill).  Bit 1 of *bad: a column of A, or of
+// S before dropping, longer than 1024.  The level expansion for cols (null:
+// all n columns), count (Jri null: cnt[j]) or fill, with the rows of j's
+// block other than j removed (rb null: no removal), columns outgrowing the
+// LDS tables appended to over.
 constexpr int SP_TC_SMALL = 256, SP_SC_SMALL = 512;    // power vector / pattern rows
-constexpr int SP_TC_LARGE = 2048, SP_SC_LARGE = 4096;
-Err launch_sp_diag(int n, const int32_t* Acp, const int32_t* Ari, const double* Aval, double* d,
+template <class T>
+struct SpCaps {  // the larger LDS tables (complex values take twice the room)
+    static constexpr int TL = num<T>::is_complex ? 1024 : 2048;
+    static constexpr int SL = num<T>::is_complex ? 2048 : 4096;
+};
+template <class T>
+Err launch_sp_diag(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, T* d,
                    int32_t* bad, hipStream_t st);
-Err launch_sp_build_s(int n, const int32_t* Acp, const int32_t* Ari, const double* Aval,
-                      const double* d, double tau, int p, int32_t* Sri, double* Sval,
-                      int32_t* scnt, int32_t* bad, hipStream_t st);
-Err launch_sp_expand(int n, const int32_t* Acp, const int32_t* Sri, const double* Sval,
-                     const int32_t* scnt, int k, double tau, int p, const int32_t* cols, int ncols,
-                     int large, int32_t* cnt, const int32_t* Jcp, int32_t* Jri, int32_t* over,
-                     int32_t* nover, hipStream_t st);
+template <class T>
+Err launch_sp_build_s(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, const T* d,
+                      double tau, int p, int32_t* Sri, T* Sval, int32_t* scnt, int32_t* bad,
+                      hipStream_t st);
+template <class T>
+Err launch_sp_block_d(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
+                      const int32_t* rb, int32_t* cnt, const int32_t* Dcp, int32_t* Dri, T* Dval,
+                      hipStream_t st);
+template <class T>
+Err launch_sp_build_s_block(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
+                            const int32_t* rb, const int32_t* bid, const int32_t* bstart,
+                            const int64_t* boff, const T* LU, const int32_t* perm, double tau,
+                            int p, int32_t* scnt, const int32_t* Scp, int32_t* Sri, T* Sval,
+                            int32_t* bad, hipStream_t st);
+template <class T>
+Err launch_sp_expand(int n, const int32_t* Scp, const int32_t* Sri, const T* Sval,
+                     const int32_t* scnt, int k, double tau, int p, const int32_t* rb,
+                     const int32_t* cols, int ncols, int large, int32_t* cnt, const int32_t* Jcp,
+                     int32_t* Jri, int32_t* over, int32_t* nover, hipStream_t st);
 // Per-column sizes for bucketing: k[j] = |J_j|, t[j] = sum nnz(A(:, J_j)).
 Err launch_column_sizes(int n, const int32_t* Acp, const int32_t* Jcp, const int32_t* Jri,
                         int32_t* kout, int32_t* tout, hipStream_t st);

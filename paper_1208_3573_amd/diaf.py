@@ -43,8 +43,8 @@ class diaf_pattern(ctypes.Structure):
 
 
 class diaf_sparsify(ctypes.Structure):
-    _fields_ = [("k", c_int32), ("p_i", c_int32), ("p_l", c_int32), ("reserved", c_int32),
-                ("tau_i", c_double), ("tau_l", c_double)]
+    _fields_ = [("k", c_int32), ("p_i", c_int32), ("p_l", c_int32), ("v0_nblocks", c_int32),
+                ("tau_i", c_double), ("tau_l", c_double), ("v0_blocks", c_void_p)]
 
 
 class diaf_spec(ctypes.Structure):
@@ -283,7 +283,7 @@ def make_spec(w="A", v="diag", v_count=0, w_topk=0, w_explicit: DevicePattern | 
         assert v_blocks.dtype == _torch().int32 and v_blocks.is_cuda
         spec.v_blocks = c_void_p(v_blocks.data_ptr())
         spec.v_nblocks = v_blocks.numel() - 1
-    spec._keep = (w_explicit, v_explicit, model, v_blocks)
+    spec._keep = (w_explicit, v_explicit, model, v_blocks, (sparsify or {}).get("v0_blocks"))
     return spec
 
 
@@ -396,19 +396,26 @@ def diaf_solve(ctx: Context, A: DeviceCSC, F: Factors | None, b, x, rtol=1e-8, m
     return info
 
 
-def make_sparsify(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0) -> diaf_sparsify:
+def make_sparsify(k=3, tau_i=0.1, p_i=0, tau_l=0.0, p_l=0, v0_blocks=None) -> diaf_sparsify:
+    """v0_blocks: None (V_0 diagonal) or an int32 device tensor of block
+    starts 0 .. n (V_0 block diagonal); the caller keeps it alive."""
     sp = diaf_sparsify()
-    sp.k, sp.p_i, sp.p_l, sp.reserved = k, p_i, p_l, 0
+    sp.k, sp.p_i, sp.p_l = k, p_i, p_l
     sp.tau_i, sp.tau_l = tau_i, tau_l
+    sp.v0_nblocks, sp.v0_blocks = 0, None
+    if v0_blocks is not None:
+        assert v0_blocks.dtype == _torch().int32 and v0_blocks.is_cuda
+        sp.v0_nblocks = v0_blocks.numel() - 1
+        sp.v0_blocks = c_void_p(v0_blocks.data_ptr())
     return sp
 
 
 def diaf_pattern_build_sparsified(ctx: Context, A: DeviceCSC, k=3, tau_i=0.1, p_i=0, tau_l=0.0,
-                                  p_l=0):
+                                  p_l=0, v0_blocks=None):
     """Sparsified powers W pattern (Algorithm 1) on the device; returns
     (colptr, rowidx) tensors."""
     torch = _torch()
-    sp = make_sparsify(k, tau_i, p_i, tau_l, p_l)
+    sp = make_sparsify(k, tau_i, p_i, tau_l, p_l, v0_blocks)
     cp = torch.empty(A.n + 1, dtype=torch.int32, device=A.colptr.device)
     nnz = c_int64()
     ctx.check(ctx.lib.diaf_pattern_build_sparsified(ctx.h, ctypes.byref(A.desc), ctypes.byref(sp),

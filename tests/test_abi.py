@@ -58,9 +58,9 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(diaf.diaf_csc) == 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(diaf.diaf_pattern) == 32
     assert ctypes.sizeof(diaf.diaf_solve_info) == 4 + 4 + 8 + 8 + 8
-    assert ctypes.sizeof(diaf.diaf_sparsify) == 4 * 4 + 8 + 8
-    assert diaf.diaf_spec.sparsify.offset == 80 and diaf.diaf_spec.v_blocks.offset == 112
-    assert diaf.diaf_spec.left.offset == 124 and ctypes.sizeof(diaf.diaf_spec) == 128
+    assert ctypes.sizeof(diaf.diaf_sparsify) == 4 * 4 + 8 + 8 + 8
+    assert diaf.diaf_spec.sparsify.offset == 80 and diaf.diaf_spec.v_blocks.offset == 120
+    assert diaf.diaf_spec.left.offset == 132 and ctypes.sizeof(diaf.diaf_spec) == 136
     assert diaf.MLP_NPARAM == 5313
 
 
