@@ -691,46 +691,52 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
     int32_t maxcand = 0;
     DIAF_TRY(read1(mx, &maxcand, st));
     // 1-hop rule: columns grouped by their number of two-hop candidates, so
-    // each launch sizes its LDS for its own class, not for the largest column
-    struct HopClass { int cand_max; std::vector<int32_t> cols; int32_t* dev = nullptr; };
+    // each launch sizes its LDS for its own class, not for the largest
+    // column; the grouping is a class sort on the device (as for the factor
+    // launches), and only the class counts come back to the host
+    struct HopClass { int cand_max; int count; const int32_t* cols; };
     std::vector<HopClass> hop;
+    int32_t *hsorted = nullptr, *hmeta = nullptr;
     struct HopFree {
-        std::vector<HopClass>* h;
-        ~HopFree() { for (auto& c : *h) dfree(c.dev); }
-    } hopfree{&hop};
+        int32_t** a; int32_t** b;
+        ~HopFree() { dfree(*a); dfree(*b); }
+    } hopfree{&hsorted, &hmeta};
     if (w_kind == DIAF_W_A_1HOP_TOPK) {
-        std::vector<int32_t> tn(n);
-        DIAF_HIP_TRY(hipMemcpyAsync(tn.data(), cnt, sizeof(int32_t) * n, hipMemcpyDeviceToHost, st));
+        ColumnClasses hc{};
+        const int bounds[] = {256, 512, 1024, 2048, 4096};
+        hc.ncls = 5;
+        for (int c = 0; c < hc.ncls; ++c) hc.kcap[c] = hc.tcap[c] = bounds[c] - w_topk - 1;
+        DIAF_TRY(dmalloc(&hsorted, sizeof(int32_t) * (size_t)std::max(n, 1)));
+        DIAF_TRY(dmalloc(&hmeta, sizeof(int32_t) * (ColumnClasses::kMax + 1)));
+        DIAF_TRY(launch_classify_columns(n, n, nullptr, cnt, cnt, hc, hsorted, hmeta, nullptr, st));
+        int32_t hm[ColumnClasses::kMax + 1] = {};
+        DIAF_HIP_TRY(hipMemcpyAsync(hm, hmeta, sizeof(int32_t) * (hc.ncls + 1),
+                                    hipMemcpyDeviceToHost, st));
         DIAF_TRY(sync(st));
-        for (int bound : {256 - w_topk - 1, 512 - w_topk - 1, 1024 - w_topk - 1, 2048 - w_topk - 1,
-                          4096 - w_topk - 1})
-            hop.push_back({bound, {}});
-        for (int j = 0; j < n; ++j) {
-            size_t c = 0;
-            while (c + 1 < hop.size() && tn[j] > hop[c].cand_max) ++c;
-            if (tn[j] > hop[c].cand_max)
-                return {DIAF_EUNSUPPORTED, "1-hop pattern: too many two-hop candidates in a column"};
-            hop[c].cols.push_back(j);
-        }
-        for (auto& c : hop) {
-            if (c.cols.empty()) continue;
-            DIAF_TRY(dmalloc(&c.dev, sizeof(int32_t) * c.cols.size()));
-            DIAF_HIP_TRY(hipMemcpyAsync(c.dev, c.cols.data(), sizeof(int32_t) * c.cols.size(),
-                                        hipMemcpyHostToDevice, st));
+        if (hm[hc.ncls] > 0)
+            return {DIAF_EUNSUPPORTED, "1-hop pattern: too many two-hop candidates in a column"};
+        int off = 0;
+        for (int c = 0; c < hc.ncls; ++c) {
+            if (hm[c]) hop.push_back({hc.kcap[c], hm[c], hsorted + off});
+            off += hm[c];
         }
     }
-    const auto run_1hop = [&](int32_t* cnt_out, const int32_t* Jcp_in, int32_t* rows_out) -> Err {
-        for (auto& c : hop)
-            DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk,
-                                            c.cand_max, c.dev, (int)c.cols.size(), cnt_out, Jcp_in,
-                                            rows_out, st));
-        return {};
-    };
-    if (w_kind == DIAF_W_A2)
+    // the 1-hop rule runs once into per-column slots (capacity |A(:, j)| +
+    // w_topk), which are packed after the scan of the counts
+    int32_t* slots = nullptr;
+    struct SlotFree {
+        int32_t** p;
+        ~SlotFree() { dfree(*p); }
+    } slotfree{&slots};
+    if (w_kind == DIAF_W_A2) {
         DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, A->colptr, A->rowidx, maxcand, cnt,
                                    nullptr, nullptr, st));
-    else
-        DIAF_TRY(run_1hop(cnt, nullptr, nullptr));
+    } else {
+        DIAF_TRY(dmalloc(&slots, sizeof(int32_t) * ((size_t)A->nnz + (size_t)n * w_topk + 1)));
+        for (auto& c : hop)
+            DIAF_TRY(launch_pattern_1hop<T>(n, A->colptr, A->rowidx, (const T*)A->val, w_topk,
+                                            c.cand_max, c.cols, c.count, cnt, slots, st));
+    }
     DIAF_TRY(exclusive_scan_i32(cnt, Jcp, n, st));
     int32_t tot = 0;
     DIAF_TRY(read1(Jcp + n, &tot, st));
@@ -745,7 +751,7 @@ Err build_pattern(const diaf_csc* A, int w_kind, int w_topk, int32_t* Jcp, int32
             DIAF_TRY(launch_pattern_a2(n, A->colptr, A->rowidx, A->colptr, A->rowidx, maxcand,
                                        nullptr, Jcp, rows, st));
         else
-            DIAF_TRY(run_1hop(nullptr, Jcp, rows));
+            DIAF_TRY(launch_compact_slots(n, A->colptr, w_topk, cnt, slots, Jcp, rows, st));
     }
     DIAF_TRY(sync(st));
     dfree(cnt);

@@ -20,11 +20,16 @@ Err launch_pattern_a2(int n, const int32_t* Ocp, const int32_t* Ori, const int32
 // lower): count (Vri == nullptr: writes cnt[j]) or fill.
 Err launch_v0_pattern(int n, const int32_t* Acp, const int32_t* Ari, int v0, int32_t* cnt,
                       const int32_t* Vcp, int32_t* Vri, hipStream_t st);
-// pattern(A) plus the ptop two-hop rows of largest |A|^2 path weight.
+// pattern(A) plus the ptop two-hop rows of largest |A|^2 path weight, for
+// the columns cols: cnt[j] rows, ascending, into column j's slot of Jtmp at
+// Acp[j] + j ptop (capacity |A(:, j)| + ptop); launch_compact_slots then
+// packs the slots at Jcp.
 template <class T>
 Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
                         int cand_max, const int32_t* cols, int ncols, int32_t* cnt,
-                        const int32_t* Jcp, int32_t* Jri, hipStream_t st);
+                        int32_t* Jtmp, hipStream_t st);
+Err launch_compact_slots(int n, const int32_t* Acp, int ptop, const int32_t* cnt,
+                         const int32_t* Jtmp, const int32_t* Jcp, int32_t* Jri, hipStream_t st);
 // Sparsified powers (Algorithm 1, real or complex A).  Diagonal V_0: d =
 // diag(A) (bit 0 of *bad on a zero); S = D^{-1}(A - D) sparsified by (tau,
 // p) per column in A's column layout with scnt[c] entries.  Block diagonal

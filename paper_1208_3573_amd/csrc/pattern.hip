@@ -327,7 +327,7 @@ Err launch_pattern_a2(int n, const int32_t* Ocp, const int32_t* Ori, const int32
 template <class T>
 __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
                                     int ptop, int cap, const int32_t* cols, int32_t* cnt,
-                                    const int32_t* Jcp, int32_t* Jri)
+                                    int32_t* Jtmp)
 {
     extern __shared__ __align__(16) unsigned char lds[];
     uint64_t* keys = (uint64_t*)lds;
@@ -341,14 +341,30 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     const int j = cols[blockIdx.x];
     const int tid = threadIdx.x;
     const int a0 = Acp[j], na = Acp[j + 1] - a0;
-    if (tid == 0) {
-        off[0] = 0;
-        for (int q = 0; q < na; ++q) {
-            int c = Ari[a0 + q];
-            off[q + 1] = off[q] + (Acp[c + 1] - Acp[c]);
+    // off[q + 1] = total length of A(:, c) over the first q + 1 columns c of
+    // pattern(A(:, j)): a block-wide inclusive scan, blockDim.x at a time
+    if (tid == 0) off[0] = 0;
+    int carry = 0;
+    for (int q0 = 0; q0 < na; q0 += blockDim.x) {
+        const int q = q0 + tid;
+        int len = 0;
+        if (q < na) {
+            const int c = Ari[a0 + q];
+            len = Acp[c + 1] - Acp[c];
         }
-        s_tot = off[na];
+        red[tid] = len;
+        __syncthreads();
+        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+            const int v = tid >= o ? red[tid - o] : 0;
+            __syncthreads();
+            red[tid] += v;
+            __syncthreads();
+        }
+        if (q < na) off[q + 1] = carry + red[tid];
+        carry += red[blockDim.x - 1];
+        __syncthreads();
     }
+    if (tid == 0) s_tot = carry;
     __syncthreads();
     const int Tn = s_tot;
     int T2 = 1;
@@ -436,12 +452,33 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     }
     __syncthreads();
     block_bitonic(keys, N2);
-    if (!Jri) {
-        if (tid == 0) cnt[j] = tot;
-        return;
-    }
-    int32_t* out = Jri + Jcp[j];
+    // into the column's slot of capacity |A(:, j)| + ptop
+    if (tid == 0) cnt[j] = tot;
+    int32_t* out = Jtmp + a0 + (size_t)j * ptop;
     for (int t = tid; t < tot; t += blockDim.x) out[t] = (int32_t)keys[t];
+}
+
+// Jri[Jcp[j] ..] = the cnt[j] rows of column j's slot in Jtmp (one wave per
+// column).
+__global__ void compact_slots_kernel(int n, const int32_t* Acp, int ptop, const int32_t* cnt,
+                                     const int32_t* Jtmp, const int32_t* Jcp, int32_t* Jri)
+{
+    const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= n) return;
+    const int32_t* src = Jtmp + Acp[j] + (size_t)j * ptop;
+    int32_t* dst = Jri + Jcp[j];
+    for (int t = lane; t < cnt[j]; t += 64) dst[t] = src[t];
+}
+
+Err launch_compact_slots(int n, const int32_t* Acp, int ptop, const int32_t* cnt,
+                         const int32_t* Jtmp, const int32_t* Jcp, int32_t* Jri, hipStream_t st)
+{
+    if (n == 0) return {};
+    hipLaunchKernelGGL(compact_slots_kernel, dim3((n + 3) / 4), dim3(256), 0, st, n, Acp, ptop, cnt,
+                       Jtmp, Jcp, Jri);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
 }
 
 // cols: the columns of one size class, all with at most cand_max two-hop
@@ -450,7 +487,7 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
 template <class T>
 Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval, int ptop,
                         int cand_max, const int32_t* cols, int ncols, int32_t* cnt,
-                        const int32_t* Jcp, int32_t* Jri, hipStream_t st)
+                        int32_t* Jtmp, hipStream_t st)
 {
     if (ncols == 0) return {};
     if (ptop > 256 || ptop < 0) return {DIAF_EUNSUPPORTED, "1-hop pattern: 0..256 extra rows"};
@@ -463,16 +500,15 @@ Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* 
     DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
     hipLaunchKernelGGL(kern, dim3(ncols), dim3(nt), lds, st, n, Acp, Ari, Aval, ptop, cap, cols, cnt,
-                       Jcp, Jri);
+                       Jtmp);
     DIAF_HIP_TRY(hipGetLastError());
     return {};
 }
 
 template Err launch_pattern_1hop<double>(int, const int32_t*, const int32_t*, const double*, int,
-                                         int, const int32_t*, int, int32_t*, const int32_t*,
-                                         int32_t*, hipStream_t);
+                                         int, const int32_t*, int, int32_t*, int32_t*,
+                                         hipStream_t);
 template Err launch_pattern_1hop<zc>(int, const int32_t*, const int32_t*, const zc*, int, int,
-                                     const int32_t*, int, int32_t*, const int32_t*, int32_t*,
-                                     hipStream_t);
+                                     const int32_t*, int, int32_t*, int32_t*, hipStream_t);
 
 }  // namespace diaf
