@@ -528,6 +528,21 @@ def main():
     if solves:
         out |= {"solve_ms": solve_ms, "bicgstab_iters": iters, "relres_true": float(R[-1, 7]),
                 "v_levels": levels}
+        # refactoring the same pattern (time stepping): the first call records
+        # the factor launches, later ones replay them as one graph
+        rt = []
+        for _ in range(1 + max(3, args.steps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            diaf.diaf_refactor(ctx, dA, last)
+            torch.cuda.synchronize()
+            rt.append((time.perf_counter() - t0) * 1e3)
+        rst = last.stats()
+        out["refactor"] = {"first_ms": rt[0], "replay_ms": float(np.median(rt[1:])),
+                           "replay_kernels_ms": rst.ms_factor, "factor_ms": factor_ms,
+                           "graph": bool(ctx.get_option("factor_graph"))
+                           and args.mode == "unit_v"}
+        log(f"refactor: first {rt[0]:.2f} ms, replay {np.median(rt[1:]):.2f} ms")
     last.close()
 
     if solves and not args.no_learned:

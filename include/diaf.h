@@ -327,6 +327,8 @@ diaf_status diaf_copy(struct diaf_ctx* ctx, void* dst, const void* src, size_t b
  *                        with shadows beyond 64 rows go to the generic kernel)
  *   "class_table"        size classes of the factor launches (0 default, 0..3;
  *                        every table sends the same columns to each kernel)
+ *   "factor_graph"       1 (default): diaf_refactor replays the recorded factor
+ *                        launches (unit-norm v) as one captured graph
  *   "small_grid"         workgroups of the one-wave factor kernel (0 = 4096)
  *   "generic_nt"         threads per column of the generic kernel (0 auto, 64,
  *                        128, 256, 512)
@@ -410,6 +412,27 @@ diaf_status diaf_factors_levels(struct diaf_ctx* ctx, const struct diaf_factors*
 void diaf_factors_destroy(struct diaf_factors* F);
 
 /* ---- apply and solve (eq. 2.1, Section 5) -------------------------------- */
+
+/* Refactor F in place for new values of the matrix it was built from: A
+ * must be the same descriptor contents as at diaf_factor (the same colptr,
+ * rowidx and val buffers, n and nnz), with new values written into val and
+ * the pattern unchanged (checked against a 64-bit fingerprint taken at
+ * factor time).  The W pattern and V's capacity are kept; the columns are
+ * factored again with F's spec and mode (the V pattern rule runs again, as
+ * Section 3.1's selection depends on the values), V is assembled and the
+ * statistics retaken; the apply structures are rebuilt on the next apply.
+ * The first refactor runs the factor launches eagerly and records them;
+ * for DIAF_UNIT_V later calls replay them as one captured hipGraph (context
+ * option "factor_graph", default 1); unit-norm w, whose hand-over of
+ * rank-deficient columns depends on the values, always runs eagerly.
+ * Results are those of diaf_factor on the new values.  Errors: DIAF_EINVAL
+ * (other buffers or sizes, a changed pattern, factors of another context,
+ * or a replay whose hand-over counts differ from the recorded pass: factor
+ * afresh), DIAF_EUNSUPPORTED (the left variant, or a W pattern that depends
+ * on the values: 1-hop, sparsified powers, learned), DIAF_EDEVICE.  For
+ * time stepping with a fixed sparsity pattern (Section 5's setting of
+ * repeated solves). */
+diaf_status diaf_refactor(struct diaf_ctx* ctx, const diaf_csc* A, struct diaf_factors* F);
 
 /* y = W V^{-1} x for triangular, diagonal or block diagonal V (n entries
  * each); y = V^{-1} W x for factors of the left variant (diaf_spec.left).

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -33,6 +34,7 @@ struct diaf_ctx {
     int64_t opt_gate_small_diag = 1;
     int64_t opt_graph = 0;
     int64_t opt_class_table = 0;  // index into kClassTables
+    int64_t opt_factor_graph = 1;  // diaf_refactor replays the factor launches as a graph
     diaf::TrsvTune trsv;
     diaf::FactorTune ftune;
     hipStream_t gstream = nullptr;  // library stream for captured solve batches
@@ -48,6 +50,19 @@ struct diaf_model {
     size_t scratch_pairs = 0;
     double* loss = nullptr;
     int step = 0;
+};
+
+// The factor launches of one pass, recorded for diaf_refactor: each launch
+// with its arguments (column lists, deferred lists and workspaces kept
+// alive in bufs), the deferred counters with the counts of the recorded
+// pass, and the graph captured from them.
+struct FactorPlan {
+    std::vector<std::function<diaf::Err(hipStream_t)>> launches;
+    std::vector<void*> bufs;
+    std::vector<std::pair<int32_t*, int32_t>> counters;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    diaf_stats stats{};  // the column and launch statistics of the recorded pass
 };
 
 struct diaf_factors {
@@ -90,6 +105,15 @@ struct diaf_factors {
     int32_t *vpat_cp = nullptr, *vpat_ri = nullptr;
     // left variant: W, V above are those of W A ~ V (M = V^{-1} W)
     int left = 0;
+    // refactoring with the same pattern: the spec, the matrix buffers and a
+    // hash of A's pattern at factor time, and the recorded factor launches
+    diaf_spec spec{};
+    const int32_t* src_cp = nullptr;
+    const int32_t* src_ri = nullptr;
+    const void* src_val = nullptr;
+    int64_t src_nnz = 0;
+    uint64_t pat_hash = 0;
+    FactorPlan* plan = nullptr;
 };
 
 namespace {
@@ -769,6 +793,12 @@ void free_factors(diaf_factors* F)
                     (void*)F->bstart, (void*)F->boff, F->blu, (void*)F->bperm,
                     (void*)F->vpat_cp, (void*)F->vpat_ri})
         dfree(p);
+    if (F->plan) {
+        if (F->plan->exec) (void)hipGraphExecDestroy(F->plan->exec);
+        if (F->plan->graph) (void)hipGraphDestroy(F->plan->graph);
+        for (void* p : F->plan->bufs) dfree(p);
+        delete F->plan;
+    }
     delete F;
 }
 
@@ -850,9 +880,12 @@ const ClassTable kClassTables[] = {
 };
 constexpr int kNumClassTables = (int)(sizeof(kClassTables) / sizeof(kClassTables[0]));
 
+// rec: when given, the factor launches are also recorded there (with the
+// buffers they read kept alive) for replay by diaf_refactor.
 template <class T>
 Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
-                   diaf_factors* F, const std::vector<int32_t>* only, int* nbuckets)
+                   diaf_factors* F, const std::vector<int32_t>* only, int* nbuckets,
+                   FactorPlan* rec = nullptr)
 {
     hipStream_t st = ctx->stream;
     const int n = (int)A->n;
@@ -861,9 +894,10 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         std::vector<void*>* v;
         ~FreeAll() { for (void* p : *v) dfree(p); }
     } free_all{&to_free};
+    std::vector<void*>& keep = rec ? rec->bufs : to_free;
     const auto scratch = [&](int32_t** p, size_t count) -> Err {
         DIAF_TRY(dmalloc(p, sizeof(int32_t) * std::max<size_t>(count, 1)));
-        to_free.push_back(*p);
+        keep.push_back(*p);
         return {};
     };
     // per-column sizes, then the columns sorted by size class on the device
@@ -966,7 +1000,8 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             }
         }
     } free_events{&events};
-    const auto timed = [&](int cls, auto&& launch) -> Err {
+    // one factor launch: timed with events, and recorded for replay
+    const auto timed = [&](int cls, std::function<Err(hipStream_t)> launch) -> Err {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         DIAF_HIP_TRY(hipEventCreate(&e0));
         if (hipEventCreate(&e1) != hipSuccess) {
@@ -976,8 +1011,18 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         events.push_back({e0, e1});
         ev_class.push_back(cls);
         DIAF_HIP_TRY(hipEventRecord(e0, st));
-        DIAF_TRY(launch());
+        DIAF_TRY(launch(st));
         DIAF_HIP_TRY(hipEventRecord(e1, st));
+        if (rec) rec->launches.push_back(std::move(launch));
+        return {};
+    };
+    // a counter cleared before its launch (by a kernel, so that a captured
+    // graph holds no memset node)
+    const auto clear_counter = [&](int32_t* c) -> Err {
+        DIAF_HIP_TRY(hipMemsetAsync(c, 0, sizeof(int32_t), st));
+        if (rec)
+            rec->launches.push_back(
+                [c](hipStream_t s) -> Err { return noalloc_clear(c, sizeof(int32_t), s); });
         return {};
     };
     int nb = 0;
@@ -995,15 +1040,17 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             int32_t *defl = nullptr, *ndef = nullptr, *dsorted = nullptr, *dtmp = nullptr;
             DIAF_TRY(scratch(&defl, nsmall));
             DIAF_TRY(scratch(&ndef, 1));
-            DIAF_HIP_TRY(hipMemsetAsync(ndef, 0, sizeof(int32_t), st));
+            DIAF_TRY(clear_counter(ndef));
             fa.cols = sorted;
             fa.ncols = nsmall;
-            DIAF_TRY(timed(-1, [&] {
-                return launch_factor_small<T>(fa, defl, ndef, ctx->ftune, st);
+            const FactorTune tune = ctx->ftune;
+            DIAF_TRY(timed(-1, [fa, defl, ndef, tune](hipStream_t s) -> Err {
+                return launch_factor_small<T>(fa, defl, ndef, tune, s);
             }));
             ++nb;
             int32_t nd = 0;
             DIAF_TRY(read1(ndef, &nd, st));
+            if (rec) rec->counters.push_back({ndef, nd});
             F->stats.cols_small += nsmall - nd;
             F->stats.occ_small = small_occupancy<T>(mode);
             if (nd > 0) {
@@ -1047,7 +1094,7 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
             DIAF_TRY(scratch(&mndef, 1));
             DIAF_TRY(scratch(&mcols, nmid));
             DIAF_TRY(scratch(&msorted, nmid));
-            DIAF_HIP_TRY(hipMemsetAsync(mndef, 0, sizeof(int32_t), st));
+            DIAF_TRY(clear_counter(mndef));
             int moff = 0;
             for (const Seg& g : segs) {
                 if (!mid_supports<T>(cc.kcap[g.c], cc.tcap[g.c])) {
@@ -1074,14 +1121,16 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
                 fa.ncols = mh[c];
                 mo += mh[c];
                 const int kcap = mcc.kcap[c], tcap = mcc.tcap[c];
-                DIAF_TRY(timed(-2, [&] {
-                    return launch_factor_mid<T>(fa, kcap, tcap, mdefl, mndef, ctx->ftune, st);
+                const FactorTune tune = ctx->ftune;
+                DIAF_TRY(timed(-2, [fa, kcap, tcap, mdefl, mndef, tune](hipStream_t s) -> Err {
+                    return launch_factor_mid<T>(fa, kcap, tcap, mdefl, mndef, tune, s);
                 }));
                 ++nb;
                 F->stats.occ_mid = mid_occupancy<T>(kcap, tcap);
             }
             int32_t nd = 0;
             DIAF_TRY(read1(mndef, &nd, st));
+            if (rec) rec->counters.push_back({mndef, nd});
             F->stats.cols_mid += nmid - nd;
             if (nd > 0) {
                 int32_t *dtmp = nullptr, *dsorted = nullptr;
@@ -1115,10 +1164,12 @@ Err factor_columns(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int 
         void* gm = nullptr;
         if (gbytes) {
             DIAF_TRY(dmalloc((unsigned char**)&gm, gbytes));
-            to_free.push_back(gm);
+            keep.push_back(gm);
         }
-        DIAF_TRY(timed(g.c, [&] {
-            return launch_factor_generic<T>(fa, kcap, tcap, F->lmax, gm, nslots, ctx->ftune, st);
+        const FactorTune tune = ctx->ftune;
+        const int lcap = F->lmax;
+        DIAF_TRY(timed(g.c, [fa, kcap, tcap, lcap, gm, nslots, tune](hipStream_t s) -> Err {
+            return launch_factor_generic<T>(fa, kcap, tcap, lcap, gm, nslots, tune, s);
         }));
         F->stats.cols_generic_class[g.c] += g.count;
         F->stats.occ_generic_class[g.c] = generic_occupancy<T>(kcap, tcap, F->lmax, mode,
@@ -1197,6 +1248,18 @@ Err compute_stats(diaf_ctx* ctx, diaf_factors* F)
     F->stats.nnz_w = F->nnzW;
     F->stats.nnz_v = F->nnzV;
     return {};
+}
+
+Err pattern_hash(const diaf_csc* A, uint64_t* h, hipStream_t st)
+{
+    unsigned long long* d = nullptr;
+    DIAF_TRY(dmalloc(&d, sizeof(unsigned long long)));
+    Err e = launch_pattern_hash((int)A->n, A->nnz, A->colptr, A->rowidx, d, st);
+    unsigned long long v = 0;
+    if (e.code == DIAF_OK) e = read1(d, &v, st);
+    dfree(d);
+    *h = v;
+    return e;
 }
 
 template <class T>
@@ -1358,6 +1421,8 @@ Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mod
 template <class T>
 Err factor_left(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mode,
                 diaf_factors** out);
+template <class T>
+Err refactor_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F);
 
 }  // namespace
 
@@ -1410,6 +1475,7 @@ diaf_status diaf_ctx_get_option(const diaf_ctx* ctx, const char* key, int64_t* v
     else if (k == "small_grid") *value = ctx->ftune.small_grid;
     else if (k == "generic_nt") *value = ctx->ftune.generic_nt;
     else if (k == "class_table") *value = ctx->opt_class_table;
+    else if (k == "factor_graph") *value = ctx->opt_factor_graph;
     else return DIAF_EINVAL;
     return DIAF_OK;
 }
@@ -1439,6 +1505,7 @@ diaf_status diaf_ctx_set_option(diaf_ctx* ctx, const char* key, int64_t value)
             return fail(ctx, DIAF_EINVAL, "trsv_waves must be 1, 2, 4, 8 or 16");
         ctx->trsv.waves = (int)value;
     }
+    else if (k == "factor_graph") ctx->opt_factor_graph = value ? 1 : 0;
     else if (k == "class_table") {
         if (value < 0 || value >= kNumClassTables)
             return fail(ctx, DIAF_EINVAL,
@@ -1522,6 +1589,30 @@ diaf_status diaf_factor(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec,
     else
         e = A->dtype == DIAF_F64 ? factor_impl<double>(ctx, A, spec, mode, out)
                                  : factor_impl<zc>(ctx, A, spec, mode, out);
+    if (e.code) return fail(ctx, e);
+    return DIAF_OK;
+}
+
+diaf_status diaf_refactor(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F)
+{
+    if (!ctx) return DIAF_EINVAL;
+    if (!F) return fail(ctx, DIAF_EINVAL, "factors are NULL");
+    Err e = check_csc_host(A);
+    if (e.code) return fail(ctx, e);
+    if (F->ctx != ctx) return fail(ctx, DIAF_EINVAL, "refactor: factors of another context");
+    if (F->left) return fail(ctx, DIAF_EUNSUPPORTED, "refactor: not for the left variant");
+    const int wk = F->spec.w_kind;
+    if (!(wk == DIAF_W_A || wk == DIAF_W_A2 || wk == DIAF_W_EXPLICIT || wk == DIAF_W_ALG2_DIAG ||
+          wk == DIAF_W_ALG2_GS_UPPER || wk == DIAF_W_ALG2_GS_LOWER))
+        return fail(ctx, DIAF_EUNSUPPORTED,
+                    "refactor: the W pattern depends on the values (1-hop, sparsified powers, "
+                    "learned); factor afresh");
+    if (A->n != F->n || A->nnz != F->src_nnz || A->dtype != F->dtype || A->colptr != F->src_cp ||
+        A->rowidx != F->src_ri || A->val != F->src_val)
+        return fail(ctx, DIAF_EINVAL, "refactor: A must be the matrix the factors were built "
+                                      "from (same buffers), with new values in place");
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DIAF_EDEVICE, "hipSetDevice");
+    e = A->dtype == DIAF_F64 ? refactor_impl<double>(ctx, A, F) : refactor_impl<zc>(ctx, A, F);
     if (e.code) return fail(ctx, e);
     return DIAF_OK;
 }
@@ -1855,7 +1946,114 @@ Err factor_impl(diaf_ctx* ctx, const diaf_csc* A, const diaf_spec* spec, int mod
     F->stats.ms_pattern = ms[0];
     F->stats.ms_factor = ms[1];
     F->stats.ms_assemble = ms[2];
+    // what diaf_refactor needs: the spec, the matrix buffers, the pattern's
+    // fingerprint
+    F->spec = *spec;
+    F->src_cp = A->colptr;
+    F->src_ri = A->rowidx;
+    F->src_val = A->val;
+    F->src_nnz = A->nnz;
+    DIAF_TRY(pattern_hash(A, &F->pat_hash, st));
     *out = F.release();
+    return {};
+}
+
+// Refactor F in place for new values of the matrix it was built from (same
+// buffers, same pattern): the W pattern and the V pattern capacity are
+// kept; the factor kernels run again (the first time eagerly, recording
+// their launches; for unit-norm v later calls replay them as one captured
+// graph), then V is assembled and the statistics taken again.  The apply
+// structures are rebuilt on the next apply.
+template <class T>
+Err refactor_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F)
+{
+    hipStream_t st = ctx->stream;
+    const int n = (int)A->n;
+    DIAF_TRY(validate_A<T>(A, st));
+    uint64_t h = 0;
+    DIAF_TRY(pattern_hash(A, &h, st));
+    if (h != F->pat_hash)
+        return {DIAF_EINVAL, "refactor: the pattern of A differs from the one the factors were "
+                             "built from"};
+    // the apply structures of the old values
+    for (void** p : {(void**)&F->Wrp, (void**)&F->Wci, (void**)&F->Vrp, (void**)&F->Vci,
+                     &F->Wcv, &F->Vcv, &F->tmp, (void**)&F->ctl, &F->blu, (void**)&F->bperm}) {
+        dfree(*p);
+        *p = nullptr;
+    }
+    F->apply_ready = false;
+    hipEvent_t ev[3];
+    for (auto& e : ev) DIAF_HIP_TRY(hipEventCreate(&e));
+    struct EvFree {
+        hipEvent_t* e;
+        ~EvFree() { for (int i = 0; i < 3; ++i) (void)hipEventDestroy(e[i]); }
+    } evfree{ev};
+    DIAF_HIP_TRY(hipEventRecord(ev[0], st));
+    const bool graph = F->mode == DIAF_UNIT_V && ctx->opt_factor_graph;
+    if (graph && F->plan && F->plan->exec) {
+        DIAF_HIP_TRY(hipGraphLaunch(F->plan->exec, st));
+        std::vector<int32_t> got(F->plan->counters.size());
+        for (size_t q = 0; q < got.size(); ++q)
+            DIAF_HIP_TRY(hipMemcpyAsync(&got[q], F->plan->counters[q].first, sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, st));
+        DIAF_TRY(sync(st));
+        for (size_t q = 0; q < got.size(); ++q)
+            if (got[q] != F->plan->counters[q].second)
+                return {DIAF_EINVAL, "refactor: the columns handed between the factor kernels "
+                                     "changed; factor afresh"};
+        const diaf_stats keep = F->stats;
+        F->stats = F->plan->stats;
+        F->stats.ms_pattern = keep.ms_pattern;
+    } else {
+        // eager pass (recording it when a graph will replay it)
+        FactorPlan* rec = nullptr;
+        if (graph) {
+            if (F->plan) {
+                if (F->plan->exec) (void)hipGraphExecDestroy(F->plan->exec);
+                if (F->plan->graph) (void)hipGraphDestroy(F->plan->graph);
+                for (void* p : F->plan->bufs) dfree(p);
+                delete F->plan;
+            }
+            F->plan = new FactorPlan;
+            rec = F->plan;
+        }
+        const double pattern_ms = F->stats.ms_pattern;
+        std::memset(&F->stats, 0, sizeof(F->stats));
+        F->stats.ms_pattern = pattern_ms;
+        int nb = 0;
+        DIAF_TRY(factor_columns<T>(ctx, A, &F->spec, F->mode, F, nullptr, &nb, rec));
+        F->stats.nbuckets = nb;
+        if (rec) {
+            // captured on the library stream (the caller's may be the null
+            // stream, which cannot be captured); replayed on the caller's
+            rec->stats = F->stats;
+            if (!ctx->gstream)
+                DIAF_HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+            hipStream_t cs = ctx->gstream;
+            DIAF_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            Err ce{};
+            for (auto& L : rec->launches) {
+                ce = L(cs);
+                if (ce.code) break;
+            }
+            hipGraph_t g = nullptr;
+            const hipError_t he = hipStreamEndCapture(cs, &g);
+            DIAF_TRY(ce);
+            if (he != hipSuccess || !g) return {DIAF_EDEVICE, "refactor: graph capture failed"};
+            rec->graph = g;
+            DIAF_HIP_TRY(hipGraphInstantiate(&rec->exec, g, nullptr, nullptr, 0));
+        }
+    }
+    DIAF_HIP_TRY(hipEventRecord(ev[1], st));
+    DIAF_TRY(assemble_v<T>(ctx, F));
+    DIAF_HIP_TRY(hipEventRecord(ev[2], st));
+    DIAF_TRY(compute_stats<T>(ctx, F));
+    float ms[2] = {0, 0};
+    for (int i = 0; i < 2; ++i) DIAF_HIP_TRY(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+    F->stats.ms_factor = ms[0];
+    F->stats.ms_assemble = ms[1];
+    if (graph && F->plan && F->plan->exec) F->stats.ms_factor_kernels = ms[0];
+    (void)n;
     return {};
 }
 

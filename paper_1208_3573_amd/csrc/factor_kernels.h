@@ -158,6 +158,9 @@ Err launch_validate_pattern(int n, const int32_t* cp, const int32_t* ri, int nee
 template <class T>
 Err launch_diag_check(int n, const int32_t* rp, const int32_t* ci, const T* val, int32_t* bad_dev,
                       hipStream_t st);
+// 64-bit fingerprint of the pattern (colptr, rowidx) into *out.
+Err launch_pattern_hash(int n, int64_t nnz, const int32_t* cp, const int32_t* ri,
+                        unsigned long long* out, hipStream_t st);
 template <class T>
 Err launch_flag_stats(int n, const uint32_t* flags, const double* r, int32_t* counts_dev,
                       double* nrm2_dev, hipStream_t st);

@@ -330,4 +330,43 @@ Err launch_conj(int64_t n, T* v, hipStream_t st)
 template Err launch_conj<double>(int64_t, double*, hipStream_t);
 template Err launch_conj<zc>(int64_t, zc*, hipStream_t);
 
+
+// Order-independent 64-bit hash of a CSC pattern: the sum over all entries
+// of a mix of (position, value), colptr and rowidx hashed with different
+// salts.  A fingerprint for detecting a changed pattern, not a checksum of
+// any strength beyond that.
+__device__ inline uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+__global__ void pattern_hash_kernel(int n, int64_t nnz, const int32_t* cp, const int32_t* ri,
+                                    unsigned long long* out)
+{
+    uint64_t h = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n + nnz;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i <= n)
+            h += mix64(((uint64_t)i << 32) ^ (uint32_t)cp[i] ^ 0x5851f42d4c957f2dull);
+        else
+            h += mix64((((uint64_t)(i - n - 1)) << 32) ^ (uint32_t)ri[i - n - 1]);
+    }
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, (unsigned long long)h);
+}
+
+Err launch_pattern_hash(int n, int64_t nnz, const int32_t* cp, const int32_t* ri,
+                        unsigned long long* out, hipStream_t st)
+{
+    DIAF_HIP_TRY(hipMemsetAsync(out, 0, sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(pattern_hash_kernel, dim3(1024), dim3(256), 0, st, n, nnz, cp, ri, out);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
+}
+
 }  // namespace diaf

@@ -96,6 +96,7 @@ _SIGS = {
     "diaf_autotune": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_spec), c_int32]),
     "diaf_autotune_cached": (c_int, [c_void_p, POINTER(diaf_csc), POINTER(diaf_spec), c_int32,
                                      ctypes.c_char_p, POINTER(c_int32)]),
+    "diaf_refactor": (c_int, [c_void_p, POINTER(diaf_csc), c_void_p]),
     "diaf_copy": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t]),
     "diaf_pattern_build": (c_int, [c_void_p, POINTER(diaf_csc), c_int32, c_int32, c_void_p,
                                    c_void_p, POINTER(c_int64)]),
@@ -373,6 +374,13 @@ def diaf_autotune(ctx: Context, A: DeviceCSC, spec: diaf_spec, mode, cache: str 
                                                os.fsencode(cache), ctypes.byref(hit)))
         out["from_cache"] = bool(hit.value)
     return {k: ctx.get_option(k) for k in TUNE_KEYS} | out
+
+
+def diaf_refactor(ctx: Context, A: DeviceCSC, F: Factors):
+    """Refactor F in place after new values were written into A's value
+    buffer (same pattern, same buffers)."""
+    ctx.check(ctx.lib.diaf_refactor(ctx.h, ctypes.byref(A.desc), F.h))
+    return F
 
 
 def diaf_apply(ctx: Context, F: Factors, x, y):
