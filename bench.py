@@ -83,12 +83,14 @@ def algorithmic_flops(A, Jcp, Jri, lcount, mode):
 
 
 def kernel_source_sha(kernel):
-    """sha256 over the sources a factor kernel is compiled from."""
+    """sha256 over the sources a factor kernel's code comes from."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1208_3573_amd", "csrc")
-    files = {"factor_small_kernel": ["factor_small.hip", "dcommon.h", "factor_kernels.h"],
-             "factor_mid_kernel": ["factor_mid.hip", "dcommon.h", "factor_kernels.h"],
-             "factor_generic_kernel": ["factor_generic.hip", "dcommon.h", "factor_kernels.h"]}[kernel]
+    # the kernel's own source and the header that defines its arguments
+    # (factor_kernels.h holds only the launchers' declarations)
+    files = {"factor_small_kernel": ["factor_small.hip", "dcommon.h"],
+             "factor_mid_kernel": ["factor_mid.hip", "dcommon.h"],
+             "factor_generic_kernel": ["factor_generic.hip", "dcommon.h"]}[kernel]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
