@@ -69,7 +69,7 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
 
 // misc slots (int view / double view)
 enum { MI_T = 0, MI_M, MI_DJ, MI_FLAGS, MI_L, MI_NC, MI_ROT, MI_BEST, MI_Q, MI_EDGE, MI_NIN,
-       MI_STAB, MI_DPOS, MI_NULL };
+       MI_STAB, MI_DPOS, MI_NULL, MI_RDIG, MI_RREM };
 enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2, MD_ERE, MD_EIM, MD_FRO2 };
 
 template <class T>
@@ -113,27 +113,34 @@ __device__ inline double wave0_sum(GenCtx<T>& c, double x)
     return r;
 }
 
-// Inclusive scan of flags[0..cnt) (0/1) into out (ranks), returns total.
+// Inclusive scan of flags[0..cnt) (0/1) into out (ranks; out may be flags),
+// returns the total.  Each thread owns a contiguous chunk; the chunk sums are
+// scanned within each wave by shuffles and across the (at most 8) waves
+// through sRed.
 template <class T>
 __device__ inline int block_scan_flags(GenCtx<T>& c, const int32_t* flags, int32_t* out, int cnt)
 {
-    // each thread owns a contiguous chunk
-    int chunk = (cnt + c.nt - 1) / c.nt;
-    int b = c.tid * chunk, e = min(cnt, b + chunk);
+    const int chunk = (cnt + c.nt - 1) / c.nt;
+    const int b = c.tid * chunk, e = min(cnt, b + chunk);
     int s = 0;
     for (int i = b; i < e; ++i) s += flags[i];
-    c.sRed[c.tid] = (double)s;
-    __syncthreads();
-    if (c.tid == 0) {
-        double acc = 0;
-        for (int t = 0; t < c.nt; ++t) { double v = c.sRed[t]; c.sRed[t] = acc; acc += v; }
-        c.md[MD_SSTAR] = acc;
+    const int lane = c.tid & 63, wv = c.tid >> 6;
+    int x = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
     }
+    int* wtot = (int*)c.sRed;
+    if (lane == 63) wtot[wv] = x;
     __syncthreads();
-    int run = (int)c.sRed[c.tid];
+    int before = 0, tot = 0;
+    for (int w = 0; w < (c.nt >> 6); ++w) {
+        const int t = wtot[w];
+        before += w < wv ? t : 0;
+        tot += t;
+    }
+    int run = before + x - s;
     for (int i = b; i < e; ++i) { run += flags[i]; out[i] = run; }
-    __syncthreads();
-    int tot = (int)c.md[MD_SSTAR];
     __syncthreads();
     return tot;
 }
@@ -390,67 +397,102 @@ __device__ inline void jacobi_eig(GenCtx<T>& c, T* E, T* Z, int k)
     __syncthreads();
 }
 
+// The q-th largest (1-based) of the admissible scores sScore[0..m) (those
+// not below zero), found by radix selection on their bit patterns, which
+// order as the values for non-negative doubles: 8 passes over 8-bit digits
+// from the top, each counting the candidates that match the digits fixed so
+// far into 256 bins and fixing the digit in which the q-th falls.  The
+// caller guarantees more than q candidates.
+template <class T>
+__device__ inline double kth_largest_score(GenCtx<T>& c, int m, int q)
+{
+    int* hist = (int*)c.sRed;  // 256 counters (sRed holds GNT doubles)
+    uint64_t prefix = 0, mask = 0;
+    int rem = q;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = c.tid; b < 256; b += c.nt) hist[b] = 0;
+        __syncthreads();
+        for (int t = c.tid; t < m; t += c.nt) {
+            const double s = c.sScore[t];
+            if (s < 0.0) continue;
+            const uint64_t key = (uint64_t)__double_as_longlong(s) & 0x7fffffffffffffffull;
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1);
+        }
+        __syncthreads();
+        if (c.tid < 64) {
+            // lane l holds bins 255 - 4l down to 252 - 4l; counts accumulate
+            // from the top bin down
+            const int lane = c.tid;
+            int h[4], loc = 0;
+            for (int r = 0; r < 4; ++r) { h[r] = hist[255 - 4 * lane - r]; loc += h[r]; }
+            int x = loc;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            const int excl = x - loc;
+            if (excl < rem && rem <= x) {
+                int run = excl, r = 0;
+                while (r < 3 && run + h[r] < rem) { run += h[r]; ++r; }
+                c.mi[MI_RDIG] = 255 - 4 * lane - r;
+                c.mi[MI_RREM] = rem - run;
+            }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)(uint32_t)c.mi[MI_RDIG] << shift;
+        mask |= 255ull << shift;
+        rem = c.mi[MI_RREM];
+    }
+    return __longlong_as_double((long long)prefix);
+}
+
 // Top-q selection with the 1e-10 tie band over the m local rows;
 // sScore[i] = |(B w0)_i| for admissible rows and -1 otherwise (rows are in
-// ascending order).  Appends the chosen local rows, ascending, to sL from
-// index 1 (index 0 holds the diagonal).  Returns the count.
+// ascending order).  With s* the q-th largest score, every row above
+// s*(1 + 1e-10) is taken and the rest of the q come from the band
+// [s*(1 - 1e-10), s*(1 + 1e-10)] in ascending row order.  Writes the chosen
+// local rows, ascending, to sL from index 1 (index 0 holds the diagonal) and
+// returns the count.  sRank is free here and holds the flags and ranks.
 template <class T>
 __device__ inline int select_topk(GenCtx<T>& c, int m, int nc, int q)
 {
     if (q <= 0) return 0;
-    if (c.tid == 0) c.mi[MI_Q] = 0;
+    int32_t* fl = c.sRank;
+    if (c.tid == 0) { c.mi[MI_EDGE] = 0; c.mi[MI_RDIG] = 0; c.mi[MI_RREM] = 1; }
     __syncthreads();
     if (nc <= q) {
-        if (c.tid == 0) {
-            int cnt = 0;
-            for (int i = 0; i < m; ++i)
-                if (c.sScore[i] >= 0.0) c.sL[1 + cnt++] = i;
-            c.mi[MI_Q] = cnt;
+        for (int t = c.tid; t < m; t += c.nt) fl[t] = c.sScore[t] >= 0.0;
+        __syncthreads();
+    } else {
+        const double ss = kth_largest_score(c, m, q);
+        const double hi = ss * (1.0 + 1e-10), lo = ss * (1.0 - 1e-10);
+        int above = 0;
+        for (int t = c.tid; t < m; t += c.nt) {
+            const double s = c.sScore[t];
+            const bool adm = s >= 0.0;
+            above += adm && s > hi;
+            fl[t] = adm && s >= lo && s <= hi;
+            if (adm && ss > 0.0 && (fabs(s - hi) <= 1e-12 * ss || fabs(s - lo) <= 1e-12 * ss))
+                c.mi[MI_EDGE] = 1;
+        }
+        const int need = q - (int)block_sum(c, (double)above);
+        block_scan_flags(c, fl, fl, m);  // band rank of each row
+        for (int t = c.tid; t < m; t += c.nt) {
+            const double s = c.sScore[t];
+            const bool adm = s >= 0.0;
+            const bool band = adm && s >= lo && s <= hi;
+            fl[t] = (adm && s > hi) || (band && fl[t] <= need);
         }
         __syncthreads();
-        int cnt = c.mi[MI_Q];
-        __syncthreads();
-        return cnt;
+        if (c.tid == 0 && c.mi[MI_EDGE]) c.mi[MI_FLAGS] |= DIAF_FLAG_TIE_EDGE;
     }
-    // rank of each candidate: larger score first, lower row on ties
+    const int cnt = block_scan_flags(c, fl, fl, m);
     for (int t = c.tid; t < m; t += c.nt) {
-        double st = c.sScore[t];
-        if (st < 0.0) continue;
-        int rk = 0;
-        for (int u = 0; u < m; ++u) {
-            double su = c.sScore[u];
-            rk += (su > st) || (su == st && u < t);
-        }
-        if (rk == q - 1) c.md[MD_SSTAR] = st;
+        const int r = fl[t], p = t ? fl[t - 1] : 0;
+        if (r != p && r <= q) c.sL[r] = t;
     }
     __syncthreads();
-    if (c.tid == 0) {
-        double ss = c.md[MD_SSTAR];
-        double hi = ss * (1.0 + 1e-10), lo = ss * (1.0 - 1e-10);
-        int cnt = 0;
-        for (int t = 0; t < m; ++t)
-            if (c.sScore[t] >= 0.0 && c.sScore[t] > hi) c.sSel[cnt++] = t;
-        for (int t = 0; t < m && cnt < q; ++t)
-            if (c.sScore[t] >= 0.0 && c.sScore[t] >= lo && c.sScore[t] <= hi) c.sSel[cnt++] = t;
-        int edge = 0;
-        for (int t = 0; t < m; ++t) {
-            if (c.sScore[t] < 0.0) continue;
-            double d1 = fabs(c.sScore[t] - hi), d2 = fabs(c.sScore[t] - lo);
-            if (ss > 0.0 && (d1 <= 1e-12 * ss || d2 <= 1e-12 * ss)) edge = 1;
-        }
-        if (edge) c.mi[MI_FLAGS] |= DIAF_FLAG_TIE_EDGE;
-        for (int a = 1; a < cnt; ++a) {  // ascending local row order
-            int v = c.sSel[a], b = a - 1;
-            while (b >= 0 && c.sSel[b] > v) { c.sSel[b + 1] = c.sSel[b]; --b; }
-            c.sSel[b + 1] = v;
-        }
-        for (int t = 0; t < cnt; ++t) c.sL[1 + t] = c.sSel[t];
-        c.mi[MI_Q] = cnt;
-    }
-    __syncthreads();
-    int cnt = c.mi[MI_Q];
-    __syncthreads();
-    return cnt;
+    return cnt < q ? cnt : q;
 }
 
 template <class T>
