@@ -185,28 +185,80 @@ __device__ inline void block_bitonic(K* keys, int N2)
     }
 }
 
-// Block-wide exclusive scan of 0/1 flags in place (returns total).
+// Inclusive sum of x over the lanes of the wave up to this one.
+__device__ inline int wave_incl_scan(int x)
+{
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
+// Block-wide exclusive scan of 0/1 flags in place (returns total).  Each
+// thread owns a contiguous chunk; chunk sums are scanned by wave shuffles
+// and across waves through red (at least blockDim.x / 64 ints).
 __device__ inline int block_scan01(int32_t* f, int cnt, int32_t* red)
 {
-    int nt = blockDim.x, tid = threadIdx.x;
-    int chunk = (cnt + nt - 1) / nt;
-    int b = tid * chunk, e = min(cnt, b + chunk);
+    const int nt = blockDim.x, tid = threadIdx.x;
+    const int chunk = (cnt + nt - 1) / nt;
+    const int b = tid * chunk, e = min(cnt, b + chunk);
     int s = 0;
     for (int i = b; i < e; ++i) s += f[i];
-    red[tid] = s;
+    const int x = wave_incl_scan(s);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 63 || tid == nt - 1) red[wv] = x;
     __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int t = 0; t < nt; ++t) { int v = red[t]; red[t] = acc; acc += v; }
-        red[nt] = acc;
+    int before = 0, tot = 0;
+    for (int w = 0; w < (nt + 63) >> 6; ++w) {
+        const int t = red[w];
+        before += w < wv ? t : 0;
+        tot += t;
     }
-    __syncthreads();
-    int run = red[tid];
-    for (int i = b; i < e; ++i) { int v = f[i]; f[i] = run; run += v; }
-    __syncthreads();
-    int tot = red[nt];
+    int run = before + x - s;
+    for (int i = b; i < e; ++i) { const int v = f[i]; f[i] = run; run += v; }
     __syncthreads();
     return tot;
+}
+
+// The q-th largest (1-based, q <= cnt) of the non-negative doubles
+// v[0..cnt), by radix selection on their bit patterns (which order as the
+// values): 8 passes over 8-bit digits from the top, each counting the values
+// that match the digits fixed so far into 256 bins (hist) and fixing the
+// digit in which the q-th falls.  blockDim.x is a multiple of 64.
+__device__ inline double block_kth_largest(const double* v, int cnt, int q, int32_t* hist,
+                                           int32_t* pick)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    uint64_t prefix = 0, mask = 0;
+    int rem = q;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += nt) hist[b] = 0;
+        __syncthreads();
+        for (int t = tid; t < cnt; t += nt) {
+            const uint64_t key = (uint64_t)__double_as_longlong(v[t]) & 0x7fffffffffffffffull;
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255], 1);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // lane l holds bins 255 - 4l down to 252 - 4l
+            int h[4], loc = 0;
+            for (int r = 0; r < 4; ++r) { h[r] = hist[255 - 4 * tid - r]; loc += h[r]; }
+            const int x = wave_incl_scan(loc), excl = x - loc;
+            if (excl < rem && rem <= x) {
+                int run = excl, r = 0;
+                while (r < 3 && run + h[r] < rem) { run += h[r]; ++r; }
+                pick[0] = 255 - 4 * tid - r;
+                pick[1] = rem - run;
+            }
+        }
+        __syncthreads();
+        prefix |= (uint64_t)(uint32_t)pick[0] << shift;
+        mask |= 255ull << shift;
+        rem = pick[1];
+    }
+    return __longlong_as_double((long long)prefix);
 }
 
 // pattern(A^2), one block per column; cap candidates max (power of two),
@@ -337,36 +389,20 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     int32_t* scrow = off + cap + 1;
     int32_t* red = scrow + cap;
     int32_t* sel = red + blockDim.x + 1;
-    __shared__ int32_t s_tot, s_nsel;
+    __shared__ int32_t s_nsel, s_above, s_pick[2], s_hist[256];
     const int j = cols[blockIdx.x];
     const int tid = threadIdx.x;
     const int a0 = Acp[j], na = Acp[j + 1] - a0;
-    // off[q + 1] = total length of A(:, c) over the first q + 1 columns c of
-    // pattern(A(:, j)): a block-wide inclusive scan, blockDim.x at a time
-    if (tid == 0) off[0] = 0;
-    int carry = 0;
-    for (int q0 = 0; q0 < na; q0 += blockDim.x) {
-        const int q = q0 + tid;
-        int len = 0;
-        if (q < na) {
-            const int c = Ari[a0 + q];
-            len = Acp[c + 1] - Acp[c];
-        }
-        red[tid] = len;
-        __syncthreads();
-        for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-            const int v = tid >= o ? red[tid - o] : 0;
-            __syncthreads();
-            red[tid] += v;
-            __syncthreads();
-        }
-        if (q < na) off[q + 1] = carry + red[tid];
-        carry += red[blockDim.x - 1];
-        __syncthreads();
+    // off[q] = total length of A(:, c) over the first q columns c of
+    // pattern(A(:, j)) (an exclusive scan), off[na] = the gathered count
+    for (int q = tid; q < na; q += blockDim.x) {
+        const int c = Ari[a0 + q];
+        off[q] = Acp[c + 1] - Acp[c];
     }
-    if (tid == 0) s_tot = carry;
     __syncthreads();
-    const int Tn = s_tot;
+    const int Tn = block_scan01(off, na, red);
+    if (tid == 0) off[na] = Tn;
+    __syncthreads();
     int T2 = 1;
     while (T2 < Tn) T2 <<= 1;
     for (int t = tid; t < T2; t += blockDim.x) {
@@ -425,19 +461,27 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
         sc[slot] = s;
         scrow[slot] = row;
     }
-    if (tid == 0) s_nsel = 0;
+    if (tid == 0) { s_nsel = 0; s_above = 0; }
     __syncthreads();
-    // rank-based top-ptop: larger score first, lower row on ties
+    // top-ptop: larger score first, lower row on ties.  With s* the take-th
+    // largest score, every candidate above s* is taken and the rest come
+    // from the candidates equal to s* in ascending row (= slot) order.
     const int take = nc < ptop ? nc : ptop;
-    for (int s = tid; s < nc; s += blockDim.x) {
-        double v = sc[s];
-        int row = scrow[s];
-        int rk = 0;
-        for (int u = 0; u < nc && rk < take; ++u) {
-            double w = sc[u];
-            rk += (w > v) || (w == v && scrow[u] < row);
+    if (nc <= ptop) {
+        for (int s = tid; s < nc; s += blockDim.x) sel[s] = scrow[s];
+    } else {
+        const double ss = block_kth_largest(sc, nc, take, s_hist, s_pick);
+        for (int s = tid; s < nc; s += blockDim.x) {
+            off[s] = sc[s] == ss;
+            if (sc[s] > ss) atomicAdd(&s_above, 1);
         }
-        if (rk < take) sel[atomicAdd(&s_nsel, 1)] = row;
+        __syncthreads();
+        block_scan01(off, nc, red);  // rank among the candidates equal to s*
+        const int need = take - s_above;
+        for (int s = tid; s < nc; s += blockDim.x) {
+            const double v = sc[s];
+            if (v > ss || (v == ss && off[s] < need)) sel[atomicAdd(&s_nsel, 1)] = scrow[s];
+        }
     }
     __syncthreads();
     // output = sorted(rows(A(:, j)) U sel)

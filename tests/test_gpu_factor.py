@@ -212,13 +212,23 @@ def test_factor_parity_full_size(ctx, name):
         F.close()
 
 
+def _unit_values(A):
+    return synth.CSC(n=A.n, colptr=A.colptr, rowidx=A.rowidx, val=np.ones_like(A.val))
+
+
 def test_pattern_builders_match_oracle(ctx):
     from paper_1208_3573_amd import diaf
     cases = [(synth.random_small(500, 4, 3), "A2", 0),
              (synth.random_lognormal(20000, 4), "A_1hop_topk", 8),
              (synth.random_lognormal(20000, 5), "A_1hop_topk", 3),
              (synth.random_small(200, 3, 2, complex_=True), "A_1hop_topk", 4),
-             (synth.convdiff(12, 3, 1), "A2", 0)]
+             (synth.convdiff(12, 3, 1), "A2", 0),
+             # constant coefficients: equal two-hop scores, ties go to the lower row
+             (synth.helmholtz(24), "A_1hop_topk", 5),
+             # unit values: scores are path counts, so nearly every score ties;
+             # 1 600 two-hop candidates per column
+             (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 8),
+             (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 100)]
     for A, kind, p in cases:
         say(f"pattern {kind} p={p} n={A.n}")
         dA = diaf.DeviceCSC.from_host(A)
