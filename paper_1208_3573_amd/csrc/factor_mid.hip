@@ -15,8 +15,9 @@
 //     of the entry ids (ascending entry = ascending column of B);
 //   * G: the diagonal from each column's own entries; an off-diagonal entry
 //     G(a, b) only for columns that share a row holding two or more entries
-//     (per-column bit masks over these "shared rows"), summed over column
-//     a's entries in A's row order;
+//     (per-column bit masks over these "shared rows", which are numbered
+//     by ascending global row), summed over the common bits of the two
+//     masks, i.e. over the shared rows in ascending global order;
 //   * G = L L^* by a right-looking Cholesky in LDS, one lane per row;
 //   * the seed w0 = G^{-1} b_j^* (V_0 = diagonals, Example 2.1), the scores
 //     |(B w0)_i| of the admissible rows and the top-(l-1) selection with the
@@ -77,7 +78,9 @@ template <class T, int MK, int MT>
 struct MidLds {
     static constexpr int HS = 2 * MT;  // hash slots (load factor <= 1/2)
     static constexpr int HB = ilog2(HS);
-    int J[MK];
+    int a0[64];              // start of each column of B in A (lanes >= |J_j|: 0)
+    int alen[64];            // and its length
+    int hd[4];               // the column's j and the bounds of J_j in Jri
     int off[MK + 1];
     int R[MT];               // local row -> global row
     T eval[MT];              // gathered values, column by column
@@ -198,16 +201,69 @@ __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
     __syncthreads();
 }
 
+// A column's head: j, the bounds of J_j in (Jcp, Jri) and, on lane a <
+// min(|J_j|, MK), the bounds of column J_j[a] of A.  A wave loads the next
+// column's head in three dependent steps spread over the current column
+// (stage 1: J_j's bounds; 2: J_j; 3: A's column bounds) and publishes it to
+// LDS (stage 4) before the current column's output stores, so the latency of
+// that chain overlaps the current column's work.  The column numbers
+// themselves come 64 at a time, one per lane, so no load is issued between
+// two columns (where its wait would also wait for the stores just issued).
+// Indices pass through a register the compiler cannot prove uniform, so
+// these are vector loads: a pending scalar load would hold up every LDS
+// wait.
+struct MidHead {
+    int j = -1, jb = 0, je = 0, c = 0, a0 = 0, a1 = 0, stage = 3;
+};
+
+__device__ inline void mid_head_start(MidHead& h, int j)
+{
+    h = MidHead{};
+    h.j = j;
+    h.stage = j >= 0 ? 0 : 3;
+}
+
+template <int MK, class T>
+__device__ inline void mid_head_advance(const FactorArgs<T>& A, MidHead& h, int upto, int lane)
+{
+    if (h.stage >= upto) return;
+    if (h.stage < 1) {
+        int z = 0;
+        __asm__ volatile("" : "+v"(z));
+        h.jb = A.Jcp[h.j + z];
+        h.je = A.Jcp[h.j + 1 + z];
+    }
+    if (h.stage < 2 && upto >= 2) {
+        if (lane < h.je - h.jb && lane < MK) h.c = A.Jri[h.jb + lane];
+    }
+    if (h.stage < 3 && upto >= 3) {
+        if (lane < h.je - h.jb && lane < MK) { h.a0 = A.Acp[h.c]; h.a1 = A.Acp[h.c + 1]; }
+    }
+    h.stage = upto;
+}
+
+template <int MK, class T, class S_t>
+__device__ inline void mid_head_publish(const FactorArgs<T>& A, S_t& S, MidHead& h, int lane)
+{
+    if (h.stage == 4) return;
+    mid_head_advance<MK>(A, h, 3, lane);
+    // every load of the head completes here, on every path and lane
+    __asm__ volatile("" ::"v"(h.j), "v"(h.jb), "v"(h.je), "v"(h.c), "v"(h.a0), "v"(h.a1));
+    S.a0[lane] = h.a0;
+    S.alen[lane] = h.a1 - h.a0;
+    if (lane == 0) { S.hd[0] = h.j; S.hd[1] = h.jb; S.hd[2] = h.je; }
+    h.stage = 4;
+    __syncthreads();
+}
+
 template <class T, int MK, int MT>
-__device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, int* deferred,
-                           int* ndeferred)
+__device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, const int k,
+                           MidHead& nx, MidLds<T, MK, MT>& S, int* deferred, int* ndeferred)
 {
     using S_t = MidLds<T, MK, MT>;
     constexpr int HS = S_t::HS;
     int lane = threadIdx.x;
     __asm__ volatile("" : "+v"(lane));
-    const int jb = A.Jcp[j];
-    const int k = A.Jcp[j + 1] - jb;
     const int lmax = A.lmax;
     const auto defer = [&]() {
         __syncthreads();
@@ -215,12 +271,7 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
     };
     // ---- 1. J_j and gather offsets (k <= 64 = one lane per column) ----
     if (k > MK) { defer(); return; }
-    int len = 0;
-    if (lane < k) {
-        const int c = A.Jri[jb + lane];
-        S.J[lane] = c;
-        len = A.Acp[c + 1] - A.Acp[c];
-    }
+    const int len = lane < k ? S.alen[lane] : 0;
     const int inc = wave_incl_scan(len, lane);
     if (lane < k) S.off[lane + 1] = inc;
     if (lane == 0) S.off[0] = 0;
@@ -229,25 +280,45 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
     for (int s = lane; s < HS; s += 64) S.h.key[s] = -1;
     __syncthreads();
     // ---- 2. gather; rows into the hash table ----
-    for (int t = lane; t < Tn; t += 64) {
-        int lo = 0, hi = k - 1;  // largest a with off[a] <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
+    // every load of this lane's entries (t = lane + 64 i) is issued before
+    // the first is used, so the gather costs one memory latency, not MT / 64
+    constexpr int EPL = MT / 64;
+    int grow[EPL];
+    T gval[EPL];
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int t = lane + 64 * i;
+        grow[i] = 0;
+        gval[i] = num<T>::zero();
+        if (t < Tn) {
+            int lo = 0, hi = k - 1;  // largest a with off[a] <= t
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int p = S.a0[lo] + (t - S.off[lo]);
+            grow[i] = A.Ari[p];
+            gval[i] = A.Aval[p];
+            S.ecol[t] = (uint8_t)lo;
         }
-        const int p = A.Acp[S.J[lo]] + (t - S.off[lo]);
-        const int row = A.Ari[p];
-        S.eval[t] = A.Aval[p];
-        S.ecol[t] = (uint8_t)lo;
-        unsigned h = ((unsigned)row * 2654435761u) >> (32 - S_t::HB);  // < HS
-        for (;;) {  // at most HS probes: the table is at most half full
-            const int prev = atomicCAS(&S.h.key[h], -1, row);
-            if (prev == -1 || prev == row) break;
-            h = (h + 1) & (unsigned)(HS - 1);
+    }
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int t = lane + 64 * i;
+        if (t < Tn) {
+            const int row = grow[i];
+            S.eval[t] = gval[i];
+            unsigned h = ((unsigned)row * 2654435761u) >> (32 - S_t::HB);  // < HS
+            for (;;) {  // at most HS probes: the table is at most half full
+                const int prev = atomicCAS(&S.h.key[h], -1, row);
+                if (prev == -1 || prev == row) break;
+                h = (h + 1) & (unsigned)(HS - 1);
+            }
+            S.eloc[t] = (uint16_t)h;
         }
-        S.eloc[t] = (uint16_t)h;
     }
     __syncthreads();
+    mid_head_advance<MK>(A, nx, 1, lane);
     // ---- 3. local rows: rank of each occupied slot ----
     int m = 0;
     for (int s0 = 0; s0 < HS; s0 += 64) {
@@ -330,14 +401,40 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
             sh = e - b >= 2;
         }
         const uint64_t msk = __ballot(sh);
-        if (r < m) S.sidx[r] = sh ? (uint16_t)(ms + __popcll(msk & ((1ull << lane) - 1ull)))
-                                  : (uint16_t)0xffff;
+        const int qi = ms + __popcll(msk & ((1ull << lane) - 1ull));
+        if (sh && qi < 64 * MSW) {  // list of the shared rows and their global rows
+            S.she[qi] = (uint16_t)r;
+            S.h.key[qi] = S.R[r];
+        }
         ms += __popcll(msk);
     }
     if (ms > 64 * MSW) { defer(); return; }
+    __syncthreads();
+    // number the shared rows by ascending global row (rank among them), so
+    // that walking a mask's bits upwards follows the rows of A in order
+    {
+        int key[MSW], rk[MSW];
+#pragma unroll
+        for (int i = 0; i < MSW; ++i) {
+            key[i] = lane + 64 * i < ms ? S.h.key[lane + 64 * i] : 0x7fffffff;
+            rk[i] = 0;
+        }
+        for (int u = 0; u < ms; ++u) {
+            const int ku = S.h.key[u];
+#pragma unroll
+            for (int i = 0; i < MSW; ++i) rk[i] += ku < key[i];
+        }
+        for (int r = lane; r < m; r += 64) S.sidx[r] = (uint16_t)0xffff;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MSW; ++i)
+            if (lane + 64 * i < ms) S.sidx[S.she[lane + 64 * i]] = (uint16_t)rk[i];
+    }
+    __syncthreads();
     // ---- 5. Gram matrix ----
     // lane a < k walks column a's entries (ascending global row): its mask
-    // over the shared rows and its list of entries in shared rows
+    // over the shared rows and its list of entries in shared rows (in the
+    // order of the mask's bits)
     int ncs = 0;
     if (lane < k) {
         uint64_t mk_[MSW] = {};
@@ -377,34 +474,32 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
             while (a * (a - 1) / 2 > pi) --a;
             while ((a + 1) * a / 2 <= pi) ++a;
             const int b = pi - a * (a - 1) / 2;
+            // the shared rows of both columns are the common bits of their
+            // masks; walking them upwards sums over the rows in ascending
+            // global order, so the sum does not depend on the local row ids.
+            // A column's entry at shared row q is its list entry number
+            // (mask bits below q).
             T acc = num<T>::zero();
-            uint64_t any = 0;
+            int ba = S.soff[a], bb = S.soff[b];
 #pragma unroll
-            for (int wd = 0; wd < MSW; ++wd) any |= S.cmask[a][wd] & S.cmask[b][wd];
-            if (any) {
-                // merge of the two columns' shared entries by global row
-                // (ascending in both), so the sum does not depend on the
-                // local row ids
-                int ia = S.soff[a], ib = S.soff[b];
-                const int ea = S.soff[a + 1], eb = S.soff[b + 1];
-                while (ia < ea && ib < eb) {
-                    const int ta = S.she[ia], tb = S.she[ib];
-                    const int ra = S.R[S.eloc[ta]], rb = S.R[S.eloc[tb]];
-                    if (ra == rb) {
-                        acc += num<T>::cmul(S.eval[ta], S.eval[tb]);  // conj(B(r, a)) B(r, b)
-                        ++ia;
-                        ++ib;
-                    } else if (ra < rb) {
-                        ++ia;
-                    } else {
-                        ++ib;
-                    }
+            for (int wd = 0; wd < MSW; ++wd) {
+                const uint64_t ma = S.cmask[a][wd], mb = S.cmask[b][wd];
+                uint64_t cm = ma & mb;
+                while (cm) {
+                    const uint64_t below = (cm & (~cm + 1ull)) - 1ull;
+                    cm &= cm - 1ull;
+                    const int ta = S.she[ba + __popcll(ma & below)];
+                    const int tb = S.she[bb + __popcll(mb & below)];
+                    acc += num<T>::cmul(S.eval[ta], S.eval[tb]);  // conj(B(r, a)) B(r, b)
                 }
+                ba += __popcll(ma);
+                bb += __popcll(mb);
             }
             S.G[ltri(a, b)] = acc;
         }
     }
     __syncthreads();
+    mid_head_advance<MK>(A, nx, 2, lane);
     // ---- 6. Cholesky G = L L^*, left-looking, one lane per row ----
     // step p: every row i >= p takes G(i, p) - sum_{q<p} L(i, q) conj(L(p, q))
     // (independent loads of its own row and of row p); row p's value is the
@@ -426,6 +521,7 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
         else if (lane > p && lane < k) S.G[ltri(lane, p)] = num<T>::mk(inv) * sp;
         __syncthreads();
     }
+    mid_head_advance<MK>(A, nx, 3, lane);
     // ---- 7. V pattern ----
     const bool topk =
         A.vrule == V_TOPK_LOWER || A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_BLOCK;
@@ -634,6 +730,7 @@ __device__ void mid_column(const FactorArgs<T>& A, int j, MidLds<T, MK, MT>& S, 
         r2 += num<T>::abs2(res);
     }
     r2 = wave_sum(r2);
+    mid_head_publish<MK>(A, S, nx, lane);  // S.a0, S.alen and S.hd are dead here
     if (lane < k) A.Wval[jb + lane] = S.f.w[lane];
     const int myg = lane < l ? S.R[S.L[lane]] : 0x7fffffff;
     int rank = 0;
@@ -672,7 +769,27 @@ __global__ void __launch_bounds__(64) factor_mid_kernel(FactorArgs<T> A, int* de
         qs = nper;
         qe = min(A.ncols, (x + 1) * chunk);
     }
-    for (int q = q0; q < qe; q += qs) mid_column(A, A.cols[q], S, deferred, ndeferred);
+    const int lane = threadIdx.x;
+    // colv on lane i: the column of iteration 64 b + i of this wave (-1 past
+    // the end), for the current block b of 64 iterations
+    const auto col_block = [&](int it0) {
+        const int q = q0 + (it0 + lane) * qs;
+        return q < qe ? A.cols[q] : -1;
+    };
+    int colv = col_block(0);
+    MidHead nx;
+    mid_head_start(nx, __builtin_amdgcn_readlane(colv, 0));
+    mid_head_publish<MK>(A, S, nx, lane);
+    for (int it = 0, q = q0; q < qe; ++it, q += qs) {
+        // this column's head, from LDS; the next column's number, from colv
+        const int j = __builtin_amdgcn_readfirstlane(S.hd[0]);
+        const int jb = __builtin_amdgcn_readfirstlane(S.hd[1]);
+        const int k = __builtin_amdgcn_readfirstlane(S.hd[2]) - jb;
+        if (((it + 1) & 63) == 0) colv = col_block(it + 1);
+        mid_head_start(nx, __builtin_amdgcn_readlane(colv, (it + 1) & 63));
+        mid_column(A, j, jb, k, nx, S, deferred, ndeferred);
+        mid_head_publish<MK>(A, S, nx, lane);
+    }
 }
 
 }  // namespace mid
