@@ -141,4 +141,31 @@ struct FactorArgs {
     int32_t* lcount;
 };
 
+#ifdef __HIPCC__
+// Columns a one-wave kernel hands back, buffered one per lane and appended
+// to the global list 64 at a time, so that a launch deferring most of its
+// columns does not serialise on one counter.  The list's order is
+// immaterial (it is sorted before use).
+struct DeferBuf {
+    int reg = 0;  // lane i: the i-th buffered column
+    int n = 0;    // buffered columns (the same on every lane)
+};
+
+__device__ inline void defer_flush(DeferBuf& b, int lane, int* list, int* count)
+{
+    if (b.n == 0) return;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, b.n);
+    base = __shfl(base, 0);
+    if (lane < b.n) list[base + lane] = b.reg;
+    b.n = 0;
+}
+
+__device__ inline void defer_push(DeferBuf& b, int j, int lane, int* list, int* count)
+{
+    if (lane == b.n) b.reg = j;
+    if (++b.n == 64) defer_flush(b, lane, list, count);
+}
+#endif
+
 }  // namespace diaf

@@ -27,28 +27,51 @@ static constexpr int GNT = 512;  // largest workgroup (small size classes use on
 struct GenLayout {
     size_t oJ, oOff, oKey, oVal, oLrow, oCol, oPos, oRowptr, oR, oRank, oY, oW, oX, oVM, oSig,
         oV, oL, oSel, oRed, oMisc, oMats, total;
+    size_t total_lds;  // split layout: bytes of the arrays placed in LDS
+    uint32_t in_lds;   // split layout: bit b set = array b (GenArr) lies in LDS
 };
+
+// Arrays of a column's working storage.
+enum GenArr { GA_J, GA_OFF, GA_KEY, GA_VAL, GA_LROW, GA_COL, GA_POS, GA_ROWPTR, GA_R, GA_RANK,
+              GA_Y, GA_W, GA_X, GA_VM, GA_SIG, GA_V, GA_L, GA_SEL, GA_RED, GA_MISC };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // Working storage of one column.  The key array (sort keys) is dead after
 // the shadow is built and is reused for the selection scores.  with_mats =
 // number of k x k matrices kept here (1: G, unit-norm v; 3: G, E, Z,
-// unit-norm w; 0: in a separate global slot).
+// unit-norm w; 0: in a separate global slot).  lds_budget > 0 splits the
+// storage: the small and index arrays read on every step (reduction and
+// flag slots, column offsets, the row/column/position cross references)
+// go, in that order of priority, to LDS while they fit in lds_budget bytes,
+// and everything else stays in the global slot.
 __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, int lcap, size_t st,
-                                                int with_mats)
+                                                int with_mats, size_t lds_budget = 0)
 {
     GenLayout L{};
-    size_t o = 0;
+    size_t o = 0, oi = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align16(o + bytes); return r; };
-    L.oJ = take(sizeof(int32_t) * kcap);
-    L.oOff = take(sizeof(int32_t) * (kcap + 1));
+    auto takep = [&](int id, size_t bytes) {
+        if (lds_budget > 0 && align16(oi + bytes) <= lds_budget) {
+            L.in_lds |= 1u << id;
+            size_t r = oi;
+            oi = align16(oi + bytes);
+            return r;
+        }
+        return take(bytes);
+    };
+    L.oMisc = takep(GA_MISC, sizeof(double) * 32);
+    L.oRed = takep(GA_RED, sizeof(double) * GNT);
+    L.oOff = takep(GA_OFF, sizeof(int32_t) * (kcap + 1));
+    L.oJ = takep(GA_J, sizeof(int32_t) * kcap);
+    L.oL = takep(GA_L, sizeof(int32_t) * lcap);
+    L.oSel = takep(GA_SEL, sizeof(int32_t) * lcap);
+    L.oLrow = takep(GA_LROW, sizeof(uint16_t) * tcap);
+    L.oCol = takep(GA_COL, sizeof(uint16_t) * tcap);
+    L.oPos = takep(GA_POS, sizeof(uint16_t) * tcap);
+    L.oRowptr = takep(GA_ROWPTR, sizeof(uint16_t) * (tcap + 1));
     L.oKey = take(sizeof(uint64_t) * tcap2);
     L.oVal = take(st * tcap);
-    L.oLrow = take(sizeof(uint16_t) * tcap);
-    L.oCol = take(sizeof(uint16_t) * tcap);
-    L.oPos = take(sizeof(uint16_t) * tcap);
-    L.oRowptr = take(sizeof(uint16_t) * (tcap + 1));
     L.oR = take(sizeof(int32_t) * tcap);
     L.oRank = take(sizeof(int32_t) * tcap);
     L.oY = take(st * tcap);
@@ -57,13 +80,10 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
     L.oVM = take(st * lcap * lcap);
     L.oSig = take(sizeof(double) * lcap);
     L.oV = take(st * lcap);
-    L.oL = take(sizeof(int32_t) * lcap);
-    L.oSel = take(sizeof(int32_t) * lcap);
-    L.oRed = take(sizeof(double) * GNT);
-    L.oMisc = take(sizeof(double) * 32);
     L.oMats = o;
     if (with_mats) take(st * (size_t)with_mats * kcap * kcap);
     L.total = o;
+    L.total_lds = oi;
     return L;
 }
 
@@ -1016,36 +1036,41 @@ template <class T, bool IN_LDS>
 __global__ void __launch_bounds__(GNT) factor_generic_kernel(FactorArgs<T> A, int kcap, int tcap,
                                                              int tcap2, int lcap, int nmats_here,
                                                              unsigned char* gws, size_t slot_bytes,
-                                                             T* gmats)
+                                                             T* gmats, size_t lds_split)
 {
     extern __shared__ __align__(16) unsigned char lds_dyn[];
     unsigned char* base = IN_LDS ? lds_dyn : gws + (size_t)blockIdx.x * slot_bytes;
-    GenLayout Lo = gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), nmats_here);
+    const GenLayout Lo =
+        gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), nmats_here, IN_LDS ? 0 : lds_split);
+    // the array's address: LDS or the block's global slot
+    const auto at = [&](int id, size_t off) -> unsigned char* {
+        return ((Lo.in_lds >> id) & 1u) ? lds_dyn + off : base + off;
+    };
     GenCtx<T> c;
     c.tid = threadIdx.x;
     c.nt = blockDim.x;
-    c.sJ = (int32_t*)(base + Lo.oJ);
-    c.sOff = (int32_t*)(base + Lo.oOff);
-    c.sKey = (uint64_t*)(base + Lo.oKey);
-    c.sScore = (double*)(base + Lo.oKey);
-    c.sVal = (T*)(base + Lo.oVal);
-    c.sLrow = (uint16_t*)(base + Lo.oLrow);
-    c.sCol = (uint16_t*)(base + Lo.oCol);
-    c.sPos = (uint16_t*)(base + Lo.oPos);
-    c.sRowptr = (uint16_t*)(base + Lo.oRowptr);
-    c.sR = (int32_t*)(base + Lo.oR);
-    c.sRank = (int32_t*)(base + Lo.oRank);
-    c.sY = (T*)(base + Lo.oY);
-    c.sW = (T*)(base + Lo.oW);
-    c.sX = (T*)(base + Lo.oX);
-    c.sVM = (T*)(base + Lo.oVM);
-    c.sSig = (double*)(base + Lo.oSig);
-    c.sV = (T*)(base + Lo.oV);
-    c.sL = (int32_t*)(base + Lo.oL);
-    c.sSel = (int32_t*)(base + Lo.oSel);
-    c.sRed = (double*)(base + Lo.oRed);
-    c.mi = (int*)(base + Lo.oMisc);
-    c.md = (double*)(base + Lo.oMisc);
+    c.sJ = (int32_t*)at(GA_J, Lo.oJ);
+    c.sOff = (int32_t*)at(GA_OFF, Lo.oOff);
+    c.sKey = (uint64_t*)at(GA_KEY, Lo.oKey);
+    c.sScore = (double*)at(GA_KEY, Lo.oKey);
+    c.sVal = (T*)at(GA_VAL, Lo.oVal);
+    c.sLrow = (uint16_t*)at(GA_LROW, Lo.oLrow);
+    c.sCol = (uint16_t*)at(GA_COL, Lo.oCol);
+    c.sPos = (uint16_t*)at(GA_POS, Lo.oPos);
+    c.sRowptr = (uint16_t*)at(GA_ROWPTR, Lo.oRowptr);
+    c.sR = (int32_t*)at(GA_R, Lo.oR);
+    c.sRank = (int32_t*)at(GA_RANK, Lo.oRank);
+    c.sY = (T*)at(GA_Y, Lo.oY);
+    c.sW = (T*)at(GA_W, Lo.oW);
+    c.sX = (T*)at(GA_X, Lo.oX);
+    c.sVM = (T*)at(GA_VM, Lo.oVM);
+    c.sSig = (double*)at(GA_SIG, Lo.oSig);
+    c.sV = (T*)at(GA_V, Lo.oV);
+    c.sL = (int32_t*)at(GA_L, Lo.oL);
+    c.sSel = (int32_t*)at(GA_SEL, Lo.oSel);
+    c.sRed = (double*)at(GA_RED, Lo.oRed);
+    c.mi = (int*)at(GA_MISC, Lo.oMisc);
+    c.md = (double*)at(GA_MISC, Lo.oMisc);
     c.xld = lcap + 1;
     const size_t kk = (size_t)kcap * kcap;
     // global k x k matrices (when not here): 1 per block for unit-norm v, 3 otherwise
@@ -1076,7 +1101,12 @@ struct GenPlan {
     size_t lds_bytes;   // dynamic LDS
     size_t slot_bytes;  // global slot per block (in_lds == false)
     bool need_gmats;    // separate global k x k matrices
+    size_t lds_split;   // in_lds == false: LDS budget of the split layout (0: none)
 };
+
+// LDS budget of the split layout (in_lds == false): with the kernel's 8 KB
+// of static LDS, four workgroups per CU
+static constexpr size_t kGenSplitLds = 32 * 1024;
 
 template <class T>
 GenPlan generic_plan(int kcap, int tcap, int lcap, int mode, int nt_override = 0)
@@ -1093,7 +1123,15 @@ GenPlan generic_plan(int kcap, int tcap, int lcap, int mode, int nt_override = 0
     } else if (without <= 96 * 1024) {
         P.in_lds = true; P.mats_here = false; P.lds_bytes = without; P.need_gmats = true;
     } else {
-        P.in_lds = false; P.mats_here = true; P.slot_bytes = (with + 255) & ~size_t(255);
+        // slot in global memory, with the hot small arrays in LDS
+        int tcap2 = 1;
+        while (tcap2 < tcap) tcap2 <<= 1;
+        const GenLayout L = gen_layout(kcap, tcap, tcap2, lcap, sizeof(T), P.nmats, kGenSplitLds);
+        P.in_lds = false;
+        P.mats_here = true;
+        P.lds_split = kGenSplitLds;
+        P.lds_bytes = L.total_lds;
+        P.slot_bytes = (L.total + 255) & ~size_t(255);
     }
     return P;
 }
@@ -1129,11 +1167,15 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
                                          (int)P.lds_bytes));
         hipLaunchKernelGGL(kern, dim3(grid), dim3(P.nt), P.lds_bytes, st, A, kcap, tcap, tcap2,
                            lcap, P.mats_here ? P.nmats : 0, (unsigned char*)nullptr, (size_t)0,
-                           (T*)gws);
+                           (T*)gws, (size_t)0);
     } else {
         auto kern = factor_generic_kernel<T, false>;
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(P.nt), 0, st, A, kcap, tcap, tcap2, lcap,
-                           P.nmats, (unsigned char*)gws, P.slot_bytes, (T*)nullptr);
+        DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)P.lds_bytes));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(P.nt), P.lds_bytes, st, A, kcap, tcap, tcap2,
+                           lcap, P.nmats, (unsigned char*)gws, P.slot_bytes, (T*)nullptr,
+                           P.lds_split);
     }
     DIAF_HIP_TRY(hipGetLastError());
     return {};
@@ -1150,8 +1192,11 @@ double generic_occupancy(int kcap, int tcap, int lcap, int mode, FactorTune tune
         hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes) !=
             hipSuccess)
         return 0.0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, P.nt, P.in_lds ? P.lds_bytes : 0) !=
-        hipSuccess)
+    if (!P.in_lds &&
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)P.lds_bytes) !=
+            hipSuccess)
+        return 0.0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, P.nt, P.lds_bytes) != hipSuccess)
         return 0.0;
     return nb * (P.nt / 64) / 4.0;
 }

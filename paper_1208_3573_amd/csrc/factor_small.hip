@@ -50,7 +50,6 @@ struct SmallLds {
     T Gk[MODE == 1 ? STRI : 1];  // unit-norm w: packed G, kept for two solves
     union {
         struct {  // gather and shadow
-            int erow[STM];   // gathered global rows
             int hkey[SHS];   // hash of the shadow rows
             union {
                 int tmp[SMM];
@@ -79,7 +78,7 @@ struct SmallLds {
             T w[SKM];
         } post;
     };
-    int J[SKM];
+    int a0[SKM];  // start of each column of B in A
     int off[SKM + 1];
     int R[SMM];  // shadow rows, ascending
     int rptr[SMM + 1];
@@ -328,7 +327,7 @@ __device__ __forceinline__ bool bottom_eig_w(SmallLds<T, MODE>& S, int k, int nt
 
 template <class T, int MODE>
 __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, SmallLds<T, MODE>& S,
-                                             int* deferred, int* ndeferred)
+                                             int* deferred, int* ndeferred, DeferBuf& db)
 {
     // opaque per call: keeps lane-derived addresses from being hoisted out of
     // the column loop (they would stay live in registers for the whole kernel)
@@ -340,9 +339,10 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     // ---- 1. J_j and gather offsets ----
     int len = 0;
     if (lane < k && k <= SKM) {
-        int c = A.Jri[jb + lane];
-        S.J[lane] = c;
-        len = A.Acp[c + 1] - A.Acp[c];
+        const int c = A.Jri[jb + lane];
+        const int a0 = A.Acp[c];
+        S.a0[lane] = a0;
+        len = A.Acp[c + 1] - a0;
     }
     int inc = wave_incl_scan(len, lane);
     if (lane < k && k <= SKM) S.off[lane + 1] = inc;
@@ -351,34 +351,58 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     for (int s = lane; s < SHS; s += 64) S.sh.hkey[s] = -1;
     __syncthreads();
     if (k > SKM || Tn > STM) {
-        if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+        defer_push(db, j, lane, deferred, ndeferred);
         return;
     }
-    // ---- 2. gather ----
-    for (int t = lane; t < Tn; t += 64) {
-        int lo = 0, hi = k - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
+    // ---- 2. gather; shadow rows into the hash table ----
+    // every load of this lane's entries (t = lane + 64 i) is issued before
+    // the first is used; the rows new to the table are counted per round, so
+    // a column whose shadow exceeds SMM rows is deferred without filling it
+    constexpr int EPL = STM / 64;
+    int grow[EPL];
+    T gval[EPL];
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int t = lane + 64 * i;
+        grow[i] = 0;
+        gval[i] = num<T>::zero();
+        if (t < Tn) {
+            int lo = 0, hi = k - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (S.off[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int p = S.a0[lo] + (t - S.off[lo]);
+            grow[i] = A.Ari[p];
+            gval[i] = A.Aval[p];
+            S.ecol[t] = (uint8_t)lo;
         }
-        int p = A.Acp[S.J[lo]] + (t - S.off[lo]);
-        S.sh.erow[t] = A.Ari[p];
-        S.eval[t] = A.Aval[p];
-        S.ecol[t] = (uint8_t)lo;
+    }
+    int mnew = 0;
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+        const int t = lane + 64 * i;
+        bool fresh = false;
+        if (t < Tn) {
+            const int row = grow[i];
+            S.eval[t] = gval[i];
+            unsigned h = ((unsigned)row * 2654435761u) >> 24;
+            for (;;) {
+                const int prev = atomicCAS(&S.sh.hkey[h], -1, row);
+                if (prev == -1 || prev == row) { fresh = prev == -1; break; }
+                h = (h + 1) & (SHS - 1);
+            }
+            S.sh.eslot[t] = (uint8_t)h;
+        }
+        mnew += __popcll(__ballot(fresh));
+        if (mnew > SMM) break;
     }
     __syncthreads();
-    // ---- 3. shadow: hash dedup, sort, local row ids ----
-    for (int t = lane; t < Tn; t += 64) {
-        int row = S.sh.erow[t];
-        unsigned h = ((unsigned)row * 2654435761u) >> 24;
-        for (;;) {
-            int prev = atomicCAS(&S.sh.hkey[h], -1, row);
-            if (prev == -1 || prev == row) break;
-            h = (h + 1) & (SHS - 1);
-        }
-        S.sh.eslot[t] = (uint8_t)h;
+    if (mnew > SMM) {
+        defer_push(db, j, lane, deferred, ndeferred);
+        return;
     }
-    __syncthreads();
+    // ---- 3. shadow: local row ids by ascending row ----
     int m = 0;
     for (int q = 0; q < SHS / 64; ++q) {
         int s = q * 64 + lane;
@@ -391,7 +415,7 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     }
     __syncthreads();
     if (m > SMM) {
-        if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+        defer_push(db, j, lane, deferred, ndeferred);
         return;
     }
     int myrow = lane < m ? S.R[lane] : 0x7fffffff;
@@ -692,7 +716,7 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
             }
             if (l > SLM || l > lmax) {
                 __syncthreads();
-                if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+                defer_push(db, j, lane, deferred, ndeferred);
                 return;
             }
         }
@@ -843,7 +867,7 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
         const double fro2 = wave_sum(f2);
         if (m - l < k || r2 <= 1e-14 * fro2) {
             __syncthreads();
-            if (lane == 0) deferred[atomicAdd(ndeferred, 1)] = j;
+            defer_push(db, j, lane, deferred, ndeferred);
             return;
         }
     }
@@ -889,7 +913,9 @@ __global__ void __launch_bounds__(64) factor_small_kernel(FactorArgs<T> A, int* 
         qe = min(A.ncols, (x + 1) * chunk);
     }
     // one call site, so the column body is inlined
-    for (int q = q0; q < qe; q += qs) small_column(A, A.cols[q], S, deferred, ndeferred);
+    DeferBuf db;
+    for (int q = q0; q < qe; q += qs) small_column(A, A.cols[q], S, deferred, ndeferred, db);
+    defer_flush(db, threadIdx.x, deferred, ndeferred);
 }
 
 template <class T>
