@@ -142,6 +142,76 @@ struct FactorArgs {
 };
 
 #ifdef __HIPCC__
+// Whole-wave reductions and scans over the 64 lanes by DPP moves within rows
+// of 16 lanes and readlane across rows: no LDS traffic, unlike shuffles
+// (ds_bpermute).  Every lane must be active.  The sums associate the same
+// way on every lane (pairs, quads, half rows, rows, then the four row sums),
+// so the result is the same on all lanes and for every launch.
+template <int CTRL>
+__device__ inline double dpp_move(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline double readlane_f64(double x, int l)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// DPP controls: quad_perm [1,0,3,2] and [2,3,0,1], row_half_mirror,
+// row_mirror, row_shr:n, row_bcast:15 and row_bcast:31.
+enum : int { DPP_QXOR1 = 0xB1, DPP_QXOR2 = 0x4E, DPP_HMIRROR = 0x141, DPP_MIRROR = 0x140,
+             DPP_SHR = 0x110, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143 };
+
+__device__ inline double dpp_wave_sum(double x)
+{
+    x += dpp_move<DPP_QXOR1>(x);
+    x += dpp_move<DPP_QXOR2>(x);
+    x += dpp_move<DPP_HMIRROR>(x);
+    x += dpp_move<DPP_MIRROR>(x);
+    return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
+}
+
+__device__ inline double dpp_wave_max(double x)
+{
+    x = fmax(x, dpp_move<DPP_QXOR1>(x));
+    x = fmax(x, dpp_move<DPP_QXOR2>(x));
+    x = fmax(x, dpp_move<DPP_HMIRROR>(x));
+    x = fmax(x, dpp_move<DPP_MIRROR>(x));
+    return fmax(fmax(readlane_f64(x, 0), readlane_f64(x, 16)),
+                fmax(readlane_f64(x, 32), readlane_f64(x, 48)));
+}
+
+__device__ inline int dpp_wave_min(int x)
+{
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, DPP_QXOR1, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, DPP_QXOR2, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, DPP_HMIRROR, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, DPP_MIRROR, 0xf, 0xf, false));
+    return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+               min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+
+// Inclusive prefix sum over the lanes: shifts by 1, 2, 4, 8 within each row
+// (lanes shifted in from outside the row add 0), then the end of row 0 to
+// rows 1 and 3 and the end of row 1 to rows 2 and 3.
+__device__ inline int dpp_wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_SHR + 1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_SHR + 2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_SHR + 4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_SHR + 8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_BCAST15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, DPP_BCAST31, 0xc, 0xf, false);
+    return x;
+}
+
 // Columns a one-wave kernel hands back, buffered one per lane and appended
 // to the global list 64 at a time, so that a launch deferring most of its
 // columns does not serialise on one counter.  The list's order is

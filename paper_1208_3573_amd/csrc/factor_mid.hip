@@ -35,39 +35,20 @@ namespace mid {
 constexpr int ML = 8;     // max |L_j| (and right-hand sides of a solve)
 constexpr int MSW = 4;    // 64-bit words of a column's shared-row mask (256 shared rows)
 
+// v of lane src (the same src on every lane) on every lane, by readlane
 template <class T>
-__device__ inline T shfl(T v, int src)
+__device__ inline T bcast(T v, int src)
 {
-    if constexpr (num<T>::is_complex) return T{__shfl(v.x, src), __shfl(v.y, src)};
-    else return __shfl(v, src);
+    if constexpr (num<T>::is_complex) return T{readlane_f64(v.x, src), readlane_f64(v.y, src)};
+    else return readlane_f64(v, src);
 }
 
-__device__ inline int wave_incl_scan(int x, int lane)
-{
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-__device__ inline double wave_sum(double x)
-{
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
-
-__device__ inline double wave_max(double x)
-{
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
-    return x;
-}
-
-__device__ inline int wave_min_int(int x)
-{
-    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o));
-    return x;
-}
+// Whole-wave scan and reductions (every lane active): DPP and readlane,
+// no LDS round trips.
+__device__ inline int wave_incl_scan(int x, int) { return dpp_wave_incl_scan(x); }
+__device__ inline double wave_sum(double x) { return dpp_wave_sum(x); }
+__device__ inline double wave_max(double x) { return dpp_wave_max(x); }
+__device__ inline int wave_min_int(int x) { return dpp_wave_min(x); }
 
 // Packed lower triangle, row-major: G(i, q), q <= i.
 __device__ inline int ltri(int i, int q) { return i * (i + 1) / 2 + q; }
@@ -177,7 +158,7 @@ __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
 #pragma unroll
         for (int t = 0; t < ML; ++t) {
             if (t >= nr) break;
-            const T zp = num<T>::mk(inv) * shfl(x[t], p);
+            const T zp = num<T>::mk(inv) * bcast(x[t], p);
             if (lane == p) x[t] = zp;
             else if (lane > p) x[t] -= lip * zp;
         }
@@ -190,7 +171,7 @@ __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
 #pragma unroll
         for (int t = 0; t < ML; ++t) {
             if (t >= nr) break;
-            const T xp = num<T>::mk(inv) * shfl(x[t], p);
+            const T xp = num<T>::mk(inv) * bcast(x[t], p);
             if (lane == p) x[t] = xp;
             else if (lane < p) x[t] -= lpi * xp;
         }
@@ -275,7 +256,7 @@ __device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, co
     const int inc = wave_incl_scan(len, lane);
     if (lane < k) S.off[lane + 1] = inc;
     if (lane == 0) S.off[0] = 0;
-    const int Tn = __shfl(inc, 63);
+    const int Tn = __builtin_amdgcn_readlane(inc, 63);
     if (Tn > MT) { defer(); return; }
     for (int s = lane; s < HS; s += 64) S.h.key[s] = -1;
     __syncthreads();
@@ -375,7 +356,7 @@ __device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, co
             const int c = r < m ? cnt[r] : 0;
             const int incl = wave_incl_scan(c, lane);
             if (r < m) S.rptr[r] = (uint16_t)(base + incl - c);
-            base += __shfl(incl, 63);
+            base += __builtin_amdgcn_readlane(incl, 63);
         }
         if (lane == 0) S.rptr[m] = (uint16_t)Tn;
     }
@@ -510,10 +491,22 @@ __device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, co
         T sp = num<T>::zero();
         if (lane >= p && lane < k) {
             sp = S.G[ltri(lane, p)];
-            for (int q = 0; q < p; ++q)
-                sp -= S.G[ltri(lane, q)] * num<T>::conj(S.G[ltri(p, q)]);
+            // four terms at a time: their loads in flight together, the
+            // subtractions in ascending q as one at a time would do them
+            const T* gi = S.G + ltri(lane, 0);
+            const T* gp = S.G + ltri(p, 0);
+            int q = 0;
+            for (; q + 4 <= p; q += 4) {
+                const T a0 = gi[q], a1 = gi[q + 1], a2 = gi[q + 2], a3 = gi[q + 3];
+                const T b0 = gp[q], b1 = gp[q + 1], b2 = gp[q + 2], b3 = gp[q + 3];
+                sp -= a0 * num<T>::conj(b0);
+                sp -= a1 * num<T>::conj(b1);
+                sp -= a2 * num<T>::conj(b2);
+                sp -= a3 * num<T>::conj(b3);
+            }
+            for (; q < p; ++q) sp -= gi[q] * num<T>::conj(gp[q]);
         }
-        const double d = num<T>::re(shfl(sp, p));
+        const double d = num<T>::re(bcast(sp, p));
         if (!(d > 1e-14 * maxd)) flags |= DIAF_FLAG_RANK_DEFICIENT;
         const double piv = (d > 1e-30 * maxd && isfinite(d)) ? sqrt(d) : 0.0;
         const double inv = piv > 0.0 ? 1.0 / piv : 0.0;
@@ -696,7 +689,7 @@ __device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, co
     const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
     const int dpos = dposm ? __ffsll((unsigned long long)dposm) - 1 : -1;
     int piv;
-    if (dpos >= 0 && num<T>::abs(shfl(vt, dpos)) >= 1e-8 * vn) {
+    if (dpos >= 0 && num<T>::abs(bcast(vt, dpos)) >= 1e-8 * vn) {
         piv = dpos;
     } else {
         const double av = lane < l ? num<T>::abs(vt) : -1.0;
@@ -706,10 +699,10 @@ __device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, co
         const uint64_t pm = __ballot(lane < l && av == mx && gr == cand);
         piv = __ffsll((unsigned long long)pm) - 1;
     }
-    const T pvv = shfl(vt, piv);
+    const T pvv = bcast(vt, piv);
     const T ph = num<T>::iszero(pvv) ? num<T>::one() : unit_conj_phase(pvv);
     vt = ph * vt;
-    if (dpos < 0 || num<T>::abs(shfl(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
+    if (dpos < 0 || num<T>::abs(bcast(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
         flags |= DIAF_FLAG_SMALL_DIAG;
     if (lane < l) S.f.v[lane] = vt;
     if (lane < k) S.f.w[lane] = ph * S.f.w[lane];
