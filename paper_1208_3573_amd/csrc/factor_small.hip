@@ -88,11 +88,12 @@ struct SmallLds {
     uint8_t csr[STM];
 };
 
+// v of lane src (the same src on every lane) on every lane, by readlane
 template <class T>
-__device__ inline T shfl(T v, int src)
+__device__ inline T bcast(T v, int src)
 {
-    if constexpr (num<T>::is_complex) return T{__shfl(v.x, src), __shfl(v.y, src)};
-    else return __shfl(v, src);
+    if constexpr (num<T>::is_complex) return T{readlane_f64(v.x, src), readlane_f64(v.y, src)};
+    else return readlane_f64(v, src);
 }
 
 // Value of lane ^ 32 (the other half of the wave).
@@ -103,26 +104,11 @@ __device__ inline T shfl_xor32(T v)
     else return __shfl_xor(v, 32);
 }
 
-__device__ inline int wave_incl_scan(int x, int lane)
-{
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    return x;
-}
-
-__device__ inline double wave_sum(double x)
-{
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    return x;
-}
-
-__device__ inline double wave_max(double x)
-{
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
-    return x;
-}
+// Whole-wave scan and reductions (every lane active): DPP and readlane,
+// no LDS round trips.
+__device__ inline int wave_incl_scan(int x, int) { return dpp_wave_incl_scan(x); }
+__device__ inline double wave_sum(double x) { return dpp_wave_sum(x); }
+__device__ inline double wave_max(double x) { return dpp_wave_max(x); }
 
 // 1 / d from the hardware reciprocal and two Newton steps, r <- r + r (1 - d r)
 // (each step squares the relative error; the result is within an ulp or
@@ -347,7 +333,7 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     int inc = wave_incl_scan(len, lane);
     if (lane < k && k <= SKM) S.off[lane + 1] = inc;
     if (lane == 0) S.off[0] = 0;
-    const int Tn = __shfl(inc, 63);
+    const int Tn = __builtin_amdgcn_readlane(inc, 63);
     for (int s = lane; s < SHS; s += 64) S.sh.hkey[s] = -1;
     __syncthreads();
     if (k > SKM || Tn > STM) {
@@ -784,7 +770,7 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
     const uint64_t dposm = __ballot(lane < l && S.L[lane] == dj);
     const int dpos = dposm ? __ffsll((unsigned long long)dposm) - 1 : -1;
     int piv;
-    if (dpos >= 0 && num<T>::abs(shfl(vt, dpos)) >= 1e-8 * vn) {
+    if (dpos >= 0 && num<T>::abs(bcast(vt, dpos)) >= 1e-8 * vn) {
         piv = dpos;
     } else {
         const double av = lane < l ? num<T>::abs(vt) : -1.0;
@@ -792,14 +778,14 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
         // lowest global row among the maxima = lowest local row
         const int lr = lane < l ? S.L[lane] : 0x7fffffff;
         int cand = (lane < l && av == mx) ? lr : 0x7fffffff;
-        for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
+        cand = dpp_wave_min(cand);
         const uint64_t pm = __ballot(lane < l && av == mx && lr == cand);
         piv = __ffsll((unsigned long long)pm) - 1;
     }
-    const T pvv = shfl(vt, piv);
+    const T pvv = bcast(vt, piv);
     const T ph = num<T>::iszero(pvv) ? num<T>::one() : unit_conj_phase(pvv);
     vt = ph * vt;
-    if (dpos < 0 || num<T>::abs(shfl(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
+    if (dpos < 0 || num<T>::abs(bcast(vt, dpos < 0 ? 0 : dpos)) < 1e-2 * vn)
         flags |= DIAF_FLAG_SMALL_DIAG;
     if (lane < l) S.post.v[lane] = vt;
     if (lane < k) S.post.w[lane] = ph * S.post.w[lane];
@@ -814,7 +800,7 @@ __device__ __forceinline__ void small_column(const FactorArgs<T>& A, int j, Smal
         const bool vtri = A.vrule == V_DIAG || A.vrule == V_GS_UPPER || A.vrule == V_GS_LOWER ||
                           A.vrule == V_TOPK_UPPER || A.vrule == V_TOPK_LOWER ||
                           A.vrule == V_LEV_UPPER || A.vrule == V_LEV_LOWER;
-        if (A.stab_r > 0.0 && vtri && dpos >= 0 && num<T>::abs(shfl(vt, dpos)) < A.stab_tol * vn) {
+        if (A.stab_r > 0.0 && vtri && dpos >= 0 && num<T>::abs(bcast(vt, dpos)) < A.stab_tol * vn) {
             flags = (flags | DIAF_FLAG_STABILIZED) & ~(DIAF_FLAG_SMALL_DIAG | DIAF_FLAG_GAP_DEGENERATE);
             const int ls = l - 1;
             const int hs = lane >> 3, ht = lane & 7;
