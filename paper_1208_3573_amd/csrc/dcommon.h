@@ -212,6 +212,25 @@ __device__ inline int dpp_wave_incl_scan(int x)
     return x;
 }
 
+// Value of lane ^ 32 (the other half of the wave) by gfx950's
+// v_permlane32_swap, which swaps the upper half of its first operand with
+// the lower half of its second: with both operands x, the second result
+// holds x of the upper half in the lower lanes and the first result x of
+// the lower half in the upper lanes.  No LDS, unlike a shuffle.
+__device__ inline unsigned xor32_u32(unsigned x, bool low_half)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return low_half ? r[1] : r[0];
+}
+
+__device__ inline double xor32_f64(double x)
+{
+    const bool low = (threadIdx.x & 63u) < 32u;
+    const long long b = __double_as_longlong(x);
+    const unsigned lo = xor32_u32((unsigned)b, low), hi = xor32_u32((unsigned)(b >> 32), low);
+    return __longlong_as_double(((long long)hi << 32) | lo);
+}
+
 // Columns a one-wave kernel hands back, buffered one per lane and appended
 // to the global list 64 at a time, so that a launch deferring most of its
 // columns does not serialise on one counter.  The list's order is

@@ -100,8 +100,8 @@ __device__ inline T bcast(T v, int src)
 template <class T>
 __device__ inline T shfl_xor32(T v)
 {
-    if constexpr (num<T>::is_complex) return T{__shfl_xor(v.x, 32), __shfl_xor(v.y, 32)};
-    else return __shfl_xor(v, 32);
+    if constexpr (num<T>::is_complex) return T{xor32_f64(v.x), xor32_f64(v.y)};
+    else return xor32_f64(v);
 }
 
 // Whole-wave scan and reductions (every lane active): DPP and readlane,
