@@ -1,6 +1,6 @@
 // Mid-size column kernel for the first basic algorithm (unit-norm columns
 // of V, paper Section 2.1): one wave per column for |J_j| <= MK (32 or 64)
-// and at most MT (256, 512 or 1024) gathered entries, so for shadows far
+// and at most MT (256, 512, 768 or 1024) gathered entries, so for shadows far
 // beyond the one-wave kernel's 64 rows.  Columns it cannot take (more than
 // 256 rows of B_j holding two or more entries, |L_j| > 8) are appended to a
 // deferred list for the generic kernel.
@@ -54,10 +54,11 @@ __device__ inline int wave_min_int(int x) { return dpp_wave_min(x); }
 __device__ inline int ltri(int i, int q) { return i * (i + 1) / 2 + q; }
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+constexpr int pow2ceil(int x) { return x <= 1 ? 1 : 2 * pow2ceil((x + 1) / 2); }
 
 template <class T, int MK, int MT>
 struct MidLds {
-    static constexpr int HS = 2 * MT;  // hash slots (load factor <= 1/2)
+    static constexpr int HS = pow2ceil(2 * MT);  // hash slots (load factor <= 1/2)
     static constexpr int HB = ilog2(HS);
     int a0[64];              // start of each column of B in A (lanes >= |J_j|: 0)
     int alen[64];            // and its length
@@ -321,7 +322,7 @@ __device__ void mid_column(const FactorArgs<T>& A, const int j, const int jb, co
         if (dm && dj < 0) dj = r0 + __ffsll((unsigned long long)dm) - 1;
     }
     __syncthreads();
-    // the hash table is dead from here: its keys' storage (HS = 2 MT ints)
+    // the hash table is dead from here: its keys' storage (HS >= 2 MT ints)
     // holds the row counters cnt[0..m) and cnt[MT..MT+m)
     int* cnt = S.h.key;
     for (int r = lane; r < m; r += 64) { cnt[r] = 0; cnt[MT + r] = 0; }
@@ -799,8 +800,9 @@ int mid_classes(int* kcap, int* tcap)
 {
     // capacities of the kernel instances, smallest LDS first (a column takes
     // the first that holds it)
-    static const int cls[][2] = {{32, 256}, {32, 512}, {64, 512}, {32, 1024}, {64, 1024}};
-    const int nc = num<T>::is_complex ? 1 : 5;
+    static const int cls[][2] = {{32, 256}, {32, 512}, {64, 512}, {32, 1024}, {64, 768},
+                                 {64, 1024}};
+    const int nc = num<T>::is_complex ? 1 : 6;
     for (int c = 0; c < nc; ++c) { kcap[c] = cls[c][0]; tcap[c] = cls[c][1]; }
     return nc;
 }
@@ -828,6 +830,7 @@ Err launch_factor_mid(const FactorArgs<T>& A, int kcap, int tcap, int* deferred,
         if (kcap <= 32 && tcap <= 512) return launch_mid_t<T, 32, 512>(A, deferred, ndeferred, grid, st);
         if (tcap <= 512) return launch_mid_t<T, 64, 512>(A, deferred, ndeferred, grid, st);
         if (kcap <= 32) return launch_mid_t<T, 32, 1024>(A, deferred, ndeferred, grid, st);
+        if (tcap <= 768) return launch_mid_t<T, 64, 768>(A, deferred, ndeferred, grid, st);
         return launch_mid_t<T, 64, 1024>(A, deferred, ndeferred, grid, st);
     }
     return {DIAF_EINVAL, "mid kernel: size class too large"};
@@ -843,6 +846,7 @@ double mid_occupancy(int kcap, int tcap)
         if (!k && kcap <= 32 && tcap <= 512) k = (const void*)mid::factor_mid_kernel<T, 32, 512>;
         if (!k && tcap <= 512) k = (const void*)mid::factor_mid_kernel<T, 64, 512>;
         if (!k && kcap <= 32) k = (const void*)mid::factor_mid_kernel<T, 32, 1024>;
+        if (!k && tcap <= 768) k = (const void*)mid::factor_mid_kernel<T, 64, 768>;
         if (!k) k = (const void*)mid::factor_mid_kernel<T, 64, 1024>;
     }
     if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0) != hipSuccess) return 0.0;
