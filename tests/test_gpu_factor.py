@@ -216,6 +216,41 @@ def _unit_values(A):
     return synth.CSC(n=A.n, colptr=A.colptr, rowidx=A.rowidx, val=np.ones_like(A.val))
 
 
+TIES = {
+    # constant coefficients and unit values: many exactly equal scores |(B w0)_i|,
+    # so the top-(l-1) choice runs through the 1e-10 tie band and its
+    # ascending-row fill
+    "helmholtz_24 unit_v topk_upper": (lambda: synth.helmholtz(24), "A2", 0, "topk_upper", 7,
+                                       "unit_v"),
+    "helmholtz_24 unit_w topk_upper": (lambda: synth.helmholtz(24), "A2", 0, "topk_upper", 7,
+                                       "unit_w"),
+    "unit values 1hop unit_v topk_lower": (lambda: _unit_values(synth.random_small(600, 6, 4)),
+                                           "A_1hop_topk", 6, "topk_lower", 5, "unit_v"),
+}
+
+
+@pytest.mark.parametrize("name", list(TIES))
+def test_generic_kernel_ties_match_oracle(ctx, name):
+    """The generic kernel (every column sent to it) on inputs with tied
+    scores: V patterns identical to the oracle's, residual and angle bars."""
+    from paper_1208_3573_amd import diaf
+    build, w, wtopk, v, l, mode = TIES[name]
+    A = build()
+    J = oracle_pattern(A, w, wtopk)
+    say(f"case {name} n={A.n}")
+    ctx.set_option("generic_only", 1)
+    try:
+        F, H, _ = run_gpu(ctx, A, w, v, l, mode, wtopk=wtopk)
+    finally:
+        ctx.set_option("generic_only", 0)
+    O = oracle.factor(A, J, mode, v, l)
+    summ = compare(H, J, O, A, mode)
+    st = F.stats()
+    assert sum(st.cols_generic_class) == A.n
+    say(f"  {summ}")
+    F.close()
+
+
 def test_pattern_builders_match_oracle(ctx):
     from paper_1208_3573_amd import diaf
     cases = [(synth.random_small(500, 4, 3), "A2", 0),
