@@ -189,8 +189,9 @@ __device__ void chol_solve(MidLds<T, MK, MT>& S, int k, int nr, int lane)
 // (stage 1: J_j's bounds; 2: J_j; 3: A's column bounds) and publishes it to
 // LDS (stage 4) before the current column's output stores, so the latency of
 // that chain overlaps the current column's work.  The column numbers
-// themselves come 64 at a time, one per lane, so no load is issued between
-// two columns (where its wait would also wait for the stores just issued).
+// themselves come 64 at a time, one per lane, so between two columns no load
+// is issued but at every 64th (a wait there would also wait for the stores
+// just issued).
 // Indices pass through a register the compiler cannot prove uniform, so
 // these are vector loads: a pending scalar load would hold up every LDS
 // wait.
