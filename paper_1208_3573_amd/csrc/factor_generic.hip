@@ -42,9 +42,11 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 // number of k x k matrices kept here (1: G, unit-norm v; 3: G, E, Z,
 // unit-norm w; 0: in a separate global slot).  lds_budget > 0 splits the
 // storage: the small and index arrays read on every step (reduction and
-// flag slots, column offsets, the row/column/position cross references)
-// go, in that order of priority, to LDS while they fit in lds_budget bytes,
-// and everything else stays in the global slot.
+// flag slots, column offsets, the small vectors, the local row of each
+// entry, the right-hand sides of the triangular solves, the column and
+// position cross references) go, in that order of priority, to LDS while
+// they fit in lds_budget bytes, and everything else stays in the global
+// slot.
 __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, int lcap, size_t st,
                                                 int with_mats, size_t lds_budget = 0)
 {
@@ -66,7 +68,12 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
     L.oJ = takep(GA_J, sizeof(int32_t) * kcap);
     L.oL = takep(GA_L, sizeof(int32_t) * lcap);
     L.oSel = takep(GA_SEL, sizeof(int32_t) * lcap);
+    L.oW = takep(GA_W, st * kcap);
+    L.oVM = takep(GA_VM, st * lcap * lcap);
+    L.oSig = takep(GA_SIG, sizeof(double) * lcap);
+    L.oV = takep(GA_V, st * lcap);
     L.oLrow = takep(GA_LROW, sizeof(uint16_t) * tcap);
+    L.oX = takep(GA_X, st * kcap * (lcap + 1));
     L.oCol = takep(GA_COL, sizeof(uint16_t) * tcap);
     L.oPos = takep(GA_POS, sizeof(uint16_t) * tcap);
     L.oRowptr = takep(GA_ROWPTR, sizeof(uint16_t) * (tcap + 1));
@@ -75,11 +82,6 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
     L.oR = take(sizeof(int32_t) * tcap);
     L.oRank = take(sizeof(int32_t) * tcap);
     L.oY = take(st * tcap);
-    L.oW = take(st * kcap);
-    L.oX = take(st * kcap * (lcap + 1));
-    L.oVM = take(st * lcap * lcap);
-    L.oSig = take(sizeof(double) * lcap);
-    L.oV = take(st * lcap);
     L.oMats = o;
     if (with_mats) take(st * (size_t)with_mats * kcap * kcap);
     L.total = o;
