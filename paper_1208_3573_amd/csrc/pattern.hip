@@ -372,10 +372,16 @@ Err launch_pattern_a2(int n, const int32_t* Ocp, const int32_t* Ori, const int32
     return {};
 }
 
-// pattern(A) + top-p two-hop rows.  Keys: (row << 32) | gather position;
-// gather positions follow ascending c, so equal rows sort by ascending c.
+// pattern(A) + top-p two-hop rows.  Keys: (row << 32) | (q << 12) | t for the
+// entry at gather position t, which comes from the q-th column c of
+// pattern(A(:, j)) (t, q < 4096 since cap <= 4096); gather positions follow
+// ascending c, so equal rows order by ascending c, and every key is unique.
+// The gather is na runs already sorted by row (the rows of each A(:, c)),
+// merged pairwise in ceil(log2 na) rounds; a round-r element belongs to the
+// merged group q >> r, so it finds its new place by one binary search in the
+// partner group.
 // Dynamic LDS: keys[cap] u64, prod[cap] f64, sc[cap] f64, off[cap+1] i32,
-// scrow[cap] i32, red[nthreads+1] i32, sel[256] i32.
+// scrow[cap] i32, red[nthreads+1] i32, sel[256] i32, cst[cap] i32.
 template <class T>
 __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ari, const T* Aval,
                                     int ptop, int cap, const int32_t* cols, int32_t* cnt,
@@ -389,58 +395,91 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     int32_t* scrow = off + cap + 1;
     int32_t* red = scrow + cap;
     int32_t* sel = red + blockDim.x + 1;
+    int32_t* cst = sel + 256;
     __shared__ int32_t s_nsel, s_above, s_pick[2], s_hist[256];
     const int j = cols[blockIdx.x];
     const int tid = threadIdx.x;
     const int a0 = Acp[j], na = Acp[j + 1] - a0;
+    // merge rounds; the gather writes into the buffer that the last round
+    // leaves in keys, and |A(c, j)| is staged in the other one
+    int rounds = 0;
+    while ((1 << rounds) < na) ++rounds;
+    uint64_t* gbuf = (rounds & 1) ? (uint64_t*)sc : keys;
+    double* acj = (rounds & 1) ? (double*)keys : sc;
     // off[q] = total length of A(:, c) over the first q columns c of
-    // pattern(A(:, j)) (an exclusive scan), off[na] = the gathered count
+    // pattern(A(:, j)) (an exclusive scan), off[na] = the gathered count.
+    // Staged in LDS for the gather and the candidate test (the score arrays
+    // are free until the scores): the rows c of A(:, j) (ascending) in
+    // scrow, |A(c, j)| in acj, the start of A(:, c) in cst.
     for (int q = tid; q < na; q += blockDim.x) {
         const int c = Ari[a0 + q];
-        off[q] = Acp[c + 1] - Acp[c];
+        const int c0 = Acp[c];
+        off[q] = Acp[c + 1] - c0;
+        cst[q] = c0;
+        scrow[q] = c;
+        if constexpr (num<T>::is_complex) {
+            const T y = Aval[a0 + q];
+            acj[q] = __dsqrt_rn(__dadd_rn(__dmul_rn(y.x, y.x), __dmul_rn(y.y, y.y)));
+        } else {
+            acj[q] = fabs(Aval[a0 + q]);
+        }
     }
     __syncthreads();
     const int Tn = block_scan01(off, na, red);
     if (tid == 0) off[na] = Tn;
     __syncthreads();
-    int T2 = 1;
-    while (T2 < Tn) T2 <<= 1;
-    for (int t = tid; t < T2; t += blockDim.x) {
-        if (t < Tn) {
-            int lo = 0, hi = na - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            int c = Ari[a0 + lo];
-            int p = Acp[c] + (t - off[lo]);
-            double aic, acj;
-            if constexpr (num<T>::is_complex) {
-                T x = Aval[p], y = Aval[a0 + lo];
-                aic = __dsqrt_rn(__dadd_rn(__dmul_rn(x.x, x.x), __dmul_rn(x.y, x.y)));
-                acj = __dsqrt_rn(__dadd_rn(__dmul_rn(y.x, y.x), __dmul_rn(y.y, y.y)));
-            } else {
-                aic = fabs(Aval[p]);
-                acj = fabs(Aval[a0 + lo]);
-            }
-            prod[t] = __dmul_rn(aic, acj);
-            keys[t] = ((uint64_t)(uint32_t)Ari[p] << 32) | (uint32_t)t;
-        } else {
-            keys[t] = ~0ull;
+    for (int t = tid; t < Tn; t += blockDim.x) {
+        int lo = 0, hi = na - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= t) lo = mid; else hi = mid - 1;
         }
+        const int p = cst[lo] + (t - off[lo]);
+        double aic;
+        if constexpr (num<T>::is_complex) {
+            const T x = Aval[p];
+            aic = __dsqrt_rn(__dadd_rn(__dmul_rn(x.x, x.x), __dmul_rn(x.y, x.y)));
+        } else {
+            aic = fabs(Aval[p]);
+        }
+        prod[t] = __dmul_rn(aic, acj[lo]);
+        gbuf[t] = ((uint64_t)(uint32_t)Ari[p] << 32) | ((uint32_t)lo << 12) | (uint32_t)t;
     }
     __syncthreads();
-    block_bitonic(keys, T2);
-    // segment starts of rows outside pattern(A(:, j)) are the candidates
+    for (int r = 0; r < rounds; ++r) {
+        const uint64_t* src = ((rounds - r) & 1) ? (const uint64_t*)sc : keys;
+        uint64_t* dst = ((rounds - r) & 1) ? keys : (uint64_t*)sc;
+        for (int t = tid; t < Tn; t += blockDim.x) {
+            const uint64_t key = src[t];
+            const int g = (int)((key >> 12) & 0xfff) >> r, h = g ^ 1;
+            const int gs = off[g << r];
+            if ((h << r) >= na) {
+                dst[t] = key;  // no partner group this round
+                continue;
+            }
+            const int hs = off[h << r], he = off[min((h + 1) << r, na)];
+            int lo = hs, hi = he;  // first partner key above this one
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (src[mid] < key) lo = mid + 1; else hi = mid;
+            }
+            dst[min(gs, hs) + (t - gs) + (lo - hs)] = key;
+        }
+        __syncthreads();
+    }
+    // segment starts of rows outside pattern(A(:, j)) are the candidates;
+    // the rows of A(:, j) are copied to cst for the final union (scrow is
+    // reused for the candidates' rows)
+    for (int q = tid; q < na; q += blockDim.x) cst[q] = scrow[q];
     for (int t = tid; t < Tn; t += blockDim.x) {
         int row = (int)(keys[t] >> 32);
         int start = (t == 0 || (keys[t] >> 32) != (keys[t - 1] >> 32));
         int inA = 0;
         if (start) {
-            int lo = a0, hi = a0 + na - 1;
+            int lo = 0, hi = na - 1;
             while (lo <= hi) {
                 int mid = (lo + hi) >> 1;
-                int v = Ari[mid];
+                int v = scrow[mid];
                 if (v == row) { inA = 1; break; }
                 if (v < row) lo = mid + 1; else hi = mid - 1;
             }
@@ -457,7 +496,7 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
         int row = (int)(keys[t] >> 32);
         double s = 0.0;
         for (int u = t; u < Tn && (int)(keys[u] >> 32) == row; ++u)
-            s = __dadd_rn(s, prod[(uint32_t)keys[u]]);
+            s = __dadd_rn(s, prod[keys[u] & 0xfff]);
         sc[slot] = s;
         scrow[slot] = row;
     }
@@ -484,22 +523,30 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
         }
     }
     __syncthreads();
-    // output = sorted(rows(A(:, j)) U sel)
+    // output = sorted(rows(A(:, j)) U sel), into the column's slot of
+    // capacity |A(:, j)| + ptop.  The picks are distinct and outside
+    // A(:, j), so each entry's place is the number of rows of both sets
+    // below it.
     const int tot = na + take;
-    int N2 = 1;
-    while (N2 < tot) N2 <<= 1;
-    for (int t = tid; t < N2; t += blockDim.x) {
-        uint64_t kv = ~0ull;
-        if (t < na) kv = (uint32_t)Ari[a0 + t];
-        else if (t < tot) kv = (uint32_t)sel[t - na];
-        keys[t] = kv;
-    }
-    __syncthreads();
-    block_bitonic(keys, N2);
-    // into the column's slot of capacity |A(:, j)| + ptop
     if (tid == 0) cnt[j] = tot;
     int32_t* out = Jtmp + a0 + (size_t)j * ptop;
-    for (int t = tid; t < tot; t += blockDim.x) out[t] = (int32_t)keys[t];
+    for (int t = tid; t < na; t += blockDim.x) {
+        const int row = cst[t];
+        int below = 0;
+        for (int u = 0; u < take; ++u) below += sel[u] < row;
+        out[t + below] = row;
+    }
+    for (int u = tid; u < take; u += blockDim.x) {
+        const int x = sel[u];
+        int lo = 0, hi = na;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cst[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        int below = 0;
+        for (int v = 0; v < take; ++v) below += sel[v] < x;
+        out[lo + below] = x;
+    }
 }
 
 // Jri[Jcp[j] ..] = the cnt[j] rows of column j's slot in Jtmp (one wave per
@@ -538,7 +585,7 @@ Err launch_pattern_1hop(int n, const int32_t* Acp, const int32_t* Ari, const T* 
     int cap = pow2_at_least(cand_max + ptop + 1 < 256 ? 256 : cand_max + ptop + 1);
     if (cap > 4096) return {DIAF_EUNSUPPORTED, "1-hop pattern: more than 3839 two-hop candidates in a column"};
     int nt = cap <= 512 ? 128 : 256;
-    size_t lds = (sizeof(uint64_t) + 2 * sizeof(double) + 2 * sizeof(int32_t)) * cap +
+    size_t lds = (sizeof(uint64_t) + 2 * sizeof(double) + 3 * sizeof(int32_t)) * cap +
                  sizeof(int32_t) * (1 + nt + 1 + 256);
     auto kern = pattern_1hop_kernel<T>;
     DIAF_HIP_TRY(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
