@@ -9,8 +9,9 @@
 // summed in ascending c with explicit round-to-nearest operations so the
 // scores are reproducible bit for bit, ties going to the lower row.
 //
-// Each column is one workgroup: candidates are gathered into LDS, sorted
-// with a bitonic network and deduplicated.  A first launch counts, a
+// Each column is one workgroup: candidates are gathered into LDS as one
+// sorted run per inner column, merged pairwise (ceil(log2) rounds of one
+// binary search per entry) and deduplicated.  A first launch counts, a
 // second fills the rows at the scanned offsets.
 #include <hipcub/hipcub.hpp>
 
@@ -166,25 +167,6 @@ Err sort_columns(int n, int m, const int32_t* in, int32_t* out, hipStream_t st)
     return {};
 }
 
-// Bitonic sort of keys[0..N2) (N2 a power of two) by the whole block.
-template <class K>
-__device__ inline void block_bitonic(K* keys, int N2)
-{
-    for (int kk = 2; kk <= N2; kk <<= 1) {
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = threadIdx.x; i < N2; i += blockDim.x) {
-                int ixj = i ^ jj;
-                if (ixj > i) {
-                    K x = keys[i], y = keys[ixj];
-                    bool up = (i & kk) == 0;
-                    if ((x > y) == up) { keys[i] = y; keys[ixj] = x; }
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
 // Inclusive sum of x over the lanes of the wave up to this one.
 __device__ inline int wave_incl_scan(int x)
 {
@@ -262,10 +244,13 @@ __device__ inline double block_kth_largest(const double* v, int cnt, int q, int3
 }
 
 // pattern(A^2), one block per column; cap candidates max (power of two),
-// dynamic LDS: keys[cap] u32, off[cap+1] i32, red[nthreads+1] i32.
+// dynamic LDS: keys[cap] u32, off[cap+1] i32, red[nthreads+1] i32,
+// keys2[cap] u32.
 // Column j of the union pattern: the sorted union of the inner lists
 // (Icp/Iri) named by the outer list of column j (Ocp/Ori).  pattern(A^2):
-// outer and inner lists are both the columns of A.
+// outer and inner lists are both the columns of A.  The gathered inner
+// lists are na sorted runs, merged pairwise in ceil(log2 na) rounds (equal
+// rows: the left group's first), then duplicates dropped.
 __global__ void pattern_a2_kernel(int n, const int32_t* Ocp, const int32_t* Ori,
                                   const int32_t* Icp, const int32_t* Iri, int cap, int32_t* cnt,
                                   const int32_t* Jcp, int32_t* Jri)
@@ -274,6 +259,7 @@ __global__ void pattern_a2_kernel(int n, const int32_t* Ocp, const int32_t* Ori,
     uint32_t* keys = (uint32_t*)lds;
     int32_t* off = (int32_t*)(keys + cap);
     int32_t* red = off + cap + 1;
+    uint32_t* keys2 = (uint32_t*)(red + blockDim.x + 1);
     __shared__ int32_t s_tot;
     const int j = blockIdx.x;
     const int tid = threadIdx.x;
@@ -288,23 +274,56 @@ __global__ void pattern_a2_kernel(int n, const int32_t* Ocp, const int32_t* Ori,
     }
     __syncthreads();
     const int T = s_tot;
-    int T2 = 1;
-    while (T2 < T) T2 <<= 1;
-    for (int t = tid; t < T2; t += blockDim.x) {
-        if (t < T) {
-            int lo = 0, hi = na - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            int c = Ori[a0 + lo];
-            keys[t] = (uint32_t)Iri[Icp[c] + (t - off[lo])];
-        } else {
-            keys[t] = 0xffffffffu;
+    // the gather writes into the buffer that the last round leaves in keys
+    int rounds = 0;
+    while ((1 << rounds) < na) ++rounds;
+    uint32_t* gbuf = (rounds & 1) ? keys2 : keys;
+    // run containing gather position t: the last q < na with off[q] <= t
+    // (inner lists may be empty)
+    auto run_of = [&](int t) {
+        int lo = 0, hi = na - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= t) lo = mid; else hi = mid - 1;
         }
+        return lo;
+    };
+    for (int t = tid; t < T; t += blockDim.x) {
+        const int q = run_of(t);
+        const int c = Ori[a0 + q];
+        gbuf[t] = (uint32_t)Iri[Icp[c] + (t - off[q])];
     }
     __syncthreads();
-    block_bitonic(keys, T2);
+    for (int r = 0; r < rounds; ++r) {
+        const uint32_t* src = ((rounds - r) & 1) ? keys2 : keys;
+        uint32_t* dst = ((rounds - r) & 1) ? keys : keys2;
+        for (int t = tid; t < T; t += blockDim.x) {
+            // merged groups of 2^r runs cover contiguous gather ranges, so
+            // the run at position t names the group of the entry there
+            const uint32_t key = src[t];
+            const int g = run_of(t) >> r, h = g ^ 1;
+            const int gs = off[g << r];
+            if ((h << r) >= na) {
+                dst[t] = key;
+                continue;
+            }
+            const int hs = off[h << r], he = off[min((h + 1) << r, na)];
+            int lo = hs, hi = he;  // partner entries below (left) or not above (right)
+            if (g < h) {
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (src[mid] < key) lo = mid + 1; else hi = mid;
+                }
+            } else {
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (src[mid] <= key) lo = mid + 1; else hi = mid;
+                }
+            }
+            dst[min(gs, hs) + (t - gs) + (lo - hs)] = key;
+        }
+        __syncthreads();
+    }
     // unique flags into off[] (reused)
     for (int t = tid; t < T; t += blockDim.x) off[t] = (t == 0 || keys[t] != keys[t - 1]) ? 1 : 0;
     __syncthreads();
@@ -361,9 +380,9 @@ Err launch_pattern_a2(int n, const int32_t* Ocp, const int32_t* Ori, const int32
 {
     if (n == 0) return {};
     int cap = pow2_at_least(maxcand < 64 ? 64 : maxcand);
-    if (cap > 16384) return {DIAF_EUNSUPPORTED, "pattern(A^2): more than 16384 candidates in a column"};
+    if (cap > 8192) return {DIAF_EUNSUPPORTED, "pattern(A^2): more than 8192 candidates in a column"};
     int nt = cap <= 256 ? 64 : (cap <= 4096 ? 256 : 1024);
-    size_t lds = sizeof(uint32_t) * cap + sizeof(int32_t) * (cap + 1) + sizeof(int32_t) * (nt + 1);
+    size_t lds = 2 * sizeof(uint32_t) * cap + sizeof(int32_t) * (cap + 1) + sizeof(int32_t) * (nt + 1);
     DIAF_HIP_TRY(hipFuncSetAttribute((const void*)pattern_a2_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(pattern_a2_kernel, dim3(n), dim3(nt), lds, st, n, Ocp, Ori, Icp, Iri, cap,
