@@ -544,45 +544,55 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
         c.sOff[a + 1] = A.Acp[col + 1] - A.Acp[col];
     }
     __syncthreads();
-    if (tid == 0) {
-        for (int a = 0; a < k; ++a) c.sOff[a + 1] += c.sOff[a];
-        c.mi[MI_T] = c.sOff[k];
-    }
-    __syncthreads();
-    const int Tn = c.mi[MI_T];
-    int T2 = 1;
-    while (T2 < Tn) T2 <<= 1;
+    const int Tn = block_scan_flags(c, c.sOff + 1, c.sOff + 1, k);
     // ---- 2. gather ----
-    for (int t = tid; t < T2; t += c.nt) {
-        if (t < Tn) {
-            int lo = 0, hi = k - 1;  // largest a with sOff[a] <= t
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (c.sOff[mid] <= t) lo = mid; else hi = mid - 1;
-            }
-            int a = lo;
-            int p = A.Acp[c.sJ[a]] + (t - c.sOff[a]);
-            c.sKey[t] = ((uint64_t)(uint32_t)A.Ari[p] << 32) | (uint32_t)t;
-            c.sVal[t] = A.Aval[p];
-            c.sCol[t] = a;
-        } else {
-            c.sKey[t] = ~0ull;
+    // Keys (row << 32) | (a << 16) | t for the entry at gather position t,
+    // which comes from A(:, J_j(a)) (t and a < 65536, the u16 cross
+    // references); gather positions follow ascending a, so this orders by
+    // (row, t), and every key is unique.  The gather is k runs sorted by row
+    // (one per column of A), merged pairwise in ceil(log2 k) rounds; the
+    // right-hand-side array, unused until the V pattern, is the second
+    // buffer, and the gather writes into the one the last round leaves in
+    // sKey.
+    int rounds = 0;
+    while ((1 << rounds) < k) ++rounds;
+    uint64_t* ybuf = (uint64_t*)c.sY;
+    uint64_t* gbuf = (rounds & 1) ? ybuf : c.sKey;
+    for (int t = tid; t < Tn; t += c.nt) {
+        int lo = 0, hi = k - 1;  // largest a with sOff[a] <= t
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (c.sOff[mid] <= t) lo = mid; else hi = mid - 1;
         }
+        int a = lo;
+        int p = A.Acp[c.sJ[a]] + (t - c.sOff[a]);
+        gbuf[t] = ((uint64_t)(uint32_t)A.Ari[p] << 32) | ((uint32_t)a << 16) | (uint32_t)t;
+        c.sVal[t] = A.Aval[p];
+        c.sCol[t] = a;
     }
     __syncthreads();
-    // ---- 3. bitonic sort by (row, t) ----
-    for (int kk = 2; kk <= T2; kk <<= 1) {
-        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < T2; i += c.nt) {
-                int ixj = i ^ jj;
-                if (ixj > i) {
-                    uint64_t x = c.sKey[i], y = c.sKey[ixj];
-                    bool up = (i & kk) == 0;
-                    if ((x > y) == up) { c.sKey[i] = y; c.sKey[ixj] = x; }
-                }
+    // ---- 3. merge rounds: sort by (row, t) ----
+    for (int r = 0; r < rounds; ++r) {
+        const uint64_t* src = ((rounds - r) & 1) ? ybuf : c.sKey;
+        uint64_t* dst = ((rounds - r) & 1) ? c.sKey : ybuf;
+        for (int t = tid; t < Tn; t += c.nt) {
+            const uint64_t key = src[t];
+            // merged groups of 2^r runs; this entry's is (its run) >> r
+            const int g = (int)((key >> 16) & 0xffff) >> r, h = g ^ 1;
+            const int gs = c.sOff[g << r];
+            if ((h << r) >= k) {
+                dst[t] = key;  // no partner group this round
+                continue;
             }
-            __syncthreads();
+            const int hs = c.sOff[h << r], he = c.sOff[min((h + 1) << r, k)];
+            int lo = hs, hi = he;  // first partner key above this one
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (src[mid] < key) lo = mid + 1; else hi = mid;
+            }
+            dst[min(gs, hs) + (t - gs) + (lo - hs)] = key;
         }
+        __syncthreads();
     }
     // ---- 4. shadow rows and CSR/CSC cross references ----
     for (int i = tid; i < Tn; i += c.nt)
@@ -591,7 +601,7 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
     int m = block_scan_flags(c, c.sRank, c.sRank, Tn);
     for (int i = tid; i < Tn; i += c.nt) {
         int lr = c.sRank[i] - 1;
-        int t = (int)(uint32_t)c.sKey[i];
+        int t = (int)(c.sKey[i] & 0xffff);
         c.sPos[i] = t;
         c.sLrow[t] = lr;
         if (i == 0 || (c.sKey[i] >> 32) != (c.sKey[i - 1] >> 32)) {
