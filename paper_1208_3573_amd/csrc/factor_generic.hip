@@ -92,7 +92,7 @@ __host__ __device__ inline GenLayout gen_layout(int kcap, int tcap, int tcap2, i
 // misc slots (int view / double view)
 enum { MI_T = 0, MI_M, MI_DJ, MI_FLAGS, MI_L, MI_NC, MI_ROT, MI_BEST, MI_Q, MI_EDGE, MI_NIN,
        MI_STAB, MI_DPOS, MI_NULL, MI_RDIG, MI_RREM };
-enum { MD_SSTAR = 16, MD_PIV, MD_MAXD, MD_GAP, MD_BN2, MD_ERE, MD_EIM, MD_FRO2 };
+enum { MD_SSTAR = 16, MD_MAXD = 18, MD_GAP, MD_BN2, MD_ERE, MD_EIM, MD_FRO2 };
 
 template <class T>
 struct GenCtx {
@@ -206,24 +206,30 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
     }
     __syncthreads();
     const double maxd = c.md[MD_MAXD];
+    // column p of the factor is staged in the reduction array (unused here;
+    // GNT doubles hold the k <= 256 entries, complex ones too)
+    T* lp = (T*)c.sRed;
+    const int lane = c.tid & 63, wv = c.tid >> 6, nw = c.nt >> 6;
     for (int p = 0; p < k; ++p) {
-        if (c.tid == 0) {
-            double d = num<T>::re(G[p * k + p]);
-            double piv = 0.0;
-            if (d > 1e-30 * maxd && isfinite(d)) piv = sqrt(d);
-            if (!(d > 1e-14 * maxd)) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
-            G[p * k + p] = num<T>::mk(piv);
-            c.md[MD_PIV] = piv;
+        // every thread forms the pivot from the updated diagonal; thread 0
+        // stores it after the barrier, once all have read the diagonal
+        const double d = num<T>::re(G[p * k + p]);
+        double piv = 0.0;
+        if (d > 1e-30 * maxd && isfinite(d)) piv = sqrt(d);
+        for (int i = p + 1 + c.tid; i < k; i += c.nt) {
+            const T v = piv > 0.0 ? num<T>::div(G[i * k + p], piv) : num<T>::zero();
+            G[i * k + p] = v;
+            lp[i] = v;
         }
         __syncthreads();
-        const double piv = c.md[MD_PIV];
-        for (int i = p + 1 + c.tid; i < k; i += c.nt)
-            G[i * k + p] = piv > 0.0 ? num<T>::div(G[i * k + p], piv) : num<T>::zero();
-        __syncthreads();
-        const int rem = k - p - 1;
-        for (int idx = c.tid; idx < rem * rem; idx += c.nt) {
-            int i = p + 1 + idx / rem, q = p + 1 + idx % rem;
-            if (q <= i) G[i * k + q] -= G[i * k + p] * num<T>::conj(G[q * k + p]);
+        if (c.tid == 0) {
+            if (!(d > 1e-14 * maxd)) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
+            G[p * k + p] = num<T>::mk(piv);
+        }
+        // trailing update of the lower triangle, one wave per row
+        for (int i = p + 1 + wv; i < k; i += nw) {
+            const T li = lp[i];
+            for (int q = p + 1 + lane; q <= i; q += 64) G[i * k + q] -= li * num<T>::conj(lp[q]);
         }
         __syncthreads();
     }
@@ -1045,7 +1051,7 @@ __device__ void factor_one_column(const FactorArgs<T>& A, int j, GenCtx<T>& c)
 }
 
 template <class T, bool IN_LDS>
-__global__ void __launch_bounds__(GNT) factor_generic_kernel(FactorArgs<T> A, int kcap, int tcap,
+__global__ void __launch_bounds__(GNT, 4) factor_generic_kernel(FactorArgs<T> A, int kcap, int tcap,
                                                              int tcap2, int lcap, int nmats_here,
                                                              unsigned char* gws, size_t slot_bytes,
                                                              T* gmats, size_t lds_split)
