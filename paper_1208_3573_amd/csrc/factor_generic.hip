@@ -226,10 +226,26 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
             if (!(d > 1e-14 * maxd)) c.mi[MI_FLAGS] |= DIAF_FLAG_RANK_DEFICIENT;
             G[p * k + p] = num<T>::mk(piv);
         }
-        // trailing update of the lower triangle, one wave per row
-        for (int i = p + 1 + wv; i < k; i += nw) {
-            const T li = lp[i];
-            for (int q = p + 1 + lane; q <= i; q += 64) G[i * k + q] -= li * num<T>::conj(lp[q]);
+        // trailing update of the lower triangle: each wave takes four rows
+        // at a time and lanes sweep the columns q <= i, 64 per pass, with the
+        // four rows' loads of a pass issued before their stores (a load
+        // issued after a store waits for it too)
+        for (int i0 = p + 1 + 4 * wv; i0 < k; i0 += 4 * nw) {
+            const int imax = min(i0 + 3, k - 1);
+            for (int q = p + 1 + lane; q - lane <= imax; q += 64) {
+                T g[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + r;
+                    g[r] = (i < k && q <= i) ? G[i * k + q] : num<T>::zero();
+                }
+                const T lq = q <= imax ? num<T>::conj(lp[q]) : num<T>::zero();
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = i0 + r;
+                    if (i < k && q <= i) G[i * k + q] = g[r] - lp[i] * lq;
+                }
+            }
         }
         __syncthreads();
     }
@@ -1086,9 +1102,11 @@ __global__ void __launch_bounds__(GNT, 4) factor_generic_kernel(FactorArgs<T> A,
     c.sV = (T*)at(GA_V, Lo.oV);
     c.sL = (int32_t*)at(GA_L, Lo.oL);
     c.sSel = (int32_t*)at(GA_SEL, Lo.oSel);
-    c.sRed = (double*)at(GA_RED, Lo.oRed);
-    c.mi = (int*)at(GA_MISC, Lo.oMisc);
-    c.md = (double*)at(GA_MISC, Lo.oMisc);
+    // the flag/reduction slots are placed first and always lie in LDS; typed
+    // as LDS here so their reads are LDS reads, not flat ones
+    c.sRed = (double*)(lds_dyn + Lo.oRed);
+    c.mi = (int*)(lds_dyn + Lo.oMisc);
+    c.md = (double*)(lds_dyn + Lo.oMisc);
     c.xld = lcap + 1;
     const size_t kk = (size_t)kcap * kcap;
     // global k x k matrices (when not here): 1 per block for unit-norm v, 3 otherwise
@@ -1125,6 +1143,8 @@ struct GenPlan {
 // LDS budget of the split layout (in_lds == false): with the kernel's 8 KB
 // of static LDS, four workgroups per CU
 static constexpr size_t kGenSplitLds = 32 * 1024;
+// the misc and reduction slots, taken first, always fit in the LDS part
+static_assert(kGenSplitLds >= sizeof(double) * (32 + GNT) + 32, "split LDS too small");
 
 template <class T>
 GenPlan generic_plan(int kcap, int tcap, int lcap, int mode, int nt_override = 0)
