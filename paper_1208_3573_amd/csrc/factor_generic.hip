@@ -23,6 +23,7 @@
 namespace diaf {
 
 static constexpr int GNT = 512;  // largest workgroup (small size classes use one wave)
+static constexpr int kGenMaxK = 256;  // largest |J_j| and l_j of a launch
 
 struct GenLayout {
     size_t oJ, oOff, oKey, oVal, oLrow, oCol, oPos, oRowptr, oR, oRank, oY, oW, oX, oVM, oSig,
@@ -199,6 +200,16 @@ __device__ inline T bget(const GenCtx<T>& c, int i, int a)
 template <class T>
 __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
 {
+    // column p of the factor is staged in the reduction array (unused here;
+    // its GNT doubles hold the k <= 256 entries, complex ones too).  For
+    // real values its second half hands the next column (rows >= p + 1, the
+    // pivot first) from each step's update to the next step, so the pivot
+    // and the column come from LDS, not back from the global slot.
+    constexpr bool kHand = !num<T>::is_complex;
+    T* lp = (T*)c.sRed;
+    double* nx = c.sRed + kGenMaxK;
+    if constexpr (kHand)
+        for (int i = c.tid; i < k; i += c.nt) nx[i] = num<T>::re(G[i * k]);
     if (c.tid == 0) {
         double mx = 0;
         for (int p = 0; p < k; ++p) mx = fmax(mx, num<T>::re(G[p * k + p]));
@@ -206,18 +217,20 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
     }
     __syncthreads();
     const double maxd = c.md[MD_MAXD];
-    // column p of the factor is staged in the reduction array (unused here;
-    // GNT doubles hold the k <= 256 entries, complex ones too)
-    T* lp = (T*)c.sRed;
     const int lane = c.tid & 63, wv = c.tid >> 6, nw = c.nt >> 6;
     for (int p = 0; p < k; ++p) {
         // every thread forms the pivot from the updated diagonal; thread 0
         // stores it after the barrier, once all have read the diagonal
-        const double d = num<T>::re(G[p * k + p]);
+        double d;
+        if constexpr (kHand) d = nx[p];
+        else d = num<T>::re(G[p * k + p]);
         double piv = 0.0;
         if (d > 1e-30 * maxd && isfinite(d)) piv = sqrt(d);
         for (int i = p + 1 + c.tid; i < k; i += c.nt) {
-            const T v = piv > 0.0 ? num<T>::div(G[i * k + p], piv) : num<T>::zero();
+            T gi;
+            if constexpr (kHand) gi = nx[i];
+            else gi = G[i * k + p];
+            const T v = piv > 0.0 ? num<T>::div(gi, piv) : num<T>::zero();
             G[i * k + p] = v;
             lp[i] = v;
         }
@@ -243,7 +256,12 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = i0 + r;
-                    if (i < k && q <= i) G[i * k + q] = g[r] - lp[i] * lq;
+                    if (i < k && q <= i) {
+                        const T v = g[r] - lp[i] * lq;
+                        G[i * k + q] = v;
+                        if constexpr (kHand)
+                            if (q == p + 1) nx[i] = v;
+                    }
                 }
             }
         }
@@ -1083,8 +1101,11 @@ __global__ void __launch_bounds__(GNT, 4) factor_generic_kernel(FactorArgs<T> A,
     GenCtx<T> c;
     c.tid = threadIdx.x;
     c.nt = blockDim.x;
-    c.sJ = (int32_t*)at(GA_J, Lo.oJ);
-    c.sOff = (int32_t*)at(GA_OFF, Lo.oOff);
+    // the arrays placed first (flag and reduction slots, J_j and its column
+    // offsets, the V rows and picks, w) always lie in LDS for kcap, lcap <=
+    // 256; typed as LDS here so their reads are LDS reads, not flat ones
+    c.sJ = (int32_t*)(lds_dyn + Lo.oJ);
+    c.sOff = (int32_t*)(lds_dyn + Lo.oOff);
     c.sKey = (uint64_t*)at(GA_KEY, Lo.oKey);
     c.sScore = (double*)at(GA_KEY, Lo.oKey);
     c.sVal = (T*)at(GA_VAL, Lo.oVal);
@@ -1095,15 +1116,13 @@ __global__ void __launch_bounds__(GNT, 4) factor_generic_kernel(FactorArgs<T> A,
     c.sR = (int32_t*)at(GA_R, Lo.oR);
     c.sRank = (int32_t*)at(GA_RANK, Lo.oRank);
     c.sY = (T*)at(GA_Y, Lo.oY);
-    c.sW = (T*)at(GA_W, Lo.oW);
+    c.sW = (T*)(lds_dyn + Lo.oW);
     c.sX = (T*)at(GA_X, Lo.oX);
     c.sVM = (T*)at(GA_VM, Lo.oVM);
     c.sSig = (double*)at(GA_SIG, Lo.oSig);
     c.sV = (T*)at(GA_V, Lo.oV);
-    c.sL = (int32_t*)at(GA_L, Lo.oL);
-    c.sSel = (int32_t*)at(GA_SEL, Lo.oSel);
-    // the flag/reduction slots are placed first and always lie in LDS; typed
-    // as LDS here so their reads are LDS reads, not flat ones
+    c.sL = (int32_t*)(lds_dyn + Lo.oL);
+    c.sSel = (int32_t*)(lds_dyn + Lo.oSel);
     c.sRed = (double*)(lds_dyn + Lo.oRed);
     c.mi = (int*)(lds_dyn + Lo.oMisc);
     c.md = (double*)(lds_dyn + Lo.oMisc);
@@ -1143,8 +1162,12 @@ struct GenPlan {
 // LDS budget of the split layout (in_lds == false): with the kernel's 8 KB
 // of static LDS, four workgroups per CU
 static constexpr size_t kGenSplitLds = 32 * 1024;
-// the misc and reduction slots, taken first, always fit in the LDS part
-static_assert(kGenSplitLds >= sizeof(double) * (32 + GNT) + 32, "split LDS too small");
+// the arrays taken first (misc, reduction, offsets, J, L, picks, w) always
+// fit in the LDS part for kcap, lcap <= 256 (checked at launch)
+static_assert(kGenSplitLds >= sizeof(double) * (32 + GNT) + sizeof(int32_t) * (kGenMaxK + 1) +
+                                  sizeof(int32_t) * 3 * kGenMaxK + 2 * sizeof(double) * kGenMaxK +
+                                  7 * 16,
+              "split LDS too small");
 
 template <class T>
 GenPlan generic_plan(int kcap, int tcap, int lcap, int mode, int nt_override = 0)
@@ -1189,6 +1212,8 @@ Err launch_factor_generic(const FactorArgs<T>& A, int kcap, int tcap, int lcap, 
 {
     if (A.ncols == 0) return {};
     if (tcap > 65535) return {DIAF_EUNSUPPORTED, "column too large"};
+    if (kcap > kGenMaxK || lcap > kGenMaxK)
+        return {DIAF_EUNSUPPORTED, "generic kernel: more than 256 W or V entries in a column"};
     int tcap2 = 1;
     while (tcap2 < tcap) tcap2 <<= 1;
     GenPlan P = generic_plan<T>(kcap, tcap, lcap, A.mode, tune.generic_nt);
