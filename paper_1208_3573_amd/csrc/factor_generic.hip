@@ -270,35 +270,66 @@ __device__ inline void cholesky(GenCtx<T>& c, T* G, int k)
 }
 
 // Solve L X = X (forward) for nr right-hand sides stored X[a * xld + t].
+// X(p, :) is final once step p starts.  For few right-hand sides every
+// thread forms x_p = X(p, :) / L(p, p) itself (the same value each time), so
+// a step needs one barrier, and the scaled rows are written back at the end;
+// for many, one pass scales row p first (two barriers a step, one division
+// per entry).
 template <class T>
 __device__ inline void lsolve(GenCtx<T>& c, const T* Lf, int k, T* X, int nr)
 {
+    const bool few = nr <= 8;
     for (int p = 0; p < k; ++p) {
         const double d = num<T>::re(Lf[p * k + p]);
-        for (int t = c.tid; t < nr; t += c.nt)
-            X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
-        __syncthreads();
+        if (!few) {
+            for (int t = c.tid; t < nr; t += c.nt)
+                X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
+            __syncthreads();
+        }
         const int rem = k - p - 1;
         for (int idx = c.tid; idx < rem * nr; idx += c.nt) {
-            int i = p + 1 + idx / nr, t = idx % nr;
-            X[i * c.xld + t] -= Lf[i * k + p] * X[p * c.xld + t];
+            const int i = p + 1 + idx / nr, t = idx % nr;
+            T xp = X[p * c.xld + t];
+            if (few) xp = d > 0.0 ? num<T>::div(xp, d) : num<T>::zero();
+            X[i * c.xld + t] -= Lf[i * k + p] * xp;
+        }
+        __syncthreads();
+    }
+    if (few) {
+        for (int idx = c.tid; idx < k * nr; idx += c.nt) {
+            const int p = idx / nr, t = idx % nr;
+            const double d = num<T>::re(Lf[p * k + p]);
+            X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
         }
         __syncthreads();
     }
 }
 
-// Solve L^* X = X (backward).
+// Solve L^* X = X (backward), in the same way.
 template <class T>
 __device__ inline void lhsolve(GenCtx<T>& c, const T* Lf, int k, T* X, int nr)
 {
+    const bool few = nr <= 8;
     for (int p = k - 1; p >= 0; --p) {
         const double d = num<T>::re(Lf[p * k + p]);
-        for (int t = c.tid; t < nr; t += c.nt)
-            X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
-        __syncthreads();
+        if (!few) {
+            for (int t = c.tid; t < nr; t += c.nt)
+                X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
+            __syncthreads();
+        }
         for (int idx = c.tid; idx < p * nr; idx += c.nt) {
-            int i = idx / nr, t = idx % nr;
-            X[i * c.xld + t] -= num<T>::conj(Lf[p * k + i]) * X[p * c.xld + t];
+            const int i = idx / nr, t = idx % nr;
+            T xp = X[p * c.xld + t];
+            if (few) xp = d > 0.0 ? num<T>::div(xp, d) : num<T>::zero();
+            X[i * c.xld + t] -= num<T>::conj(Lf[p * k + i]) * xp;
+        }
+        __syncthreads();
+    }
+    if (few) {
+        for (int idx = c.tid; idx < k * nr; idx += c.nt) {
+            const int p = idx / nr, t = idx % nr;
+            const double d = num<T>::re(Lf[p * k + p]);
+            X[p * c.xld + t] = d > 0.0 ? num<T>::div(X[p * c.xld + t], d) : num<T>::zero();
         }
         __syncthreads();
     }
