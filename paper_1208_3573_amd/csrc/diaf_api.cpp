@@ -1354,10 +1354,11 @@ Err compute_levels(diaf_ctx* ctx, diaf_factors* F)
 
 // Right: t = V^{-1} x ; y = W t.  Left: t = W x ; y = V^{-1} t.  All on
 // stream st, no host sync.  t (n entries) and ctl (the triangular solve's
-// control words) are the factors' own buffers, or the caller's.
+// control words) are the factors' own buffers, or the caller's; prefilled:
+// the triangular solve's output already holds its not-ready sentinel.
 template <class T>
 Err enqueue_apply_with(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const int32_t* done,
-                       hipStream_t st, T* t, TrsvCtl* ctl)
+                       hipStream_t st, T* t, TrsvCtl* ctl, bool prefilled = false)
 {
     const int n = (int)F->n;
     const T* vin = x;
@@ -1374,7 +1375,7 @@ Err enqueue_apply_with(diaf_ctx* ctx, diaf_factors* F, const T* x, T* y, const i
                                        vout, done, st));
     else
         DIAF_TRY(launch_trsv<T>(n, F->Vrp, F->Vci, (const T*)F->Vcv, F->vtri > 0, vin, vout,
-                                ctl, done, ctx->trsv, st));
+                                ctl, done, ctx->trsv, st, prefilled));
     if (F->left) return {};
     return launch_spmv_csr<T>(n, F->nnzW, F->Wrp, F->Wci, (const T*)F->Wcv, (const T*)t, y, done,
                               st);
@@ -2199,6 +2200,24 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
         V.ph = V.p;
         V.sh = V.s;
     }
+    // Right preconditioning with a triangular V: the two solves of an
+    // iteration write to buffers of their own, which the stage kernels after
+    // them (bicg_alpha, bicg_xr) refill with the not-ready sentinel, so no
+    // solve needs a fill launch (filled here once for the first iteration).
+    const bool trsv_prec = !left && F && F->vtri != 0 && F->vtri != 3;
+    T* tsolve = nullptr;
+    if (trsv_prec) {
+        DIAF_TRY(dmalloc(&tsolve, sizeof(T) * (size_t)n * 2));
+        blocks.keep(tsolve);
+        DIAF_TRY(launch_fill_sentinel<T>(n, tsolve, st));
+        DIAF_TRY(launch_fill_sentinel<T>(n, tsolve + n, st));
+        V.clr_a = tsolve;
+        V.clr_x = tsolve + n;
+    }
+    const auto apply_prec = [&](const T* in, T* out, T* tbuf) -> Err {
+        if (tbuf) return enqueue_apply_with<T>(ctx, F, in, out, done, st, tbuf, F->ctl, true);
+        return enqueue_apply<T>(ctx, F, in, out, done, st);
+    };
     DIAF_TRY(bicg_init<T>(V, rtol, maxit, st));
     BicgState<T> hs{};
     const int batch = (int)ctx->opt_batch;
@@ -2218,12 +2237,12 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
                 DIAF_TRY(bicg_xr<T>(V, st));
                 continue;
             }
-            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.p, V.ph, done, st));
+            if (F) DIAF_TRY(apply_prec(V.p, V.ph, V.clr_a));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.ph, V.p, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
             DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.ph, V.v, done, st));
             DIAF_TRY(bicg_alpha<T>(V, st));
             DIAF_TRY(bicg_s<T>(V, st));
-            if (F) DIAF_TRY(enqueue_apply<T>(ctx, F, V.s, V.sh, done, st));
+            if (F) DIAF_TRY(apply_prec(V.s, V.sh, V.clr_x));
             else DIAF_HIP_TRY(hipMemcpyAsync(V.sh, V.s, sizeof(T) * n, hipMemcpyDeviceToDevice, st));
             DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.sh, V.t, done, st));
             DIAF_TRY(bicg_omega<T>(V, st));

@@ -215,9 +215,15 @@ struct TrsvTune {
     int backoff = 1;
     int waves = 8;
 };
+// prefilled: x already holds the not-ready sentinel in every entry (else the
+// launch fills it first).
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
-                T* x, TrsvCtl* ctl, const int32_t* done, TrsvTune tune, hipStream_t st);
+                T* x, TrsvCtl* ctl, const int32_t* done, TrsvTune tune, hipStream_t st,
+                bool prefilled = false);
+// x = the triangular solve's not-ready sentinel in every entry.
+template <class T>
+Err launch_fill_sentinel(int n, T* x, hipStream_t st);
 template <class T>
 Err launch_diag_solve(int n, const int32_t* rp, const int32_t* ci, const T* val, const T* b, T* x,
                       const int32_t* done, hipStream_t st);
@@ -231,6 +237,11 @@ struct BicgVecs {
     int n;
     const T* b;
     T *x, *r, *rh, *p, *v, *ph, *s, *sh, *t;
+    // when set, bicg_alpha and bicg_xr fill these with the triangular
+    // solve's not-ready sentinel: the outputs of the iteration's first and
+    // second solve, dead by then, so the solves need no fill launch
+    T* clr_a = nullptr;
+    T* clr_x = nullptr;
     double* partial;  // reduction scratch (>= 2 * nblocks doubles, complex: 4x)
     BicgState<T>* st;
 };

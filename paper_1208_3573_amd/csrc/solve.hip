@@ -152,6 +152,15 @@ __global__ void fill_sentinel_kernel(int n, T* x, const int32_t* done)
     if (i < (int64_t)n * W) ((uint64_t*)x)[i] = TRSV_SENTINEL;
 }
 
+// Entry i of x = the not-ready sentinel (every word of it).
+template <class T>
+__device__ inline void set_sentinel(T* x, int i)
+{
+    constexpr int W = words<T>::W;
+#pragma unroll
+    for (int k = 0; k < W; ++k) ((uint64_t*)x)[(int64_t)i * W + k] = TRSV_SENTINEL;
+}
+
 // Polling of entry c of x in two steps: issue the load of its raw words now
 // and examine them later, so that other work can run while it is in flight.
 template <class T>
@@ -467,12 +476,14 @@ __global__ void __launch_bounds__(64 * NW) trsv_kernel(int n, const int32_t* rp,
 
 template <class T>
 Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int upper, const T* b,
-                T* x, TrsvCtl* ctl, const int32_t* done, TrsvTune tune, hipStream_t st)
+                T* x, TrsvCtl* ctl, const int32_t* done, TrsvTune tune, hipStream_t st,
+                bool prefilled)
 {
     if (n == 0) return {};
     int64_t nw = (int64_t)n * words<T>::W;
-    hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
-                       n, x, done);
+    if (!prefilled)
+        hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0,
+                           st, n, x, done);
     const int rows = 64 * tune.waves;
     const dim3 grid((n + rows - 1) / rows);
 #define TRSV_CASE(NW)                                                                         \
@@ -489,6 +500,17 @@ Err launch_trsv(int n, const int32_t* rp, const int32_t* ci, const T* val, int u
     TRSV_CASE(16)
 #undef TRSV_CASE
     return {DIAF_EINVAL, "triangular solve: waves per workgroup must be 1, 2, 4, 8 or 16"};
+}
+
+template <class T>
+Err launch_fill_sentinel(int n, T* x, hipStream_t st)
+{
+    if (n == 0) return {};
+    int64_t nw = (int64_t)n * words<T>::W;
+    hipLaunchKernelGGL(fill_sentinel_kernel<T>, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
+                       n, x, (const int32_t*)nullptr);
+    DIAF_HIP_TRY(hipGetLastError());
+    return {};
 }
 
 // Level of every row in the triangular dependency DAG (same sync-free
@@ -736,6 +758,7 @@ __global__ void __launch_bounds__(RNT) bicg_alpha_kernel(BicgVecs<T> V)
         T d = num<T>::cmul(V.rh[i], V.v[i]);
         acc[0] += num<T>::re(d);
         acc[1] += num<T>::im(d);
+        if (V.clr_a) set_sentinel(V.clr_a, i);
     }
     if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket)) {
         double s[2];
@@ -811,6 +834,7 @@ __global__ void __launch_bounds__(RNT) bicg_xr_kernel(BicgVecs<T> V)
         T r = V.s[i] - omega * V.t[i];
         V.r[i] = r;
         acc[0] += num<T>::abs2(r);
+        if (V.clr_x) set_sentinel(V.clr_x, i);
     }
     if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
         double s[1];
@@ -882,7 +906,8 @@ Err bicg_half_fix(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_half
     template Err launch_spmv_csr<T>(int, int64_t, const int32_t*, const int32_t*, const T*,        \
                                     const T*, T*, const int32_t*, hipStream_t);                   \
     template Err launch_trsv<T>(int, const int32_t*, const int32_t*, const T*, int, const T*, T*, \
-                                TrsvCtl*, const int32_t*, TrsvTune, hipStream_t);                 \
+                                TrsvCtl*, const int32_t*, TrsvTune, hipStream_t, bool);           \
+    template Err launch_fill_sentinel<T>(int, T*, hipStream_t);                                   \
     template Err launch_diag_solve<T>(int, const int32_t*, const int32_t*, const T*, const T*,    \
                                       T*, const int32_t*, hipStream_t);                           \
     template Err bicg_init<T>(const BicgVecs<T>&, double, int, hipStream_t);                      \
