@@ -2224,7 +2224,6 @@ Err solve_impl(diaf_ctx* ctx, const diaf_csc* A, diaf_factors* F, const T* b, T*
     // one batch of iterations; every stage returns at once after convergence
     const auto enqueue_batch = [&]() -> Err {
         for (int q = 0; q < batch; ++q) {
-            DIAF_TRY(bicg_rho<T>(V, st));
             DIAF_TRY(bicg_update_p<T>(V, st));
             if (left) {
                 DIAF_TRY(launch_spmv_csr<T>(n, A->nnz, rp, ci, cv, V.p, av, done, st));

@@ -242,11 +242,10 @@ struct BicgVecs {
     // second solve, dead by then, so the solves need no fill launch
     T* clr_a = nullptr;
     T* clr_x = nullptr;
-    double* partial;  // reduction scratch (>= 2 * nblocks doubles, complex: 4x)
+    double* partial;  // reduction scratch (>= 3 * nblocks doubles)
     BicgState<T>* st;
 };
 template <class T> Err bicg_init(const BicgVecs<T>& V, double tol, int maxit, hipStream_t st);
-template <class T> Err bicg_rho(const BicgVecs<T>& V, hipStream_t st);
 template <class T> Err bicg_update_p(const BicgVecs<T>& V, hipStream_t st);
 template <class T> Err bicg_alpha(const BicgVecs<T>& V, hipStream_t st);
 template <class T> Err bicg_s(const BicgVecs<T>& V, hipStream_t st);

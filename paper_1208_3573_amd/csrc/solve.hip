@@ -674,10 +674,30 @@ __device__ inline bool bad_scalar(T a)
 
 #define BICG_GRID_LOOP for (int i = blockIdx.x * RNT + threadIdx.x; i < V.n; i += gridDim.x * RNT)
 
+// The start of an iteration, from rho = <rh, r> of its residual: the maxit
+// stop, the iteration count, the breakdown test and beta (by the last block
+// of the stage that computed rho).
+template <class T>
+__device__ inline void bicg_begin_iteration(BicgState<T>* S, T rho)
+{
+    if (S->it + 1 > S->maxit) { S->done = 1; S->flag = 1; return; }
+    S->it += 1;
+    if (bad_scalar(rho)) { S->done = 1; S->flag = 2; return; }
+    S->rho = rho;
+    if (S->it == 1) {
+        S->beta = num<T>::zero();
+    } else {
+        T q = div_t(rho, S->rho_prev);
+        T a = div_t(S->alpha, S->omega);
+        S->beta = q * a;
+    }
+}
+
+// x = 0, r = rh = b, ||b||, and the first iteration's rho = <rh, r>.
 template <class T>
 __global__ void __launch_bounds__(RNT) bicg_init_kernel(BicgVecs<T> V, double tol, int maxit)
 {
-    double acc[1] = {0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     BICG_GRID_LOOP {
         T bi = V.b[i];
         V.x[i] = num<T>::zero();
@@ -686,10 +706,13 @@ __global__ void __launch_bounds__(RNT) bicg_init_kernel(BicgVecs<T> V, double to
         V.p[i] = num<T>::zero();
         V.v[i] = num<T>::zero();
         acc[0] += num<T>::abs2(bi);
+        T d = num<T>::cmul(bi, bi);
+        acc[1] += num<T>::re(d);
+        acc[2] += num<T>::im(d);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
-        double s[1];
-        sum_partials<1>(V.partial, gridDim.x, s);
+    if (reduce_partials<3>(acc, V.partial, &V.st->red_ticket)) {
+        double s[3];
+        sum_partials<3>(V.partial, gridDim.x, s);
         if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->bnorm = sqrt(s[0]);
@@ -706,38 +729,7 @@ __global__ void __launch_bounds__(RNT) bicg_init_kernel(BicgVecs<T> V, double to
         S->done = (s[0] == 0.0) ? 1 : 0;
         S->flag = (s[0] == 0.0) ? 0 : 1;
         S->red_ticket = 0;
-    }
-}
-
-// rho = <rh, r>; beta; iteration count and the maxit stop.
-template <class T>
-__global__ void __launch_bounds__(RNT) bicg_rho_kernel(BicgVecs<T> V)
-{
-    if (V.st->done) return;
-    double acc[2] = {0.0, 0.0};
-    BICG_GRID_LOOP {
-        T d = num<T>::cmul(V.rh[i], V.r[i]);
-        acc[0] += num<T>::re(d);
-        acc[1] += num<T>::im(d);
-    }
-    if (reduce_partials<2>(acc, V.partial, &V.st->red_ticket)) {
-        double s[2];
-        sum_partials<2>(V.partial, gridDim.x, s);
-        if (threadIdx.x != 0) return;
-        BicgState<T>* S = V.st;
-        S->red_ticket = 0;
-        T rho = mk2<T>(s[0], s[1]);
-        if (S->it + 1 > S->maxit) { S->done = 1; S->flag = 1; return; }
-        S->it += 1;
-        if (bad_scalar(rho)) { S->done = 1; S->flag = 2; return; }
-        S->rho = rho;
-        if (S->it == 1) {
-            S->beta = num<T>::zero();
-        } else {
-            T q = div_t(rho, S->rho_prev);
-            T a = div_t(S->alpha, S->omega);
-            S->beta = q * a;
-        }
+        if (!S->done) bicg_begin_iteration(S, mk2<T>(s[1], s[2]));
     }
 }
 
@@ -825,30 +817,35 @@ __global__ void __launch_bounds__(RNT) bicg_omega_kernel(BicgVecs<T> V)
     }
 }
 
-// x = x + alpha ph + omega sh; r = s - omega t; full-step convergence test.
+// x = x + alpha ph + omega sh; r = s - omega t; full-step convergence test;
+// the next iteration's rho = <rh, r> in the same pass.
 template <class T>
 __global__ void __launch_bounds__(RNT) bicg_xr_kernel(BicgVecs<T> V)
 {
     if (V.st->done) return;
     const T alpha = V.st->alpha, omega = V.st->omega;
-    double acc[1] = {0.0};
+    double acc[3] = {0.0, 0.0, 0.0};
     BICG_GRID_LOOP {
         V.x[i] = V.x[i] + alpha * V.ph[i] + omega * V.sh[i];
         T r = V.s[i] - omega * V.t[i];
         V.r[i] = r;
         acc[0] += num<T>::abs2(r);
+        T d = num<T>::cmul(V.rh[i], r);
+        acc[1] += num<T>::re(d);
+        acc[2] += num<T>::im(d);
         if (V.clr_x) set_sentinel(V.clr_x, i);
     }
-    if (reduce_partials<1>(acc, V.partial, &V.st->red_ticket)) {
-        double s[1];
-        sum_partials<1>(V.partial, gridDim.x, s);
+    if (reduce_partials<3>(acc, V.partial, &V.st->red_ticket)) {
+        double s[3];
+        sum_partials<3>(V.partial, gridDim.x, s);
         if (threadIdx.x != 0) return;
         BicgState<T>* S = V.st;
         S->red_ticket = 0;
         double nr = sqrt(s[0]);
         S->res = nr / S->bnorm;
         S->rho_prev = S->rho;
-        if (nr <= S->tol * S->bnorm) { S->done = 1; S->flag = 0; }
+        if (nr <= S->tol * S->bnorm) { S->done = 1; S->flag = 0; return; }
+        bicg_begin_iteration(S, mk2<T>(s[1], s[2]));
     }
 }
 
@@ -890,7 +887,6 @@ __global__ void __launch_bounds__(RNT) bicg_half_fix_kernel(BicgVecs<T> V)
     return {};
 
 template <class T> Err bicg_init(const BicgVecs<T>& V, double tol, int maxit, hipStream_t st) { LAUNCH_STAGE(bicg_init_kernel, tol, maxit) }
-template <class T> Err bicg_rho(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_rho_kernel) }
 template <class T> Err bicg_update_p(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_p_kernel) }
 template <class T> Err bicg_alpha(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_alpha_kernel) }
 template <class T> Err bicg_s(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_s_kernel) }
@@ -914,7 +910,6 @@ Err bicg_half_fix(const BicgVecs<T>& V, hipStream_t st) { LAUNCH_STAGE(bicg_half
     template Err launch_diag_solve<T>(int, const int32_t*, const int32_t*, const T*, const T*,    \
                                       T*, const int32_t*, hipStream_t);                           \
     template Err bicg_init<T>(const BicgVecs<T>&, double, int, hipStream_t);                      \
-    template Err bicg_rho<T>(const BicgVecs<T>&, hipStream_t);                                    \
     template Err bicg_update_p<T>(const BicgVecs<T>&, hipStream_t);                               \
     template Err bicg_alpha<T>(const BicgVecs<T>&, hipStream_t);                                  \
     template Err bicg_s<T>(const BicgVecs<T>&, hipStream_t);                                      \
