@@ -206,9 +206,12 @@ __device__ inline int block_scan01(int32_t* f, int cnt, int32_t* red)
 
 // The q-th largest (1-based, q <= cnt) of the non-negative doubles
 // v[0..cnt), by radix selection on their bit patterns (which order as the
-// values): 8 passes over 8-bit digits from the top, each counting the values
-// that match the digits fixed so far into 256 bins (hist) and fixing the
-// digit in which the q-th falls.  blockDim.x is a multiple of 64.
+// values): up to 8 passes over 8-bit digits from the top, each counting the
+// values that match the digits fixed so far into 256 bins (hist) and fixing
+// the digit in which the q-th falls.  Once that bin holds exactly as many
+// values as the rank still needed, the q-th is their minimum, taken in one
+// more sweep (usually after a few passes).  pick holds 3 ints; blockDim.x is
+// a multiple of 64.
 __device__ inline double block_kth_largest(const double* v, int cnt, int q, int32_t* hist,
                                            int32_t* pick)
 {
@@ -233,12 +236,40 @@ __device__ inline double block_kth_largest(const double* v, int cnt, int q, int3
                 while (r < 3 && run + h[r] < rem) { run += h[r]; ++r; }
                 pick[0] = 255 - 4 * tid - r;
                 pick[1] = rem - run;
+                pick[2] = h[r];
             }
         }
         __syncthreads();
         prefix |= (uint64_t)(uint32_t)pick[0] << shift;
         mask |= 255ull << shift;
         rem = pick[1];
+        if (shift > 0 && pick[2] == rem) {
+            // every value in the bin ranks at or above the q-th: its minimum
+            uint64_t lo = ~0ull;
+            for (int t = tid; t < cnt; t += nt) {
+                const uint64_t key = (uint64_t)__double_as_longlong(v[t]) & 0x7fffffffffffffffull;
+                if ((key & mask) == prefix) lo = key < lo ? key : lo;
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const uint64_t y = __shfl_xor(lo, o);
+                lo = y < lo ? y : lo;
+            }
+            // wave minima through hist (read by wave 0 before the barrier
+            // above), as 32-bit halves
+            const int w0 = tid >> 6;
+            if ((tid & 63) == 0) {
+                hist[2 * w0] = (int32_t)(uint32_t)lo;
+                hist[2 * w0 + 1] = (int32_t)(uint32_t)(lo >> 32);
+            }
+            __syncthreads();
+            for (int w = 0; w < (nt >> 6); ++w) {
+                const uint64_t y = (uint64_t)(uint32_t)hist[2 * w] |
+                                   ((uint64_t)(uint32_t)hist[2 * w + 1] << 32);
+                lo = y < lo ? y : lo;
+            }
+            __syncthreads();  // hist is reused by the caller's next call
+            return __longlong_as_double((long long)lo);
+        }
     }
     return __longlong_as_double((long long)prefix);
 }
@@ -415,7 +446,7 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     int32_t* red = scrow + cap;
     int32_t* sel = red + blockDim.x + 1;
     int32_t* cst = sel + 256;
-    __shared__ int32_t s_nsel, s_above, s_pick[2], s_hist[256];
+    __shared__ int32_t s_nsel, s_above, s_pick[3], s_hist[256];
     const int j = cols[blockIdx.x];
     const int tid = threadIdx.x;
     const int a0 = Acp[j], na = Acp[j + 1] - a0;
