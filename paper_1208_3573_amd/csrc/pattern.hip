@@ -446,7 +446,7 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
     int32_t* red = scrow + cap;
     int32_t* sel = red + blockDim.x + 1;
     int32_t* cst = sel + 256;
-    __shared__ int32_t s_nsel, s_above, s_pick[3], s_hist[256];
+    __shared__ int32_t s_nsel, s_above, s_equal, s_pick[3], s_hist[256];
     const int j = cols[blockIdx.x];
     const int tid = threadIdx.x;
     const int a0 = Acp[j], na = Acp[j + 1] - a0;
@@ -550,7 +550,7 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
         sc[slot] = s;
         scrow[slot] = row;
     }
-    if (tid == 0) { s_nsel = 0; s_above = 0; }
+    if (tid == 0) { s_nsel = 0; s_above = 0; s_equal = 0; }
     __syncthreads();
     // top-ptop: larger score first, lower row on ties.  With s* the take-th
     // largest score, every candidate above s* is taken and the rest come
@@ -563,13 +563,18 @@ __global__ void pattern_1hop_kernel(int n, const int32_t* Acp, const int32_t* Ar
         for (int s = tid; s < nc; s += blockDim.x) {
             off[s] = sc[s] == ss;
             if (sc[s] > ss) atomicAdd(&s_above, 1);
+            if (sc[s] == ss) atomicAdd(&s_equal, 1);
         }
         __syncthreads();
-        block_scan01(off, nc, red);  // rank among the candidates equal to s*
         const int need = take - s_above;
+        // rank among the candidates equal to s*, unless all of them are taken
+        // (s_equal >= need since s* is the take-th largest)
+        const bool all_equal = s_equal == need;
+        if (!all_equal) block_scan01(off, nc, red);
         for (int s = tid; s < nc; s += blockDim.x) {
             const double v = sc[s];
-            if (v > ss || (v == ss && off[s] < need)) sel[atomicAdd(&s_nsel, 1)] = scrow[s];
+            if (v > ss || (v == ss && (all_equal || off[s] < need)))
+                sel[atomicAdd(&s_nsel, 1)] = scrow[s];
         }
     }
     __syncthreads();
