@@ -373,7 +373,10 @@ diaf_status diaf_autotune_cached(struct diaf_ctx* ctx, const diaf_csc* A, const 
 
 /* W pattern of kind w_kind (A, A2, A_1HOP_TOPK, ALG2_*) for A, two-phase: with rowidx_out == NULL,
  * writes colptr_out[n+1] (device) and the total to *nnz_host; then call
- * again with rowidx_out of *nnz_host entries and the same colptr_out. */
+ * again with rowidx_out of *nnz_host entries and the same colptr_out.
+ * DIAF_EUNSUPPORTED when a column has more candidates than a workgroup's
+ * LDS holds: for A2, 8192 (the sum of |A(:, c)| over the rows c of
+ * A(:, j)); for A_1HOP_TOPK, 4095 - w_topk two-hop candidates, w_topk <= 256. */
 diaf_status diaf_pattern_build(struct diaf_ctx* ctx, const diaf_csc* A, int32_t w_kind,
                                int32_t w_topk, int32_t* colptr_out, int32_t* rowidx_out,
                                int64_t* nnz_host);
