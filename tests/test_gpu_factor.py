@@ -263,7 +263,10 @@ def test_pattern_builders_match_oracle(ctx):
              # unit values: scores are path counts, so nearly every score ties;
              # 1 600 two-hop candidates per column
              (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 8),
-             (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 100)]
+             (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 100),
+             # 78^2 = 6084 candidates in every column: the largest A2 launch
+             # (4097 to 8192 candidates, 1024 threads, 7 merge rounds)
+             (synth.random_small(2000, 77, 11), "A2", 0)]
     for A, kind, p in cases:
         say(f"pattern {kind} p={p} n={A.n}")
         dA = diaf.DeviceCSC.from_host(A)
@@ -271,6 +274,18 @@ def test_pattern_builders_match_oracle(ctx):
         J = oracle_pattern(A, kind, p)
         assert np.array_equal(cp.cpu().numpy(), J.colptr)
         assert np.array_equal(ri.cpu().numpy(), J.rowidx)
+
+
+def test_pattern_a2_candidate_limit(ctx):
+    """A column of pattern(A^2) with more than 8192 candidates (here 96^2 =
+    9216: the sum of |A(:, c)| over its rows c) is refused, not truncated."""
+    from paper_1208_3573_amd import diaf
+    A = synth.random_small(1200, 95, 12)
+    say("pattern A2 with 9216 candidates per column")
+    dA = diaf.DeviceCSC.from_host(A)
+    with pytest.raises(diaf.DiafError) as ei:
+        diaf.diaf_pattern_build(ctx, dA, "A2", 0)
+    assert ei.value.code == diaf.DIAF_EUNSUPPORTED
 
 
 def test_factor_is_deterministic(ctx):
