@@ -264,6 +264,10 @@ def test_pattern_builders_match_oracle(ctx):
              # 1 600 two-hop candidates per column
              (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 8),
              (_unit_values(synth.random_small(1500, 40, 6)), "A_1hop_topk", 100),
+             # 55^2 = 3025 gathered candidates per column: the largest 1-hop
+             # launch class (up to 4087 at p = 8), with and without ties
+             (synth.random_small(2000, 54, 13), "A_1hop_topk", 8),
+             (_unit_values(synth.random_small(2000, 54, 14)), "A_1hop_topk", 8),
              # 78^2 = 6084 candidates in every column: the largest A2 launch
              # (4097 to 8192 candidates, 1024 threads, 7 merge rounds)
              (synth.random_small(2000, 77, 11), "A2", 0)]
