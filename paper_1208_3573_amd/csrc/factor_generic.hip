@@ -2,8 +2,9 @@
 // any |J_j| up to 256 and up to 8192 gathered entries.
 //
 // Per column j (paper Sections 2.1, 2.2, 3.1):
-//   gather A(:, J_j) from CSC, sort the entries by (row, column) in LDS to
-//   get the shadow R_j and row-ordered access, form the Gram matrix
+//   gather A(:, J_j) from CSC, sort the entries by (row, column) (pairwise
+//   merges of the gathered columns, each already sorted by row) to get the
+//   shadow R_j and row-ordered access, form the Gram matrix
 //   G = B^* B of B = A(R_j, J_j) by sparse merges, then
 //   - unit-norm v (first basic algorithm): Cholesky G = L L^*, the seed
 //     w0 = G^{-1} b_j^* (V_0 = diagonals), the V pattern, M = L^{-1} B_L^*
